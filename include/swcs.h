@@ -1,0 +1,202 @@
+/* swcs.h -- C ABI of the MI355X sparse wavefunction circuit solver (SWCS).
+ *
+ * The library evaluates the hot path of ADAPT-VQE with a sparse wavefunction
+ * circuit solver (Mullinax et al., "Classical Pre-optimization Approach for
+ * ADAPT-VQE", arXiv 2411.07920) on one AMD Instinct MI355X (gfx950):
+ *
+ *   - the factorized unitary coupled-cluster ansatz, Eq. (1), built from the
+ *     single- and double-excitation unitaries of Eqs. (2) and (3) and their
+ *     generalized forms (Sec. II.C), applied to a sparse state of
+ *     (uint64 determinant, float64 amplitude) pairs, each unitary evaluated
+ *     exactly (Sec. II.B) and the state pruned after every unitary (Fig. 1);
+ *   - the energy, the operator-pool gradient of ADAPT step 4 (Sec. II.C) and
+ *     the analytic parameter gradients used by the VQE optimizer (Sec. II.B);
+ *   - the kernels of a learned pool screener (features, MLP, Adam, selection).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Orbitals.  n spatial orbitals, 2n <= 64 spin-orbitals, spin-orbital
+ *   P = 2p + sigma (sigma 0 = alpha, 1 = beta).  Bit P of a determinant key is
+ *   the occupation of P; |D> = a+_{P1}...a+_{Pk}|0> with P1 < ... < Pk, so a
+ *   ladder operator on P carries (-1)^(occupied spin-orbitals below P).
+ * Hamiltonian.  H = e_core + sum_PQ h_PQ a+_P a_Q
+ *   + 1/2 sum_PQRS (PQ|RS) a+_P a+_R a_S a_Q with spin-orbital integrals built
+ *   from the spatial h[p*n+q] and eri[((p*n+q)*n+r)*n+s] = (pq|rs) (chemists'
+ *   notation), spin-conserving.
+ * Pool.  Row k of the int32 table [K x 4] is (P, Q, R, S): a double
+ *   T = a+_P a+_Q a_S a_R (P > Q, R > S, disjoint index sets, equal spin
+ *   multisets) or, with R = S = -1, a single T = a+_P a_Q (P > Q, equal spin).
+ *   The generator is A = T - T^dagger and the unitary exp(theta A).
+ * Truncation.  After every unitary either entries with |c| < eps are dropped
+ *   (eps = 0 keeps everything, exact zeros included) or, when ncut > 0, only the
+ *   ncut entries of largest |c| are kept (ties keep the smaller key).  The state
+ *   is not renormalized.
+ * Energy.  E = <psi|H|psi> / <psi|psi> (Rayleigh quotient of the pruned state).
+ * Memory.  Unless stated otherwise, pointer arguments are HOST pointers that
+ *   are read (or written) during the call only; the library copies inputs to
+ *   its own device memory, which it allocates with hipMalloc and frees in
+ *   swcs_destroy.  Screener calls (swcs_features .. swcs_select) take DEVICE
+ *   pointers owned by the caller and enqueue work on the context stream
+ *   without synchronizing.
+ * Streams.  All device work of a context runs on its stream (default: the
+ *   null stream).  Calls that return host values synchronize that stream.
+ * Errors.  Every int-returning call returns SWCS_OK (0) or a negative status
+ *   and records a message readable with swcs_last_error.  Nothing aborts and
+ *   nothing throws across this boundary.  A context is not thread-safe.
+ * Call order.  Integrals, reference and pool must be set before applying an
+ *   ansatz; energy / gradient calls refer to the last applied ansatz or state,
+ *   otherwise they return SWCS_E_STATE.
+ */
+#ifndef SWCS_H
+#define SWCS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct swcs_ctx swcs_ctx;
+
+enum {
+  SWCS_OK = 0,
+  SWCS_E_INVALID = -1,     /* bad argument (shape, range, symmetry, NaN)    */
+  SWCS_E_STATE = -2,       /* call order violated                           */
+  SWCS_E_OOM = -3,         /* device allocation failed                      */
+  SWCS_E_CAPACITY = -4,    /* state would exceed the configured maximum     */
+  SWCS_E_DEVICE = -5,      /* HIP runtime error                             */
+  SWCS_E_UNSUPPORTED = -6  /* no usable device / feature not available      */
+};
+
+/* Library version string (static storage). */
+const char* swcs_version(void);
+
+/* Create a context on HIP device `device` for n_spatial orbitals (2n <= 64)
+ * and n_alpha / n_beta electrons.  *out receives the context or NULL. */
+int swcs_create(int n_spatial, int n_alpha, int n_beta, int device, swcs_ctx** out);
+
+/* Release the context and all device memory it owns.  NULL is ignored. */
+void swcs_destroy(swcs_ctx* ctx);
+
+/* Message of the last failing call on ctx (owned by ctx; valid until the next
+ * call).  With ctx == NULL: the last failure of swcs_create on this thread. */
+const char* swcs_last_error(const swcs_ctx* ctx);
+
+/* Run all later work on `hip_stream` (a hipStream_t; NULL = null stream). */
+int swcs_set_stream(swcs_ctx* ctx, void* hip_stream);
+
+/* Upper bound on stored determinants (0 = library default, sized from free
+ * device memory).  Growth past it fails with SWCS_E_CAPACITY. */
+int swcs_set_capacity(swcs_ctx* ctx, int64_t max_dets);
+
+/* Step 1 of the ADAPT procedure (Sec. II.C): molecular integrals.  h[n*n] and
+ * eri[n^4] (host, float64, layouts above).  Rejects non-finite values, an
+ * asymmetric h and an eri without 8-fold symmetry (tolerance 1e-12). */
+int swcs_set_integrals(swcs_ctx* ctx, const double* h, const double* eri, double e_core);
+
+/* Step 3: the reference determinant (e.g. Hartree-Fock).  Its alpha and beta
+ * popcounts must equal n_alpha and n_beta and it must fit in 2n bits. */
+int swcs_set_reference(swcs_ctx* ctx, uint64_t det);
+
+/* Step 2: the operator pool, int32 ops[K*4] (host, rows as above).  Rows are
+ * validated (range, ordering, disjointness, spin conservation). */
+int swcs_set_pool(swcs_ctx* ctx, const int32_t* ops, int64_t K);
+
+/* Eq. (1): psi = prod_I U_I(theta_I) psi_0 with psi_0 = the reference, the
+ * unitary of pool row op_idx[0] applied first (new operators are appended at
+ * the end, as in step 5 of ADAPT), pruning after every unitary (Fig. 1) with
+ * eps (ncut == 0) or ncut (ncut > 0).  op_idx[M], theta[M] are host arrays;
+ * M may be 0.  *n_det_out (may be NULL) receives the number of kept
+ * determinants.  The run keeps checkpoints for swcs_param_gradients. */
+int swcs_apply_ansatz(swcs_ctx* ctx, const int32_t* op_idx, const double* theta, int64_t M,
+                      double eps, int64_t ncut, int64_t* n_det_out);
+
+/* Continue from the current state: apply M more unitaries with the same
+ * pruning rule without resetting to the reference.  Parameter gradients are
+ * not available after this call (they need an ansatz started from psi_0). */
+int swcs_apply_gates(swcs_ctx* ctx, const int32_t* op_idx, const double* theta, int64_t M,
+                     double eps, int64_t ncut, int64_t* n_det_out);
+
+/* Replace the current state by n (key, amplitude) pairs (host arrays, keys
+ * distinct, each in the (n_alpha, n_beta) sector). */
+int swcs_set_state(swcs_ctx* ctx, const uint64_t* keys, const double* amps, int64_t n);
+
+/* Export the current state sorted ascending by key into caller arrays of
+ * length cap.  *n receives the state size; if it exceeds cap nothing is
+ * written and SWCS_E_INVALID is returned. */
+int swcs_get_state(swcs_ctx* ctx, uint64_t* keys, double* amps, int64_t cap, int64_t* n);
+
+/* Energy of the current state: *E = numer / norm2 with numer = <psi|H|psi>
+ * (Slater-Condon rules over the kept determinants) and norm2 = <psi|psi>.
+ * Any output pointer may be NULL. */
+int swcs_energy(swcs_ctx* ctx, double* E, double* numer, double* norm2);
+
+/* ADAPT step 4 (Sec. II.C): g_k = <psi|[H, A_k]|psi> / <psi|psi>, the
+ * derivative of E with respect to the parameter of pool operator k appended
+ * at the end of the ansatz, for k in subset[n_subset] (host int32; NULL =
+ * all K in pool order).  g_out has n_subset (or K) entries. */
+int swcs_pool_gradients(swcs_ctx* ctx, const int32_t* subset, int64_t n_subset, double* g_out);
+
+/* Analytic parameter gradients (Sec. II.B) of the last swcs_apply_ansatz:
+ * dE_dtheta[M] with every gate's kept support held fixed (the pruning acts as
+ * a fixed projection; at eps = 0 and no ncut this is the exact gradient).
+ * Reverse (adjoint) sweep over states recomputed from checkpoints stored
+ * every ceil(sqrt(M)) gates.  *E_out (may be NULL) receives E. */
+int swcs_param_gradients(swcs_ctx* ctx, double* dE_dtheta, double* E_out);
+
+/* Per-gate sizes of the last apply call: n_in[M] receives the number of kept
+ * determinants entering each gate.  Returns SWCS_E_INVALID if M differs. */
+int swcs_gate_sizes(swcs_ctx* ctx, int64_t* n_in, int64_t M);
+
+/* Spin-orbital occupations <n_P> = sum_D psi(D)^2 [P in D] / norm2 of the
+ * current state, n_out[2n] (host). */
+int swcs_occupations(swcs_ctx* ctx, double* n_out);
+
+/* ---- learned pool screener (device pointers, float32, ctx stream) ---- */
+
+/* Number of float32 parameters of the screener MLP 16 -> 128 -> 128 -> 1
+ * (ReLU), laid out W1[16x128], b1[128], W2[128x128], b2[128], W3[128], b3. */
+int64_t swcs_mlp_param_count(void);
+
+/* Sixteen features per pool operator into d_feat[K x 16]:
+ *  0-3 closed-shell Fock diagonal f_pp of the spatial orbitals of P,Q,R,S
+ *      (occupied = lowest n_alpha spatial orbitals; 0 when absent),
+ *  4   |(pr|qs)| for doubles, |f_pq| for singles,
+ *  5-8 occupations <n_P> of the current state for P,Q,R,S (0 when absent),
+ *  9   d_prev_absg[k], 10 log10(d_prev_absg[k] + 1e-16),
+ *  11  d_age[k] / 10, 12-14 one-hot single / same-spin / opposite-spin double,
+ *  15  d_count[k].  Requires a current state. */
+int swcs_features(swcs_ctx* ctx, const float* d_prev_absg, const float* d_age,
+                  const float* d_count, float* d_feat);
+
+/* Forward pass on B rows of d_x[B x 16] into d_y[B].  If d_act is not NULL it
+ * receives the post-ReLU activations [B x 256] (layer 1 then layer 2) used by
+ * swcs_mlp_backward. */
+int swcs_mlp_forward(swcs_ctx* ctx, const float* d_W, const float* d_x, int64_t B, float* d_y,
+                     float* d_act);
+
+/* Gradient of sum_b d_dy[b] * y_b with respect to the parameters into d_dW
+ * (overwritten), from the inputs and the activations of the forward pass. */
+int swcs_mlp_backward(swcs_ctx* ctx, const float* d_W, const float* d_x, const float* d_act,
+                      const float* d_dy, int64_t B, float* d_dW);
+
+/* Mean squared error: *d_loss = mean (y - t)^2 and d_dy = 2 (y - t) / B. */
+int swcs_mse(swcs_ctx* ctx, const float* d_y, const float* d_t, int64_t B, float* d_dy,
+             float* d_loss);
+
+/* One Adam step with bias correction (step >= 1) on P parameters. */
+int swcs_adam_step(swcs_ctx* ctx, float* d_W, float* d_m, float* d_v, const float* d_dW,
+                   int64_t P, float lr, float b1, float b2, float eps, int step);
+
+/* Selection: the n_top operators of largest score (ties: smaller index) plus
+ * the n_rand remaining operators of smallest d_rand key (ties: smaller index),
+ * written ascending into d_idx[n_top + n_rand]. */
+int swcs_select(swcs_ctx* ctx, const float* d_score, const uint32_t* d_rand, int64_t K,
+                int64_t n_top, int64_t n_rand, int32_t* d_idx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SWCS_H */

@@ -1,0 +1,483 @@
+"""Pins of the CPU oracle against facts the oracle's own code does not produce:
+dense Jordan-Wigner brute force, scipy's matrix exponential, closed forms
+derived from the Slater-Condon rules, invariants (norm, particle number, S_z),
+the variational bound, finite differences and trigonometric fits.
+
+Each test names what it pins; see oracle/core.py for the table.
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.linalg
+import scipy.sparse.linalg
+
+import oracle
+from dense_jw import DenseProblem
+from paper_2411_07920_amd.inputs import (CONFIGS, draw_ansatz, enumerate_pool, make_integrals,
+                                         pool_count, reference_key, sector_size)
+
+
+@pytest.fixture(scope="module")
+def small():
+    """c1 integrals: 6 spatial orbitals, 4 electrons (225-determinant sector)."""
+    c = CONFIGS["c1"]
+    h, eri = make_integrals(c.n, c.rank, c.seed_int)
+    pool = enumerate_pool(c.n)
+    dense = DenseProblem(c.n, 2, 2, h, eri)
+    orc = oracle.Oracle(c.n, 2, 2, h, eri)
+    ops, theta = draw_ansatz(len(pool), c.n_ops, c.theta_lo, c.theta_hi, c.seed_ansatz)
+    return dict(c=c, h=h, eri=eri, pool=pool, dense=dense, orc=orc, ops=ops, theta=theta,
+                ref=reference_key(c.n_elec), n=c.n, ne=c.n_elec)
+
+
+def _acts(row, key):
+    """True if T or T^dagger of a pool row has a nonzero action on key."""
+    P, Q, R, S = (int(x) for x in row)
+    cre = [P, Q] if R >= 0 else [P]
+    ann = [R, S] if R >= 0 else [Q]
+    occ = lambda x: (key >> x) & 1
+    t = all(occ(a) for a in ann) and not any(occ(c) for c in cre)
+    td = all(occ(c) for c in cre) and not any(occ(a) for a in ann)
+    return t or td
+
+
+def dense_ansatz(dense, pool, ops, theta, ref):
+    v = dense.ref_vec(ref)
+    for k, t in zip(ops, theta):
+        v = scipy.sparse.linalg.expm_multiply(t * dense.generator_sparse(pool[k]), v)
+    return v
+
+
+@pytest.fixture(scope="module")
+def medium():
+    """16 spin-orbitals, 8 electrons (4,900-determinant sector), larger angles.
+    Operators are drawn so that each acts on some determinant of the current
+    (dense, exactly evolved) state, which makes the state spread."""
+    n, ne = 8, 8
+    h, eri = make_integrals(n, n, 1101)
+    pool = enumerate_pool(n)
+    dense = DenseProblem(n, 4, 4, h, eri)
+    orc = oracle.Oracle(n, 4, 4, h, eri)
+    rng = np.random.default_rng(2101)
+    ref = reference_key(ne)
+    v = dense.ref_vec(ref)
+    ops, theta = [], []
+    for _ in range(40):
+        support = dense.basis[np.abs(v) > 1e-3]
+        key = int(support[rng.integers(len(support))])
+        cands = [k for k in range(len(pool)) if _acts(pool[k], key)]
+        k = int(cands[rng.integers(len(cands))])
+        t = float(rng.uniform(-0.6, 0.6))
+        v = scipy.sparse.linalg.expm_multiply(t * dense.generator_sparse(pool[k]), v)
+        ops.append(k)
+        theta.append(t)
+    return dict(h=h, eri=eri, pool=pool, dense=dense, orc=orc, ops=np.array(ops, dtype=np.int32),
+                theta=np.array(theta), ref=ref, n=n, ne=ne, v_exact=v)
+
+
+# ---------------------------------------------------------------- inputs
+def test_pool_counts_closed_form():
+    expect = {6: 570, 14: 22750, 20: 101650, 26: 301600}
+    for n in (3, 4, 6, 14):
+        pool = enumerate_pool(n)
+        s, d = pool_count(n)
+        assert len(pool) == s + d
+        assert int((pool[:, 2] < 0).sum()) == s
+    for n, k in expect.items():
+        s, d = pool_count(n)
+        assert s + d == k
+    assert sum(pool_count(6)) == len(enumerate_pool(6))
+
+
+def test_pool_rows_valid():
+    pool = enumerate_pool(6)
+    seen = set()
+    for P, Q, R, S in pool.tolist():
+        if R < 0:
+            assert P > Q and (P & 1) == (Q & 1)
+            gen = frozenset([(P, Q)])
+        else:
+            assert P > Q and R > S and len({P, Q, R, S}) == 4
+            assert sorted([P & 1, Q & 1]) == sorted([R & 1, S & 1])
+            assert (P, Q) > (R, S)
+            gen = frozenset([(P, Q), (R, S)])
+        assert gen not in seen
+        seen.add(gen)
+
+
+def test_integrals_symmetry_and_psd():
+    h, eri = make_integrals(6, 6, 1001)
+    assert np.allclose(h, h.T, atol=0, rtol=0)
+    for perm in [(1, 0, 2, 3), (0, 1, 3, 2), (2, 3, 0, 1), (1, 0, 3, 2), (3, 2, 1, 0)]:
+        assert np.abs(eri - eri.transpose(perm)).max() < 1e-15
+    pair = eri.reshape(36, 36)
+    assert np.linalg.eigvalsh(pair).min() > -1e-12
+    d = np.diag(h)
+    assert np.all(np.diff(d) >= 0) and d.min() >= -2 and d.max() <= 1
+
+
+# ---------------------------------------------------------------- Slater-Condon
+def test_hmat_matches_dense_all_pairs(small):
+    dense, orc = small["dense"], small["orc"]
+    B = dense.basis
+    M = np.array([[orc.hmat(int(b), int(k)) for k in B] for b in B])
+    assert np.abs(M - dense.H).max() < 1e-13
+
+
+def test_hmat_matches_dense_sampled_16so(medium):
+    dense, orc = medium["dense"], medium["orc"]
+    B = dense.basis
+    rng = np.random.default_rng(5)
+    rows = rng.choice(len(B), 6, replace=False)
+    for r in rows:
+        got = np.array([orc.hmat(int(B[r]), int(k)) for k in B])
+        assert np.abs(got - dense.H[r]).max() < 1e-13
+    ii = rng.integers(0, len(B), 4000)
+    jj = rng.integers(0, len(B), 4000)
+    got = np.array([orc.hmat(int(B[i]), int(B[j])) for i, j in zip(ii, jj)])
+    assert np.abs(got - dense.H[ii, jj]).max() < 1e-13
+
+
+# ---------------------------------------------------------------- gates
+def test_expm_closed_form(small):
+    dense, pool = small["dense"], small["pool"]
+    rng = np.random.default_rng(3)
+    for k in list(range(0, 30, 7)) + list(rng.choice(len(pool), 12, replace=False)):
+        A = dense.generator(pool[k])
+        assert np.abs(A @ A @ A + A).max() < 1e-15
+        for t in (-0.7, 0.05, 1.3):
+            U = scipy.linalg.expm(t * A)
+            closed = np.eye(len(A)) + math.sin(t) * A + (1 - math.cos(t)) * (A @ A)
+            assert np.abs(U - closed).max() < 1e-14
+
+
+def _random_state(dense, rng, frac):
+    B = dense.basis
+    keep = rng.random(len(B)) < frac
+    keys = B[keep].astype(np.uint64)
+    amps = rng.normal(size=len(keys))
+    return keys, amps
+
+
+def test_gate_matches_expm_random_states(medium):
+    dense, pool = medium["dense"], medium["pool"]
+    rng = np.random.default_rng(11)
+    for trial in range(12):
+        keys, amps = _random_state(dense, rng, 0.05)
+        st = oracle.OracleState.from_arrays(keys, amps)
+        k = int(rng.integers(len(pool)))
+        t = float(rng.uniform(-1.5, 1.5))
+        out = oracle.Oracle.apply_gate(st, pool[k], math.cos(t), math.sin(t))
+        v = scipy.sparse.linalg.expm_multiply(t * dense.generator_sparse(pool[k]),
+                                              dense.vec(dict(zip(keys.tolist(), amps))))
+        got = dense.vec(out.as_dict())
+        assert np.abs(got - v).max() < 1e-13
+        # support: input keys plus created partners, nothing else
+        assert set(out.as_dict()) >= set(keys.tolist())
+
+
+def test_ansatz_matches_dense_chain_c1(small):
+    s = small
+    st = oracle.Oracle.apply_ansatz(s["pool"], s["ops"], s["theta"], 0.0, s["ref"])
+    v = dense_ansatz(s["dense"], s["pool"], s["ops"], s["theta"], s["ref"])
+    assert np.abs(s["dense"].vec(st.as_dict()) - v).max() < 1e-13
+
+
+def test_ansatz_matches_dense_chain_16so(medium):
+    s = medium
+    st = oracle.Oracle.apply_ansatz(s["pool"], s["ops"], s["theta"], 0.0, s["ref"])
+    v = s["v_exact"]
+    assert np.abs(s["dense"].vec(st.as_dict()) - v).max() < 1e-13
+    assert len(st) > 300
+
+
+def test_norm_preserved_eps0(medium):
+    s = medium
+    st = oracle.Oracle.apply_ansatz(s["pool"], s["ops"], s["theta"], 0.0, s["ref"])
+    _, a = st.export()
+    assert abs((a * a).sum() - 1.0) < 1e-14 * len(s["ops"])
+
+
+def test_truncation_removes_exactly_dropped_mass(medium):
+    s = medium
+    st = oracle.OracleState.from_arrays(np.array([s["ref"]], dtype=np.uint64), np.array([1.0]))
+    for k, t in zip(s["ops"], s["theta"]):
+        _, a_in = st.export()
+        n_in = (a_in * a_in).sum()
+        out, d2 = oracle.Oracle.apply_gate_truncate(st, s["pool"][k], math.cos(t), math.sin(t), 1e-3)
+        _, a_out = out.export()
+        assert abs((a_out * a_out).sum() - (n_in - d2)) < 1e-14
+        assert np.all(np.abs(a_out) >= 1e-3)
+        st = out
+
+
+def test_particle_number_and_sz(medium):
+    s = medium
+    st = oracle.Oracle.apply_ansatz(s["pool"], s["ops"], s["theta"], 0.0, s["ref"])
+    k, _ = st.export()
+    alpha = np.uint64(int("01" * s["n"], 2))
+    for key in k.tolist():
+        assert bin(key).count("1") == s["ne"]
+        assert bin(key & int(alpha)).count("1") == s["ne"] // 2
+
+
+def test_ncut_keeps_largest(medium):
+    s = medium
+    st_full = oracle.Oracle.apply_ansatz(s["pool"], s["ops"], s["theta"], 0.0, s["ref"])
+    big = oracle.Oracle.apply_ansatz(s["pool"], s["ops"], s["theta"], 0.0, s["ref"], ncut=10 ** 6)
+    assert st_full.as_dict() == big.as_dict()
+    st = oracle.Oracle.apply_ansatz(s["pool"], s["ops"], s["theta"], 0.0, s["ref"], ncut=50)
+    assert len(st) == 50
+
+
+# ---------------------------------------------------------------- energy
+def hf_energy_closed_form(h, eri, n_occ):
+    occ = range(n_occ)
+    e = 2.0 * sum(h[i, i] for i in occ)
+    e += sum(2.0 * eri[i, i, j, j] - eri[i, j, j, i] for i in occ for j in occ)
+    return e
+
+
+def test_hf_energy_closed_form():
+    for n, ne, seed in ((6, 4, 1001), (8, 6, 9), (14, 10, 1002)):
+        h, eri = make_integrals(n, n, seed)
+        orc = oracle.Oracle(n, ne // 2, ne // 2, h, eri)
+        st = oracle.OracleState.from_arrays(np.array([reference_key(ne)], dtype=np.uint64),
+                                            np.array([1.0]))
+        e, _, _ = orc.energy(st)
+        assert abs(e - hf_energy_closed_form(h, eri, ne // 2)) < 1e-12
+
+
+def test_energy_matches_dense_and_variational(small, medium):
+    for s in (small, medium):
+        st = oracle.Oracle.apply_ansatz(s["pool"], s["ops"], s["theta"], 0.0, s["ref"])
+        e, numer, norm2 = s["orc"].energy(st)
+        v = s["dense"].vec(st.as_dict())
+        assert abs(e - (v @ s["dense"].H @ v) / (v @ v)) < 1e-12
+        assert e >= s["dense"].fci() - 1e-12
+        st2 = oracle.Oracle.apply_ansatz(s["pool"], s["ops"], s["theta"], 1e-3, s["ref"])
+        e2, _, _ = s["orc"].energy(st2)
+        assert e2 >= s["dense"].fci() - 1e-12
+
+
+def test_one_gate_energy_curve(small):
+    s = small
+    h, eri, pool, ref, dense = s["h"], s["eri"], s["pool"], s["ref"], s["dense"]
+    e_hf = hf_energy_closed_form(h, eri, 2)
+
+    def so_eri(P, Q, R, S):
+        if (P & 1) != (Q & 1) or (R & 1) != (S & 1):
+            return 0.0
+        return eri[P >> 1, Q >> 1, R >> 1, S >> 1]
+
+    tested = 0
+    for k, (P, Q, R, S) in enumerate(pool.tolist()):
+        if R < 0:
+            continue
+        occ = [(ref >> x) & 1 for x in (P, Q, R, S)]
+        if occ == [0, 0, 1, 1]:
+            sign = 1.0
+            X = ref ^ (1 << R) ^ (1 << S) ^ (1 << P) ^ (1 << Q)
+        elif occ == [1, 1, 0, 0]:
+            sign = -1.0
+            X = ref ^ (1 << R) ^ (1 << S) ^ (1 << P) ^ (1 << Q)
+        else:
+            continue
+        coupling = so_eri(P, R, Q, S) - so_eri(P, S, Q, R)
+        hxx = dense.H[dense.index[X], dense.index[X]]
+        for t in (-0.4, 0.13, 1.1):
+            st = oracle.Oracle.apply_ansatz(pool, np.array([k]), np.array([t]), 0.0, ref)
+            e, _, _ = s["orc"].energy(st)
+            expect = math.cos(t) ** 2 * e_hf + math.sin(t) ** 2 * hxx + sign * math.sin(2 * t) * coupling
+            assert abs(e - expect) < 1e-12
+        tested += 1
+        if tested > 25:
+            break
+    assert tested > 5
+
+
+def test_sigma_projected_double_loop_and_dense(medium):
+    s = medium
+    st = oracle.Oracle.apply_ansatz(s["pool"], s["ops"][:25], s["theta"][:25], 1e-3, s["ref"])
+    keys, amps = st.export()
+    sig = s["orc"].sigma_projected(st)
+    loop = np.array([sum(s["orc"].hmat(int(a), int(b)) * cb for b, cb in zip(keys, amps)) for a in keys])
+    assert np.abs(sig - loop).max() < 1e-12
+    v = s["dense"].vec(dict(zip(keys.tolist(), amps)))
+    hv = s["dense"].H @ v
+    idx = [s["dense"].index[int(k)] for k in keys]
+    assert np.abs(sig - hv[idx]).max() < 1e-12
+    # sigma on arbitrary (external) determinants
+    ext = s["dense"].basis[::37].astype(np.uint64)
+    got = s["orc"].sigma_at(st, ext)
+    assert np.abs(got - hv[[s["dense"].index[int(k)] for k in ext]]).max() < 1e-12
+
+
+# ---------------------------------------------------------------- pool gradients
+def test_pool_gradients_at_hf_closed_form(small):
+    s = small
+    h, eri, pool, ref = s["h"], s["eri"], s["pool"], s["ref"]
+    st = oracle.OracleState.from_arrays(np.array([ref], dtype=np.uint64), np.array([1.0]))
+    g = s["orc"].pool_gradients(st, pool)
+
+    def so_eri(P, Q, R, S):
+        if (P & 1) != (Q & 1) or (R & 1) != (S & 1):
+            return 0.0
+        return eri[P >> 1, Q >> 1, R >> 1, S >> 1]
+
+    occ = [x for x in range(2 * s["n"]) if (ref >> x) & 1]
+    expect = np.zeros(len(pool))
+    for k, (P, Q, R, S) in enumerate(pool.tolist()):
+        if R < 0:
+            F = (h[P >> 1, Q >> 1] if (P & 1) == (Q & 1) else 0.0) + sum(
+                so_eri(P, Q, J, J) - so_eri(P, J, J, Q) for J in occ)
+            if ((ref >> Q) & 1) and not ((ref >> P) & 1):
+                expect[k] = 2 * F
+            elif ((ref >> P) & 1) and not ((ref >> Q) & 1):
+                expect[k] = -2 * F
+        else:
+            o = [(ref >> x) & 1 for x in (P, Q, R, S)]
+            coupling = so_eri(P, R, Q, S) - so_eri(P, S, Q, R)
+            if o == [0, 0, 1, 1]:
+                expect[k] = 2 * coupling
+            elif o == [1, 1, 0, 0]:
+                expect[k] = -2 * coupling
+    assert np.abs(g - expect).max() < 1e-12
+    assert np.count_nonzero(expect) > 20
+
+
+def test_pool_gradients_dense_commutator(small, medium):
+    for s, count in ((small, None), (medium, 60)):
+        st = oracle.Oracle.apply_ansatz(s["pool"], s["ops"], s["theta"], 1e-3, s["ref"])
+        v = s["dense"].vec(st.as_dict())
+        H = s["dense"].H
+        ks = range(len(s["pool"])) if count is None else np.random.default_rng(1).choice(
+            len(s["pool"]), count, replace=False)
+        ks = np.array(list(ks), dtype=np.int32)
+        g = s["orc"].pool_gradients(st, s["pool"], subset=ks)
+        for t, k in enumerate(ks):
+            A = s["dense"].generator_sparse(s["pool"][k])
+            expect = (v @ (H @ (A @ v)) - v @ (A @ (H @ v))) / (v @ v)
+            assert abs(g[t] - expect) < 1e-12
+
+
+def test_pool_gradients_fd_of_appended_gate(small):
+    s = small
+    st = oracle.Oracle.apply_ansatz(s["pool"], s["ops"], s["theta"], 0.0, s["ref"])
+    g = s["orc"].pool_gradients(st, s["pool"])
+    hstep = 1e-4
+    for k in np.argsort(-np.abs(g))[:6].tolist() + [3, 100, 400]:
+        ep = s["orc"].energy(oracle.Oracle.apply_ansatz(
+            s["pool"], np.append(s["ops"], k), np.append(s["theta"], hstep), 0.0, s["ref"]))[0]
+        em = s["orc"].energy(oracle.Oracle.apply_ansatz(
+            s["pool"], np.append(s["ops"], k), np.append(s["theta"], -hstep), 0.0, s["ref"]))[0]
+        assert abs((ep - em) / (2 * hstep) - g[k]) < 1e-8
+
+
+# ---------------------------------------------------------------- parameter gradients
+def test_param_gradients_central_fd_eps0(medium):
+    s = medium
+    dE, E = s["orc"].param_gradients(s["pool"], s["ops"], s["theta"], 0.0, s["ref"])
+    hstep = 1e-5
+    for i in range(0, len(s["ops"]), 3):
+        tp = s["theta"].copy(); tp[i] += hstep
+        tm = s["theta"].copy(); tm[i] -= hstep
+        ep = s["orc"].energy(oracle.Oracle.apply_ansatz(s["pool"], s["ops"], tp, 0.0, s["ref"]))[0]
+        em = s["orc"].energy(oracle.Oracle.apply_ansatz(s["pool"], s["ops"], tm, 0.0, s["ref"]))[0]
+        assert abs((ep - em) / (2 * hstep) - dE[i]) < 1e-8
+    assert np.abs(dE).max() > 1e-3
+
+
+def test_param_gradients_trig_fit(medium):
+    """E(theta_i) has frequencies 0, 1, 2 only (A has eigenvalues 0 and +-i),
+    so five samples determine it and its derivative exactly."""
+    s = medium
+    dE, _ = s["orc"].param_gradients(s["pool"], s["ops"], s["theta"], 0.0, s["ref"])
+    for i in (0, 7, 19, len(s["ops"]) - 1):
+        ts = s["theta"][i] + np.array([-0.9, -0.4, 0.0, 0.5, 1.1])
+        es = []
+        for t in ts:
+            th = s["theta"].copy(); th[i] = t
+            es.append(s["orc"].energy(oracle.Oracle.apply_ansatz(s["pool"], s["ops"], th, 0.0, s["ref"]))[0])
+        X = np.stack([np.ones(5), np.cos(ts), np.sin(ts), np.cos(2 * ts), np.sin(2 * ts)], axis=1)
+        a = np.linalg.solve(X, np.array(es))
+        t0 = s["theta"][i]
+        d = -a[1] * math.sin(t0) + a[2] * math.cos(t0) - 2 * a[3] * math.sin(2 * t0) + 2 * a[4] * math.cos(2 * t0)
+        assert abs(d - dE[i]) < 1e-11
+
+
+def test_last_parameter_is_pool_gradient(medium):
+    s = medium
+    dE, _ = s["orc"].param_gradients(s["pool"], s["ops"], s["theta"], 0.0, s["ref"])
+    st = oracle.Oracle.apply_ansatz(s["pool"], s["ops"], s["theta"], 0.0, s["ref"])
+    g = s["orc"].pool_gradients(st, s["pool"], subset=np.array([s["ops"][-1]]))
+    assert abs(g[0] - dE[-1]) < 1e-11
+
+
+def test_param_gradients_masked_fd_eps_positive(medium):
+    s = medium
+    eps = 2e-3
+    dE, E = s["orc"].param_gradients(s["pool"], s["ops"], s["theta"], eps, s["ref"])
+    e0 = s["orc"].energy_frozen(s["pool"], s["ops"], s["theta"], s["theta"], eps, s["ref"])
+    assert abs(e0 - E) < 1e-14
+    hstep = 1e-5
+    for i in range(0, len(s["ops"]), 3):
+        tp = s["theta"].copy(); tp[i] += hstep
+        tm = s["theta"].copy(); tm[i] -= hstep
+        ep = s["orc"].energy_frozen(s["pool"], s["ops"], s["theta"], tp, eps, s["ref"])
+        em = s["orc"].energy_frozen(s["pool"], s["ops"], s["theta"], tm, eps, s["ref"])
+        assert abs((ep - em) / (2 * hstep) - dE[i]) < 1e-8
+
+
+# ---------------------------------------------------------------- screener oracle
+def test_mlp_backward_finite_differences():
+    rng = np.random.default_rng(0)
+    w = oracle.mlp_init(7)
+    w[oracle.LAYOUT["b1"][0]:oracle.LAYOUT["b1"][0] + 128] = rng.normal(0, 0.1, 128)
+    x = rng.normal(size=(9, 16))
+    t = rng.normal(size=9)
+    loss, g = oracle.mlp_loss_grad(w, x, t)
+    assert oracle.N_PARAMS == 18817 and g.shape == (18817,)
+    idx = rng.choice(oracle.N_PARAMS, 60, replace=False).tolist() + [oracle.N_PARAMS - 1]
+    hstep = 1e-6
+    for j in idx:
+        wp = w.copy(); wp[j] += hstep
+        wm = w.copy(); wm[j] -= hstep
+        fd = (oracle.mlp_loss_grad(wp, x, t)[0] - oracle.mlp_loss_grad(wm, x, t)[0]) / (2 * hstep)
+        assert abs(fd - g[j]) < 1e-7 * max(1.0, abs(g[j]))
+
+
+def test_adam_first_step_is_signed_lr():
+    g = np.array([3.0, -0.2, 1e-3])
+    w, m, v = oracle.adam_step(np.zeros(3), np.zeros(3), np.zeros(3), g, 0.01, 0.9, 0.999, 1e-12, 1)
+    assert np.allclose(w, -0.01 * np.sign(g), rtol=1e-8)
+
+
+def test_select_subset_small_case():
+    score = np.array([0.5, 2.0, 2.0, -1.0, 0.1, 3.0, 0.0, 0.2, 0.3, 0.4])
+    rk = np.array([9, 8, 7, 6, 5, 4, 3, 2, 1, 0], dtype=np.uint32)
+    sel = oracle.select_subset(score, rk, frac_top=0.25, frac_rand=0.15)
+    # top ceil(2.5)=3: 5 (3.0), 1 and 2 (2.0); random ceil(1.5)=2 smallest keys among rest: 9, 8
+    assert sel.tolist() == [1, 2, 5, 8, 9]
+
+
+def test_features_hand_case():
+    n = 3
+    h, eri = make_integrals(n, 2, 5)
+    fock = oracle.fock_spatial(h, eri, 1)
+    pool = np.array([[2, 0, -1, -1], [3, 2, 1, 0]], dtype=np.int32)
+    occ = np.array([0.9, 0.8, 0.1, 0.2, 0.05, 0.0])
+    F = oracle.features(pool, fock, eri, occ, np.array([0.0, 0.5]), np.array([3, 0]), np.array([0, 2]))
+    f00 = h[0, 0] + 2 * eri[0, 0, 0, 0] - eri[0, 0, 0, 0]
+    assert abs(fock[0, 0] - f00) < 1e-15
+    assert F[0, 0] == fock[1, 1] and F[0, 1] == fock[0, 0] and F[0, 2] == 0.0
+    assert F[0, 4] == abs(fock[1, 0]) and F[0, 12] == 1.0 and F[0, 11] == 0.3
+    assert F[0, 5] == occ[2] and F[0, 6] == occ[0]
+    assert F[1, 4] == abs(eri[1, 0, 1, 0]) and F[1, 14] == 1.0 and F[1, 15] == 2
+    assert F[1, 9] == 0.5 and abs(F[1, 10] - math.log10(0.5)) < 1e-15
+
+
+def test_sector_size_counts():
+    assert sector_size(6, 2, 2) == 225
+    assert sector_size(14, 5, 5) == 4008004
