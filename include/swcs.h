@@ -132,6 +132,12 @@ int swcs_get_state(swcs_ctx* ctx, uint64_t* keys, double* amps, int64_t cap, int
  * Any output pointer may be NULL. */
 int swcs_energy(swcs_ctx* ctx, double* E, double* numer, double* norm2);
 
+/* The projected sigma vector sigma_P(D) = sum_{D' in psi} H_{D D'} psi(D')
+ * on the kept determinants, exported as (key, sigma) pairs sorted by key into
+ * caller arrays of length cap (same size rules as swcs_get_state).  E is
+ * sum psi sigma_P / sum psi^2. */
+int swcs_sigma_projected(swcs_ctx* ctx, uint64_t* keys, double* sigma, int64_t cap, int64_t* n);
+
 /* ADAPT step 4 (Sec. II.C): g_k = <psi|[H, A_k]|psi> / <psi|psi>, the
  * derivative of E with respect to the parameter of pool operator k appended
  * at the end of the ansatz, for k in subset[n_subset] (host int32; NULL =

@@ -1,0 +1,328 @@
+// Sigma-vector kernels: the projected sigma vector and energy, the external
+// sigma vector pushed into an accumulation table, the pool-gradient
+// contraction, occupations and deterministic reductions.
+//
+// Matrix elements follow the Slater-Condon rules (Szabo & Ostlund, cited in
+// Sec. III) for H = sum h a+a + 1/2 sum (pq|rs) a+a+aa.  Each determinant's
+// spin-conserving singles and doubles are enumerated by a flat connection
+// index; the occupied / virtual lists and a pair-unranking table are staged
+// in LDS once per determinant so every lane decodes its connections from LDS.
+#include "swcs_internal.h"
+
+namespace swcs {
+
+constexpr int kSigBlock = 256;
+constexpr int kMaxPairs = 32 * 31 / 2;
+
+struct SigShared {
+  int occ_a[32], occ_b[32], vir_a[32], vir_b[32];
+  unsigned char px[kMaxPairs], py[kMaxPairs];
+};
+
+__device__ inline void build_pair_table(SigShared& S) {
+  for (int t = threadIdx.x; t < kMaxPairs; t += blockDim.x) {
+    int y = 1;
+    while ((y + 1) * y / 2 <= t) ++y;
+    S.py[t] = (unsigned char)y;
+    S.px[t] = (unsigned char)(t - y * (y - 1) / 2);
+  }
+}
+
+// Thread p < n places spatial orbital p in the alpha / beta lists.
+__device__ inline void build_lists_shared(u64 D, int n, SigShared& S) {
+  const int p = threadIdx.x;
+  if (p < n) {
+    const u64 below = (p == 0) ? 0ULL : ((1ULL << (2 * p)) - 1ULL);
+    const u64 amask = 0x5555555555555555ULL, bmask = 0xAAAAAAAAAAAAAAAAULL;
+    const u64 occ_below = D & below, vir_below = ~D & below;
+    if ((D >> (2 * p)) & 1ULL) S.occ_a[__popcll(occ_below & amask)] = 2 * p;
+    else S.vir_a[__popcll(vir_below & amask)] = 2 * p;
+    if ((D >> (2 * p + 1)) & 1ULL) S.occ_b[__popcll(occ_below & bmask)] = 2 * p + 1;
+    else S.vir_b[__popcll(vir_below & bmask)] = 2 * p + 1;
+  }
+}
+
+// Decode connection c (0 <= c < E.total) into holes h0 < h1, particles p0 < p1.
+__device__ inline int decode_shared(const ExcSpace& E, const SigShared& S, int c, int* h0, int* h1,
+                                    int* p0, int* p1) {
+  if (c < (int)E.s_a) {
+    const int i = c / E.va, a = c - (c / E.va) * E.va;
+    *h0 = S.occ_a[i]; *p0 = S.vir_a[a];
+    return 1;
+  }
+  c -= (int)E.s_a;
+  if (c < (int)E.s_b) {
+    const int i = c / E.vb, a = c - (c / E.vb) * E.vb;
+    *h0 = S.occ_b[i]; *p0 = S.vir_b[a];
+    return 1;
+  }
+  c -= (int)E.s_b;
+  if (c < (int)E.d_aa) {
+    const int nv = E.va * (E.va - 1) / 2;
+    const int io = c / nv, iv = c - io * nv;
+    *h0 = S.occ_a[S.px[io]]; *h1 = S.occ_a[S.py[io]];
+    *p0 = S.vir_a[S.px[iv]]; *p1 = S.vir_a[S.py[iv]];
+    return 2;
+  }
+  c -= (int)E.d_aa;
+  if (c < (int)E.d_bb) {
+    const int nv = E.vb * (E.vb - 1) / 2;
+    const int io = c / nv, iv = c - io * nv;
+    *h0 = S.occ_b[S.px[io]]; *h1 = S.occ_b[S.py[io]];
+    *p0 = S.vir_b[S.px[iv]]; *p1 = S.vir_b[S.py[iv]];
+    return 2;
+  }
+  c -= (int)E.d_bb;
+  const int vv = E.va * E.vb;
+  const int ij = c / vv, ab = c - ij * vv;
+  const int i = ij / E.nb, j = ij - i * E.nb;
+  const int a = ab / E.vb, b = ab - a * E.vb;
+  const int Ia = S.occ_a[i], Jb = S.occ_b[j], Aa = S.vir_a[a], Bb = S.vir_b[b];
+  *h0 = min(Ia, Jb); *h1 = max(Ia, Jb);
+  *p0 = min(Aa, Bb); *p1 = max(Aa, Bb);
+  return 2;
+}
+
+__device__ inline double block_sum(double v, double* red) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = kSigBlock / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+// sigma_P(D) = sum_{D' in psi} H_{D D'} psi(D') for every stored entry D
+// (dead entries get 0), plus per-block partial sums of psi*sigma and psi^2.
+__global__ void __launch_bounds__(kSigBlock)
+k_sigma_proj(const u64* __restrict__ keys, const double* __restrict__ amps,
+             const HashSlot* __restrict__ hash, u64 hmask, Ints I, ExcSpace E, u64 n,
+             double* __restrict__ sigma, double* __restrict__ partial) {
+  __shared__ SigShared S;
+  __shared__ double red[kSigBlock];
+  build_pair_table(S);
+  double num = 0.0, nrm = 0.0;
+  const int C = (int)E.total;
+  for (u64 d = blockIdx.x; d < n; d += gridDim.x) {
+    const double psiD = amps[d];
+    if (is_dead(psiD)) {
+      if (threadIdx.x == 0) sigma[d] = 0.0;
+      continue;
+    }
+    const u64 D = keys[d];
+    __syncthreads();
+    build_lists_shared(D, I.n, S);
+    __syncthreads();
+    double acc = 0.0;
+    for (int c = threadIdx.x; c < C; c += kSigBlock) {
+      int h0, h1 = 0, p0, p1 = 0;
+      const int nh = decode_shared(E, S, c, &h0, &h1, &p0, &p1);
+      u64 X = D ^ (1ULL << h0) ^ (1ULL << p0);
+      if (nh == 2) X ^= (1ULL << h1) ^ (1ULL << p1);
+      const long long j = hash_find(hash, hmask, X);
+      if (j < 0) continue;
+      const double psiX = amps[j];
+      if (is_dead(psiX)) continue;
+      acc += connection_element(I, D, nh, h0, h1, p0, p1) * psiX;
+    }
+    if (threadIdx.x == 0) acc += diag_element(I, D) * psiD;
+    const double sig = block_sum(acc, red);
+    if (threadIdx.x == 0) {
+      sigma[d] = sig;
+      num += psiD * sig;
+      nrm += psiD * psiD;
+    }
+  }
+  if (threadIdx.x == 0) {
+    partial[blockIdx.x] = num;
+    partial[gridDim.x + blockIdx.x] = nrm;
+  }
+}
+
+// Batch of an external determinant when the accumulation table is split.
+__device__ inline int batch_of(u64 X, int nbatch) {
+  return (int)((mix64(X ^ 0x9e3779b97f4a7c15ULL) >> 32) % (u64)nbatch);
+}
+
+// sigma(X) += H_{X D'} psi(D') for every stored, alive D' and every X among
+// D' and its singles and doubles (only X of the current batch).
+__global__ void __launch_bounds__(kSigBlock)
+k_sigma_push(const u64* __restrict__ keys, const double* __restrict__ amps, Ints I, ExcSpace E,
+             u64 n, AccSlot* __restrict__ tab, u64 tmask, int nbatch, int batch,
+             unsigned* __restrict__ flags) {
+  __shared__ SigShared S;
+  build_pair_table(S);
+  const int C = (int)E.total;
+  for (u64 d = blockIdx.x; d < n; d += gridDim.x) {
+    const double psiD = amps[d];
+    if (is_dead(psiD)) continue;
+    const u64 D = keys[d];
+    __syncthreads();
+    build_lists_shared(D, I.n, S);
+    __syncthreads();
+    if (threadIdx.x == 0 && (nbatch == 1 || batch_of(D, nbatch) == batch))
+      if (!acc_add(tab, tmask, D, diag_element(I, D) * psiD)) atomicOr(flags, kFlagOverflow);
+    for (int c = threadIdx.x; c < C; c += kSigBlock) {
+      int h0, h1 = 0, p0, p1 = 0;
+      const int nh = decode_shared(E, S, c, &h0, &h1, &p0, &p1);
+      u64 X = D ^ (1ULL << h0) ^ (1ULL << p0);
+      if (nh == 2) X ^= (1ULL << h1) ^ (1ULL << p1);
+      if (nbatch > 1 && batch_of(X, nbatch) != batch) continue;
+      if (!acc_add(tab, tmask, X, connection_element(I, D, nh, h0, h1, p0, p1) * psiD))
+        atomicOr(flags, kFlagOverflow);
+    }
+  }
+}
+
+// Pool-gradient contraction, operator-major.  Block (x, y) takes a tile of
+// determinants staged in LDS (x) and 256 pool operators, one per thread (y); each
+// thread accumulates psi(D) a_k(D) sigma(X_k(D)) over the tile, where
+// a_k(D) = <X|T|D> if T acts on D and -<X|T^dagger|D> if T^dagger does.
+constexpr int kContractTile = 1024;
+
+__global__ void __launch_bounds__(256)
+k_pool_contract(const u64* __restrict__ keys, const double* __restrict__ amps, u64 n,
+                const OpDesc* __restrict__ ops, const int* __restrict__ subset, long long n_ops,
+                const AccSlot* __restrict__ tab, u64 tmask, double* __restrict__ g, double scale) {
+  __shared__ u64 skey[kContractTile];
+  __shared__ double samp[kContractTile];
+  const u64 t0 = (u64)blockIdx.x * kContractTile;
+  const int tile = (int)((n - t0) < (u64)kContractTile ? (n - t0) : (u64)kContractTile);
+  for (int t = threadIdx.x; t < tile; t += blockDim.x) {
+    const double a = amps[t0 + t];
+    skey[t] = is_dead(a) ? 0ULL : keys[t0 + t];
+    samp[t] = a;
+  }
+  __syncthreads();
+  const long long slot = (long long)blockIdx.y * blockDim.x + threadIdx.x;
+  if (slot >= n_ops) return;
+  const int k = subset ? subset[slot] : (int)slot;
+  const OpDesc op = ops[k];
+  const u64 pm = op.ann | op.cre;
+  double acc = 0.0;
+  for (int t = 0; t < tile; ++t) {
+    const u64 D = skey[t];
+    if (D == 0ULL) continue;
+    const bool isT = ((D & op.ann) == op.ann) && ((D & op.cre) == 0);
+    const bool isTd = ((D & op.cre) == op.cre) && ((D & op.ann) == 0);
+    if (!(isT || isTd)) continue;
+    const u64 X = D ^ pm;
+    double sx;
+    if (!acc_find(tab, tmask, X, &sx)) continue;
+    const double a = isT ? (double)phase_of_T(op, D) : -(double)phase_of_T(op, X);
+    acc += samp[t] * a * sx;
+  }
+  if (acc != 0.0) unsafeAtomicAdd(&g[slot], scale * acc);
+}
+
+// Per-block partial sums of psi^2 [P in D] for P < nso and of psi^2.
+__global__ void __launch_bounds__(256)
+k_occupations(const u64* __restrict__ keys, const double* __restrict__ amps, u64 n, int nso,
+              double* __restrict__ partial) {
+  __shared__ double red[256];
+  double acc[65];
+  for (int P = 0; P <= nso; ++P) acc[P] = 0.0;
+  const u64 stride = (u64)gridDim.x * blockDim.x;
+  for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const double a = amps[i];
+    if (is_dead(a)) continue;
+    const double w = a * a;
+    const u64 D = keys[i];
+    for (int P = 0; P < nso; ++P)
+      if ((D >> P) & 1ULL) acc[P] += w;
+    acc[nso] += w;
+  }
+  for (int P = 0; P <= nso; ++P) {
+    red[threadIdx.x] = acc[P];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[(size_t)P * gridDim.x + blockIdx.x] = red[0];
+    __syncthreads();
+  }
+}
+
+// out[v] = sum_{b < count} partial[v * stride + b] in a fixed order.
+__global__ void k_reduce_partials(const double* __restrict__ partial, int count, int stride,
+                                  double* __restrict__ out) {
+  __shared__ double red[256];
+  const int v = blockIdx.x;
+  double acc = 0.0;
+  for (int b = threadIdx.x; b < count; b += blockDim.x) acc += partial[(size_t)v * stride + b];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[v] = red[0];
+}
+
+// mu = scale * (sigma - E psi) on alive entries, 0 elsewhere.
+__global__ void k_mu_init(const double* __restrict__ amps, const double* __restrict__ sigma, u64 n,
+                          double scale, double E, double* __restrict__ mu) {
+  const u64 stride = (u64)gridDim.x * blockDim.x;
+  for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const double a = amps[i];
+    mu[i] = is_dead(a) ? 0.0 : scale * (sigma[i] - E * a);
+  }
+}
+
+hipError_t launch_sigma_proj(const DeviceState& st, const Ints& I, const ExcSpace& E, u64 n,
+                             double* sigma, double* partial_num, double* partial_norm, int grid,
+                             hipStream_t stream) {
+  (void)partial_norm;
+  hipLaunchKernelGGL(k_sigma_proj, dim3(grid), dim3(kSigBlock), 0, stream, st.keys, st.amps,
+                     st.hash, st.hmask, I, E, n, sigma, partial_num);
+  return hipGetLastError();
+}
+
+hipError_t launch_mu_init(const DeviceState& st, const double* sigma, u64 n, double scale, double E,
+                          double* mu, hipStream_t stream) {
+  u64 g = (n + 255) / 256;
+  if (g < 1) g = 1;
+  if (g > 8192) g = 8192;
+  hipLaunchKernelGGL(k_mu_init, dim3((unsigned)g), dim3(256), 0, stream, st.amps, sigma, n, scale,
+                     E, mu);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_partials(const double* partial, int count, int stride, int nvec,
+                                  double* out, hipStream_t stream) {
+  hipLaunchKernelGGL(k_reduce_partials, dim3(nvec), dim3(256), 0, stream, partial, count, stride,
+                     out);
+  return hipGetLastError();
+}
+
+hipError_t launch_sigma_push(const DeviceState& st, const Ints& I, const ExcSpace& E, u64 n,
+                             AccSlot* tab, u64 tmask, int nbatch, int batch, int grid,
+                             hipStream_t stream) {
+  hipLaunchKernelGGL(k_sigma_push, dim3(grid), dim3(kSigBlock), 0, stream, st.keys, st.amps, I, E,
+                     n, tab, tmask, nbatch, batch, &st.ctr->flags);
+  return hipGetLastError();
+}
+
+hipError_t launch_pool_contract_ops(const DeviceState& st, u64 n, const OpDesc* ops,
+                                    const int* subset, long long n_ops, const AccSlot* tab,
+                                    u64 tmask, double* g, double scale, hipStream_t stream) {
+  if (n == 0 || n_ops == 0) return hipSuccess;
+  const unsigned gy = (unsigned)((n_ops + 255) / 256);
+  const unsigned gx = (unsigned)((n + kContractTile - 1) / kContractTile);
+  hipLaunchKernelGGL(k_pool_contract, dim3(gx, gy), dim3(256), 0, stream, st.keys, st.amps, n, ops,
+                     subset, n_ops, tab, tmask, g, scale);
+  return hipGetLastError();
+}
+
+hipError_t launch_occupations(const DeviceState& st, u64 n, int nso, double* partial, int grid,
+                              hipStream_t stream) {
+  hipLaunchKernelGGL(k_occupations, dim3(grid), dim3(256), 0, stream, st.keys, st.amps, n, nso,
+                     partial);
+  return hipGetLastError();
+}
+
+}  // namespace swcs

@@ -1,0 +1,289 @@
+// Stable LSD radix sort of 64-bit keys (with optional 64-bit payloads),
+// alive-entry compaction and the screener's top-k + random selection.
+//
+// One 8-bit digit per pass: (1) per-tile digit histograms, (2) one exclusive
+// scan over (digit, tile) in digit-major order, (3) a stable scatter in which
+// each 256-item row of a tile ranks its items by wave ballots on the digit
+// bits and a prefix over the four waves.  Only ceil(key_bits / 8) passes run.
+#include "swcs_internal.h"
+
+namespace swcs {
+
+constexpr int kSortThreads = 256;
+constexpr int kSortRows = 16;
+constexpr int kSortTile = kSortThreads * kSortRows;
+
+__global__ void __launch_bounds__(kSortThreads)
+k_radix_hist(const u64* __restrict__ keys, u64 count, int shift, u64* __restrict__ counts,
+             int nblocks) {
+  __shared__ unsigned hist[256];
+  hist[threadIdx.x] = 0;
+  __syncthreads();
+  const u64 base = (u64)blockIdx.x * kSortTile;
+  for (int r = 0; r < kSortRows; ++r) {
+    const u64 i = base + (u64)r * kSortThreads + threadIdx.x;
+    if (i < count) atomicAdd(&hist[(keys[i] >> shift) & 255u], 1u);
+  }
+  __syncthreads();
+  counts[(u64)threadIdx.x * nblocks + blockIdx.x] = hist[threadIdx.x];
+}
+
+// In-place exclusive scan of data[len] with one block of 1024 threads.
+__global__ void __launch_bounds__(1024) k_scan_exclusive(u64* __restrict__ data, u64 len) {
+  __shared__ u64 part[1024];
+  const u64 per = (len + 1023) / 1024;
+  const u64 lo = (u64)threadIdx.x * per;
+  const u64 hi = (lo + per < len) ? lo + per : len;
+  u64 s = 0;
+  for (u64 i = lo; i < hi; ++i) s += data[i];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    u64 v = (threadIdx.x >= (unsigned)off) ? part[threadIdx.x - off] : 0;
+    __syncthreads();
+    part[threadIdx.x] += v;
+    __syncthreads();
+  }
+  u64 run = (threadIdx.x == 0) ? 0 : part[threadIdx.x - 1];
+  for (u64 i = lo; i < hi; ++i) {
+    const u64 v = data[i];
+    data[i] = run;
+    run += v;
+  }
+}
+
+__global__ void __launch_bounds__(kSortThreads)
+k_radix_scatter(const u64* __restrict__ keys_in, const u64* __restrict__ vals_in, u64 count,
+                int shift, const u64* __restrict__ offsets, int nblocks, u64* __restrict__ keys_out,
+                u64* __restrict__ vals_out) {
+  __shared__ u64 base_off[256];
+  __shared__ unsigned running[256];
+  __shared__ unsigned wave_cnt[4][256];
+  const int lane = __lane_id();
+  const int wave = threadIdx.x >> 6;
+  base_off[threadIdx.x] = offsets[(u64)threadIdx.x * nblocks + blockIdx.x];
+  running[threadIdx.x] = 0;
+  const u64 tile0 = (u64)blockIdx.x * kSortTile;
+  for (int r = 0; r < kSortRows; ++r) {
+    for (int w = 0; w < 4; ++w) wave_cnt[w][threadIdx.x] = 0;
+    __syncthreads();
+    const u64 i = tile0 + (u64)r * kSortThreads + threadIdx.x;
+    const bool valid = i < count;
+    u64 key = 0, val = 0;
+    unsigned digit = 0;
+    if (valid) {
+      key = keys_in[i];
+      if (vals_in) val = vals_in[i];
+      digit = (unsigned)((key >> shift) & 255u);
+    }
+    u64 peers = __ballot(valid);
+    for (int b = 0; b < 8; ++b) {
+      const u64 m = __ballot(valid && ((digit >> b) & 1u));
+      peers &= ((digit >> b) & 1u) ? m : ~m;
+    }
+    const unsigned below = (unsigned)__popcll(peers & ((1ULL << lane) - 1ULL));
+    if (valid && below == 0) wave_cnt[wave][digit] = (unsigned)__popcll(peers);
+    __syncthreads();
+    if (valid) {
+      unsigned before = running[digit] + below;
+      for (int w = 0; w < wave; ++w) before += wave_cnt[w][digit];
+      const u64 dst = base_off[digit] + before;
+      keys_out[dst] = key;
+      if (vals_in) vals_out[dst] = val;
+    }
+    __syncthreads();
+    running[threadIdx.x] += wave_cnt[0][threadIdx.x] + wave_cnt[1][threadIdx.x] +
+                            wave_cnt[2][threadIdx.x] + wave_cnt[3][threadIdx.x];
+    __syncthreads();
+  }
+}
+
+u64 radix_sort_scratch_elems(u64 count) {
+  const u64 nblocks = (count + kSortTile - 1) / kSortTile;
+  return 256 * (nblocks < 1 ? 1 : nblocks);
+}
+
+// Sorts (keys, vals) ascending by the low key_bits bits of the key.  The
+// result ends in keys / vals; tmp_* are ping-pong buffers of the same size.
+hipError_t radix_sort_pairs(u64* keys, u64* vals, u64* tmp_keys, u64* tmp_vals, u64 count,
+                            int key_bits, u64* scratch, u64 scratch_elems, hipStream_t stream) {
+  if (count <= 1) return hipSuccess;
+  const int nblocks = (int)((count + kSortTile - 1) / kSortTile);
+  if ((u64)256 * nblocks > scratch_elems) return hipErrorInvalidValue;
+  const int passes = (key_bits + 7) / 8;
+  u64 *kin = keys, *vin = vals, *kout = tmp_keys, *vout = tmp_vals;
+  for (int p = 0; p < passes; ++p) {
+    const int shift = 8 * p;
+    hipLaunchKernelGGL(k_radix_hist, dim3(nblocks), dim3(kSortThreads), 0, stream, kin, count, shift,
+                       scratch, nblocks);
+    hipLaunchKernelGGL(k_scan_exclusive, dim3(1), dim3(1024), 0, stream, scratch,
+                       (u64)256 * nblocks);
+    hipLaunchKernelGGL(k_radix_scatter, dim3(nblocks), dim3(kSortThreads), 0, stream, kin, vin,
+                       count, shift, scratch, nblocks, kout, vout);
+    u64* t = kin; kin = kout; kout = t;
+    t = vin; vin = vout; vout = t;
+  }
+  if (kin != keys) {
+    hipMemcpyAsync(keys, kin, count * sizeof(u64), hipMemcpyDeviceToDevice, stream);
+    if (vals) hipMemcpyAsync(vals, vin, count * sizeof(u64), hipMemcpyDeviceToDevice, stream);
+  }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- compaction
+// Per-tile counts of alive entries, scan, then an order-preserving scatter.
+__global__ void __launch_bounds__(kSortThreads)
+k_alive_count(const double* __restrict__ amps, u64 n, u64* __restrict__ counts) {
+  __shared__ unsigned c;
+  if (threadIdx.x == 0) c = 0;
+  __syncthreads();
+  const u64 base = (u64)blockIdx.x * kSortTile;
+  unsigned mine = 0;
+  for (int r = 0; r < kSortRows; ++r) {
+    const u64 i = base + (u64)r * kSortThreads + threadIdx.x;
+    if (i < n && !is_dead(amps[i])) ++mine;
+  }
+  atomicAdd(&c, mine);
+  __syncthreads();
+  if (threadIdx.x == 0) counts[blockIdx.x] = c;
+}
+
+__global__ void __launch_bounds__(kSortThreads)
+k_alive_scatter(const u64* __restrict__ keys, const double* __restrict__ amps,
+                const double* __restrict__ vals, u64 n, const u64* __restrict__ offsets,
+                u64* __restrict__ out_keys,
+                double* __restrict__ out_amps, u64* __restrict__ d_count, int nblocks) {
+  __shared__ unsigned wave_cnt[4];
+  __shared__ unsigned running;
+  const int lane = __lane_id();
+  const int wave = threadIdx.x >> 6;
+  if (threadIdx.x == 0) running = 0;
+  const u64 base = (u64)blockIdx.x * kSortTile;
+  const u64 off = offsets[blockIdx.x];
+  for (int r = 0; r < kSortRows; ++r) {
+    const u64 i = base + (u64)r * kSortThreads + threadIdx.x;
+    const bool keep = i < n && !is_dead(amps[i]);
+    const u64 m = __ballot(keep);
+    if (lane == 0) wave_cnt[wave] = (unsigned)__popcll(m);
+    __syncthreads();
+    if (keep) {
+      unsigned pos = running + (unsigned)__popcll(m & ((1ULL << lane) - 1ULL));
+      for (int w = 0; w < wave; ++w) pos += wave_cnt[w];
+      out_keys[off + pos] = keys[i];
+      out_amps[off + pos] = vals[i];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) running += wave_cnt[0] + wave_cnt[1] + wave_cnt[2] + wave_cnt[3];
+    __syncthreads();
+  }
+  if (blockIdx.x == nblocks - 1 && threadIdx.x == 0) *d_count = off + running;
+}
+
+u64 compact_scratch_elems(u64 n) { return (n + kSortTile - 1) / kSortTile + 1; }
+
+// Alive entries in storage order: keys and vals[i] (vals = amps by default).
+hipError_t launch_compact_alive(const DeviceState& st, u64 n, const double* vals, u64* out_keys,
+                                double* out_amps, u64* d_count, u64* scratch, u64 scratch_elems,
+                                hipStream_t stream) {
+  if (!vals) vals = st.amps;
+  const int nblocks = (int)((n + kSortTile - 1) / kSortTile);
+  if (n == 0) return hipMemsetAsync(d_count, 0, sizeof(u64), stream);
+  if ((u64)nblocks > scratch_elems) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_alive_count, dim3(nblocks), dim3(kSortThreads), 0, stream, st.amps, n,
+                     scratch);
+  hipLaunchKernelGGL(k_scan_exclusive, dim3(1), dim3(1024), 0, stream, scratch, (u64)nblocks);
+  hipLaunchKernelGGL(k_alive_scatter, dim3(nblocks), dim3(kSortThreads), 0, stream, st.keys,
+                     st.amps, vals, n, scratch, out_keys, out_amps, d_count, nblocks);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- selection
+// Order-preserving map of a float to uint32 (larger float -> larger code).
+__device__ inline unsigned float_code(float f) {
+  const unsigned b = __float_as_uint(f);
+  return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+
+__global__ void k_select_keys_top(const float* __restrict__ score, long long K, u64* __restrict__ out) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < K) out[i] = ((u64)(~float_code(score[i])) << 32) | (u64)i;
+}
+
+__global__ void k_select_mark(const u64* __restrict__ sorted, long long take,
+                              unsigned char* __restrict__ flags) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < take) flags[sorted[i] & 0xffffffffULL] = 1;
+}
+
+__global__ void k_select_keys_rand(const uint32_t* __restrict__ rnd,
+                                   const unsigned char* __restrict__ flags, long long K,
+                                   u64* __restrict__ out) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < K) out[i] = flags[i] ? ~0ULL : (((u64)rnd[i] << 32) | (u64)i);
+}
+
+__global__ void k_select_clear(unsigned char* flags, long long K) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < K) flags[i] = 0;
+}
+
+// Ascending list of flagged indices: one block, running prefix over chunks.
+__global__ void __launch_bounds__(256)
+k_select_gather(const unsigned char* __restrict__ flags, long long K, int* __restrict__ idx) {
+  __shared__ unsigned wave_cnt[4];
+  __shared__ unsigned long long running;
+  const int lane = __lane_id();
+  const int wave = threadIdx.x >> 6;
+  if (threadIdx.x == 0) running = 0;
+  __syncthreads();
+  for (long long b = 0; b < K; b += 256) {
+    const long long i = b + threadIdx.x;
+    const bool f = i < K && flags[i];
+    const u64 m = __ballot(f);
+    if (lane == 0) wave_cnt[wave] = (unsigned)__popcll(m);
+    __syncthreads();
+    if (f) {
+      unsigned long long pos = running + (unsigned)__popcll(m & ((1ULL << lane) - 1ULL));
+      for (int w = 0; w < wave; ++w) pos += wave_cnt[w];
+      idx[pos] = (int)i;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) running += wave_cnt[0] + wave_cnt[1] + wave_cnt[2] + wave_cnt[3];
+    __syncthreads();
+  }
+}
+
+u64 select_scratch_elems(long long K) {
+  // keys, tmp keys, flags (bytes, rounded up), sort histogram scratch
+  return 2 * (u64)K + ((u64)K + 7) / 8 + radix_sort_scratch_elems((u64)K);
+}
+
+hipError_t launch_select(const float* score, const uint32_t* rnd, long long K, long long n_top,
+                         long long n_rand, int* idx, u64* scratch, u64 scratch_elems,
+                         hipStream_t stream) {
+  if (scratch_elems < select_scratch_elems(K)) return hipErrorInvalidValue;
+  u64* keys = scratch;
+  u64* tmp = scratch + K;
+  unsigned char* flags = (unsigned char*)(scratch + 2 * K);
+  u64* hist = scratch + 2 * K + (K + 7) / 8;
+  const u64 hist_elems = radix_sort_scratch_elems((u64)K);
+  const unsigned g = (unsigned)((K + 255) / 256);
+  hipLaunchKernelGGL(k_select_clear, dim3(g), dim3(256), 0, stream, flags, K);
+  hipLaunchKernelGGL(k_select_keys_top, dim3(g), dim3(256), 0, stream, score, K, keys);
+  hipError_t e = radix_sort_pairs(keys, nullptr, tmp, nullptr, (u64)K, 64, hist, hist_elems, stream);
+  if (e != hipSuccess) return e;
+  if (n_top > 0)
+    hipLaunchKernelGGL(k_select_mark, dim3((unsigned)((n_top + 255) / 256)), dim3(256), 0, stream,
+                       keys, n_top, flags);
+  if (n_rand > 0) {
+    hipLaunchKernelGGL(k_select_keys_rand, dim3(g), dim3(256), 0, stream, rnd, flags, K, keys);
+    e = radix_sort_pairs(keys, nullptr, tmp, nullptr, (u64)K, 64, hist, hist_elems, stream);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_select_mark, dim3((unsigned)((n_rand + 255) / 256)), dim3(256), 0, stream,
+                       keys, n_rand, flags);
+  }
+  hipLaunchKernelGGL(k_select_gather, dim3(1), dim3(256), 0, stream, flags, K, idx);
+  return hipGetLastError();
+}
+
+}  // namespace swcs

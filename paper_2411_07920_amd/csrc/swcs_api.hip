@@ -1,0 +1,906 @@
+// C ABI of libswcs: argument validation, device memory, and the host
+// orchestration of the kernels in k_state / k_sigma / k_sort / k_screener.
+// Declarations and the contract of every call are in include/swcs.h.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/swcs.h"
+#include "swcs_internal.h"
+
+using namespace swcs;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+// Device buffer that grows on demand (contents are not preserved on growth).
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  hipError_t ensure(size_t want) {
+    if (want <= bytes && p) return hipSuccess;
+    if (p) hipFree(p);
+    p = nullptr;
+    bytes = 0;
+    if (want == 0) want = 8;
+    hipError_t e = hipMalloc(&p, want);
+    if (e != hipSuccess) {
+      p = nullptr;
+      return e;
+    }
+    bytes = want;
+    return hipSuccess;
+  }
+  void release() {
+    if (p) hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  template <class T> T* as() const { return (T*)p; }
+};
+
+u64 next_pow2(u64 x) {
+  u64 p = 1;
+  while (p < x) p <<= 1;
+  return p;
+}
+
+double binom(int n, int k) {
+  if (k < 0 || k > n) return 0.0;
+  double r = 1.0;
+  for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
+  return r;
+}
+
+}  // namespace
+
+struct swcs_ctx {
+  int n = 0, na = 0, nb = 0, nso = 0, device = 0, num_cu = 1;
+  hipStream_t stream = nullptr;
+  std::string err;
+  int64_t max_dets = 0;
+  u64 sector = 0;
+  ExcSpace exc;
+
+  // integrals
+  bool have_ints = false;
+  double ecore = 0.0;
+  DevBuf h, eri, J, K, fock;
+
+  // reference and pool
+  bool have_ref = false;
+  u64 ref = 0;
+  bool have_pool = false;
+  int64_t K_pool = 0;
+  std::vector<OpDesc> ops_host;
+  std::vector<int32_t> pool_rows;
+  DevBuf ops;
+
+  // state
+  DevBuf keys, amps, hash, ctr;
+  DeviceState st;
+  bool have_state = false;
+  u64 peak_n = 0;
+
+  // last ansatz (for parameter gradients)
+  bool ansatz_valid = false;
+  std::vector<int32_t> a_ops;
+  std::vector<double> a_theta, a_c, a_s;
+  double a_eps = 0.0;
+  int64_t a_ncut = 0;
+  int seg = 1;
+  std::vector<DevBuf> ckpt;
+  DevBuf ckpt_n;      // u64 per checkpoint
+  DevBuf gate_n_in;   // u64 per gate of the last apply call
+  int64_t last_M = 0;
+
+  // scratch
+  DevBuf partial, partial2, sigma, mu, work, seg_states, acc_tab, gbuf, subset_buf, scalars,
+      exp_keys, exp_amps, exp_tmp_k, exp_tmp_v, sort_scratch, ctr_r, occ, sel_scratch, mlp_partial;
+
+  ~swcs_ctx() {
+    DevBuf* all[] = {&h, &eri, &J, &K, &fock, &ops, &keys, &amps, &hash, &ctr, &ckpt_n, &gate_n_in,
+                     &partial, &partial2, &sigma, &mu, &work, &seg_states, &acc_tab, &gbuf,
+                     &subset_buf, &scalars, &exp_keys, &exp_amps, &exp_tmp_k, &exp_tmp_v,
+                     &sort_scratch, &ctr_r, &occ, &sel_scratch, &mlp_partial};
+    for (DevBuf* b : all) b->release();
+    for (auto& b : ckpt) b.release();
+  }
+};
+
+namespace {
+
+int fail(swcs_ctx* c, int code, const std::string& msg) {
+  c->err = msg;
+  return code;
+}
+
+int hip_fail(swcs_ctx* c, hipError_t e, const char* where) {
+  int code = (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) ? SWCS_E_OOM : SWCS_E_DEVICE;
+  c->err = std::string(where) + ": " + hipGetErrorString(e);
+  return code;
+}
+
+#define HIP_TRY(ctx, expr, where)                       \
+  do {                                                  \
+    hipError_t _e = (expr);                             \
+    if (_e != hipSuccess) return hip_fail(ctx, _e, where); \
+  } while (0)
+
+int grid_blocks(swcs_ctx* c, u64 work_items, int per_block) {
+  u64 g = (work_items + per_block - 1) / per_block;
+  u64 maxg = (u64)c->num_cu * 16;
+  if (g > maxg) g = maxg;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
+int sigma_grid(swcs_ctx* c, u64 n) {
+  u64 g = n;
+  u64 maxg = (u64)c->num_cu * 32;
+  if (g > maxg) g = maxg;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
+Ints ints_view(swcs_ctx* c) {
+  Ints I;
+  I.h = c->h.as<double>();
+  I.eri = c->eri.as<double>();
+  I.J = c->J.as<double>();
+  I.K = c->K.as<double>();
+  I.ecore = c->ecore;
+  I.n = c->n;
+  return I;
+}
+
+Counters read_counters(swcs_ctx* c, hipError_t* e) {
+  Counters h;
+  std::memset(&h, 0, sizeof(h));
+  *e = hipMemcpyAsync(&h, c->ctr.p, sizeof(Counters), hipMemcpyDeviceToHost, c->stream);
+  if (*e == hipSuccess) *e = hipStreamSynchronize(c->stream);
+  return h;
+}
+
+u64 max_capacity(swcs_ctx* c) {
+  u64 cap = c->sector;
+  if (c->max_dets > 0 && (u64)c->max_dets < cap) cap = (u64)c->max_dets;
+  if (c->max_dets <= 0) {
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) == hipSuccess) {
+      u64 lim = (u64)(free_b / 96);  // keys + amps + 2 hash slots + headroom
+      if (lim < cap) cap = lim;
+    }
+  }
+  if (cap < 16) cap = 16;
+  return cap;
+}
+
+// (Re)allocate the state arrays with capacity `cap`, preserving the first
+// n_keep entries, and rebuild the hash index.
+int state_reserve(swcs_ctx* c, u64 cap, u64 n_keep) {
+  const u64 hslots = next_pow2(2 * cap);
+  DevBuf nk, na;
+  HIP_TRY(c, nk.ensure(cap * sizeof(u64)), "alloc keys");
+  HIP_TRY(c, na.ensure(cap * sizeof(double)), "alloc amps");
+  if (n_keep > 0) {
+    HIP_TRY(c, hipMemcpyAsync(nk.p, c->keys.p, n_keep * sizeof(u64), hipMemcpyDeviceToDevice, c->stream), "copy keys");
+    HIP_TRY(c, hipMemcpyAsync(na.p, c->amps.p, n_keep * sizeof(double), hipMemcpyDeviceToDevice, c->stream), "copy amps");
+    HIP_TRY(c, hipStreamSynchronize(c->stream), "sync");
+  }
+  c->keys.release();
+  c->amps.release();
+  c->keys = nk;
+  c->amps = na;
+  nk.p = nullptr;
+  na.p = nullptr;
+  if (c->hash.bytes < hslots * sizeof(HashSlot)) {
+    c->hash.release();
+    HIP_TRY(c, c->hash.ensure(hslots * sizeof(HashSlot)), "alloc hash");
+  }
+  c->st.keys = c->keys.as<u64>();
+  c->st.amps = c->amps.as<double>();
+  c->st.hash = c->hash.as<HashSlot>();
+  c->st.cap = cap;
+  c->st.hmask = hslots - 1;
+  c->st.ctr = c->ctr.as<Counters>();
+  HIP_TRY(c, launch_hash_clear(c->st.hash, hslots, c->stream), "hash clear");
+  if (n_keep > 0) HIP_TRY(c, launch_hash_build(c->st, n_keep, c->stream), "hash build");
+  return SWCS_OK;
+}
+
+// Reset the state to the single reference determinant.
+int state_reset_to_reference(swcs_ctx* c) {
+  u64 cap = next_pow2(std::max<u64>(4096, 4 * c->peak_n));
+  cap = std::min<u64>(cap, max_capacity(c));
+  if (cap < 2) cap = 2;
+  if (!c->keys.p || c->st.cap != cap) {
+    int r = state_reserve(c, cap, 0);
+    if (r) return r;
+  } else {
+    HIP_TRY(c, launch_hash_clear(c->st.hash, c->st.hmask + 1, c->stream), "hash clear");
+  }
+  const double one = 1.0;
+  HIP_TRY(c, hipMemcpyAsync(c->keys.p, &c->ref, sizeof(u64), hipMemcpyHostToDevice, c->stream), "ref key");
+  HIP_TRY(c, hipMemcpyAsync(c->amps.p, &one, sizeof(double), hipMemcpyHostToDevice, c->stream), "ref amp");
+  Counters h;
+  std::memset(&h, 0, sizeof(h));
+  h.n = 1;
+  h.alive = 1;
+  HIP_TRY(c, hipMemcpyAsync(c->ctr.p, &h, sizeof(h), hipMemcpyHostToDevice, c->stream), "counters");
+  HIP_TRY(c, launch_hash_build(c->st, 1, c->stream), "hash build");
+  HIP_TRY(c, hipStreamSynchronize(c->stream), "sync");  // host sources above
+  c->have_state = true;
+  return SWCS_OK;
+}
+
+int check_ready(swcs_ctx* c) {
+  if (!c->have_ints) return fail(c, SWCS_E_STATE, "integrals not set");
+  if (!c->have_ref) return fail(c, SWCS_E_STATE, "reference not set");
+  if (!c->have_pool) return fail(c, SWCS_E_STATE, "pool not set");
+  return SWCS_OK;
+}
+
+int validate_gates(swcs_ctx* c, const int32_t* op_idx, const double* theta, int64_t M, double eps,
+                   int64_t ncut) {
+  if (M < 0) return fail(c, SWCS_E_INVALID, "M < 0");
+  if (M > 0 && (!op_idx || !theta)) return fail(c, SWCS_E_INVALID, "null op_idx/theta");
+  if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(c, SWCS_E_INVALID, "eps must be finite and >= 0");
+  if (ncut < 0) return fail(c, SWCS_E_INVALID, "ncut < 0");
+  if (ncut > 0) return fail(c, SWCS_E_UNSUPPORTED, "N_CUT pruning is not available in this build");
+  for (int64_t i = 0; i < M; ++i) {
+    if (op_idx[i] < 0 || op_idx[i] >= c->K_pool) return fail(c, SWCS_E_INVALID, "op index out of range");
+    if (!std::isfinite(theta[i])) return fail(c, SWCS_E_INVALID, "non-finite theta");
+  }
+  return SWCS_OK;
+}
+
+// Enqueue gates [g0, M) of (ops, c, s); checkpoints every `seg` gates when
+// ckpt is requested.  Returns after one synchronization with the counters.
+int run_chain(swcs_ctx* c, const int32_t* op_idx, const double* cs, const double* sn, int64_t M,
+              double eps, bool ckpt, Counters* out) {
+  int64_t g0 = 0;
+  for (int attempt = 0; attempt < 64; ++attempt) {
+    for (int64_t g = g0; g < M; ++g) {
+      if (ckpt && g % c->seg == 0) {
+        const int j = (int)(g / c->seg);
+        HIP_TRY(c, c->ckpt[j].ensure(c->st.cap * sizeof(double)), "alloc checkpoint");
+        HIP_TRY(c, launch_ckpt_save(c->st, c->ckpt[j].as<double>(), c->ckpt_n.as<u64>() + j,
+                                    grid_blocks(c, c->st.cap / 4, 256), c->stream), "checkpoint");
+      }
+      const OpDesc& op = c->ops_host[op_idx[g]];
+      HIP_TRY(c, launch_gate(c->st, op, cs[g], sn[g], eps, c->gate_n_in.as<u64>() + g, 1,
+                             (unsigned)g, grid_blocks(c, c->st.cap / 2, 256), c->stream), "gate");
+    }
+    hipError_t e;
+    Counters h = read_counters(c, &e);
+    if (e != hipSuccess) return hip_fail(c, e, "read counters");
+    if (h.flags & kFlagOverflow) return fail(c, SWCS_E_DEVICE, "internal overflow in gate chain");
+    if (!(h.flags & kFlagStopped)) {
+      *out = h;
+      return SWCS_OK;
+    }
+    // Grow so that the stopped gate (and a few more) fit, then resume.
+    const u64 need = h.n + h.alive;
+    u64 cap = next_pow2(std::max<u64>(2 * c->st.cap, 2 * need));
+    const u64 maxc = max_capacity(c);
+    if (cap > maxc) cap = maxc;
+    if (cap < need) return fail(c, SWCS_E_CAPACITY, "state exceeds the maximum capacity");
+    int r = state_reserve(c, cap, h.n);
+    if (r) return r;
+    g0 = (int64_t)h.stop_gate;
+    h.flags &= ~kFlagStopped;
+    h.stop_gate = 0;
+    HIP_TRY(c, hipMemcpyAsync(c->ctr.p, &h, sizeof(h), hipMemcpyHostToDevice, c->stream), "counters");
+    HIP_TRY(c, hipStreamSynchronize(c->stream), "sync");
+    // Checkpoint of the gate where the chain resumes was skipped if it lies
+    // on a segment boundary: the loop above re-enqueues it.
+  }
+  return fail(c, SWCS_E_CAPACITY, "capacity growth did not converge");
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* swcs_version(void) { return "swcs-mi355x 0.1 (gfx950)"; }
+
+int swcs_create(int n_spatial, int n_alpha, int n_beta, int device, swcs_ctx** out) {
+  if (!out) {
+    g_create_error = "out is NULL";
+    return SWCS_E_INVALID;
+  }
+  *out = nullptr;
+  if (n_spatial < 1 || 2 * n_spatial > 64 || n_alpha < 0 || n_beta < 0 || n_alpha > n_spatial ||
+      n_beta > n_spatial || n_alpha + n_beta < 1) {
+    g_create_error = "invalid orbital / electron counts (need 1 <= 2n <= 64, 0 <= n_a, n_b <= n)";
+    return SWCS_E_INVALID;
+  }
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count < 1) {
+    g_create_error = "no HIP device available";
+    return SWCS_E_UNSUPPORTED;
+  }
+  if (device < 0 || device >= count) {
+    g_create_error = "device index out of range";
+    return SWCS_E_INVALID;
+  }
+  if (hipSetDevice(device) != hipSuccess) {
+    g_create_error = "hipSetDevice failed";
+    return SWCS_E_DEVICE;
+  }
+  swcs_ctx* c = new swcs_ctx;
+  c->n = n_spatial;
+  c->na = n_alpha;
+  c->nb = n_beta;
+  c->nso = 2 * n_spatial;
+  c->device = device;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess) c->num_cu = prop.multiProcessorCount;
+  double sec = binom(n_spatial, n_alpha) * binom(n_spatial, n_beta);
+  c->sector = sec > 1e18 ? (u64)1e18 : (u64)sec;
+  c->exc = make_exc_space(n_spatial, n_alpha, n_beta);
+  if (c->ctr.ensure(sizeof(Counters)) != hipSuccess || c->scalars.ensure(64 * sizeof(double)) != hipSuccess) {
+    g_create_error = "device allocation failed";
+    delete c;
+    return SWCS_E_OOM;
+  }
+  hipMemset(c->ctr.p, 0, sizeof(Counters));
+  c->st.ctr = c->ctr.as<Counters>();
+  *out = c;
+  return SWCS_OK;
+}
+
+void swcs_destroy(swcs_ctx* ctx) {
+  if (!ctx) return;
+  hipSetDevice(ctx->device);
+  if (ctx->stream) hipStreamSynchronize(ctx->stream);
+  else hipDeviceSynchronize();
+  delete ctx;
+}
+
+const char* swcs_last_error(const swcs_ctx* ctx) {
+  if (!ctx) return g_create_error.c_str();
+  return ctx->err.c_str();
+}
+
+int swcs_set_stream(swcs_ctx* c, void* hip_stream) {
+  if (!c) return SWCS_E_INVALID;
+  c->stream = (hipStream_t)hip_stream;
+  return SWCS_OK;
+}
+
+int swcs_set_capacity(swcs_ctx* c, int64_t max_dets) {
+  if (!c) return SWCS_E_INVALID;
+  if (max_dets < 0) return fail(c, SWCS_E_INVALID, "max_dets < 0");
+  c->max_dets = max_dets;
+  return SWCS_OK;
+}
+
+int swcs_set_integrals(swcs_ctx* c, const double* h, const double* eri, double e_core) {
+  if (!c) return SWCS_E_INVALID;
+  if (!h || !eri) return fail(c, SWCS_E_INVALID, "null integrals");
+  hipSetDevice(c->device);
+  const int n = c->n;
+  const size_t n2 = (size_t)n * n, n4 = n2 * n2;
+  if (!std::isfinite(e_core)) return fail(c, SWCS_E_INVALID, "non-finite e_core");
+  for (size_t i = 0; i < n2; ++i)
+    if (!std::isfinite(h[i])) return fail(c, SWCS_E_INVALID, "non-finite h");
+  for (size_t i = 0; i < n4; ++i)
+    if (!std::isfinite(eri[i])) return fail(c, SWCS_E_INVALID, "non-finite eri");
+  for (int p = 0; p < n; ++p)
+    for (int q = 0; q < n; ++q)
+      if (std::fabs(h[p * n + q] - h[q * n + p]) > 1e-12) return fail(c, SWCS_E_INVALID, "h not symmetric");
+  auto E = [&](int p, int q, int r, int s) { return eri[((size_t)(p * n + q) * n + r) * n + s]; };
+  for (int p = 0; p < n; ++p)
+    for (int q = 0; q < n; ++q)
+      for (int r = 0; r < n; ++r)
+        for (int s = 0; s < n; ++s) {
+          const double v = E(p, q, r, s);
+          if (std::fabs(v - E(q, p, r, s)) > 1e-12 || std::fabs(v - E(p, q, s, r)) > 1e-12 ||
+              std::fabs(v - E(r, s, p, q)) > 1e-12)
+            return fail(c, SWCS_E_INVALID, "eri lacks 8-fold symmetry");
+        }
+  std::vector<double> Jh(n2), Kh(n2);
+  for (int p = 0; p < n; ++p)
+    for (int q = 0; q < n; ++q) {
+      Jh[p * n + q] = E(p, p, q, q);
+      Kh[p * n + q] = E(p, q, q, p);
+    }
+  HIP_TRY(c, c->h.ensure(n2 * 8), "alloc h");
+  HIP_TRY(c, c->eri.ensure(n4 * 8), "alloc eri");
+  HIP_TRY(c, c->J.ensure(n2 * 8), "alloc J");
+  HIP_TRY(c, c->K.ensure(n2 * 8), "alloc K");
+  HIP_TRY(c, c->fock.ensure(n2 * 8), "alloc fock");
+  HIP_TRY(c, hipMemcpy(c->h.p, h, n2 * 8, hipMemcpyHostToDevice), "copy h");
+  HIP_TRY(c, hipMemcpy(c->eri.p, eri, n4 * 8, hipMemcpyHostToDevice), "copy eri");
+  HIP_TRY(c, hipMemcpy(c->J.p, Jh.data(), n2 * 8, hipMemcpyHostToDevice), "copy J");
+  HIP_TRY(c, hipMemcpy(c->K.p, Kh.data(), n2 * 8, hipMemcpyHostToDevice), "copy K");
+  HIP_TRY(c, launch_fock(c->h.as<double>(), c->eri.as<double>(), n, c->na, c->fock.as<double>(),
+                         c->stream), "fock");
+  HIP_TRY(c, hipStreamSynchronize(c->stream), "sync");
+  c->ecore = e_core;
+  c->have_ints = true;
+  c->ansatz_valid = false;
+  return SWCS_OK;
+}
+
+int swcs_set_reference(swcs_ctx* c, uint64_t det) {
+  if (!c) return SWCS_E_INVALID;
+  if (c->nso < 64 && (det >> c->nso) != 0) return fail(c, SWCS_E_INVALID, "reference has bits beyond 2n");
+  const int a = __builtin_popcountll(det & 0x5555555555555555ULL);
+  const int b = __builtin_popcountll(det & 0xAAAAAAAAAAAAAAAAULL);
+  if (a != c->na || b != c->nb) return fail(c, SWCS_E_INVALID, "reference electron counts differ from n_alpha/n_beta");
+  c->ref = det;
+  c->have_ref = true;
+  c->ansatz_valid = false;
+  return SWCS_OK;
+}
+
+int swcs_set_pool(swcs_ctx* c, const int32_t* rows, int64_t K) {
+  if (!c) return SWCS_E_INVALID;
+  if (K < 0 || (K > 0 && !rows)) return fail(c, SWCS_E_INVALID, "bad pool arguments");
+  if (K > (int64_t)1 << 30) return fail(c, SWCS_E_INVALID, "pool too large");
+  hipSetDevice(c->device);
+  std::vector<OpDesc> ops((size_t)K);
+  const int N = c->nso;
+  for (int64_t k = 0; k < K; ++k) {
+    const int32_t* r = rows + 4 * k;
+    OpDesc o;
+    o.P = r[0]; o.Q = r[1]; o.R = r[2]; o.S = r[3];
+    const bool single = (o.R == -1 && o.S == -1);
+    if (o.P < 0 || o.P >= N || o.Q < 0 || o.Q >= N || o.P <= o.Q)
+      return fail(c, SWCS_E_INVALID, "pool row " + std::to_string(k) + ": need 2n > P > Q >= 0");
+    if (single) {
+      if ((o.P & 1) != (o.Q & 1)) return fail(c, SWCS_E_INVALID, "pool row " + std::to_string(k) + ": single changes spin");
+      o.cre = 1ULL << o.P;
+      o.ann = 1ULL << o.Q;
+    } else {
+      if (o.R < 0 || o.R >= N || o.S < 0 || o.S >= N || o.R <= o.S)
+        return fail(c, SWCS_E_INVALID, "pool row " + std::to_string(k) + ": need 2n > R > S >= 0");
+      if (o.P == o.R || o.P == o.S || o.Q == o.R || o.Q == o.S)
+        return fail(c, SWCS_E_INVALID, "pool row " + std::to_string(k) + ": index sets overlap");
+      if (((o.P & 1) + (o.Q & 1)) != ((o.R & 1) + (o.S & 1)))
+        return fail(c, SWCS_E_INVALID, "pool row " + std::to_string(k) + ": double changes spin");
+      o.cre = (1ULL << o.P) | (1ULL << o.Q);
+      o.ann = (1ULL << o.R) | (1ULL << o.S);
+    }
+    ops[(size_t)k] = o;
+  }
+  HIP_TRY(c, c->ops.ensure(std::max<size_t>(1, (size_t)K) * sizeof(OpDesc)), "alloc pool");
+  if (K > 0) HIP_TRY(c, hipMemcpy(c->ops.p, ops.data(), (size_t)K * sizeof(OpDesc), hipMemcpyHostToDevice), "copy pool");
+  c->ops_host.swap(ops);
+  c->pool_rows.assign(rows, rows + 4 * K);
+  c->K_pool = K;
+  c->have_pool = true;
+  c->ansatz_valid = false;
+  return SWCS_OK;
+}
+
+static int apply_common(swcs_ctx* c, const int32_t* op_idx, const double* theta, int64_t M,
+                        double eps, int64_t ncut, int64_t* n_det_out, bool from_reference) {
+  int r = check_ready(c);
+  if (r) return r;
+  r = validate_gates(c, op_idx, theta, M, eps, ncut);
+  if (r) return r;
+  if (!from_reference && !c->have_state) return fail(c, SWCS_E_STATE, "no current state");
+  hipSetDevice(c->device);
+  std::vector<double> cs((size_t)M), sn((size_t)M);
+  for (int64_t i = 0; i < M; ++i) {
+    cs[(size_t)i] = std::cos(theta[i]);
+    sn[(size_t)i] = std::sin(theta[i]);
+  }
+  HIP_TRY(c, c->gate_n_in.ensure(std::max<int64_t>(1, M) * sizeof(u64)), "alloc stats");
+  c->ansatz_valid = false;
+  if (from_reference) {
+    r = state_reset_to_reference(c);
+    if (r) return r;
+    c->seg = std::max<int>(1, (int)std::ceil(std::sqrt((double)std::max<int64_t>(1, M))));
+    const int nck = (int)((M + c->seg - 1) / c->seg) + 1;
+    if ((int)c->ckpt.size() < nck) c->ckpt.resize(nck);
+    HIP_TRY(c, c->ckpt_n.ensure((size_t)nck * sizeof(u64)), "alloc ckpt sizes");
+  }
+  Counters h;
+  r = run_chain(c, op_idx, cs.data(), sn.data(), M, eps, from_reference, &h);
+  if (r) return r;
+  c->peak_n = std::max<u64>(c->peak_n, h.n);
+  c->last_M = M;
+  if (from_reference) {
+    c->a_ops.assign(op_idx, op_idx + M);
+    c->a_theta.assign(theta, theta + M);
+    c->a_c = cs;
+    c->a_s = sn;
+    c->a_eps = eps;
+    c->a_ncut = ncut;
+    c->ansatz_valid = true;
+  }
+  if (n_det_out) *n_det_out = (int64_t)h.alive;
+  return SWCS_OK;
+}
+
+int swcs_apply_ansatz(swcs_ctx* c, const int32_t* op_idx, const double* theta, int64_t M,
+                      double eps, int64_t ncut, int64_t* n_det_out) {
+  if (!c) return SWCS_E_INVALID;
+  return apply_common(c, op_idx, theta, M, eps, ncut, n_det_out, true);
+}
+
+int swcs_apply_gates(swcs_ctx* c, const int32_t* op_idx, const double* theta, int64_t M,
+                     double eps, int64_t ncut, int64_t* n_det_out) {
+  if (!c) return SWCS_E_INVALID;
+  return apply_common(c, op_idx, theta, M, eps, ncut, n_det_out, false);
+}
+
+int swcs_set_state(swcs_ctx* c, const uint64_t* keys, const double* amps, int64_t n) {
+  if (!c) return SWCS_E_INVALID;
+  if (n < 0 || (n > 0 && (!keys || !amps))) return fail(c, SWCS_E_INVALID, "bad state arguments");
+  hipSetDevice(c->device);
+  std::vector<u64> sorted(keys, keys + n);
+  std::sort(sorted.begin(), sorted.end());
+  for (int64_t i = 0; i < n; ++i) {
+    const u64 k = keys[i];
+    if (c->nso < 64 && (k >> c->nso) != 0) return fail(c, SWCS_E_INVALID, "key has bits beyond 2n");
+    if (__builtin_popcountll(k & 0x5555555555555555ULL) != c->na ||
+        __builtin_popcountll(k & 0xAAAAAAAAAAAAAAAAULL) != c->nb)
+      return fail(c, SWCS_E_INVALID, "key outside the (n_alpha, n_beta) sector");
+    if (!std::isfinite(amps[i])) return fail(c, SWCS_E_INVALID, "non-finite amplitude");
+    if (i > 0 && sorted[(size_t)i] == sorted[(size_t)i - 1]) return fail(c, SWCS_E_INVALID, "duplicate key");
+  }
+  u64 cap = next_pow2(std::max<u64>(4096, 2 * (u64)n));
+  cap = std::min<u64>(cap, max_capacity(c));
+  if (cap < (u64)n) return fail(c, SWCS_E_CAPACITY, "state exceeds the maximum capacity");
+  int r = state_reserve(c, cap, 0);
+  if (r) return r;
+  if (n > 0) {
+    HIP_TRY(c, hipMemcpy(c->keys.p, keys, n * sizeof(u64), hipMemcpyHostToDevice), "copy keys");
+    HIP_TRY(c, hipMemcpy(c->amps.p, amps, n * sizeof(double), hipMemcpyHostToDevice), "copy amps");
+  }
+  Counters h;
+  std::memset(&h, 0, sizeof(h));
+  h.n = (u64)n;
+  h.alive = (u64)n;
+  HIP_TRY(c, hipMemcpy(c->ctr.p, &h, sizeof(h), hipMemcpyHostToDevice), "counters");
+  if (n > 0) HIP_TRY(c, launch_hash_build(c->st, (u64)n, c->stream), "hash build");
+  HIP_TRY(c, hipStreamSynchronize(c->stream), "sync");
+  c->peak_n = std::max<u64>(c->peak_n, (u64)n);
+  c->have_state = true;
+  c->ansatz_valid = false;
+  return SWCS_OK;
+}
+
+// Export (key, vals[i]) of the alive entries sorted by key; vals = amps if NULL.
+static int export_sorted(swcs_ctx* c, u64 n, u64 alive, const double* vals, uint64_t* keys,
+                         double* out) {
+  HIP_TRY(c, c->exp_keys.ensure(n * 8), "alloc");
+  HIP_TRY(c, c->exp_amps.ensure(n * 8), "alloc");
+  HIP_TRY(c, c->exp_tmp_k.ensure(n * 8), "alloc");
+  HIP_TRY(c, c->exp_tmp_v.ensure(n * 8), "alloc");
+  const u64 scr = std::max(radix_sort_scratch_elems(n), compact_scratch_elems(n));
+  HIP_TRY(c, c->sort_scratch.ensure(scr * 8), "alloc");
+  HIP_TRY(c, launch_compact_alive(c->st, n, vals, c->exp_keys.as<u64>(), c->exp_amps.as<double>(),
+                                  c->scalars.as<u64>() + 8, c->sort_scratch.as<u64>(), scr, c->stream), "compact");
+  HIP_TRY(c, radix_sort_pairs(c->exp_keys.as<u64>(), c->exp_amps.as<u64>(), c->exp_tmp_k.as<u64>(),
+                              c->exp_tmp_v.as<u64>(), alive, c->nso, c->sort_scratch.as<u64>(), scr,
+                              c->stream), "sort");
+  HIP_TRY(c, hipMemcpyAsync(keys, c->exp_keys.p, alive * 8, hipMemcpyDeviceToHost, c->stream), "copy");
+  HIP_TRY(c, hipMemcpyAsync(out, c->exp_amps.p, alive * 8, hipMemcpyDeviceToHost, c->stream), "copy");
+  HIP_TRY(c, hipStreamSynchronize(c->stream), "sync");
+  return SWCS_OK;
+}
+
+int swcs_get_state(swcs_ctx* c, uint64_t* keys, double* amps, int64_t cap, int64_t* n_out) {
+  if (!c) return SWCS_E_INVALID;
+  if (!c->have_state) return fail(c, SWCS_E_STATE, "no current state");
+  hipSetDevice(c->device);
+  hipError_t e;
+  Counters h = read_counters(c, &e);
+  if (e != hipSuccess) return hip_fail(c, e, "read counters");
+  if (n_out) *n_out = (int64_t)h.alive;
+  if ((int64_t)h.alive > cap) return fail(c, SWCS_E_INVALID, "output capacity too small");
+  if (h.alive == 0) return SWCS_OK;
+  if (!keys || !amps) return fail(c, SWCS_E_INVALID, "null output arrays");
+  return export_sorted(c, h.n, h.alive, nullptr, keys, amps);
+}
+
+// sigma_P over the stored entries; returns numer and norm2 on the host.
+static int energy_internal(swcs_ctx* c, u64 n, double* numer, double* norm2) {
+  const int grid = sigma_grid(c, n);
+  HIP_TRY(c, c->sigma.ensure(std::max<u64>(1, n) * 8), "alloc sigma");
+  HIP_TRY(c, c->partial.ensure((size_t)2 * grid * 8), "alloc partial");
+  HIP_TRY(c, launch_sigma_proj(c->st, ints_view(c), c->exc, n, c->sigma.as<double>(),
+                               c->partial.as<double>(), nullptr, grid, c->stream), "sigma");
+  HIP_TRY(c, launch_reduce_partials(c->partial.as<double>(), grid, grid, 2, c->scalars.as<double>(), c->stream), "reduce");
+  double out[2];
+  HIP_TRY(c, hipMemcpyAsync(out, c->scalars.p, 16, hipMemcpyDeviceToHost, c->stream), "copy");
+  HIP_TRY(c, hipStreamSynchronize(c->stream), "sync");
+  *numer = out[0];
+  *norm2 = out[1];
+  return SWCS_OK;
+}
+
+int swcs_energy(swcs_ctx* c, double* E, double* numer, double* norm2) {
+  if (!c) return SWCS_E_INVALID;
+  if (!c->have_ints) return fail(c, SWCS_E_STATE, "integrals not set");
+  if (!c->have_state) return fail(c, SWCS_E_STATE, "no current state");
+  hipSetDevice(c->device);
+  hipError_t e;
+  Counters h = read_counters(c, &e);
+  if (e != hipSuccess) return hip_fail(c, e, "read counters");
+  double nu = 0.0, no = 0.0;
+  int r = energy_internal(c, h.n, &nu, &no);
+  if (r) return r;
+  if (numer) *numer = nu;
+  if (norm2) *norm2 = no;
+  if (E) *E = nu / no;
+  return SWCS_OK;
+}
+
+int swcs_sigma_projected(swcs_ctx* c, uint64_t* keys, double* sigma, int64_t cap, int64_t* n_out) {
+  if (!c) return SWCS_E_INVALID;
+  if (!c->have_ints) return fail(c, SWCS_E_STATE, "integrals not set");
+  if (!c->have_state) return fail(c, SWCS_E_STATE, "no current state");
+  hipSetDevice(c->device);
+  hipError_t e;
+  Counters h = read_counters(c, &e);
+  if (e != hipSuccess) return hip_fail(c, e, "read counters");
+  if (n_out) *n_out = (int64_t)h.alive;
+  if ((int64_t)h.alive > cap) return fail(c, SWCS_E_INVALID, "output capacity too small");
+  if (h.alive == 0) return SWCS_OK;
+  if (!keys || !sigma) return fail(c, SWCS_E_INVALID, "null output arrays");
+  double nu, no;
+  int r = energy_internal(c, h.n, &nu, &no);
+  if (r) return r;
+  return export_sorted(c, h.n, h.alive, c->sigma.as<double>(), keys, sigma);
+}
+
+static int norm2_internal(swcs_ctx* c, u64 n, double* norm2) {
+  const int grid = grid_blocks(c, n, 256);
+  HIP_TRY(c, c->partial.ensure((size_t)grid * 8 * 2), "alloc partial");
+  HIP_TRY(c, launch_occupations(c->st, n, 0, c->partial.as<double>(), grid, c->stream), "norm");
+  HIP_TRY(c, launch_reduce_partials(c->partial.as<double>(), grid, grid, 1, c->scalars.as<double>(), c->stream), "reduce");
+  HIP_TRY(c, hipMemcpyAsync(norm2, c->scalars.p, 8, hipMemcpyDeviceToHost, c->stream), "copy");
+  HIP_TRY(c, hipStreamSynchronize(c->stream), "sync");
+  return SWCS_OK;
+}
+
+int swcs_pool_gradients(swcs_ctx* c, const int32_t* subset, int64_t n_subset, double* g_out) {
+  if (!c) return SWCS_E_INVALID;
+  int r = check_ready(c);
+  if (r) return r;
+  if (!c->have_state) return fail(c, SWCS_E_STATE, "no current state");
+  if (!g_out) return fail(c, SWCS_E_INVALID, "null g_out");
+  const int64_t count = subset ? n_subset : c->K_pool;
+  if (subset) {
+    if (n_subset < 0) return fail(c, SWCS_E_INVALID, "n_subset < 0");
+    for (int64_t t = 0; t < n_subset; ++t)
+      if (subset[t] < 0 || subset[t] >= c->K_pool) return fail(c, SWCS_E_INVALID, "subset index out of range");
+  }
+  if (count == 0) return SWCS_OK;
+  hipSetDevice(c->device);
+  hipError_t e;
+  Counters h = read_counters(c, &e);
+  if (e != hipSuccess) return hip_fail(c, e, "read counters");
+  const u64 n = h.n;
+  double norm2 = 0.0;
+  r = norm2_internal(c, n, &norm2);
+  if (r) return r;
+  if (!(norm2 > 0.0)) return fail(c, SWCS_E_STATE, "state has zero norm");
+  HIP_TRY(c, c->gbuf.ensure((size_t)count * 8), "alloc g");
+  HIP_TRY(c, hipMemsetAsync(c->gbuf.p, 0, (size_t)count * 8, c->stream), "zero g");
+  const int* d_subset = nullptr;
+  if (subset) {
+    HIP_TRY(c, c->subset_buf.ensure((size_t)n_subset * 4), "alloc subset");
+    HIP_TRY(c, hipMemcpyAsync(c->subset_buf.p, subset, (size_t)n_subset * 4, hipMemcpyHostToDevice, c->stream), "copy subset");
+    d_subset = c->subset_buf.as<int>();
+  }
+  // External-space table: at most alive * (C + 1) distinct keys (and never
+  // more than the sector); load factor <= 1/2; split by key hash when the
+  // table would exceed the memory budget.
+  const double bound_d = std::min<double>((double)c->sector, (double)h.alive * (double)(c->exc.total + 1));
+  size_t free_b = 0, total_b = 0;
+  hipMemGetInfo(&free_b, &total_b);
+  const double budget = std::max<double>(64.0 * 1024 * 1024, 0.4 * (double)free_b);
+  int nbatch = 1;
+  while ((2.0 * bound_d / nbatch) * sizeof(AccSlot) * 1.25 > budget && nbatch < 4096) nbatch *= 2;
+  u64 slots = next_pow2((u64)std::max<double>(64.0, 2.0 * bound_d / nbatch * (nbatch > 1 ? 1.25 : 1.0)));
+  HIP_TRY(c, c->acc_tab.ensure(slots * sizeof(AccSlot)), "alloc sigma table");
+  const double scale = 2.0 / norm2;
+  for (int b = 0; b < nbatch; ++b) {
+    HIP_TRY(c, hipMemsetAsync(c->acc_tab.p, 0, slots * sizeof(AccSlot), c->stream), "clear table");
+    HIP_TRY(c, launch_sigma_push(c->st, ints_view(c), c->exc, n, c->acc_tab.as<AccSlot>(), slots - 1,
+                                 nbatch, b, sigma_grid(c, n), c->stream), "sigma push");
+    HIP_TRY(c, launch_pool_contract_ops(c->st, n, c->ops.as<OpDesc>(), d_subset, count,
+                                        c->acc_tab.as<AccSlot>(), slots - 1, c->gbuf.as<double>(),
+                                        scale, c->stream), "contract");
+  }
+  HIP_TRY(c, hipMemcpyAsync(g_out, c->gbuf.p, (size_t)count * 8, hipMemcpyDeviceToHost, c->stream), "copy g");
+  Counters h2 = read_counters(c, &e);
+  if (e != hipSuccess) return hip_fail(c, e, "read counters");
+  if (h2.flags & kFlagOverflow) return fail(c, SWCS_E_DEVICE, "sigma table overflow");
+  return SWCS_OK;
+}
+
+int swcs_param_gradients(swcs_ctx* c, double* dE, double* E_out) {
+  if (!c) return SWCS_E_INVALID;
+  if (!c->ansatz_valid) return fail(c, SWCS_E_STATE, "no ansatz applied from the reference");
+  if (!dE && c->a_ops.size() > 0) return fail(c, SWCS_E_INVALID, "null dE_dtheta");
+  hipSetDevice(c->device);
+  const int64_t M = (int64_t)c->a_ops.size();
+  hipError_t e;
+  Counters hfin = read_counters(c, &e);
+  if (e != hipSuccess) return hip_fail(c, e, "read counters");
+  const u64 n = hfin.n;
+  double numer = 0.0, norm2 = 0.0;
+  int r = energy_internal(c, n, &numer, &norm2);
+  if (r) return r;
+  const double E = numer / norm2;
+  if (E_out) *E_out = E;
+  if (M == 0) return SWCS_OK;
+  const int seg = c->seg;
+  const int nseg = (int)((M + seg - 1) / seg);
+  const int grid = grid_blocks(c, n, 256);
+  HIP_TRY(c, c->mu.ensure(n * 8), "alloc mu");
+  HIP_TRY(c, c->seg_states.ensure((size_t)seg * n * 8), "alloc segment states");
+  HIP_TRY(c, c->partial2.ensure((size_t)M * grid * 8), "alloc partials");
+  HIP_TRY(c, c->ctr_r.ensure(sizeof(Counters)), "alloc counters");
+  HIP_TRY(c, c->gbuf.ensure((size_t)M * 8), "alloc dE");
+  HIP_TRY(c, launch_mu_init(c->st, c->sigma.as<double>(), n, 2.0 / norm2, E, c->mu.as<double>(), c->stream), "mu init");
+  // Recompute view: same keys and hash, amplitudes in a segment buffer,
+  // separate counters with capacity checks off (no key is ever appended:
+  // every key the recomputation can reach was stored by the forward run).
+  DeviceState rv = c->st;
+  rv.cap = n;
+  rv.ctr = c->ctr_r.as<Counters>();
+  Counters hr;
+  std::memset(&hr, 0, sizeof(hr));
+  hr.n = n;
+  hr.alive = 0;
+  for (int j = nseg - 1; j >= 0; --j) {
+    const int64_t g_lo = (int64_t)j * seg;
+    const int64_t g_hi = std::min<int64_t>(M, g_lo + seg);
+    const int len = (int)(g_hi - g_lo);
+    double* S = c->seg_states.as<double>();
+    HIP_TRY(c, launch_restore(S, c->ckpt[j].as<double>(), c->ckpt_n.as<u64>() + j, n, c->stream), "restore");
+    HIP_TRY(c, hipMemcpyAsync(c->ctr_r.p, &hr, sizeof(hr), hipMemcpyHostToDevice, c->stream), "counters");
+    for (int t = 1; t < len; ++t) {
+      double* dst = S + (size_t)t * n;
+      HIP_TRY(c, hipMemcpyAsync(dst, S + (size_t)(t - 1) * n, n * 8, hipMemcpyDeviceToDevice, c->stream), "copy state");
+      rv.amps = dst;
+      const int64_t g = g_lo + t - 1;
+      HIP_TRY(c, launch_gate(rv, c->ops_host[c->a_ops[g]], c->a_c[g], c->a_s[g], c->a_eps, nullptr, 0,
+                             (unsigned)g, grid, c->stream), "recompute gate");
+    }
+    for (int t = len - 1; t >= 0; --t) {
+      const int64_t g = g_lo + t;
+      HIP_TRY(c, launch_adjoint_step(c->st, c->ops_host[c->a_ops[g]], c->a_c[g], c->a_s[g],
+                                     S + (size_t)t * n, c->mu.as<double>(),
+                                     c->partial2.as<double>() + (size_t)g * grid, n, grid, c->stream), "adjoint step");
+    }
+  }
+  HIP_TRY(c, launch_reduce_partials(c->partial2.as<double>(), grid, grid, (int)M, c->gbuf.as<double>(), c->stream), "reduce");
+  HIP_TRY(c, hipMemcpyAsync(dE, c->gbuf.p, (size_t)M * 8, hipMemcpyDeviceToHost, c->stream), "copy dE");
+  Counters hr2 = read_counters(c, &e);  // synchronizes
+  if (e != hipSuccess) return hip_fail(c, e, "sync");
+  Counters chk;
+  HIP_TRY(c, hipMemcpy(&chk, c->ctr_r.p, sizeof(chk), hipMemcpyDeviceToHost), "read recompute counters");
+  if (chk.n != n || (chk.flags & kFlagOverflow))
+    return fail(c, SWCS_E_DEVICE, "recomputation diverged from the forward run");
+  (void)hr2;
+  return SWCS_OK;
+}
+
+int swcs_gate_sizes(swcs_ctx* c, int64_t* n_in, int64_t M) {
+  if (!c) return SWCS_E_INVALID;
+  if (M != c->last_M) return fail(c, SWCS_E_INVALID, "M differs from the last apply call");
+  if (M == 0) return SWCS_OK;
+  if (!n_in) return fail(c, SWCS_E_INVALID, "null n_in");
+  hipSetDevice(c->device);
+  HIP_TRY(c, hipMemcpyAsync(n_in, c->gate_n_in.p, (size_t)M * 8, hipMemcpyDeviceToHost, c->stream), "copy");
+  HIP_TRY(c, hipStreamSynchronize(c->stream), "sync");
+  return SWCS_OK;
+}
+
+static int occupations_device(swcs_ctx* c, u64 n) {
+  const int grid = grid_blocks(c, n, 256);
+  HIP_TRY(c, c->partial.ensure((size_t)grid * (c->nso + 1) * 8), "alloc partial");
+  HIP_TRY(c, c->occ.ensure((size_t)(c->nso + 1) * 8), "alloc occ");
+  HIP_TRY(c, launch_occupations(c->st, n, c->nso, c->partial.as<double>(), grid, c->stream), "occupations");
+  HIP_TRY(c, launch_reduce_partials(c->partial.as<double>(), grid, grid, c->nso + 1, c->occ.as<double>(), c->stream), "reduce");
+  return SWCS_OK;
+}
+
+int swcs_occupations(swcs_ctx* c, double* n_out) {
+  if (!c) return SWCS_E_INVALID;
+  if (!c->have_state) return fail(c, SWCS_E_STATE, "no current state");
+  if (!n_out) return fail(c, SWCS_E_INVALID, "null n_out");
+  hipSetDevice(c->device);
+  hipError_t e;
+  Counters h = read_counters(c, &e);
+  if (e != hipSuccess) return hip_fail(c, e, "read counters");
+  int r = occupations_device(c, h.n);
+  if (r) return r;
+  std::vector<double> tmp((size_t)c->nso + 1);
+  HIP_TRY(c, hipMemcpyAsync(tmp.data(), c->occ.p, tmp.size() * 8, hipMemcpyDeviceToHost, c->stream), "copy");
+  HIP_TRY(c, hipStreamSynchronize(c->stream), "sync");
+  for (int P = 0; P < c->nso; ++P) n_out[P] = tmp[(size_t)P] / tmp[(size_t)c->nso];
+  return SWCS_OK;
+}
+
+int64_t swcs_mlp_param_count(void) { return kMlpParams; }
+
+int swcs_features(swcs_ctx* c, const float* d_prev_absg, const float* d_age, const float* d_count,
+                  float* d_feat) {
+  if (!c) return SWCS_E_INVALID;
+  int r = check_ready(c);
+  if (r) return r;
+  if (!c->have_state) return fail(c, SWCS_E_STATE, "no current state");
+  if (!d_prev_absg || !d_age || !d_count || !d_feat) return fail(c, SWCS_E_INVALID, "null device pointer");
+  hipSetDevice(c->device);
+  hipError_t e;
+  Counters h = read_counters(c, &e);
+  if (e != hipSuccess) return hip_fail(c, e, "read counters");
+  r = occupations_device(c, h.n);
+  if (r) return r;
+  HIP_TRY(c, launch_features(c->ops.as<OpDesc>(), c->K_pool, c->fock.as<double>(), c->eri.as<double>(),
+                             c->n, c->occ.as<double>(), d_prev_absg, d_age, d_count, d_feat, c->stream), "features");
+  return SWCS_OK;
+}
+
+int swcs_mlp_forward(swcs_ctx* c, const float* d_W, const float* d_x, int64_t B, float* d_y,
+                     float* d_act) {
+  if (!c) return SWCS_E_INVALID;
+  if (B < 0 || (B > 0 && (!d_W || !d_x || !d_y))) return fail(c, SWCS_E_INVALID, "bad mlp arguments");
+  hipSetDevice(c->device);
+  HIP_TRY(c, launch_mlp_forward(d_W, d_x, B, d_y, d_act, c->stream), "mlp forward");
+  return SWCS_OK;
+}
+
+int swcs_mlp_backward(swcs_ctx* c, const float* d_W, const float* d_x, const float* d_act,
+                      const float* d_dy, int64_t B, float* d_dW) {
+  if (!c) return SWCS_E_INVALID;
+  if (B < 0 || !d_W || !d_dW || (B > 0 && (!d_x || !d_act || !d_dy)))
+    return fail(c, SWCS_E_INVALID, "bad mlp arguments");
+  hipSetDevice(c->device);
+  const long long rows = std::max<long long>(1, mlp_backward_partial_rows(B));
+  HIP_TRY(c, c->mlp_partial.ensure((size_t)rows * kMlpParams * 4), "alloc partial");
+  HIP_TRY(c, launch_mlp_backward(d_W, d_x, d_act, d_dy, B, d_dW, c->mlp_partial.as<float>(), rows,
+                                 c->stream), "mlp backward");
+  return SWCS_OK;
+}
+
+int swcs_mse(swcs_ctx* c, const float* d_y, const float* d_t, int64_t B, float* d_dy, float* d_loss) {
+  if (!c) return SWCS_E_INVALID;
+  if (B <= 0 || !d_y || !d_t || !d_dy || !d_loss) return fail(c, SWCS_E_INVALID, "bad mse arguments");
+  hipSetDevice(c->device);
+  HIP_TRY(c, launch_mse(d_y, d_t, B, d_dy, d_loss, c->stream), "mse");
+  return SWCS_OK;
+}
+
+int swcs_adam_step(swcs_ctx* c, float* d_W, float* d_m, float* d_v, const float* d_dW, int64_t P,
+                   float lr, float b1, float b2, float eps, int step) {
+  if (!c) return SWCS_E_INVALID;
+  if (P <= 0 || !d_W || !d_m || !d_v || !d_dW || step < 1 || !(b1 >= 0 && b1 < 1) || !(b2 >= 0 && b2 < 1))
+    return fail(c, SWCS_E_INVALID, "bad adam arguments");
+  hipSetDevice(c->device);
+  HIP_TRY(c, launch_adam(d_W, d_m, d_v, d_dW, P, lr, b1, b2, eps, step, c->stream), "adam");
+  return SWCS_OK;
+}
+
+int swcs_select(swcs_ctx* c, const float* d_score, const uint32_t* d_rand, int64_t K, int64_t n_top,
+                int64_t n_rand, int32_t* d_idx) {
+  if (!c) return SWCS_E_INVALID;
+  if (K <= 0 || K > ((int64_t)1 << 31) - 1 || n_top < 0 || n_rand < 0 || n_top + n_rand > K ||
+      !d_score || !d_idx || (n_rand > 0 && !d_rand))
+    return fail(c, SWCS_E_INVALID, "bad select arguments");
+  hipSetDevice(c->device);
+  const u64 need = select_scratch_elems(K);
+  HIP_TRY(c, c->sel_scratch.ensure(need * 8), "alloc select scratch");
+  HIP_TRY(c, launch_select(d_score, d_rand, K, n_top, n_rand, d_idx, c->sel_scratch.as<u64>(), need,
+                           c->stream), "select");
+  return SWCS_OK;
+}
+
+}  // extern "C"

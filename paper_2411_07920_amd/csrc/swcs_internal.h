@@ -1,0 +1,328 @@
+// Internal definitions shared by the HIP translation units of libswcs.
+// Device data layout, hash tables, phase rules and host launch wrappers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string>
+#include <vector>
+
+namespace swcs {
+
+typedef unsigned long long u64;
+
+// Amplitude bit pattern that marks a stored determinant as not part of the
+// state (pruned, or never reached).  A quiet NaN no arithmetic produces.
+constexpr u64 kDeadBits = 0x7ff8dead0000deadULL;
+constexpr u64 kEmptyKey = 0ULL;  // no determinant of >= 1 electron has key 0
+
+__host__ __device__ inline u64 mix64(u64 x) {
+  x ^= x >> 30;
+  x *= 0xbf58476d1ce4e5b9ULL;
+  x ^= x >> 27;
+  x *= 0x94d049bb133111ebULL;
+  x ^= x >> 31;
+  return x;
+}
+
+__device__ inline bool is_dead(double a) { return (u64)__double_as_longlong(a) == kDeadBits; }
+__device__ inline double dead_value() { return __longlong_as_double((long long)kDeadBits); }
+
+// One operator of the pool, preprocessed on the host.
+//   T = a+_P a+_Q a_S a_R (double) or a+_P a_Q (single, R = S = -1)
+//   ann = bits annihilated by T, cre = bits created by T.
+struct OpDesc {
+  u64 ann;
+  u64 cre;
+  int P, Q, R, S;
+};
+
+// Sign of T acting on D (T must act: ann subset of D, cre disjoint from D).
+// The rightmost ladder operator acts first; each contributes
+// (-1)^(occupied spin-orbitals below its index) in the current determinant.
+__device__ inline int phase_of_T(const OpDesc& op, u64 D) {
+  int s;
+  if (op.R < 0) {
+    s = __popcll(D & ((1ULL << op.Q) - 1ULL));
+    D ^= 1ULL << op.Q;
+    s += __popcll(D & ((1ULL << op.P) - 1ULL));
+  } else {
+    s = __popcll(D & ((1ULL << op.R) - 1ULL));
+    D ^= 1ULL << op.R;
+    s += __popcll(D & ((1ULL << op.S) - 1ULL));
+    D ^= 1ULL << op.S;
+    s += __popcll(D & ((1ULL << op.Q) - 1ULL));
+    D ^= 1ULL << op.Q;
+    s += __popcll(D & ((1ULL << op.P) - 1ULL));
+  }
+  return (s & 1) ? -1 : 1;
+}
+
+// Open-addressing (linear probing) index from determinant key to position in
+// the structure-of-arrays state.  Slots are 16 bytes so a probe touches one
+// line for both key and index.  Capacity is a power of two.
+struct HashSlot {
+  u64 key;
+  u64 idx;
+};
+
+__device__ inline long long hash_find(const HashSlot* __restrict__ tab, u64 mask, u64 key) {
+  u64 h = mix64(key) & mask;
+  while (true) {
+    u64 k = tab[h].key;
+    if (k == key) return (long long)tab[h].idx;
+    if (k == kEmptyKey) return -1;
+    h = (h + 1) & mask;
+  }
+}
+
+// Insert a key known to be absent; concurrent inserts of other keys allowed.
+__device__ inline void hash_insert_new(HashSlot* tab, u64 mask, u64 key, u64 idx) {
+  u64 h = mix64(key) & mask;
+  while (true) {
+    u64 prev = atomicCAS(&tab[h].key, kEmptyKey, key);
+    if (prev == kEmptyKey || prev == key) {
+      tab[h].idx = idx;
+      return;
+    }
+    h = (h + 1) & mask;
+  }
+}
+
+// Accumulation table for the external sigma vector: key -> double.
+struct AccSlot {
+  u64 key;
+  double val;
+};
+
+// Returns false (and adds nothing) if every slot is taken by other keys.
+__device__ inline bool acc_add(AccSlot* tab, u64 mask, u64 key, double v) {
+  u64 h = mix64(key) & mask;
+  for (u64 probes = 0; probes <= mask; ++probes) {
+    u64 k = tab[h].key;
+    if (k == key) {
+      unsafeAtomicAdd(&tab[h].val, v);
+      return true;
+    }
+    if (k == kEmptyKey) {
+      u64 prev = atomicCAS(&tab[h].key, kEmptyKey, key);
+      if (prev == kEmptyKey || prev == key) {
+        unsafeAtomicAdd(&tab[h].val, v);
+        return true;
+      }
+    }
+    h = (h + 1) & mask;
+  }
+  return false;
+}
+
+__device__ inline bool acc_find(const AccSlot* __restrict__ tab, u64 mask, u64 key, double* v) {
+  u64 h = mix64(key) & mask;
+  for (u64 probes = 0; probes <= mask; ++probes) {
+    u64 k = tab[h].key;
+    if (k == key) {
+      *v = tab[h].val;
+      return true;
+    }
+    if (k == kEmptyKey) return false;
+    h = (h + 1) & mask;
+  }
+  return false;
+}
+
+// Device counters of the state.  n: stored entries (alive or dead);
+// alive: entries that are part of the state; app / dalive / ticket: per-gate
+// scratch folded in by the last block of each gate launch; flags: error bits.
+struct Counters {
+  u64 n;
+  u64 alive;
+  u64 app;
+  long long dalive;
+  unsigned int ticket;
+  unsigned int flags;
+  u64 stop_gate;
+};
+
+// kFlagOverflow: an append or table insert found no room (a bug guard: the
+// host sizes buffers so it cannot happen).  kFlagStopped: a gate found too
+// little capacity and did nothing; later gates of the chain skip too.
+enum : unsigned int { kFlagOverflow = 1u, kFlagStopped = 2u };
+
+// Integrals on the device, spin-free spatial arrays.
+struct Ints {
+  const double* h;    // n*n
+  const double* eri;  // n^4
+  const double* J;    // n*n, J[p*n+q] = (pp|qq)
+  const double* K;    // n*n, K[p*n+q] = (pq|qp)
+  double ecore;
+  int n;
+};
+
+__device__ inline double eri_sp(const Ints& I, int p, int q, int r, int s) {
+  int n = I.n;
+  return I.eri[((size_t)(p * n + q) * n + r) * n + s];
+}
+
+// Spin-orbital (PQ|RS) with the spin deltas.
+__device__ inline double eri_so(const Ints& I, int P, int Q, int R, int S) {
+  if (((P ^ Q) & 1) || ((R ^ S) & 1)) return 0.0;
+  return eri_sp(I, P >> 1, Q >> 1, R >> 1, S >> 1);
+}
+
+// Diagonal Slater-Condon element of determinant D.
+__device__ inline double diag_element(const Ints& I, u64 D) {
+  double e1 = 0.0, e2 = 0.0;
+  u64 x = D;
+  while (x) {
+    int P = __ffsll((long long)x) - 1;
+    x &= x - 1;
+    int p = P >> 1;
+    e1 += I.h[p * I.n + p];
+    u64 y = D;
+    while (y) {
+      int Q = __ffsll((long long)y) - 1;
+      y &= y - 1;
+      int q = Q >> 1;
+      e2 += I.J[p * I.n + q];
+      if (((P ^ Q) & 1) == 0) e2 -= I.K[p * I.n + q];
+    }
+  }
+  return I.ecore + e1 + 0.5 * e2;
+}
+
+// <D'|H|D> for D' = a+_A a_I D (same spin, I in D, A not in D).
+__device__ inline double single_element(const Ints& I, u64 D, int Ih, int A) {
+  int s = __popcll(D & ((1ULL << Ih) - 1ULL));
+  u64 x = D ^ (1ULL << Ih);
+  s += __popcll(x & ((1ULL << A) - 1ULL));
+  int a = A >> 1, i = Ih >> 1, n = I.n;
+  double v = I.h[a * n + i];
+  u64 y = D;
+  while (y) {
+    int Q = __ffsll((long long)y) - 1;
+    y &= y - 1;
+    int q = Q >> 1;
+    v += eri_sp(I, a, i, q, q);
+    if (((Q ^ A) & 1) == 0) v -= eri_sp(I, a, q, q, i);
+  }
+  return (s & 1) ? -v : v;
+}
+
+// <D'|H|D> for D' = a+_A a+_B a_J a_I D with I < J in D and A < B not in D.
+__device__ inline double double_element(const Ints& I, u64 D, int Ih, int Jh, int A, int B) {
+  int s = __popcll(D & ((1ULL << Ih) - 1ULL));
+  u64 x = D ^ (1ULL << Ih);
+  s += __popcll(x & ((1ULL << Jh) - 1ULL));
+  x ^= 1ULL << Jh;
+  s += __popcll(x & ((1ULL << B) - 1ULL));
+  x ^= 1ULL << B;
+  s += __popcll(x & ((1ULL << A) - 1ULL));
+  double v = eri_so(I, A, Ih, B, Jh) - eri_so(I, A, Jh, B, Ih);
+  return (s & 1) ? -v : v;
+}
+
+// Enumeration of the spin-conserving single and double excitations of a
+// determinant with na alpha and nb beta electrons in n spatial orbitals.
+// Connection c in [0, C) decodes to (holes, particles) in spin-orbitals.
+struct ExcSpace {
+  int n, na, nb;
+  int va, vb;        // virtual counts
+  long long s_a, s_b, d_aa, d_bb, d_ab;  // counts per class
+  long long total;
+};
+
+inline ExcSpace make_exc_space(int n, int na, int nb) {
+  ExcSpace e;
+  e.n = n; e.na = na; e.nb = nb;
+  e.va = n - na; e.vb = n - nb;
+  e.s_a = (long long)na * e.va;
+  e.s_b = (long long)nb * e.vb;
+  e.d_aa = (long long)na * (na - 1) / 2 * ((long long)e.va * (e.va - 1) / 2);
+  e.d_bb = (long long)nb * (nb - 1) / 2 * ((long long)e.vb * (e.vb - 1) / 2);
+  e.d_ab = (long long)na * nb * e.va * e.vb;
+  e.total = e.s_a + e.s_b + e.d_aa + e.d_bb + e.d_ab;
+  return e;
+}
+
+// <D'|H|D> for the connection decoded above.
+__device__ inline double connection_element(const Ints& I, u64 D, int nh, int h0, int h1, int p0,
+                                            int p1) {
+  if (nh == 1) return single_element(I, D, h0, p0);
+  return double_element(I, D, h0, h1, p0, p1);
+}
+
+// ---------------------------------------------------------------- host side
+struct DeviceState {
+  u64* keys = nullptr;
+  double* amps = nullptr;
+  HashSlot* hash = nullptr;
+  Counters* ctr = nullptr;
+  u64 cap = 0;        // SoA capacity
+  u64 hmask = 0;      // hash capacity - 1
+};
+
+// Launch wrappers (defined in the .hip files).  All enqueue on `stream`.
+hipError_t launch_hash_clear(HashSlot* tab, u64 slots, hipStream_t stream);
+hipError_t launch_hash_build(const DeviceState& st, u64 n, hipStream_t stream);
+hipError_t launch_gate(const DeviceState& st, const OpDesc& op, double c, double sn, double eps,
+                       u64* gate_n_in, int check_cap, unsigned gate_index, int grid,
+                       hipStream_t stream);
+hipError_t launch_adjoint_step(const DeviceState& st, const OpDesc& op, double c, double sn,
+                               const double* amps_prev, double* mu, double* partial, u64 n_total,
+                               int grid, hipStream_t stream);
+hipError_t launch_ckpt_save(const DeviceState& st, double* dst, u64* dst_n, int grid,
+                            hipStream_t stream);
+hipError_t launch_restore(double* dst, const double* src, const u64* n_src, u64 n_total,
+                          hipStream_t stream);
+hipError_t launch_mark_dead_range(double* amps, u64 lo, u64 hi, hipStream_t stream);
+hipError_t launch_sigma_proj(const DeviceState& st, const Ints& I, const ExcSpace& E, u64 n,
+                             double* sigma, double* partial_num, double* partial_norm, int grid,
+                             hipStream_t stream);
+hipError_t launch_mu_init(const DeviceState& st, const double* sigma, u64 n, double scale, double E,
+                          double* mu, hipStream_t stream);
+hipError_t launch_reduce_partials(const double* partial, int count, int stride, int nvec,
+                                  double* out, hipStream_t stream);
+hipError_t launch_sigma_push(const DeviceState& st, const Ints& I, const ExcSpace& E, u64 n,
+                             AccSlot* tab, u64 tmask, int nbatch, int batch, int grid,
+                             hipStream_t stream);
+hipError_t launch_pool_contract_ops(const DeviceState& st, u64 n, const OpDesc* ops,
+                                    const int* subset, long long n_ops, const AccSlot* tab,
+                                    u64 tmask, double* g, double scale, hipStream_t stream);
+hipError_t launch_occupations(const DeviceState& st, u64 n, int nso, double* partial, int grid,
+                              hipStream_t stream);
+hipError_t launch_compact_alive(const DeviceState& st, u64 n, const double* vals, u64* out_keys,
+                                double* out_amps, u64* d_count, u64* scratch, u64 scratch_elems,
+                                hipStream_t stream);
+hipError_t radix_sort_pairs(u64* keys, u64* vals, u64* tmp_keys, u64* tmp_vals, u64 count,
+                            int key_bits, u64* scratch, u64 scratch_elems, hipStream_t stream);
+u64 radix_sort_scratch_elems(u64 count);
+u64 compact_scratch_elems(u64 n);
+
+// Screener.
+hipError_t launch_fock(const double* h, const double* eri, int n, int n_occ, double* fock,
+                       hipStream_t stream);
+hipError_t launch_features(const OpDesc* ops, long long K, const double* fock, const double* eri,
+                           int n, const double* occ, const float* prev_absg, const float* age,
+                           const float* count, float* feat, hipStream_t stream);
+hipError_t launch_mlp_forward(const float* W, const float* x, long long B, float* y, float* act,
+                              hipStream_t stream);
+long long mlp_backward_partial_rows(long long B);
+hipError_t launch_mlp_backward(const float* W, const float* x, const float* act, const float* dy,
+                               long long B, float* dW, float* partial, long long partial_rows,
+                               hipStream_t stream);
+hipError_t launch_mse(const float* y, const float* t, long long B, float* dy, float* loss,
+                      hipStream_t stream);
+hipError_t launch_adam(float* W, float* m, float* v, const float* g, long long P, float lr,
+                       float b1, float b2, float eps, int step, hipStream_t stream);
+hipError_t launch_select(const float* score, const uint32_t* rnd, long long K, long long n_top,
+                         long long n_rand, int* idx, u64* scratch, u64 scratch_elems,
+                         hipStream_t stream);
+u64 select_scratch_elems(long long K);
+
+constexpr int kMlpIn = 16;
+constexpr int kMlpHidden = 128;
+constexpr long long kMlpParams = kMlpIn * kMlpHidden + kMlpHidden + kMlpHidden * kMlpHidden +
+                                 kMlpHidden + kMlpHidden + 1;
+constexpr int kMlpRowsPerBlock = 32;
+
+}  // namespace swcs

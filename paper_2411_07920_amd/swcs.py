@@ -1,0 +1,347 @@
+"""Thin Python binding of libswcs (argument marshalling only).
+
+Every computation runs in the HIP kernels of ``libswcs.so``; this module
+converts numpy arrays / torch tensors to pointers, checks return codes and
+raises :class:`SwcsError` with the library's message.  Importing it without
+the built library fails loudly: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libswcs.so")
+
+SWCS_OK = 0
+SWCS_E_INVALID = -1
+SWCS_E_STATE = -2
+SWCS_E_OOM = -3
+SWCS_E_CAPACITY = -4
+SWCS_E_DEVICE = -5
+SWCS_E_UNSUPPORTED = -6
+_NAMES = {0: "SWCS_OK", -1: "SWCS_E_INVALID", -2: "SWCS_E_STATE", -3: "SWCS_E_OOM",
+          -4: "SWCS_E_CAPACITY", -5: "SWCS_E_DEVICE", -6: "SWCS_E_UNSUPPORTED"}
+
+
+class SwcsError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+_vp = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_i64p = ctypes.POINTER(ctypes.c_int64)
+_dp = ctypes.POINTER(ctypes.c_double)
+_u64p = ctypes.POINTER(ctypes.c_uint64)
+_f = ctypes.c_float
+
+# name -> (restype, argtypes); mirrors include/swcs.h
+SIGNATURES = {
+    "swcs_version": (ctypes.c_char_p, []),
+    "swcs_create": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                   ctypes.POINTER(_vp)]),
+    "swcs_destroy": (None, [_vp]),
+    "swcs_last_error": (ctypes.c_char_p, [_vp]),
+    "swcs_set_stream": (ctypes.c_int, [_vp, _vp]),
+    "swcs_set_capacity": (ctypes.c_int, [_vp, _i64]),
+    "swcs_set_integrals": (ctypes.c_int, [_vp, _dp, _dp, ctypes.c_double]),
+    "swcs_set_reference": (ctypes.c_int, [_vp, ctypes.c_uint64]),
+    "swcs_set_pool": (ctypes.c_int, [_vp, _i32p, _i64]),
+    "swcs_apply_ansatz": (ctypes.c_int, [_vp, _i32p, _dp, _i64, ctypes.c_double, _i64, _i64p]),
+    "swcs_apply_gates": (ctypes.c_int, [_vp, _i32p, _dp, _i64, ctypes.c_double, _i64, _i64p]),
+    "swcs_set_state": (ctypes.c_int, [_vp, _u64p, _dp, _i64]),
+    "swcs_get_state": (ctypes.c_int, [_vp, _u64p, _dp, _i64, _i64p]),
+    "swcs_energy": (ctypes.c_int, [_vp, _dp, _dp, _dp]),
+    "swcs_sigma_projected": (ctypes.c_int, [_vp, _u64p, _dp, _i64, _i64p]),
+    "swcs_pool_gradients": (ctypes.c_int, [_vp, _i32p, _i64, _dp]),
+    "swcs_param_gradients": (ctypes.c_int, [_vp, _dp, _dp]),
+    "swcs_gate_sizes": (ctypes.c_int, [_vp, _i64p, _i64]),
+    "swcs_occupations": (ctypes.c_int, [_vp, _dp]),
+    "swcs_mlp_param_count": (ctypes.c_int64, []),
+    "swcs_features": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
+    "swcs_mlp_forward": (ctypes.c_int, [_vp, _vp, _vp, _i64, _vp, _vp]),
+    "swcs_mlp_backward": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _i64, _vp]),
+    "swcs_mse": (ctypes.c_int, [_vp, _vp, _vp, _i64, _vp, _vp]),
+    "swcs_adam_step": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _i64, _f, _f, _f, _f, ctypes.c_int]),
+    "swcs_select": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i64, _i64, _vp]),
+}
+
+
+def load():
+    """Load libswcs.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -c 'import __graft_entry__ as g; g.build()'`")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _ptr(a, ct):
+    return a.ctypes.data_as(ctypes.POINTER(ct))
+
+
+def _dev(t):
+    """Device pointer of a torch tensor (or an int address)."""
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    if not t.is_cuda:
+        raise ValueError("screener calls take device tensors")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return t.data_ptr()
+
+
+def version() -> str:
+    return load().swcs_version().decode()
+
+
+def mlp_param_count() -> int:
+    return int(load().swcs_mlp_param_count())
+
+
+class Context:
+    """One SWCS problem on one HIP device (see include/swcs.h)."""
+
+    def __init__(self, n_spatial: int, n_alpha: int, n_beta: int, device: int = 0):
+        self._lib = load()
+        h = _vp()
+        rc = self._lib.swcs_create(n_spatial, n_alpha, n_beta, device, ctypes.byref(h))
+        if rc != SWCS_OK:
+            raise SwcsError(rc, self._lib.swcs_last_error(None).decode())
+        self._h = h
+        self.n, self.n_alpha, self.n_beta = n_spatial, n_alpha, n_beta
+        self._keep = []
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.swcs_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def _check(self, rc):
+        if rc != SWCS_OK:
+            raise SwcsError(rc, self._lib.swcs_last_error(self._h).decode())
+
+    # -- set-up ---------------------------------------------------------
+    def set_stream(self, stream):
+        """stream: a torch.cuda.Stream, an int hipStream_t, or None."""
+        if stream is None:
+            ptr = None
+        elif isinstance(stream, int):
+            ptr = stream
+        else:
+            ptr = stream.cuda_stream
+        self._check(self._lib.swcs_set_stream(self._h, ptr))
+
+    def set_capacity(self, max_dets: int):
+        self._check(self._lib.swcs_set_capacity(self._h, int(max_dets)))
+
+    def set_integrals(self, h, eri, e_core: float = 0.0):
+        h = np.ascontiguousarray(h, dtype=np.float64)
+        eri = np.ascontiguousarray(eri, dtype=np.float64)
+        n = self.n
+        if h.shape != (n, n) or eri.shape != (n, n, n, n):
+            raise ValueError("integral shapes must be (n, n) and (n, n, n, n)")
+        self._check(self._lib.swcs_set_integrals(self._h, _ptr(h, ctypes.c_double),
+                                                 _ptr(eri, ctypes.c_double), float(e_core)))
+
+    def set_reference(self, det: int):
+        self._check(self._lib.swcs_set_reference(self._h, int(det)))
+
+    def set_pool(self, rows):
+        rows = np.ascontiguousarray(rows, dtype=np.int32)
+        if rows.ndim != 2 or rows.shape[1] != 4:
+            raise ValueError("pool must be int32[K, 4]")
+        self.K = len(rows)
+        self._check(self._lib.swcs_set_pool(self._h, _ptr(rows, ctypes.c_int32), len(rows)))
+
+    # -- state ----------------------------------------------------------
+    def apply_ansatz(self, ops, theta, eps: float = 0.0, ncut: int = 0) -> int:
+        ops = np.ascontiguousarray(ops, dtype=np.int32)
+        theta = np.ascontiguousarray(theta, dtype=np.float64)
+        if ops.shape != theta.shape or ops.ndim != 1:
+            raise ValueError("ops and theta must be 1-D of equal length")
+        out = ctypes.c_int64()
+        self._check(self._lib.swcs_apply_ansatz(self._h, _ptr(ops, ctypes.c_int32),
+                                                _ptr(theta, ctypes.c_double), len(ops), float(eps),
+                                                int(ncut), ctypes.byref(out)))
+        return int(out.value)
+
+    def apply_gates(self, ops, theta, eps: float = 0.0, ncut: int = 0) -> int:
+        ops = np.ascontiguousarray(ops, dtype=np.int32)
+        theta = np.ascontiguousarray(theta, dtype=np.float64)
+        if ops.shape != theta.shape or ops.ndim != 1:
+            raise ValueError("ops and theta must be 1-D of equal length")
+        out = ctypes.c_int64()
+        self._check(self._lib.swcs_apply_gates(self._h, _ptr(ops, ctypes.c_int32),
+                                               _ptr(theta, ctypes.c_double), len(ops), float(eps),
+                                               int(ncut), ctypes.byref(out)))
+        return int(out.value)
+
+    def set_state(self, keys, amps):
+        keys = np.ascontiguousarray(keys, dtype=np.uint64)
+        amps = np.ascontiguousarray(amps, dtype=np.float64)
+        if keys.shape != amps.shape:
+            raise ValueError("keys and amps must have equal length")
+        self._check(self._lib.swcs_set_state(self._h, _ptr(keys, ctypes.c_uint64),
+                                             _ptr(amps, ctypes.c_double), len(keys)))
+
+    def get_state(self):
+        """(keys uint64, amps float64), sorted ascending by key."""
+        n = ctypes.c_int64()
+        rc = self._lib.swcs_get_state(self._h, None, None, 0, ctypes.byref(n))
+        if rc not in (SWCS_OK, SWCS_E_INVALID):
+            self._check(rc)
+        cnt = int(n.value)
+        keys = np.zeros(cnt, dtype=np.uint64)
+        amps = np.zeros(cnt, dtype=np.float64)
+        self._check(self._lib.swcs_get_state(self._h, _ptr(keys, ctypes.c_uint64),
+                                             _ptr(amps, ctypes.c_double), cnt, ctypes.byref(n)))
+        return keys, amps
+
+    # -- energy and gradients ------------------------------------------
+    def energy(self):
+        """(E, numer, norm2)."""
+        e, nu, no = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        self._check(self._lib.swcs_energy(self._h, ctypes.byref(e), ctypes.byref(nu),
+                                          ctypes.byref(no)))
+        return e.value, nu.value, no.value
+
+    def sigma_projected(self):
+        """(keys, sigma_P) on the kept determinants, sorted by key."""
+        n = ctypes.c_int64()
+        rc = self._lib.swcs_sigma_projected(self._h, None, None, 0, ctypes.byref(n))
+        if rc not in (SWCS_OK, SWCS_E_INVALID):
+            self._check(rc)
+        cnt = int(n.value)
+        keys = np.zeros(cnt, dtype=np.uint64)
+        sig = np.zeros(cnt, dtype=np.float64)
+        self._check(self._lib.swcs_sigma_projected(self._h, _ptr(keys, ctypes.c_uint64),
+                                                   _ptr(sig, ctypes.c_double), cnt, ctypes.byref(n)))
+        return keys, sig
+
+    def pool_gradients(self, subset=None):
+        if subset is None:
+            out = np.zeros(self.K)
+            self._check(self._lib.swcs_pool_gradients(self._h, None, 0, _ptr(out, ctypes.c_double)))
+        else:
+            subset = np.ascontiguousarray(subset, dtype=np.int32)
+            out = np.zeros(len(subset))
+            self._check(self._lib.swcs_pool_gradients(self._h, _ptr(subset, ctypes.c_int32),
+                                                      len(subset), _ptr(out, ctypes.c_double)))
+        return out
+
+    def param_gradients(self, M: int):
+        """(dE/dtheta[M], E) of the last apply_ansatz."""
+        out = np.zeros(max(M, 1))
+        e = ctypes.c_double()
+        self._check(self._lib.swcs_param_gradients(self._h, _ptr(out, ctypes.c_double),
+                                                   ctypes.byref(e)))
+        return out[:M], e.value
+
+    def gate_sizes(self, M: int):
+        out = np.zeros(max(M, 1), dtype=np.int64)
+        self._check(self._lib.swcs_gate_sizes(self._h, _ptr(out, ctypes.c_int64), M))
+        return out[:M]
+
+    def occupations(self):
+        out = np.zeros(2 * self.n)
+        self._check(self._lib.swcs_occupations(self._h, _ptr(out, ctypes.c_double)))
+        return out
+
+    # -- screener (device tensors) --------------------------------------
+    def features(self, prev_absg, age, count, out):
+        self._check(self._lib.swcs_features(self._h, _dev(prev_absg), _dev(age), _dev(count),
+                                            _dev(out)))
+
+    def mlp_forward(self, W, x, y, act=None):
+        B = int(x.shape[0])
+        self._check(self._lib.swcs_mlp_forward(self._h, _dev(W), _dev(x), B, _dev(y), _dev(act)))
+
+    def mlp_backward(self, W, x, act, dy, dW):
+        B = int(x.shape[0])
+        self._check(self._lib.swcs_mlp_backward(self._h, _dev(W), _dev(x), _dev(act), _dev(dy), B,
+                                                _dev(dW)))
+
+    def mse(self, y, t, dy, loss):
+        self._check(self._lib.swcs_mse(self._h, _dev(y), _dev(t), int(y.shape[0]), _dev(dy),
+                                       _dev(loss)))
+
+    def adam_step(self, W, m, v, dW, lr, b1, b2, eps, step):
+        self._check(self._lib.swcs_adam_step(self._h, _dev(W), _dev(m), _dev(v), _dev(dW),
+                                             int(W.numel()), float(lr), float(b1), float(b2),
+                                             float(eps), int(step)))
+
+    def select(self, score, rand, n_top, n_rand, out_idx):
+        K = int(score.shape[0])
+        self._check(self._lib.swcs_select(self._h, _dev(score), _dev(rand), K, int(n_top),
+                                          int(n_rand), _dev(out_idx)))
+
+
+def make_context(n, n_alpha, n_beta, h, eri, pool, ref, device=0, e_core=0.0, stream=None):
+    ctx = Context(n, n_alpha, n_beta, device)
+    if stream is not None:
+        ctx.set_stream(stream)
+    ctx.set_integrals(h, eri, e_core)
+    ctx.set_reference(ref)
+    ctx.set_pool(pool)
+    return ctx
+
+
+def _autograd_function():
+    import torch
+
+    class AnsatzEnergy(torch.autograd.Function):
+        """E(theta) of an ansatz on a Context; backward = adjoint gradients.
+
+        forward(theta (float64 CPU tensor), ctx_obj, ops, eps, ncut) -> E
+        """
+
+        @staticmethod
+        def forward(fctx, theta, swcs_ctx, ops, eps, ncut):
+            th = theta.detach().cpu().numpy().astype(np.float64)
+            swcs_ctx.apply_ansatz(ops, th, eps, ncut)
+            dE, E = swcs_ctx.param_gradients(len(th))
+            fctx.save_for_backward(torch.from_numpy(dE))
+            return torch.tensor(E, dtype=torch.float64)
+
+        @staticmethod
+        def backward(fctx, grad_out):
+            (dE,) = fctx.saved_tensors
+            return grad_out * dE, None, None, None, None
+
+    return AnsatzEnergy
+
+
+def ansatz_energy(theta, swcs_ctx, ops, eps=0.0, ncut=0):
+    """torch autograd entry: E(theta) with adjoint backward."""
+    return _autograd_function().apply(theta, swcs_ctx, ops, eps, ncut)
