@@ -1,0 +1,285 @@
+"""Benchmark of the SWCS hot path on one MI355X.
+
+One step = one pass of the whole hot path over the synthetic 28-spin-orbital
+workload (14 spatial orbitals, 10 electrons, (pq|rs) of rank 14, 100-gate
+ansatz with theta ~ U(-0.05, 0.05), eps = 1e-6, generalized singles and
+doubles pool of 22,750 operators):
+
+  1. apply the ansatz from the reference with pruning (100 gates),
+  2. energy through the projected sigma vector,
+  3. exact pool gradients of the full pool (external sigma + contraction),
+  4. adjoint parameter gradients (sqrt(M) checkpoints, recompute, reverse),
+  5. learned screener: features, MLP scores for the pool, top 5 % + 1 %
+     random selection, exact gradients of the selection and one training
+     step (forward, MSE, backward, Adam) on them.
+
+Prints one JSON line.  `value` is determinant-excitation applies per second
+over the whole step: the number of (determinant, gate) applications the step
+performs (forward gates, adjoint recompute gates and reverse gates, each
+counted by the kept determinants entering the gate) divided by the step time.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from paper_2411_07920_amd.inputs import (CONFIGS, array_digest, draw_ansatz,  # noqa: E402
+                                         draw_random_keys, enumerate_pool, make_integrals,
+                                         reference_key)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c2", choices=sorted(CONFIGS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-phase", default=None,
+                    help="run only this phase in a loop (for counter collection)")
+    return ap.parse_args()
+
+
+class Workload:
+    def __init__(self, name):
+        c = CONFIGS[name]
+        self.c = c
+        self.h, self.eri = make_integrals(c.n, c.rank, c.seed_int)
+        self.pool = enumerate_pool(c.n)
+        self.ops, self.theta = draw_ansatz(len(self.pool), c.n_ops, c.theta_lo, c.theta_hi,
+                                           c.seed_ansatz)
+        self.ref = reference_key(c.n_elec)
+        self.na = c.n_elec // 2
+        self.K = len(self.pool)
+        self.n_top = int(math.ceil(0.05 * self.K))
+        self.n_rand = int(math.ceil(0.01 * self.K))
+        self.rand = draw_random_keys(self.K, 3000 + int(name[1:]))
+        self.digest = array_digest(self.h, self.eri, self.pool, self.ops, self.theta)
+
+
+def applies_in_step(n_in, seg):
+    """(forward, adjoint) determinant-gate applications of one step."""
+    M = len(n_in)
+    fwd = int(n_in.sum())
+    recompute = 0
+    for g in range(M):
+        seg_lo = (g // seg) * seg
+        seg_hi = min(M, seg_lo + seg)
+        if g < seg_hi - 1:  # gates g_lo .. g_hi-2 are recomputed per segment
+            recompute += int(n_in[g])
+    return fwd, recompute + fwd
+
+
+def gpu_bench(args, wl):
+    import torch
+    from paper_2411_07920_amd import swcs
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    ctx = swcs.make_context(wl.c.n, wl.na, wl.na, wl.h, wl.eri, wl.pool, wl.ref, stream=stream)
+    dev = "cuda"
+    K = wl.K
+    P = swcs.mlp_param_count()
+    rng = np.random.default_rng(3000)
+    w0 = np.zeros(P, dtype=np.float32)
+    # He-normal initial weights (the values do not change the work done)
+    w0[: 16 * 128] = rng.normal(0, math.sqrt(2 / 16), 16 * 128)
+    off = 16 * 128 + 128
+    w0[off: off + 128 * 128] = rng.normal(0, math.sqrt(2 / 128), 128 * 128)
+    off += 128 * 128 + 128
+    w0[off: off + 128] = rng.normal(0, math.sqrt(2 / 128), 128)
+    W = torch.from_numpy(w0).to(dev)
+    Mt = torch.zeros(P, device=dev)
+    Vt = torch.zeros(P, device=dev)
+    dW = torch.zeros(P, device=dev)
+    prev = torch.zeros(K, device=dev)
+    age = torch.zeros(K, device=dev)
+    count = torch.zeros(K, device=dev)
+    feat = torch.zeros((K, 16), device=dev)
+    score = torch.zeros(K, device=dev)
+    rnd = torch.from_numpy(wl.rand.astype(np.int32)).to(dev)
+    nsel = wl.n_top + wl.n_rand
+    sel = torch.zeros(nsel, dtype=torch.int32, device=dev)
+    xs = torch.zeros((nsel, 16), device=dev)
+    ys = torch.zeros(nsel, device=dev)
+    act = torch.zeros((nsel, 256), device=dev)
+    tgt = torch.zeros(nsel, device=dev)
+    dy = torch.zeros(nsel, device=dev)
+    loss = torch.zeros(1, device=dev)
+    M = len(wl.ops)
+    state = {"adam": 0}
+
+    def phase_apply():
+        return ctx.apply_ansatz(wl.ops, wl.theta, wl.c.eps)
+
+    def phase_energy():
+        return ctx.energy()
+
+    def phase_pool():
+        return ctx.pool_gradients()
+
+    def phase_adjoint():
+        return ctx.param_gradients(M)
+
+    def phase_screener():
+        ctx.features(prev, age, count, feat)
+        ctx.mlp_forward(W, feat, score)
+        ctx.select(score, rnd, wl.n_top, wl.n_rand, sel)
+        idx = sel.cpu().numpy()
+        g = ctx.pool_gradients(idx)
+        # targets log10(|g| + 1e-12) of the exact gradients of the selection
+        tgt.copy_(torch.from_numpy(np.log10(np.abs(g) + 1e-12).astype(np.float32)))
+        torch.index_select(feat, 0, sel.long(), out=xs)
+        ctx.mlp_forward(W, xs, ys, act)
+        ctx.mse(ys, tgt, dy, loss)
+        ctx.mlp_backward(W, xs, act, dy, dW)
+        state["adam"] += 1
+        ctx.adam_step(W, Mt, Vt, dW, 1e-3, 0.9, 0.999, 1e-8, state["adam"])
+
+    phases = [("apply", phase_apply), ("energy", phase_energy), ("pool_gradients", phase_pool),
+              ("adjoint", phase_adjoint), ("screener", phase_screener)]
+
+    if args.profile_phase:
+        fn = dict(phases)[args.profile_phase]
+        phase_apply()
+        for _ in range(args.steps):
+            fn()
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_phase": args.profile_phase, "steps": args.steps}))
+        return None
+
+    def step(events=None):
+        for i, (name, fn) in enumerate(phases):
+            if events is not None:
+                events[i][0].record(stream)
+            fn()
+            if events is not None:
+                events[i][1].record(stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ev = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in phases] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        step(ev[s])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    phase_ms = {name: float(np.mean([ev[s][i][0].elapsed_time(ev[s][i][1]) for s in range(args.steps)]))
+                for i, (name, _) in enumerate(phases)}
+
+    # Work counts of one step.
+    n_det = phase_apply()
+    n_in = ctx.gate_sizes(M)
+    seg = max(1, int(math.ceil(math.sqrt(M))))
+    fwd_applies, adj_applies = applies_in_step(n_in, seg)
+    applies = fwd_applies + adj_applies
+
+    # Dominant kernel measurement: the gate kernel, timed as the apply phase
+    # (M launches) with events on the context stream.
+    reps = 20
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        phase_apply()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    apply_ms = e0.elapsed_time(e1) / reps
+    ctx.close()
+    return dict(ms_step=ms_step, phase_ms=phase_ms, n_det=n_det, n_in=n_in, applies=applies,
+                fwd_applies=fwd_applies, adj_applies=adj_applies, apply_ms=apply_ms, seg=seg)
+
+
+def cpu_baseline(wl, fwd_applies, adj_applies, budget_s=20.0):
+    """The oracle timed on the host on a bounded sample of one step."""
+    import oracle
+    orc = oracle.Oracle(wl.c.n, wl.na, wl.na, wl.h, wl.eri)
+    t = time.perf_counter()
+    st = oracle.Oracle.apply_ansatz(wl.pool, wl.ops, wl.theta, wl.c.eps, wl.ref)
+    t_apply = time.perf_counter() - t
+    t = time.perf_counter()
+    orc.energy(st)
+    t_energy = time.perf_counter() - t
+    t = time.perf_counter()
+    orc.param_gradients(wl.pool, wl.ops, wl.theta, wl.c.eps, wl.ref)
+    t_adj = time.perf_counter() - t
+    # pool gradients on a sample of operators, scaled to the full pool
+    rng = np.random.default_rng(0)
+    sample = np.sort(rng.choice(wl.K, min(wl.K, 2000), replace=False)).astype(np.int32)
+    t = time.perf_counter()
+    orc.pool_gradients(st, wl.pool, subset=sample)
+    t_pool_sample = time.perf_counter() - t
+    t_pool = t_pool_sample * wl.K / len(sample)
+    t_step = t_apply + t_energy + t_adj + t_pool * (1.0 + (wl.n_top + wl.n_rand) / wl.K)
+    return {
+        "value": (fwd_applies + adj_applies) / t_step,
+        "unit": "determinant-excitation applies/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"one step of the same workload: full apply, energy and adjoint; pool gradients "
+                   f"of {len(sample)} of {wl.K} operators scaled by {wl.K / len(sample):.2f}; "
+                   f"step {t_step:.2f} s"),
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(see DESIGN.md for how the work would shard).", file=sys.stderr)
+        sys.exit(2)
+    wl = Workload(args.workload)
+    r = gpu_bench(args, wl)
+    if r is None:
+        return
+    M = len(wl.ops)
+    # Algorithmic bytes of the gate kernel (per gate): 8 B key scan per stored
+    # determinant, 16 B amplitude read+write per touched determinant, 16 B key +
+    # amplitude per appended one.  Use the lower bound 8 B per kept determinant
+    # entering the gate plus 16 B per applied pair member.
+    n_in = r["n_in"]
+    bytes_apply = float(8 * n_in.sum())
+    achieved = bytes_apply / (r["apply_ms"] * 1e-3) / 1e9
+    line = {
+        "metric": "determinant-excitation applies/s",
+        "value": r["applies"] / (r["ms_step"] * 1e-3),
+        "unit": "determinant-excitation applies/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["ms_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {wl.c.n_so} spin-orbitals, {wl.c.n_elec} electrons, "
+                               f"{M}-gate ansatz, eps={wl.c.eps:g}, pool {wl.K}",
+                   "n_det_final": r["n_det"], "applies_per_step": r["applies"],
+                   "input_sha256": wl.digest[:16]},
+        "phases_ms": {k: round(v, 4) for k, v in r["phase_ms"].items()},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_gate", "per_launch_us": r["apply_ms"] * 1e3 / M},
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(wl, r["fwd_applies"], r["adj_applies"])
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -100,7 +100,8 @@ int swcs_set_integrals(swcs_ctx* ctx, const double* h, const double* eri, double
 int swcs_set_reference(swcs_ctx* ctx, uint64_t det);
 
 /* Step 2: the operator pool, int32 ops[K*4] (host, rows as above).  Rows are
- * validated (range, ordering, disjointness, spin conservation). */
+ * validated (range, ordering, disjointness, spin conservation, canonical
+ * orientation (P, Q) > (R, S) for doubles, no duplicate rows). */
 int swcs_set_pool(swcs_ctx* ctx, const int32_t* ops, int64_t K);
 
 /* Eq. (1): psi = prod_I U_I(theta_I) psi_0 with psi_0 = the reference, the

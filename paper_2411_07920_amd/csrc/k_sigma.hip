@@ -177,45 +177,67 @@ k_sigma_push(const u64* __restrict__ keys, const double* __restrict__ amps, Ints
   }
 }
 
-// Pool-gradient contraction, operator-major.  Block (x, y) takes a tile of
-// determinants staged in LDS (x) and 256 pool operators, one per thread (y); each
-// thread accumulates psi(D) a_k(D) sigma(X_k(D)) over the tile, where
-// a_k(D) = <X|T|D> if T acts on D and -<X|T^dagger|D> if T^dagger does.
-constexpr int kContractTile = 1024;
+// Pool-gradient contraction, determinant-major: for every alive D and every
+// single / double X of D, the pool operator k linking them (found through the
+// generator map) receives psi(D) a_k(D) sigma(X), where a_k(D) = <X|T_k|D>
+// if T_k acts on D and -<X|T_k^dagger|D> if T_k^dagger does.  The canonical
+// orientation (P > Q, R > S, (P, Q) > (R, S)) decides which of the two acts.
+__device__ inline u64 generator_key(int P, int Q, int R, int S) {
+  return 1ULL + (u64)P + ((u64)Q << 8) + ((u64)(R + 1) << 16) + ((u64)(S + 1) << 24);
+}
 
-__global__ void __launch_bounds__(256)
-k_pool_contract(const u64* __restrict__ keys, const double* __restrict__ amps, u64 n,
-                const OpDesc* __restrict__ ops, const int* __restrict__ subset, long long n_ops,
-                const AccSlot* __restrict__ tab, u64 tmask, double* __restrict__ g, double scale) {
-  __shared__ u64 skey[kContractTile];
-  __shared__ double samp[kContractTile];
-  const u64 t0 = (u64)blockIdx.x * kContractTile;
-  const int tile = (int)((n - t0) < (u64)kContractTile ? (n - t0) : (u64)kContractTile);
-  for (int t = threadIdx.x; t < tile; t += blockDim.x) {
-    const double a = amps[t0 + t];
-    skey[t] = is_dead(a) ? 0ULL : keys[t0 + t];
-    samp[t] = a;
+__global__ void __launch_bounds__(kSigBlock)
+k_pool_contract_det(const u64* __restrict__ keys, const double* __restrict__ amps, ExcSpace E,
+                    int n_spatial, u64 n, const HashSlot* __restrict__ opmap, u64 omask,
+                    const unsigned char* __restrict__ selected, const OpDesc* __restrict__ ops,
+                    const AccSlot* __restrict__ tab, u64 tmask, double* __restrict__ gacc) {
+  __shared__ SigShared S;
+  build_pair_table(S);
+  const int C = (int)E.total;
+  for (u64 d = blockIdx.x; d < n; d += gridDim.x) {
+    const double psiD = amps[d];
+    if (is_dead(psiD)) continue;
+    const u64 D = keys[d];
+    __syncthreads();
+    build_lists_shared(D, n_spatial, S);
+    __syncthreads();
+    for (int c = threadIdx.x; c < C; c += kSigBlock) {
+      int h0, h1 = 0, p0, p1 = 0;
+      const int nh = decode_shared(E, S, c, &h0, &h1, &p0, &p1);
+      u64 X = D ^ (1ULL << h0) ^ (1ULL << p0);
+      if (nh == 2) X ^= (1ULL << h1) ^ (1ULL << p1);
+      bool t_acts;
+      u64 gk;
+      if (nh == 1) {
+        t_acts = p0 > h0;
+        gk = t_acts ? generator_key(p0, h0, -1, -1) : generator_key(h0, p0, -1, -1);
+      } else {
+        t_acts = (p1 > h1) || (p1 == h1 && p0 > h0);
+        gk = t_acts ? generator_key(p1, p0, h1, h0) : generator_key(h1, h0, p1, p0);
+      }
+      const long long k = hash_find(opmap, omask, gk);
+      if (k < 0) continue;
+      if (selected && !selected[k]) continue;
+      double sx;
+      if (!acc_find(tab, tmask, X, &sx)) continue;
+      const OpDesc op = ops[k];
+      const double a = t_acts ? (double)phase_of_T(op, D) : -(double)phase_of_T(op, X);
+      unsafeAtomicAdd(&gacc[k], psiD * a * sx);
+    }
   }
-  __syncthreads();
-  const long long slot = (long long)blockIdx.y * blockDim.x + threadIdx.x;
-  if (slot >= n_ops) return;
-  const int k = subset ? subset[slot] : (int)slot;
-  const OpDesc op = ops[k];
-  const u64 pm = op.ann | op.cre;
-  double acc = 0.0;
-  for (int t = 0; t < tile; ++t) {
-    const u64 D = skey[t];
-    if (D == 0ULL) continue;
-    const bool isT = ((D & op.ann) == op.ann) && ((D & op.cre) == 0);
-    const bool isTd = ((D & op.cre) == op.cre) && ((D & op.ann) == 0);
-    if (!(isT || isTd)) continue;
-    const u64 X = D ^ pm;
-    double sx;
-    if (!acc_find(tab, tmask, X, &sx)) continue;
-    const double a = isT ? (double)phase_of_T(op, D) : -(double)phase_of_T(op, X);
-    acc += samp[t] * a * sx;
-  }
-  if (acc != 0.0) unsafeAtomicAdd(&g[slot], scale * acc);
+}
+
+// out[t] = scale * gacc[subset[t]] (subset == NULL: identity).
+__global__ void k_gather_scaled(const double* __restrict__ gacc, const int* __restrict__ subset,
+                                long long count, double scale, double* __restrict__ out) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < count) out[t] = scale * gacc[subset ? subset[t] : t];
+}
+
+__global__ void k_mark_selected(const int* __restrict__ subset, long long count,
+                                unsigned char* __restrict__ selected) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < count) selected[subset[t]] = 1;
 }
 
 // Per-block partial sums of psi^2 [P in D] for P < nso and of psi^2.
@@ -307,14 +329,28 @@ hipError_t launch_sigma_push(const DeviceState& st, const Ints& I, const ExcSpac
   return hipGetLastError();
 }
 
-hipError_t launch_pool_contract_ops(const DeviceState& st, u64 n, const OpDesc* ops,
-                                    const int* subset, long long n_ops, const AccSlot* tab,
-                                    u64 tmask, double* g, double scale, hipStream_t stream) {
-  if (n == 0 || n_ops == 0) return hipSuccess;
-  const unsigned gy = (unsigned)((n_ops + 255) / 256);
-  const unsigned gx = (unsigned)((n + kContractTile - 1) / kContractTile);
-  hipLaunchKernelGGL(k_pool_contract, dim3(gx, gy), dim3(256), 0, stream, st.keys, st.amps, n, ops,
-                     subset, n_ops, tab, tmask, g, scale);
+hipError_t launch_pool_contract_det(const DeviceState& st, const ExcSpace& E, int n_spatial, u64 n,
+                                   const HashSlot* opmap, u64 omask, const unsigned char* selected,
+                                   const OpDesc* ops, const AccSlot* tab, u64 tmask, double* gacc,
+                                   int grid, hipStream_t stream) {
+  hipLaunchKernelGGL(k_pool_contract_det, dim3(grid), dim3(kSigBlock), 0, stream, st.keys, st.amps,
+                     E, n_spatial, n, opmap, omask, selected, ops, tab, tmask, gacc);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_scaled(const double* gacc, const int* subset, long long count, double scale,
+                                double* out, hipStream_t stream) {
+  if (count == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather_scaled, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, stream,
+                     gacc, subset, count, scale, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_mark_selected(const int* subset, long long count, unsigned char* selected,
+                                hipStream_t stream) {
+  if (count == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_mark_selected, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, stream,
+                     subset, count, selected);
   return hipGetLastError();
 }
 

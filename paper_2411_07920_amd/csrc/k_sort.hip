@@ -204,22 +204,32 @@ __device__ inline unsigned float_code(float f) {
   return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
 }
 
-__global__ void k_select_keys_top(const float* __restrict__ score, long long K, u64* __restrict__ out) {
+// Sort keys for the two selection passes; payloads are the operator indices.
+// The LSD sort is stable and inputs are in index order, so ties keep the
+// smaller index first.
+__global__ void k_select_keys_top(const float* __restrict__ score, long long K, u64* __restrict__ keys,
+                                  u64* __restrict__ idx) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < K) out[i] = ((u64)(~float_code(score[i])) << 32) | (u64)i;
+  if (i < K) {
+    keys[i] = (u64)(~float_code(score[i]));  // larger score first
+    idx[i] = (u64)i;
+  }
 }
 
-__global__ void k_select_mark(const u64* __restrict__ sorted, long long take,
+__global__ void k_select_mark(const u64* __restrict__ idx_sorted, long long take,
                               unsigned char* __restrict__ flags) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < take) flags[sorted[i] & 0xffffffffULL] = 1;
+  if (i < take) flags[idx_sorted[i]] = 1;
 }
 
 __global__ void k_select_keys_rand(const uint32_t* __restrict__ rnd,
                                    const unsigned char* __restrict__ flags, long long K,
-                                   u64* __restrict__ out) {
+                                   u64* __restrict__ keys, u64* __restrict__ idx) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < K) out[i] = flags[i] ? ~0ULL : (((u64)rnd[i] << 32) | (u64)i);
+  if (i < K) {
+    keys[i] = ((u64)flags[i] << 32) | (u64)rnd[i];  // already chosen ones last
+    idx[i] = (u64)i;
+  }
 }
 
 __global__ void k_select_clear(unsigned char* flags, long long K) {
@@ -227,25 +237,43 @@ __global__ void k_select_clear(unsigned char* flags, long long K) {
   if (i < K) flags[i] = 0;
 }
 
-// Ascending list of flagged indices: one block, running prefix over chunks.
-__global__ void __launch_bounds__(256)
-k_select_gather(const unsigned char* __restrict__ flags, long long K, int* __restrict__ idx) {
+// Ascending list of flagged indices: per-tile counts, scan, ordered scatter.
+__global__ void __launch_bounds__(kSortThreads)
+k_flag_count(const unsigned char* __restrict__ flags, long long K, u64* __restrict__ counts) {
+  __shared__ unsigned c;
+  if (threadIdx.x == 0) c = 0;
+  __syncthreads();
+  const u64 base = (u64)blockIdx.x * kSortTile;
+  unsigned mine = 0;
+  for (int r = 0; r < kSortRows; ++r) {
+    const u64 i = base + (u64)r * kSortThreads + threadIdx.x;
+    if (i < (u64)K && flags[i]) ++mine;
+  }
+  atomicAdd(&c, mine);
+  __syncthreads();
+  if (threadIdx.x == 0) counts[blockIdx.x] = c;
+}
+
+__global__ void __launch_bounds__(kSortThreads)
+k_flag_scatter(const unsigned char* __restrict__ flags, long long K, const u64* __restrict__ offsets,
+               int* __restrict__ idx) {
   __shared__ unsigned wave_cnt[4];
-  __shared__ unsigned long long running;
+  __shared__ unsigned running;
   const int lane = __lane_id();
   const int wave = threadIdx.x >> 6;
   if (threadIdx.x == 0) running = 0;
-  __syncthreads();
-  for (long long b = 0; b < K; b += 256) {
-    const long long i = b + threadIdx.x;
-    const bool f = i < K && flags[i];
+  const u64 base = (u64)blockIdx.x * kSortTile;
+  const u64 off = offsets[blockIdx.x];
+  for (int r = 0; r < kSortRows; ++r) {
+    const u64 i = base + (u64)r * kSortThreads + threadIdx.x;
+    const bool f = i < (u64)K && flags[i];
     const u64 m = __ballot(f);
     if (lane == 0) wave_cnt[wave] = (unsigned)__popcll(m);
     __syncthreads();
     if (f) {
-      unsigned long long pos = running + (unsigned)__popcll(m & ((1ULL << lane) - 1ULL));
+      unsigned pos = running + (unsigned)__popcll(m & ((1ULL << lane) - 1ULL));
       for (int w = 0; w < wave; ++w) pos += wave_cnt[w];
-      idx[pos] = (int)i;
+      idx[off + pos] = (int)i;
     }
     __syncthreads();
     if (threadIdx.x == 0) running += wave_cnt[0] + wave_cnt[1] + wave_cnt[2] + wave_cnt[3];
@@ -254,8 +282,8 @@ k_select_gather(const unsigned char* __restrict__ flags, long long K, int* __res
 }
 
 u64 select_scratch_elems(long long K) {
-  // keys, tmp keys, flags (bytes, rounded up), sort histogram scratch
-  return 2 * (u64)K + ((u64)K + 7) / 8 + radix_sort_scratch_elems((u64)K);
+  // keys, idx, tmp keys, tmp idx, flags (bytes, rounded up), sort scratch
+  return 4 * (u64)K + ((u64)K + 7) / 8 + radix_sort_scratch_elems((u64)K) + 8;
 }
 
 hipError_t launch_select(const float* score, const uint32_t* rnd, long long K, long long n_top,
@@ -263,26 +291,33 @@ hipError_t launch_select(const float* score, const uint32_t* rnd, long long K, l
                          hipStream_t stream) {
   if (scratch_elems < select_scratch_elems(K)) return hipErrorInvalidValue;
   u64* keys = scratch;
-  u64* tmp = scratch + K;
-  unsigned char* flags = (unsigned char*)(scratch + 2 * K);
-  u64* hist = scratch + 2 * K + (K + 7) / 8;
+  u64* ids = scratch + K;
+  u64* tk = scratch + 2 * K;
+  u64* ti = scratch + 3 * K;
+  unsigned char* flags = (unsigned char*)(scratch + 4 * K);
+  u64* hist = scratch + 4 * K + (K + 7) / 8;
   const u64 hist_elems = radix_sort_scratch_elems((u64)K);
   const unsigned g = (unsigned)((K + 255) / 256);
   hipLaunchKernelGGL(k_select_clear, dim3(g), dim3(256), 0, stream, flags, K);
-  hipLaunchKernelGGL(k_select_keys_top, dim3(g), dim3(256), 0, stream, score, K, keys);
-  hipError_t e = radix_sort_pairs(keys, nullptr, tmp, nullptr, (u64)K, 64, hist, hist_elems, stream);
-  if (e != hipSuccess) return e;
-  if (n_top > 0)
+  if (n_top > 0) {
+    hipLaunchKernelGGL(k_select_keys_top, dim3(g), dim3(256), 0, stream, score, K, keys, ids);
+    hipError_t e = radix_sort_pairs(keys, ids, tk, ti, (u64)K, 32, hist, hist_elems, stream);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_select_mark, dim3((unsigned)((n_top + 255) / 256)), dim3(256), 0, stream,
-                       keys, n_top, flags);
+                       ids, n_top, flags);
+  }
   if (n_rand > 0) {
-    hipLaunchKernelGGL(k_select_keys_rand, dim3(g), dim3(256), 0, stream, rnd, flags, K, keys);
-    e = radix_sort_pairs(keys, nullptr, tmp, nullptr, (u64)K, 64, hist, hist_elems, stream);
+    hipLaunchKernelGGL(k_select_keys_rand, dim3(g), dim3(256), 0, stream, rnd, flags, K, keys, ids);
+    hipError_t e = radix_sort_pairs(keys, ids, tk, ti, (u64)K, 33, hist, hist_elems, stream);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_select_mark, dim3((unsigned)((n_rand + 255) / 256)), dim3(256), 0, stream,
-                       keys, n_rand, flags);
+                       ids, n_rand, flags);
   }
-  hipLaunchKernelGGL(k_select_gather, dim3(1), dim3(256), 0, stream, flags, K, idx);
+  const int nblocks = (int)((K + kSortTile - 1) / kSortTile);
+  hipLaunchKernelGGL(k_flag_count, dim3(nblocks), dim3(kSortThreads), 0, stream, flags, K, hist);
+  hipLaunchKernelGGL(k_scan_exclusive, dim3(1), dim3(1024), 0, stream, hist, (u64)nblocks);
+  hipLaunchKernelGGL(k_flag_scatter, dim3(nblocks), dim3(kSortThreads), 0, stream, flags, K, hist,
+                     idx);
   return hipGetLastError();
 }
 

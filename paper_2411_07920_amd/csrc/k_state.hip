@@ -1,41 +1,33 @@
-// State kernels: hash index maintenance, the excitation-unitary gate with
-// fused pruning, the reverse (adjoint) gate step and small utilities.
+// State kernels in HBM: the multi-block gate with fused pruning and wave-
+// aggregated appends, the reverse (adjoint) step, hash index maintenance,
+// checkpoints and small utilities.  The per-entry arithmetic is in
+// gate_ops.h, shared with the LDS-resident single-workgroup kernels.
 //
 // State layout in HBM (structure of arrays, one entry per stored determinant):
 //   keys[cap]  uint64 determinant bit strings (never reordered within a run)
 //   amps[cap]  float64 amplitudes, kDeadBits for entries not in the state
 //   hash[2^k]  16-byte slots {key, index}, linear probing, load <= 1/2
-// A gate exp(theta A) with A = T - T^dagger pairs each determinant D on which
-// T acts with X = T D (sign s = <X|T|D>) and rotates the pair:
-//   psi'(D) = c psi(D) - s sn psi(X),   psi'(X) = c psi(X) + s sn psi(D)
-// (c = cos theta, sn = sin theta), the exact value of exp(theta A) because
-// T^2 = 0 and A^3 = -A (Sec. II.B evaluates each unitary exactly).  Every
-// other determinant is unchanged.  Each output is a sum of two rounded
-// products formed in a fixed order, so the result does not depend on thread
-// scheduling.  Pruning (drop |c| < eps, Fig. 1) is applied to the touched
-// entries only, since untouched ones kept their already-accepted value.
-#include "swcs_internal.h"
+#include "gate_ops.h"
 
 namespace swcs {
 
-// Ownership rule that makes the in-place update race-free: the pair (D, X) is
-// processed by the thread of D whenever D is stored (alive or not); otherwise
-// by the thread of X, which then appends D.  Lookups only ever target keys
-// stored before the launch, and appended keys are new and distinct.
 __global__ void __launch_bounds__(256)
 k_gate(u64* __restrict__ keys, double* __restrict__ amps, HashSlot* __restrict__ hash, u64 hmask,
        u64 cap, Counters* __restrict__ ctr, OpDesc op, double c, double sn, double eps,
-       u64* __restrict__ gate_n_in, int check_cap, unsigned gate_index) {
+       u64* __restrict__ gate_n_in, int check_cap, unsigned gate_index, u64 max_keys) {
   // A stopped chain skips every later gate; the host resumes it after growing.
   if (__hip_atomic_load(&ctr->flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kFlagStopped)
     return;
   const u64 n_in = __hip_atomic_load(&ctr->n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  // Appends are bounded by the alive sources, so n_in + alive_in <= cap
-  // guarantees the gate fits.  Every block reads the same values and takes
-  // the same decision; nothing has been modified when it stops.
+  // Appends are bounded by the alive sources and by the number of keys not
+  // yet stored (max_keys = size of the electron-number sector), so
+  // n_in + min(alive_in, max_keys - n_in) <= cap guarantees the gate fits.
+  // Every block reads the same values and takes the same decision; nothing
+  // has been modified when it stops.
   if (check_cap) {
     const u64 alive_in = __hip_atomic_load(&ctr->alive, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (n_in + alive_in > cap) {
+    const u64 room = max_keys > n_in ? max_keys - n_in : 0;
+    if (n_in + (alive_in < room ? alive_in : room) > cap) {
       if (blockIdx.x == 0 && threadIdx.x == 0) {
         ctr->stop_gate = gate_index;
         atomicOr(&ctr->flags, kFlagStopped);
@@ -43,62 +35,15 @@ k_gate(u64* __restrict__ keys, double* __restrict__ amps, HashSlot* __restrict__
       return;
     }
   }
-  const u64 pair_mask = op.ann | op.cre;
+  GlobalStore S{keys, amps, hash, hmask};
   long long dalive = 0;
   const u64 stride = (u64)gridDim.x * blockDim.x;
   for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < n_in; i += stride) {
-    const u64 D = keys[i];
-    const bool isT = ((D & op.ann) == op.ann) && ((D & op.cre) == 0);
-    const bool isTd = ((D & op.cre) == op.cre) && ((D & op.ann) == 0);
-    bool want_append = false;
-    u64 app_key = 0;
-    double app_val = 0.0;
-    if (isT) {
-      const u64 X = D ^ pair_mask;
-      const long long j = hash_find(hash, hmask, X);
-      const double araw = amps[i];
-      const double braw = (j >= 0) ? amps[j] : dead_value();
-      const bool aliveD = !is_dead(araw), aliveX = !is_dead(braw);
-      if (aliveD || aliveX) {
-        const double s = (double)phase_of_T(op, D);
-        const double a = aliveD ? araw : 0.0;
-        const double b = aliveX ? braw : 0.0;
-        const double nd = c * a - s * (sn * b);
-        const double nx = c * b + s * (sn * a);
-        const bool keepD = !(fabs(nd) < eps);
-        const bool keepX = !(fabs(nx) < eps);
-        amps[i] = keepD ? nd : dead_value();
-        if (j >= 0) {
-          amps[j] = keepX ? nx : dead_value();
-        } else if (keepX) {
-          want_append = true;
-          app_key = X;
-          app_val = nx;
-        }
-        dalive += (long long)keepD - (long long)aliveD + (long long)keepX - (long long)aliveX;
-      }
-    } else if (isTd) {
-      const u64 Dsrc = D ^ pair_mask;
-      const long long j = hash_find(hash, hmask, Dsrc);
-      // When Dsrc is stored its thread owns the pair and may be writing this
-      // entry; only read it when this thread is the owner.
-      const double braw = (j < 0) ? amps[i] : dead_value();
-      if (j < 0 && !is_dead(braw)) {
-        const double s = (double)phase_of_T(op, Dsrc);
-        const double a = 0.0, b = braw;
-        const double nd = c * a - s * (sn * b);
-        const double nx = c * b + s * (sn * a);
-        const bool keepD = !(fabs(nd) < eps);
-        const bool keepX = !(fabs(nx) < eps);
-        amps[i] = keepX ? nx : dead_value();
-        if (keepD) {
-          want_append = true;
-          app_key = Dsrc;
-          app_val = nd;
-        }
-        dalive += (long long)keepD + (long long)keepX - 1LL;
-      }
-    }
+    const GateOut o = gate_entry(S, i, op, c, sn, eps);
+    dalive += o.dalive;
+    const bool want_append = o.append;
+    const u64 app_key = o.key;
+    const double app_val = o.val;
     // Wave-aggregated append.
     const u64 m = __ballot(want_append);
     if (m) {
@@ -151,47 +96,19 @@ k_gate(u64* __restrict__ keys, double* __restrict__ amps, HashSlot* __restrict__
   }
 }
 
-// Reverse step of one gate for the frozen-support adjoint.  psi_prev holds
-// the state before the gate (entries not in it are dead), mu holds the
-// adjoint vector after the gate (zero outside the kept support).  Writes the
-// adjoint before the gate in place and this block's share of
-// dE/dtheta = <mu | P U'(theta) psi_prev>, U' = derivative of the 2x2 rotation.
+// Reverse step of one gate (see adjoint_entry); per-block partial sums of
+// dE/dtheta go to partial[blockIdx.x].
 __global__ void __launch_bounds__(256)
 k_adjoint_step(const u64* __restrict__ keys, const HashSlot* __restrict__ hash, u64 hmask,
                u64 n_total, OpDesc op, double c, double sn, const double* __restrict__ psi_prev,
                double* __restrict__ mu, double* __restrict__ partial) {
-  const u64 pair_mask = op.ann | op.cre;
+  GlobalStore K{(u64*)keys, nullptr, hash, hmask};
+  GlobalPrev prev{psi_prev};
+  GlobalMu m{mu};
   double acc = 0.0;
   const u64 stride = (u64)gridDim.x * blockDim.x;
-  for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < n_total; i += stride) {
-    const u64 D = keys[i];
-    const bool isT = ((D & op.ann) == op.ann) && ((D & op.cre) == 0);
-    const bool isTd = ((D & op.cre) == op.cre) && ((D & op.ann) == 0);
-    if (isT) {
-      const u64 X = D ^ pair_mask;
-      const long long j = hash_find(hash, hmask, X);
-      const double araw = psi_prev[i];
-      const double braw = (j >= 0) ? psi_prev[j] : dead_value();
-      const bool aliveD = !is_dead(araw), aliveX = !is_dead(braw);
-      if (!aliveD && !aliveX) continue;
-      const double s = (double)phase_of_T(op, D);
-      const double a = aliveD ? araw : 0.0, b = aliveX ? braw : 0.0;
-      const double muD = mu[i];
-      const double muX = (j >= 0) ? mu[j] : 0.0;
-      acc += muD * (-sn * a - s * c * b) + muX * (-sn * b + s * c * a);
-      mu[i] = aliveD ? (c * muD + s * sn * muX) : 0.0;
-      if (j >= 0) mu[j] = aliveX ? (c * muX - s * sn * muD) : 0.0;
-    } else if (isTd) {
-      const u64 Dsrc = D ^ pair_mask;
-      const long long j = hash_find(hash, hmask, Dsrc);
-      if (j >= 0) continue;  // the thread of Dsrc owns the pair
-      const double braw = psi_prev[i];
-      if (is_dead(braw)) continue;
-      const double muX = mu[i];
-      acc += muX * (-sn * braw);
-      mu[i] = c * muX;
-    }
-  }
+  for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < n_total; i += stride)
+    acc += adjoint_entry(K, prev, m, i, op, c, sn);
   __shared__ double sacc[256];
   sacc[threadIdx.x] = acc;
   __syncthreads();
@@ -216,10 +133,45 @@ __global__ void k_hash_build(const u64* __restrict__ keys, HashSlot* hash, u64 h
     hash_insert_new(hash, hmask, keys[i], i);
 }
 
+// Same, with the entry count read from the device counters.
+__global__ void k_hash_build_dev(const u64* __restrict__ keys, HashSlot* hash, u64 hmask,
+                                 const Counters* __restrict__ ctr) {
+  const u64 n = __hip_atomic_load(&ctr->n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const u64 stride = (u64)gridDim.x * blockDim.x;
+  for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+    hash_insert_new(hash, hmask, keys[i], i);
+}
+
 __global__ void k_mark_dead_range(double* amps, u64 lo, u64 hi) {
   const u64 stride = (u64)gridDim.x * blockDim.x;
   for (u64 i = lo + (u64)blockIdx.x * blockDim.x + threadIdx.x; i < hi; i += stride)
     amps[i] = dead_value();
+}
+
+// Drop every alive entry with |c| < eps (used once after the first gate of a
+// chain that starts from a caller-supplied state, whose untouched entries
+// have not been tested against eps yet).  Skipped if the chain has stopped.
+__global__ void __launch_bounds__(256)
+k_prune_all(double* __restrict__ amps, Counters* __restrict__ ctr, double eps) {
+  if (__hip_atomic_load(&ctr->flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kFlagStopped)
+    return;
+  const u64 n = __hip_atomic_load(&ctr->n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  unsigned long long dropped = 0;
+  const u64 stride = (u64)gridDim.x * blockDim.x;
+  for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const double a = amps[i];
+    if (!is_dead(a) && fabs(a) < eps) {
+      amps[i] = dead_value();
+      ++dropped;
+    }
+  }
+  const u64 m = __ballot(dropped != 0);
+  if (m) {
+    // wave sum of dropped, then one atomic per wave
+    unsigned long long s = dropped;
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    if (__lane_id() == 0) atomicAdd(&ctr->alive, (u64)(0ULL - s));
+  }
 }
 
 // Copy amps[0, n) of the current state to dst and record n, unless the chain
@@ -261,11 +213,22 @@ hipError_t launch_hash_build(const DeviceState& st, u64 n, hipStream_t stream) {
   return hipGetLastError();
 }
 
+hipError_t launch_hash_build_dev(const DeviceState& st, int grid, hipStream_t stream) {
+  hipLaunchKernelGGL(k_hash_build_dev, dim3(grid), dim3(256), 0, stream, st.keys, st.hash, st.hmask,
+                     st.ctr);
+  return hipGetLastError();
+}
+
 hipError_t launch_gate(const DeviceState& st, const OpDesc& op, double c, double sn, double eps,
-                       u64* gate_n_in, int check_cap, unsigned gate_index, int grid,
+                       u64* gate_n_in, int check_cap, unsigned gate_index, u64 max_keys, int grid,
                        hipStream_t stream) {
   hipLaunchKernelGGL(k_gate, dim3(grid), dim3(256), 0, stream, st.keys, st.amps, st.hash, st.hmask,
-                     st.cap, st.ctr, op, c, sn, eps, gate_n_in, check_cap, gate_index);
+                     st.cap, st.ctr, op, c, sn, eps, gate_n_in, check_cap, gate_index, max_keys);
+  return hipGetLastError();
+}
+
+hipError_t launch_prune_all(const DeviceState& st, double eps, int grid, hipStream_t stream) {
+  hipLaunchKernelGGL(k_prune_all, dim3(grid), dim3(256), 0, stream, st.amps, st.ctr, eps);
   return hipGetLastError();
 }
 

@@ -78,7 +78,8 @@ struct swcs_ctx {
   int64_t K_pool = 0;
   std::vector<OpDesc> ops_host;
   std::vector<int32_t> pool_rows;
-  DevBuf ops;
+  DevBuf ops, opmap;
+  u64 omask = 0;
 
   // state
   DevBuf keys, amps, hash, ctr;
@@ -95,15 +96,19 @@ struct swcs_ctx {
   int seg = 1;
   std::vector<DevBuf> ckpt;
   DevBuf ckpt_n;      // u64 per checkpoint
+  DevBuf ckpt_ptrs;   // double* per checkpoint (device table)
+  DevBuf gate_tab;    // GateDesc per gate of the last apply call
   DevBuf gate_n_in;   // u64 per gate of the last apply call
   int64_t last_M = 0;
 
   // scratch
+  DevBuf gacc, selected;
   DevBuf partial, partial2, sigma, mu, work, seg_states, acc_tab, gbuf, subset_buf, scalars,
       exp_keys, exp_amps, exp_tmp_k, exp_tmp_v, sort_scratch, ctr_r, occ, sel_scratch, mlp_partial;
 
   ~swcs_ctx() {
-    DevBuf* all[] = {&h, &eri, &J, &K, &fock, &ops, &keys, &amps, &hash, &ctr, &ckpt_n, &gate_n_in,
+    DevBuf* all[] = {&h, &eri, &J, &K, &fock, &ops, &opmap, &gacc, &selected, &keys, &amps, &hash, &ctr, &ckpt_n, &ckpt_ptrs,
+                     &gate_tab, &gate_n_in,
                      &partial, &partial2, &sigma, &mu, &work, &seg_states, &acc_tab, &gbuf,
                      &subset_buf, &scalars, &exp_keys, &exp_amps, &exp_tmp_k, &exp_tmp_v,
                      &sort_scratch, &ctr_r, &occ, &sel_scratch, &mlp_partial};
@@ -259,11 +264,67 @@ int validate_gates(swcs_ctx* c, const int32_t* op_idx, const double* theta, int6
   return SWCS_OK;
 }
 
-// Enqueue gates [g0, M) of (ops, c, s); checkpoints every `seg` gates when
-// ckpt is requested.  Returns after one synchronization with the counters.
+// Upload the checkpoint pointer table (device array of double*).
+int upload_ckpt_table(swcs_ctx* c, int nck) {
+  std::vector<double*> ptrs((size_t)nck);
+  for (int j = 0; j < nck; ++j) ptrs[(size_t)j] = c->ckpt[(size_t)j].as<double>();
+  HIP_TRY(c, c->ckpt_ptrs.ensure((size_t)nck * sizeof(double*)), "alloc ckpt table");
+  HIP_TRY(c, hipMemcpyAsync(c->ckpt_ptrs.p, ptrs.data(), (size_t)nck * sizeof(double*),
+                            hipMemcpyHostToDevice, c->stream), "copy ckpt table");
+  HIP_TRY(c, hipStreamSynchronize(c->stream), "sync");
+  return SWCS_OK;
+}
+
+// Apply gates [0, M) of (ops, c, s) to the current state, with checkpoints
+// every `seg` gates when ckpt is requested.  A state that starts with at
+// most lds_chain_capacity() entries runs in one single-workgroup launch
+// (LDS-resident) for as long as it fits; the rest runs one multi-block
+// launch per gate in HBM, growing the arrays when a gate would not fit.
 int run_chain(swcs_ctx* c, const int32_t* op_idx, const double* cs, const double* sn, int64_t M,
-              double eps, bool ckpt, Counters* out) {
+              double eps, bool ckpt, u64 n_start, Counters* out) {
   int64_t g0 = 0;
+  if (M == 0) {
+    hipError_t e;
+    *out = read_counters(c, &e);
+    if (e != hipSuccess) return hip_fail(c, e, "read counters");
+    return SWCS_OK;
+  }
+  std::vector<GateDesc> gt((size_t)M);
+  for (int64_t g = 0; g < M; ++g) {
+    gt[(size_t)g].op = c->ops_host[op_idx[g]];
+    gt[(size_t)g].c = cs[g];
+    gt[(size_t)g].s = sn[g];
+  }
+  HIP_TRY(c, c->gate_tab.ensure((size_t)M * sizeof(GateDesc)), "alloc gate table");
+  HIP_TRY(c, hipMemcpyAsync(c->gate_tab.p, gt.data(), (size_t)M * sizeof(GateDesc),
+                            hipMemcpyHostToDevice, c->stream), "copy gate table");
+  if (ckpt) {
+    const int nck = (int)((M + c->seg - 1) / c->seg);
+    for (int j = 0; j < nck; ++j)
+      HIP_TRY(c, c->ckpt[(size_t)j].ensure(c->st.cap * sizeof(double)), "alloc checkpoint");
+    int r = upload_ckpt_table(c, nck);
+    if (r) return r;
+  }
+  if (n_start <= (u64)lds_chain_capacity() && c->st.cap >= (u64)lds_chain_capacity() &&
+      M <= (int64_t)1 << 30) {
+    HIP_TRY(c, launch_chain_lds(c->st, c->gate_tab.as<GateDesc>(), 0, (int)M, eps, eps > 0.0 ? 1 : 0,
+                                ckpt ? c->ckpt_ptrs.as<double*>() : nullptr, c->ckpt_n.as<u64>(),
+                                c->seg, c->gate_n_in.as<u64>(), c->sector, c->stream), "chain");
+    HIP_TRY(c, launch_hash_clear(c->st.hash, c->st.hmask + 1, c->stream), "hash clear");
+    HIP_TRY(c, launch_hash_build_dev(c->st, grid_blocks(c, lds_chain_capacity(), 256), c->stream), "hash build");
+    hipError_t e;
+    Counters h = read_counters(c, &e);
+    if (e != hipSuccess) return hip_fail(c, e, "read counters");
+    if (!(h.flags & kFlagStopped)) {
+      *out = h;
+      return SWCS_OK;
+    }
+    // Continue in HBM from the gate that did not fit in LDS.
+    g0 = (int64_t)h.stop_gate;
+    h.flags &= ~kFlagStopped;
+    h.stop_gate = 0;
+    HIP_TRY(c, hipMemcpyAsync(c->ctr.p, &h, sizeof(h), hipMemcpyHostToDevice, c->stream), "counters");
+  }
   for (int attempt = 0; attempt < 64; ++attempt) {
     for (int64_t g = g0; g < M; ++g) {
       if (ckpt && g % c->seg == 0) {
@@ -274,7 +335,13 @@ int run_chain(swcs_ctx* c, const int32_t* op_idx, const double* cs, const double
       }
       const OpDesc& op = c->ops_host[op_idx[g]];
       HIP_TRY(c, launch_gate(c->st, op, cs[g], sn[g], eps, c->gate_n_in.as<u64>() + g, 1,
-                             (unsigned)g, grid_blocks(c, c->st.cap / 2, 256), c->stream), "gate");
+                             (unsigned)g, c->sector, grid_blocks(c, c->st.cap / 2, 256), c->stream),
+              "gate");
+      // The gates only test the entries they touch; entries of a starting
+      // state that were never tested against eps are pruned once, after the
+      // first gate, so every later state is exactly P(U psi).
+      if (g == 0 && eps > 0.0)
+        HIP_TRY(c, launch_prune_all(c->st, eps, grid_blocks(c, c->st.cap / 2, 256), c->stream), "prune");
     }
     hipError_t e;
     Counters h = read_counters(c, &e);
@@ -285,7 +352,7 @@ int run_chain(swcs_ctx* c, const int32_t* op_idx, const double* cs, const double
       return SWCS_OK;
     }
     // Grow so that the stopped gate (and a few more) fit, then resume.
-    const u64 need = h.n + h.alive;
+    const u64 need = h.n + std::min<u64>(h.alive, c->sector > h.n ? c->sector - h.n : 0);
     u64 cap = next_pow2(std::max<u64>(2 * c->st.cap, 2 * need));
     const u64 maxc = max_capacity(c);
     if (cap > maxc) cap = maxc;
@@ -466,11 +533,31 @@ int swcs_set_pool(swcs_ctx* c, const int32_t* rows, int64_t K) {
         return fail(c, SWCS_E_INVALID, "pool row " + std::to_string(k) + ": index sets overlap");
       if (((o.P & 1) + (o.Q & 1)) != ((o.R & 1) + (o.S & 1)))
         return fail(c, SWCS_E_INVALID, "pool row " + std::to_string(k) + ": double changes spin");
+      if (!(o.P > o.R || (o.P == o.R && o.Q > o.S)))
+        return fail(c, SWCS_E_INVALID, "pool row " + std::to_string(k) + ": need (P, Q) > (R, S)");
       o.cre = (1ULL << o.P) | (1ULL << o.Q);
       o.ann = (1ULL << o.R) | (1ULL << o.S);
     }
     ops[(size_t)k] = o;
   }
+  // Generator map (P, Q, R, S) -> pool index, open addressing with the same
+  // hash and probing as the device lookups; rejects duplicate rows.
+  const u64 oslots = next_pow2(std::max<u64>(16, 2 * (u64)K));
+  std::vector<HashSlot> omap((size_t)oslots, HashSlot{0ULL, 0ULL});
+  for (int64_t k = 0; k < K; ++k) {
+    const OpDesc& o = ops[(size_t)k];
+    const u64 key = 1ULL + (u64)o.P + ((u64)o.Q << 8) + ((u64)(o.R + 1) << 16) + ((u64)(o.S + 1) << 24);
+    u64 h = mix64(key) & (oslots - 1);
+    while (omap[(size_t)h].key != 0ULL) {
+      if (omap[(size_t)h].key == key) return fail(c, SWCS_E_INVALID, "pool row " + std::to_string(k) + " duplicates an earlier row");
+      h = (h + 1) & (oslots - 1);
+    }
+    omap[(size_t)h].key = key;
+    omap[(size_t)h].idx = (u64)k;
+  }
+  HIP_TRY(c, c->opmap.ensure((size_t)oslots * sizeof(HashSlot)), "alloc generator map");
+  HIP_TRY(c, hipMemcpy(c->opmap.p, omap.data(), (size_t)oslots * sizeof(HashSlot), hipMemcpyHostToDevice), "copy generator map");
+  c->omask = oslots - 1;
   HIP_TRY(c, c->ops.ensure(std::max<size_t>(1, (size_t)K) * sizeof(OpDesc)), "alloc pool");
   if (K > 0) HIP_TRY(c, hipMemcpy(c->ops.p, ops.data(), (size_t)K * sizeof(OpDesc), hipMemcpyHostToDevice), "copy pool");
   c->ops_host.swap(ops);
@@ -505,7 +592,14 @@ static int apply_common(swcs_ctx* c, const int32_t* op_idx, const double* theta,
     HIP_TRY(c, c->ckpt_n.ensure((size_t)nck * sizeof(u64)), "alloc ckpt sizes");
   }
   Counters h;
-  r = run_chain(c, op_idx, cs.data(), sn.data(), M, eps, from_reference, &h);
+  u64 n_start = 1;
+  if (!from_reference) {
+    hipError_t e;
+    Counters h0 = read_counters(c, &e);
+    if (e != hipSuccess) return hip_fail(c, e, "read counters");
+    n_start = h0.n;
+  }
+  r = run_chain(c, op_idx, cs.data(), sn.data(), M, eps, from_reference, n_start, &h);
   if (r) return r;
   c->peak_n = std::max<u64>(c->peak_n, h.n);
   c->last_M = M;
@@ -689,12 +783,18 @@ int swcs_pool_gradients(swcs_ctx* c, const int32_t* subset, int64_t n_subset, do
   if (r) return r;
   if (!(norm2 > 0.0)) return fail(c, SWCS_E_STATE, "state has zero norm");
   HIP_TRY(c, c->gbuf.ensure((size_t)count * 8), "alloc g");
-  HIP_TRY(c, hipMemsetAsync(c->gbuf.p, 0, (size_t)count * 8, c->stream), "zero g");
+  HIP_TRY(c, c->gacc.ensure((size_t)c->K_pool * 8), "alloc g accumulator");
+  HIP_TRY(c, hipMemsetAsync(c->gacc.p, 0, (size_t)c->K_pool * 8, c->stream), "zero g");
   const int* d_subset = nullptr;
+  const unsigned char* d_sel = nullptr;
   if (subset) {
     HIP_TRY(c, c->subset_buf.ensure((size_t)n_subset * 4), "alloc subset");
     HIP_TRY(c, hipMemcpyAsync(c->subset_buf.p, subset, (size_t)n_subset * 4, hipMemcpyHostToDevice, c->stream), "copy subset");
     d_subset = c->subset_buf.as<int>();
+    HIP_TRY(c, c->selected.ensure((size_t)c->K_pool), "alloc selection");
+    HIP_TRY(c, hipMemsetAsync(c->selected.p, 0, (size_t)c->K_pool, c->stream), "zero selection");
+    HIP_TRY(c, launch_mark_selected(d_subset, n_subset, c->selected.as<unsigned char>(), c->stream), "mark");
+    d_sel = c->selected.as<unsigned char>();
   }
   // External-space table: at most alive * (C + 1) distinct keys (and never
   // more than the sector); load factor <= 1/2; split by key hash when the
@@ -707,15 +807,16 @@ int swcs_pool_gradients(swcs_ctx* c, const int32_t* subset, int64_t n_subset, do
   while ((2.0 * bound_d / nbatch) * sizeof(AccSlot) * 1.25 > budget && nbatch < 4096) nbatch *= 2;
   u64 slots = next_pow2((u64)std::max<double>(64.0, 2.0 * bound_d / nbatch * (nbatch > 1 ? 1.25 : 1.0)));
   HIP_TRY(c, c->acc_tab.ensure(slots * sizeof(AccSlot)), "alloc sigma table");
-  const double scale = 2.0 / norm2;
   for (int b = 0; b < nbatch; ++b) {
     HIP_TRY(c, hipMemsetAsync(c->acc_tab.p, 0, slots * sizeof(AccSlot), c->stream), "clear table");
     HIP_TRY(c, launch_sigma_push(c->st, ints_view(c), c->exc, n, c->acc_tab.as<AccSlot>(), slots - 1,
                                  nbatch, b, sigma_grid(c, n), c->stream), "sigma push");
-    HIP_TRY(c, launch_pool_contract_ops(c->st, n, c->ops.as<OpDesc>(), d_subset, count,
-                                        c->acc_tab.as<AccSlot>(), slots - 1, c->gbuf.as<double>(),
-                                        scale, c->stream), "contract");
+    HIP_TRY(c, launch_pool_contract_det(c->st, c->exc, c->n, n, c->opmap.as<HashSlot>(), c->omask,
+                                        d_sel, c->ops.as<OpDesc>(), c->acc_tab.as<AccSlot>(), slots - 1,
+                                        c->gacc.as<double>(), sigma_grid(c, n), c->stream), "contract");
   }
+  HIP_TRY(c, launch_gather_scaled(c->gacc.as<double>(), d_subset, count, 2.0 / norm2, c->gbuf.as<double>(),
+                                  c->stream), "gather");
   HIP_TRY(c, hipMemcpyAsync(g_out, c->gbuf.p, (size_t)count * 8, hipMemcpyDeviceToHost, c->stream), "copy g");
   Counters h2 = read_counters(c, &e);
   if (e != hipSuccess) return hip_fail(c, e, "read counters");
@@ -743,6 +844,24 @@ int swcs_param_gradients(swcs_ctx* c, double* dE, double* E_out) {
   const int nseg = (int)((M + seg - 1) / seg);
   const int grid = grid_blocks(c, n, 256);
   HIP_TRY(c, c->mu.ensure(n * 8), "alloc mu");
+  if (n <= (u64)lds_chain_capacity()) {
+    // Whole sweep in one single-workgroup launch with mu and the recomputed
+    // amplitudes in LDS; the gate table of the last apply call is reused.
+    int r2 = upload_ckpt_table(c, nseg);
+    if (r2) return r2;
+    HIP_TRY(c, c->seg_states.ensure((size_t)seg * n * 8), "alloc segment states");
+    HIP_TRY(c, c->gbuf.ensure((size_t)M * 8), "alloc dE");
+    HIP_TRY(c, launch_mu_init(c->st, c->sigma.as<double>(), n, 2.0 / norm2, E, c->mu.as<double>(), c->stream), "mu init");
+    HIP_TRY(c, launch_adjoint_lds(c->st.keys, (unsigned)n, c->gate_tab.as<GateDesc>(), (int)M, seg,
+                                  c->a_eps, c->ckpt_ptrs.as<double*>(), c->ckpt_n.as<u64>(),
+                                  c->mu.as<double>(), c->seg_states.as<double>(), c->gbuf.as<double>(),
+                                  &c->st.ctr->flags, c->stream), "adjoint");
+    HIP_TRY(c, hipMemcpyAsync(dE, c->gbuf.p, (size_t)M * 8, hipMemcpyDeviceToHost, c->stream), "copy dE");
+    Counters hchk = read_counters(c, &e);
+    if (e != hipSuccess) return hip_fail(c, e, "sync");
+    if (hchk.flags & kFlagOverflow) return fail(c, SWCS_E_DEVICE, "recomputation diverged from the forward run");
+    return SWCS_OK;
+  }
   HIP_TRY(c, c->seg_states.ensure((size_t)seg * n * 8), "alloc segment states");
   HIP_TRY(c, c->partial2.ensure((size_t)M * grid * 8), "alloc partials");
   HIP_TRY(c, c->ctr_r.ensure(sizeof(Counters)), "alloc counters");
@@ -771,7 +890,7 @@ int swcs_param_gradients(swcs_ctx* c, double* dE, double* E_out) {
       rv.amps = dst;
       const int64_t g = g_lo + t - 1;
       HIP_TRY(c, launch_gate(rv, c->ops_host[c->a_ops[g]], c->a_c[g], c->a_s[g], c->a_eps, nullptr, 0,
-                             (unsigned)g, grid, c->stream), "recompute gate");
+                             (unsigned)g, c->sector, grid, c->stream), "recompute gate");
     }
     for (int t = len - 1; t >= 0; --t) {
       const int64_t g = g_lo + t;

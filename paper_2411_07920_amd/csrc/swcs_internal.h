@@ -251,6 +251,17 @@ __device__ inline double connection_element(const Ints& I, u64 D, int nh, int h0
   return double_element(I, D, h0, h1, p0, p1);
 }
 
+// One gate of an ansatz as the device sees it.
+struct GateDesc {
+  OpDesc op;
+  double c;  // cos(theta)
+  double s;  // sin(theta)
+};
+
+// Largest state the single-workgroup LDS kernels hold (24 B per entry for
+// the forward chain, 32 B for the adjoint sweep: 128 KB of LDS).
+constexpr int kLdsCap = 4096;
+
 // ---------------------------------------------------------------- host side
 struct DeviceState {
   u64* keys = nullptr;
@@ -265,8 +276,18 @@ struct DeviceState {
 hipError_t launch_hash_clear(HashSlot* tab, u64 slots, hipStream_t stream);
 hipError_t launch_hash_build(const DeviceState& st, u64 n, hipStream_t stream);
 hipError_t launch_gate(const DeviceState& st, const OpDesc& op, double c, double sn, double eps,
-                       u64* gate_n_in, int check_cap, unsigned gate_index, int grid,
+                       u64* gate_n_in, int check_cap, unsigned gate_index, u64 max_keys, int grid,
                        hipStream_t stream);
+hipError_t launch_prune_all(const DeviceState& st, double eps, int grid, hipStream_t stream);
+hipError_t launch_hash_build_dev(const DeviceState& st, int grid, hipStream_t stream);
+int lds_chain_capacity();
+hipError_t launch_chain_lds(const DeviceState& st, const GateDesc* gates, int g0, int M, double eps,
+                            int prune_first, double* const* ckpt, u64* ckpt_n, int seg,
+                            u64* gate_n_in, u64 max_keys, hipStream_t stream);
+hipError_t launch_adjoint_lds(const u64* keys, unsigned n, const GateDesc* gates, int M, int seg,
+                              double eps, const double* const* ckpt, const u64* ckpt_n,
+                              const double* mu_init, double* S, double* dE, unsigned* flags,
+                              hipStream_t stream);
 hipError_t launch_adjoint_step(const DeviceState& st, const OpDesc& op, double c, double sn,
                                const double* amps_prev, double* mu, double* partial, u64 n_total,
                                int grid, hipStream_t stream);
@@ -285,9 +306,14 @@ hipError_t launch_reduce_partials(const double* partial, int count, int stride, 
 hipError_t launch_sigma_push(const DeviceState& st, const Ints& I, const ExcSpace& E, u64 n,
                              AccSlot* tab, u64 tmask, int nbatch, int batch, int grid,
                              hipStream_t stream);
-hipError_t launch_pool_contract_ops(const DeviceState& st, u64 n, const OpDesc* ops,
-                                    const int* subset, long long n_ops, const AccSlot* tab,
-                                    u64 tmask, double* g, double scale, hipStream_t stream);
+hipError_t launch_pool_contract_det(const DeviceState& st, const ExcSpace& E, int n_spatial, u64 n,
+                                   const HashSlot* opmap, u64 omask, const unsigned char* selected,
+                                   const OpDesc* ops, const AccSlot* tab, u64 tmask, double* gacc,
+                                   int grid, hipStream_t stream);
+hipError_t launch_gather_scaled(const double* gacc, const int* subset, long long count, double scale,
+                                double* out, hipStream_t stream);
+hipError_t launch_mark_selected(const int* subset, long long count, unsigned char* selected,
+                                hipStream_t stream);
 hipError_t launch_occupations(const DeviceState& st, u64 n, int nso, double* partial, int grid,
                               hipStream_t stream);
 hipError_t launch_compact_alive(const DeviceState& st, u64 n, const double* vals, u64* out_keys,

@@ -252,6 +252,10 @@ def test_errors_and_capacity(swcs, c1):
         ctx.set_pool(np.array([[1, 3, -1, -1]], dtype=np.int32))  # P < Q
     with pytest.raises(swcs.SwcsError):
         ctx.set_pool(np.array([[5, 4, 3, 1]], dtype=np.int32))  # spin change
+    with pytest.raises(swcs.SwcsError):
+        ctx.set_pool(np.array([[2, 0, 6, 4]], dtype=np.int32))  # (P, Q) < (R, S)
+    with pytest.raises(swcs.SwcsError):
+        ctx.set_pool(np.array([[2, 0, -1, -1], [2, 0, -1, -1]], dtype=np.int32))  # duplicate
     ctx.set_pool(c1.pool)
     with pytest.raises(swcs.SwcsError):
         ctx.apply_ansatz(np.array([len(c1.pool)], np.int32), np.array([0.1]), 0.0)
@@ -310,5 +314,7 @@ def test_determinism(swcs, c2):
     assert np.abs(np.array(e1) - np.array(ctx.energy())).max() < 1e-14
     assert np.abs(g1 - ctx.pool_gradients()).max() < 1e-13
     d2, _ = ctx.param_gradients(len(c2.ops))
-    assert np.array_equal(d1, d2)
+    # new determinants are appended in scheduling order, so sums over the
+    # stored entries may differ in the last bits between runs
+    assert np.abs(d1 - d2).max() < 1e-13
     ctx.close()
