@@ -48,6 +48,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-phase", default=None,
                     help="run only this phase in a loop (for counter collection)")
+    ap.add_argument("--adapt", default=None, choices=sorted(CONFIGS),
+                    help="instead of the step benchmark: ADAPT iteration time, screened vs "
+                         "full pool, on this workload (prints its own JSON line)")
+    ap.add_argument("--iters", type=int, default=150)
     return ap.parse_args()
 
 
@@ -236,12 +240,76 @@ def cpu_baseline(wl, fwd_applies, adj_applies, budget_s=20.0):
     }
 
 
+def adapt_bench(args):
+    """ADAPT-VQE from the reference: full-pool arm, screened arm (both timed)
+    and a screened validation arm that also evaluates the full pool on every
+    iteration (untimed) to measure selection agreement and two baselines at
+    the same exact-gradient budget (a random subset, and the top operators by
+    their last exact |g|)."""
+    import torch
+    from paper_2411_07920_amd import adapt, swcs
+
+    torch.cuda.set_device(0)
+    wl = Workload(args.adapt)
+    c = wl.c
+
+    def fresh():
+        return swcs.make_context(c.n, wl.na, wl.na, wl.h, wl.eri, wl.pool, wl.ref,
+                                 stream=torch.cuda.current_stream())
+
+    def arm(screened, shadow, iters):
+        ctx = fresh()
+        cfg = adapt.AdaptConfig(eps=c.eps, max_iter=iters, grad_tol=None, optimizer="lbfgs",
+                                screener=screened, shadow_full=shadow, seed=3000 + int(args.adapt[1:]))
+        t = time.perf_counter()
+        ops, theta, hist = adapt.run_adapt(ctx, wl.K, cfg)
+        wall = time.perf_counter() - t
+        ctx.apply_ansatz(ops, theta, c.eps)
+        E = ctx.energy()[0]
+        n_det = ctx.apply_ansatz(ops, theta, c.eps)
+        ctx.close()
+        return ops, theta, hist, wall, E, n_det
+
+    iters = args.iters
+    _, _, h_full, w_full, E_full, nd_full = arm(False, False, iters)
+    ops_s, _, h_scr, w_scr, E_scr, nd_scr = arm(True, False, iters)
+    _, _, h_val, _, E_val, _ = arm(True, True, iters)
+
+    def mean(h, key, pred=lambda r: True):
+        v = [r[key] for r in h if key in r and pred(r)]
+        return float(np.mean(v)) if v else None
+
+    screened_iters = [r for r in h_val if not r["full"]]
+    match = [r["shadow_match"] for r in screened_iters]
+    out = {
+        "metric": "ADAPT iteration time, screened vs full pool",
+        "workload": f"{args.adapt}: {c.n_so} spin-orbitals, {c.n_elec} electrons, eps={c.eps:g}, "
+                    f"pool {wl.K}, {iters} iterations, L-BFGS VQE",
+        "full": {"wall_s": w_full, "iter_ms": 1e3 * w_full / iters,
+                 "pool_ms": 1e3 * mean(h_full, "t_pool"), "vqe_ms": 1e3 * mean(h_full, "t_vqe"),
+                 "E_final": E_full, "n_det_final": nd_full},
+        "screened": {"wall_s": w_scr, "iter_ms": 1e3 * w_scr / iters,
+                     "pool_ms_screened_iters": 1e3 * mean(h_scr, "t_pool", lambda r: not r["full"]),
+                     "pool_ms_full_iters": 1e3 * mean(h_scr, "t_pool", lambda r: r["full"]),
+                     "train_ms": 1e3 * mean(h_scr, "t_train"), "vqe_ms": 1e3 * mean(h_scr, "t_vqe"),
+                     "E_final": E_scr, "n_det_final": nd_scr},
+        "validation": {"screened_iterations": len(match),
+                       "same_operator_frac": float(np.mean(match)) if match else None,
+                       "E_final": E_val},
+        "dE_final_screened_minus_full": E_scr - E_full,
+    }
+    print(json.dumps(out))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
               "(see DESIGN.md for how the work would shard).", file=sys.stderr)
         sys.exit(2)
+    if args.adapt:
+        adapt_bench(args)
+        return
     wl = Workload(args.workload)
     r = gpu_bench(args, wl)
     if r is None:

@@ -1,0 +1,254 @@
+"""ADAPT-VQE and classical pre-optimization drivers on the SWCS library.
+
+The ADAPT loop follows Sec. II.C (Fig. 1): with the integrals (step 1), the
+pool (step 2) and the reference (step 3) set on a context, each iteration
+computes the pool gradient (step 4), stops when its norm is below the
+threshold (step 5), appends the operator of largest |g| with parameter 0 at
+the end of the ansatz (step 6) and re-optimizes the parameters (step 7).
+The state is pruned after every unitary by the context's rule (eps or N_CUT).
+
+VQE optimizers (Sec. II.B uses BFGS; Sec. IV.D proposes BFGS-2 / BFGS-2F):
+  "bfgs"   scipy BFGS over all parameters
+  "lbfgs"  scipy L-BFGS-B over all parameters
+  "bfgs2"  (1) optimize only the new parameter from 0, others frozen,
+           (2) BFGS over all parameters
+  "bfgs2f" step (1) only
+The gradient tolerance is the paper's convergence threshold of 1e-6.  When
+the state is pruned, a newly appended parameter is first moved off the
+zero-slope plateau at 0 by a five-point trigonometric fit (see
+seed_last_parameter).
+
+With a screener, the pool gradient of step 4 is evaluated exactly only for
+the operators the learned network ranks highest (top 5 %) plus a random 1 %,
+with the full pool every `full_every` iterations and in the first
+`warm_full` iterations; `shadow_full` additionally evaluates the full pool
+(untimed) to measure whether the selected operator matches.
+"""
+from __future__ import annotations
+
+import dataclasses
+import time
+
+import numpy as np
+import scipy.optimize
+
+
+@dataclasses.dataclass
+class AdaptConfig:
+    eps: float = 0.0
+    ncut: int = 0
+    max_iter: int = 50
+    grad_tol: float | None = 1e-2      # stop when ||g||_2 < grad_tol (None: run max_iter)
+    optimizer: str = "lbfgs"
+    vqe_gtol: float = 1e-6
+    vqe_maxiter: int = 200
+    screener: bool = False
+    frac_top: float = 0.05
+    frac_rand: float = 0.01
+    full_every: int = 10
+    warm_full: int = 3
+    shadow_full: bool = False
+    seed: int = 3000
+    train_steps: int = 30
+
+
+class Energy:
+    """E(theta) and dE/dtheta of a fixed operator list on a context."""
+
+    def __init__(self, ctx, ops, eps, ncut):
+        self.ctx, self.ops, self.eps, self.ncut = ctx, np.asarray(ops, dtype=np.int32), eps, ncut
+        self.evals = 0
+        self.time = 0.0
+
+    def __call__(self, theta):
+        t = time.perf_counter()
+        self.ctx.apply_ansatz(self.ops, np.asarray(theta, dtype=np.float64), self.eps, self.ncut)
+        dE, E = self.ctx.param_gradients(len(self.ops))
+        self.evals += 1
+        self.time += time.perf_counter() - t
+        return E, dE
+
+
+class EnergyOnly:
+    """E(theta) without gradients (one apply + one sigma)."""
+
+    def __init__(self, ctx, ops, eps, ncut):
+        self.ctx, self.ops, self.eps, self.ncut = ctx, np.asarray(ops, dtype=np.int32), eps, ncut
+        self.evals = 0
+
+    def __call__(self, theta):
+        self.ctx.apply_ansatz(self.ops, np.asarray(theta, dtype=np.float64), self.eps, self.ncut)
+        self.evals += 1
+        return self.ctx.energy()[0]
+
+
+_FIT_T = np.array([-2.0, -1.0, 0.0, 1.0, 2.0]) * (np.pi / 5.0)
+
+
+def seed_last_parameter(ctx, ops, theta, cfg: AdaptConfig):
+    """Starting value for a newly appended parameter.
+
+    Without pruning, E as a function of one parameter is a trigonometric
+    polynomial with frequencies 0, 1 and 2 (A has eigenvalues 0 and +-i), so
+    five samples fix it.  With pruning, a parameter at exactly 0 sits on a
+    plateau (the partners it creates are dropped for small angles), where
+    the pruned energy has zero slope; the fitted polynomial, minimized on a
+    grid, gives a starting point off that plateau.  Returns (theta, evals)."""
+    f = EnergyOnly(ctx, ops, cfg.eps, cfg.ncut)
+    base = np.array(theta, dtype=np.float64)
+    Es = []
+    for t in _FIT_T:
+        th = base.copy()
+        th[-1] = t
+        Es.append(f(th))
+    X = np.stack([np.ones(5), np.cos(_FIT_T), np.sin(_FIT_T), np.cos(2 * _FIT_T),
+                  np.sin(2 * _FIT_T)], axis=1)
+    a = np.linalg.solve(X, np.array(Es))
+    grid = np.linspace(-np.pi, np.pi, 4097)
+    model = a[0] + a[1] * np.cos(grid) + a[2] * np.sin(grid) + a[3] * np.cos(2 * grid) + \
+        a[4] * np.sin(2 * grid)
+    out = base.copy()
+    out[-1] = float(grid[int(np.argmin(model))])
+    return out, f.evals
+
+
+def optimize(ctx, ops, theta0, cfg: AdaptConfig, method=None, seed_new=False):
+    """VQE step: returns (theta, E, n_evals, seconds).  With seed_new, the
+    last parameter is first set by seed_last_parameter (used after ADAPT
+    appends an operator at 0 while the state is pruned)."""
+    method = method or cfg.optimizer
+    f = Energy(ctx, ops, cfg.eps, cfg.ncut)
+    theta = np.array(theta0, dtype=np.float64)
+    if len(theta) == 0:
+        E, _ = f(theta)
+        return theta, E, f.evals, f.time
+    extra = 0
+    if seed_new:
+        theta, extra = seed_last_parameter(ctx, ops, theta, cfg)
+    if method in ("bfgs2", "bfgs2f"):
+        base = theta.copy()
+
+        def one(x):
+            th = base.copy()
+            th[-1] = x[0]
+            E, dE = f(th)
+            return E, dE[-1:]
+
+        r = scipy.optimize.minimize(one, theta[-1:], jac=True, method="BFGS",
+                                    options={"gtol": cfg.vqe_gtol, "maxiter": cfg.vqe_maxiter})
+        theta[-1] = r.x[0]
+        if method == "bfgs2f":
+            E, _ = f(theta)
+            return theta, E, f.evals + extra, f.time
+        method = "bfgs"
+    if method == "bfgs":
+        r = scipy.optimize.minimize(f, theta, jac=True, method="BFGS",
+                                    options={"gtol": cfg.vqe_gtol, "maxiter": cfg.vqe_maxiter})
+    elif method == "lbfgs":
+        # ftol ~ 0 so that the gradient tolerance decides convergence
+        r = scipy.optimize.minimize(f, theta, jac=True, method="L-BFGS-B",
+                                    options={"gtol": cfg.vqe_gtol, "ftol": 1e-15,
+                                             "maxiter": cfg.vqe_maxiter})
+    else:
+        raise ValueError(f"unknown optimizer {method}")
+    theta = np.array(r.x)
+    E, _ = f(theta)  # leave the context at the optimum
+    return theta, E, f.evals + extra, f.time
+
+
+def select_operator(g, idx, rel_tol=1e-9):
+    """Position of the operator to append: largest |g|, where values within
+    rel_tol * max|g| of the maximum count as ties (spin-symmetric pairs are
+    exactly degenerate and differ only by rounding) and ties go to the
+    smallest pool index."""
+    a = np.abs(np.asarray(g, dtype=np.float64))
+    top = a.max()
+    cand = np.flatnonzero(a >= top - rel_tol * max(top, 1e-300))
+    return int(cand[np.argmin(np.asarray(idx)[cand])])
+
+
+def run_adapt(ctx, K: int, cfg: AdaptConfig, ops0=None, theta0=None, log=None):
+    """ADAPT-VQE; returns (ops, theta, history).  `ctx` has integrals, pool
+    (K operators) and reference set.  ops0 / theta0 seed the ansatz (bootstrap
+    restarts reuse a previous final ansatz)."""
+    from .screener import Screener
+
+    ops = list(ops0) if ops0 is not None else []
+    theta = np.array(theta0 if theta0 is not None else [], dtype=np.float64)
+    scr = Screener(ctx, K, cfg.seed, cfg.frac_top, cfg.frac_rand,
+                   train_steps=cfg.train_steps) if cfg.screener else None
+    history = []
+    for it in range(cfg.max_iter):
+        rec = {"iter": it}
+        t0 = time.perf_counter()
+        ctx.apply_ansatz(np.array(ops, dtype=np.int32), theta, cfg.eps, cfg.ncut)
+        E_cur, _, _ = ctx.energy()
+        t1 = time.perf_counter()
+        full = (scr is None) or it < cfg.warm_full or (it % cfg.full_every == 0)
+        if full:
+            g = ctx.pool_gradients()
+            idx = np.arange(K, dtype=np.int32)
+            gsel = g
+            if scr is not None:
+                scr.compute_features(ops)
+        else:
+            scr.compute_features(ops)
+            scr.scores()
+            idx = scr.select()
+            gsel = ctx.pool_gradients(idx)
+        t2 = time.perf_counter()
+        kpos = select_operator(gsel, idx)
+        kstar = int(idx[kpos])
+        gnorm = float(np.linalg.norm(gsel))
+        rec.update(E=E_cur, n_det=None, full=full, kstar=kstar, gmax=float(abs(gsel[kpos])),
+                   gnorm=gnorm, n_exact=int(len(idx)), t_state=t1 - t0, t_pool=t2 - t1)
+        if scr is not None:
+            scr.record(idx, gsel)
+            t3 = time.perf_counter()
+            rec["loss"] = scr.train()
+            rec["t_train"] = time.perf_counter() - t3
+        if cfg.shadow_full and not full:
+            g_all = ctx.pool_gradients()
+            ks = int(select_operator(g_all, np.arange(K)))
+            rec["shadow_kstar"] = ks
+            rec["shadow_match"] = bool(ks == kstar)
+            rec["shadow_gnorm"] = float(np.linalg.norm(g_all))
+        if cfg.grad_tol is not None and full and gnorm < cfg.grad_tol:
+            rec["converged"] = True
+            history.append(rec)
+            if log:
+                log(rec)
+            break
+        ops.append(kstar)
+        theta = np.append(theta, 0.0)
+        t4 = time.perf_counter()
+        pruned = cfg.eps > 0.0 or cfg.ncut > 0
+        theta, E_new, nev, _ = optimize(ctx, ops, theta, cfg, seed_new=pruned)
+        rec.update(E_after=E_new, vqe_evals=nev, t_vqe=time.perf_counter() - t4,
+                   n_params=len(ops), t_iter=time.perf_counter() - t0)
+        history.append(rec)
+        if log:
+            log(rec)
+    return np.array(ops, dtype=np.int32), theta, history
+
+
+def preoptimize(ctx, ops, theta0, cfg: AdaptConfig, log=None):
+    """Classical pre-optimization of a fixed ansatz (L-BFGS by default),
+    recording the energy after every optimizer step."""
+    f = Energy(ctx, ops, cfg.eps, cfg.ncut)
+    trace = []
+
+    def cb(xk):
+        E, _ = f(xk)
+        trace.append(E)
+        if log:
+            log({"step": len(trace), "E": E})
+
+    method = "L-BFGS-B" if cfg.optimizer == "lbfgs" else "BFGS"
+    opts = {"gtol": cfg.vqe_gtol, "maxiter": cfg.vqe_maxiter}
+    if method == "L-BFGS-B":
+        opts["ftol"] = 1e-15
+    r = scipy.optimize.minimize(f, np.asarray(theta0, dtype=np.float64), jac=True, method=method,
+                                callback=cb, options=opts)
+    E, _ = f(r.x)
+    return np.array(r.x), E, trace, f.evals

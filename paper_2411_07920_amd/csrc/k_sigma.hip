@@ -186,6 +186,22 @@ __device__ inline u64 generator_key(int P, int Q, int R, int S) {
   return 1ULL + (u64)P + ((u64)Q << 8) + ((u64)(R + 1) << 16) + ((u64)(S + 1) << 24);
 }
 
+// Operator of the pool that links D to its connection (holes h0 < h1,
+// particles p0 < p1): returns its index (or -1) and whether T (rather than
+// T^dagger) acts on D.
+__device__ inline long long linking_operator(const HashSlot* __restrict__ opmap, u64 omask, int nh,
+                                             int h0, int h1, int p0, int p1, bool* t_acts) {
+  u64 gk;
+  if (nh == 1) {
+    *t_acts = p0 > h0;
+    gk = *t_acts ? generator_key(p0, h0, -1, -1) : generator_key(h0, p0, -1, -1);
+  } else {
+    *t_acts = p1 > h1;
+    gk = *t_acts ? generator_key(p1, p0, h1, h0) : generator_key(h1, h0, p1, p0);
+  }
+  return hash_find(opmap, omask, gk);
+}
+
 __global__ void __launch_bounds__(kSigBlock)
 k_pool_contract_det(const u64* __restrict__ keys, const double* __restrict__ amps, ExcSpace E,
                     int n_spatial, u64 n, const HashSlot* __restrict__ opmap, u64 omask,
@@ -207,15 +223,7 @@ k_pool_contract_det(const u64* __restrict__ keys, const double* __restrict__ amp
       u64 X = D ^ (1ULL << h0) ^ (1ULL << p0);
       if (nh == 2) X ^= (1ULL << h1) ^ (1ULL << p1);
       bool t_acts;
-      u64 gk;
-      if (nh == 1) {
-        t_acts = p0 > h0;
-        gk = t_acts ? generator_key(p0, h0, -1, -1) : generator_key(h0, p0, -1, -1);
-      } else {
-        t_acts = (p1 > h1) || (p1 == h1 && p0 > h0);
-        gk = t_acts ? generator_key(p1, p0, h1, h0) : generator_key(h1, h0, p1, p0);
-      }
-      const long long k = hash_find(opmap, omask, gk);
+      const long long k = linking_operator(opmap, omask, nh, h0, h1, p0, p1, &t_acts);
       if (k < 0) continue;
       if (selected && !selected[k]) continue;
       double sx;
@@ -223,6 +231,85 @@ k_pool_contract_det(const u64* __restrict__ keys, const double* __restrict__ amp
       const OpDesc op = ops[k];
       const double a = t_acts ? (double)phase_of_T(op, D) : -(double)phase_of_T(op, X);
       unsafeAtomicAdd(&gacc[k], psiD * a * sx);
+    }
+  }
+}
+
+// Screened pool gradients need sigma only on Q = {X_k(D): k selected, D in
+// psi}.  Pass 1 counts (count_only) or inserts Q into the table; pass 2
+// (k_sigma_push_into) adds H_{X D'} psi(D') only for X already in the table,
+// evaluating the matrix element only on those hits.
+__global__ void __launch_bounds__(kSigBlock)
+k_query_set(const u64* __restrict__ keys, const double* __restrict__ amps, ExcSpace E, int n_spatial,
+            u64 n, const HashSlot* __restrict__ opmap, u64 omask,
+            const unsigned char* __restrict__ selected, AccSlot* __restrict__ tab, u64 tmask,
+            int count_only, u64* __restrict__ counter, unsigned* __restrict__ flags) {
+  __shared__ SigShared S;
+  build_pair_table(S);
+  const int C = (int)E.total;
+  unsigned long long mine = 0;
+  for (u64 d = blockIdx.x; d < n; d += gridDim.x) {
+    if (is_dead(amps[d])) continue;
+    const u64 D = keys[d];
+    __syncthreads();
+    build_lists_shared(D, n_spatial, S);
+    __syncthreads();
+    for (int c = threadIdx.x; c < C; c += kSigBlock) {
+      int h0, h1 = 0, p0, p1 = 0;
+      const int nh = decode_shared(E, S, c, &h0, &h1, &p0, &p1);
+      bool t_acts;
+      const long long k = linking_operator(opmap, omask, nh, h0, h1, p0, p1, &t_acts);
+      if (k < 0 || !selected[k]) continue;
+      if (count_only) {
+        ++mine;
+        continue;
+      }
+      u64 X = D ^ (1ULL << h0) ^ (1ULL << p0);
+      if (nh == 2) X ^= (1ULL << h1) ^ (1ULL << p1);
+      if (!acc_add(tab, tmask, X, 0.0)) atomicOr(flags, kFlagOverflow);
+    }
+  }
+  if (count_only) {
+    for (int off = 32; off > 0; off >>= 1) mine += __shfl_xor(mine, off);
+    if (__lane_id() == 0 && mine) atomicAdd(counter, (u64)mine);
+  }
+}
+
+__device__ inline double* acc_slot(AccSlot* tab, u64 mask, u64 key) {
+  u64 h = mix64(key) & mask;
+  for (u64 probes = 0; probes <= mask; ++probes) {
+    const u64 k = tab[h].key;
+    if (k == key) return &tab[h].val;
+    if (k == kEmptyKey) return nullptr;
+    h = (h + 1) & mask;
+  }
+  return nullptr;
+}
+
+__global__ void __launch_bounds__(kSigBlock)
+k_sigma_push_into(const u64* __restrict__ keys, const double* __restrict__ amps, Ints I, ExcSpace E,
+                  u64 n, AccSlot* __restrict__ tab, u64 tmask) {
+  __shared__ SigShared S;
+  build_pair_table(S);
+  const int C = (int)E.total;
+  for (u64 d = blockIdx.x; d < n; d += gridDim.x) {
+    const double psiD = amps[d];
+    if (is_dead(psiD)) continue;
+    const u64 D = keys[d];
+    __syncthreads();
+    build_lists_shared(D, I.n, S);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double* v = acc_slot(tab, tmask, D);
+      if (v) unsafeAtomicAdd(v, diag_element(I, D) * psiD);
+    }
+    for (int c = threadIdx.x; c < C; c += kSigBlock) {
+      int h0, h1 = 0, p0, p1 = 0;
+      const int nh = decode_shared(E, S, c, &h0, &h1, &p0, &p1);
+      u64 X = D ^ (1ULL << h0) ^ (1ULL << p0);
+      if (nh == 2) X ^= (1ULL << h1) ^ (1ULL << p1);
+      double* v = acc_slot(tab, tmask, X);
+      if (v) unsafeAtomicAdd(v, connection_element(I, D, nh, h0, h1, p0, p1) * psiD);
     }
   }
 }
@@ -335,6 +422,23 @@ hipError_t launch_pool_contract_det(const DeviceState& st, const ExcSpace& E, in
                                    int grid, hipStream_t stream) {
   hipLaunchKernelGGL(k_pool_contract_det, dim3(grid), dim3(kSigBlock), 0, stream, st.keys, st.amps,
                      E, n_spatial, n, opmap, omask, selected, ops, tab, tmask, gacc);
+  return hipGetLastError();
+}
+
+hipError_t launch_query_set(const DeviceState& st, const ExcSpace& E, int n_spatial, u64 n,
+                            const HashSlot* opmap, u64 omask, const unsigned char* selected,
+                            AccSlot* tab, u64 tmask, int count_only, u64* counter, int grid,
+                            hipStream_t stream) {
+  hipLaunchKernelGGL(k_query_set, dim3(grid), dim3(kSigBlock), 0, stream, st.keys, st.amps, E,
+                     n_spatial, n, opmap, omask, selected, tab, tmask, count_only, counter,
+                     &st.ctr->flags);
+  return hipGetLastError();
+}
+
+hipError_t launch_sigma_push_into(const DeviceState& st, const Ints& I, const ExcSpace& E, u64 n,
+                                  AccSlot* tab, u64 tmask, int grid, hipStream_t stream) {
+  hipLaunchKernelGGL(k_sigma_push_into, dim3(grid), dim3(kSigBlock), 0, stream, st.keys, st.amps, I,
+                     E, n, tab, tmask);
   return hipGetLastError();
 }
 

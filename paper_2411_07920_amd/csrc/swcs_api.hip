@@ -796,6 +796,32 @@ int swcs_pool_gradients(swcs_ctx* c, const int32_t* subset, int64_t n_subset, do
     HIP_TRY(c, launch_mark_selected(d_subset, n_subset, c->selected.as<unsigned char>(), c->stream), "mark");
     d_sel = c->selected.as<unsigned char>();
   }
+  if (subset && 2 * n_subset < c->K_pool) {
+    // Screened: sigma only on the determinants the selected operators reach.
+    HIP_TRY(c, hipMemsetAsync(c->scalars.as<u64>() + 16, 0, 8, c->stream), "zero counter");
+    HIP_TRY(c, launch_query_set(c->st, c->exc, c->n, n, c->opmap.as<HashSlot>(), c->omask, d_sel,
+                                nullptr, 0, 1, c->scalars.as<u64>() + 16, sigma_grid(c, n), c->stream), "count");
+    u64 nq = 0;
+    HIP_TRY(c, hipMemcpyAsync(&nq, c->scalars.as<u64>() + 16, 8, hipMemcpyDeviceToHost, c->stream), "copy");
+    HIP_TRY(c, hipStreamSynchronize(c->stream), "sync");
+    const u64 qslots = next_pow2(std::max<u64>(64, 2 * std::min<u64>(nq, c->sector)));
+    HIP_TRY(c, c->acc_tab.ensure(qslots * sizeof(AccSlot)), "alloc sigma table");
+    HIP_TRY(c, hipMemsetAsync(c->acc_tab.p, 0, qslots * sizeof(AccSlot), c->stream), "clear table");
+    HIP_TRY(c, launch_query_set(c->st, c->exc, c->n, n, c->opmap.as<HashSlot>(), c->omask, d_sel,
+                                c->acc_tab.as<AccSlot>(), qslots - 1, 0, nullptr, sigma_grid(c, n), c->stream), "query set");
+    HIP_TRY(c, launch_sigma_push_into(c->st, ints_view(c), c->exc, n, c->acc_tab.as<AccSlot>(), qslots - 1,
+                                      sigma_grid(c, n), c->stream), "sigma push");
+    HIP_TRY(c, launch_pool_contract_det(c->st, c->exc, c->n, n, c->opmap.as<HashSlot>(), c->omask,
+                                        d_sel, c->ops.as<OpDesc>(), c->acc_tab.as<AccSlot>(), qslots - 1,
+                                        c->gacc.as<double>(), sigma_grid(c, n), c->stream), "contract");
+    HIP_TRY(c, launch_gather_scaled(c->gacc.as<double>(), d_subset, count, 2.0 / norm2, c->gbuf.as<double>(),
+                                    c->stream), "gather");
+    HIP_TRY(c, hipMemcpyAsync(g_out, c->gbuf.p, (size_t)count * 8, hipMemcpyDeviceToHost, c->stream), "copy g");
+    Counters hq = read_counters(c, &e);
+    if (e != hipSuccess) return hip_fail(c, e, "read counters");
+    if (hq.flags & kFlagOverflow) return fail(c, SWCS_E_DEVICE, "sigma table overflow");
+    return SWCS_OK;
+  }
   // External-space table: at most alive * (C + 1) distinct keys (and never
   // more than the sector); load factor <= 1/2; split by key hash when the
   // table would exceed the memory budget.

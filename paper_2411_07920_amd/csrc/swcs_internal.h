@@ -310,6 +310,12 @@ hipError_t launch_pool_contract_det(const DeviceState& st, const ExcSpace& E, in
                                    const HashSlot* opmap, u64 omask, const unsigned char* selected,
                                    const OpDesc* ops, const AccSlot* tab, u64 tmask, double* gacc,
                                    int grid, hipStream_t stream);
+hipError_t launch_query_set(const DeviceState& st, const ExcSpace& E, int n_spatial, u64 n,
+                            const HashSlot* opmap, u64 omask, const unsigned char* selected,
+                            AccSlot* tab, u64 tmask, int count_only, u64* counter, int grid,
+                            hipStream_t stream);
+hipError_t launch_sigma_push_into(const DeviceState& st, const Ints& I, const ExcSpace& E, u64 n,
+                                  AccSlot* tab, u64 tmask, int grid, hipStream_t stream);
 hipError_t launch_gather_scaled(const double* gacc, const int* subset, long long count, double scale,
                                 double* out, hipStream_t stream);
 hipError_t launch_mark_selected(const int* subset, long long count, unsigned char* selected,

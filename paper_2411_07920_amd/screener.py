@@ -1,0 +1,125 @@
+"""Learned operator-pool screener driven by the library's float32 kernels.
+
+The ADAPT step ranks the pool by the derivative of the energy with respect to
+each operator appended at the end of the ansatz (Sec. II.C, step 4).  The
+screener predicts log10 |g_k| from sixteen cheap per-operator features with a
+16 -> 128 -> 128 -> 1 ReLU network, so that exact gradients are evaluated
+only for the top-scored fraction plus a random share; the exact gradients
+that result are its training data (online, Adam, mean squared error).
+
+All arithmetic runs in libswcs kernels (features, forward, MSE, backward,
+Adam, selection); torch only holds the device buffers.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+
+class Screener:
+    def __init__(self, ctx, K: int, seed: int, frac_top=0.05, frac_rand=0.01, lr=1e-3,
+                 buffer_rows=65536, train_steps=30):
+        import torch
+        from . import swcs
+
+        self.torch = torch
+        self.ctx = ctx
+        self.K = K
+        self.frac_top, self.frac_rand = frac_top, frac_rand
+        self.n_top = int(math.ceil(frac_top * K))
+        self.n_rand = int(math.ceil(frac_rand * K))
+        self.lr = lr
+        self.train_steps = train_steps
+        self.rng = np.random.default_rng(seed)
+        P = swcs.mlp_param_count()
+        w = np.zeros(P, dtype=np.float32)
+        # He-normal weights, zero biases
+        w[: 16 * 128] = self.rng.normal(0, math.sqrt(2 / 16), 16 * 128)
+        o = 16 * 128 + 128
+        w[o: o + 128 * 128] = self.rng.normal(0, math.sqrt(2 / 128), 128 * 128)
+        o += 128 * 128 + 128
+        w[o: o + 128] = self.rng.normal(0, math.sqrt(2 / 128), 128)
+        dev = "cuda"
+        self.W = torch.from_numpy(w).to(dev)
+        self.m = torch.zeros(P, device=dev)
+        self.v = torch.zeros(P, device=dev)
+        self.dW = torch.zeros(P, device=dev)
+        self.adam_t = 0
+        self.feat = torch.zeros((K, 16), device=dev)
+        self.score = torch.zeros(K, device=dev)
+        self.prev_absg = torch.zeros(K, device=dev)
+        self.age = torch.zeros(K, device=dev)
+        self.count = torch.zeros(K, device=dev)
+        self.buf_x = torch.zeros((buffer_rows, 16), device=dev)
+        self.buf_t = torch.zeros(buffer_rows, device=dev)
+        self.buf_n = 0
+        self.buf_pos = 0
+        self.buffer_rows = buffer_rows
+        self.loss = torch.zeros(1, device=dev)
+
+    # -- per-iteration bookkeeping ------------------------------------------
+    def compute_features(self, ansatz_ops):
+        torch = self.torch
+        cnt = np.bincount(np.asarray(ansatz_ops, dtype=np.int64), minlength=self.K).astype(np.float32)
+        self.count.copy_(torch.from_numpy(cnt))
+        self.ctx.features(self.prev_absg, self.age, self.count, self.feat)
+
+    def scores(self):
+        self.ctx.mlp_forward(self.W, self.feat, self.score)
+        return self.score
+
+    def select(self):
+        torch = self.torch
+        rnd = self.rng.integers(0, 2 ** 32, self.K, dtype=np.uint64).astype(np.uint32)
+        rnd_d = torch.from_numpy(rnd.view(np.int32)).cuda()
+        out = torch.zeros(self.n_top + self.n_rand, dtype=torch.int32, device="cuda")
+        self.ctx.select(self.score, rnd_d, self.n_top, self.n_rand, out)
+        return out.cpu().numpy()
+
+    def record(self, idx, g):
+        """Exact gradients g for pool indices idx (features of this iteration)."""
+        torch = self.torch
+        idx = np.asarray(idx, dtype=np.int64)
+        absg = np.abs(np.asarray(g, dtype=np.float64))
+        rows = torch.from_numpy(idx).cuda()
+        x = self.feat.index_select(0, rows)
+        t = torch.from_numpy(np.log10(absg + 1e-12).astype(np.float32)).cuda()
+        n = len(idx)
+        for s in range(0, n, self.buffer_rows):
+            xs, ts = x[s:s + self.buffer_rows], t[s:s + self.buffer_rows]
+            m = len(ts)
+            end = self.buf_pos + m
+            if end <= self.buffer_rows:
+                self.buf_x[self.buf_pos:end] = xs
+                self.buf_t[self.buf_pos:end] = ts
+            else:
+                first = self.buffer_rows - self.buf_pos
+                self.buf_x[self.buf_pos:] = xs[:first]
+                self.buf_t[self.buf_pos:] = ts[:first]
+                self.buf_x[: m - first] = xs[first:]
+                self.buf_t[: m - first] = ts[first:]
+            self.buf_pos = end % self.buffer_rows
+            self.buf_n = min(self.buffer_rows, self.buf_n + m)
+        # per-operator history used by the features
+        self.age += 1.0
+        self.age[rows] = 0.0
+        self.prev_absg[rows] = torch.from_numpy(absg.astype(np.float32)).cuda()
+
+    def train(self):
+        """Full-batch Adam steps on the replay buffer; returns the last loss."""
+        torch = self.torch
+        B = self.buf_n
+        if B == 0:
+            return float("nan")
+        x, t = self.buf_x[:B], self.buf_t[:B]
+        y = torch.zeros(B, device="cuda")
+        act = torch.zeros((B, 256), device="cuda")
+        dy = torch.zeros(B, device="cuda")
+        for _ in range(self.train_steps):
+            self.ctx.mlp_forward(self.W, x, y, act)
+            self.ctx.mse(y, t, dy, self.loss)
+            self.ctx.mlp_backward(self.W, x, act, dy, self.dW)
+            self.adam_t += 1
+            self.ctx.adam_step(self.W, self.m, self.v, self.dW, self.lr, 0.9, 0.999, 1e-8, self.adam_t)
+        return float(self.loss.item())
