@@ -193,19 +193,52 @@ def gpu_bench(args, wl):
     fwd_applies, adj_applies = applies_in_step(n_in, seg)
     applies = fwd_applies + adj_applies
 
-    # Dominant kernel measurement: the gate kernel, timed as the apply phase
-    # (M launches) with events on the context stream.
-    reps = 20
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(reps):
-        phase_apply()
-    e1.record(stream)
-    torch.cuda.synchronize()
-    apply_ms = e0.elapsed_time(e1) / reps
+    # Per-kernel GPU time of one step: the library records HIP events on the
+    # context stream around every launch of the selected kernel.
+    kern = {}
+    reps = max(3, args.steps // 2)
+    for kname in ("chain_lds", "gate", "adjoint_lds", "gate_replay", "adjoint_rec", "sigma_proj",
+                  "sigma_push", "sigma_push_into", "pool_contract", "contract_ops"):
+        ctx.timer_start(kname)
+        for _ in range(reps):
+            step()
+        launches, total = ctx.timer_stop()
+        if launches:
+            kern[kname] = {"launches_per_step": launches / reps, "ms_per_step": total / reps,
+                           "us_per_launch": 1e3 * total / launches}
     ctx.close()
     return dict(ms_step=ms_step, phase_ms=phase_ms, n_det=n_det, n_in=n_in, applies=applies,
-                fwd_applies=fwd_applies, adj_applies=adj_applies, apply_ms=apply_ms, seg=seg)
+                fwd_applies=fwd_applies, adj_applies=adj_applies, kernels=kern, seg=seg)
+
+
+def algorithmic_bytes(kname, wl, r):
+    """Lower-bound bytes the method must move per launch of a kernel (see
+    the design doc): 8 B per stored determinant scanned by a gate; 16 B per
+    (source, connection) read-modify-write of the external sigma table; 8 B
+    per probe of a hash table and 16 B per source determinant read."""
+    from paper_2411_07920_amd.inputs import sector_size  # noqa: F401
+    n_in = r["n_in"]
+    M = len(n_in)
+    n = r["n_det"]
+    na = wl.na
+    from math import comb
+    nv = wl.c.n - na
+    C = 2 * na * nv + 2 * comb(na, 2) * comb(nv, 2) + na * na * nv * nv
+    if kname in ("chain_lds",):
+        return 8.0 * n_in.sum()                      # whole chain per launch
+    if kname in ("gate", "gate_replay", "adjoint_rec"):
+        return 8.0 * n_in.sum() / M                  # one gate per launch
+    if kname == "adjoint_lds":
+        return 2 * 8.0 * n_in.sum()                  # replay + reverse per gate
+    if kname == "sigma_proj":
+        return n * (C * 8.0 + 16.0)
+    if kname in ("sigma_push", "sigma_push_into"):
+        return n * ((C + 1) * 16.0 + 16.0)
+    if kname == "pool_contract":
+        return n * (C * 8.0 + 16.0)
+    if kname == "contract_ops":
+        return n * 16.0 + wl.n_top * 0.0
+    return 0.0
 
 
 def cpu_baseline(wl, fwd_applies, adj_applies, budget_s=20.0):
@@ -262,7 +295,15 @@ def adapt_bench(args):
         cfg = adapt.AdaptConfig(eps=c.eps, max_iter=iters, grad_tol=None, optimizer="lbfgs",
                                 screener=screened, shadow_full=shadow, seed=3000 + int(args.adapt[1:]))
         t = time.perf_counter()
-        ops, theta, hist = adapt.run_adapt(ctx, wl.K, cfg)
+        name = "screened" + ("+shadow" if shadow else "") if screened else "full"
+
+        def log(r):
+            print(f"[adapt {name}] it={r['iter']} E={r.get('E_after', r['E']):.10f} "
+                  f"k={r['kstar']} exact={r['n_exact']} pool={1e3 * r['t_pool']:.1f}ms "
+                  f"vqe={1e3 * r.get('t_vqe', 0.0):.1f}ms evals={r.get('vqe_evals', 0)}",
+                  file=sys.stderr, flush=True)
+
+        ops, theta, hist = adapt.run_adapt(ctx, wl.K, cfg, log=log)
         wall = time.perf_counter() - t
         ctx.apply_ansatz(ops, theta, c.eps)
         E = ctx.energy()[0]
@@ -315,13 +356,11 @@ def main():
     if r is None:
         return
     M = len(wl.ops)
-    # Algorithmic bytes of the gate kernel (per gate): 8 B key scan per stored
-    # determinant, 16 B amplitude read+write per touched determinant, 16 B key +
-    # amplitude per appended one.  Use the lower bound 8 B per kept determinant
-    # entering the gate plus 16 B per applied pair member.
-    n_in = r["n_in"]
-    bytes_apply = float(8 * n_in.sum())
-    achieved = bytes_apply / (r["apply_ms"] * 1e-3) / 1e9
+    kern = r["kernels"]
+    dom = max(kern, key=lambda k: kern[k]["ms_per_step"])
+    per_launch_s = kern[dom]["us_per_launch"] * 1e-6
+    bytes_launch = algorithmic_bytes(dom, wl, r)
+    achieved = bytes_launch / per_launch_s / 1e9
     line = {
         "metric": "determinant-excitation applies/s",
         "value": r["applies"] / (r["ms_step"] * 1e-3),
@@ -342,7 +381,9 @@ def main():
         "phases_ms": {k: round(v, 4) for k, v in r["phase_ms"].items()},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_gate", "per_launch_us": r["apply_ms"] * 1e3 / M},
+                     "kernel": dom, "us_per_launch": kern[dom]["us_per_launch"],
+                     "algorithmic_bytes_per_launch": bytes_launch},
+        "kernels_ms_per_step": {k: round(v["ms_per_step"], 4) for k, v in kern.items()},
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(wl, r["fwd_applies"], r["adj_applies"])

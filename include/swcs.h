@@ -160,6 +160,30 @@ int swcs_gate_sizes(swcs_ctx* ctx, int64_t* n_in, int64_t M);
  * current state, n_out[2n] (host). */
 int swcs_occupations(swcs_ctx* ctx, double* n_out);
 
+/* ---- measurement ---- */
+
+/* Kernels that swcs_timer_start can time. */
+enum {
+  SWCS_K_CHAIN_LDS = 1,     /* whole gate chain in one LDS-resident workgroup   */
+  SWCS_K_GATE = 2,          /* one gate, multi-block, state in HBM              */
+  SWCS_K_SIGMA_PROJ = 3,    /* projected sigma vector + energy partial sums     */
+  SWCS_K_SIGMA_PUSH = 4,    /* external sigma vector accumulation               */
+  SWCS_K_POOL_CONTRACT = 5, /* pool-gradient contraction                        */
+  SWCS_K_ADJOINT_LDS = 6,   /* whole adjoint sweep in one LDS-resident workgroup */
+  SWCS_K_GATE_REPLAY = 7,   /* one replayed gate with pair logging (adjoint)    */
+  SWCS_K_ADJOINT_REC = 8,   /* one reverse step over logged pairs (adjoint)     */
+  SWCS_K_SIGMA_PUSH_INTO = 9, /* external sigma on the screened query set        */
+  SWCS_K_CONTRACT_OPS = 10   /* operator-major contraction of a small subset     */
+};
+
+/* From now on record HIP events on the context stream around every launch
+ * of kernel `kernel_id` (one of SWCS_K_*), discarding earlier records. */
+int swcs_timer_start(swcs_ctx* ctx, int kernel_id);
+
+/* Synchronize the stream, return the number of timed launches and their
+ * summed duration in milliseconds, and stop timing. */
+int swcs_timer_stop(swcs_ctx* ctx, int64_t* launches, double* total_ms);
+
 /* ---- learned pool screener (device pointers, float32, ctx stream) ---- */
 
 /* Number of float32 parameters of the screener MLP 16 -> 128 -> 128 -> 1

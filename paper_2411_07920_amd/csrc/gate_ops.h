@@ -25,13 +25,31 @@ struct GateOut {
   u64 key;
   double val;
   long long dalive;
+  // The pair this thread owned (active = at least one member was in the
+  // state before the gate): entry positions (kNoEntry if not stored; an
+  // appended member is filled in by the caller), values before the gate
+  // (dead if not in the state) and the sign s = <X|T|D>.
+  bool active;
+  u64 iD, iX;
+  double a_old, b_old;
+  int s;
+};
+
+constexpr u64 kNoEntry = ~0ULL;
+
+// One logged pair of a gate, consumed by the reverse (adjoint) step.
+struct PairRec {
+  unsigned iD, iX;  // 0xffffffff = not stored
+  int s;
+  unsigned pad;
+  double a_old, b_old;
 };
 
 // Store: key(i), amp(i), set_amp(i, v), find(key) -> index or -1.
 template <class Store>
 __device__ inline GateOut gate_entry(Store& S, u64 i, const OpDesc& op, double c, double sn,
                                      double eps) {
-  GateOut o{false, 0ULL, 0.0, 0};
+  GateOut o{false, 0ULL, 0.0, 0, false, kNoEntry, kNoEntry, 0.0, 0.0, 0};
   const u64 D = S.key(i);
   const bool isT = ((D & op.ann) == op.ann) && ((D & op.cre) == 0);
   const bool isTd = ((D & op.cre) == op.cre) && ((D & op.ann) == 0);
@@ -59,6 +77,12 @@ __device__ inline GateOut gate_entry(Store& S, u64 i, const OpDesc& op, double c
         o.val = nx;
       }
       o.dalive = (long long)keepD - (long long)aliveD + (long long)keepX - (long long)aliveX;
+      o.active = true;
+      o.iD = i;
+      o.iX = (j >= 0) ? (u64)j : kNoEntry;
+      o.a_old = araw;
+      o.b_old = braw;
+      o.s = (int)s;
     }
   } else if (isTd) {
     const u64 Dsrc = D ^ pair_mask;
@@ -81,49 +105,43 @@ __device__ inline GateOut gate_entry(Store& S, u64 i, const OpDesc& op, double c
           o.val = nd;
         }
         o.dalive = (long long)keepD + (long long)keepX - 1LL;
+        o.active = true;
+        o.iD = kNoEntry;
+        o.iX = i;
+        o.a_old = dead_value();
+        o.b_old = braw;
+        o.s = (int)s;
       }
     }
   }
   return o;
 }
 
-// Reverse step of one gate for the frozen-support adjoint.  prev(i) is the
-// amplitude before the gate (dead if not in that state); mu holds the
-// adjoint after the gate (zero outside the kept support) and is overwritten
-// with the adjoint before the gate.  Returns this entry's share of
-// dE/dtheta = <mu | P U'(theta) psi_prev>, U' the derivative of the rotation.
-template <class Keys, class Prev, class Mu>
-__device__ inline double adjoint_entry(const Keys& K, const Prev& prev, Mu& mu, u64 i,
-                                       const OpDesc& op, double c, double sn) {
-  const u64 D = K.key(i);
-  const bool isT = ((D & op.ann) == op.ann) && ((D & op.cre) == 0);
-  const bool isTd = ((D & op.cre) == op.cre) && ((D & op.ann) == 0);
-  const u64 pair_mask = op.ann | op.cre;
-  if (isT) {
-    const u64 X = D ^ pair_mask;
-    const long long j = K.find(X);
-    const double araw = prev(i);
-    const double braw = (j >= 0) ? prev((u64)j) : dead_value();
-    const bool aliveD = !is_dead(araw), aliveX = !is_dead(braw);
-    if (!aliveD && !aliveX) return 0.0;
-    const double s = (double)phase_of_T(op, D);
-    const double a = aliveD ? araw : 0.0, b = aliveX ? braw : 0.0;
-    const double muD = mu.get(i);
-    const double muX = (j >= 0) ? mu.get((u64)j) : 0.0;
-    mu.set(i, aliveD ? (c * muD + s * sn * muX) : 0.0);
-    if (j >= 0) mu.set((u64)j, aliveX ? (c * muX - s * sn * muD) : 0.0);
-    return muD * (-sn * a - s * c * b) + muX * (-sn * b + s * c * a);
-  }
-  if (isTd) {
-    const u64 Dsrc = D ^ pair_mask;
-    if (K.find(Dsrc) >= 0) return 0.0;  // the thread of Dsrc owns the pair
-    const double braw = prev(i);
-    if (is_dead(braw)) return 0.0;
-    const double muX = mu.get(i);
-    mu.set(i, c * muX);
-    return muX * (-sn * braw);
-  }
-  return 0.0;
+// Reverse step of one logged pair: with a, b the pair's values before the
+// gate and mu after it, contributes mu^T P U'(theta) (a, b) to dE/dtheta and
+// overwrites mu with U(theta)^T mu restricted to the pair members that were
+// in the state before the gate.
+template <class Mu>
+__device__ inline double adjoint_pair(const PairRec& r, Mu& mu, double c, double sn) {
+  const bool aliveD = !is_dead(r.a_old), aliveX = !is_dead(r.b_old);
+  const double a = aliveD ? r.a_old : 0.0, b = aliveX ? r.b_old : 0.0;
+  const double s = (double)r.s;
+  const double muD = (r.iD != 0xffffffffu) ? mu.get(r.iD) : 0.0;
+  const double muX = (r.iX != 0xffffffffu) ? mu.get(r.iX) : 0.0;
+  if (r.iD != 0xffffffffu) mu.set(r.iD, aliveD ? (c * muD + s * sn * muX) : 0.0);
+  if (r.iX != 0xffffffffu) mu.set(r.iX, aliveX ? (c * muX - s * sn * muD) : 0.0);
+  return muD * (-sn * a - s * c * b) + muX * (-sn * b + s * c * a);
+}
+
+__device__ inline PairRec make_rec(const GateOut& o) {
+  PairRec r;
+  r.iD = (o.iD == kNoEntry) ? 0xffffffffu : (unsigned)o.iD;
+  r.iX = (o.iX == kNoEntry) ? 0xffffffffu : (unsigned)o.iX;
+  r.s = o.s;
+  r.pad = 0;
+  r.a_old = o.a_old;
+  r.b_old = o.b_old;
+  return r;
 }
 
 // ---------------------------------------------------------------- stores
@@ -136,11 +154,6 @@ struct GlobalStore {
   __device__ double amp(u64 i) const { return amps[i]; }
   __device__ void set_amp(u64 i, double v) { amps[i] = v; }
   __device__ long long find(u64 k) const { return hash_find(hash, hmask, k); }
-};
-
-struct GlobalPrev {
-  const double* p;
-  __device__ double operator()(u64 i) const { return p[i]; }
 };
 
 struct GlobalMu {

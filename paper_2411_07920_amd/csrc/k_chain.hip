@@ -134,23 +134,28 @@ k_chain_lds(u64* __restrict__ keys, double* __restrict__ amps, Counters* __restr
 }
 
 // Whole frozen-support adjoint sweep for a final state of n <= CAP stored
-// determinants.  For each segment (last first): restore the checkpoint,
-// recompute the segment's states (kept in HBM scratch S[t]), then run the
-// reverse steps with the adjoint vector mu held in LDS.  dE[g] is a block sum
-// in a fixed order.
+// determinants.  For each segment (last first): restore the checkpoint into
+// LDS, replay the segment's gates logging one PairRec per active pair (HBM
+// scratch, seg * n records at most), then run the reverse steps over the
+// logged pairs with the adjoint vector mu held in LDS.  dE[g] is a block sum
+// in a fixed wave order.
+constexpr int kMaxSeg = 256;
+
 template <int CAP>
 __global__ void __launch_bounds__(kChainThreads)
 k_adjoint_lds(const u64* __restrict__ keys, unsigned n, const GateDesc* __restrict__ gates, int M,
               int seg, double eps, const double* const* __restrict__ ckpt,
               const u64* __restrict__ ckpt_n, const double* __restrict__ mu_init,
-              double* __restrict__ S, double* __restrict__ dE, unsigned* __restrict__ flags) {
+              PairRec* __restrict__ logbuf, double* __restrict__ dE, unsigned* __restrict__ flags) {
   __shared__ u64 skeys[CAP];
   __shared__ double sW[CAP];
   __shared__ double smu[CAP];
   __shared__ int sslots[2 * CAP];
   __shared__ double wsum[kChainThreads / 64];
+  __shared__ unsigned cnt[kMaxSeg];
   const int tid = threadIdx.x;
   for (int t = tid; t < 2 * CAP; t += kChainThreads) sslots[t] = 0;
+  for (int t = tid; t < kMaxSeg; t += kChainThreads) cnt[t] = 0;
   for (unsigned i = tid; i < n; i += kChainThreads) {
     skeys[i] = keys[i];
     smu[i] = mu_init[i];
@@ -167,33 +172,30 @@ k_adjoint_lds(const u64* __restrict__ keys, unsigned n, const GateDesc* __restri
     const int len = g_hi - g_lo;
     const unsigned nj = (unsigned)ckpt_n[j];
     const double* src = ckpt[j];
-    for (unsigned i = tid; i < n; i += kChainThreads) {
-      const double v = (i < nj) ? src[i] : dead_value();
-      sW[i] = v;
-      S[i] = v;
-    }
+    for (unsigned i = tid; i < n; i += kChainThreads) sW[i] = (i < nj) ? src[i] : dead_value();
     __syncthreads();
-    for (int t = 1; t < len; ++t) {
-      const GateDesc gd = gates[g_lo + t - 1];
+    for (int t = 0; t < len; ++t) {
+      const GateDesc gd = gates[g_lo + t];
+      PairRec* lg = logbuf + (size_t)t * n;
       for (unsigned i = tid; i < n; i += kChainThreads) {
         const GateOut o = gate_entry(L, i, gd.op, gd.c, gd.s, eps);
         if (o.append) atomicOr(flags, kFlagOverflow);  // cannot happen: all keys are stored
+        if (o.active) lg[atomicAdd(&cnt[t], 1u)] = make_rec(o);
       }
-      __syncthreads();
-      double* St = S + (size_t)t * n;
-      for (unsigned i = tid; i < n; i += kChainThreads) St[i] = sW[i];
       __syncthreads();
     }
     for (int t = len - 1; t >= 0; --t) {
       const GateDesc gd = gates[g_lo + t];
-      GlobalPrev prev{S + (size_t)t * n};
+      const PairRec* lg = logbuf + (size_t)t * n;
+      const unsigned c = cnt[t];
       double acc = 0.0;
-      for (unsigned i = tid; i < n; i += kChainThreads)
-        acc += adjoint_entry(L, prev, mu, i, gd.op, gd.c, gd.s);
+      for (unsigned r = tid; r < c; r += kChainThreads) acc += adjoint_pair(lg[r], mu, gd.c, gd.s);
       __syncthreads();
       const double tot = block_sum_1024(acc, wsum);
       if (tid == 0) dE[g_lo + t] = tot;
     }
+    for (int t = tid; t < len; t += kChainThreads) cnt[t] = 0;
+    __syncthreads();
   }
 }
 
@@ -208,12 +210,15 @@ hipError_t launch_chain_lds(const DeviceState& st, const GateDesc* gates, int g0
   return hipGetLastError();
 }
 
+int lds_adjoint_max_segment() { return kMaxSeg; }
+
 hipError_t launch_adjoint_lds(const u64* keys, unsigned n, const GateDesc* gates, int M, int seg,
                               double eps, const double* const* ckpt, const u64* ckpt_n,
-                              const double* mu_init, double* S, double* dE, unsigned* flags,
+                              const double* mu_init, PairRec* logbuf, double* dE, unsigned* flags,
                               hipStream_t stream) {
+  if (seg > kMaxSeg) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_adjoint_lds<kLdsCap>, dim3(1), dim3(kChainThreads), 0, stream, keys, n, gates,
-                     M, seg, eps, ckpt, ckpt_n, mu_init, S, dE, flags);
+                     M, seg, eps, ckpt, ckpt_n, mu_init, logbuf, dE, flags);
   return hipGetLastError();
 }
 

@@ -275,6 +275,78 @@ k_query_set(const u64* __restrict__ keys, const double* __restrict__ amps, ExcSp
   }
 }
 
+// Operator-major passes for a screened subset: block (x, y) stages a tile of
+// determinants in LDS (x) and gives each thread one selected operator (y).
+// Pass "query" counts or inserts X_k(D) for every active (k, D); pass
+// "contract" accumulates psi(D) a_k(D) sigma(X_k(D)) per operator slot.
+constexpr int kOpTile = 16;
+
+__global__ void __launch_bounds__(256)
+k_query_ops(const u64* __restrict__ keys, const double* __restrict__ amps, u64 n,
+            const OpDesc* __restrict__ ops, const int* __restrict__ subset, long long n_sub,
+            AccSlot* __restrict__ tab, u64 tmask, int count_only, u64* __restrict__ counter,
+            unsigned* __restrict__ flags) {
+  __shared__ u64 skey[kOpTile];
+  const u64 t0 = (u64)blockIdx.x * kOpTile;
+  const int tile = (int)((n - t0) < (u64)kOpTile ? (n - t0) : (u64)kOpTile);
+  for (int t = threadIdx.x; t < tile; t += blockDim.x)
+    skey[t] = is_dead(amps[t0 + t]) ? 0ULL : keys[t0 + t];
+  __syncthreads();
+  const long long slot = (long long)blockIdx.y * blockDim.x + threadIdx.x;
+  unsigned long long mine = 0;
+  if (slot < n_sub) {
+    const OpDesc op = ops[subset[slot]];
+    const u64 pm = op.ann | op.cre;
+    for (int t = 0; t < tile; ++t) {
+      const u64 D = skey[t];
+      if (D == 0ULL) continue;
+      const bool act = (((D & op.ann) == op.ann) && ((D & op.cre) == 0)) ||
+                       (((D & op.cre) == op.cre) && ((D & op.ann) == 0));
+      if (!act) continue;
+      if (count_only) ++mine;
+      else if (!acc_add(tab, tmask, D ^ pm, 0.0)) atomicOr(flags, kFlagOverflow);
+    }
+  }
+  if (count_only) {
+    for (int off = 32; off > 0; off >>= 1) mine += __shfl_xor(mine, off);
+    if (__lane_id() == 0 && mine) atomicAdd(counter, (u64)mine);
+  }
+}
+
+__global__ void __launch_bounds__(256)
+k_contract_ops(const u64* __restrict__ keys, const double* __restrict__ amps, u64 n,
+               const OpDesc* __restrict__ ops, const int* __restrict__ subset, long long n_sub,
+               const AccSlot* __restrict__ tab, u64 tmask, double* __restrict__ gslot) {
+  __shared__ u64 skey[kOpTile];
+  __shared__ double samp[kOpTile];
+  const u64 t0 = (u64)blockIdx.x * kOpTile;
+  const int tile = (int)((n - t0) < (u64)kOpTile ? (n - t0) : (u64)kOpTile);
+  for (int t = threadIdx.x; t < tile; t += blockDim.x) {
+    const double a = amps[t0 + t];
+    skey[t] = is_dead(a) ? 0ULL : keys[t0 + t];
+    samp[t] = a;
+  }
+  __syncthreads();
+  const long long slot = (long long)blockIdx.y * blockDim.x + threadIdx.x;
+  if (slot >= n_sub) return;
+  const OpDesc op = ops[subset[slot]];
+  const u64 pm = op.ann | op.cre;
+  double acc = 0.0;
+  for (int t = 0; t < tile; ++t) {
+    const u64 D = skey[t];
+    if (D == 0ULL) continue;
+    const bool isT = ((D & op.ann) == op.ann) && ((D & op.cre) == 0);
+    const bool isTd = ((D & op.cre) == op.cre) && ((D & op.ann) == 0);
+    if (!(isT || isTd)) continue;
+    const u64 X = D ^ pm;
+    double sx;
+    if (!acc_find(tab, tmask, X, &sx)) continue;
+    const double a = isT ? (double)phase_of_T(op, D) : -(double)phase_of_T(op, X);
+    acc += samp[t] * a * sx;
+  }
+  if (acc != 0.0) unsafeAtomicAdd(&gslot[slot], acc);
+}
+
 __device__ inline double* acc_slot(AccSlot* tab, u64 mask, u64 key) {
   u64 h = mix64(key) & mask;
   for (u64 probes = 0; probes <= mask; ++probes) {
@@ -314,11 +386,13 @@ k_sigma_push_into(const u64* __restrict__ keys, const double* __restrict__ amps,
   }
 }
 
-// out[t] = scale * gacc[subset[t]] (subset == NULL: identity).
+// out[t] = (2 / norm2) * gacc[subset[t]] (subset == NULL: identity), with
+// norm2 = <psi|psi> read from device memory.
 __global__ void k_gather_scaled(const double* __restrict__ gacc, const int* __restrict__ subset,
-                                long long count, double scale, double* __restrict__ out) {
+                                long long count, const double* __restrict__ norm2,
+                                double* __restrict__ out) {
   const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < count) out[t] = scale * gacc[subset ? subset[t] : t];
+  if (t < count) out[t] = (2.0 / norm2[0]) * gacc[subset ? subset[t] : t];
 }
 
 __global__ void k_mark_selected(const int* __restrict__ subset, long long count,
@@ -372,9 +446,11 @@ __global__ void k_reduce_partials(const double* __restrict__ partial, int count,
   if (threadIdx.x == 0) out[v] = red[0];
 }
 
-// mu = scale * (sigma - E psi) on alive entries, 0 elsewhere.
+// mu = (2 / norm2) (sigma - E psi) on alive entries, 0 elsewhere, with
+// (numer, norm2) = nn[0], nn[1] in device memory and E = numer / norm2.
 __global__ void k_mu_init(const double* __restrict__ amps, const double* __restrict__ sigma, u64 n,
-                          double scale, double E, double* __restrict__ mu) {
+                          const double* __restrict__ nn, double* __restrict__ mu) {
+  const double scale = 2.0 / nn[1], E = nn[0] / nn[1];
   const u64 stride = (u64)gridDim.x * blockDim.x;
   for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
     const double a = amps[i];
@@ -391,13 +467,12 @@ hipError_t launch_sigma_proj(const DeviceState& st, const Ints& I, const ExcSpac
   return hipGetLastError();
 }
 
-hipError_t launch_mu_init(const DeviceState& st, const double* sigma, u64 n, double scale, double E,
+hipError_t launch_mu_init(const DeviceState& st, const double* sigma, u64 n, const double* nn,
                           double* mu, hipStream_t stream) {
   u64 g = (n + 255) / 256;
   if (g < 1) g = 1;
   if (g > 8192) g = 8192;
-  hipLaunchKernelGGL(k_mu_init, dim3((unsigned)g), dim3(256), 0, stream, st.amps, sigma, n, scale,
-                     E, mu);
+  hipLaunchKernelGGL(k_mu_init, dim3((unsigned)g), dim3(256), 0, stream, st.amps, sigma, n, nn, mu);
   return hipGetLastError();
 }
 
@@ -435,6 +510,26 @@ hipError_t launch_query_set(const DeviceState& st, const ExcSpace& E, int n_spat
   return hipGetLastError();
 }
 
+hipError_t launch_query_ops(const DeviceState& st, u64 n, const OpDesc* ops, const int* subset,
+                            long long n_sub, AccSlot* tab, u64 tmask, int count_only, u64* counter,
+                            hipStream_t stream) {
+  if (n == 0 || n_sub == 0) return hipSuccess;
+  const dim3 grid((unsigned)((n + kOpTile - 1) / kOpTile), (unsigned)((n_sub + 255) / 256));
+  hipLaunchKernelGGL(k_query_ops, grid, dim3(256), 0, stream, st.keys, st.amps, n, ops, subset,
+                     n_sub, tab, tmask, count_only, counter, &st.ctr->flags);
+  return hipGetLastError();
+}
+
+hipError_t launch_contract_ops(const DeviceState& st, u64 n, const OpDesc* ops, const int* subset,
+                               long long n_sub, const AccSlot* tab, u64 tmask, double* gslot,
+                               hipStream_t stream) {
+  if (n == 0 || n_sub == 0) return hipSuccess;
+  const dim3 grid((unsigned)((n + kOpTile - 1) / kOpTile), (unsigned)((n_sub + 255) / 256));
+  hipLaunchKernelGGL(k_contract_ops, grid, dim3(256), 0, stream, st.keys, st.amps, n, ops, subset,
+                     n_sub, tab, tmask, gslot);
+  return hipGetLastError();
+}
+
 hipError_t launch_sigma_push_into(const DeviceState& st, const Ints& I, const ExcSpace& E, u64 n,
                                   AccSlot* tab, u64 tmask, int grid, hipStream_t stream) {
   hipLaunchKernelGGL(k_sigma_push_into, dim3(grid), dim3(kSigBlock), 0, stream, st.keys, st.amps, I,
@@ -442,11 +537,11 @@ hipError_t launch_sigma_push_into(const DeviceState& st, const Ints& I, const Ex
   return hipGetLastError();
 }
 
-hipError_t launch_gather_scaled(const double* gacc, const int* subset, long long count, double scale,
-                                double* out, hipStream_t stream) {
+hipError_t launch_gather_scaled(const double* gacc, const int* subset, long long count,
+                                const double* norm2, double* out, hipStream_t stream) {
   if (count == 0) return hipSuccess;
   hipLaunchKernelGGL(k_gather_scaled, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, stream,
-                     gacc, subset, count, scale, out);
+                     gacc, subset, count, norm2, out);
   return hipGetLastError();
 }
 

@@ -13,14 +13,19 @@ constexpr int kSortThreads = 256;
 constexpr int kSortRows = 16;
 constexpr int kSortTile = kSortThreads * kSortRows;
 
+// Rows of 256 items per tile: 16 for large sorts, 1 for small ones (more
+// tiles, shorter serial row loop per tile).
+inline int sort_rows(u64 count) { return count < (1ULL << 20) ? 1 : kSortRows; }
+
+template <int ROWS>
 __global__ void __launch_bounds__(kSortThreads)
 k_radix_hist(const u64* __restrict__ keys, u64 count, int shift, u64* __restrict__ counts,
              int nblocks) {
   __shared__ unsigned hist[256];
   hist[threadIdx.x] = 0;
   __syncthreads();
-  const u64 base = (u64)blockIdx.x * kSortTile;
-  for (int r = 0; r < kSortRows; ++r) {
+  const u64 base = (u64)blockIdx.x * (kSortThreads * ROWS);
+  for (int r = 0; r < ROWS; ++r) {
     const u64 i = base + (u64)r * kSortThreads + threadIdx.x;
     if (i < count) atomicAdd(&hist[(keys[i] >> shift) & 255u], 1u);
   }
@@ -52,6 +57,7 @@ __global__ void __launch_bounds__(1024) k_scan_exclusive(u64* __restrict__ data,
   }
 }
 
+template <int ROWS>
 __global__ void __launch_bounds__(kSortThreads)
 k_radix_scatter(const u64* __restrict__ keys_in, const u64* __restrict__ vals_in, u64 count,
                 int shift, const u64* __restrict__ offsets, int nblocks, u64* __restrict__ keys_out,
@@ -63,8 +69,8 @@ k_radix_scatter(const u64* __restrict__ keys_in, const u64* __restrict__ vals_in
   const int wave = threadIdx.x >> 6;
   base_off[threadIdx.x] = offsets[(u64)threadIdx.x * nblocks + blockIdx.x];
   running[threadIdx.x] = 0;
-  const u64 tile0 = (u64)blockIdx.x * kSortTile;
-  for (int r = 0; r < kSortRows; ++r) {
+  const u64 tile0 = (u64)blockIdx.x * (kSortThreads * ROWS);
+  for (int r = 0; r < ROWS; ++r) {
     for (int w = 0; w < 4; ++w) wave_cnt[w][threadIdx.x] = 0;
     __syncthreads();
     const u64 i = tile0 + (u64)r * kSortThreads + threadIdx.x;
@@ -99,7 +105,8 @@ k_radix_scatter(const u64* __restrict__ keys_in, const u64* __restrict__ vals_in
 }
 
 u64 radix_sort_scratch_elems(u64 count) {
-  const u64 nblocks = (count + kSortTile - 1) / kSortTile;
+  const u64 tile = (u64)kSortThreads * sort_rows(count);
+  const u64 nblocks = (count + tile - 1) / tile;
   return 256 * (nblocks < 1 ? 1 : nblocks);
 }
 
@@ -108,24 +115,36 @@ u64 radix_sort_scratch_elems(u64 count) {
 hipError_t radix_sort_pairs(u64* keys, u64* vals, u64* tmp_keys, u64* tmp_vals, u64 count,
                             int key_bits, u64* scratch, u64 scratch_elems, hipStream_t stream) {
   if (count <= 1) return hipSuccess;
-  const int nblocks = (int)((count + kSortTile - 1) / kSortTile);
+  const int rows = sort_rows(count);
+  const u64 tile = (u64)kSortThreads * rows;
+  const int nblocks = (int)((count + tile - 1) / tile);
   if ((u64)256 * nblocks > scratch_elems) return hipErrorInvalidValue;
   const int passes = (key_bits + 7) / 8;
   u64 *kin = keys, *vin = vals, *kout = tmp_keys, *vout = tmp_vals;
   for (int p = 0; p < passes; ++p) {
     const int shift = 8 * p;
-    hipLaunchKernelGGL(k_radix_hist, dim3(nblocks), dim3(kSortThreads), 0, stream, kin, count, shift,
-                       scratch, nblocks);
+    if (rows == 1)
+      hipLaunchKernelGGL(k_radix_hist<1>, dim3(nblocks), dim3(kSortThreads), 0, stream, kin, count,
+                         shift, scratch, nblocks);
+    else
+      hipLaunchKernelGGL(k_radix_hist<kSortRows>, dim3(nblocks), dim3(kSortThreads), 0, stream, kin,
+                         count, shift, scratch, nblocks);
     hipLaunchKernelGGL(k_scan_exclusive, dim3(1), dim3(1024), 0, stream, scratch,
                        (u64)256 * nblocks);
-    hipLaunchKernelGGL(k_radix_scatter, dim3(nblocks), dim3(kSortThreads), 0, stream, kin, vin,
-                       count, shift, scratch, nblocks, kout, vout);
+    if (rows == 1)
+      hipLaunchKernelGGL(k_radix_scatter<1>, dim3(nblocks), dim3(kSortThreads), 0, stream, kin, vin,
+                         count, shift, scratch, nblocks, kout, vout);
+    else
+      hipLaunchKernelGGL(k_radix_scatter<kSortRows>, dim3(nblocks), dim3(kSortThreads), 0, stream,
+                         kin, vin, count, shift, scratch, nblocks, kout, vout);
     u64* t = kin; kin = kout; kout = t;
     t = vin; vin = vout; vout = t;
   }
   if (kin != keys) {
-    hipMemcpyAsync(keys, kin, count * sizeof(u64), hipMemcpyDeviceToDevice, stream);
-    if (vals) hipMemcpyAsync(vals, vin, count * sizeof(u64), hipMemcpyDeviceToDevice, stream);
+    hipError_t e = hipMemcpyAsync(keys, kin, count * sizeof(u64), hipMemcpyDeviceToDevice, stream);
+    if (e == hipSuccess && vals)
+      e = hipMemcpyAsync(vals, vin, count * sizeof(u64), hipMemcpyDeviceToDevice, stream);
+    if (e != hipSuccess) return e;
   }
   return hipGetLastError();
 }

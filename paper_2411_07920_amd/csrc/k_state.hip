@@ -96,19 +96,43 @@ k_gate(u64* __restrict__ keys, double* __restrict__ amps, HashSlot* __restrict__
   }
 }
 
-// Reverse step of one gate (see adjoint_entry); per-block partial sums of
-// dE/dtheta go to partial[blockIdx.x].
+// Replay of one gate inside the adjoint's recomputation: the same update as
+// k_gate on a working copy of the amplitudes, plus one PairRec per active
+// pair (wave-aggregated appends to log[]).  Every key the replay can reach is
+// already stored, so nothing is appended to the state.
 __global__ void __launch_bounds__(256)
-k_adjoint_step(const u64* __restrict__ keys, const HashSlot* __restrict__ hash, u64 hmask,
-               u64 n_total, OpDesc op, double c, double sn, const double* __restrict__ psi_prev,
-               double* __restrict__ mu, double* __restrict__ partial) {
-  GlobalStore K{(u64*)keys, nullptr, hash, hmask};
-  GlobalPrev prev{psi_prev};
+k_gate_replay(const u64* __restrict__ keys, double* __restrict__ amps,
+              const HashSlot* __restrict__ hash, u64 hmask, u64 n, OpDesc op, double c, double sn,
+              double eps, PairRec* __restrict__ log, u64* __restrict__ log_count,
+              unsigned* __restrict__ flags) {
+  GlobalStore S{(u64*)keys, amps, hash, hmask};
+  const u64 stride = (u64)gridDim.x * blockDim.x;
+  for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const GateOut o = gate_entry(S, i, op, c, sn, eps);
+    if (o.append) atomicOr(flags, kFlagOverflow);
+    const u64 m = __ballot(o.active);
+    if (m) {
+      const int lane = __lane_id();
+      const int leader = __ffsll((long long)m) - 1;
+      u64 base = 0;
+      if (lane == leader) base = atomicAdd(log_count, (u64)__popcll(m));
+      base = __shfl(base, leader);
+      if (o.active) log[base + (u64)__popcll(m & ((1ULL << lane) - 1ULL))] = make_rec(o);
+    }
+  }
+}
+
+// Reverse step of one gate over its logged pairs (see adjoint_pair);
+// per-block partial sums of dE/dtheta go to partial[blockIdx.x].
+__global__ void __launch_bounds__(256)
+k_adjoint_rec(const PairRec* __restrict__ log, const u64* __restrict__ log_count,
+              double* __restrict__ mu, double c, double sn, double* __restrict__ partial) {
   GlobalMu m{mu};
+  const u64 cnt = *log_count;
   double acc = 0.0;
   const u64 stride = (u64)gridDim.x * blockDim.x;
-  for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < n_total; i += stride)
-    acc += adjoint_entry(K, prev, m, i, op, c, sn);
+  for (u64 r = (u64)blockIdx.x * blockDim.x + threadIdx.x; r < cnt; r += stride)
+    acc += adjoint_pair(log[r], m, c, sn);
   __shared__ double sacc[256];
   sacc[threadIdx.x] = acc;
   __syncthreads();
@@ -131,6 +155,22 @@ __global__ void k_hash_build(const u64* __restrict__ keys, HashSlot* hash, u64 h
   const u64 stride = (u64)gridDim.x * blockDim.x;
   for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
     hash_insert_new(hash, hmask, keys[i], i);
+}
+
+// State = the single reference determinant with amplitude 1.
+__global__ void k_reset_reference(u64* __restrict__ keys, double* __restrict__ amps,
+                                  Counters* __restrict__ ctr, u64 ref) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    keys[0] = ref;
+    amps[0] = 1.0;
+    ctr->n = 1;
+    ctr->alive = 1;
+    ctr->app = 0;
+    ctr->dalive = 0;
+    ctr->ticket = 0;
+    ctr->flags = 0;
+    ctr->stop_gate = 0;
+  }
 }
 
 // Same, with the entry count read from the device counters.
@@ -213,6 +253,11 @@ hipError_t launch_hash_build(const DeviceState& st, u64 n, hipStream_t stream) {
   return hipGetLastError();
 }
 
+hipError_t launch_reset_reference(const DeviceState& st, u64 ref, hipStream_t stream) {
+  hipLaunchKernelGGL(k_reset_reference, dim3(1), dim3(64), 0, stream, st.keys, st.amps, st.ctr, ref);
+  return hipGetLastError();
+}
+
 hipError_t launch_hash_build_dev(const DeviceState& st, int grid, hipStream_t stream) {
   hipLaunchKernelGGL(k_hash_build_dev, dim3(grid), dim3(256), 0, stream, st.keys, st.hash, st.hmask,
                      st.ctr);
@@ -232,11 +277,18 @@ hipError_t launch_prune_all(const DeviceState& st, double eps, int grid, hipStre
   return hipGetLastError();
 }
 
-hipError_t launch_adjoint_step(const DeviceState& st, const OpDesc& op, double c, double sn,
-                               const double* amps_prev, double* mu, double* partial, u64 n_total,
-                               int grid, hipStream_t stream) {
-  hipLaunchKernelGGL(k_adjoint_step, dim3(grid), dim3(256), 0, stream, st.keys, st.hash, st.hmask,
-                     n_total, op, c, sn, amps_prev, mu, partial);
+hipError_t launch_gate_replay(const DeviceState& st, double* amps, u64 n, const OpDesc& op,
+                             double c, double sn, double eps, PairRec* log, u64* log_count, int grid,
+                             hipStream_t stream) {
+  hipLaunchKernelGGL(k_gate_replay, dim3(grid), dim3(256), 0, stream, st.keys, amps, st.hash,
+                     st.hmask, n, op, c, sn, eps, log, log_count, &st.ctr->flags);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint_rec(const PairRec* log, const u64* log_count, double* mu, double c,
+                              double sn, double* partial, int grid, hipStream_t stream) {
+  hipLaunchKernelGGL(k_adjoint_rec, dim3(grid), dim3(256), 0, stream, log, log_count, mu, c, sn,
+                     partial);
   return hipGetLastError();
 }
 

@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "../../include/swcs.h"
+#include "gate_ops.h"
 #include "swcs_internal.h"
 
 using namespace swcs;
@@ -23,7 +24,7 @@ struct DevBuf {
   size_t bytes = 0;
   hipError_t ensure(size_t want) {
     if (want <= bytes && p) return hipSuccess;
-    if (p) hipFree(p);
+    if (p) (void)hipFree(p);
     p = nullptr;
     bytes = 0;
     if (want == 0) want = 8;
@@ -36,7 +37,7 @@ struct DevBuf {
     return hipSuccess;
   }
   void release() {
-    if (p) hipFree(p);
+    if (p) (void)hipFree(p);
     p = nullptr;
     bytes = 0;
   }
@@ -84,6 +85,8 @@ struct swcs_ctx {
   // state
   DevBuf keys, amps, hash, ctr;
   DeviceState st;
+  Counters hc;            // host copy of the device counters
+  bool hc_valid = false;  // true while no launch may have changed them
   bool have_state = false;
   u64 peak_n = 0;
 
@@ -97,9 +100,16 @@ struct swcs_ctx {
   std::vector<DevBuf> ckpt;
   DevBuf ckpt_n;      // u64 per checkpoint
   DevBuf ckpt_ptrs;   // double* per checkpoint (device table)
+  std::vector<double*> ckpt_ptrs_host;  // last uploaded contents of ckpt_ptrs
+  std::vector<GateDesc> gate_tab_host;  // source of the last gate-table upload
   DevBuf gate_tab;    // GateDesc per gate of the last apply call
   DevBuf gate_n_in;   // u64 per gate of the last apply call
   int64_t last_M = 0;
+
+  // kernel timer: HIP events around every launch of one kernel
+  int timer_kernel = 0;
+  std::vector<hipEvent_t> ev_start, ev_stop;
+  size_t ev_used = 0;
 
   // scratch
   DevBuf gacc, selected;
@@ -114,6 +124,8 @@ struct swcs_ctx {
                      &sort_scratch, &ctr_r, &occ, &sel_scratch, &mlp_partial};
     for (DevBuf* b : all) b->release();
     for (auto& b : ckpt) b.release();
+    for (hipEvent_t e : ev_start) (void)hipEventDestroy(e);
+    for (hipEvent_t e : ev_stop) (void)hipEventDestroy(e);
   }
 };
 
@@ -134,6 +146,33 @@ int hip_fail(swcs_ctx* c, hipError_t e, const char* where) {
   do {                                                  \
     hipError_t _e = (expr);                             \
     if (_e != hipSuccess) return hip_fail(ctx, _e, where); \
+  } while (0)
+
+// Event pair around a launch of the kernel selected by swcs_timer_start.
+hipError_t timer_mark(swcs_ctx* c, int kid, bool start) {
+  if (c->timer_kernel != kid) return hipSuccess;
+  if (start) {
+    if (c->ev_used == c->ev_start.size()) {
+      hipEvent_t a, b;
+      hipError_t e = hipEventCreate(&a);
+      if (e != hipSuccess) return e;
+      e = hipEventCreate(&b);
+      if (e != hipSuccess) return e;
+      c->ev_start.push_back(a);
+      c->ev_stop.push_back(b);
+    }
+    return hipEventRecord(c->ev_start[c->ev_used], c->stream);
+  }
+  hipError_t e = hipEventRecord(c->ev_stop[c->ev_used], c->stream);
+  ++c->ev_used;
+  return e;
+}
+
+#define TIMED(ctx, kid, expr, where)                             \
+  do {                                                           \
+    HIP_TRY(ctx, timer_mark(ctx, kid, true), "timer");           \
+    HIP_TRY(ctx, expr, where);                                   \
+    HIP_TRY(ctx, timer_mark(ctx, kid, false), "timer");          \
   } while (0)
 
 int grid_blocks(swcs_ctx* c, u64 work_items, int per_block) {
@@ -168,7 +207,21 @@ Counters read_counters(swcs_ctx* c, hipError_t* e) {
   std::memset(&h, 0, sizeof(h));
   *e = hipMemcpyAsync(&h, c->ctr.p, sizeof(Counters), hipMemcpyDeviceToHost, c->stream);
   if (*e == hipSuccess) *e = hipStreamSynchronize(c->stream);
+  if (*e == hipSuccess) {
+    c->hc = h;
+    c->hc_valid = true;
+  }
   return h;
+}
+
+// Counters without a round trip when nothing has changed them since the
+// last read (state sizes only change in apply / set_state).
+Counters get_counters(swcs_ctx* c, hipError_t* e) {
+  if (c->hc_valid) {
+    *e = hipSuccess;
+    return c->hc;
+  }
+  return read_counters(c, e);
 }
 
 u64 max_capacity(swcs_ctx* c) {
@@ -229,16 +282,12 @@ int state_reset_to_reference(swcs_ctx* c) {
   } else {
     HIP_TRY(c, launch_hash_clear(c->st.hash, c->st.hmask + 1, c->stream), "hash clear");
   }
-  const double one = 1.0;
-  HIP_TRY(c, hipMemcpyAsync(c->keys.p, &c->ref, sizeof(u64), hipMemcpyHostToDevice, c->stream), "ref key");
-  HIP_TRY(c, hipMemcpyAsync(c->amps.p, &one, sizeof(double), hipMemcpyHostToDevice, c->stream), "ref amp");
-  Counters h;
-  std::memset(&h, 0, sizeof(h));
-  h.n = 1;
-  h.alive = 1;
-  HIP_TRY(c, hipMemcpyAsync(c->ctr.p, &h, sizeof(h), hipMemcpyHostToDevice, c->stream), "counters");
+  HIP_TRY(c, launch_reset_reference(c->st, c->ref, c->stream), "reset");
   HIP_TRY(c, launch_hash_build(c->st, 1, c->stream), "hash build");
-  HIP_TRY(c, hipStreamSynchronize(c->stream), "sync");  // host sources above
+  std::memset(&c->hc, 0, sizeof(c->hc));
+  c->hc.n = 1;
+  c->hc.alive = 1;
+  c->hc_valid = true;
   c->have_state = true;
   return SWCS_OK;
 }
@@ -268,10 +317,14 @@ int validate_gates(swcs_ctx* c, const int32_t* op_idx, const double* theta, int6
 int upload_ckpt_table(swcs_ctx* c, int nck) {
   std::vector<double*> ptrs((size_t)nck);
   for (int j = 0; j < nck; ++j) ptrs[(size_t)j] = c->ckpt[(size_t)j].as<double>();
-  HIP_TRY(c, c->ckpt_ptrs.ensure((size_t)nck * sizeof(double*)), "alloc ckpt table");
-  HIP_TRY(c, hipMemcpyAsync(c->ckpt_ptrs.p, ptrs.data(), (size_t)nck * sizeof(double*),
-                            hipMemcpyHostToDevice, c->stream), "copy ckpt table");
+  if (ptrs == c->ckpt_ptrs_host && c->ckpt_ptrs.bytes >= (size_t)nck * sizeof(double*))
+    return SWCS_OK;  // device table already current
+  // The previous upload may still be reading the host copy: wait for it.
   HIP_TRY(c, hipStreamSynchronize(c->stream), "sync");
+  c->ckpt_ptrs_host = ptrs;
+  HIP_TRY(c, c->ckpt_ptrs.ensure((size_t)nck * sizeof(double*)), "alloc ckpt table");
+  HIP_TRY(c, hipMemcpyAsync(c->ckpt_ptrs.p, c->ckpt_ptrs_host.data(), (size_t)nck * sizeof(double*),
+                            hipMemcpyHostToDevice, c->stream), "copy ckpt table");
   return SWCS_OK;
 }
 
@@ -283,13 +336,18 @@ int upload_ckpt_table(swcs_ctx* c, int nck) {
 int run_chain(swcs_ctx* c, const int32_t* op_idx, const double* cs, const double* sn, int64_t M,
               double eps, bool ckpt, u64 n_start, Counters* out) {
   int64_t g0 = 0;
+  c->hc_valid = false;
   if (M == 0) {
     hipError_t e;
     *out = read_counters(c, &e);
     if (e != hipSuccess) return hip_fail(c, e, "read counters");
     return SWCS_OK;
   }
-  std::vector<GateDesc> gt((size_t)M);
+  // The previous upload from gate_tab_host must be complete before it is
+  // rewritten.
+  HIP_TRY(c, hipStreamSynchronize(c->stream), "sync");
+  std::vector<GateDesc>& gt = c->gate_tab_host;
+  gt.resize((size_t)M);
   for (int64_t g = 0; g < M; ++g) {
     gt[(size_t)g].op = c->ops_host[op_idx[g]];
     gt[(size_t)g].c = cs[g];
@@ -307,7 +365,7 @@ int run_chain(swcs_ctx* c, const int32_t* op_idx, const double* cs, const double
   }
   if (n_start <= (u64)lds_chain_capacity() && c->st.cap >= (u64)lds_chain_capacity() &&
       M <= (int64_t)1 << 30) {
-    HIP_TRY(c, launch_chain_lds(c->st, c->gate_tab.as<GateDesc>(), 0, (int)M, eps, eps > 0.0 ? 1 : 0,
+    TIMED(c, SWCS_K_CHAIN_LDS, launch_chain_lds(c->st, c->gate_tab.as<GateDesc>(), 0, (int)M, eps, eps > 0.0 ? 1 : 0,
                                 ckpt ? c->ckpt_ptrs.as<double*>() : nullptr, c->ckpt_n.as<u64>(),
                                 c->seg, c->gate_n_in.as<u64>(), c->sector, c->stream), "chain");
     HIP_TRY(c, launch_hash_clear(c->st.hash, c->st.hmask + 1, c->stream), "hash clear");
@@ -334,7 +392,7 @@ int run_chain(swcs_ctx* c, const int32_t* op_idx, const double* cs, const double
                                     grid_blocks(c, c->st.cap / 4, 256), c->stream), "checkpoint");
       }
       const OpDesc& op = c->ops_host[op_idx[g]];
-      HIP_TRY(c, launch_gate(c->st, op, cs[g], sn[g], eps, c->gate_n_in.as<u64>() + g, 1,
+      TIMED(c, SWCS_K_GATE, launch_gate(c->st, op, cs[g], sn[g], eps, c->gate_n_in.as<u64>() + g, 1,
                              (unsigned)g, c->sector, grid_blocks(c, c->st.cap / 2, 256), c->stream),
               "gate");
       // The gates only test the entries they touch; entries of a starting
@@ -416,7 +474,11 @@ int swcs_create(int n_spatial, int n_alpha, int n_beta, int device, swcs_ctx** o
     delete c;
     return SWCS_E_OOM;
   }
-  hipMemset(c->ctr.p, 0, sizeof(Counters));
+  if (hipMemset(c->ctr.p, 0, sizeof(Counters)) != hipSuccess) {
+    g_create_error = "device memset failed";
+    delete c;
+    return SWCS_E_DEVICE;
+  }
   c->st.ctr = c->ctr.as<Counters>();
   *out = c;
   return SWCS_OK;
@@ -424,9 +486,9 @@ int swcs_create(int n_spatial, int n_alpha, int n_beta, int device, swcs_ctx** o
 
 void swcs_destroy(swcs_ctx* ctx) {
   if (!ctx) return;
-  hipSetDevice(ctx->device);
-  if (ctx->stream) hipStreamSynchronize(ctx->stream);
-  else hipDeviceSynchronize();
+  (void)hipSetDevice(ctx->device);
+  if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+  else (void)hipDeviceSynchronize();
   delete ctx;
 }
 
@@ -451,7 +513,7 @@ int swcs_set_capacity(swcs_ctx* c, int64_t max_dets) {
 int swcs_set_integrals(swcs_ctx* c, const double* h, const double* eri, double e_core) {
   if (!c) return SWCS_E_INVALID;
   if (!h || !eri) return fail(c, SWCS_E_INVALID, "null integrals");
-  hipSetDevice(c->device);
+  HIP_TRY(c, hipSetDevice(c->device), "hipSetDevice");
   const int n = c->n;
   const size_t n2 = (size_t)n * n, n4 = n2 * n2;
   if (!std::isfinite(e_core)) return fail(c, SWCS_E_INVALID, "non-finite e_core");
@@ -512,7 +574,7 @@ int swcs_set_pool(swcs_ctx* c, const int32_t* rows, int64_t K) {
   if (!c) return SWCS_E_INVALID;
   if (K < 0 || (K > 0 && !rows)) return fail(c, SWCS_E_INVALID, "bad pool arguments");
   if (K > (int64_t)1 << 30) return fail(c, SWCS_E_INVALID, "pool too large");
-  hipSetDevice(c->device);
+  HIP_TRY(c, hipSetDevice(c->device), "hipSetDevice");
   std::vector<OpDesc> ops((size_t)K);
   const int N = c->nso;
   for (int64_t k = 0; k < K; ++k) {
@@ -575,7 +637,7 @@ static int apply_common(swcs_ctx* c, const int32_t* op_idx, const double* theta,
   r = validate_gates(c, op_idx, theta, M, eps, ncut);
   if (r) return r;
   if (!from_reference && !c->have_state) return fail(c, SWCS_E_STATE, "no current state");
-  hipSetDevice(c->device);
+  HIP_TRY(c, hipSetDevice(c->device), "hipSetDevice");
   std::vector<double> cs((size_t)M), sn((size_t)M);
   for (int64_t i = 0; i < M; ++i) {
     cs[(size_t)i] = std::cos(theta[i]);
@@ -595,7 +657,7 @@ static int apply_common(swcs_ctx* c, const int32_t* op_idx, const double* theta,
   u64 n_start = 1;
   if (!from_reference) {
     hipError_t e;
-    Counters h0 = read_counters(c, &e);
+    Counters h0 = get_counters(c, &e);
     if (e != hipSuccess) return hip_fail(c, e, "read counters");
     n_start = h0.n;
   }
@@ -631,7 +693,7 @@ int swcs_apply_gates(swcs_ctx* c, const int32_t* op_idx, const double* theta, in
 int swcs_set_state(swcs_ctx* c, const uint64_t* keys, const double* amps, int64_t n) {
   if (!c) return SWCS_E_INVALID;
   if (n < 0 || (n > 0 && (!keys || !amps))) return fail(c, SWCS_E_INVALID, "bad state arguments");
-  hipSetDevice(c->device);
+  HIP_TRY(c, hipSetDevice(c->device), "hipSetDevice");
   std::vector<u64> sorted(keys, keys + n);
   std::sort(sorted.begin(), sorted.end());
   for (int64_t i = 0; i < n; ++i) {
@@ -659,6 +721,8 @@ int swcs_set_state(swcs_ctx* c, const uint64_t* keys, const double* amps, int64_
   HIP_TRY(c, hipMemcpy(c->ctr.p, &h, sizeof(h), hipMemcpyHostToDevice), "counters");
   if (n > 0) HIP_TRY(c, launch_hash_build(c->st, (u64)n, c->stream), "hash build");
   HIP_TRY(c, hipStreamSynchronize(c->stream), "sync");
+  c->hc = h;
+  c->hc_valid = true;
   c->peak_n = std::max<u64>(c->peak_n, (u64)n);
   c->have_state = true;
   c->ansatz_valid = false;
@@ -688,9 +752,9 @@ static int export_sorted(swcs_ctx* c, u64 n, u64 alive, const double* vals, uint
 int swcs_get_state(swcs_ctx* c, uint64_t* keys, double* amps, int64_t cap, int64_t* n_out) {
   if (!c) return SWCS_E_INVALID;
   if (!c->have_state) return fail(c, SWCS_E_STATE, "no current state");
-  hipSetDevice(c->device);
+  HIP_TRY(c, hipSetDevice(c->device), "hipSetDevice");
   hipError_t e;
-  Counters h = read_counters(c, &e);
+  Counters h = get_counters(c, &e);
   if (e != hipSuccess) return hip_fail(c, e, "read counters");
   if (n_out) *n_out = (int64_t)h.alive;
   if ((int64_t)h.alive > cap) return fail(c, SWCS_E_INVALID, "output capacity too small");
@@ -699,14 +763,22 @@ int swcs_get_state(swcs_ctx* c, uint64_t* keys, double* amps, int64_t cap, int64
   return export_sorted(c, h.n, h.alive, nullptr, keys, amps);
 }
 
-// sigma_P over the stored entries; returns numer and norm2 on the host.
-static int energy_internal(swcs_ctx* c, u64 n, double* numer, double* norm2) {
+// sigma_P over the stored entries; (numer, norm2) land in scalars[0..1] on
+// the device, without synchronizing.
+static int energy_enqueue(swcs_ctx* c, u64 n) {
   const int grid = sigma_grid(c, n);
   HIP_TRY(c, c->sigma.ensure(std::max<u64>(1, n) * 8), "alloc sigma");
   HIP_TRY(c, c->partial.ensure((size_t)2 * grid * 8), "alloc partial");
-  HIP_TRY(c, launch_sigma_proj(c->st, ints_view(c), c->exc, n, c->sigma.as<double>(),
+  TIMED(c, SWCS_K_SIGMA_PROJ, launch_sigma_proj(c->st, ints_view(c), c->exc, n, c->sigma.as<double>(),
                                c->partial.as<double>(), nullptr, grid, c->stream), "sigma");
   HIP_TRY(c, launch_reduce_partials(c->partial.as<double>(), grid, grid, 2, c->scalars.as<double>(), c->stream), "reduce");
+  return SWCS_OK;
+}
+
+// Same, returning numer and norm2 on the host.
+static int energy_internal(swcs_ctx* c, u64 n, double* numer, double* norm2) {
+  int r = energy_enqueue(c, n);
+  if (r) return r;
   double out[2];
   HIP_TRY(c, hipMemcpyAsync(out, c->scalars.p, 16, hipMemcpyDeviceToHost, c->stream), "copy");
   HIP_TRY(c, hipStreamSynchronize(c->stream), "sync");
@@ -719,9 +791,9 @@ int swcs_energy(swcs_ctx* c, double* E, double* numer, double* norm2) {
   if (!c) return SWCS_E_INVALID;
   if (!c->have_ints) return fail(c, SWCS_E_STATE, "integrals not set");
   if (!c->have_state) return fail(c, SWCS_E_STATE, "no current state");
-  hipSetDevice(c->device);
+  HIP_TRY(c, hipSetDevice(c->device), "hipSetDevice");
   hipError_t e;
-  Counters h = read_counters(c, &e);
+  Counters h = get_counters(c, &e);
   if (e != hipSuccess) return hip_fail(c, e, "read counters");
   double nu = 0.0, no = 0.0;
   int r = energy_internal(c, h.n, &nu, &no);
@@ -736,9 +808,9 @@ int swcs_sigma_projected(swcs_ctx* c, uint64_t* keys, double* sigma, int64_t cap
   if (!c) return SWCS_E_INVALID;
   if (!c->have_ints) return fail(c, SWCS_E_STATE, "integrals not set");
   if (!c->have_state) return fail(c, SWCS_E_STATE, "no current state");
-  hipSetDevice(c->device);
+  HIP_TRY(c, hipSetDevice(c->device), "hipSetDevice");
   hipError_t e;
-  Counters h = read_counters(c, &e);
+  Counters h = get_counters(c, &e);
   if (e != hipSuccess) return hip_fail(c, e, "read counters");
   if (n_out) *n_out = (int64_t)h.alive;
   if ((int64_t)h.alive > cap) return fail(c, SWCS_E_INVALID, "output capacity too small");
@@ -750,13 +822,12 @@ int swcs_sigma_projected(swcs_ctx* c, uint64_t* keys, double* sigma, int64_t cap
   return export_sorted(c, h.n, h.alive, c->sigma.as<double>(), keys, sigma);
 }
 
-static int norm2_internal(swcs_ctx* c, u64 n, double* norm2) {
+// <psi|psi> into scalars[2] on the device, without synchronizing.
+static int norm2_enqueue(swcs_ctx* c, u64 n) {
   const int grid = grid_blocks(c, n, 256);
   HIP_TRY(c, c->partial.ensure((size_t)grid * 8 * 2), "alloc partial");
   HIP_TRY(c, launch_occupations(c->st, n, 0, c->partial.as<double>(), grid, c->stream), "norm");
-  HIP_TRY(c, launch_reduce_partials(c->partial.as<double>(), grid, grid, 1, c->scalars.as<double>(), c->stream), "reduce");
-  HIP_TRY(c, hipMemcpyAsync(norm2, c->scalars.p, 8, hipMemcpyDeviceToHost, c->stream), "copy");
-  HIP_TRY(c, hipStreamSynchronize(c->stream), "sync");
+  HIP_TRY(c, launch_reduce_partials(c->partial.as<double>(), grid, grid, 1, c->scalars.as<double>() + 2, c->stream), "reduce");
   return SWCS_OK;
 }
 
@@ -773,15 +844,15 @@ int swcs_pool_gradients(swcs_ctx* c, const int32_t* subset, int64_t n_subset, do
       if (subset[t] < 0 || subset[t] >= c->K_pool) return fail(c, SWCS_E_INVALID, "subset index out of range");
   }
   if (count == 0) return SWCS_OK;
-  hipSetDevice(c->device);
+  HIP_TRY(c, hipSetDevice(c->device), "hipSetDevice");
   hipError_t e;
-  Counters h = read_counters(c, &e);
+  Counters h = get_counters(c, &e);
   if (e != hipSuccess) return hip_fail(c, e, "read counters");
   const u64 n = h.n;
-  double norm2 = 0.0;
-  r = norm2_internal(c, n, &norm2);
+  if (h.alive == 0) return fail(c, SWCS_E_STATE, "state is empty");
+  r = norm2_enqueue(c, n);
   if (r) return r;
-  if (!(norm2 > 0.0)) return fail(c, SWCS_E_STATE, "state has zero norm");
+  const double* norm2 = c->scalars.as<double>() + 2;
   HIP_TRY(c, c->gbuf.ensure((size_t)count * 8), "alloc g");
   HIP_TRY(c, c->gacc.ensure((size_t)c->K_pool * 8), "alloc g accumulator");
   HIP_TRY(c, hipMemsetAsync(c->gacc.p, 0, (size_t)c->K_pool * 8, c->stream), "zero g");
@@ -798,24 +869,46 @@ int swcs_pool_gradients(swcs_ctx* c, const int32_t* subset, int64_t n_subset, do
   }
   if (subset && 2 * n_subset < c->K_pool) {
     // Screened: sigma only on the determinants the selected operators reach.
-    HIP_TRY(c, hipMemsetAsync(c->scalars.as<u64>() + 16, 0, 8, c->stream), "zero counter");
-    HIP_TRY(c, launch_query_set(c->st, c->exc, c->n, n, c->opmap.as<HashSlot>(), c->omask, d_sel,
-                                nullptr, 0, 1, c->scalars.as<u64>() + 16, sigma_grid(c, n), c->stream), "count");
+    // Small subsets are walked operator-major (|psi| x n_subset activity
+    // tests); larger ones determinant-major through the generator map.
+    const bool op_major = n_subset <= c->exc.total;
+    u64* qcount = c->scalars.as<u64>() + 16;
+    HIP_TRY(c, hipMemsetAsync(qcount, 0, 8, c->stream), "zero counter");
+    if (op_major)
+      HIP_TRY(c, launch_query_ops(c->st, n, c->ops.as<OpDesc>(), d_subset, n_subset, nullptr, 0, 1,
+                                  qcount, c->stream), "count");
+    else
+      HIP_TRY(c, launch_query_set(c->st, c->exc, c->n, n, c->opmap.as<HashSlot>(), c->omask, d_sel,
+                                  nullptr, 0, 1, qcount, sigma_grid(c, n), c->stream), "count");
     u64 nq = 0;
-    HIP_TRY(c, hipMemcpyAsync(&nq, c->scalars.as<u64>() + 16, 8, hipMemcpyDeviceToHost, c->stream), "copy");
+    HIP_TRY(c, hipMemcpyAsync(&nq, qcount, 8, hipMemcpyDeviceToHost, c->stream), "copy");
     HIP_TRY(c, hipStreamSynchronize(c->stream), "sync");
     const u64 qslots = next_pow2(std::max<u64>(64, 2 * std::min<u64>(nq, c->sector)));
     HIP_TRY(c, c->acc_tab.ensure(qslots * sizeof(AccSlot)), "alloc sigma table");
     HIP_TRY(c, hipMemsetAsync(c->acc_tab.p, 0, qslots * sizeof(AccSlot), c->stream), "clear table");
-    HIP_TRY(c, launch_query_set(c->st, c->exc, c->n, n, c->opmap.as<HashSlot>(), c->omask, d_sel,
-                                c->acc_tab.as<AccSlot>(), qslots - 1, 0, nullptr, sigma_grid(c, n), c->stream), "query set");
-    HIP_TRY(c, launch_sigma_push_into(c->st, ints_view(c), c->exc, n, c->acc_tab.as<AccSlot>(), qslots - 1,
+    if (op_major)
+      HIP_TRY(c, launch_query_ops(c->st, n, c->ops.as<OpDesc>(), d_subset, n_subset,
+                                  c->acc_tab.as<AccSlot>(), qslots - 1, 0, nullptr, c->stream), "query set");
+    else
+      HIP_TRY(c, launch_query_set(c->st, c->exc, c->n, n, c->opmap.as<HashSlot>(), c->omask, d_sel,
+                                  c->acc_tab.as<AccSlot>(), qslots - 1, 0, nullptr, sigma_grid(c, n),
+                                  c->stream), "query set");
+    TIMED(c, SWCS_K_SIGMA_PUSH_INTO, launch_sigma_push_into(c->st, ints_view(c), c->exc, n, c->acc_tab.as<AccSlot>(), qslots - 1,
                                       sigma_grid(c, n), c->stream), "sigma push");
-    HIP_TRY(c, launch_pool_contract_det(c->st, c->exc, c->n, n, c->opmap.as<HashSlot>(), c->omask,
-                                        d_sel, c->ops.as<OpDesc>(), c->acc_tab.as<AccSlot>(), qslots - 1,
-                                        c->gacc.as<double>(), sigma_grid(c, n), c->stream), "contract");
-    HIP_TRY(c, launch_gather_scaled(c->gacc.as<double>(), d_subset, count, 2.0 / norm2, c->gbuf.as<double>(),
-                                    c->stream), "gather");
+    if (op_major) {
+      HIP_TRY(c, hipMemsetAsync(c->gbuf.p, 0, (size_t)count * 8, c->stream), "zero g");
+      TIMED(c, SWCS_K_CONTRACT_OPS, launch_contract_ops(c->st, n, c->ops.as<OpDesc>(), d_subset, n_subset,
+                                                        c->acc_tab.as<AccSlot>(), qslots - 1,
+                                                        c->gbuf.as<double>(), c->stream), "contract");
+      HIP_TRY(c, launch_gather_scaled(c->gbuf.as<double>(), nullptr, count, norm2,
+                                      c->gbuf.as<double>(), c->stream), "scale");
+    } else {
+      TIMED(c, SWCS_K_POOL_CONTRACT, launch_pool_contract_det(c->st, c->exc, c->n, n, c->opmap.as<HashSlot>(), c->omask,
+                                          d_sel, c->ops.as<OpDesc>(), c->acc_tab.as<AccSlot>(), qslots - 1,
+                                          c->gacc.as<double>(), sigma_grid(c, n), c->stream), "contract");
+      HIP_TRY(c, launch_gather_scaled(c->gacc.as<double>(), d_subset, count, norm2, c->gbuf.as<double>(),
+                                      c->stream), "gather");
+    }
     HIP_TRY(c, hipMemcpyAsync(g_out, c->gbuf.p, (size_t)count * 8, hipMemcpyDeviceToHost, c->stream), "copy g");
     Counters hq = read_counters(c, &e);
     if (e != hipSuccess) return hip_fail(c, e, "read counters");
@@ -827,7 +920,7 @@ int swcs_pool_gradients(swcs_ctx* c, const int32_t* subset, int64_t n_subset, do
   // table would exceed the memory budget.
   const double bound_d = std::min<double>((double)c->sector, (double)h.alive * (double)(c->exc.total + 1));
   size_t free_b = 0, total_b = 0;
-  hipMemGetInfo(&free_b, &total_b);
+  if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) free_b = 0;
   const double budget = std::max<double>(64.0 * 1024 * 1024, 0.4 * (double)free_b);
   int nbatch = 1;
   while ((2.0 * bound_d / nbatch) * sizeof(AccSlot) * 1.25 > budget && nbatch < 4096) nbatch *= 2;
@@ -835,13 +928,13 @@ int swcs_pool_gradients(swcs_ctx* c, const int32_t* subset, int64_t n_subset, do
   HIP_TRY(c, c->acc_tab.ensure(slots * sizeof(AccSlot)), "alloc sigma table");
   for (int b = 0; b < nbatch; ++b) {
     HIP_TRY(c, hipMemsetAsync(c->acc_tab.p, 0, slots * sizeof(AccSlot), c->stream), "clear table");
-    HIP_TRY(c, launch_sigma_push(c->st, ints_view(c), c->exc, n, c->acc_tab.as<AccSlot>(), slots - 1,
+    TIMED(c, SWCS_K_SIGMA_PUSH, launch_sigma_push(c->st, ints_view(c), c->exc, n, c->acc_tab.as<AccSlot>(), slots - 1,
                                  nbatch, b, sigma_grid(c, n), c->stream), "sigma push");
-    HIP_TRY(c, launch_pool_contract_det(c->st, c->exc, c->n, n, c->opmap.as<HashSlot>(), c->omask,
+    TIMED(c, SWCS_K_POOL_CONTRACT, launch_pool_contract_det(c->st, c->exc, c->n, n, c->opmap.as<HashSlot>(), c->omask,
                                         d_sel, c->ops.as<OpDesc>(), c->acc_tab.as<AccSlot>(), slots - 1,
                                         c->gacc.as<double>(), sigma_grid(c, n), c->stream), "contract");
   }
-  HIP_TRY(c, launch_gather_scaled(c->gacc.as<double>(), d_subset, count, 2.0 / norm2, c->gbuf.as<double>(),
+  HIP_TRY(c, launch_gather_scaled(c->gacc.as<double>(), d_subset, count, norm2, c->gbuf.as<double>(),
                                   c->stream), "gather");
   HIP_TRY(c, hipMemcpyAsync(g_out, c->gbuf.p, (size_t)count * 8, hipMemcpyDeviceToHost, c->stream), "copy g");
   Counters h2 = read_counters(c, &e);
@@ -854,86 +947,75 @@ int swcs_param_gradients(swcs_ctx* c, double* dE, double* E_out) {
   if (!c) return SWCS_E_INVALID;
   if (!c->ansatz_valid) return fail(c, SWCS_E_STATE, "no ansatz applied from the reference");
   if (!dE && c->a_ops.size() > 0) return fail(c, SWCS_E_INVALID, "null dE_dtheta");
-  hipSetDevice(c->device);
+  HIP_TRY(c, hipSetDevice(c->device), "hipSetDevice");
   const int64_t M = (int64_t)c->a_ops.size();
   hipError_t e;
-  Counters hfin = read_counters(c, &e);
+  Counters hfin = get_counters(c, &e);
   if (e != hipSuccess) return hip_fail(c, e, "read counters");
   const u64 n = hfin.n;
-  double numer = 0.0, norm2 = 0.0;
-  int r = energy_internal(c, n, &numer, &norm2);
+  int r;
+  if (M == 0) {
+    double numer = 0.0, norm2 = 0.0;
+    r = energy_internal(c, n, &numer, &norm2);
+    if (r) return r;
+    if (E_out) *E_out = numer / norm2;
+    return SWCS_OK;
+  }
+  r = energy_enqueue(c, n);
   if (r) return r;
-  const double E = numer / norm2;
-  if (E_out) *E_out = E;
-  if (M == 0) return SWCS_OK;
+  const double* nn = c->scalars.as<double>();
   const int seg = c->seg;
   const int nseg = (int)((M + seg - 1) / seg);
   const int grid = grid_blocks(c, n, 256);
   HIP_TRY(c, c->mu.ensure(n * 8), "alloc mu");
-  if (n <= (u64)lds_chain_capacity()) {
-    // Whole sweep in one single-workgroup launch with mu and the recomputed
+  HIP_TRY(c, c->gbuf.ensure((size_t)M * 8), "alloc dE");
+  // Pair logs of one segment: at most one record per stored entry per gate.
+  HIP_TRY(c, c->seg_states.ensure((size_t)seg * n * sizeof(PairRec)), "alloc pair logs");
+  PairRec* logs = c->seg_states.as<PairRec>();
+  HIP_TRY(c, launch_mu_init(c->st, c->sigma.as<double>(), n, nn, c->mu.as<double>(), c->stream), "mu init");
+  if (n <= (u64)lds_chain_capacity() && seg <= lds_adjoint_max_segment()) {
+    // Whole sweep in one single-workgroup launch with mu and the replayed
     // amplitudes in LDS; the gate table of the last apply call is reused.
     int r2 = upload_ckpt_table(c, nseg);
     if (r2) return r2;
-    HIP_TRY(c, c->seg_states.ensure((size_t)seg * n * 8), "alloc segment states");
-    HIP_TRY(c, c->gbuf.ensure((size_t)M * 8), "alloc dE");
-    HIP_TRY(c, launch_mu_init(c->st, c->sigma.as<double>(), n, 2.0 / norm2, E, c->mu.as<double>(), c->stream), "mu init");
-    HIP_TRY(c, launch_adjoint_lds(c->st.keys, (unsigned)n, c->gate_tab.as<GateDesc>(), (int)M, seg,
+    TIMED(c, SWCS_K_ADJOINT_LDS, launch_adjoint_lds(c->st.keys, (unsigned)n, c->gate_tab.as<GateDesc>(), (int)M, seg,
                                   c->a_eps, c->ckpt_ptrs.as<double*>(), c->ckpt_n.as<u64>(),
-                                  c->mu.as<double>(), c->seg_states.as<double>(), c->gbuf.as<double>(),
+                                  c->mu.as<double>(), logs, c->gbuf.as<double>(),
                                   &c->st.ctr->flags, c->stream), "adjoint");
-    HIP_TRY(c, hipMemcpyAsync(dE, c->gbuf.p, (size_t)M * 8, hipMemcpyDeviceToHost, c->stream), "copy dE");
-    Counters hchk = read_counters(c, &e);
-    if (e != hipSuccess) return hip_fail(c, e, "sync");
-    if (hchk.flags & kFlagOverflow) return fail(c, SWCS_E_DEVICE, "recomputation diverged from the forward run");
-    return SWCS_OK;
-  }
-  HIP_TRY(c, c->seg_states.ensure((size_t)seg * n * 8), "alloc segment states");
-  HIP_TRY(c, c->partial2.ensure((size_t)M * grid * 8), "alloc partials");
-  HIP_TRY(c, c->ctr_r.ensure(sizeof(Counters)), "alloc counters");
-  HIP_TRY(c, c->gbuf.ensure((size_t)M * 8), "alloc dE");
-  HIP_TRY(c, launch_mu_init(c->st, c->sigma.as<double>(), n, 2.0 / norm2, E, c->mu.as<double>(), c->stream), "mu init");
-  // Recompute view: same keys and hash, amplitudes in a segment buffer,
-  // separate counters with capacity checks off (no key is ever appended:
-  // every key the recomputation can reach was stored by the forward run).
-  DeviceState rv = c->st;
-  rv.cap = n;
-  rv.ctr = c->ctr_r.as<Counters>();
-  Counters hr;
-  std::memset(&hr, 0, sizeof(hr));
-  hr.n = n;
-  hr.alive = 0;
-  for (int j = nseg - 1; j >= 0; --j) {
-    const int64_t g_lo = (int64_t)j * seg;
-    const int64_t g_hi = std::min<int64_t>(M, g_lo + seg);
-    const int len = (int)(g_hi - g_lo);
-    double* S = c->seg_states.as<double>();
-    HIP_TRY(c, launch_restore(S, c->ckpt[j].as<double>(), c->ckpt_n.as<u64>() + j, n, c->stream), "restore");
-    HIP_TRY(c, hipMemcpyAsync(c->ctr_r.p, &hr, sizeof(hr), hipMemcpyHostToDevice, c->stream), "counters");
-    for (int t = 1; t < len; ++t) {
-      double* dst = S + (size_t)t * n;
-      HIP_TRY(c, hipMemcpyAsync(dst, S + (size_t)(t - 1) * n, n * 8, hipMemcpyDeviceToDevice, c->stream), "copy state");
-      rv.amps = dst;
-      const int64_t g = g_lo + t - 1;
-      HIP_TRY(c, launch_gate(rv, c->ops_host[c->a_ops[g]], c->a_c[g], c->a_s[g], c->a_eps, nullptr, 0,
-                             (unsigned)g, c->sector, grid, c->stream), "recompute gate");
+  } else {
+    // Per segment: restore the checkpoint into a working copy, replay the
+    // segment's gates logging their active pairs, then walk the logs back.
+    HIP_TRY(c, c->partial2.ensure((size_t)M * grid * 8), "alloc partials");
+    HIP_TRY(c, c->work.ensure(n * 8), "alloc working amplitudes");
+    HIP_TRY(c, c->ctr_r.ensure((size_t)seg * sizeof(u64)), "alloc log counters");
+    double* W = c->work.as<double>();
+    u64* lc = c->ctr_r.as<u64>();
+    for (int j = nseg - 1; j >= 0; --j) {
+      const int64_t g_lo = (int64_t)j * seg;
+      const int64_t g_hi = std::min<int64_t>(M, g_lo + seg);
+      const int len = (int)(g_hi - g_lo);
+      HIP_TRY(c, launch_restore(W, c->ckpt[j].as<double>(), c->ckpt_n.as<u64>() + j, n, c->stream), "restore");
+      HIP_TRY(c, hipMemsetAsync(lc, 0, (size_t)len * sizeof(u64), c->stream), "zero log counters");
+      for (int t = 0; t < len; ++t) {
+        const int64_t g = g_lo + t;
+        TIMED(c, SWCS_K_GATE_REPLAY, launch_gate_replay(c->st, W, n, c->ops_host[c->a_ops[g]], c->a_c[g], c->a_s[g],
+                                      c->a_eps, logs + (size_t)t * n, lc + t, grid, c->stream), "replay");
+      }
+      for (int t = len - 1; t >= 0; --t) {
+        const int64_t g = g_lo + t;
+        TIMED(c, SWCS_K_ADJOINT_REC, launch_adjoint_rec(logs + (size_t)t * n, lc + t, c->mu.as<double>(), c->a_c[g], c->a_s[g],
+                                      c->partial2.as<double>() + (size_t)g * grid, grid, c->stream), "reverse");
+      }
     }
-    for (int t = len - 1; t >= 0; --t) {
-      const int64_t g = g_lo + t;
-      HIP_TRY(c, launch_adjoint_step(c->st, c->ops_host[c->a_ops[g]], c->a_c[g], c->a_s[g],
-                                     S + (size_t)t * n, c->mu.as<double>(),
-                                     c->partial2.as<double>() + (size_t)g * grid, n, grid, c->stream), "adjoint step");
-    }
+    HIP_TRY(c, launch_reduce_partials(c->partial2.as<double>(), grid, grid, (int)M, c->gbuf.as<double>(), c->stream), "reduce");
   }
-  HIP_TRY(c, launch_reduce_partials(c->partial2.as<double>(), grid, grid, (int)M, c->gbuf.as<double>(), c->stream), "reduce");
   HIP_TRY(c, hipMemcpyAsync(dE, c->gbuf.p, (size_t)M * 8, hipMemcpyDeviceToHost, c->stream), "copy dE");
-  Counters hr2 = read_counters(c, &e);  // synchronizes
+  double nn_host[2];
+  HIP_TRY(c, hipMemcpyAsync(nn_host, nn, 16, hipMemcpyDeviceToHost, c->stream), "copy energy");
+  Counters hchk = read_counters(c, &e);  // synchronizes
   if (e != hipSuccess) return hip_fail(c, e, "sync");
-  Counters chk;
-  HIP_TRY(c, hipMemcpy(&chk, c->ctr_r.p, sizeof(chk), hipMemcpyDeviceToHost), "read recompute counters");
-  if (chk.n != n || (chk.flags & kFlagOverflow))
-    return fail(c, SWCS_E_DEVICE, "recomputation diverged from the forward run");
-  (void)hr2;
+  if (hchk.flags & kFlagOverflow) return fail(c, SWCS_E_DEVICE, "recomputation diverged from the forward run");
+  if (E_out) *E_out = nn_host[0] / nn_host[1];
   return SWCS_OK;
 }
 
@@ -942,7 +1024,7 @@ int swcs_gate_sizes(swcs_ctx* c, int64_t* n_in, int64_t M) {
   if (M != c->last_M) return fail(c, SWCS_E_INVALID, "M differs from the last apply call");
   if (M == 0) return SWCS_OK;
   if (!n_in) return fail(c, SWCS_E_INVALID, "null n_in");
-  hipSetDevice(c->device);
+  HIP_TRY(c, hipSetDevice(c->device), "hipSetDevice");
   HIP_TRY(c, hipMemcpyAsync(n_in, c->gate_n_in.p, (size_t)M * 8, hipMemcpyDeviceToHost, c->stream), "copy");
   HIP_TRY(c, hipStreamSynchronize(c->stream), "sync");
   return SWCS_OK;
@@ -961,9 +1043,9 @@ int swcs_occupations(swcs_ctx* c, double* n_out) {
   if (!c) return SWCS_E_INVALID;
   if (!c->have_state) return fail(c, SWCS_E_STATE, "no current state");
   if (!n_out) return fail(c, SWCS_E_INVALID, "null n_out");
-  hipSetDevice(c->device);
+  HIP_TRY(c, hipSetDevice(c->device), "hipSetDevice");
   hipError_t e;
-  Counters h = read_counters(c, &e);
+  Counters h = get_counters(c, &e);
   if (e != hipSuccess) return hip_fail(c, e, "read counters");
   int r = occupations_device(c, h.n);
   if (r) return r;
@@ -971,6 +1053,32 @@ int swcs_occupations(swcs_ctx* c, double* n_out) {
   HIP_TRY(c, hipMemcpyAsync(tmp.data(), c->occ.p, tmp.size() * 8, hipMemcpyDeviceToHost, c->stream), "copy");
   HIP_TRY(c, hipStreamSynchronize(c->stream), "sync");
   for (int P = 0; P < c->nso; ++P) n_out[P] = tmp[(size_t)P] / tmp[(size_t)c->nso];
+  return SWCS_OK;
+}
+
+int swcs_timer_start(swcs_ctx* c, int kernel_id) {
+  if (!c) return SWCS_E_INVALID;
+  if (kernel_id < SWCS_K_CHAIN_LDS || kernel_id > SWCS_K_CONTRACT_OPS)
+    return fail(c, SWCS_E_INVALID, "unknown kernel id");
+  c->timer_kernel = kernel_id;
+  c->ev_used = 0;
+  return SWCS_OK;
+}
+
+int swcs_timer_stop(swcs_ctx* c, int64_t* launches, double* total_ms) {
+  if (!c) return SWCS_E_INVALID;
+  HIP_TRY(c, hipSetDevice(c->device), "hipSetDevice");
+  HIP_TRY(c, hipStreamSynchronize(c->stream), "sync");
+  double tot = 0.0;
+  for (size_t i = 0; i < c->ev_used; ++i) {
+    float ms = 0.0f;
+    HIP_TRY(c, hipEventElapsedTime(&ms, c->ev_start[i], c->ev_stop[i]), "elapsed");
+    tot += ms;
+  }
+  if (launches) *launches = (int64_t)c->ev_used;
+  if (total_ms) *total_ms = tot;
+  c->timer_kernel = 0;
+  c->ev_used = 0;
   return SWCS_OK;
 }
 
@@ -983,9 +1091,9 @@ int swcs_features(swcs_ctx* c, const float* d_prev_absg, const float* d_age, con
   if (r) return r;
   if (!c->have_state) return fail(c, SWCS_E_STATE, "no current state");
   if (!d_prev_absg || !d_age || !d_count || !d_feat) return fail(c, SWCS_E_INVALID, "null device pointer");
-  hipSetDevice(c->device);
+  HIP_TRY(c, hipSetDevice(c->device), "hipSetDevice");
   hipError_t e;
-  Counters h = read_counters(c, &e);
+  Counters h = get_counters(c, &e);
   if (e != hipSuccess) return hip_fail(c, e, "read counters");
   r = occupations_device(c, h.n);
   if (r) return r;
@@ -998,7 +1106,7 @@ int swcs_mlp_forward(swcs_ctx* c, const float* d_W, const float* d_x, int64_t B,
                      float* d_act) {
   if (!c) return SWCS_E_INVALID;
   if (B < 0 || (B > 0 && (!d_W || !d_x || !d_y))) return fail(c, SWCS_E_INVALID, "bad mlp arguments");
-  hipSetDevice(c->device);
+  HIP_TRY(c, hipSetDevice(c->device), "hipSetDevice");
   HIP_TRY(c, launch_mlp_forward(d_W, d_x, B, d_y, d_act, c->stream), "mlp forward");
   return SWCS_OK;
 }
@@ -1008,7 +1116,7 @@ int swcs_mlp_backward(swcs_ctx* c, const float* d_W, const float* d_x, const flo
   if (!c) return SWCS_E_INVALID;
   if (B < 0 || !d_W || !d_dW || (B > 0 && (!d_x || !d_act || !d_dy)))
     return fail(c, SWCS_E_INVALID, "bad mlp arguments");
-  hipSetDevice(c->device);
+  HIP_TRY(c, hipSetDevice(c->device), "hipSetDevice");
   const long long rows = std::max<long long>(1, mlp_backward_partial_rows(B));
   HIP_TRY(c, c->mlp_partial.ensure((size_t)rows * kMlpParams * 4), "alloc partial");
   HIP_TRY(c, launch_mlp_backward(d_W, d_x, d_act, d_dy, B, d_dW, c->mlp_partial.as<float>(), rows,
@@ -1019,7 +1127,7 @@ int swcs_mlp_backward(swcs_ctx* c, const float* d_W, const float* d_x, const flo
 int swcs_mse(swcs_ctx* c, const float* d_y, const float* d_t, int64_t B, float* d_dy, float* d_loss) {
   if (!c) return SWCS_E_INVALID;
   if (B <= 0 || !d_y || !d_t || !d_dy || !d_loss) return fail(c, SWCS_E_INVALID, "bad mse arguments");
-  hipSetDevice(c->device);
+  HIP_TRY(c, hipSetDevice(c->device), "hipSetDevice");
   HIP_TRY(c, launch_mse(d_y, d_t, B, d_dy, d_loss, c->stream), "mse");
   return SWCS_OK;
 }
@@ -1029,7 +1137,7 @@ int swcs_adam_step(swcs_ctx* c, float* d_W, float* d_m, float* d_v, const float*
   if (!c) return SWCS_E_INVALID;
   if (P <= 0 || !d_W || !d_m || !d_v || !d_dW || step < 1 || !(b1 >= 0 && b1 < 1) || !(b2 >= 0 && b2 < 1))
     return fail(c, SWCS_E_INVALID, "bad adam arguments");
-  hipSetDevice(c->device);
+  HIP_TRY(c, hipSetDevice(c->device), "hipSetDevice");
   HIP_TRY(c, launch_adam(d_W, d_m, d_v, d_dW, P, lr, b1, b2, eps, step, c->stream), "adam");
   return SWCS_OK;
 }
@@ -1040,7 +1148,7 @@ int swcs_select(swcs_ctx* c, const float* d_score, const uint32_t* d_rand, int64
   if (K <= 0 || K > ((int64_t)1 << 31) - 1 || n_top < 0 || n_rand < 0 || n_top + n_rand > K ||
       !d_score || !d_idx || (n_rand > 0 && !d_rand))
     return fail(c, SWCS_E_INVALID, "bad select arguments");
-  hipSetDevice(c->device);
+  HIP_TRY(c, hipSetDevice(c->device), "hipSetDevice");
   const u64 need = select_scratch_elems(K);
   HIP_TRY(c, c->sel_scratch.ensure(need * 8), "alloc select scratch");
   HIP_TRY(c, launch_select(d_score, d_rand, K, n_top, n_rand, d_idx, c->sel_scratch.as<u64>(), need,

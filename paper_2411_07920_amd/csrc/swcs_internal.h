@@ -273,6 +273,7 @@ struct DeviceState {
 };
 
 // Launch wrappers (defined in the .hip files).  All enqueue on `stream`.
+struct PairRec;
 hipError_t launch_hash_clear(HashSlot* tab, u64 slots, hipStream_t stream);
 hipError_t launch_hash_build(const DeviceState& st, u64 n, hipStream_t stream);
 hipError_t launch_gate(const DeviceState& st, const OpDesc& op, double c, double sn, double eps,
@@ -280,17 +281,21 @@ hipError_t launch_gate(const DeviceState& st, const OpDesc& op, double c, double
                        hipStream_t stream);
 hipError_t launch_prune_all(const DeviceState& st, double eps, int grid, hipStream_t stream);
 hipError_t launch_hash_build_dev(const DeviceState& st, int grid, hipStream_t stream);
+hipError_t launch_reset_reference(const DeviceState& st, u64 ref, hipStream_t stream);
 int lds_chain_capacity();
 hipError_t launch_chain_lds(const DeviceState& st, const GateDesc* gates, int g0, int M, double eps,
                             int prune_first, double* const* ckpt, u64* ckpt_n, int seg,
                             u64* gate_n_in, u64 max_keys, hipStream_t stream);
+int lds_adjoint_max_segment();
 hipError_t launch_adjoint_lds(const u64* keys, unsigned n, const GateDesc* gates, int M, int seg,
                               double eps, const double* const* ckpt, const u64* ckpt_n,
-                              const double* mu_init, double* S, double* dE, unsigned* flags,
+                              const double* mu_init, PairRec* logbuf, double* dE, unsigned* flags,
                               hipStream_t stream);
-hipError_t launch_adjoint_step(const DeviceState& st, const OpDesc& op, double c, double sn,
-                               const double* amps_prev, double* mu, double* partial, u64 n_total,
-                               int grid, hipStream_t stream);
+hipError_t launch_gate_replay(const DeviceState& st, double* amps, u64 n, const OpDesc& op,
+                             double c, double sn, double eps, PairRec* log, u64* log_count, int grid,
+                             hipStream_t stream);
+hipError_t launch_adjoint_rec(const PairRec* log, const u64* log_count, double* mu, double c,
+                              double sn, double* partial, int grid, hipStream_t stream);
 hipError_t launch_ckpt_save(const DeviceState& st, double* dst, u64* dst_n, int grid,
                             hipStream_t stream);
 hipError_t launch_restore(double* dst, const double* src, const u64* n_src, u64 n_total,
@@ -299,7 +304,7 @@ hipError_t launch_mark_dead_range(double* amps, u64 lo, u64 hi, hipStream_t stre
 hipError_t launch_sigma_proj(const DeviceState& st, const Ints& I, const ExcSpace& E, u64 n,
                              double* sigma, double* partial_num, double* partial_norm, int grid,
                              hipStream_t stream);
-hipError_t launch_mu_init(const DeviceState& st, const double* sigma, u64 n, double scale, double E,
+hipError_t launch_mu_init(const DeviceState& st, const double* sigma, u64 n, const double* nn,
                           double* mu, hipStream_t stream);
 hipError_t launch_reduce_partials(const double* partial, int count, int stride, int nvec,
                                   double* out, hipStream_t stream);
@@ -314,10 +319,16 @@ hipError_t launch_query_set(const DeviceState& st, const ExcSpace& E, int n_spat
                             const HashSlot* opmap, u64 omask, const unsigned char* selected,
                             AccSlot* tab, u64 tmask, int count_only, u64* counter, int grid,
                             hipStream_t stream);
+hipError_t launch_query_ops(const DeviceState& st, u64 n, const OpDesc* ops, const int* subset,
+                            long long n_sub, AccSlot* tab, u64 tmask, int count_only, u64* counter,
+                            hipStream_t stream);
+hipError_t launch_contract_ops(const DeviceState& st, u64 n, const OpDesc* ops, const int* subset,
+                               long long n_sub, const AccSlot* tab, u64 tmask, double* gslot,
+                               hipStream_t stream);
 hipError_t launch_sigma_push_into(const DeviceState& st, const Ints& I, const ExcSpace& E, u64 n,
                                   AccSlot* tab, u64 tmask, int grid, hipStream_t stream);
-hipError_t launch_gather_scaled(const double* gacc, const int* subset, long long count, double scale,
-                                double* out, hipStream_t stream);
+hipError_t launch_gather_scaled(const double* gacc, const int* subset, long long count,
+                                const double* norm2, double* out, hipStream_t stream);
 hipError_t launch_mark_selected(const int* subset, long long count, unsigned char* selected,
                                 hipStream_t stream);
 hipError_t launch_occupations(const DeviceState& st, u64 n, int nso, double* partial, int grid,

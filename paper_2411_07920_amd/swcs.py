@@ -23,6 +23,9 @@ SWCS_E_OOM = -3
 SWCS_E_CAPACITY = -4
 SWCS_E_DEVICE = -5
 SWCS_E_UNSUPPORTED = -6
+KERNELS = {"chain_lds": 1, "gate": 2, "sigma_proj": 3, "sigma_push": 4, "pool_contract": 5,
+           "adjoint_lds": 6, "gate_replay": 7, "adjoint_rec": 8, "sigma_push_into": 9,
+           "contract_ops": 10}
 _NAMES = {0: "SWCS_OK", -1: "SWCS_E_INVALID", -2: "SWCS_E_STATE", -3: "SWCS_E_OOM",
           -4: "SWCS_E_CAPACITY", -5: "SWCS_E_DEVICE", -6: "SWCS_E_UNSUPPORTED"}
 
@@ -65,6 +68,8 @@ SIGNATURES = {
     "swcs_param_gradients": (ctypes.c_int, [_vp, _dp, _dp]),
     "swcs_gate_sizes": (ctypes.c_int, [_vp, _i64p, _i64]),
     "swcs_occupations": (ctypes.c_int, [_vp, _dp]),
+    "swcs_timer_start": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "swcs_timer_stop": (ctypes.c_int, [_vp, _i64p, _dp]),
     "swcs_mlp_param_count": (ctypes.c_int64, []),
     "swcs_features": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "swcs_mlp_forward": (ctypes.c_int, [_vp, _vp, _vp, _i64, _vp, _vp]),
@@ -277,6 +282,17 @@ class Context:
         out = np.zeros(2 * self.n)
         self._check(self._lib.swcs_occupations(self._h, _ptr(out, ctypes.c_double)))
         return out
+
+    # -- measurement ----------------------------------------------------
+    def timer_start(self, kernel: str):
+        self._check(self._lib.swcs_timer_start(self._h, KERNELS[kernel]))
+
+    def timer_stop(self):
+        """(launches, total_ms) of the kernel timed since timer_start."""
+        n = ctypes.c_int64()
+        ms = ctypes.c_double()
+        self._check(self._lib.swcs_timer_stop(self._h, ctypes.byref(n), ctypes.byref(ms)))
+        return int(n.value), float(ms.value)
 
     # -- screener (device tensors) --------------------------------------
     def features(self, prev_absg, age, count, out):
