@@ -52,6 +52,9 @@ def parse():
                     help="instead of the step benchmark: ADAPT iteration time, screened vs "
                          "full pool, on this workload (prints its own JSON line)")
     ap.add_argument("--iters", type=int, default=150)
+    ap.add_argument("--micro", type=int, default=0,
+                    help="instead of the step benchmark: gate and sigma kernels on a synthetic "
+                         "state of this many determinants (52 spin-orbitals, 16 electrons)")
     return ap.parse_args()
 
 
@@ -342,6 +345,57 @@ def adapt_bench(args):
     print(json.dumps(out))
 
 
+def micro_bench(args):
+    """Kernel rates on a structure-free synthetic state in the 52-spin-orbital,
+    16-electron sector (uniform alpha and beta strings, log-uniform |c|)."""
+    import torch
+    from paper_2411_07920_amd import swcs
+    from paper_2411_07920_amd.inputs import draw_synthetic_state
+
+    torch.cuda.set_device(0)
+    wl = Workload("c5")
+    c = wl.c
+    N = args.micro
+    keys, amps = draw_synthetic_state(c.n, wl.na, wl.na, N, 4005)
+    ctx = swcs.make_context(c.n, wl.na, wl.na, wl.h, wl.eri, wl.pool, wl.ref,
+                            stream=torch.cuda.current_stream())
+    rng = np.random.default_rng(4005)
+    singles = np.flatnonzero(wl.pool[:, 2] < 0)
+    doubles = np.flatnonzero(wl.pool[:, 2] >= 0)
+    ops = np.concatenate([rng.choice(doubles, 16), rng.choice(singles, 4)]).astype(np.int32)
+    theta = rng.uniform(-0.3, 0.3, len(ops))
+    out = {"metric": "kernel rates on a synthetic state", "n_det": N,
+           "workload": "52 spin-orbitals, 16 electrons, uniform sector sample, |c| in [1e-8, 1e-2]"}
+    # Gates in HBM (eps = 0: every created partner is kept).
+    reps = 3
+    tot_ms, launches, n_in_sum = 0.0, 0, 0
+    for _ in range(reps):
+        ctx.set_state(keys, amps)
+        ctx.timer_start("gate")
+        ctx.apply_gates(ops, theta, 0.0)
+        l, ms = ctx.timer_stop()
+        n_in_sum += int(ctx.gate_sizes(len(ops)).sum())
+        tot_ms += ms
+        launches += l
+    us = 1e3 * tot_ms / launches
+    bytes_per_launch = 8.0 * n_in_sum / launches
+    out["gate"] = {"us_per_launch": us, "dets_per_s": (n_in_sum / launches) / (us * 1e-6),
+                   "algorithmic_GBps": bytes_per_launch / (us * 1e-6) / 1e9,
+                   "frac_hbm": bytes_per_launch / (us * 1e-6) / 1e9 / HBM_PEAK_GBS}
+    if N <= 2_000_000:
+        ctx.set_state(keys, amps)
+        ctx.timer_start("sigma_proj")
+        ctx.energy()
+        l, ms = ctx.timer_stop()
+        from math import comb
+        nv = c.n - wl.na
+        C = 2 * wl.na * nv + 2 * comb(wl.na, 2) * comb(nv, 2) + wl.na * wl.na * nv * nv
+        out["sigma_proj"] = {"ms": ms, "rows_per_s": N / (ms * 1e-3),
+                             "probes_per_s": N * C / (ms * 1e-3), "connections_per_row": C}
+    ctx.close()
+    print(json.dumps(out))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -350,6 +404,9 @@ def main():
         sys.exit(2)
     if args.adapt:
         adapt_bench(args)
+        return
+    if args.micro:
+        micro_bench(args)
         return
     wl = Workload(args.workload)
     r = gpu_bench(args, wl)

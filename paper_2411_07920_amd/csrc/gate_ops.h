@@ -144,6 +144,60 @@ __device__ inline PairRec make_rec(const GateOut& o) {
   return r;
 }
 
+// ---------------------------------------------------------------- N_CUT
+// Order used by N_CUT pruning: larger |c| first, ties broken by the smaller
+// key.  Encoded as the 128-bit value (bits of |c|, ~key), compared as
+// unsigned; "keep the ncut largest" keeps the entries whose value is >= the
+// ncut-th largest.  Found by an MSB-first radix select over 16 digits of 8 bits.
+__device__ inline void ncut_value(double a, u64 key, u64* hi, u64* lo) {
+  *hi = (u64)__double_as_longlong(fabs(a));
+  *lo = ~key;
+}
+
+__device__ inline unsigned ncut_digit(u64 hi, u64 lo, int d) {
+  return d < 8 ? (unsigned)((hi >> (56 - 8 * d)) & 255u) : (unsigned)((lo >> (120 - 8 * d)) & 255u);
+}
+
+struct NcutState {
+  u64 phi, plo, mhi, mlo;  // prefix of the selected value and its known-bit mask
+  unsigned k;              // rank still to find inside the current prefix
+  unsigned skip;           // 1: keep everything (fewer than ncut alive, or chain stopped)
+  unsigned pad[2];
+  unsigned hist[256];
+};
+
+__device__ inline bool ncut_matches(const NcutState& st, u64 hi, u64 lo) {
+  return ((hi & st.mhi) == st.phi) && ((lo & st.mlo) == st.plo);
+}
+
+// After the digit histogram of pass d: choose the digit holding rank k
+// (counted from the largest) and extend the prefix; sets skip when fewer
+// than k values remain (then nothing is pruned).
+__device__ inline void ncut_pick(NcutState& st, int d) {
+  unsigned cum = 0;
+  int v = -1;
+  for (int x = 255; x >= 0; --x) {
+    const unsigned h = st.hist[x];
+    if (cum + h >= st.k) {
+      v = x;
+      break;
+    }
+    cum += h;
+  }
+  if (v < 0) {
+    st.skip = 1;
+    return;
+  }
+  st.k -= cum;
+  if (d < 8) {
+    st.phi |= (u64)v << (56 - 8 * d);
+    st.mhi |= 255ULL << (56 - 8 * d);
+  } else {
+    st.plo |= (u64)v << (120 - 8 * d);
+    st.mlo |= 255ULL << (120 - 8 * d);
+  }
+}
+
 // ---------------------------------------------------------------- stores
 struct GlobalStore {
   u64* keys;

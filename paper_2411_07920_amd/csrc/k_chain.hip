@@ -23,6 +23,55 @@ __device__ inline double block_sum_1024(double v, double* wsum) {
   return r;  // valid in thread 0
 }
 
+// Keep only the ncut alive entries of amps[0, n) that come first in the N_CUT
+// order (gate_ops.h); the rest are marked dead.  Called by all threads of
+// the block; returns the number of entries dropped (valid in every thread).
+__device__ inline unsigned lds_ncut(double* amps, const u64* keys, unsigned n, unsigned ncut,
+                                    NcutState& st) {
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    st.phi = st.plo = st.mhi = st.mlo = 0;
+    st.k = ncut;
+    st.skip = 0;
+    st.pad[0] = 0;
+  }
+  for (int d = 0; d < 16; ++d) {
+    if (tid < 256) st.hist[tid] = 0;
+    __syncthreads();
+    if (st.skip) break;
+    for (unsigned i = tid; i < n; i += kChainThreads) {
+      const double a = amps[i];
+      if (is_dead(a)) continue;
+      u64 hi, lo;
+      ncut_value(a, keys[i], &hi, &lo);
+      if (ncut_matches(st, hi, lo)) atomicAdd(&st.hist[ncut_digit(hi, lo, d)], 1u);
+    }
+    __syncthreads();
+    if (tid == 0) ncut_pick(st, d);
+    __syncthreads();
+  }
+  if (st.skip) return 0;
+  // st.phi / st.plo is now the ncut-th largest value; drop everything below.
+  unsigned dropped = 0;
+  for (unsigned i = tid; i < n; i += kChainThreads) {
+    const double a = amps[i];
+    if (is_dead(a)) continue;
+    u64 hi, lo;
+    ncut_value(a, keys[i], &hi, &lo);
+    if (hi < st.phi || (hi == st.phi && lo < st.plo)) {
+      amps[i] = dead_value();
+      ++dropped;
+    }
+  }
+  if (tid == 0) st.pad[0] = 0;
+  __syncthreads();
+  if (dropped) atomicAdd(&st.pad[0], dropped);
+  __syncthreads();
+  const unsigned tot = st.pad[0];
+  __syncthreads();
+  return tot;
+}
+
 // Forward chain of gates [g0, M) on the state held in keys / amps (HBM),
 // moved into LDS for the duration.  Checkpoints (amplitudes before gate g
 // for g % seg == 0) and the per-gate input sizes are written to HBM.  If a
@@ -33,7 +82,8 @@ __global__ void __launch_bounds__(kChainThreads)
 k_chain_lds(u64* __restrict__ keys, double* __restrict__ amps, Counters* __restrict__ ctr,
             const GateDesc* __restrict__ gates, int g0, int M, double eps, int prune_first,
             double* const* __restrict__ ckpt, u64* __restrict__ ckpt_n, int seg,
-            u64* __restrict__ gate_n_in, u64 max_keys) {
+            u64* __restrict__ gate_n_in, u64 max_keys, unsigned ncut) {
+  __shared__ NcutState nst;
   __shared__ u64 skeys[CAP];
   __shared__ double samps[CAP];
   __shared__ int sslots[2 * CAP];
@@ -101,6 +151,11 @@ k_chain_lds(u64* __restrict__ keys, double* __restrict__ amps, Counters* __restr
       s_dalive = 0;
     }
     __syncthreads();
+    if (ncut && s_alive > ncut) {
+      const unsigned dropped = lds_ncut(samps, skeys, s_n, ncut, nst);
+      if (tid == 0) s_alive -= dropped;
+      __syncthreads();
+    }
     if (g == 0 && prune_first) {
       // Entries of a caller-supplied starting state that the first gate did
       // not touch have not been tested against eps yet.
@@ -146,7 +201,9 @@ __global__ void __launch_bounds__(kChainThreads)
 k_adjoint_lds(const u64* __restrict__ keys, unsigned n, const GateDesc* __restrict__ gates, int M,
               int seg, double eps, const double* const* __restrict__ ckpt,
               const u64* __restrict__ ckpt_n, const double* __restrict__ mu_init,
-              PairRec* __restrict__ logbuf, double* __restrict__ dE, unsigned* __restrict__ flags) {
+              PairRec* __restrict__ logbuf, double* __restrict__ dE, unsigned* __restrict__ flags,
+              unsigned ncut) {
+  __shared__ NcutState nst;
   __shared__ u64 skeys[CAP];
   __shared__ double sW[CAP];
   __shared__ double smu[CAP];
@@ -183,6 +240,7 @@ k_adjoint_lds(const u64* __restrict__ keys, unsigned n, const GateDesc* __restri
         if (o.active) lg[atomicAdd(&cnt[t], 1u)] = make_rec(o);
       }
       __syncthreads();
+      if (ncut) lds_ncut(sW, skeys, n, ncut, nst);
     }
     for (int t = len - 1; t >= 0; --t) {
       const GateDesc gd = gates[g_lo + t];
@@ -203,10 +261,10 @@ int lds_chain_capacity() { return kLdsCap; }
 
 hipError_t launch_chain_lds(const DeviceState& st, const GateDesc* gates, int g0, int M, double eps,
                             int prune_first, double* const* ckpt, u64* ckpt_n, int seg,
-                            u64* gate_n_in, u64 max_keys, hipStream_t stream) {
+                            u64* gate_n_in, u64 max_keys, unsigned ncut, hipStream_t stream) {
   hipLaunchKernelGGL(k_chain_lds<kLdsCap>, dim3(1), dim3(kChainThreads), 0, stream, st.keys,
                      st.amps, st.ctr, gates, g0, M, eps, prune_first, ckpt, ckpt_n, seg, gate_n_in,
-                     max_keys);
+                     max_keys, ncut);
   return hipGetLastError();
 }
 
@@ -215,10 +273,10 @@ int lds_adjoint_max_segment() { return kMaxSeg; }
 hipError_t launch_adjoint_lds(const u64* keys, unsigned n, const GateDesc* gates, int M, int seg,
                               double eps, const double* const* ckpt, const u64* ckpt_n,
                               const double* mu_init, PairRec* logbuf, double* dE, unsigned* flags,
-                              hipStream_t stream) {
+                              unsigned ncut, hipStream_t stream) {
   if (seg > kMaxSeg) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_adjoint_lds<kLdsCap>, dim3(1), dim3(kChainThreads), 0, stream, keys, n, gates,
-                     M, seg, eps, ckpt, ckpt_n, mu_init, logbuf, dE, flags);
+                     M, seg, eps, ckpt, ckpt_n, mu_init, logbuf, dE, flags, ncut);
   return hipGetLastError();
 }
 

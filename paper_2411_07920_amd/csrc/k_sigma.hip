@@ -3,10 +3,10 @@
 // contraction, occupations and deterministic reductions.
 //
 // Matrix elements follow the Slater-Condon rules (Szabo & Ostlund, cited in
-// Sec. III) for H = sum h a+a + 1/2 sum (pq|rs) a+a+aa.  Each determinant's
-// spin-conserving singles and doubles are enumerated by a flat connection
-// index; the occupied / virtual lists and a pair-unranking table are staged
-// in LDS once per determinant so every lane decodes its connections from LDS.
+// Sec. III) for H = sum h a+a + 1/2 sum (pq|rs) a+a+aa.  One block handles
+// one determinant at a time: its occupied / virtual lists and the hole- and
+// particle-set tables of its spin-conserving singles and doubles are staged
+// in LDS, and the lanes walk the connections from those tables.
 #include "swcs_internal.h"
 
 namespace swcs {
@@ -42,45 +42,132 @@ __device__ inline void build_lists_shared(u64 D, int n, SigShared& S) {
   }
 }
 
-// Decode connection c (0 <= c < E.total) into holes h0 < h1, particles p0 < p1.
-__device__ inline int decode_shared(const ExcSpace& E, const SigShared& S, int c, int* h0, int* h1,
-                                    int* p0, int* p1) {
-  if (c < (int)E.s_a) {
-    const int i = c / E.va, a = c - (c / E.va) * E.va;
-    *h0 = S.occ_a[i]; *p0 = S.vir_a[a];
-    return 1;
+// Connection tables of one determinant, in LDS: the hole sets and particle
+// sets of the five spin-conserving classes (alpha single, beta single,
+// alpha-alpha double, beta-beta double, alpha-beta double) as bit masks plus
+// their sorted spin-orbital indices.  A connection is (hole set h, particle
+// set p) of one class, X = D ^ hmask[h] ^ pmask[p]; the lanes walk the
+// (h, p) grid of each class with a stride of the block size, stepping the
+// indices incrementally (one division per class and lane).
+struct ConnTables {
+  u64* hmask;  // arrays in dynamic LDS, sized by the launcher (conn_tables_bytes)
+  u64* pmask;
+  unsigned char *h0, *h1, *p0, *p1;
+  int hbeg[5], nh[5], pbeg[5], np[5];
+};
+
+__host__ __device__ inline void conn_set_counts(const ExcSpace& E, int* NH, int* NP) {
+  const int na = E.na, nb = E.nb, va = E.va, vb = E.vb;
+  *NH = na + nb + na * (na - 1) / 2 + nb * (nb - 1) / 2 + na * nb;
+  *NP = va + vb + va * (va - 1) / 2 + vb * (vb - 1) / 2 + va * vb;
+}
+
+size_t conn_tables_bytes(const ExcSpace& E) {
+  int NH, NP;
+  conn_set_counts(E, &NH, &NP);
+  return (size_t)(NH + NP) * 10;
+}
+
+// Carve the tables out of the dynamic LDS buffer.
+__device__ inline void attach_conn_tables(ConnTables& T, unsigned char* dyn, const ExcSpace& E) {
+  int NH, NP;
+  conn_set_counts(E, &NH, &NP);
+  T.hmask = (u64*)dyn;
+  T.pmask = T.hmask + NH;
+  T.h0 = (unsigned char*)(T.pmask + NP);
+  T.h1 = T.h0 + NH;
+  T.p0 = T.h1 + NH;
+  T.p1 = T.p0 + NP;
+}
+
+__device__ inline void build_conn_tables(const SigShared& S, const ExcSpace& E, ConnTables& T) {
+  const int na = E.na, nb = E.nb, va = E.va, vb = E.vb;
+  if (threadIdx.x == 0) {
+    int h = 0, p = 0;
+    const int nhs[5] = {na, nb, na * (na - 1) / 2, nb * (nb - 1) / 2, na * nb};
+    const int nps[5] = {va, vb, va * (va - 1) / 2, vb * (vb - 1) / 2, va * vb};
+    for (int c = 0; c < 5; ++c) {
+      T.hbeg[c] = h;
+      T.nh[c] = nhs[c];
+      T.pbeg[c] = p;
+      T.np[c] = nps[c];
+      h += nhs[c];
+      p += nps[c];
+    }
   }
-  c -= (int)E.s_a;
-  if (c < (int)E.s_b) {
-    const int i = c / E.vb, a = c - (c / E.vb) * E.vb;
-    *h0 = S.occ_b[i]; *p0 = S.vir_b[a];
-    return 1;
+  __syncthreads();
+  const int tid = threadIdx.x;
+  // holes
+  for (int t = tid; t < na; t += blockDim.x) {
+    const int P = S.occ_a[t];
+    T.hmask[T.hbeg[0] + t] = 1ULL << P; T.h0[T.hbeg[0] + t] = P; T.h1[T.hbeg[0] + t] = P;
   }
-  c -= (int)E.s_b;
-  if (c < (int)E.d_aa) {
-    const int nv = E.va * (E.va - 1) / 2;
-    const int io = c / nv, iv = c - io * nv;
-    *h0 = S.occ_a[S.px[io]]; *h1 = S.occ_a[S.py[io]];
-    *p0 = S.vir_a[S.px[iv]]; *p1 = S.vir_a[S.py[iv]];
-    return 2;
+  for (int t = tid; t < nb; t += blockDim.x) {
+    const int P = S.occ_b[t];
+    T.hmask[T.hbeg[1] + t] = 1ULL << P; T.h0[T.hbeg[1] + t] = P; T.h1[T.hbeg[1] + t] = P;
   }
-  c -= (int)E.d_aa;
-  if (c < (int)E.d_bb) {
-    const int nv = E.vb * (E.vb - 1) / 2;
-    const int io = c / nv, iv = c - io * nv;
-    *h0 = S.occ_b[S.px[io]]; *h1 = S.occ_b[S.py[io]];
-    *p0 = S.vir_b[S.px[iv]]; *p1 = S.vir_b[S.py[iv]];
-    return 2;
+  for (int t = tid; t < T.nh[2]; t += blockDim.x) {
+    const int x = S.occ_a[S.px[t]], y = S.occ_a[S.py[t]];
+    T.hmask[T.hbeg[2] + t] = (1ULL << x) | (1ULL << y); T.h0[T.hbeg[2] + t] = x; T.h1[T.hbeg[2] + t] = y;
   }
-  c -= (int)E.d_bb;
-  const int vv = E.va * E.vb;
-  const int ij = c / vv, ab = c - ij * vv;
-  const int i = ij / E.nb, j = ij - i * E.nb;
-  const int a = ab / E.vb, b = ab - a * E.vb;
-  const int Ia = S.occ_a[i], Jb = S.occ_b[j], Aa = S.vir_a[a], Bb = S.vir_b[b];
-  *h0 = min(Ia, Jb); *h1 = max(Ia, Jb);
-  *p0 = min(Aa, Bb); *p1 = max(Aa, Bb);
-  return 2;
+  for (int t = tid; t < T.nh[3]; t += blockDim.x) {
+    const int x = S.occ_b[S.px[t]], y = S.occ_b[S.py[t]];
+    T.hmask[T.hbeg[3] + t] = (1ULL << x) | (1ULL << y); T.h0[T.hbeg[3] + t] = x; T.h1[T.hbeg[3] + t] = y;
+  }
+  for (int t = tid; t < T.nh[4]; t += blockDim.x) {
+    const int i = t / nb, j = t - (t / nb) * nb;
+    const int x = S.occ_a[i], y = S.occ_b[j];
+    T.hmask[T.hbeg[4] + t] = (1ULL << x) | (1ULL << y);
+    T.h0[T.hbeg[4] + t] = min(x, y); T.h1[T.hbeg[4] + t] = max(x, y);
+  }
+  // particles
+  for (int t = tid; t < va; t += blockDim.x) {
+    const int P = S.vir_a[t];
+    T.pmask[T.pbeg[0] + t] = 1ULL << P; T.p0[T.pbeg[0] + t] = P; T.p1[T.pbeg[0] + t] = P;
+  }
+  for (int t = tid; t < vb; t += blockDim.x) {
+    const int P = S.vir_b[t];
+    T.pmask[T.pbeg[1] + t] = 1ULL << P; T.p0[T.pbeg[1] + t] = P; T.p1[T.pbeg[1] + t] = P;
+  }
+  for (int t = tid; t < T.np[2]; t += blockDim.x) {
+    const int x = S.vir_a[S.px[t]], y = S.vir_a[S.py[t]];
+    T.pmask[T.pbeg[2] + t] = (1ULL << x) | (1ULL << y); T.p0[T.pbeg[2] + t] = x; T.p1[T.pbeg[2] + t] = y;
+  }
+  for (int t = tid; t < T.np[3]; t += blockDim.x) {
+    const int x = S.vir_b[S.px[t]], y = S.vir_b[S.py[t]];
+    T.pmask[T.pbeg[3] + t] = (1ULL << x) | (1ULL << y); T.p0[T.pbeg[3] + t] = x; T.p1[T.pbeg[3] + t] = y;
+  }
+  for (int t = tid; t < T.np[4]; t += blockDim.x) {
+    const int a = t / vb, b = t - (t / vb) * vb;
+    const int x = S.vir_a[a], y = S.vir_b[b];
+    T.pmask[T.pbeg[4] + t] = (1ULL << x) | (1ULL << y);
+    T.p0[T.pbeg[4] + t] = min(x, y); T.p1[T.pbeg[4] + t] = max(x, y);
+  }
+}
+
+// Calls f(X, nh, h0, h1, p0, p1) for every single (nh = 1) and double
+// (nh = 2) connection X of D assigned to this lane; holes h0 < h1 and
+// particles p0 < p1 are spin-orbital indices.
+template <class F>
+__device__ inline void for_each_connection(const ConnTables& T, u64 D, F&& f) {
+  for (int c = 0; c < 5; ++c) {
+    const int nh = T.nh[c], np = T.np[c];
+    if (nh == 0 || np == 0) continue;
+    const int hb = T.hbeg[c], pb = T.pbeg[c];
+    int hi = (int)threadIdx.x / np;
+    int pi = (int)threadIdx.x - hi * np;
+    const int nholes = c < 2 ? 1 : 2;
+    while (hi < nh) {
+      const int H = hb + hi, Pp = pb + pi;
+      const u64 X = D ^ T.hmask[H] ^ T.pmask[Pp];
+      f(X, nholes, (int)T.h0[H], (int)T.h1[H], (int)T.p0[Pp], (int)T.p1[Pp]);
+      pi += blockDim.x;
+      while (pi >= np) {
+        pi -= np;
+        ++hi;
+      }
+    }
+  }
 }
 
 __device__ inline double block_sum(double v, double* red) {
@@ -99,13 +186,16 @@ __device__ inline double block_sum(double v, double* red) {
 // (dead entries get 0), plus per-block partial sums of psi*sigma and psi^2.
 __global__ void __launch_bounds__(kSigBlock)
 k_sigma_proj(const u64* __restrict__ keys, const double* __restrict__ amps,
-             const HashSlot* __restrict__ hash, u64 hmask, Ints I, ExcSpace E, u64 n,
-             double* __restrict__ sigma, double* __restrict__ partial) {
+             const HashSlot* __restrict__ hash, u64 hmask, const unsigned* __restrict__ filt,
+             u64 fmask, Ints I, ExcSpace E, u64 n, double* __restrict__ sigma,
+             double* __restrict__ partial) {
   __shared__ SigShared S;
+  __shared__ ConnTables T;
+  extern __shared__ __align__(16) unsigned char conn_dyn[];
   __shared__ double red[kSigBlock];
   build_pair_table(S);
+  if (threadIdx.x == 0) attach_conn_tables(T, conn_dyn, E);
   double num = 0.0, nrm = 0.0;
-  const int C = (int)E.total;
   for (u64 d = blockIdx.x; d < n; d += gridDim.x) {
     const double psiD = amps[d];
     if (is_dead(psiD)) {
@@ -116,18 +206,17 @@ k_sigma_proj(const u64* __restrict__ keys, const double* __restrict__ amps,
     __syncthreads();
     build_lists_shared(D, I.n, S);
     __syncthreads();
+    build_conn_tables(S, E, T);
+    __syncthreads();
     double acc = 0.0;
-    for (int c = threadIdx.x; c < C; c += kSigBlock) {
-      int h0, h1 = 0, p0, p1 = 0;
-      const int nh = decode_shared(E, S, c, &h0, &h1, &p0, &p1);
-      u64 X = D ^ (1ULL << h0) ^ (1ULL << p0);
-      if (nh == 2) X ^= (1ULL << h1) ^ (1ULL << p1);
+    for_each_connection(T, D, [&](u64 X, int nh, int h0, int h1, int p0, int p1) {
+      if (!filter_maybe(filt, fmask, X)) return;
       const long long j = hash_find(hash, hmask, X);
-      if (j < 0) continue;
+      if (j < 0) return;
       const double psiX = amps[j];
-      if (is_dead(psiX)) continue;
+      if (is_dead(psiX)) return;
       acc += connection_element(I, D, nh, h0, h1, p0, p1) * psiX;
-    }
+    });
     if (threadIdx.x == 0) acc += diag_element(I, D) * psiD;
     const double sig = block_sum(acc, red);
     if (threadIdx.x == 0) {
@@ -154,8 +243,10 @@ k_sigma_push(const u64* __restrict__ keys, const double* __restrict__ amps, Ints
              u64 n, AccSlot* __restrict__ tab, u64 tmask, int nbatch, int batch,
              unsigned* __restrict__ flags) {
   __shared__ SigShared S;
+  __shared__ ConnTables T;
+  extern __shared__ __align__(16) unsigned char conn_dyn[];
   build_pair_table(S);
-  const int C = (int)E.total;
+  if (threadIdx.x == 0) attach_conn_tables(T, conn_dyn, E);
   for (u64 d = blockIdx.x; d < n; d += gridDim.x) {
     const double psiD = amps[d];
     if (is_dead(psiD)) continue;
@@ -163,17 +254,15 @@ k_sigma_push(const u64* __restrict__ keys, const double* __restrict__ amps, Ints
     __syncthreads();
     build_lists_shared(D, I.n, S);
     __syncthreads();
+    build_conn_tables(S, E, T);
+    __syncthreads();
     if (threadIdx.x == 0 && (nbatch == 1 || batch_of(D, nbatch) == batch))
       if (!acc_add(tab, tmask, D, diag_element(I, D) * psiD)) atomicOr(flags, kFlagOverflow);
-    for (int c = threadIdx.x; c < C; c += kSigBlock) {
-      int h0, h1 = 0, p0, p1 = 0;
-      const int nh = decode_shared(E, S, c, &h0, &h1, &p0, &p1);
-      u64 X = D ^ (1ULL << h0) ^ (1ULL << p0);
-      if (nh == 2) X ^= (1ULL << h1) ^ (1ULL << p1);
-      if (nbatch > 1 && batch_of(X, nbatch) != batch) continue;
+    for_each_connection(T, D, [&](u64 X, int nh, int h0, int h1, int p0, int p1) {
+      if (nbatch > 1 && batch_of(X, nbatch) != batch) return;
       if (!acc_add(tab, tmask, X, connection_element(I, D, nh, h0, h1, p0, p1) * psiD))
         atomicOr(flags, kFlagOverflow);
-    }
+    });
   }
 }
 
@@ -208,8 +297,10 @@ k_pool_contract_det(const u64* __restrict__ keys, const double* __restrict__ amp
                     const unsigned char* __restrict__ selected, const OpDesc* __restrict__ ops,
                     const AccSlot* __restrict__ tab, u64 tmask, double* __restrict__ gacc) {
   __shared__ SigShared S;
+  __shared__ ConnTables T;
+  extern __shared__ __align__(16) unsigned char conn_dyn[];
   build_pair_table(S);
-  const int C = (int)E.total;
+  if (threadIdx.x == 0) attach_conn_tables(T, conn_dyn, E);
   for (u64 d = blockIdx.x; d < n; d += gridDim.x) {
     const double psiD = amps[d];
     if (is_dead(psiD)) continue;
@@ -217,21 +308,19 @@ k_pool_contract_det(const u64* __restrict__ keys, const double* __restrict__ amp
     __syncthreads();
     build_lists_shared(D, n_spatial, S);
     __syncthreads();
-    for (int c = threadIdx.x; c < C; c += kSigBlock) {
-      int h0, h1 = 0, p0, p1 = 0;
-      const int nh = decode_shared(E, S, c, &h0, &h1, &p0, &p1);
-      u64 X = D ^ (1ULL << h0) ^ (1ULL << p0);
-      if (nh == 2) X ^= (1ULL << h1) ^ (1ULL << p1);
+    build_conn_tables(S, E, T);
+    __syncthreads();
+    for_each_connection(T, D, [&](u64 X, int nh, int h0, int h1, int p0, int p1) {
       bool t_acts;
       const long long k = linking_operator(opmap, omask, nh, h0, h1, p0, p1, &t_acts);
-      if (k < 0) continue;
-      if (selected && !selected[k]) continue;
+      if (k < 0) return;
+      if (selected && !selected[k]) return;
       double sx;
-      if (!acc_find(tab, tmask, X, &sx)) continue;
+      if (!acc_find(tab, tmask, X, &sx)) return;
       const OpDesc op = ops[k];
       const double a = t_acts ? (double)phase_of_T(op, D) : -(double)phase_of_T(op, X);
       unsafeAtomicAdd(&gacc[k], psiD * a * sx);
-    }
+    });
   }
 }
 
@@ -245,8 +334,10 @@ k_query_set(const u64* __restrict__ keys, const double* __restrict__ amps, ExcSp
             const unsigned char* __restrict__ selected, AccSlot* __restrict__ tab, u64 tmask,
             int count_only, u64* __restrict__ counter, unsigned* __restrict__ flags) {
   __shared__ SigShared S;
+  __shared__ ConnTables T;
+  extern __shared__ __align__(16) unsigned char conn_dyn[];
   build_pair_table(S);
-  const int C = (int)E.total;
+  if (threadIdx.x == 0) attach_conn_tables(T, conn_dyn, E);
   unsigned long long mine = 0;
   for (u64 d = blockIdx.x; d < n; d += gridDim.x) {
     if (is_dead(amps[d])) continue;
@@ -254,20 +345,18 @@ k_query_set(const u64* __restrict__ keys, const double* __restrict__ amps, ExcSp
     __syncthreads();
     build_lists_shared(D, n_spatial, S);
     __syncthreads();
-    for (int c = threadIdx.x; c < C; c += kSigBlock) {
-      int h0, h1 = 0, p0, p1 = 0;
-      const int nh = decode_shared(E, S, c, &h0, &h1, &p0, &p1);
+    build_conn_tables(S, E, T);
+    __syncthreads();
+    for_each_connection(T, D, [&](u64 X, int nh, int h0, int h1, int p0, int p1) {
       bool t_acts;
       const long long k = linking_operator(opmap, omask, nh, h0, h1, p0, p1, &t_acts);
-      if (k < 0 || !selected[k]) continue;
+      if (k < 0 || !selected[k]) return;
       if (count_only) {
         ++mine;
-        continue;
+        return;
       }
-      u64 X = D ^ (1ULL << h0) ^ (1ULL << p0);
-      if (nh == 2) X ^= (1ULL << h1) ^ (1ULL << p1);
       if (!acc_add(tab, tmask, X, 0.0)) atomicOr(flags, kFlagOverflow);
-    }
+    });
   }
   if (count_only) {
     for (int off = 32; off > 0; off >>= 1) mine += __shfl_xor(mine, off);
@@ -362,8 +451,10 @@ __global__ void __launch_bounds__(kSigBlock)
 k_sigma_push_into(const u64* __restrict__ keys, const double* __restrict__ amps, Ints I, ExcSpace E,
                   u64 n, AccSlot* __restrict__ tab, u64 tmask) {
   __shared__ SigShared S;
+  __shared__ ConnTables T;
+  extern __shared__ __align__(16) unsigned char conn_dyn[];
   build_pair_table(S);
-  const int C = (int)E.total;
+  if (threadIdx.x == 0) attach_conn_tables(T, conn_dyn, E);
   for (u64 d = blockIdx.x; d < n; d += gridDim.x) {
     const double psiD = amps[d];
     if (is_dead(psiD)) continue;
@@ -371,18 +462,16 @@ k_sigma_push_into(const u64* __restrict__ keys, const double* __restrict__ amps,
     __syncthreads();
     build_lists_shared(D, I.n, S);
     __syncthreads();
+    build_conn_tables(S, E, T);
+    __syncthreads();
     if (threadIdx.x == 0) {
       double* v = acc_slot(tab, tmask, D);
       if (v) unsafeAtomicAdd(v, diag_element(I, D) * psiD);
     }
-    for (int c = threadIdx.x; c < C; c += kSigBlock) {
-      int h0, h1 = 0, p0, p1 = 0;
-      const int nh = decode_shared(E, S, c, &h0, &h1, &p0, &p1);
-      u64 X = D ^ (1ULL << h0) ^ (1ULL << p0);
-      if (nh == 2) X ^= (1ULL << h1) ^ (1ULL << p1);
+    for_each_connection(T, D, [&](u64 X, int nh, int h0, int h1, int p0, int p1) {
       double* v = acc_slot(tab, tmask, X);
       if (v) unsafeAtomicAdd(v, connection_element(I, D, nh, h0, h1, p0, p1) * psiD);
-    }
+    });
   }
 }
 
@@ -462,8 +551,8 @@ hipError_t launch_sigma_proj(const DeviceState& st, const Ints& I, const ExcSpac
                              double* sigma, double* partial_num, double* partial_norm, int grid,
                              hipStream_t stream) {
   (void)partial_norm;
-  hipLaunchKernelGGL(k_sigma_proj, dim3(grid), dim3(kSigBlock), 0, stream, st.keys, st.amps,
-                     st.hash, st.hmask, I, E, n, sigma, partial_num);
+  hipLaunchKernelGGL(k_sigma_proj, dim3(grid), dim3(kSigBlock), conn_tables_bytes(E), stream, st.keys, st.amps,
+                     st.hash, st.hmask, st.filt, st.fmask, I, E, n, sigma, partial_num);
   return hipGetLastError();
 }
 
@@ -486,7 +575,7 @@ hipError_t launch_reduce_partials(const double* partial, int count, int stride, 
 hipError_t launch_sigma_push(const DeviceState& st, const Ints& I, const ExcSpace& E, u64 n,
                              AccSlot* tab, u64 tmask, int nbatch, int batch, int grid,
                              hipStream_t stream) {
-  hipLaunchKernelGGL(k_sigma_push, dim3(grid), dim3(kSigBlock), 0, stream, st.keys, st.amps, I, E,
+  hipLaunchKernelGGL(k_sigma_push, dim3(grid), dim3(kSigBlock), conn_tables_bytes(E), stream, st.keys, st.amps, I, E,
                      n, tab, tmask, nbatch, batch, &st.ctr->flags);
   return hipGetLastError();
 }
@@ -495,7 +584,7 @@ hipError_t launch_pool_contract_det(const DeviceState& st, const ExcSpace& E, in
                                    const HashSlot* opmap, u64 omask, const unsigned char* selected,
                                    const OpDesc* ops, const AccSlot* tab, u64 tmask, double* gacc,
                                    int grid, hipStream_t stream) {
-  hipLaunchKernelGGL(k_pool_contract_det, dim3(grid), dim3(kSigBlock), 0, stream, st.keys, st.amps,
+  hipLaunchKernelGGL(k_pool_contract_det, dim3(grid), dim3(kSigBlock), conn_tables_bytes(E), stream, st.keys, st.amps,
                      E, n_spatial, n, opmap, omask, selected, ops, tab, tmask, gacc);
   return hipGetLastError();
 }
@@ -504,7 +593,7 @@ hipError_t launch_query_set(const DeviceState& st, const ExcSpace& E, int n_spat
                             const HashSlot* opmap, u64 omask, const unsigned char* selected,
                             AccSlot* tab, u64 tmask, int count_only, u64* counter, int grid,
                             hipStream_t stream) {
-  hipLaunchKernelGGL(k_query_set, dim3(grid), dim3(kSigBlock), 0, stream, st.keys, st.amps, E,
+  hipLaunchKernelGGL(k_query_set, dim3(grid), dim3(kSigBlock), conn_tables_bytes(E), stream, st.keys, st.amps, E,
                      n_spatial, n, opmap, omask, selected, tab, tmask, count_only, counter,
                      &st.ctr->flags);
   return hipGetLastError();
@@ -532,7 +621,7 @@ hipError_t launch_contract_ops(const DeviceState& st, u64 n, const OpDesc* ops, 
 
 hipError_t launch_sigma_push_into(const DeviceState& st, const Ints& I, const ExcSpace& E, u64 n,
                                   AccSlot* tab, u64 tmask, int grid, hipStream_t stream) {
-  hipLaunchKernelGGL(k_sigma_push_into, dim3(grid), dim3(kSigBlock), 0, stream, st.keys, st.amps, I,
+  hipLaunchKernelGGL(k_sigma_push_into, dim3(grid), dim3(kSigBlock), conn_tables_bytes(E), stream, st.keys, st.amps, I,
                      E, n, tab, tmask);
   return hipGetLastError();
 }

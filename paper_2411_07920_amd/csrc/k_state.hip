@@ -157,6 +157,97 @@ __global__ void k_hash_build(const u64* __restrict__ keys, HashSlot* hash, u64 h
     hash_insert_new(hash, hmask, keys[i], i);
 }
 
+// Presence filter of the alive keys: clear, then set one bit per key.
+__global__ void k_filter_clear(unsigned* __restrict__ filt, u64 words) {
+  const u64 stride = (u64)gridDim.x * blockDim.x;
+  for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += stride) filt[i] = 0u;
+}
+
+__global__ void k_filter_set(const u64* __restrict__ keys, const double* __restrict__ amps, u64 n,
+                             unsigned* __restrict__ filt, u64 fmask) {
+  const u64 stride = (u64)gridDim.x * blockDim.x;
+  for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    if (is_dead(amps[i])) continue;
+    const u64 b = filter_bit(keys[i], fmask);
+    atomicOr(&filt[b >> 5], 1u << (b & 31));
+  }
+}
+
+// N_CUT pruning of a state in HBM: a radix select of the ncut-th largest
+// value in the N_CUT order (gate_ops.h), one histogram launch and one pick
+// launch per 8-bit digit, then one marking launch.  With ctr the stored
+// count comes from the counters and the alive count is updated; otherwise
+// n_host entries are scanned.
+__global__ void k_ncut_init(NcutState* __restrict__ st, unsigned ncut,
+                            const Counters* __restrict__ ctr) {
+  if (blockIdx.x != 0) return;
+  const int t = threadIdx.x;
+  if (t < 256) st->hist[t] = 0;
+  if (t == 0) {
+    st->phi = st->plo = st->mhi = st->mlo = 0;
+    st->k = ncut;
+    unsigned skip = 0;
+    if (ctr) {
+      const unsigned fl = __hip_atomic_load(&ctr->flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const u64 alive = __hip_atomic_load(&ctr->alive, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if ((fl & kFlagStopped) || alive <= ncut) skip = 1;
+    }
+    st->skip = skip;
+  }
+}
+
+__global__ void __launch_bounds__(256)
+k_ncut_hist(const double* __restrict__ amps, const u64* __restrict__ keys, u64 n_host,
+            const Counters* __restrict__ ctr, NcutState* __restrict__ st, int d) {
+  if (st->skip) return;
+  __shared__ unsigned h[256];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const u64 n = ctr ? __hip_atomic_load(&ctr->n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : n_host;
+  const NcutState s = *st;
+  const u64 stride = (u64)gridDim.x * blockDim.x;
+  for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const double a = amps[i];
+    if (is_dead(a)) continue;
+    u64 hi, lo;
+    ncut_value(a, keys[i], &hi, &lo);
+    if (ncut_matches(s, hi, lo)) atomicAdd(&h[ncut_digit(hi, lo, d)], 1u);
+  }
+  __syncthreads();
+  if (h[threadIdx.x]) atomicAdd(&st->hist[threadIdx.x], h[threadIdx.x]);
+}
+
+__global__ void k_ncut_pick(NcutState* __restrict__ st, int d) {
+  if (st->skip) return;
+  if (threadIdx.x == 0) ncut_pick(*st, d);
+  __syncthreads();
+  if (threadIdx.x < 256) st->hist[threadIdx.x] = 0;
+}
+
+__global__ void __launch_bounds__(256)
+k_ncut_mark(double* __restrict__ amps, const u64* __restrict__ keys, u64 n_host,
+            Counters* __restrict__ ctr, const NcutState* __restrict__ st) {
+  if (st->skip) return;
+  const u64 n = ctr ? __hip_atomic_load(&ctr->n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : n_host;
+  const u64 thi = st->phi, tlo = st->plo;
+  unsigned long long dropped = 0;
+  const u64 stride = (u64)gridDim.x * blockDim.x;
+  for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const double a = amps[i];
+    if (is_dead(a)) continue;
+    u64 hi, lo;
+    ncut_value(a, keys[i], &hi, &lo);
+    if (hi < thi || (hi == thi && lo < tlo)) {
+      amps[i] = dead_value();
+      ++dropped;
+    }
+  }
+  if (ctr) {
+    for (int off = 32; off > 0; off >>= 1) dropped += __shfl_xor(dropped, off);
+    if (__lane_id() == 0 && dropped) atomicAdd(&ctr->alive, (u64)(0ULL - dropped));
+  }
+}
+
 // State = the single reference determinant with amplitude 1.
 __global__ void k_reset_reference(u64* __restrict__ keys, double* __restrict__ amps,
                                   Counters* __restrict__ ctr, u64 ref) {
@@ -250,6 +341,27 @@ hipError_t launch_hash_clear(HashSlot* tab, u64 slots, hipStream_t stream) {
 hipError_t launch_hash_build(const DeviceState& st, u64 n, hipStream_t stream) {
   hipLaunchKernelGGL(k_hash_build, dim3(grid_for(n, 256, 8192)), dim3(256), 0, stream, st.keys,
                      st.hash, st.hmask, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_filter_build(const DeviceState& st, u64 n, int grid, hipStream_t stream) {
+  const u64 words = (st.fmask + 1) / 32;
+  hipLaunchKernelGGL(k_filter_clear, dim3(grid_for(words, 256, 4096)), dim3(256), 0, stream, st.filt,
+                     words);
+  if (n > 0)
+    hipLaunchKernelGGL(k_filter_set, dim3(grid), dim3(256), 0, stream, st.keys, st.amps, n, st.filt,
+                       st.fmask);
+  return hipGetLastError();
+}
+
+hipError_t launch_ncut(double* amps, const u64* keys, u64 n_host, Counters* ctr, NcutState* st,
+                       unsigned ncut, int grid, hipStream_t stream) {
+  hipLaunchKernelGGL(k_ncut_init, dim3(1), dim3(256), 0, stream, st, ncut, ctr);
+  for (int d = 0; d < 16; ++d) {
+    hipLaunchKernelGGL(k_ncut_hist, dim3(grid), dim3(256), 0, stream, amps, keys, n_host, ctr, st, d);
+    hipLaunchKernelGGL(k_ncut_pick, dim3(1), dim3(256), 0, stream, st, d);
+  }
+  hipLaunchKernelGGL(k_ncut_mark, dim3(grid), dim3(256), 0, stream, amps, keys, n_host, ctr, st);
   return hipGetLastError();
 }
 

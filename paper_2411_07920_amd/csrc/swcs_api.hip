@@ -83,7 +83,8 @@ struct swcs_ctx {
   u64 omask = 0;
 
   // state
-  DevBuf keys, amps, hash, ctr;
+  DevBuf keys, amps, hash, ctr, filt;
+  u64 filt_bits_alloc = 0;
   DeviceState st;
   Counters hc;            // host copy of the device counters
   bool hc_valid = false;  // true while no launch may have changed them
@@ -112,12 +113,12 @@ struct swcs_ctx {
   size_t ev_used = 0;
 
   // scratch
-  DevBuf gacc, selected;
+  DevBuf gacc, selected, ncut_state;
   DevBuf partial, partial2, sigma, mu, work, seg_states, acc_tab, gbuf, subset_buf, scalars,
       exp_keys, exp_amps, exp_tmp_k, exp_tmp_v, sort_scratch, ctr_r, occ, sel_scratch, mlp_partial;
 
   ~swcs_ctx() {
-    DevBuf* all[] = {&h, &eri, &J, &K, &fock, &ops, &opmap, &gacc, &selected, &keys, &amps, &hash, &ctr, &ckpt_n, &ckpt_ptrs,
+    DevBuf* all[] = {&h, &eri, &J, &K, &fock, &ops, &opmap, &gacc, &selected, &ncut_state, &filt, &keys, &amps, &hash, &ctr, &ckpt_n, &ckpt_ptrs,
                      &gate_tab, &gate_n_in,
                      &partial, &partial2, &sigma, &mu, &work, &seg_states, &acc_tab, &gbuf,
                      &subset_buf, &scalars, &exp_keys, &exp_amps, &exp_tmp_k, &exp_tmp_v,
@@ -260,14 +261,28 @@ int state_reserve(swcs_ctx* c, u64 cap, u64 n_keep) {
     c->hash.release();
     HIP_TRY(c, c->hash.ensure(hslots * sizeof(HashSlot)), "alloc hash");
   }
+  const u64 fbits = next_pow2(std::max<u64>(4096, 16 * cap));
+  HIP_TRY(c, c->filt.ensure(fbits / 8), "alloc filter");
+  c->filt_bits_alloc = fbits;
   c->st.keys = c->keys.as<u64>();
   c->st.amps = c->amps.as<double>();
   c->st.hash = c->hash.as<HashSlot>();
   c->st.cap = cap;
   c->st.hmask = hslots - 1;
+  c->st.filt = c->filt.as<unsigned>();
+  c->st.fmask = fbits - 1;
   c->st.ctr = c->ctr.as<Counters>();
   HIP_TRY(c, launch_hash_clear(c->st.hash, hslots, c->stream), "hash clear");
   if (n_keep > 0) HIP_TRY(c, launch_hash_build(c->st, n_keep, c->stream), "hash build");
+  return SWCS_OK;
+}
+
+// Presence filter of the alive keys, about 16 bits per key (bounded by the
+// allocation) so that it stays cache-resident.
+int build_filter(swcs_ctx* c, u64 n, u64 alive) {
+  const u64 want = next_pow2(std::max<u64>(4096, 16 * alive));
+  c->st.fmask = std::min<u64>(want, c->filt_bits_alloc) - 1;
+  HIP_TRY(c, launch_filter_build(c->st, n, grid_blocks(c, n, 256), c->stream), "filter");
   return SWCS_OK;
 }
 
@@ -305,7 +320,7 @@ int validate_gates(swcs_ctx* c, const int32_t* op_idx, const double* theta, int6
   if (M > 0 && (!op_idx || !theta)) return fail(c, SWCS_E_INVALID, "null op_idx/theta");
   if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(c, SWCS_E_INVALID, "eps must be finite and >= 0");
   if (ncut < 0) return fail(c, SWCS_E_INVALID, "ncut < 0");
-  if (ncut > 0) return fail(c, SWCS_E_UNSUPPORTED, "N_CUT pruning is not available in this build");
+  if (ncut > 0x7fffffffLL) return fail(c, SWCS_E_INVALID, "ncut too large");
   for (int64_t i = 0; i < M; ++i) {
     if (op_idx[i] < 0 || op_idx[i] >= c->K_pool) return fail(c, SWCS_E_INVALID, "op index out of range");
     if (!std::isfinite(theta[i])) return fail(c, SWCS_E_INVALID, "non-finite theta");
@@ -334,7 +349,9 @@ int upload_ckpt_table(swcs_ctx* c, int nck) {
 // (LDS-resident) for as long as it fits; the rest runs one multi-block
 // launch per gate in HBM, growing the arrays when a gate would not fit.
 int run_chain(swcs_ctx* c, const int32_t* op_idx, const double* cs, const double* sn, int64_t M,
-              double eps, bool ckpt, u64 n_start, Counters* out) {
+              double eps, unsigned ncut, bool ckpt, u64 n_start, Counters* out) {
+  // With N_CUT the gates keep everything and the selection prunes.
+  if (ncut) eps = 0.0;
   int64_t g0 = 0;
   c->hc_valid = false;
   if (M == 0) {
@@ -367,7 +384,7 @@ int run_chain(swcs_ctx* c, const int32_t* op_idx, const double* cs, const double
       M <= (int64_t)1 << 30) {
     TIMED(c, SWCS_K_CHAIN_LDS, launch_chain_lds(c->st, c->gate_tab.as<GateDesc>(), 0, (int)M, eps, eps > 0.0 ? 1 : 0,
                                 ckpt ? c->ckpt_ptrs.as<double*>() : nullptr, c->ckpt_n.as<u64>(),
-                                c->seg, c->gate_n_in.as<u64>(), c->sector, c->stream), "chain");
+                                c->seg, c->gate_n_in.as<u64>(), c->sector, ncut, c->stream), "chain");
     HIP_TRY(c, launch_hash_clear(c->st.hash, c->st.hmask + 1, c->stream), "hash clear");
     HIP_TRY(c, launch_hash_build_dev(c->st, grid_blocks(c, lds_chain_capacity(), 256), c->stream), "hash build");
     hipError_t e;
@@ -400,6 +417,9 @@ int run_chain(swcs_ctx* c, const int32_t* op_idx, const double* cs, const double
       // first gate, so every later state is exactly P(U psi).
       if (g == 0 && eps > 0.0)
         HIP_TRY(c, launch_prune_all(c->st, eps, grid_blocks(c, c->st.cap / 2, 256), c->stream), "prune");
+      if (ncut)
+        HIP_TRY(c, launch_ncut(c->st.amps, c->st.keys, 0, c->st.ctr, c->ncut_state.as<NcutState>(), ncut,
+                               grid_blocks(c, c->st.cap / 2, 256), c->stream), "ncut");
     }
     hipError_t e;
     Counters h = read_counters(c, &e);
@@ -661,7 +681,10 @@ static int apply_common(swcs_ctx* c, const int32_t* op_idx, const double* theta,
     if (e != hipSuccess) return hip_fail(c, e, "read counters");
     n_start = h0.n;
   }
-  r = run_chain(c, op_idx, cs.data(), sn.data(), M, eps, from_reference, n_start, &h);
+  HIP_TRY(c, c->ncut_state.ensure(sizeof(NcutState)), "alloc ncut state");
+  r = run_chain(c, op_idx, cs.data(), sn.data(), M, eps, (unsigned)ncut, from_reference, n_start, &h);
+  if (r) return r;
+  r = build_filter(c, h.n, h.alive);
   if (r) return r;
   c->peak_n = std::max<u64>(c->peak_n, h.n);
   c->last_M = M;
@@ -720,6 +743,8 @@ int swcs_set_state(swcs_ctx* c, const uint64_t* keys, const double* amps, int64_
   h.alive = (u64)n;
   HIP_TRY(c, hipMemcpy(c->ctr.p, &h, sizeof(h), hipMemcpyHostToDevice), "counters");
   if (n > 0) HIP_TRY(c, launch_hash_build(c->st, (u64)n, c->stream), "hash build");
+  r = build_filter(c, (u64)n, (u64)n);
+  if (r) return r;
   HIP_TRY(c, hipStreamSynchronize(c->stream), "sync");
   c->hc = h;
   c->hc_valid = true;
@@ -979,9 +1004,9 @@ int swcs_param_gradients(swcs_ctx* c, double* dE, double* E_out) {
     int r2 = upload_ckpt_table(c, nseg);
     if (r2) return r2;
     TIMED(c, SWCS_K_ADJOINT_LDS, launch_adjoint_lds(c->st.keys, (unsigned)n, c->gate_tab.as<GateDesc>(), (int)M, seg,
-                                  c->a_eps, c->ckpt_ptrs.as<double*>(), c->ckpt_n.as<u64>(),
+                                  c->a_ncut ? 0.0 : c->a_eps, c->ckpt_ptrs.as<double*>(), c->ckpt_n.as<u64>(),
                                   c->mu.as<double>(), logs, c->gbuf.as<double>(),
-                                  &c->st.ctr->flags, c->stream), "adjoint");
+                                  &c->st.ctr->flags, (unsigned)c->a_ncut, c->stream), "adjoint");
   } else {
     // Per segment: restore the checkpoint into a working copy, replay the
     // segment's gates logging their active pairs, then walk the logs back.
@@ -999,7 +1024,10 @@ int swcs_param_gradients(swcs_ctx* c, double* dE, double* E_out) {
       for (int t = 0; t < len; ++t) {
         const int64_t g = g_lo + t;
         TIMED(c, SWCS_K_GATE_REPLAY, launch_gate_replay(c->st, W, n, c->ops_host[c->a_ops[g]], c->a_c[g], c->a_s[g],
-                                      c->a_eps, logs + (size_t)t * n, lc + t, grid, c->stream), "replay");
+                                      c->a_ncut ? 0.0 : c->a_eps, logs + (size_t)t * n, lc + t, grid, c->stream), "replay");
+        if (c->a_ncut)
+          HIP_TRY(c, launch_ncut(W, c->st.keys, n, nullptr, c->ncut_state.as<NcutState>(), (unsigned)c->a_ncut,
+                                 grid, c->stream), "ncut");
       }
       for (int t = len - 1; t >= 0; --t) {
         const int64_t g = g_lo + t;

@@ -270,7 +270,21 @@ struct DeviceState {
   Counters* ctr = nullptr;
   u64 cap = 0;        // SoA capacity
   u64 hmask = 0;      // hash capacity - 1
+  unsigned* filt = nullptr;  // presence filter of the alive keys (1 bit per hash)
+  u64 fmask = 0;             // filter bits - 1
 };
+
+// Presence filter: one bit per (independent) hash of an alive key, about 16
+// bits per key so that it stays in L2; a clear bit proves absence, so most
+// probes for determinants that are not in the state never reach the table.
+__device__ inline u64 filter_bit(u64 key, u64 fmask) {
+  return mix64(key ^ 0xd6e8feb86659fd93ULL) & fmask;
+}
+
+__device__ inline bool filter_maybe(const unsigned* __restrict__ filt, u64 fmask, u64 key) {
+  const u64 b = filter_bit(key, fmask);
+  return (filt[b >> 5] >> (b & 31)) & 1u;
+}
 
 // Launch wrappers (defined in the .hip files).  All enqueue on `stream`.
 struct PairRec;
@@ -281,16 +295,20 @@ hipError_t launch_gate(const DeviceState& st, const OpDesc& op, double c, double
                        hipStream_t stream);
 hipError_t launch_prune_all(const DeviceState& st, double eps, int grid, hipStream_t stream);
 hipError_t launch_hash_build_dev(const DeviceState& st, int grid, hipStream_t stream);
+hipError_t launch_filter_build(const DeviceState& st, u64 n, int grid, hipStream_t stream);
 hipError_t launch_reset_reference(const DeviceState& st, u64 ref, hipStream_t stream);
+struct NcutState;
+hipError_t launch_ncut(double* amps, const u64* keys, u64 n_host, Counters* ctr, NcutState* st,
+                       unsigned ncut, int grid, hipStream_t stream);
 int lds_chain_capacity();
 hipError_t launch_chain_lds(const DeviceState& st, const GateDesc* gates, int g0, int M, double eps,
                             int prune_first, double* const* ckpt, u64* ckpt_n, int seg,
-                            u64* gate_n_in, u64 max_keys, hipStream_t stream);
+                            u64* gate_n_in, u64 max_keys, unsigned ncut, hipStream_t stream);
 int lds_adjoint_max_segment();
 hipError_t launch_adjoint_lds(const u64* keys, unsigned n, const GateDesc* gates, int M, int seg,
                               double eps, const double* const* ckpt, const u64* ckpt_n,
                               const double* mu_init, PairRec* logbuf, double* dE, unsigned* flags,
-                              hipStream_t stream);
+                              unsigned ncut, hipStream_t stream);
 hipError_t launch_gate_replay(const DeviceState& st, double* amps, u64 n, const OpDesc& op,
                              double c, double sn, double eps, PairRec* log, u64* log_count, int grid,
                              hipStream_t stream);

@@ -159,30 +159,47 @@ def draw_ansatz(n_pool: int, n_ops: int, lo: float, hi: float, seed: int):
     return ops, theta
 
 
+def _strings(n: int, k: int) -> np.ndarray:
+    """All n-bit masks with k bits set (one spin's occupation strings), ascending."""
+    if n <= 26:
+        x = np.arange(1 << n, dtype=np.uint32)
+        pc = np.zeros_like(x, dtype=np.uint8)
+        for b in range(n):
+            pc += ((x >> np.uint32(b)) & np.uint32(1)).astype(np.uint8)
+        return x[pc == k].astype(np.uint64)
+    from itertools import combinations
+    out = [sum(1 << i for i in c) for c in combinations(range(n), k)]
+    return np.array(sorted(out), dtype=np.uint64)
+
+
+def _spread(mask: np.ndarray, n: int, offset: int) -> np.ndarray:
+    """Place bit p of a spatial mask at spin-orbital 2p + offset."""
+    out = np.zeros_like(mask, dtype=np.uint64)
+    for p in range(n):
+        bit = (mask >> np.uint64(p)) & np.uint64(1)
+        out |= bit << np.uint64(2 * p + offset)
+    return out
+
+
 def draw_synthetic_state(n: int, n_alpha: int, n_beta: int, count: int, seed: int):
     """``count`` distinct determinants drawn uniformly from the (n_alpha, n_beta)
-    sector, random signs and log-uniform magnitudes in [1e-8, 1e-2].
+    sector (an alpha string and a beta string, each uniform), random signs and
+    log-uniform magnitudes in [1e-8, 1e-2].
 
-    Returns ``(keys uint64[count], amps float64[count])`` with keys in draw
-    order (not sorted).  Used as a structure-free stand-in for a large
-    truncated state.
+    Returns ``(keys uint64[count], amps float64[count])`` in draw order (not
+    sorted).  A structure-free stand-in for a large truncated state.
     """
     rng = np.random.default_rng(seed)
     total = sector_size(n, n_alpha, n_beta)
     if count > total:
         raise ValueError("count exceeds sector size")
+    sa = _spread(_strings(n, n_alpha), n, 0)
+    sb = sa if n_beta == n_alpha else None
+    sb = _spread(_strings(n, n_beta), n, 1) if sb is None else (sa << np.uint64(1))
     keys = np.zeros(0, dtype=np.uint64)
-    alpha_bits = (2 * np.arange(n)).astype(np.uint64)
-    beta_bits = alpha_bits + np.uint64(1)
     while len(keys) < count:
-        need = int((count - len(keys)) * 1.1) + 16
-        a = np.argsort(rng.random((need, n)), axis=1)[:, :n_alpha]
-        b = np.argsort(rng.random((need, n)), axis=1)[:, :n_beta]
-        k = np.zeros(need, dtype=np.uint64)
-        for j in range(n_alpha):
-            k |= np.left_shift(np.uint64(1), alpha_bits[a[:, j]])
-        for j in range(n_beta):
-            k |= np.left_shift(np.uint64(1), beta_bits[b[:, j]])
+        need = int((count - len(keys)) * 1.05) + 16
+        k = sa[rng.integers(0, len(sa), need)] | sb[rng.integers(0, len(sb), need)]
         keys = np.concatenate([keys, k])
         _, first = np.unique(keys, return_index=True)
         keys = keys[np.sort(first)]

@@ -318,3 +318,43 @@ def test_determinism(swcs, c2):
     # stored entries may differ in the last bits between runs
     assert np.abs(d1 - d2).max() < 1e-13
     ctx.close()
+
+
+def _ncut_case(swcs, case, ncut, pool_subset=None):
+    _say(f"[parity] {case.name}: N_CUT={ncut}")
+    st = oracle.Oracle.apply_ansatz(case.pool, case.ops, case.theta, 0.0, case.ref, ncut=ncut)
+    ctx = make_ctx(swcs, case)
+    ndet = ctx.apply_ansatz(case.ops, case.theta, 0.0, ncut=ncut)
+    k, a = ctx.get_state()
+    k_ref, a_ref = st.export()
+    assert ndet == len(k_ref) and np.array_equal(k, k_ref) and np.array_equal(a, a_ref)
+    E, _, _ = ctx.energy()
+    assert abs(E - case.orc.energy(st)[0]) < TOL
+    g = ctx.pool_gradients(pool_subset)
+    g_ref = case.orc.pool_gradients(st, case.pool, subset=pool_subset)
+    assert np.abs(g - g_ref).max() < TOL
+    dE, _ = ctx.param_gradients(len(case.ops))
+    dE_ref, _ = case.orc.param_gradients(case.pool, case.ops, case.theta, 0.0, case.ref, ncut=ncut)
+    assert np.abs(dE - dE_ref).max() < TOL
+    ctx.close()
+    return len(k_ref)
+
+
+def test_ncut_c2_lds_path(swcs, c2):
+    assert _ncut_case(swcs, c2, 200) == 200
+
+
+def test_ncut_spread_hbm_path(swcs, spread):
+    # more than 4,096 stored determinants: the chain leaves LDS and the
+    # selection runs as the multi-kernel radix select in HBM
+    assert _ncut_case(swcs, spread, 2500) == 2500
+
+
+def test_ncut_ties_at_zero(swcs, c1):
+    """theta = 0 gates create exact zeros; N_CUT keeps the largest |c| and
+    breaks ties by the smaller key."""
+    th = c1.theta.copy()
+    th[::3] = 0.0
+    case = Case(c1.n, c1.ne, c1.h, c1.eri, c1.pool, c1.ops, th, 0.0, "c1-zeros")
+    for ncut in (5, 20, 40):
+        _ncut_case(swcs, case, ncut)
