@@ -11,73 +11,110 @@
 
 namespace swcs {
 
-__global__ void __launch_bounds__(256)
+// One gate over the stored entries.  Each block of kGateThreads threads walks
+// tiles of kGateTile consecutive entries (kGateItems per thread, coalesced);
+// the new partner keys a tile creates are staged in LDS and written out
+// together behind a single atomic on the append counter, so the number of
+// same-address device atomics is one per tile plus two per block, not one per
+// wavefront.
+__global__ void __launch_bounds__(kGateThreads)
 k_gate(u64* __restrict__ keys, double* __restrict__ amps, HashSlot* __restrict__ hash, u64 hmask,
        u64 cap, Counters* __restrict__ ctr, OpDesc op, double c, double sn, double eps,
        u64* __restrict__ gate_n_in, int check_cap, unsigned gate_index, u64 max_keys) {
-  // A stopped chain skips every later gate; the host resumes it after growing.
-  if (__hip_atomic_load(&ctr->flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kFlagStopped)
-    return;
-  const u64 n_in = __hip_atomic_load(&ctr->n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  // Appends are bounded by the alive sources and by the number of keys not
-  // yet stored (max_keys = size of the electron-number sector), so
-  // n_in + min(alive_in, max_keys - n_in) <= cap guarantees the gate fits.
-  // Every block reads the same values and takes the same decision; nothing
-  // has been modified when it stops.
-  if (check_cap) {
-    const u64 alive_in = __hip_atomic_load(&ctr->alive, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const u64 room = max_keys > n_in ? max_keys - n_in : 0;
-    if (n_in + (alive_in < room ? alive_in : room) > cap) {
-      if (blockIdx.x == 0 && threadIdx.x == 0) {
-        ctr->stop_gate = gate_index;
-        atomicOr(&ctr->flags, kFlagStopped);
+  __shared__ u64 s_key[kGateTile];
+  __shared__ double s_val[kGateTile];
+  __shared__ unsigned s_cnt;
+  __shared__ int s_run;
+  __shared__ u64 s_n_in, s_base;
+  __shared__ long long s_wsum[kGateThreads / 64];
+  __shared__ bool is_last;
+  if (threadIdx.x == 0) {
+    // A stopped chain skips every later gate; the host resumes it after
+    // growing.  Appends are bounded by the alive sources and by the number of
+    // keys not yet stored (max_keys = size of the electron-number sector), so
+    // n_in + min(alive_in, max_keys - n_in) <= cap guarantees the gate fits.
+    // Every block reads the same values and takes the same decision; nothing
+    // has been modified when it stops.
+    int run = 1;
+    const unsigned fl = __hip_atomic_load(&ctr->flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const u64 n_in = __hip_atomic_load(&ctr->n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (fl & kFlagStopped) {
+      run = 0;
+    } else if (check_cap) {
+      const u64 alive_in = __hip_atomic_load(&ctr->alive, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const u64 room = max_keys > n_in ? max_keys - n_in : 0;
+      if (n_in + (alive_in < room ? alive_in : room) > cap) {
+        run = 0;
+        if (blockIdx.x == 0) {
+          ctr->stop_gate = gate_index;
+          atomicOr(&ctr->flags, kFlagStopped);
+        }
       }
-      return;
     }
+    s_run = run;
+    s_n_in = n_in;
+    s_cnt = 0;
   }
+  __syncthreads();
+  if (!s_run) return;
+  const u64 n_in = s_n_in;
   GlobalStore S{keys, amps, hash, hmask};
   long long dalive = 0;
-  const u64 stride = (u64)gridDim.x * blockDim.x;
-  for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < n_in; i += stride) {
-    const GateOut o = gate_entry(S, i, op, c, sn, eps);
-    dalive += o.dalive;
-    const bool want_append = o.append;
-    const u64 app_key = o.key;
-    const double app_val = o.val;
-    // Wave-aggregated append.
-    const u64 m = __ballot(want_append);
-    if (m) {
-      const int lane = __lane_id();
-      const int leader = __ffsll((long long)m) - 1;
-      u64 base = 0;
-      if (lane == leader) base = atomicAdd(&ctr->app, (u64)__popcll(m));
-      base = __shfl(base, leader);
-      if (want_append) {
-        const u64 idx = n_in + base + (u64)__popcll(m & ((1ULL << lane) - 1ULL));
+  const int lane = __lane_id();
+  const u64 below = (1ULL << lane) - 1ULL;
+  const u64 ntiles = (n_in + kGateTile - 1) / kGateTile;
+  for (u64 t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const u64 i0 = t * (u64)kGateTile + threadIdx.x;
+    for (int j = 0; j < kGateItems; ++j) {
+      const u64 i = i0 + (u64)j * kGateThreads;
+      GateOut o{false, 0ULL, 0.0, 0, false, kNoEntry, kNoEntry, 0.0, 0.0, 0};
+      if (i < n_in) o = gate_entry(S, i, op, c, sn, eps);
+      dalive += o.dalive;
+      const u64 m = __ballot(o.append);
+      if (m) {
+        const int leader = __ffsll((long long)m) - 1;
+        unsigned b = 0;
+        if (lane == leader) b = atomicAdd(&s_cnt, (unsigned)__popcll(m));
+        b = __shfl(b, leader);
+        if (o.append) {
+          const unsigned slot = b + (unsigned)__popcll(m & below);
+          s_key[slot] = o.key;
+          s_val[slot] = o.val;
+        }
+      }
+    }
+    __syncthreads();
+    const unsigned cnt = s_cnt;
+    if (cnt) {
+      if (threadIdx.x == 0) s_base = atomicAdd(&ctr->app, (u64)cnt);
+      __syncthreads();
+      const u64 gb = n_in + s_base;
+      for (unsigned j = threadIdx.x; j < cnt; j += kGateThreads) {
+        const u64 idx = gb + j;
         if (idx < cap) {
-          keys[idx] = app_key;
-          amps[idx] = app_val;
-          hash_insert_new(hash, hmask, app_key, idx);
+          keys[idx] = s_key[j];
+          amps[idx] = s_val[j];
+          hash_insert_new(hash, hmask, s_key[j], idx);
         } else {
           atomicOr(&ctr->flags, kFlagOverflow);
         }
       }
+      __syncthreads();
+      if (threadIdx.x == 0) s_cnt = 0;
+      __syncthreads();
     }
   }
   // Block reduction of the alive-count change, then last-block finalization.
-  __shared__ long long sdelta[256];
-  __shared__ bool is_last;
-  sdelta[threadIdx.x] = dalive;
+  for (int off = 32; off > 0; off >>= 1) dalive += __shfl_xor(dalive, off);
+  if (lane == 0) s_wsum[threadIdx.x / 64] = dalive;
   __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) sdelta[threadIdx.x] += sdelta[threadIdx.x + w];
-    __syncthreads();
-  }
   if (threadIdx.x == 0) {
-    if (sdelta[0] != 0) atomicAdd((unsigned long long*)&ctr->dalive, (unsigned long long)sdelta[0]);
+    long long d = 0;
+    for (int w = 0; w < kGateThreads / 64; ++w) d += s_wsum[w];
+    if (d != 0) atomicAdd((unsigned long long*)&ctr->dalive, (unsigned long long)d);
     __threadfence();
-    const unsigned t = atomicAdd(&ctr->ticket, 1u);
-    is_last = (t == gridDim.x - 1);
+    const unsigned tk = atomicAdd(&ctr->ticket, 1u);
+    is_last = (tk == gridDim.x - 1);
   }
   __syncthreads();
   if (is_last && threadIdx.x == 0) {
@@ -86,8 +123,7 @@ k_gate(u64* __restrict__ keys, double* __restrict__ amps, HashSlot* __restrict__
     const long long da = (long long)atomicAdd((unsigned long long*)&ctr->dalive, 0ULL);
     const u64 alive = ctr->alive;
     if (gate_n_in) *gate_n_in = alive;
-    const u64 napp = app;
-    ctr->n = n_in + (napp < cap - n_in ? napp : cap - n_in);
+    ctr->n = n_in + (app < cap - n_in ? app : cap - n_in);
     ctr->alive = (u64)((long long)alive + da);
     ctr->app = 0;
     ctr->dalive = 0;
@@ -98,26 +134,49 @@ k_gate(u64* __restrict__ keys, double* __restrict__ amps, HashSlot* __restrict__
 
 // Replay of one gate inside the adjoint's recomputation: the same update as
 // k_gate on a working copy of the amplitudes, plus one PairRec per active
-// pair (wave-aggregated appends to log[]).  Every key the replay can reach is
-// already stored, so nothing is appended to the state.
-__global__ void __launch_bounds__(256)
+// pair, staged per tile in LDS and appended to log[] behind one atomic per
+// tile.  Every key the replay can reach is already stored, so nothing is
+// appended to the state.
+__global__ void __launch_bounds__(kGateThreads)
 k_gate_replay(const u64* __restrict__ keys, double* __restrict__ amps,
               const HashSlot* __restrict__ hash, u64 hmask, u64 n, OpDesc op, double c, double sn,
               double eps, PairRec* __restrict__ log, u64* __restrict__ log_count,
               unsigned* __restrict__ flags) {
+  __shared__ PairRec s_rec[kReplayTile];
+  __shared__ unsigned s_cnt;
+  __shared__ u64 s_base;
+  if (threadIdx.x == 0) s_cnt = 0;
+  __syncthreads();
   GlobalStore S{(u64*)keys, amps, hash, hmask};
-  const u64 stride = (u64)gridDim.x * blockDim.x;
-  for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-    const GateOut o = gate_entry(S, i, op, c, sn, eps);
-    if (o.append) atomicOr(flags, kFlagOverflow);
-    const u64 m = __ballot(o.active);
-    if (m) {
-      const int lane = __lane_id();
-      const int leader = __ffsll((long long)m) - 1;
-      u64 base = 0;
-      if (lane == leader) base = atomicAdd(log_count, (u64)__popcll(m));
-      base = __shfl(base, leader);
-      if (o.active) log[base + (u64)__popcll(m & ((1ULL << lane) - 1ULL))] = make_rec(o);
+  const int lane = __lane_id();
+  const u64 below = (1ULL << lane) - 1ULL;
+  const u64 ntiles = (n + kReplayTile - 1) / kReplayTile;
+  for (u64 t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const u64 i0 = t * (u64)kReplayTile + threadIdx.x;
+    for (int j = 0; j < kReplayTile / kGateThreads; ++j) {
+      const u64 i = i0 + (u64)j * kGateThreads;
+      GateOut o{false, 0ULL, 0.0, 0, false, kNoEntry, kNoEntry, 0.0, 0.0, 0};
+      if (i < n) o = gate_entry(S, i, op, c, sn, eps);
+      if (o.append) atomicOr(flags, kFlagOverflow);
+      const u64 m = __ballot(o.active);
+      if (m) {
+        const int leader = __ffsll((long long)m) - 1;
+        unsigned b = 0;
+        if (lane == leader) b = atomicAdd(&s_cnt, (unsigned)__popcll(m));
+        b = __shfl(b, leader);
+        if (o.active) s_rec[b + (unsigned)__popcll(m & below)] = make_rec(o);
+      }
+    }
+    __syncthreads();
+    const unsigned cnt = s_cnt;
+    if (cnt) {
+      if (threadIdx.x == 0) s_base = atomicAdd(log_count, (u64)cnt);
+      __syncthreads();
+      const u64 gb = s_base;
+      for (unsigned j = threadIdx.x; j < cnt; j += kGateThreads) log[gb + j] = s_rec[j];
+      __syncthreads();
+      if (threadIdx.x == 0) s_cnt = 0;
+      __syncthreads();
     }
   }
 }
@@ -379,7 +438,7 @@ hipError_t launch_hash_build_dev(const DeviceState& st, int grid, hipStream_t st
 hipError_t launch_gate(const DeviceState& st, const OpDesc& op, double c, double sn, double eps,
                        u64* gate_n_in, int check_cap, unsigned gate_index, u64 max_keys, int grid,
                        hipStream_t stream) {
-  hipLaunchKernelGGL(k_gate, dim3(grid), dim3(256), 0, stream, st.keys, st.amps, st.hash, st.hmask,
+  hipLaunchKernelGGL(k_gate, dim3(grid), dim3(kGateThreads), 0, stream, st.keys, st.amps, st.hash, st.hmask,
                      st.cap, st.ctr, op, c, sn, eps, gate_n_in, check_cap, gate_index, max_keys);
   return hipGetLastError();
 }
@@ -392,7 +451,7 @@ hipError_t launch_prune_all(const DeviceState& st, double eps, int grid, hipStre
 hipError_t launch_gate_replay(const DeviceState& st, double* amps, u64 n, const OpDesc& op,
                              double c, double sn, double eps, PairRec* log, u64* log_count, int grid,
                              hipStream_t stream) {
-  hipLaunchKernelGGL(k_gate_replay, dim3(grid), dim3(256), 0, stream, st.keys, amps, st.hash,
+  hipLaunchKernelGGL(k_gate_replay, dim3(grid), dim3(kGateThreads), 0, stream, st.keys, amps, st.hash,
                      st.hmask, n, op, c, sn, eps, log, log_count, &st.ctr->flags);
   return hipGetLastError();
 }

@@ -184,6 +184,16 @@ int grid_blocks(swcs_ctx* c, u64 work_items, int per_block) {
   return (int)g;
 }
 
+// Grid of the tiled gate kernels: one block per tile up to two resident
+// 1024-thread blocks per compute unit.
+int gate_grid(swcs_ctx* c, u64 n_entries, int tile) {
+  u64 g = (n_entries + tile - 1) / tile;
+  const u64 maxg = (u64)c->num_cu * 2;
+  if (g > maxg) g = maxg;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
 int sigma_grid(swcs_ctx* c, u64 n) {
   u64 g = n;
   u64 maxg = (u64)c->num_cu * 32;
@@ -410,7 +420,7 @@ int run_chain(swcs_ctx* c, const int32_t* op_idx, const double* cs, const double
       }
       const OpDesc& op = c->ops_host[op_idx[g]];
       TIMED(c, SWCS_K_GATE, launch_gate(c->st, op, cs[g], sn[g], eps, c->gate_n_in.as<u64>() + g, 1,
-                             (unsigned)g, c->sector, grid_blocks(c, c->st.cap / 2, 256), c->stream),
+                             (unsigned)g, c->sector, gate_grid(c, c->st.cap / 2, kGateTile), c->stream),
               "gate");
       // The gates only test the entries they touch; entries of a starting
       // state that were never tested against eps are pruned once, after the
@@ -1024,7 +1034,8 @@ int swcs_param_gradients(swcs_ctx* c, double* dE, double* E_out) {
       for (int t = 0; t < len; ++t) {
         const int64_t g = g_lo + t;
         TIMED(c, SWCS_K_GATE_REPLAY, launch_gate_replay(c->st, W, n, c->ops_host[c->a_ops[g]], c->a_c[g], c->a_s[g],
-                                      c->a_ncut ? 0.0 : c->a_eps, logs + (size_t)t * n, lc + t, grid, c->stream), "replay");
+                                      c->a_ncut ? 0.0 : c->a_eps, logs + (size_t)t * n, lc + t,
+                                      gate_grid(c, n, kReplayTile), c->stream), "replay");
         if (c->a_ncut)
           HIP_TRY(c, launch_ncut(W, c->st.keys, n, nullptr, c->ncut_state.as<NcutState>(), (unsigned)c->a_ncut,
                                  grid, c->stream), "ncut");

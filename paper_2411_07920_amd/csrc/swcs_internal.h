@@ -262,6 +262,13 @@ struct GateDesc {
 // the forward chain, 32 B for the adjoint sweep: 128 KB of LDS).
 constexpr int kLdsCap = 4096;
 
+// Multi-block gate kernels in HBM: threads per block, entries per thread and
+// tile sizes (a tile's appended keys / logged pairs are staged in LDS).
+constexpr int kGateThreads = 1024;
+constexpr int kGateItems = 4;
+constexpr int kGateTile = kGateThreads * kGateItems;
+constexpr int kReplayTile = 2048;
+
 // ---------------------------------------------------------------- host side
 struct DeviceState {
   u64* keys = nullptr;
