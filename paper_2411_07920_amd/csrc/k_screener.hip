@@ -2,14 +2,14 @@
 // 16 -> 128 -> 128 -> 1 ReLU MLP forward and backward passes, mean squared
 // error and Adam.  Parameters are one flat vector:
 //   W1[16][128] | b1[128] | W2[128][128] | b2[128] | W3[128] | b3[1]
-// (row-major, input index first).  Each block handles 32 rows; the backward
-// pass writes per-block partial gradients that a second kernel sums in block
-// order, so results are deterministic.
+// (row-major, input index first).  The backward pass writes per-block
+// partial gradients that a second kernel sums in block order, so results are
+// deterministic.
 #include "swcs_internal.h"
 
 namespace swcs {
 
-constexpr int kIn = kMlpIn, kH = kMlpHidden, kRows = kMlpRowsPerBlock;
+constexpr int kIn = kMlpIn, kH = kMlpHidden;
 constexpr int oW1 = 0, ob1 = oW1 + kIn * kH, oW2 = ob1 + kH, ob2 = oW2 + kH * kH, oW3 = ob2 + kH,
               ob3 = oW3 + kH;
 
@@ -64,142 +64,199 @@ __global__ void k_fock(const double* __restrict__ h, const double* __restrict__ 
   fock[t] = v;
 }
 
+// The dense layers run on the FP32 matrix cores: one 16x16x4 step adds
+// A (16x4) times B (4x16) to a 16x16 accumulator held as four floats per
+// lane.  Lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16] and holds
+// D[4 (l / 16) + r][l % 16] in acc[r].
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ inline f32x4 mma4(float a, float b, f32x4 acc) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+}
+
+// LDS row strides (floats): 132 spreads the 16 rows a lane group reads in the
+// "row = l % 16" pattern over distinct banks, 144 spreads the 4 rows of the
+// "row = l / 16" pattern.
+constexpr int kStrideRowLane = kH + 4;
+constexpr int kStrideColLane = kH + 16;
+constexpr int kFwdRows = 64;       // rows per block iteration, 16 per wavefront
+constexpr int kBwdRows = 32;       // rows per block iteration of the backward pass
+constexpr int kMlpMaxBlocks = 256;
+
+// Forward pass: a1 = relu(x W1 + b1), a2 = relu(a1 W2 + b2), y = a2 W3 + b3;
+// act (optional) receives [a1 | a2] per row for the backward pass.  Each
+// wavefront computes 16 rows: 8 column tiles of 16, 4 k-steps for layer 1 and
+// 32 for layer 2; the weights are staged in LDS once per block.
 __global__ void __launch_bounds__(256)
 k_mlp_forward(const float* __restrict__ W, const float* __restrict__ x, long long B,
               float* __restrict__ y, float* __restrict__ act) {
-  __shared__ float sx[kRows][kIn];
-  __shared__ float a1[kRows][kH + 1];
-  __shared__ float a2[kRows][kH + 1];
-  __shared__ float yp[kRows][8];
-  const long long r0 = (long long)blockIdx.x * kRows;
-  const int tid = threadIdx.x;
-  for (int t = tid; t < kRows * kIn; t += 256) {
-    const long long r = r0 + t / kIn;
-    sx[t / kIn][t % kIn] = (r < B) ? x[r * kIn + t % kIn] : 0.0f;
+  __shared__ float w1s[kIn][kStrideColLane];
+  __shared__ float w2s[kH][kStrideColLane];
+  __shared__ float a1t[4][16][kStrideRowLane];
+  __shared__ float b1s[kH], b2s[kH], w3s[kH];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, li = lane & 15, lk = lane >> 4;
+  for (int t = tid; t < kIn * kH; t += 256) w1s[t / kH][t % kH] = W[oW1 + t];
+  for (int t = tid; t < kH * kH; t += 256) w2s[t / kH][t % kH] = W[oW2 + t];
+  if (tid < kH) {
+    b1s[tid] = W[ob1 + tid];
+    b2s[tid] = W[ob2 + tid];
+    w3s[tid] = W[oW3 + tid];
   }
+  const float b3 = W[ob3];
   __syncthreads();
-  const int u = tid & (kH - 1);
-  const int rb = tid >> 7;  // 0 or 1
-  {
-    float acc[kRows / 2];
-    const float b = W[ob1 + u];
-    for (int j = 0; j < kRows / 2; ++j) acc[j] = b;
-    for (int i = 0; i < kIn; ++i) {
-      const float w = W[oW1 + i * kH + u];
-      for (int j = 0; j < kRows / 2; ++j) acc[j] += sx[rb + 2 * j][i] * w;
-    }
-    for (int j = 0; j < kRows / 2; ++j) a1[rb + 2 * j][u] = fmaxf(acc[j], 0.0f);
-  }
-  __syncthreads();
-  {
-    float acc[kRows / 2];
-    const float b = W[ob2 + u];
-    for (int j = 0; j < kRows / 2; ++j) acc[j] = b;
-    for (int k = 0; k < kH; ++k) {
-      const float w = W[oW2 + k * kH + u];
-      for (int j = 0; j < kRows / 2; ++j) acc[j] += a1[rb + 2 * j][k] * w;
-    }
-    for (int j = 0; j < kRows / 2; ++j) a2[rb + 2 * j][u] = fmaxf(acc[j], 0.0f);
-  }
-  __syncthreads();
-  {
-    const int r = tid >> 3, c = tid & 7;
-    float s = 0.0f;
-    for (int k = c * 16; k < c * 16 + 16; ++k) s += a2[r][k] * W[oW3 + k];
-    yp[r][c] = s;
-  }
-  __syncthreads();
-  if (tid < kRows) {
-    float s = W[ob3];
-    for (int c = 0; c < 8; ++c) s += yp[tid][c];
-    if (r0 + tid < B) y[r0 + tid] = s;
-  }
-  if (act) {
-    for (int t = tid; t < kRows * kH; t += 256) {
-      const int r = t / kH, k = t % kH;
-      if (r0 + r < B) {
-        act[(r0 + r) * (2 * kH) + k] = a1[r][k];
-        act[(r0 + r) * (2 * kH) + kH + k] = a2[r][k];
+  const long long groups = (B + kFwdRows - 1) / kFwdRows;
+  for (long long g = blockIdx.x; g < groups; g += gridDim.x) {
+    const long long r0 = g * kFwdRows + 16 * wave;
+    {
+      const long long ra = r0 + li;
+      float xa[4];
+      for (int s = 0; s < 4; ++s) xa[s] = (ra < B) ? x[ra * kIn + 4 * s + lk] : 0.0f;
+      for (int t = 0; t < 8; ++t) {
+        f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+        for (int s = 0; s < 4; ++s) acc = mma4(xa[s], w1s[4 * s + lk][16 * t + li], acc);
+        for (int r = 0; r < 4; ++r)
+          a1t[wave][4 * lk + r][16 * t + li] = fmaxf(acc[r] + b1s[16 * t + li], 0.0f);
       }
     }
+    __syncthreads();
+    f32x4 acc[8];
+    for (int t = 0; t < 8; ++t) acc[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int s = 0; s < kH / 4; ++s) {
+      const float a = a1t[wave][li][4 * s + lk];
+      for (int t = 0; t < 8; ++t) acc[t] = mma4(a, w2s[4 * s + lk][16 * t + li], acc[t]);
+    }
+    float ys[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+    for (int t = 0; t < 8; ++t) {
+      const int col = 16 * t + li;
+      for (int r = 0; r < 4; ++r) {
+        const float a2 = fmaxf(acc[t][r] + b2s[col], 0.0f);
+        acc[t][r] = a2;
+        ys[r] += a2 * w3s[col];
+      }
+    }
+    for (int r = 0; r < 4; ++r)
+      for (int off = 1; off < 16; off <<= 1) ys[r] += __shfl_xor(ys[r], off);
+    if (li == 0) {
+      for (int r = 0; r < 4; ++r) {
+        const long long row = r0 + 4 * lk + r;
+        if (row < B) y[row] = ys[r] + b3;
+      }
+    }
+    if (act) {
+      for (int t = 0; t < 8; ++t) {
+        for (int r = 0; r < 4; ++r) {
+          const long long row = r0 + 4 * lk + r;
+          if (row < B) {
+            act[row * (2 * kH) + 16 * t + li] = a1t[wave][4 * lk + r][16 * t + li];
+            act[row * (2 * kH) + kH + 16 * t + li] = acc[t][r];
+          }
+        }
+      }
+    }
+    __syncthreads();
   }
 }
 
-// Per-block partial gradient of sum_b dy_b y_b into partial[block][P].
+// Per-block partial gradient of sum_b dy_b y_b into partial[block][P].  Per
+// group of 32 rows:
+//   dz2 = dy W3^T [a2 > 0]               (elementwise, thread per column)
+//   dz1 = (dz2 W2^T) [a1 > 0]            (matrix cores, wavefront w: columns 32w..32w+31)
+//   dW2 += a1^T dz2, dW1 += x^T dz1      (matrix cores, wavefront w: rows 32w.. of dW2,
+//                                         columns 32w.. of dW1; accumulators in registers)
+// plus the column sums for b1, b2, W3 and b3.  Fixed summation order.
 __global__ void __launch_bounds__(256)
 k_mlp_backward_partial(const float* __restrict__ W, const float* __restrict__ x,
                        const float* __restrict__ act, const float* __restrict__ dy, long long B,
                        float* __restrict__ partial) {
-  __shared__ float sx[kRows][kIn];
-  __shared__ float a1[kRows][kH + 1];
-  __shared__ float dz2[kRows][kH + 1];
-  __shared__ float dz1[kRows][kH + 1];
-  __shared__ float sdy[kRows];
-  const long long r0 = (long long)blockIdx.x * kRows;
-  const int tid = threadIdx.x;
+  __shared__ float w2s[kH][kStrideRowLane];
+  __shared__ float a1s[kBwdRows][kStrideColLane];
+  __shared__ float dz2s[kBwdRows][kStrideRowLane];
+  __shared__ float dz1s[kBwdRows][kStrideColLane];
+  __shared__ float xs[kBwdRows][kIn];
+  __shared__ float dys[kBwdRows];
+  __shared__ float red[3][2][kH];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, li = lane & 15, lk = lane >> 4;
+  const int u = tid & (kH - 1), half = tid >> 7;
+  for (int t = tid; t < kH * kH; t += 256) w2s[t / kH][t % kH] = W[oW2 + t];
+  const float w3u = W[oW3 + u];
+  f32x4 acc2[2][8], acc1[2];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 8; ++j) acc2[i][j] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+  acc1[0] = acc1[1] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+  float gW3 = 0.0f, gb2 = 0.0f, gb1 = 0.0f, gb3 = 0.0f;
+  const long long groups = (B + kBwdRows - 1) / kBwdRows;
+  for (long long g = blockIdx.x; g < groups; g += gridDim.x) {
+    const long long r0 = g * kBwdRows;
+    __syncthreads();  // previous group consumed; w2s staged
+    for (int t = tid; t < kBwdRows * kIn; t += 256) {
+      const long long r = r0 + t / kIn;
+      xs[t / kIn][t % kIn] = (r < B) ? x[r * kIn + t % kIn] : 0.0f;
+    }
+    if (tid < kBwdRows) dys[tid] = (r0 + tid < B) ? dy[r0 + tid] : 0.0f;
+    for (int r = half; r < kBwdRows; r += 2) {
+      const long long row = r0 + r;
+      const bool ok = row < B;
+      const float a1v = ok ? act[row * (2 * kH) + u] : 0.0f;
+      const float a2v = ok ? act[row * (2 * kH) + kH + u] : 0.0f;
+      const float d = ok ? dy[row] : 0.0f;
+      const float z = (a2v > 0.0f) ? d * w3u : 0.0f;
+      a1s[r][u] = a1v;
+      dz2s[r][u] = z;
+      gW3 += a2v * d;
+      gb2 += z;
+    }
+    __syncthreads();
+    if (tid == 0)
+      for (int r = 0; r < kBwdRows; ++r) gb3 += dys[r];
+    {
+      f32x4 acc[2][2];
+      for (int i = 0; i < 2; ++i) acc[i][0] = acc[i][1] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+      for (int s = 0; s < kH / 4; ++s) {
+        const float a0 = dz2s[li][4 * s + lk], a1 = dz2s[16 + li][4 * s + lk];
+        for (int t = 0; t < 2; ++t) {
+          const float b = w2s[32 * wave + 16 * t + li][4 * s + lk];
+          acc[0][t] = mma4(a0, b, acc[0][t]);
+          acc[1][t] = mma4(a1, b, acc[1][t]);
+        }
+      }
+      for (int i = 0; i < 2; ++i)
+        for (int t = 0; t < 2; ++t)
+          for (int r = 0; r < 4; ++r) {
+            const int row = 16 * i + 4 * lk + r, col = 32 * wave + 16 * t + li;
+            dz1s[row][col] = (a1s[row][col] > 0.0f) ? acc[i][t][r] : 0.0f;
+          }
+    }
+    __syncthreads();
+    for (int r = half; r < kBwdRows; r += 2) gb1 += dz1s[r][u];
+    for (int s = 0; s < kBwdRows / 4; ++s) {
+      const int rr = 4 * s + lk;
+      const float a0 = a1s[rr][32 * wave + li], a1 = a1s[rr][32 * wave + 16 + li];
+      for (int j = 0; j < 8; ++j) {
+        const float b = dz2s[rr][16 * j + li];
+        acc2[0][j] = mma4(a0, b, acc2[0][j]);
+        acc2[1][j] = mma4(a1, b, acc2[1][j]);
+      }
+      const float ax = xs[rr][li];
+      for (int t = 0; t < 2; ++t) acc1[t] = mma4(ax, dz1s[rr][32 * wave + 16 * t + li], acc1[t]);
+    }
+  }
+  red[0][half][u] = gW3;
+  red[1][half][u] = gb2;
+  red[2][half][u] = gb1;
+  __syncthreads();
   float* out = partial + (size_t)blockIdx.x * kMlpParams;
-  for (int t = tid; t < kRows * kIn; t += 256) {
-    const long long r = r0 + t / kIn;
-    sx[t / kIn][t % kIn] = (r < B) ? x[r * kIn + t % kIn] : 0.0f;
-  }
-  if (tid < kRows) sdy[tid] = (r0 + tid < B) ? dy[r0 + tid] : 0.0f;
-  for (int t = tid; t < kRows * kH; t += 256) {
-    const int r = t / kH, k = t % kH;
-    const bool ok = r0 + r < B;
-    a1[r][k] = ok ? act[(r0 + r) * (2 * kH) + k] : 0.0f;
-    const float a2v = ok ? act[(r0 + r) * (2 * kH) + kH + k] : 0.0f;
-    dz2[r][k] = a2v;  // stash a2 here for the W3 gradient
-  }
-  __syncthreads();
-  // dW3, db3 and dz2 = dy * W3 * [a2 > 0]
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 8; ++j)
+      for (int r = 0; r < 4; ++r)
+        out[oW2 + (32 * wave + 16 * i + 4 * lk + r) * kH + 16 * j + li] = acc2[i][j][r];
+  for (int t = 0; t < 2; ++t)
+    for (int r = 0; r < 4; ++r) out[oW1 + (4 * lk + r) * kH + 32 * wave + 16 * t + li] = acc1[t][r];
   if (tid < kH) {
-    float s = 0.0f;
-    for (int r = 0; r < kRows; ++r) s += dz2[r][tid] * sdy[r];
-    out[oW3 + tid] = s;
+    out[oW3 + tid] = red[0][0][tid] + red[0][1][tid];
+    out[ob2 + tid] = red[1][0][tid] + red[1][1][tid];
+    out[ob1 + tid] = red[2][0][tid] + red[2][1][tid];
   }
-  if (tid == kH) {
-    float s = 0.0f;
-    for (int r = 0; r < kRows; ++r) s += sdy[r];
-    out[ob3] = s;
-  }
-  __syncthreads();
-  for (int t = tid; t < kRows * kH; t += 256) {
-    const int r = t / kH, k = t % kH;
-    const float a2v = dz2[r][k];
-    dz2[r][k] = (a2v > 0.0f) ? sdy[r] * W[oW3 + k] : 0.0f;
-  }
-  __syncthreads();
-  // dW2[k][u] = sum_r a1[r][k] dz2[r][u], db2
-  for (int t = tid; t < kH * kH; t += 256) {
-    const int k = t / kH, u = t % kH;
-    float s = 0.0f;
-    for (int r = 0; r < kRows; ++r) s += a1[r][k] * dz2[r][u];
-    out[oW2 + t] = s;
-  }
-  if (tid < kH) {
-    float s = 0.0f;
-    for (int r = 0; r < kRows; ++r) s += dz2[r][tid];
-    out[ob2 + tid] = s;
-  }
-  // dz1[r][k] = (sum_u dz2[r][u] W2[k][u]) [a1 > 0]
-  for (int t = tid; t < kRows * kH; t += 256) {
-    const int r = t / kH, k = t % kH;
-    float s = 0.0f;
-    for (int u = 0; u < kH; ++u) s += dz2[r][u] * W[oW2 + k * kH + u];
-    dz1[r][k] = (a1[r][k] > 0.0f) ? s : 0.0f;
-  }
-  __syncthreads();
-  for (int t = tid; t < kIn * kH; t += 256) {
-    const int i = t / kH, k = t % kH;
-    float s = 0.0f;
-    for (int r = 0; r < kRows; ++r) s += sx[r][i] * dz1[r][k];
-    out[oW1 + t] = s;
-  }
-  if (tid < kH) {
-    float s = 0.0f;
-    for (int r = 0; r < kRows; ++r) s += dz1[r][tid];
-    out[ob1 + tid] = s;
-  }
+  if (tid == 0) out[ob3] = gb3;
 }
 
 __global__ void k_sum_partials_f32(const float* __restrict__ partial, long long rows, long long P,
@@ -211,13 +268,15 @@ __global__ void k_sum_partials_f32(const float* __restrict__ partial, long long 
   out[p] = s;
 }
 
+// Mean squared error and its gradient dy = 2 (y - t) / B: per-block partial
+// sums of squares, then one block adds them in block order.
 __global__ void __launch_bounds__(256)
-k_mse(const float* __restrict__ y, const float* __restrict__ t, long long B, float* __restrict__ dy,
-      float* __restrict__ loss) {
+k_mse_partial(const float* __restrict__ y, const float* __restrict__ t, long long B,
+              float* __restrict__ dy, float* __restrict__ partial) {
   __shared__ float red[256];
   float s = 0.0f;
   const float inv = 1.0f / (float)B;
-  for (long long i = threadIdx.x; i < B; i += 256) {
+  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < B; i += (long long)gridDim.x * 256) {
     const float r = y[i] - t[i];
     s += r * r;
     dy[i] = 2.0f * r * inv;
@@ -228,7 +287,15 @@ k_mse(const float* __restrict__ y, const float* __restrict__ t, long long B, flo
     if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x == 0) *loss = red[0] * inv;
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+__global__ void k_mse_finish(const float* __restrict__ partial, int nblocks, long long B,
+                             float* __restrict__ loss) {
+  if (threadIdx.x != 0) return;
+  float s = 0.0f;
+  for (int b = 0; b < nblocks; ++b) s += partial[b];
+  *loss = s / (float)B;
 }
 
 __global__ void k_adam(float* __restrict__ W, float* __restrict__ m, float* __restrict__ v,
@@ -263,12 +330,16 @@ hipError_t launch_features(const OpDesc* ops, long long K, const double* fock, c
 hipError_t launch_mlp_forward(const float* W, const float* x, long long B, float* y, float* act,
                               hipStream_t stream) {
   if (B == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_mlp_forward, dim3((unsigned)((B + kRows - 1) / kRows)), dim3(256), 0, stream,
-                     W, x, B, y, act);
+  const long long groups = (B + kFwdRows - 1) / kFwdRows;
+  const unsigned grid = (unsigned)(groups < kMlpMaxBlocks ? groups : kMlpMaxBlocks);
+  hipLaunchKernelGGL(k_mlp_forward, dim3(grid), dim3(256), 0, stream, W, x, B, y, act);
   return hipGetLastError();
 }
 
-long long mlp_backward_partial_rows(long long B) { return (B + kRows - 1) / kRows; }
+long long mlp_backward_partial_rows(long long B) {
+  const long long groups = (B + kBwdRows - 1) / kBwdRows;
+  return groups < kMlpMaxBlocks ? groups : kMlpMaxBlocks;
+}
 
 hipError_t launch_mlp_backward(const float* W, const float* x, const float* act, const float* dy,
                                long long B, float* dW, float* partial, long long partial_rows,
@@ -283,9 +354,16 @@ hipError_t launch_mlp_backward(const float* W, const float* x, const float* act,
   return hipGetLastError();
 }
 
+int mse_partial_count(long long B) {
+  const long long blocks = (B + 255) / 256;
+  return (int)(blocks < kMlpMaxBlocks ? (blocks < 1 ? 1 : blocks) : kMlpMaxBlocks);
+}
+
 hipError_t launch_mse(const float* y, const float* t, long long B, float* dy, float* loss,
-                      hipStream_t stream) {
-  hipLaunchKernelGGL(k_mse, dim3(1), dim3(256), 0, stream, y, t, B, dy, loss);
+                      float* partial, hipStream_t stream) {
+  const int nb = mse_partial_count(B);
+  hipLaunchKernelGGL(k_mse_partial, dim3(nb), dim3(256), 0, stream, y, t, B, dy, partial);
+  hipLaunchKernelGGL(k_mse_finish, dim3(1), dim3(64), 0, stream, partial, nb, B, loss);
   return hipGetLastError();
 }
 

@@ -115,14 +115,14 @@ struct swcs_ctx {
   // scratch
   DevBuf gacc, selected, ncut_state;
   DevBuf partial, partial2, sigma, mu, work, seg_states, acc_tab, gbuf, subset_buf, scalars,
-      exp_keys, exp_amps, exp_tmp_k, exp_tmp_v, sort_scratch, ctr_r, occ, sel_scratch, mlp_partial;
+      exp_keys, exp_amps, exp_tmp_k, exp_tmp_v, sort_scratch, ctr_r, occ, sel_scratch, mlp_partial, mse_partial;
 
   ~swcs_ctx() {
     DevBuf* all[] = {&h, &eri, &J, &K, &fock, &ops, &opmap, &gacc, &selected, &ncut_state, &filt, &keys, &amps, &hash, &ctr, &ckpt_n, &ckpt_ptrs,
                      &gate_tab, &gate_n_in,
                      &partial, &partial2, &sigma, &mu, &work, &seg_states, &acc_tab, &gbuf,
                      &subset_buf, &scalars, &exp_keys, &exp_amps, &exp_tmp_k, &exp_tmp_v,
-                     &sort_scratch, &ctr_r, &occ, &sel_scratch, &mlp_partial};
+                     &sort_scratch, &ctr_r, &occ, &sel_scratch, &mlp_partial, &mse_partial};
     for (DevBuf* b : all) b->release();
     for (auto& b : ckpt) b.release();
     for (hipEvent_t e : ev_start) (void)hipEventDestroy(e);
@@ -1167,7 +1167,8 @@ int swcs_mse(swcs_ctx* c, const float* d_y, const float* d_t, int64_t B, float* 
   if (!c) return SWCS_E_INVALID;
   if (B <= 0 || !d_y || !d_t || !d_dy || !d_loss) return fail(c, SWCS_E_INVALID, "bad mse arguments");
   HIP_TRY(c, hipSetDevice(c->device), "hipSetDevice");
-  HIP_TRY(c, launch_mse(d_y, d_t, B, d_dy, d_loss, c->stream), "mse");
+  HIP_TRY(c, c->mse_partial.ensure((size_t)mse_partial_count(B) * 4), "alloc partial");
+  HIP_TRY(c, launch_mse(d_y, d_t, B, d_dy, d_loss, c->mse_partial.as<float>(), c->stream), "mse");
   return SWCS_OK;
 }
 

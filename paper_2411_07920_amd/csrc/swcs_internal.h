@@ -378,8 +378,9 @@ long long mlp_backward_partial_rows(long long B);
 hipError_t launch_mlp_backward(const float* W, const float* x, const float* act, const float* dy,
                                long long B, float* dW, float* partial, long long partial_rows,
                                hipStream_t stream);
+int mse_partial_count(long long B);
 hipError_t launch_mse(const float* y, const float* t, long long B, float* dy, float* loss,
-                      hipStream_t stream);
+                      float* partial, hipStream_t stream);
 hipError_t launch_adam(float* W, float* m, float* v, const float* g, long long P, float lr,
                        float b1, float b2, float eps, int step, hipStream_t stream);
 hipError_t launch_select(const float* score, const uint32_t* rnd, long long K, long long n_top,
@@ -391,6 +392,5 @@ constexpr int kMlpIn = 16;
 constexpr int kMlpHidden = 128;
 constexpr long long kMlpParams = kMlpIn * kMlpHidden + kMlpHidden + kMlpHidden * kMlpHidden +
                                  kMlpHidden + kMlpHidden + 1;
-constexpr int kMlpRowsPerBlock = 32;
 
 }  // namespace swcs
