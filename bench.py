@@ -303,7 +303,7 @@ def adapt_bench(args):
         def log(r):
             print(f"[adapt {name}] it={r['iter']} E={r.get('E_after', r['E']):.10f} "
                   f"k={r['kstar']} exact={r['n_exact']} pool={1e3 * r['t_pool']:.1f}ms "
-                  f"vqe={1e3 * r.get('t_vqe', 0.0):.1f}ms evals={r.get('vqe_evals', 0)}",
+                  f"vqe={1e3 * r.get('t_vqe', 0.0):.1f}ms evals={r.get('vqe_evals', 0)} n_det={r['n_det']}",
                   file=sys.stderr, flush=True)
 
         ops, theta, hist = adapt.run_adapt(ctx, wl.K, cfg, log=log)
@@ -382,16 +382,25 @@ def micro_bench(args):
     out["gate"] = {"us_per_launch": us, "dets_per_s": (n_in_sum / launches) / (us * 1e-6),
                    "algorithmic_GBps": bytes_per_launch / (us * 1e-6) / 1e9,
                    "frac_hbm": bytes_per_launch / (us * 1e-6) / 1e9 / HBM_PEAK_GBS}
-    if N <= 2_000_000:
-        ctx.set_state(keys, amps)
-        ctx.timer_start("sigma_proj")
+    from math import comb
+    nv = c.n - wl.na
+    C = 2 * wl.na * nv + 2 * comb(wl.na, 2) * comb(nv, 2) + wl.na * wl.na * nv * nv
+    ctx.set_state(keys, amps)
+    for method in ("hole_pairs", "enumerate"):
+        if method == "enumerate" and N > 2_000_000:
+            continue
+        ctx.set_sigma_method(method)
         ctx.energy()
-        l, ms = ctx.timer_stop()
-        from math import comb
-        nv = c.n - wl.na
-        C = 2 * wl.na * nv + 2 * comb(wl.na, 2) * comb(nv, 2) + wl.na * wl.na * nv * nv
-        out["sigma_proj"] = {"ms": ms, "rows_per_s": N / (ms * 1e-3),
-                             "probes_per_s": N * C / (ms * 1e-3), "connections_per_row": C}
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record()
+        ctx.energy()
+        t1.record()
+        torch.cuda.synchronize()
+        ms = t0.elapsed_time(t1)
+        out["sigma_" + method] = {"ms": ms, "rows_per_s": N / (ms * 1e-3),
+                                  "connections_per_row": C}
+    ctx.set_sigma_method("auto")
     ctx.close()
     print(json.dumps(out))
 

@@ -90,6 +90,17 @@ int swcs_set_stream(swcs_ctx* ctx, void* hip_stream);
  * device memory).  Growth past it fails with SWCS_E_CAPACITY. */
 int swcs_set_capacity(swcs_ctx* ctx, int64_t max_dets);
 
+/* How sigma_P (energy, parameter gradients) is formed.  ENUMERATE probes
+ * every single and double excitation of every alive determinant (alive * C
+ * probes).  HOLE_PAIRS groups the determinants by their subsets of N_e - 2
+ * electrons (a sort of n * C(N_e, 2) records) and evaluates only pairs that
+ * share one, which are exactly the pairs within a double excitation.  AUTO
+ * (default) takes HOLE_PAIRS when the probe count would exceed 3e7.  Both
+ * give the same sigma up to summation order.  Returns SWCS_E_INVALID for an
+ * unknown method. */
+enum { SWCS_SIGMA_AUTO = 0, SWCS_SIGMA_ENUMERATE = 1, SWCS_SIGMA_HOLE_PAIRS = 2 };
+int swcs_set_sigma_method(swcs_ctx* ctx, int method);
+
 /* Step 1 of the ADAPT procedure (Sec. II.C): molecular integrals.  h[n*n] and
  * eri[n^4] (host, float64, layouts above).  Rejects non-finite values, an
  * asymmetric h and an eri without 8-fold symmetry (tolerance 1e-12). */
@@ -173,7 +184,8 @@ enum {
   SWCS_K_GATE_REPLAY = 7,   /* one replayed gate with pair logging (adjoint)    */
   SWCS_K_ADJOINT_REC = 8,   /* one reverse step over logged pairs (adjoint)     */
   SWCS_K_SIGMA_PUSH_INTO = 9, /* external sigma on the screened query set        */
-  SWCS_K_CONTRACT_OPS = 10   /* operator-major contraction of a small subset     */
+  SWCS_K_CONTRACT_OPS = 10,  /* operator-major contraction of a small subset     */
+  SWCS_K_HOLEPAIR = 11       /* sigma_P pair evaluation inside hole-pair groups  */
 };
 
 /* From now on record HIP events on the context stream around every launch

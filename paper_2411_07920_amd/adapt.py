@@ -181,7 +181,7 @@ def run_adapt(ctx, K: int, cfg: AdaptConfig, ops0=None, theta0=None, log=None):
     for it in range(cfg.max_iter):
         rec = {"iter": it}
         t0 = time.perf_counter()
-        ctx.apply_ansatz(np.array(ops, dtype=np.int32), theta, cfg.eps, cfg.ncut)
+        n_det = ctx.apply_ansatz(np.array(ops, dtype=np.int32), theta, cfg.eps, cfg.ncut)
         E_cur, _, _ = ctx.energy()
         t1 = time.perf_counter()
         full = (scr is None) or it < cfg.warm_full or (it % cfg.full_every == 0)
@@ -200,7 +200,7 @@ def run_adapt(ctx, K: int, cfg: AdaptConfig, ops0=None, theta0=None, log=None):
         kpos = select_operator(gsel, idx)
         kstar = int(idx[kpos])
         gnorm = float(np.linalg.norm(gsel))
-        rec.update(E=E_cur, n_det=None, full=full, kstar=kstar, gmax=float(abs(gsel[kpos])),
+        rec.update(E=E_cur, n_det=int(n_det), full=full, kstar=kstar, gmax=float(abs(gsel[kpos])),
                    gnorm=gnorm, n_exact=int(len(idx)), t_state=t1 - t0, t_pool=t2 - t1)
         if scr is not None:
             scr.record(idx, gsel)

@@ -231,6 +231,131 @@ k_sigma_proj(const u64* __restrict__ keys, const double* __restrict__ amps,
   }
 }
 
+// ---------------------------------------------------------------- hole pairs
+// sigma_P for large states by grouping instead of enumeration.  Two distinct
+// determinants of one sector have a nonzero Slater-Condon element only if
+// they differ in at most two electrons, so they share at least one subset of
+// N_e - 2 electrons.  Every alive entry emits its C(N_e, 2) such subsets (its
+// key with two occupied bits cleared); after a sort by subset the members of
+// each group are exactly the candidate partners.  A double-excitation pair
+// shares one subset; a single-excitation pair shares N_e - 1 and is counted
+// only on the one that drops the lowest common electron.
+
+// Record g = i * C(ne, 2) + p: subset p of entry i (key ~0 for dead entries).
+__global__ void __launch_bounds__(256)
+k_holepair_emit(const u64* __restrict__ keys, const double* __restrict__ amps, u64 n, int ne,
+                u64* __restrict__ out_key, u64* __restrict__ out_val) {
+  const u64 np = (u64)ne * (u64)(ne - 1) / 2;
+  const u64 total = n * np;
+  const u64 stride = (u64)gridDim.x * blockDim.x;
+  for (u64 g = (u64)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += stride) {
+    const u64 i = g / np;
+    int p = (int)(g - i * np);
+    u64 key = ~0ULL;
+    if (!is_dead(amps[i])) {
+      // pair rank p -> ranks a < b among the occupied bits
+      int a = 0;
+      while (p >= ne - 1 - a) {
+        p -= ne - 1 - a;
+        ++a;
+      }
+      const int b = a + 1 + p;
+      const u64 D = keys[i];
+      u64 x = D;
+      for (int t = 0; t < a; ++t) x &= x - 1;
+      const u64 ba = x & (0ULL - x);
+      for (int t = a; t < b; ++t) x &= x - 1;
+      const u64 bb = x & (0ULL - x);
+      key = D ^ ba ^ bb;
+    }
+    out_key[g] = key;
+    out_val[g] = i;
+  }
+}
+
+// sigma[i] = H_ii psi_i for alive entries, 0 for dead ones.
+__global__ void __launch_bounds__(256)
+k_sigma_diag(const u64* __restrict__ keys, const double* __restrict__ amps, Ints I, u64 n,
+             double* __restrict__ sigma) {
+  const u64 stride = (u64)gridDim.x * blockDim.x;
+  for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const double a = amps[i];
+    sigma[i] = is_dead(a) ? 0.0 : diag_element(I, keys[i]) * a;
+  }
+}
+
+// One thread per sorted record: adds H_{D X} psi(X) over the other members X
+// of its group to sigma(D).
+__global__ void __launch_bounds__(256)
+k_holepair_sigma(const u64* __restrict__ skey, const u64* __restrict__ sidx, u64 total,
+                 const u64* __restrict__ keys, const double* __restrict__ amps, Ints I,
+                 double* __restrict__ sigma) {
+  const u64 stride = (u64)gridDim.x * blockDim.x;
+  for (u64 g = (u64)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += stride) {
+    const u64 S = skey[g];
+    if (S == ~0ULL) continue;
+    const bool prev = g > 0 && skey[g - 1] == S;
+    const bool next = g + 1 < total && skey[g + 1] == S;
+    if (!prev && !next) continue;
+    u64 lo = g;
+    while (lo > 0 && skey[lo - 1] == S) --lo;
+    u64 hi = g + 1;
+    while (hi < total && skey[hi] == S) ++hi;
+    const u64 iD = sidx[g];
+    const u64 D = keys[iD];
+    double acc = 0.0;
+    for (u64 f = lo; f < hi; ++f) {
+      if (f == g) continue;
+      const u64 iX = sidx[f];
+      const u64 X = keys[iX];
+      const u64 diff = D ^ X;
+      const u64 holes = D & diff, parts = X & diff;
+      double h;
+      if (__popcll(diff) == 4) {
+        const int h0 = __ffsll((long long)holes) - 1, h1 = 63 - __clzll((long long)holes);
+        const int p0 = __ffsll((long long)parts) - 1, p1 = 63 - __clzll((long long)parts);
+        h = double_element(I, D, h0, h1, p0, p1);
+      } else {
+        const u64 common = D & X;
+        if (S != (common & (common - 1))) continue;
+        h = single_element(I, D, __ffsll((long long)holes) - 1, __ffsll((long long)parts) - 1);
+      }
+      acc += h * amps[iX];
+    }
+    if (acc != 0.0) unsafeAtomicAdd(&sigma[iD], acc);
+  }
+}
+
+// Per-block partial sums of psi * sigma (partial[b]) and psi^2
+// (partial[grid + b]) over the alive entries.
+__global__ void __launch_bounds__(256)
+k_sigma_dots(const double* __restrict__ amps, const double* __restrict__ sigma, u64 n,
+             double* __restrict__ partial) {
+  __shared__ double r1[256], r2[256];
+  double num = 0.0, nrm = 0.0;
+  const u64 stride = (u64)gridDim.x * blockDim.x;
+  for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const double a = amps[i];
+    if (is_dead(a)) continue;
+    num += a * sigma[i];
+    nrm += a * a;
+  }
+  r1[threadIdx.x] = num;
+  r2[threadIdx.x] = nrm;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      r1[threadIdx.x] += r1[threadIdx.x + w];
+      r2[threadIdx.x] += r2[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    partial[blockIdx.x] = r1[0];
+    partial[gridDim.x + blockIdx.x] = r2[0];
+  }
+}
+
 // Batch of an external determinant when the accumulation table is split.
 __device__ inline int batch_of(u64 X, int nbatch) {
   return (int)((mix64(X ^ 0x9e3779b97f4a7c15ULL) >> 32) % (u64)nbatch);
@@ -553,6 +678,57 @@ hipError_t launch_sigma_proj(const DeviceState& st, const Ints& I, const ExcSpac
   (void)partial_norm;
   hipLaunchKernelGGL(k_sigma_proj, dim3(grid), dim3(kSigBlock), conn_tables_bytes(E), stream, st.keys, st.amps,
                      st.hash, st.hmask, st.filt, st.fmask, I, E, n, sigma, partial_num);
+  return hipGetLastError();
+}
+
+hipError_t launch_holepair_emit(const DeviceState& st, u64 n, int ne, u64* out_key, u64* out_val,
+                                int grid, hipStream_t stream) {
+  hipLaunchKernelGGL(k_holepair_emit, dim3(grid), dim3(256), 0, stream, st.keys, st.amps, n, ne,
+                     out_key, out_val);
+  return hipGetLastError();
+}
+
+hipError_t launch_sigma_diag(const DeviceState& st, const Ints& I, u64 n, double* sigma, int grid,
+                             hipStream_t stream) {
+  hipLaunchKernelGGL(k_sigma_diag, dim3(grid), dim3(256), 0, stream, st.keys, st.amps, I, n, sigma);
+  return hipGetLastError();
+}
+
+hipError_t launch_holepair_sigma(const DeviceState& st, const Ints& I, const u64* skey,
+                                 const u64* sidx, u64 total, double* sigma, int grid,
+                                 hipStream_t stream) {
+  hipLaunchKernelGGL(k_holepair_sigma, dim3(grid), dim3(256), 0, stream, skey, sidx, total, st.keys,
+                     st.amps, I, sigma);
+  return hipGetLastError();
+}
+
+hipError_t launch_sigma_dots(const DeviceState& st, const double* sigma, u64 n, double* partial,
+                             int grid, hipStream_t stream) {
+  hipLaunchKernelGGL(k_sigma_dots, dim3(grid), dim3(256), 0, stream, st.amps, sigma, n, partial);
+  return hipGetLastError();
+}
+
+// Number of occupied slots of an accumulation table: per-block partial
+// counts (as doubles, exact below 2^53) in partial[blockIdx.x].
+__global__ void __launch_bounds__(256)
+k_count_keys(const AccSlot* __restrict__ tab, u64 slots, double* __restrict__ partial) {
+  __shared__ double red[256];
+  double cnt = 0.0;
+  const u64 stride = (u64)gridDim.x * blockDim.x;
+  for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < slots; i += stride)
+    cnt += (tab[i].key != kEmptyKey) ? 1.0 : 0.0;
+  red[threadIdx.x] = cnt;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+hipError_t launch_count_keys(const AccSlot* tab, u64 slots, double* partial, int grid,
+                             hipStream_t stream) {
+  hipLaunchKernelGGL(k_count_keys, dim3(grid), dim3(256), 0, stream, tab, slots, partial);
   return hipGetLastError();
 }
 

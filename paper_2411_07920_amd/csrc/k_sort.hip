@@ -33,7 +33,8 @@ k_radix_hist(const u64* __restrict__ keys, u64 count, int shift, u64* __restrict
   counts[(u64)threadIdx.x * nblocks + blockIdx.x] = hist[threadIdx.x];
 }
 
-// In-place exclusive scan of data[len] with one block of 1024 threads.
+// In-place exclusive scan of data[len] with one block of 1024 threads (for
+// short arrays, and for the block sums of the multi-block scan below).
 __global__ void __launch_bounds__(1024) k_scan_exclusive(u64* __restrict__ data, u64 len) {
   __shared__ u64 part[1024];
   const u64 per = (len + 1023) / 1024;
@@ -55,6 +56,89 @@ __global__ void __launch_bounds__(1024) k_scan_exclusive(u64* __restrict__ data,
     data[i] = run;
     run += v;
   }
+}
+
+// Multi-block exclusive scan: chunk sums, a scan of the sums, then each
+// block scans its chunk from its offset.
+constexpr int kScanThreads = 1024;
+constexpr int kScanItems = 4;
+constexpr u64 kScanChunk = (u64)kScanThreads * kScanItems;
+constexpr u64 kScanSingleBlock = 1ULL << 16;
+
+__device__ inline u64 block_exclusive_1024(u64 v, u64* part, u64* total) {
+  part[threadIdx.x] = v;
+  __syncthreads();
+  for (int off = 1; off < kScanThreads; off <<= 1) {
+    const u64 w = (threadIdx.x >= (unsigned)off) ? part[threadIdx.x - off] : 0;
+    __syncthreads();
+    part[threadIdx.x] += w;
+    __syncthreads();
+  }
+  const u64 incl = part[threadIdx.x];
+  *total = part[kScanThreads - 1];
+  return incl - v;
+}
+
+__global__ void __launch_bounds__(kScanThreads)
+k_scan_chunk_sums(const u64* __restrict__ data, u64 len, u64* __restrict__ sums) {
+  __shared__ u64 red[kScanThreads];
+  const u64 base = (u64)blockIdx.x * kScanChunk;
+  u64 s = 0;
+  for (int j = 0; j < kScanItems; ++j) {
+    const u64 i = base + (u64)j * kScanThreads + threadIdx.x;
+    if (i < len) s += data[i];
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = kScanThreads / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) sums[blockIdx.x] = red[0];
+}
+
+__global__ void __launch_bounds__(kScanThreads)
+k_scan_chunk_apply(u64* __restrict__ data, u64 len, const u64* __restrict__ offs) {
+  __shared__ u64 stage[kScanChunk];
+  __shared__ u64 part[kScanThreads];
+  const u64 base = (u64)blockIdx.x * kScanChunk;
+  for (int j = 0; j < kScanItems; ++j) {
+    const u64 i = base + (u64)j * kScanThreads + threadIdx.x;
+    stage[(u64)j * kScanThreads + threadIdx.x] = (i < len) ? data[i] : 0;
+  }
+  __syncthreads();
+  u64 v[kScanItems], t = 0;
+  for (int j = 0; j < kScanItems; ++j) {
+    v[j] = stage[(u64)threadIdx.x * kScanItems + j];
+    t += v[j];
+  }
+  u64 total;
+  u64 run = offs[blockIdx.x] + block_exclusive_1024(t, part, &total);
+  for (int j = 0; j < kScanItems; ++j) {
+    stage[(u64)threadIdx.x * kScanItems + j] = run;
+    run += v[j];
+  }
+  __syncthreads();
+  for (int j = 0; j < kScanItems; ++j) {
+    const u64 i = base + (u64)j * kScanThreads + threadIdx.x;
+    if (i < len) data[i] = stage[(u64)j * kScanThreads + threadIdx.x];
+  }
+}
+
+// Extra scratch (u64 elements) that scan_exclusive needs for len elements.
+u64 scan_scratch_elems(u64 len) { return len <= kScanSingleBlock ? 0 : (len + kScanChunk - 1) / kScanChunk; }
+
+// Exclusive scan of data[len] in place; sums has scan_scratch_elems(len) elements.
+void scan_exclusive(u64* data, u64 len, u64* sums, hipStream_t stream) {
+  if (len <= kScanSingleBlock) {
+    hipLaunchKernelGGL(k_scan_exclusive, dim3(1), dim3(1024), 0, stream, data, len);
+    return;
+  }
+  const u64 nb = (len + kScanChunk - 1) / kScanChunk;
+  hipLaunchKernelGGL(k_scan_chunk_sums, dim3((unsigned)nb), dim3(kScanThreads), 0, stream, data, len, sums);
+  hipLaunchKernelGGL(k_scan_exclusive, dim3(1), dim3(1024), 0, stream, sums, nb);
+  hipLaunchKernelGGL(k_scan_chunk_apply, dim3((unsigned)nb), dim3(kScanThreads), 0, stream, data, len,
+                     (const u64*)sums);
 }
 
 template <int ROWS>
@@ -107,7 +191,8 @@ k_radix_scatter(const u64* __restrict__ keys_in, const u64* __restrict__ vals_in
 u64 radix_sort_scratch_elems(u64 count) {
   const u64 tile = (u64)kSortThreads * sort_rows(count);
   const u64 nblocks = (count + tile - 1) / tile;
-  return 256 * (nblocks < 1 ? 1 : nblocks);
+  const u64 len = 256 * (nblocks < 1 ? 1 : nblocks);
+  return len + scan_scratch_elems(len);
 }
 
 // Sorts (keys, vals) ascending by the low key_bits bits of the key.  The
@@ -118,7 +203,8 @@ hipError_t radix_sort_pairs(u64* keys, u64* vals, u64* tmp_keys, u64* tmp_vals, 
   const int rows = sort_rows(count);
   const u64 tile = (u64)kSortThreads * rows;
   const int nblocks = (int)((count + tile - 1) / tile);
-  if ((u64)256 * nblocks > scratch_elems) return hipErrorInvalidValue;
+  const u64 len = (u64)256 * nblocks;
+  if (len + scan_scratch_elems(len) > scratch_elems) return hipErrorInvalidValue;
   const int passes = (key_bits + 7) / 8;
   u64 *kin = keys, *vin = vals, *kout = tmp_keys, *vout = tmp_vals;
   for (int p = 0; p < passes; ++p) {
@@ -129,8 +215,7 @@ hipError_t radix_sort_pairs(u64* keys, u64* vals, u64* tmp_keys, u64* tmp_vals, 
     else
       hipLaunchKernelGGL(k_radix_hist<kSortRows>, dim3(nblocks), dim3(kSortThreads), 0, stream, kin,
                          count, shift, scratch, nblocks);
-    hipLaunchKernelGGL(k_scan_exclusive, dim3(1), dim3(1024), 0, stream, scratch,
-                       (u64)256 * nblocks);
+    scan_exclusive(scratch, len, scratch + len, stream);
     if (rows == 1)
       hipLaunchKernelGGL(k_radix_scatter<1>, dim3(nblocks), dim3(kSortThreads), 0, stream, kin, vin,
                          count, shift, scratch, nblocks, kout, vout);
@@ -198,7 +283,10 @@ k_alive_scatter(const u64* __restrict__ keys, const double* __restrict__ amps,
   if (blockIdx.x == nblocks - 1 && threadIdx.x == 0) *d_count = off + running;
 }
 
-u64 compact_scratch_elems(u64 n) { return (n + kSortTile - 1) / kSortTile + 1; }
+u64 compact_scratch_elems(u64 n) {
+  const u64 len = (n + kSortTile - 1) / kSortTile + 1;
+  return len + scan_scratch_elems(len);
+}
 
 // Alive entries in storage order: keys and vals[i] (vals = amps by default).
 hipError_t launch_compact_alive(const DeviceState& st, u64 n, const double* vals, u64* out_keys,
@@ -207,10 +295,10 @@ hipError_t launch_compact_alive(const DeviceState& st, u64 n, const double* vals
   if (!vals) vals = st.amps;
   const int nblocks = (int)((n + kSortTile - 1) / kSortTile);
   if (n == 0) return hipMemsetAsync(d_count, 0, sizeof(u64), stream);
-  if ((u64)nblocks > scratch_elems) return hipErrorInvalidValue;
+  if ((u64)nblocks + scan_scratch_elems((u64)nblocks) > scratch_elems) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_alive_count, dim3(nblocks), dim3(kSortThreads), 0, stream, st.amps, n,
                      scratch);
-  hipLaunchKernelGGL(k_scan_exclusive, dim3(1), dim3(1024), 0, stream, scratch, (u64)nblocks);
+  scan_exclusive(scratch, (u64)nblocks, scratch + nblocks, stream);
   hipLaunchKernelGGL(k_alive_scatter, dim3(nblocks), dim3(kSortThreads), 0, stream, st.keys,
                      st.amps, vals, n, scratch, out_keys, out_amps, d_count, nblocks);
   return hipGetLastError();

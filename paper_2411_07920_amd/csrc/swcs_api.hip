@@ -115,14 +115,17 @@ struct swcs_ctx {
   // scratch
   DevBuf gacc, selected, ncut_state;
   DevBuf partial, partial2, sigma, mu, work, seg_states, acc_tab, gbuf, subset_buf, scalars,
-      exp_keys, exp_amps, exp_tmp_k, exp_tmp_v, sort_scratch, ctr_r, occ, sel_scratch, mlp_partial, mse_partial;
+      exp_keys, exp_amps, exp_tmp_k, exp_tmp_v, sort_scratch, ctr_r, occ, sel_scratch, mlp_partial, mse_partial, hp_key, hp_val, hp_tk, hp_tv;
+  int sigma_method = SWCS_SIGMA_AUTO;
+  double ext_count = 0.0, ext_alive = 0.0;  // distinct external keys of the last full pool pass
 
   ~swcs_ctx() {
     DevBuf* all[] = {&h, &eri, &J, &K, &fock, &ops, &opmap, &gacc, &selected, &ncut_state, &filt, &keys, &amps, &hash, &ctr, &ckpt_n, &ckpt_ptrs,
                      &gate_tab, &gate_n_in,
                      &partial, &partial2, &sigma, &mu, &work, &seg_states, &acc_tab, &gbuf,
                      &subset_buf, &scalars, &exp_keys, &exp_amps, &exp_tmp_k, &exp_tmp_v,
-                     &sort_scratch, &ctr_r, &occ, &sel_scratch, &mlp_partial, &mse_partial};
+                     &sort_scratch, &ctr_r, &occ, &sel_scratch, &mlp_partial, &mse_partial,
+                     &hp_key, &hp_val, &hp_tk, &hp_tv};
     for (DevBuf* b : all) b->release();
     for (auto& b : ckpt) b.release();
     for (hipEvent_t e : ev_start) (void)hipEventDestroy(e);
@@ -540,6 +543,14 @@ int swcs_set_capacity(swcs_ctx* c, int64_t max_dets) {
   return SWCS_OK;
 }
 
+int swcs_set_sigma_method(swcs_ctx* c, int method) {
+  if (!c) return SWCS_E_INVALID;
+  if (method != SWCS_SIGMA_AUTO && method != SWCS_SIGMA_ENUMERATE && method != SWCS_SIGMA_HOLE_PAIRS)
+    return fail(c, SWCS_E_INVALID, "unknown sigma method");
+  c->sigma_method = method;
+  return SWCS_OK;
+}
+
 int swcs_set_integrals(swcs_ctx* c, const double* h, const double* eri, double e_core) {
   if (!c) return SWCS_E_INVALID;
   if (!h || !eri) return fail(c, SWCS_E_INVALID, "null integrals");
@@ -798,14 +809,49 @@ int swcs_get_state(swcs_ctx* c, uint64_t* keys, double* amps, int64_t cap, int64
   return export_sorted(c, h.n, h.alive, nullptr, keys, amps);
 }
 
+// Enumeration probes every connection of every alive entry (alive * C
+// probes); hole-pair grouping sorts n * C(N_e, 2) records instead.  The
+// automatic choice takes grouping once the probe count passes this bound.
+constexpr double kHolePairProbes = 3.0e7;
+
+static bool use_holepair(swcs_ctx* c, u64 alive) {
+  const int ne = c->na + c->nb;
+  if (ne < 2 || c->sigma_method == SWCS_SIGMA_ENUMERATE) return false;
+  if (c->sigma_method == SWCS_SIGMA_HOLE_PAIRS) return true;
+  return (double)alive * (double)c->exc.total > kHolePairProbes;
+}
+
 // sigma_P over the stored entries; (numer, norm2) land in scalars[0..1] on
 // the device, without synchronizing.
 static int energy_enqueue(swcs_ctx* c, u64 n) {
   const int grid = sigma_grid(c, n);
   HIP_TRY(c, c->sigma.ensure(std::max<u64>(1, n) * 8), "alloc sigma");
   HIP_TRY(c, c->partial.ensure((size_t)2 * grid * 8), "alloc partial");
-  TIMED(c, SWCS_K_SIGMA_PROJ, launch_sigma_proj(c->st, ints_view(c), c->exc, n, c->sigma.as<double>(),
-                               c->partial.as<double>(), nullptr, grid, c->stream), "sigma");
+  hipError_t e;
+  const Counters h = get_counters(c, &e);
+  if (e != hipSuccess) return hip_fail(c, e, "read counters");
+  if (n > 0 && use_holepair(c, h.alive)) {
+    const int ne = c->na + c->nb;
+    const u64 total = n * ((u64)ne * (u64)(ne - 1) / 2);
+    HIP_TRY(c, c->hp_key.ensure(total * 8), "alloc hole-pair keys");
+    HIP_TRY(c, c->hp_val.ensure(total * 8), "alloc hole-pair values");
+    HIP_TRY(c, c->hp_tk.ensure(total * 8), "alloc hole-pair keys");
+    HIP_TRY(c, c->hp_tv.ensure(total * 8), "alloc hole-pair values");
+    const u64 scr = radix_sort_scratch_elems(total);
+    HIP_TRY(c, c->sort_scratch.ensure(scr * 8), "alloc sort scratch");
+    const int rg = grid_blocks(c, total, 256);
+    HIP_TRY(c, launch_holepair_emit(c->st, n, ne, c->hp_key.as<u64>(), c->hp_val.as<u64>(), rg, c->stream), "emit");
+    HIP_TRY(c, radix_sort_pairs(c->hp_key.as<u64>(), c->hp_val.as<u64>(), c->hp_tk.as<u64>(), c->hp_tv.as<u64>(),
+                                total, c->nso, c->sort_scratch.as<u64>(), scr, c->stream), "sort");
+    HIP_TRY(c, launch_sigma_diag(c->st, ints_view(c), n, c->sigma.as<double>(), grid_blocks(c, n, 256),
+                                 c->stream), "diagonal");
+    TIMED(c, SWCS_K_HOLEPAIR, launch_holepair_sigma(c->st, ints_view(c), c->hp_key.as<u64>(), c->hp_val.as<u64>(),
+                                  total, c->sigma.as<double>(), rg, c->stream), "hole pairs");
+    HIP_TRY(c, launch_sigma_dots(c->st, c->sigma.as<double>(), n, c->partial.as<double>(), grid, c->stream), "dots");
+  } else {
+    TIMED(c, SWCS_K_SIGMA_PROJ, launch_sigma_proj(c->st, ints_view(c), c->exc, n, c->sigma.as<double>(),
+                                 c->partial.as<double>(), nullptr, grid, c->stream), "sigma");
+  }
   HIP_TRY(c, launch_reduce_partials(c->partial.as<double>(), grid, grid, 2, c->scalars.as<double>(), c->stream), "reduce");
   return SWCS_OK;
 }
@@ -950,31 +996,63 @@ int swcs_pool_gradients(swcs_ctx* c, const int32_t* subset, int64_t n_subset, do
     if (hq.flags & kFlagOverflow) return fail(c, SWCS_E_DEVICE, "sigma table overflow");
     return SWCS_OK;
   }
-  // External-space table: at most alive * (C + 1) distinct keys (and never
-  // more than the sector); load factor <= 1/2; split by key hash when the
-  // table would exceed the memory budget.
+  // External-space table.  At most alive * (C + 1) distinct keys (and never
+  // more than the sector) can occur, but states built by gate chains overlap
+  // heavily, so the table is sized from the distinct-key count of the
+  // previous call scaled by the alive count; load factor <= 1/2; split by key
+  // hash only when the table would exceed the memory budget.  A table that
+  // fills up raises kFlagOverflow and the pass is repeated with twice the
+  // estimate.
   const double bound_d = std::min<double>((double)c->sector, (double)h.alive * (double)(c->exc.total + 1));
+  double guess = bound_d;
+  if (c->ext_count > 0.0 && c->ext_alive > 0.0)
+    guess = std::min(bound_d, 1.5 * c->ext_count * std::max(1.0, (double)h.alive / c->ext_alive));
   size_t free_b = 0, total_b = 0;
   if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) free_b = 0;
-  const double budget = std::max<double>(64.0 * 1024 * 1024, 0.4 * (double)free_b);
-  int nbatch = 1;
-  while ((2.0 * bound_d / nbatch) * sizeof(AccSlot) * 1.25 > budget && nbatch < 4096) nbatch *= 2;
-  u64 slots = next_pow2((u64)std::max<double>(64.0, 2.0 * bound_d / nbatch * (nbatch > 1 ? 1.25 : 1.0)));
-  HIP_TRY(c, c->acc_tab.ensure(slots * sizeof(AccSlot)), "alloc sigma table");
-  for (int b = 0; b < nbatch; ++b) {
-    HIP_TRY(c, hipMemsetAsync(c->acc_tab.p, 0, slots * sizeof(AccSlot), c->stream), "clear table");
-    TIMED(c, SWCS_K_SIGMA_PUSH, launch_sigma_push(c->st, ints_view(c), c->exc, n, c->acc_tab.as<AccSlot>(), slots - 1,
-                                 nbatch, b, sigma_grid(c, n), c->stream), "sigma push");
-    TIMED(c, SWCS_K_POOL_CONTRACT, launch_pool_contract_det(c->st, c->exc, c->n, n, c->opmap.as<HashSlot>(), c->omask,
-                                        d_sel, c->ops.as<OpDesc>(), c->acc_tab.as<AccSlot>(), slots - 1,
-                                        c->gacc.as<double>(), sigma_grid(c, n), c->stream), "contract");
+  const double budget = std::max<double>(64.0 * 1024 * 1024, 0.4 * (double)(free_b + c->acc_tab.bytes));
+  const int cgrid = grid_blocks(c, 1u << 22, 256);
+  HIP_TRY(c, c->partial2.ensure((size_t)cgrid * 8), "alloc partials");
+  for (int attempt = 0;; ++attempt) {
+    int nbatch = 1;
+    while ((2.0 * guess / nbatch) * sizeof(AccSlot) > budget && nbatch < 4096) nbatch *= 2;
+    const u64 slots = next_pow2((u64)std::max<double>(64.0, 2.0 * guess / nbatch * (nbatch > 1 ? 1.25 : 1.0)));
+    HIP_TRY(c, c->acc_tab.ensure(slots * sizeof(AccSlot)), "alloc sigma table");
+    if (attempt > 0) HIP_TRY(c, hipMemsetAsync(c->gacc.p, 0, (size_t)c->K_pool * 8, c->stream), "zero g");
+    double distinct = 0.0;
+    for (int b = 0; b < nbatch; ++b) {
+      HIP_TRY(c, hipMemsetAsync(c->acc_tab.p, 0, slots * sizeof(AccSlot), c->stream), "clear table");
+      TIMED(c, SWCS_K_SIGMA_PUSH, launch_sigma_push(c->st, ints_view(c), c->exc, n, c->acc_tab.as<AccSlot>(), slots - 1,
+                                   nbatch, b, sigma_grid(c, n), c->stream), "sigma push");
+      TIMED(c, SWCS_K_POOL_CONTRACT, launch_pool_contract_det(c->st, c->exc, c->n, n, c->opmap.as<HashSlot>(), c->omask,
+                                          d_sel, c->ops.as<OpDesc>(), c->acc_tab.as<AccSlot>(), slots - 1,
+                                          c->gacc.as<double>(), sigma_grid(c, n), c->stream), "contract");
+      HIP_TRY(c, launch_count_keys(c->acc_tab.as<AccSlot>(), slots, c->partial2.as<double>(), cgrid, c->stream), "count");
+      HIP_TRY(c, launch_reduce_partials(c->partial2.as<double>(), cgrid, cgrid, 1, c->scalars.as<double>() + 24,
+                                        c->stream), "count");
+      double cnt = 0.0;
+      HIP_TRY(c, hipMemcpyAsync(&cnt, c->scalars.as<double>() + 24, 8, hipMemcpyDeviceToHost, c->stream), "copy");
+      Counters hb = read_counters(c, &e);  // synchronizes
+      if (e != hipSuccess) return hip_fail(c, e, "read counters");
+      if (hb.flags & kFlagOverflow) break;
+      distinct += cnt;
+    }
+    Counters h2 = read_counters(c, &e);
+    if (e != hipSuccess) return hip_fail(c, e, "read counters");
+    if (!(h2.flags & kFlagOverflow)) {
+      c->ext_count = distinct;
+      c->ext_alive = (double)h.alive;
+      break;
+    }
+    if (guess >= bound_d || attempt >= 16) return fail(c, SWCS_E_DEVICE, "sigma table overflow");
+    guess = std::min(bound_d, 2.0 * guess);
+    h2.flags &= ~kFlagOverflow;
+    HIP_TRY(c, hipMemcpyAsync(c->ctr.p, &h2, sizeof(h2), hipMemcpyHostToDevice, c->stream), "counters");
+    c->hc = h2;
   }
   HIP_TRY(c, launch_gather_scaled(c->gacc.as<double>(), d_subset, count, norm2, c->gbuf.as<double>(),
                                   c->stream), "gather");
   HIP_TRY(c, hipMemcpyAsync(g_out, c->gbuf.p, (size_t)count * 8, hipMemcpyDeviceToHost, c->stream), "copy g");
-  Counters h2 = read_counters(c, &e);
-  if (e != hipSuccess) return hip_fail(c, e, "read counters");
-  if (h2.flags & kFlagOverflow) return fail(c, SWCS_E_DEVICE, "sigma table overflow");
+  HIP_TRY(c, hipStreamSynchronize(c->stream), "sync");
   return SWCS_OK;
 }
 
@@ -1097,7 +1175,7 @@ int swcs_occupations(swcs_ctx* c, double* n_out) {
 
 int swcs_timer_start(swcs_ctx* c, int kernel_id) {
   if (!c) return SWCS_E_INVALID;
-  if (kernel_id < SWCS_K_CHAIN_LDS || kernel_id > SWCS_K_CONTRACT_OPS)
+  if (kernel_id < SWCS_K_CHAIN_LDS || kernel_id > SWCS_K_HOLEPAIR)
     return fail(c, SWCS_E_INVALID, "unknown kernel id");
   c->timer_kernel = kernel_id;
   c->ev_used = 0;

@@ -95,10 +95,17 @@ struct AccSlot {
   double val;
 };
 
-// Returns false (and adds nothing) if every slot is taken by other keys.
+// Probe limit of the accumulation table: an insert that finds no free slot
+// within this many probes fails (the caller raises kFlagOverflow and the host
+// retries with a larger table), so a lookup that has not met its key within
+// the same distance can stop.
+constexpr u64 kAccMaxProbes = 4096;
+
+// Returns false (and adds nothing) if no slot within kAccMaxProbes is free.
 __device__ inline bool acc_add(AccSlot* tab, u64 mask, u64 key, double v) {
   u64 h = mix64(key) & mask;
-  for (u64 probes = 0; probes <= mask; ++probes) {
+  const u64 lim = mask < kAccMaxProbes ? mask : kAccMaxProbes;
+  for (u64 probes = 0; probes <= lim; ++probes) {
     u64 k = tab[h].key;
     if (k == key) {
       unsafeAtomicAdd(&tab[h].val, v);
@@ -118,7 +125,8 @@ __device__ inline bool acc_add(AccSlot* tab, u64 mask, u64 key, double v) {
 
 __device__ inline bool acc_find(const AccSlot* __restrict__ tab, u64 mask, u64 key, double* v) {
   u64 h = mix64(key) & mask;
-  for (u64 probes = 0; probes <= mask; ++probes) {
+  const u64 lim = mask < kAccMaxProbes ? mask : kAccMaxProbes;
+  for (u64 probes = 0; probes <= lim; ++probes) {
     u64 k = tab[h].key;
     if (k == key) {
       *v = tab[h].val;
@@ -328,6 +336,17 @@ hipError_t launch_restore(double* dst, const double* src, const u64* n_src, u64 
 hipError_t launch_mark_dead_range(double* amps, u64 lo, u64 hi, hipStream_t stream);
 hipError_t launch_sigma_proj(const DeviceState& st, const Ints& I, const ExcSpace& E, u64 n,
                              double* sigma, double* partial_num, double* partial_norm, int grid,
+                             hipStream_t stream);
+hipError_t launch_holepair_emit(const DeviceState& st, u64 n, int ne, u64* out_key, u64* out_val,
+                                int grid, hipStream_t stream);
+hipError_t launch_sigma_diag(const DeviceState& st, const Ints& I, u64 n, double* sigma, int grid,
+                             hipStream_t stream);
+hipError_t launch_holepair_sigma(const DeviceState& st, const Ints& I, const u64* skey,
+                                 const u64* sidx, u64 total, double* sigma, int grid,
+                                 hipStream_t stream);
+hipError_t launch_sigma_dots(const DeviceState& st, const double* sigma, u64 n, double* partial,
+                             int grid, hipStream_t stream);
+hipError_t launch_count_keys(const AccSlot* tab, u64 slots, double* partial, int grid,
                              hipStream_t stream);
 hipError_t launch_mu_init(const DeviceState& st, const double* sigma, u64 n, const double* nn,
                           double* mu, hipStream_t stream);

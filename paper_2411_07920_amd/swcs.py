@@ -25,7 +25,8 @@ SWCS_E_DEVICE = -5
 SWCS_E_UNSUPPORTED = -6
 KERNELS = {"chain_lds": 1, "gate": 2, "sigma_proj": 3, "sigma_push": 4, "pool_contract": 5,
            "adjoint_lds": 6, "gate_replay": 7, "adjoint_rec": 8, "sigma_push_into": 9,
-           "contract_ops": 10}
+           "contract_ops": 10, "holepair": 11}
+SIGMA_METHODS = {"auto": 0, "enumerate": 1, "hole_pairs": 2}
 _NAMES = {0: "SWCS_OK", -1: "SWCS_E_INVALID", -2: "SWCS_E_STATE", -3: "SWCS_E_OOM",
           -4: "SWCS_E_CAPACITY", -5: "SWCS_E_DEVICE", -6: "SWCS_E_UNSUPPORTED"}
 
@@ -55,6 +56,7 @@ SIGNATURES = {
     "swcs_last_error": (ctypes.c_char_p, [_vp]),
     "swcs_set_stream": (ctypes.c_int, [_vp, _vp]),
     "swcs_set_capacity": (ctypes.c_int, [_vp, _i64]),
+    "swcs_set_sigma_method": (ctypes.c_int, [_vp, ctypes.c_int]),
     "swcs_set_integrals": (ctypes.c_int, [_vp, _dp, _dp, ctypes.c_double]),
     "swcs_set_reference": (ctypes.c_int, [_vp, ctypes.c_uint64]),
     "swcs_set_pool": (ctypes.c_int, [_vp, _i32p, _i64]),
@@ -169,6 +171,10 @@ class Context:
 
     def set_capacity(self, max_dets: int):
         self._check(self._lib.swcs_set_capacity(self._h, int(max_dets)))
+
+    def set_sigma_method(self, method: str):
+        """'auto', 'enumerate' or 'hole_pairs' (how sigma_P is formed)."""
+        self._check(self._lib.swcs_set_sigma_method(self._h, SIGMA_METHODS[method]))
 
     def set_integrals(self, h, eri, e_core: float = 0.0):
         h = np.ascontiguousarray(h, dtype=np.float64)
