@@ -396,31 +396,39 @@ k_sigma_push(const u64* __restrict__ keys, const double* __restrict__ amps, Ints
 // generator map) receives psi(D) a_k(D) sigma(X), where a_k(D) = <X|T_k|D>
 // if T_k acts on D and -<X|T_k^dagger|D> if T_k^dagger does.  The canonical
 // orientation (P > Q, R > S, (P, Q) > (R, S)) decides which of the two acts.
-__device__ inline u64 generator_key(int P, int Q, int R, int S) {
-  return 1ULL + (u64)P + ((u64)Q << 8) + ((u64)(R + 1) << 16) + ((u64)(S + 1) << 24);
-}
-
 // Operator of the pool that links D to its connection (holes h0 < h1,
-// particles p0 < p1): returns its index (or -1) and whether T (rather than
-// T^dagger) acts on D.
-__device__ inline long long linking_operator(const HashSlot* __restrict__ opmap, u64 omask, int nh,
-                                             int h0, int h1, int p0, int p1, bool* t_acts) {
-  u64 gk;
+// particles p0 < p1): returns its index (or -1), whether T (rather than
+// T^dagger) acts on D, and the operator's (P, Q, R, S).  The generator table
+// is indexed directly: singles at pair(P, Q), doubles at npairs +
+// tri(pair(P, Q)) + pair(R, S) with pair(a, b) = a (a - 1) / 2 + b.
+__device__ inline int pair_index(int a, int b) { return a * (a - 1) / 2 + b; }
+
+__device__ inline int linking_operator(const int* __restrict__ optab, int npairs, int nh, int h0,
+                                       int h1, int p0, int p1, bool* t_acts, OpDesc* op) {
   if (nh == 1) {
     *t_acts = p0 > h0;
-    gk = *t_acts ? generator_key(p0, h0, -1, -1) : generator_key(h0, p0, -1, -1);
-  } else {
-    *t_acts = p1 > h1;
-    gk = *t_acts ? generator_key(p1, p0, h1, h0) : generator_key(h1, h0, p1, p0);
+    op->P = *t_acts ? p0 : h0;
+    op->Q = *t_acts ? h0 : p0;
+    op->R = op->S = -1;
+    return optab[pair_index(op->P, op->Q)];
   }
-  return hash_find(opmap, omask, gk);
+  *t_acts = p1 > h1;
+  op->P = *t_acts ? p1 : h1;
+  op->Q = *t_acts ? p0 : h0;
+  op->R = *t_acts ? h1 : p1;
+  op->S = *t_acts ? h0 : p0;
+  const int pq = pair_index(op->P, op->Q), rs = pair_index(op->R, op->S);
+  return optab[npairs + pq * (pq - 1) / 2 + rs];
 }
 
+// g_k accumulation, determinant-major: every connection X of every alive D
+// names its linking operator k; adds psi(D) a_k(D) sigma(X) to gacc[k]
+// (only X of the current batch when the sigma table is split).
 __global__ void __launch_bounds__(kSigBlock)
 k_pool_contract_det(const u64* __restrict__ keys, const double* __restrict__ amps, ExcSpace E,
-                    int n_spatial, u64 n, const HashSlot* __restrict__ opmap, u64 omask,
-                    const unsigned char* __restrict__ selected, const OpDesc* __restrict__ ops,
-                    const AccSlot* __restrict__ tab, u64 tmask, double* __restrict__ gacc) {
+                    int n_spatial, u64 n, const int* __restrict__ optab, int npairs,
+                    const unsigned char* __restrict__ selected, const AccSlot* __restrict__ tab,
+                    u64 tmask, int nbatch, int batch, double* __restrict__ gacc) {
   __shared__ SigShared S;
   __shared__ ConnTables T;
   extern __shared__ __align__(16) unsigned char conn_dyn[];
@@ -436,13 +444,14 @@ k_pool_contract_det(const u64* __restrict__ keys, const double* __restrict__ amp
     build_conn_tables(S, E, T);
     __syncthreads();
     for_each_connection(T, D, [&](u64 X, int nh, int h0, int h1, int p0, int p1) {
+      if (nbatch > 1 && batch_of(X, nbatch) != batch) return;
       bool t_acts;
-      const long long k = linking_operator(opmap, omask, nh, h0, h1, p0, p1, &t_acts);
+      OpDesc op;
+      const int k = linking_operator(optab, npairs, nh, h0, h1, p0, p1, &t_acts, &op);
       if (k < 0) return;
       if (selected && !selected[k]) return;
       double sx;
       if (!acc_find(tab, tmask, X, &sx)) return;
-      const OpDesc op = ops[k];
       const double a = t_acts ? (double)phase_of_T(op, D) : -(double)phase_of_T(op, X);
       unsafeAtomicAdd(&gacc[k], psiD * a * sx);
     });
@@ -455,7 +464,7 @@ k_pool_contract_det(const u64* __restrict__ keys, const double* __restrict__ amp
 // evaluating the matrix element only on those hits.
 __global__ void __launch_bounds__(kSigBlock)
 k_query_set(const u64* __restrict__ keys, const double* __restrict__ amps, ExcSpace E, int n_spatial,
-            u64 n, const HashSlot* __restrict__ opmap, u64 omask,
+            u64 n, const int* __restrict__ optab, int npairs,
             const unsigned char* __restrict__ selected, AccSlot* __restrict__ tab, u64 tmask,
             int count_only, u64* __restrict__ counter, unsigned* __restrict__ flags) {
   __shared__ SigShared S;
@@ -474,7 +483,8 @@ k_query_set(const u64* __restrict__ keys, const double* __restrict__ amps, ExcSp
     __syncthreads();
     for_each_connection(T, D, [&](u64 X, int nh, int h0, int h1, int p0, int p1) {
       bool t_acts;
-      const long long k = linking_operator(opmap, omask, nh, h0, h1, p0, p1, &t_acts);
+      OpDesc op;
+      const int k = linking_operator(optab, npairs, nh, h0, h1, p0, p1, &t_acts, &op);
       if (k < 0 || !selected[k]) return;
       if (count_only) {
         ++mine;
@@ -757,20 +767,20 @@ hipError_t launch_sigma_push(const DeviceState& st, const Ints& I, const ExcSpac
 }
 
 hipError_t launch_pool_contract_det(const DeviceState& st, const ExcSpace& E, int n_spatial, u64 n,
-                                   const HashSlot* opmap, u64 omask, const unsigned char* selected,
-                                   const OpDesc* ops, const AccSlot* tab, u64 tmask, double* gacc,
-                                   int grid, hipStream_t stream) {
+                                   const int* optab, int npairs, const unsigned char* selected,
+                                   const AccSlot* tab, u64 tmask, int nbatch, int batch,
+                                   double* gacc, int grid, hipStream_t stream) {
   hipLaunchKernelGGL(k_pool_contract_det, dim3(grid), dim3(kSigBlock), conn_tables_bytes(E), stream, st.keys, st.amps,
-                     E, n_spatial, n, opmap, omask, selected, ops, tab, tmask, gacc);
+                     E, n_spatial, n, optab, npairs, selected, tab, tmask, nbatch, batch, gacc);
   return hipGetLastError();
 }
 
 hipError_t launch_query_set(const DeviceState& st, const ExcSpace& E, int n_spatial, u64 n,
-                            const HashSlot* opmap, u64 omask, const unsigned char* selected,
+                            const int* optab, int npairs, const unsigned char* selected,
                             AccSlot* tab, u64 tmask, int count_only, u64* counter, int grid,
                             hipStream_t stream) {
   hipLaunchKernelGGL(k_query_set, dim3(grid), dim3(kSigBlock), conn_tables_bytes(E), stream, st.keys, st.amps, E,
-                     n_spatial, n, opmap, omask, selected, tab, tmask, count_only, counter,
+                     n_spatial, n, optab, npairs, selected, tab, tmask, count_only, counter,
                      &st.ctr->flags);
   return hipGetLastError();
 }

@@ -79,8 +79,8 @@ struct swcs_ctx {
   int64_t K_pool = 0;
   std::vector<OpDesc> ops_host;
   std::vector<int32_t> pool_rows;
-  DevBuf ops, opmap;
-  u64 omask = 0;
+  DevBuf ops, opmap;  // pool rows; generator table (P, Q, R, S) -> pool index
+  int npairs = 0;
 
   // state
   DevBuf keys, amps, hash, ctr, filt;
@@ -643,24 +643,29 @@ int swcs_set_pool(swcs_ctx* c, const int32_t* rows, int64_t K) {
     }
     ops[(size_t)k] = o;
   }
-  // Generator map (P, Q, R, S) -> pool index, open addressing with the same
-  // hash and probing as the device lookups; rejects duplicate rows.
-  const u64 oslots = next_pow2(std::max<u64>(16, 2 * (u64)K));
-  std::vector<HashSlot> omap((size_t)oslots, HashSlot{0ULL, 0ULL});
+  // Generator table (P, Q, R, S) -> pool index, indexed directly: singles at
+  // pair(P, Q), doubles at npairs + tri(pair(P, Q)) + pair(R, S), with
+  // pair(a, b) = a (a - 1) / 2 + b; -1 where the pool has no operator.
+  // Rejects duplicate rows.
+  const int64_t npairs = (int64_t)c->nso * (c->nso - 1) / 2;
+  std::vector<int> optab((size_t)(npairs + npairs * (npairs - 1) / 2), -1);
+  auto pair_index = [](int64_t a, int64_t b) { return a * (a - 1) / 2 + b; };
   for (int64_t k = 0; k < K; ++k) {
     const OpDesc& o = ops[(size_t)k];
-    const u64 key = 1ULL + (u64)o.P + ((u64)o.Q << 8) + ((u64)(o.R + 1) << 16) + ((u64)(o.S + 1) << 24);
-    u64 h = mix64(key) & (oslots - 1);
-    while (omap[(size_t)h].key != 0ULL) {
-      if (omap[(size_t)h].key == key) return fail(c, SWCS_E_INVALID, "pool row " + std::to_string(k) + " duplicates an earlier row");
-      h = (h + 1) & (oslots - 1);
+    int64_t slot;
+    if (o.R < 0) {
+      slot = pair_index(o.P, o.Q);
+    } else {
+      const int64_t pq = pair_index(o.P, o.Q), rs = pair_index(o.R, o.S);
+      slot = npairs + pq * (pq - 1) / 2 + rs;
     }
-    omap[(size_t)h].key = key;
-    omap[(size_t)h].idx = (u64)k;
+    if (optab[(size_t)slot] >= 0)
+      return fail(c, SWCS_E_INVALID, "pool row " + std::to_string(k) + " duplicates an earlier row");
+    optab[(size_t)slot] = (int)k;
   }
-  HIP_TRY(c, c->opmap.ensure((size_t)oslots * sizeof(HashSlot)), "alloc generator map");
-  HIP_TRY(c, hipMemcpy(c->opmap.p, omap.data(), (size_t)oslots * sizeof(HashSlot), hipMemcpyHostToDevice), "copy generator map");
-  c->omask = oslots - 1;
+  HIP_TRY(c, c->opmap.ensure(optab.size() * sizeof(int)), "alloc generator table");
+  HIP_TRY(c, hipMemcpy(c->opmap.p, optab.data(), optab.size() * sizeof(int), hipMemcpyHostToDevice), "copy generator table");
+  c->npairs = (int)npairs;
   HIP_TRY(c, c->ops.ensure(std::max<size_t>(1, (size_t)K) * sizeof(OpDesc)), "alloc pool");
   if (K > 0) HIP_TRY(c, hipMemcpy(c->ops.p, ops.data(), (size_t)K * sizeof(OpDesc), hipMemcpyHostToDevice), "copy pool");
   c->ops_host.swap(ops);
@@ -959,7 +964,7 @@ int swcs_pool_gradients(swcs_ctx* c, const int32_t* subset, int64_t n_subset, do
       HIP_TRY(c, launch_query_ops(c->st, n, c->ops.as<OpDesc>(), d_subset, n_subset, nullptr, 0, 1,
                                   qcount, c->stream), "count");
     else
-      HIP_TRY(c, launch_query_set(c->st, c->exc, c->n, n, c->opmap.as<HashSlot>(), c->omask, d_sel,
+      HIP_TRY(c, launch_query_set(c->st, c->exc, c->n, n, c->opmap.as<int>(), c->npairs, d_sel,
                                   nullptr, 0, 1, qcount, sigma_grid(c, n), c->stream), "count");
     u64 nq = 0;
     HIP_TRY(c, hipMemcpyAsync(&nq, qcount, 8, hipMemcpyDeviceToHost, c->stream), "copy");
@@ -971,7 +976,7 @@ int swcs_pool_gradients(swcs_ctx* c, const int32_t* subset, int64_t n_subset, do
       HIP_TRY(c, launch_query_ops(c->st, n, c->ops.as<OpDesc>(), d_subset, n_subset,
                                   c->acc_tab.as<AccSlot>(), qslots - 1, 0, nullptr, c->stream), "query set");
     else
-      HIP_TRY(c, launch_query_set(c->st, c->exc, c->n, n, c->opmap.as<HashSlot>(), c->omask, d_sel,
+      HIP_TRY(c, launch_query_set(c->st, c->exc, c->n, n, c->opmap.as<int>(), c->npairs, d_sel,
                                   c->acc_tab.as<AccSlot>(), qslots - 1, 0, nullptr, sigma_grid(c, n),
                                   c->stream), "query set");
     TIMED(c, SWCS_K_SIGMA_PUSH_INTO, launch_sigma_push_into(c->st, ints_view(c), c->exc, n, c->acc_tab.as<AccSlot>(), qslots - 1,
@@ -984,8 +989,8 @@ int swcs_pool_gradients(swcs_ctx* c, const int32_t* subset, int64_t n_subset, do
       HIP_TRY(c, launch_gather_scaled(c->gbuf.as<double>(), nullptr, count, norm2,
                                       c->gbuf.as<double>(), c->stream), "scale");
     } else {
-      TIMED(c, SWCS_K_POOL_CONTRACT, launch_pool_contract_det(c->st, c->exc, c->n, n, c->opmap.as<HashSlot>(), c->omask,
-                                          d_sel, c->ops.as<OpDesc>(), c->acc_tab.as<AccSlot>(), qslots - 1,
+      TIMED(c, SWCS_K_POOL_CONTRACT, launch_pool_contract_det(c->st, c->exc, c->n, n, c->opmap.as<int>(), c->npairs,
+                                          d_sel, c->acc_tab.as<AccSlot>(), qslots - 1, 1, 0,
                                           c->gacc.as<double>(), sigma_grid(c, n), c->stream), "contract");
       HIP_TRY(c, launch_gather_scaled(c->gacc.as<double>(), d_subset, count, norm2, c->gbuf.as<double>(),
                                       c->stream), "gather");
@@ -1023,8 +1028,8 @@ int swcs_pool_gradients(swcs_ctx* c, const int32_t* subset, int64_t n_subset, do
       HIP_TRY(c, hipMemsetAsync(c->acc_tab.p, 0, slots * sizeof(AccSlot), c->stream), "clear table");
       TIMED(c, SWCS_K_SIGMA_PUSH, launch_sigma_push(c->st, ints_view(c), c->exc, n, c->acc_tab.as<AccSlot>(), slots - 1,
                                    nbatch, b, sigma_grid(c, n), c->stream), "sigma push");
-      TIMED(c, SWCS_K_POOL_CONTRACT, launch_pool_contract_det(c->st, c->exc, c->n, n, c->opmap.as<HashSlot>(), c->omask,
-                                          d_sel, c->ops.as<OpDesc>(), c->acc_tab.as<AccSlot>(), slots - 1,
+      TIMED(c, SWCS_K_POOL_CONTRACT, launch_pool_contract_det(c->st, c->exc, c->n, n, c->opmap.as<int>(), c->npairs,
+                                          d_sel, c->acc_tab.as<AccSlot>(), slots - 1, nbatch, b,
                                           c->gacc.as<double>(), sigma_grid(c, n), c->stream), "contract");
       HIP_TRY(c, launch_count_keys(c->acc_tab.as<AccSlot>(), slots, c->partial2.as<double>(), cgrid, c->stream), "count");
       HIP_TRY(c, launch_reduce_partials(c->partial2.as<double>(), cgrid, cgrid, 1, c->scalars.as<double>() + 24,

@@ -356,11 +356,11 @@ hipError_t launch_sigma_push(const DeviceState& st, const Ints& I, const ExcSpac
                              AccSlot* tab, u64 tmask, int nbatch, int batch, int grid,
                              hipStream_t stream);
 hipError_t launch_pool_contract_det(const DeviceState& st, const ExcSpace& E, int n_spatial, u64 n,
-                                   const HashSlot* opmap, u64 omask, const unsigned char* selected,
-                                   const OpDesc* ops, const AccSlot* tab, u64 tmask, double* gacc,
-                                   int grid, hipStream_t stream);
+                                   const int* optab, int npairs, const unsigned char* selected,
+                                   const AccSlot* tab, u64 tmask, int nbatch, int batch,
+                                   double* gacc, int grid, hipStream_t stream);
 hipError_t launch_query_set(const DeviceState& st, const ExcSpace& E, int n_spatial, u64 n,
-                            const HashSlot* opmap, u64 omask, const unsigned char* selected,
+                            const int* optab, int npairs, const unsigned char* selected,
                             AccSlot* tab, u64 tmask, int count_only, u64* counter, int grid,
                             hipStream_t stream);
 hipError_t launch_query_ops(const DeviceState& st, u64 n, const OpDesc* ops, const int* subset,

@@ -156,6 +156,21 @@ def test_spreading_16so_full_parity(swcs, spread):
     run_full(swcs, spread)
 
 
+def test_c2_subset_paths(swcs, c2):
+    """Screened pool gradients on both restricted paths: a subset smaller than
+    the connection count is walked operator-major, a larger one (still under
+    half the pool) determinant-major through the generator table."""
+    ctx = make_ctx(swcs, c2)
+    ctx.apply_ansatz(c2.ops, c2.theta, c2.eps)
+    rng = np.random.default_rng(12)
+    for size in (500, 6000):
+        subset = np.sort(rng.choice(len(c2.pool), size, replace=False)).astype(np.int32)
+        g = ctx.pool_gradients(subset)
+        g_ref = c2.orc.pool_gradients(c2.st, c2.pool, subset=subset)
+        assert np.abs(g - g_ref).max() < TOL
+    ctx.close()
+
+
 def test_c3_parity_sampled_pool(swcs):
     case = config_case("c3")
     rng = np.random.default_rng(3)
