@@ -9,6 +9,7 @@
 namespace swcs {
 
 constexpr int kChainThreads = 1024;
+constexpr int kGateChunk = 256;  // gate descriptors staged in LDS at a time
 
 // Deterministic block sum (fixed order over the 16 waves).
 __device__ inline double block_sum_1024(double v, double* wsum) {
@@ -90,6 +91,7 @@ k_chain_lds(u64* __restrict__ keys, double* __restrict__ amps, Counters* __restr
   __shared__ unsigned s_n, s_app, s_alive;
   __shared__ int s_dalive;
   __shared__ int s_stop;
+  __shared__ GateDesc sg[kGateChunk];
   const int tid = threadIdx.x;
   if (tid == 0) {
     s_n = (unsigned)ctr->n;
@@ -117,6 +119,12 @@ k_chain_lds(u64* __restrict__ keys, double* __restrict__ amps, Counters* __restr
   for (unsigned i = tid; i < n0; i += kChainThreads) S.insert(skeys[i], (int)i);
   __syncthreads();
   for (int g = g0; g < M; ++g) {
+    if ((g - g0) % kGateChunk == 0) {
+      // stage the next chunk of gate descriptors (all earlier reads of sg done)
+      __syncthreads();
+      for (int t = tid; t < kGateChunk && g + t < M; t += kChainThreads) sg[t] = gates[g + t];
+      __syncthreads();
+    }
     const unsigned n = s_n, alive = s_alive;
     if (ckpt && g % seg == 0) {
       double* dst = ckpt[g / seg];
@@ -128,7 +136,7 @@ k_chain_lds(u64* __restrict__ keys, double* __restrict__ amps, Counters* __restr
       if (tid == 0) s_stop = g;
       break;  // uniform: every thread read the same n and alive
     }
-    const GateDesc gd = gates[g];
+    const GateDesc gd = sg[(g - g0) % kGateChunk];
     int dal = 0;
     for (unsigned i = tid; i < n; i += kChainThreads) {
       const GateOut o = gate_entry(S, i, gd.op, gd.c, gd.s, eps);
@@ -210,6 +218,7 @@ k_adjoint_lds(const u64* __restrict__ keys, unsigned n, const GateDesc* __restri
   __shared__ int sslots[2 * CAP];
   __shared__ double wsum[kChainThreads / 64];
   __shared__ unsigned cnt[kMaxSeg];
+  __shared__ GateDesc sg[kMaxSeg];
   const int tid = threadIdx.x;
   for (int t = tid; t < 2 * CAP; t += kChainThreads) sslots[t] = 0;
   for (int t = tid; t < kMaxSeg; t += kChainThreads) cnt[t] = 0;
@@ -230,9 +239,10 @@ k_adjoint_lds(const u64* __restrict__ keys, unsigned n, const GateDesc* __restri
     const unsigned nj = (unsigned)ckpt_n[j];
     const double* src = ckpt[j];
     for (unsigned i = tid; i < n; i += kChainThreads) sW[i] = (i < nj) ? src[i] : dead_value();
+    for (int t = tid; t < len; t += kChainThreads) sg[t] = gates[g_lo + t];
     __syncthreads();
     for (int t = 0; t < len; ++t) {
-      const GateDesc gd = gates[g_lo + t];
+      const GateDesc gd = sg[t];
       PairRec* lg = logbuf + (size_t)t * n;
       for (unsigned i = tid; i < n; i += kChainThreads) {
         const GateOut o = gate_entry(L, i, gd.op, gd.c, gd.s, eps);
@@ -242,15 +252,32 @@ k_adjoint_lds(const u64* __restrict__ keys, unsigned n, const GateDesc* __restri
       __syncthreads();
       if (ncut) lds_ncut(sW, skeys, n, ncut, nst);
     }
+    // Reverse over the segment's logs; each thread's first record of the
+    // next (earlier) gate is loaded while the current gate is processed.
+    PairRec cur{};
+    bool has = false;
+    if (len > 0 && (unsigned)tid < cnt[len - 1]) {
+      cur = logbuf[(size_t)(len - 1) * n + tid];
+      has = true;
+    }
     for (int t = len - 1; t >= 0; --t) {
-      const GateDesc gd = gates[g_lo + t];
+      const GateDesc gd = sg[t];
       const PairRec* lg = logbuf + (size_t)t * n;
       const unsigned c = cnt[t];
+      PairRec nxt{};
+      bool has_next = false;
+      if (t > 0 && (unsigned)tid < cnt[t - 1]) {
+        nxt = logbuf[(size_t)(t - 1) * n + tid];
+        has_next = true;
+      }
       double acc = 0.0;
-      for (unsigned r = tid; r < c; r += kChainThreads) acc += adjoint_pair(lg[r], mu, gd.c, gd.s);
+      if (has) acc += adjoint_pair(cur, mu, gd.c, gd.s);
+      for (unsigned r = tid + kChainThreads; r < c; r += kChainThreads) acc += adjoint_pair(lg[r], mu, gd.c, gd.s);
       __syncthreads();
       const double tot = block_sum_1024(acc, wsum);
       if (tid == 0) dE[g_lo + t] = tot;
+      cur = nxt;
+      has = has_next;
     }
     for (int t = tid; t < len; t += kChainThreads) cnt[t] = 0;
     __syncthreads();

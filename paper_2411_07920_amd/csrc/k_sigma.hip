@@ -366,12 +366,14 @@ __device__ inline int batch_of(u64 X, int nbatch) {
 __global__ void __launch_bounds__(kSigBlock)
 k_sigma_push(const u64* __restrict__ keys, const double* __restrict__ amps, Ints I, ExcSpace E,
              u64 n, AccSlot* __restrict__ tab, u64 tmask, int nbatch, int batch,
-             unsigned* __restrict__ flags) {
+             unsigned* __restrict__ flags, double* __restrict__ inserted) {
   __shared__ SigShared S;
   __shared__ ConnTables T;
   extern __shared__ __align__(16) unsigned char conn_dyn[];
+  __shared__ double red[kSigBlock];
   build_pair_table(S);
   if (threadIdx.x == 0) attach_conn_tables(T, conn_dyn, E);
+  double ins = 0.0;  // keys this thread inserted (exact below 2^53)
   for (u64 d = blockIdx.x; d < n; d += gridDim.x) {
     const double psiD = amps[d];
     if (is_dead(psiD)) continue;
@@ -381,21 +383,22 @@ k_sigma_push(const u64* __restrict__ keys, const double* __restrict__ amps, Ints
     __syncthreads();
     build_conn_tables(S, E, T);
     __syncthreads();
-    if (threadIdx.x == 0 && (nbatch == 1 || batch_of(D, nbatch) == batch))
-      if (!acc_add(tab, tmask, D, diag_element(I, D) * psiD)) atomicOr(flags, kFlagOverflow);
+    if (threadIdx.x == 0 && (nbatch == 1 || batch_of(D, nbatch) == batch)) {
+      const int r = acc_add(tab, tmask, D, diag_element(I, D) * psiD);
+      if (!r) atomicOr(flags, kFlagOverflow);
+      ins += (r == 2) ? 1.0 : 0.0;
+    }
     for_each_connection(T, D, [&](u64 X, int nh, int h0, int h1, int p0, int p1) {
       if (nbatch > 1 && batch_of(X, nbatch) != batch) return;
-      if (!acc_add(tab, tmask, X, connection_element(I, D, nh, h0, h1, p0, p1) * psiD))
-        atomicOr(flags, kFlagOverflow);
+      const int r = acc_add(tab, tmask, X, connection_element(I, D, nh, h0, h1, p0, p1) * psiD);
+      if (!r) atomicOr(flags, kFlagOverflow);
+      ins += (r == 2) ? 1.0 : 0.0;
     });
   }
+  const double tot = block_sum(ins, red);
+  if (threadIdx.x == 0) inserted[blockIdx.x] = tot;
 }
 
-// Pool-gradient contraction, determinant-major: for every alive D and every
-// single / double X of D, the pool operator k linking them (found through the
-// generator map) receives psi(D) a_k(D) sigma(X), where a_k(D) = <X|T_k|D>
-// if T_k acts on D and -<X|T_k^dagger|D> if T_k^dagger does.  The canonical
-// orientation (P > Q, R > S, (P, Q) > (R, S)) decides which of the two acts.
 // Operator of the pool that links D to its connection (holes h0 < h1,
 // particles p0 < p1): returns its index (or -1), whether T (rather than
 // T^dagger) acts on D, and the operator's (P, Q, R, S).  The generator table
@@ -629,28 +632,33 @@ __global__ void k_mark_selected(const int* __restrict__ subset, long long count,
 __global__ void __launch_bounds__(256)
 k_occupations(const u64* __restrict__ keys, const double* __restrict__ amps, u64 n, int nso,
               double* __restrict__ partial) {
-  __shared__ double red[256];
+  __shared__ double red[4][65];
   double acc[65];
-  for (int P = 0; P <= nso; ++P) acc[P] = 0.0;
+#pragma unroll
+  for (int P = 0; P < 65; ++P) acc[P] = 0.0;
   const u64 stride = (u64)gridDim.x * blockDim.x;
   for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
     const double a = amps[i];
     if (is_dead(a)) continue;
     const double w = a * a;
     const u64 D = keys[i];
-    for (int P = 0; P < nso; ++P)
+#pragma unroll
+    for (int P = 0; P < 64; ++P)
       if ((D >> P) & 1ULL) acc[P] += w;
-    acc[nso] += w;
+    acc[64] += w;
   }
-  for (int P = 0; P <= nso; ++P) {
-    red[threadIdx.x] = acc[P];
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-      if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) partial[(size_t)P * gridDim.x + blockIdx.x] = red[0];
-    __syncthreads();
+  // wavefront sums, then the four wavefronts of the block in order
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int P = 0; P < 65; ++P) {
+    double v = acc[P];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if (lane == 0) red[wave][P] = v;
+  }
+  __syncthreads();
+  if ((int)threadIdx.x <= nso) {
+    const int P = ((int)threadIdx.x == nso) ? 64 : (int)threadIdx.x;
+    partial[(size_t)threadIdx.x * gridDim.x + blockIdx.x] = red[0][P] + red[1][P] + red[2][P] + red[3][P];
   }
 }
 
@@ -718,30 +726,6 @@ hipError_t launch_sigma_dots(const DeviceState& st, const double* sigma, u64 n, 
   return hipGetLastError();
 }
 
-// Number of occupied slots of an accumulation table: per-block partial
-// counts (as doubles, exact below 2^53) in partial[blockIdx.x].
-__global__ void __launch_bounds__(256)
-k_count_keys(const AccSlot* __restrict__ tab, u64 slots, double* __restrict__ partial) {
-  __shared__ double red[256];
-  double cnt = 0.0;
-  const u64 stride = (u64)gridDim.x * blockDim.x;
-  for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < slots; i += stride)
-    cnt += (tab[i].key != kEmptyKey) ? 1.0 : 0.0;
-  red[threadIdx.x] = cnt;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
-}
-
-hipError_t launch_count_keys(const AccSlot* tab, u64 slots, double* partial, int grid,
-                             hipStream_t stream) {
-  hipLaunchKernelGGL(k_count_keys, dim3(grid), dim3(256), 0, stream, tab, slots, partial);
-  return hipGetLastError();
-}
-
 hipError_t launch_mu_init(const DeviceState& st, const double* sigma, u64 n, const double* nn,
                           double* mu, hipStream_t stream) {
   u64 g = (n + 255) / 256;
@@ -759,10 +743,10 @@ hipError_t launch_reduce_partials(const double* partial, int count, int stride, 
 }
 
 hipError_t launch_sigma_push(const DeviceState& st, const Ints& I, const ExcSpace& E, u64 n,
-                             AccSlot* tab, u64 tmask, int nbatch, int batch, int grid,
-                             hipStream_t stream) {
+                             AccSlot* tab, u64 tmask, int nbatch, int batch, double* inserted,
+                             int grid, hipStream_t stream) {
   hipLaunchKernelGGL(k_sigma_push, dim3(grid), dim3(kSigBlock), conn_tables_bytes(E), stream, st.keys, st.amps, I, E,
-                     n, tab, tmask, nbatch, batch, &st.ctr->flags);
+                     n, tab, tmask, nbatch, batch, &st.ctr->flags, inserted);
   return hipGetLastError();
 }
 

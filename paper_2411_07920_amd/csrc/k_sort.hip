@@ -33,33 +33,9 @@ k_radix_hist(const u64* __restrict__ keys, u64 count, int shift, u64* __restrict
   counts[(u64)threadIdx.x * nblocks + blockIdx.x] = hist[threadIdx.x];
 }
 
-// In-place exclusive scan of data[len] with one block of 1024 threads (for
-// short arrays, and for the block sums of the multi-block scan below).
-__global__ void __launch_bounds__(1024) k_scan_exclusive(u64* __restrict__ data, u64 len) {
-  __shared__ u64 part[1024];
-  const u64 per = (len + 1023) / 1024;
-  const u64 lo = (u64)threadIdx.x * per;
-  const u64 hi = (lo + per < len) ? lo + per : len;
-  u64 s = 0;
-  for (u64 i = lo; i < hi; ++i) s += data[i];
-  part[threadIdx.x] = s;
-  __syncthreads();
-  for (int off = 1; off < 1024; off <<= 1) {
-    u64 v = (threadIdx.x >= (unsigned)off) ? part[threadIdx.x - off] : 0;
-    __syncthreads();
-    part[threadIdx.x] += v;
-    __syncthreads();
-  }
-  u64 run = (threadIdx.x == 0) ? 0 : part[threadIdx.x - 1];
-  for (u64 i = lo; i < hi; ++i) {
-    const u64 v = data[i];
-    data[i] = run;
-    run += v;
-  }
-}
-
-// Multi-block exclusive scan: chunk sums, a scan of the sums, then each
-// block scans its chunk from its offset.
+// Exclusive scans.  Tiles of kScanChunk elements are loaded coalesced into
+// LDS (kScanItems independent loads per thread), each thread scans
+// kScanItems consecutive elements, and a block scan joins the threads.
 constexpr int kScanThreads = 1024;
 constexpr int kScanItems = 4;
 constexpr u64 kScanChunk = (u64)kScanThreads * kScanItems;
@@ -79,6 +55,46 @@ __device__ inline u64 block_exclusive_1024(u64 v, u64* part, u64* total) {
   return incl - v;
 }
 
+// Scans the tile data[base, base + kScanChunk) in place starting from
+// `carry`; returns the tile total.  Every thread of the block calls it.
+__device__ inline u64 scan_tile(u64* __restrict__ data, u64 len, u64 base, u64 carry, u64* stage,
+                                u64* part) {
+  for (int j = 0; j < kScanItems; ++j) {
+    const u64 i = base + (u64)j * kScanThreads + threadIdx.x;
+    stage[(u64)j * kScanThreads + threadIdx.x] = (i < len) ? data[i] : 0;
+  }
+  __syncthreads();
+  u64 v[kScanItems], t = 0;
+  for (int j = 0; j < kScanItems; ++j) {
+    v[j] = stage[(u64)threadIdx.x * kScanItems + j];
+    t += v[j];
+  }
+  u64 total;
+  u64 run = carry + block_exclusive_1024(t, part, &total);
+  for (int j = 0; j < kScanItems; ++j) {
+    stage[(u64)threadIdx.x * kScanItems + j] = run;
+    run += v[j];
+  }
+  __syncthreads();
+  for (int j = 0; j < kScanItems; ++j) {
+    const u64 i = base + (u64)j * kScanThreads + threadIdx.x;
+    if (i < len) data[i] = stage[(u64)j * kScanThreads + threadIdx.x];
+  }
+  __syncthreads();
+  return total;
+}
+
+// In-place exclusive scan of data[len] with one block (short arrays, and the
+// chunk sums of the multi-block scan below).
+__global__ void __launch_bounds__(kScanThreads) k_scan_exclusive(u64* __restrict__ data, u64 len) {
+  __shared__ u64 stage[kScanChunk];
+  __shared__ u64 part[kScanThreads];
+  u64 carry = 0;
+  for (u64 base = 0; base < len; base += kScanChunk) carry += scan_tile(data, len, base, carry, stage, part);
+}
+
+// Multi-block exclusive scan: chunk sums, a scan of the sums, then each
+// block scans its chunk from its offset.
 __global__ void __launch_bounds__(kScanThreads)
 k_scan_chunk_sums(const u64* __restrict__ data, u64 len, u64* __restrict__ sums) {
   __shared__ u64 red[kScanThreads];
@@ -101,28 +117,7 @@ __global__ void __launch_bounds__(kScanThreads)
 k_scan_chunk_apply(u64* __restrict__ data, u64 len, const u64* __restrict__ offs) {
   __shared__ u64 stage[kScanChunk];
   __shared__ u64 part[kScanThreads];
-  const u64 base = (u64)blockIdx.x * kScanChunk;
-  for (int j = 0; j < kScanItems; ++j) {
-    const u64 i = base + (u64)j * kScanThreads + threadIdx.x;
-    stage[(u64)j * kScanThreads + threadIdx.x] = (i < len) ? data[i] : 0;
-  }
-  __syncthreads();
-  u64 v[kScanItems], t = 0;
-  for (int j = 0; j < kScanItems; ++j) {
-    v[j] = stage[(u64)threadIdx.x * kScanItems + j];
-    t += v[j];
-  }
-  u64 total;
-  u64 run = offs[blockIdx.x] + block_exclusive_1024(t, part, &total);
-  for (int j = 0; j < kScanItems; ++j) {
-    stage[(u64)threadIdx.x * kScanItems + j] = run;
-    run += v[j];
-  }
-  __syncthreads();
-  for (int j = 0; j < kScanItems; ++j) {
-    const u64 i = base + (u64)j * kScanThreads + threadIdx.x;
-    if (i < len) data[i] = stage[(u64)j * kScanThreads + threadIdx.x];
-  }
+  (void)scan_tile(data, len, (u64)blockIdx.x * kScanChunk, offs[blockIdx.x], stage, part);
 }
 
 // Extra scratch (u64 elements) that scan_exclusive needs for len elements.

@@ -1015,33 +1015,31 @@ int swcs_pool_gradients(swcs_ctx* c, const int32_t* subset, int64_t n_subset, do
   size_t free_b = 0, total_b = 0;
   if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) free_b = 0;
   const double budget = std::max<double>(64.0 * 1024 * 1024, 0.4 * (double)(free_b + c->acc_tab.bytes));
-  const int cgrid = grid_blocks(c, 1u << 22, 256);
-  HIP_TRY(c, c->partial2.ensure((size_t)cgrid * 8), "alloc partials");
+  const int sgrid = sigma_grid(c, n);
   for (int attempt = 0;; ++attempt) {
     int nbatch = 1;
     while ((2.0 * guess / nbatch) * sizeof(AccSlot) > budget && nbatch < 4096) nbatch *= 2;
-    const u64 slots = next_pow2((u64)std::max<double>(64.0, 2.0 * guess / nbatch * (nbatch > 1 ? 1.25 : 1.0)));
+    u64 slots = next_pow2((u64)std::max<double>(64.0, 2.0 * guess / nbatch * (nbatch > 1 ? 1.25 : 1.0)));
+    // a single table that fits twice over runs at load <= 1/4 (shorter probes)
+    if (nbatch == 1 && 2.0 * (double)slots * sizeof(AccSlot) <= budget) slots *= 2;
     HIP_TRY(c, c->acc_tab.ensure(slots * sizeof(AccSlot)), "alloc sigma table");
+    HIP_TRY(c, c->partial2.ensure((size_t)sgrid * nbatch * 8), "alloc partials");
     if (attempt > 0) HIP_TRY(c, hipMemsetAsync(c->gacc.p, 0, (size_t)c->K_pool * 8, c->stream), "zero g");
-    double distinct = 0.0;
+    double* ins = c->partial2.as<double>();
     for (int b = 0; b < nbatch; ++b) {
       HIP_TRY(c, hipMemsetAsync(c->acc_tab.p, 0, slots * sizeof(AccSlot), c->stream), "clear table");
       TIMED(c, SWCS_K_SIGMA_PUSH, launch_sigma_push(c->st, ints_view(c), c->exc, n, c->acc_tab.as<AccSlot>(), slots - 1,
-                                   nbatch, b, sigma_grid(c, n), c->stream), "sigma push");
+                                   nbatch, b, ins + (size_t)b * sgrid, sgrid, c->stream), "sigma push");
       TIMED(c, SWCS_K_POOL_CONTRACT, launch_pool_contract_det(c->st, c->exc, c->n, n, c->opmap.as<int>(), c->npairs,
                                           d_sel, c->acc_tab.as<AccSlot>(), slots - 1, nbatch, b,
-                                          c->gacc.as<double>(), sigma_grid(c, n), c->stream), "contract");
-      HIP_TRY(c, launch_count_keys(c->acc_tab.as<AccSlot>(), slots, c->partial2.as<double>(), cgrid, c->stream), "count");
-      HIP_TRY(c, launch_reduce_partials(c->partial2.as<double>(), cgrid, cgrid, 1, c->scalars.as<double>() + 24,
-                                        c->stream), "count");
-      double cnt = 0.0;
-      HIP_TRY(c, hipMemcpyAsync(&cnt, c->scalars.as<double>() + 24, 8, hipMemcpyDeviceToHost, c->stream), "copy");
-      Counters hb = read_counters(c, &e);  // synchronizes
-      if (e != hipSuccess) return hip_fail(c, e, "read counters");
-      if (hb.flags & kFlagOverflow) break;
-      distinct += cnt;
+                                          c->gacc.as<double>(), sgrid, c->stream), "contract");
     }
-    Counters h2 = read_counters(c, &e);
+    // distinct keys over all batches (the batches partition the keys)
+    HIP_TRY(c, launch_reduce_partials(ins, sgrid * nbatch, sgrid * nbatch, 1, c->scalars.as<double>() + 24,
+                                      c->stream), "count");
+    double distinct = 0.0;
+    HIP_TRY(c, hipMemcpyAsync(&distinct, c->scalars.as<double>() + 24, 8, hipMemcpyDeviceToHost, c->stream), "copy");
+    Counters h2 = read_counters(c, &e);  // synchronizes
     if (e != hipSuccess) return hip_fail(c, e, "read counters");
     if (!(h2.flags & kFlagOverflow)) {
       c->ext_count = distinct;

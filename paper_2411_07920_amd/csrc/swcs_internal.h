@@ -101,26 +101,28 @@ struct AccSlot {
 // the same distance can stop.
 constexpr u64 kAccMaxProbes = 4096;
 
-// Returns false (and adds nothing) if no slot within kAccMaxProbes is free.
-__device__ inline bool acc_add(AccSlot* tab, u64 mask, u64 key, double v) {
+// Adds v to the entry of key, inserting the key if needed.  Returns 2 if
+// the key was inserted, 1 if it was present, 0 (adding nothing) if no slot
+// within kAccMaxProbes is free.
+__device__ inline int acc_add(AccSlot* tab, u64 mask, u64 key, double v) {
   u64 h = mix64(key) & mask;
   const u64 lim = mask < kAccMaxProbes ? mask : kAccMaxProbes;
   for (u64 probes = 0; probes <= lim; ++probes) {
     u64 k = tab[h].key;
     if (k == key) {
       unsafeAtomicAdd(&tab[h].val, v);
-      return true;
+      return 1;
     }
     if (k == kEmptyKey) {
       u64 prev = atomicCAS(&tab[h].key, kEmptyKey, key);
       if (prev == kEmptyKey || prev == key) {
         unsafeAtomicAdd(&tab[h].val, v);
-        return true;
+        return prev == kEmptyKey ? 2 : 1;
       }
     }
     h = (h + 1) & mask;
   }
-  return false;
+  return 0;
 }
 
 __device__ inline bool acc_find(const AccSlot* __restrict__ tab, u64 mask, u64 key, double* v) {
@@ -346,15 +348,13 @@ hipError_t launch_holepair_sigma(const DeviceState& st, const Ints& I, const u64
                                  hipStream_t stream);
 hipError_t launch_sigma_dots(const DeviceState& st, const double* sigma, u64 n, double* partial,
                              int grid, hipStream_t stream);
-hipError_t launch_count_keys(const AccSlot* tab, u64 slots, double* partial, int grid,
-                             hipStream_t stream);
 hipError_t launch_mu_init(const DeviceState& st, const double* sigma, u64 n, const double* nn,
                           double* mu, hipStream_t stream);
 hipError_t launch_reduce_partials(const double* partial, int count, int stride, int nvec,
                                   double* out, hipStream_t stream);
 hipError_t launch_sigma_push(const DeviceState& st, const Ints& I, const ExcSpace& E, u64 n,
-                             AccSlot* tab, u64 tmask, int nbatch, int batch, int grid,
-                             hipStream_t stream);
+                             AccSlot* tab, u64 tmask, int nbatch, int batch, double* inserted,
+                             int grid, hipStream_t stream);
 hipError_t launch_pool_contract_det(const DeviceState& st, const ExcSpace& E, int n_spatial, u64 n,
                                    const int* optab, int npairs, const unsigned char* selected,
                                    const AccSlot* tab, u64 tmask, int nbatch, int batch,
