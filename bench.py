@@ -52,6 +52,9 @@ def parse():
                     help="instead of the step benchmark: ADAPT iteration time, screened vs "
                          "full pool, on this workload (prints its own JSON line)")
     ap.add_argument("--iters", type=int, default=150)
+    ap.add_argument("--large-state", type=int, default=16_000_000,
+                    help="determinants of the synthetic state for the HBM-path gate and sigma "
+                         "measurement added to the step line (0 = skip)")
     ap.add_argument("--micro", type=int, default=0,
                     help="instead of the step benchmark: gate and sigma kernels on a synthetic "
                          "state of this many determinants (52 spin-orbitals, 16 electrons)")
@@ -215,10 +218,11 @@ def gpu_bench(args, wl):
 
 
 def algorithmic_bytes(kname, wl, r):
-    """Lower-bound bytes the method must move per launch of a kernel (see
-    the design doc): 8 B per stored determinant scanned by a gate; 16 B per
-    (source, connection) read-modify-write of the external sigma table; 8 B
-    per probe of a hash table and 16 B per source determinant read."""
+    """Lower-bound bytes the method must move per launch of a kernel: 8 B per
+    stored determinant scanned by a gate (the key test; the single-workgroup
+    adjoint counts a replay and a reverse step per gate); 16 B per (source,
+    connection) read-modify-write of the external sigma table; 8 B per probe
+    of a hash table and 16 B per source determinant read."""
     from paper_2411_07920_amd.inputs import sector_size  # noqa: F401
     n_in = r["n_in"]
     M = len(n_in)
@@ -345,49 +349,32 @@ def adapt_bench(args):
     print(json.dumps(out))
 
 
-def micro_bench(args):
-    """Kernel rates on a structure-free synthetic state in the 52-spin-orbital,
-    16-electron sector (uniform alpha and beta strings, log-uniform |c|)."""
+def large_state_bench(N, sigma=True):
+    """Gate and sigma_P kernels on a structure-free synthetic state of N
+    determinants in the 52-spin-orbital, 16-electron sector (uniform alpha and
+    beta strings, log-uniform |c|): eight double-excitation gates at eps = 0
+    on the HBM path, then sigma_P by hole-pair grouping (and by enumeration
+    when N <= 2,000,000).  Gate bytes per launch: 16 B per alive input entry
+    (key scan and amplitude) plus 32 B per appended entry (key, amplitude,
+    index slot)."""
     import torch
+    from math import comb
     from paper_2411_07920_amd import swcs
     from paper_2411_07920_amd.inputs import draw_synthetic_state
 
     torch.cuda.set_device(0)
     wl = Workload("c5")
     c = wl.c
-    N = args.micro
     keys, amps = draw_synthetic_state(c.n, wl.na, wl.na, N, 4005)
     ctx = swcs.make_context(c.n, wl.na, wl.na, wl.h, wl.eri, wl.pool, wl.ref,
                             stream=torch.cuda.current_stream())
-    rng = np.random.default_rng(4005)
-    singles = np.flatnonzero(wl.pool[:, 2] < 0)
-    doubles = np.flatnonzero(wl.pool[:, 2] >= 0)
-    ops = np.concatenate([rng.choice(doubles, 16), rng.choice(singles, 4)]).astype(np.int32)
-    theta = rng.uniform(-0.3, 0.3, len(ops))
-    out = {"metric": "kernel rates on a synthetic state", "n_det": N,
-           "workload": "52 spin-orbitals, 16 electrons, uniform sector sample, |c| in [1e-8, 1e-2]"}
-    # Gates in HBM (eps = 0: every created partner is kept).
-    reps = 3
-    tot_ms, launches, n_in_sum = 0.0, 0, 0
-    for _ in range(reps):
-        ctx.set_state(keys, amps)
-        ctx.timer_start("gate")
-        ctx.apply_gates(ops, theta, 0.0)
-        l, ms = ctx.timer_stop()
-        n_in_sum += int(ctx.gate_sizes(len(ops)).sum())
-        tot_ms += ms
-        launches += l
-    us = 1e3 * tot_ms / launches
-    bytes_per_launch = 8.0 * n_in_sum / launches
-    out["gate"] = {"us_per_launch": us, "dets_per_s": (n_in_sum / launches) / (us * 1e-6),
-                   "algorithmic_GBps": bytes_per_launch / (us * 1e-6) / 1e9,
-                   "frac_hbm": bytes_per_launch / (us * 1e-6) / 1e9 / HBM_PEAK_GBS}
-    from math import comb
+    out = {"n_det": N, "workload": f"synthetic state, {N} determinants, 52 spin-orbitals, "
+                                   f"16 electrons, uniform sector sample, |c| in [1e-8, 1e-2]"}
     nv = c.n - wl.na
     C = 2 * wl.na * nv + 2 * comb(wl.na, 2) * comb(nv, 2) + wl.na * wl.na * nv * nv
     ctx.set_state(keys, amps)
     for method in ("hole_pairs", "enumerate"):
-        if method == "enumerate" and N > 2_000_000:
+        if not sigma or (method == "enumerate" and N > 2_000_000):
             continue
         ctx.set_sigma_method(method)
         ctx.energy()
@@ -398,18 +385,42 @@ def micro_bench(args):
         t1.record()
         torch.cuda.synchronize()
         ms = t0.elapsed_time(t1)
-        out["sigma_" + method] = {"ms": ms, "rows_per_s": N / (ms * 1e-3),
-                                  "connections_per_row": C}
+        out["sigma_" + method] = {"ms": ms, "rows_per_s": N / (ms * 1e-3), "connections_per_row": C}
     ctx.set_sigma_method("auto")
+    rng = np.random.default_rng(4005)
+    doubles = np.flatnonzero(wl.pool[:, 2] >= 0)
+    ops = rng.choice(doubles, 8).astype(np.int32)
+    theta = rng.uniform(-0.3, 0.3, len(ops))
+    # A gate that would overflow the capacity returns at once and is launched
+    # again after the host grows the state, so time is averaged per gate.
+    ctx.timer_start("gate")
+    n_out = ctx.apply_gates(ops, theta, 0.0)
+    launches, ms = ctx.timer_stop()
+    n_in = ctx.gate_sizes(len(ops)).astype(np.float64)
+    after = np.append(n_in[1:], n_out)
+    nbytes = float((16.0 * n_in + 32.0 * np.maximum(after - n_in, 0.0)).sum())
+    us = 1e3 * ms / len(ops)
+    gbps = nbytes / len(ops) / (us * 1e-6) / 1e9
+    out["gate"] = {"gates": len(ops), "launches": launches, "us_per_gate": us,
+                   "dets_per_s": float(n_in.sum()) / (ms * 1e-3),
+                   "algorithmic_bytes_per_gate": nbytes / len(ops),
+                   "achieved_GBps": gbps, "frac_hbm": gbps / HBM_PEAK_GBS,
+                   "n_det_in": int(n_in[0]), "n_det_out": int(n_out)}
     ctx.close()
+    return out
+
+
+def micro_bench(args):
+    out = large_state_bench(args.micro)
+    out["metric"] = "kernel rates on a synthetic state"
     print(json.dumps(out))
 
 
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
-              "(see DESIGN.md for how the work would shard).", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path.",
+              file=sys.stderr)
         sys.exit(2)
     if args.adapt:
         adapt_bench(args)
@@ -453,6 +464,8 @@ def main():
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(wl, r["fwd_applies"], r["adj_applies"])
+    if args.large_state:
+        line["large_state"] = large_state_bench(args.large_state)
     print(json.dumps(line))
 
 

@@ -248,4 +248,120 @@ struct LdsMu {
   __device__ void set(u64 i, double v) { p[i] = v; }
 };
 
+// gate_entry for N entries of one thread in the HBM kernels: entry j is
+// i0 + j * stride (skipped at or beyond n).  The entries go through each
+// stage together -- keys, first index probes, amplitudes -- so that their
+// memory requests overlap; outputs are exactly those of gate_entry.
+template <int N>
+__device__ inline void gate_entries_staged(const GlobalStore& S, u64 n, u64 i0, u64 stride,
+                                           const OpDesc& op, double c, double sn, double eps,
+                                           GateOut (&o)[N]) {
+  const u64 pair_mask = op.ann | op.cre;
+  u64 D[N], partner[N], h[N];
+  int kind[N];  // 0: untouched, 1: T acts on D, 2: T^dagger acts on D
+  HashSlot sl[N];
+  long long jx[N];
+  double araw[N], braw[N];
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    const u64 i = i0 + (u64)j * stride;
+    D[j] = (i < n) ? S.keys[i] : 0ULL;
+  }
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    const u64 i = i0 + (u64)j * stride;
+    const bool isT = ((D[j] & op.ann) == op.ann) && ((D[j] & op.cre) == 0);
+    const bool isTd = ((D[j] & op.cre) == op.cre) && ((D[j] & op.ann) == 0);
+    kind[j] = (i < n) ? (isT ? 1 : (isTd ? 2 : 0)) : 0;
+    partner[j] = D[j] ^ pair_mask;
+    if (kind[j]) {
+      h[j] = mix64(partner[j]) & S.hmask;
+      sl[j] = S.hash[h[j]];
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    jx[j] = -1;
+    if (kind[j]) {
+      while (true) {
+        if (sl[j].key == partner[j]) {
+          jx[j] = (long long)sl[j].idx;
+          break;
+        }
+        if (sl[j].key == kEmptyKey) break;
+        h[j] = (h[j] + 1) & S.hmask;
+        sl[j] = S.hash[h[j]];
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    const u64 i = i0 + (u64)j * stride;
+    araw[j] = dead_value();
+    braw[j] = dead_value();
+    if (kind[j] == 1) {
+      araw[j] = S.amps[i];
+      if (jx[j] >= 0) braw[j] = S.amps[jx[j]];
+    } else if (kind[j] == 2 && jx[j] < 0) {
+      braw[j] = S.amps[i];
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    const u64 i = i0 + (u64)j * stride;
+    GateOut& r = o[j];
+    r = GateOut{false, 0ULL, 0.0, 0, false, kNoEntry, kNoEntry, 0.0, 0.0, 0};
+    if (kind[j] == 1) {
+      const bool aliveD = !is_dead(araw[j]), aliveX = !is_dead(braw[j]);
+      if (aliveD || aliveX) {
+        const double s = (double)phase_of_T(op, D[j]);
+        const double a = aliveD ? araw[j] : 0.0;
+        const double b = aliveX ? braw[j] : 0.0;
+        const double nd = c * a - s * (sn * b);
+        const double nx = c * b + s * (sn * a);
+        const bool keepD = !(fabs(nd) < eps);
+        const bool keepX = !(fabs(nx) < eps);
+        S.amps[i] = keepD ? nd : dead_value();
+        if (jx[j] >= 0) {
+          S.amps[jx[j]] = keepX ? nx : dead_value();
+        } else if (keepX) {
+          r.append = true;
+          r.key = partner[j];
+          r.val = nx;
+        }
+        r.dalive = (long long)keepD - (long long)aliveD + (long long)keepX - (long long)aliveX;
+        r.active = true;
+        r.iD = i;
+        r.iX = (jx[j] >= 0) ? (u64)jx[j] : kNoEntry;
+        r.a_old = araw[j];
+        r.b_old = braw[j];
+        r.s = (int)s;
+      }
+    } else if (kind[j] == 2 && jx[j] < 0 && !is_dead(braw[j])) {
+      // D = T partner and the partner is not stored: this thread owns the pair
+      const double s = (double)phase_of_T(op, partner[j]);
+      const double a = 0.0, b = braw[j];
+      const double nd = c * a - s * (sn * b);
+      const double nx = c * b + s * (sn * a);
+      const bool keepD = !(fabs(nd) < eps);
+      const bool keepX = !(fabs(nx) < eps);
+      S.amps[i] = keepX ? nx : dead_value();
+      if (keepD) {
+        r.append = true;
+        r.key = partner[j];
+        r.val = nd;
+      }
+      r.dalive = (long long)keepD + (long long)keepX - 1LL;
+      r.active = true;
+      r.iD = kNoEntry;
+      r.iX = i;
+      r.a_old = dead_value();
+      r.b_old = braw[j];
+      r.s = (int)s;
+    }
+  }
+}
+
+
+
 }  // namespace swcs

@@ -58,28 +58,28 @@ k_gate(u64* __restrict__ keys, double* __restrict__ amps, HashSlot* __restrict__
   __syncthreads();
   if (!s_run) return;
   const u64 n_in = s_n_in;
-  GlobalStore S{keys, amps, hash, hmask};
   long long dalive = 0;
   const int lane = __lane_id();
   const u64 below = (1ULL << lane) - 1ULL;
   const u64 ntiles = (n_in + kGateTile - 1) / kGateTile;
+  const GlobalStore S{keys, amps, hash, hmask};
   for (u64 t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    const u64 i0 = t * (u64)kGateTile + threadIdx.x;
+    GateOut o[kGateItems];
+    gate_entries_staged<kGateItems>(S, n_in, t * (u64)kGateTile + threadIdx.x, kGateThreads, op, c, sn,
+                                    eps, o);
+#pragma unroll
     for (int j = 0; j < kGateItems; ++j) {
-      const u64 i = i0 + (u64)j * kGateThreads;
-      GateOut o{false, 0ULL, 0.0, 0, false, kNoEntry, kNoEntry, 0.0, 0.0, 0};
-      if (i < n_in) o = gate_entry(S, i, op, c, sn, eps);
-      dalive += o.dalive;
-      const u64 m = __ballot(o.append);
+      dalive += o[j].dalive;
+      const u64 m = __ballot(o[j].append);
       if (m) {
         const int leader = __ffsll((long long)m) - 1;
         unsigned b = 0;
         if (lane == leader) b = atomicAdd(&s_cnt, (unsigned)__popcll(m));
         b = __shfl(b, leader);
-        if (o.append) {
+        if (o[j].append) {
           const unsigned slot = b + (unsigned)__popcll(m & below);
-          s_key[slot] = o.key;
-          s_val[slot] = o.val;
+          s_key[slot] = o[j].key;
+          s_val[slot] = o[j].val;
         }
       }
     }
@@ -147,24 +147,25 @@ k_gate_replay(const u64* __restrict__ keys, double* __restrict__ amps,
   __shared__ u64 s_base;
   if (threadIdx.x == 0) s_cnt = 0;
   __syncthreads();
-  GlobalStore S{(u64*)keys, amps, hash, hmask};
+  const GlobalStore S{(u64*)keys, amps, (HashSlot*)hash, hmask};
   const int lane = __lane_id();
   const u64 below = (1ULL << lane) - 1ULL;
   const u64 ntiles = (n + kReplayTile - 1) / kReplayTile;
+  constexpr int kItems = kReplayTile / kGateThreads;
   for (u64 t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    const u64 i0 = t * (u64)kReplayTile + threadIdx.x;
-    for (int j = 0; j < kReplayTile / kGateThreads; ++j) {
-      const u64 i = i0 + (u64)j * kGateThreads;
-      GateOut o{false, 0ULL, 0.0, 0, false, kNoEntry, kNoEntry, 0.0, 0.0, 0};
-      if (i < n) o = gate_entry(S, i, op, c, sn, eps);
-      if (o.append) atomicOr(flags, kFlagOverflow);
-      const u64 m = __ballot(o.active);
+    GateOut o[kItems];
+    gate_entries_staged<kItems>(S, n, t * (u64)kReplayTile + threadIdx.x, kGateThreads, op, c, sn,
+                                eps, o);
+#pragma unroll
+    for (int j = 0; j < kItems; ++j) {
+      if (o[j].append) atomicOr(flags, kFlagOverflow);
+      const u64 m = __ballot(o[j].active);
       if (m) {
         const int leader = __ffsll((long long)m) - 1;
         unsigned b = 0;
         if (lane == leader) b = atomicAdd(&s_cnt, (unsigned)__popcll(m));
         b = __shfl(b, leader);
-        if (o.active) s_rec[b + (unsigned)__popcll(m & below)] = make_rec(o);
+        if (o[j].active) s_rec[b + (unsigned)__popcll(m & below)] = make_rec(o[j]);
       }
     }
     __syncthreads();
