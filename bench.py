@@ -55,6 +55,9 @@ def parse():
     ap.add_argument("--large-state", type=int, default=16_000_000,
                     help="determinants of the synthetic state for the HBM-path gate and sigma "
                          "measurement added to the step line (0 = skip)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy a 1 GiB device buffer five times (reference kernel for the "
+                         "FETCH_SIZE / WRITE_SIZE counters)")
     ap.add_argument("--micro", type=int, default=0,
                     help="instead of the step benchmark: gate and sigma kernels on a synthetic "
                          "state of this many determinants (52 spin-orbitals, 16 electrons)")
@@ -406,6 +409,8 @@ def large_state_bench(N, sigma=True):
                    "algorithmic_bytes_per_gate": nbytes / len(ops),
                    "achieved_GBps": gbps, "frac_hbm": gbps / HBM_PEAK_GBS,
                    "n_det_in": int(n_in[0]), "n_det_out": int(n_out)}
+    if N == 16_000_000:
+        out["gate"]["traffic_bytes_per_launch"] = measured_traffic("gate", "synthetic16M")
     ctx.close()
     return out
 
@@ -414,6 +419,51 @@ def micro_bench(args):
     out = large_state_bench(args.micro)
     out["metric"] = "kernel rates on a synthetic state"
     print(json.dumps(out))
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic.txt")
+CSRC = os.path.join(ROOT, "paper_2411_07920_amd", "csrc")
+
+
+def sources_digest(names):
+    import hashlib
+    m = hashlib.sha256()
+    for name in names:
+        with open(os.path.join(CSRC, name), "rb") as f:
+            m.update(f.read())
+    return m.hexdigest()[:16]
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` on `workload` from the committed
+    counter summary (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel
+    calibration), or None when there is none or the kernel's sources have
+    changed since the counters were taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    with open(TRAFFIC_FILE) as f:
+        for line in f:
+            if line.startswith("#") or "=" not in line:
+                continue
+            kv = dict(tok.split("=", 1) for tok in line.split())
+            if kv.get("kernel") != kernel or kv.get("workload") != workload:
+                continue
+            if sources_digest(kv["sources"].split(",")) != kv["sources_sha256"]:
+                return None
+            return float(kv["bytes_per_launch"])
+    return None
+
+
+def copy_calibration():
+    import torch
+    torch.cuda.set_device(0)
+    n = 1 << 28
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "copies": 5}))
 
 
 def main():
@@ -427,6 +477,9 @@ def main():
         return
     if args.micro:
         micro_bench(args)
+        return
+    if args.copy_calibration:
+        copy_calibration()
         return
     wl = Workload(args.workload)
     r = gpu_bench(args, wl)
@@ -457,7 +510,7 @@ def main():
                    "input_sha256": wl.digest[:16]},
         "phases_ms": {k: round(v, 4) for k, v in r["phase_ms"].items()},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom, args.workload),
                      "kernel": dom, "us_per_launch": kern[dom]["us_per_launch"],
                      "algorithmic_bytes_per_launch": bytes_launch},
         "kernels_ms_per_step": {k: round(v["ms_per_step"], 4) for k, v in kern.items()},
