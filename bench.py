@@ -322,6 +322,7 @@ def adapt_bench(args):
         return ops, theta, hist, wall, E, n_det
 
     iters = args.iters
+    arm(False, False, min(iters, 5))  # untimed warm-up: code load, clocks, first allocations
     _, _, h_full, w_full, E_full, nd_full = arm(False, False, iters)
     ops_s, _, h_scr, w_scr, E_scr, nd_scr = arm(True, False, iters)
     _, _, h_val, _, E_val, _ = arm(True, True, iters)
