@@ -124,6 +124,7 @@ def gpu_bench(args, wl):
     rnd = torch.from_numpy(wl.rand.astype(np.int32)).to(dev)
     nsel = wl.n_top + wl.n_rand
     sel = torch.zeros(nsel, dtype=torch.int32, device=dev)
+    gsel = torch.zeros(nsel, dtype=torch.float64, device=dev)
     xs = torch.zeros((nsel, 16), device=dev)
     ys = torch.zeros(nsel, device=dev)
     act = torch.zeros((nsel, 256), device=dev)
@@ -149,10 +150,10 @@ def gpu_bench(args, wl):
         ctx.features(prev, age, count, feat)
         ctx.mlp_forward(W, feat, score)
         ctx.select(score, rnd, wl.n_top, wl.n_rand, sel)
-        idx = sel.cpu().numpy()
-        g = ctx.pool_gradients(idx)
-        # targets log10(|g| + 1e-12) of the exact gradients of the selection
-        tgt.copy_(torch.from_numpy(np.log10(np.abs(g) + 1e-12).astype(np.float32)))
+        # exact gradients of the selection and their targets log10(|g| + 1e-12),
+        # stream-ordered on the device
+        ctx.pool_gradients_device(sel, gsel)
+        ctx.log_abs(gsel, tgt)
         torch.index_select(feat, 0, sel.long(), out=xs)
         ctx.mlp_forward(W, xs, ys, act)
         ctx.mse(ys, tgt, dy, loss)

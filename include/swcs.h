@@ -156,6 +156,16 @@ int swcs_sigma_projected(swcs_ctx* ctx, uint64_t* keys, double* sigma, int64_t c
  * all K in pool order).  g_out has n_subset (or K) entries. */
 int swcs_pool_gradients(swcs_ctx* ctx, const int32_t* subset, int64_t n_subset, double* g_out);
 
+/* Same as swcs_pool_gradients for a subset, with the subset and the result in
+ * DEVICE memory and no host round trip: d_subset[n_subset] int32 pool indices,
+ * d_g[n_subset] float64 written on the context stream (read it after the
+ * stream has synchronized).  Indices outside [0, K) give NaN in d_g.  The
+ * query table of the selected operators is sized from the bound
+ * (alive determinants x min(n_subset, C)) when that table stays below
+ * 512 MB, otherwise from an exact count, which synchronizes once. */
+int swcs_pool_gradients_device(swcs_ctx* ctx, const int32_t* d_subset, int64_t n_subset,
+                               double* d_g);
+
 /* Analytic parameter gradients (Sec. II.B) of the last swcs_apply_ansatz:
  * dE_dtheta[M] with every gate's kept support held fixed (the pruning acts as
  * a fixed projection; at eps = 0 and no ncut this is the exact gradient).
@@ -227,6 +237,9 @@ int swcs_mlp_backward(swcs_ctx* ctx, const float* d_W, const float* d_x, const f
 /* Mean squared error: *d_loss = mean (y - t)^2 and d_dy = 2 (y - t) / B. */
 int swcs_mse(swcs_ctx* ctx, const float* d_y, const float* d_t, int64_t B, float* d_dy,
              float* d_loss);
+
+/* Screener targets: d_t[i] = log10(|d_g[i]| + 1e-12) as float32 (device). */
+int swcs_log_abs(swcs_ctx* ctx, const double* d_g, int64_t n, float* d_t);
 
 /* One Adam step with bias correction (step >= 1) on P parameters. */
 int swcs_adam_step(swcs_ctx* ctx, float* d_W, float* d_m, float* d_v, const float* d_dW,

@@ -189,13 +189,17 @@ def run_adapt(ctx, K: int, cfg: AdaptConfig, ops0=None, theta0=None, log=None):
             g = ctx.pool_gradients()
             idx = np.arange(K, dtype=np.int32)
             gsel = g
+            rec_idx, rec_g = idx, gsel
             if scr is not None:
                 scr.compute_features(ops)
         else:
             scr.compute_features(ops)
             scr.scores()
-            idx = scr.select()
-            gsel = ctx.pool_gradients(idx)
+            idx_d = scr.select()
+            g_d = scr.exact_gradients(idx_d)
+            idx = idx_d.cpu().numpy()
+            gsel = g_d.cpu().numpy()
+            rec_idx, rec_g = idx_d, g_d
         t2 = time.perf_counter()
         kpos = select_operator(gsel, idx)
         kstar = int(idx[kpos])
@@ -203,7 +207,7 @@ def run_adapt(ctx, K: int, cfg: AdaptConfig, ops0=None, theta0=None, log=None):
         rec.update(E=E_cur, n_det=int(n_det), full=full, kstar=kstar, gmax=float(abs(gsel[kpos])),
                    gnorm=gnorm, n_exact=int(len(idx)), t_state=t1 - t0, t_pool=t2 - t1)
         if scr is not None:
-            scr.record(idx, gsel)
+            scr.record(rec_idx, rec_g)
             t3 = time.perf_counter()
             rec["loss"] = scr.train()
             rec["t_train"] = time.perf_counter() - t3

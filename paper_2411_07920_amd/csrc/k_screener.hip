@@ -298,6 +298,12 @@ __global__ void k_mse_finish(const float* __restrict__ partial, int nblocks, lon
   *loss = s / (float)B;
 }
 
+// Screener targets t = log10(|g| + 1e-12) (float64 arithmetic, float32 result).
+__global__ void k_log_abs(const double* __restrict__ g, long long n, float* __restrict__ t) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) t[i] = (float)log10(fabs(g[i]) + 1e-12);
+}
+
 __global__ void k_adam(float* __restrict__ W, float* __restrict__ m, float* __restrict__ v,
                        const float* __restrict__ g, long long P, float lr, float b1, float b2,
                        float eps, float c1, float c2) {
@@ -364,6 +370,12 @@ hipError_t launch_mse(const float* y, const float* t, long long B, float* dy, fl
   const int nb = mse_partial_count(B);
   hipLaunchKernelGGL(k_mse_partial, dim3(nb), dim3(256), 0, stream, y, t, B, dy, partial);
   hipLaunchKernelGGL(k_mse_finish, dim3(1), dim3(64), 0, stream, partial, nb, B, loss);
+  return hipGetLastError();
+}
+
+hipError_t launch_log_abs(const double* g, long long n, float* t, hipStream_t stream) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_log_abs, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, g, n, t);
   return hipGetLastError();
 }
 

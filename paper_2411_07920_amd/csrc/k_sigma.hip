@@ -628,6 +628,27 @@ __global__ void k_mark_selected(const int* __restrict__ subset, long long count,
   if (t < count) selected[subset[t]] = 1;
 }
 
+// Copy of a caller's device subset with indices outside [0, K) replaced by 0
+// (so every later lookup stays in bounds) ...
+__global__ void k_sanitize_subset(const int* __restrict__ in, long long count, long long K,
+                                  int* __restrict__ out) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < count) {
+    const int k = in[t];
+    out[t] = (k >= 0 && k < K) ? k : 0;
+  }
+}
+
+// ... and NaN written to the gradients of those entries afterwards.
+__global__ void k_nan_invalid(const int* __restrict__ in, long long count, long long K,
+                              double* __restrict__ g) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < count) {
+    const int k = in[t];
+    if (k < 0 || k >= K) g[t] = __longlong_as_double(0x7ff8000000000000LL);
+  }
+}
+
 // Per-block partial sums of psi^2 [P in D] for P < nso and of psi^2.
 __global__ void __launch_bounds__(256)
 k_occupations(const u64* __restrict__ keys, const double* __restrict__ amps, u64 n, int nso,
@@ -809,6 +830,22 @@ hipError_t launch_mark_selected(const int* subset, long long count, unsigned cha
   if (count == 0) return hipSuccess;
   hipLaunchKernelGGL(k_mark_selected, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, stream,
                      subset, count, selected);
+  return hipGetLastError();
+}
+
+hipError_t launch_sanitize_subset(const int* in, long long count, long long K, int* out,
+                                  hipStream_t stream) {
+  if (count == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sanitize_subset, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, stream,
+                     in, count, K, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_nan_invalid(const int* in, long long count, long long K, double* g,
+                              hipStream_t stream) {
+  if (count == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_nan_invalid, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, stream,
+                     in, count, K, g);
   return hipGetLastError();
 }
 

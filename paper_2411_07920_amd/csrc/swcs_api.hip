@@ -917,47 +917,26 @@ static int norm2_enqueue(swcs_ctx* c, u64 n) {
   return SWCS_OK;
 }
 
-int swcs_pool_gradients(swcs_ctx* c, const int32_t* subset, int64_t n_subset, double* g_out) {
-  if (!c) return SWCS_E_INVALID;
-  int r = check_ready(c);
-  if (r) return r;
-  if (!c->have_state) return fail(c, SWCS_E_STATE, "no current state");
-  if (!g_out) return fail(c, SWCS_E_INVALID, "null g_out");
-  const int64_t count = subset ? n_subset : c->K_pool;
-  if (subset) {
-    if (n_subset < 0) return fail(c, SWCS_E_INVALID, "n_subset < 0");
-    for (int64_t t = 0; t < n_subset; ++t)
-      if (subset[t] < 0 || subset[t] >= c->K_pool) return fail(c, SWCS_E_INVALID, "subset index out of range");
-  }
-  if (count == 0) return SWCS_OK;
-  HIP_TRY(c, hipSetDevice(c->device), "hipSetDevice");
-  hipError_t e;
-  Counters h = get_counters(c, &e);
-  if (e != hipSuccess) return hip_fail(c, e, "read counters");
-  const u64 n = h.n;
-  if (h.alive == 0) return fail(c, SWCS_E_STATE, "state is empty");
-  r = norm2_enqueue(c, n);
-  if (r) return r;
-  const double* norm2 = c->scalars.as<double>() + 2;
-  HIP_TRY(c, c->gbuf.ensure((size_t)count * 8), "alloc g");
-  HIP_TRY(c, c->gacc.ensure((size_t)c->K_pool * 8), "alloc g accumulator");
-  HIP_TRY(c, hipMemsetAsync(c->gacc.p, 0, (size_t)c->K_pool * 8, c->stream), "zero g");
-  const int* d_subset = nullptr;
-  const unsigned char* d_sel = nullptr;
-  if (subset) {
-    HIP_TRY(c, c->subset_buf.ensure((size_t)n_subset * 4), "alloc subset");
-    HIP_TRY(c, hipMemcpyAsync(c->subset_buf.p, subset, (size_t)n_subset * 4, hipMemcpyHostToDevice, c->stream), "copy subset");
-    d_subset = c->subset_buf.as<int>();
-    HIP_TRY(c, c->selected.ensure((size_t)c->K_pool), "alloc selection");
-    HIP_TRY(c, hipMemsetAsync(c->selected.p, 0, (size_t)c->K_pool, c->stream), "zero selection");
-    HIP_TRY(c, launch_mark_selected(d_subset, n_subset, c->selected.as<unsigned char>(), c->stream), "mark");
-    d_sel = c->selected.as<unsigned char>();
-  }
-  if (subset && 2 * n_subset < c->K_pool) {
-    // Screened: sigma only on the determinants the selected operators reach.
-    // Small subsets are walked operator-major (|psi| x n_subset activity
-    // tests); larger ones determinant-major through the generator map.
-    const bool op_major = n_subset <= c->exc.total;
+// The screened query table is sized from a bound on its key count (no host
+// round trip) when that table stays below this size, otherwise from an exact
+// count.
+constexpr double kQueryBoundBytes = 512.0 * 1024 * 1024;
+
+// Screened pool gradients of the n_subset operators d_subset (valid device
+// indices) into d_out (device, n_subset doubles): sigma only on the
+// determinants the selected operators reach.  Small subsets are walked
+// operator-major (|psi| x n_subset activity tests), larger ones
+// determinant-major through the generator table.  Synchronizes only when the
+// query table has to be sized by an exact count.
+static int screened_gradients(swcs_ctx* c, u64 n, u64 alive, const int* d_subset, int64_t n_subset,
+                              const unsigned char* d_sel, const double* norm2, double* d_out) {
+  const bool op_major = n_subset <= c->exc.total;
+  const double bound = std::min<double>((double)c->sector,
+                                        (double)alive * (double)(op_major ? n_subset : c->exc.total));
+  u64 nq;
+  if (2.0 * bound * sizeof(AccSlot) <= kQueryBoundBytes) {
+    nq = (u64)bound;
+  } else {
     u64* qcount = c->scalars.as<u64>() + 16;
     HIP_TRY(c, hipMemsetAsync(qcount, 0, 8, c->stream), "zero counter");
     if (op_major)
@@ -966,35 +945,113 @@ int swcs_pool_gradients(swcs_ctx* c, const int32_t* subset, int64_t n_subset, do
     else
       HIP_TRY(c, launch_query_set(c->st, c->exc, c->n, n, c->opmap.as<int>(), c->npairs, d_sel,
                                   nullptr, 0, 1, qcount, sigma_grid(c, n), c->stream), "count");
-    u64 nq = 0;
     HIP_TRY(c, hipMemcpyAsync(&nq, qcount, 8, hipMemcpyDeviceToHost, c->stream), "copy");
     HIP_TRY(c, hipStreamSynchronize(c->stream), "sync");
-    const u64 qslots = next_pow2(std::max<u64>(64, 2 * std::min<u64>(nq, c->sector)));
-    HIP_TRY(c, c->acc_tab.ensure(qslots * sizeof(AccSlot)), "alloc sigma table");
-    HIP_TRY(c, hipMemsetAsync(c->acc_tab.p, 0, qslots * sizeof(AccSlot), c->stream), "clear table");
-    if (op_major)
-      HIP_TRY(c, launch_query_ops(c->st, n, c->ops.as<OpDesc>(), d_subset, n_subset,
-                                  c->acc_tab.as<AccSlot>(), qslots - 1, 0, nullptr, c->stream), "query set");
-    else
-      HIP_TRY(c, launch_query_set(c->st, c->exc, c->n, n, c->opmap.as<int>(), c->npairs, d_sel,
-                                  c->acc_tab.as<AccSlot>(), qslots - 1, 0, nullptr, sigma_grid(c, n),
-                                  c->stream), "query set");
-    TIMED(c, SWCS_K_SIGMA_PUSH_INTO, launch_sigma_push_into(c->st, ints_view(c), c->exc, n, c->acc_tab.as<AccSlot>(), qslots - 1,
-                                      sigma_grid(c, n), c->stream), "sigma push");
-    if (op_major) {
-      HIP_TRY(c, hipMemsetAsync(c->gbuf.p, 0, (size_t)count * 8, c->stream), "zero g");
-      TIMED(c, SWCS_K_CONTRACT_OPS, launch_contract_ops(c->st, n, c->ops.as<OpDesc>(), d_subset, n_subset,
-                                                        c->acc_tab.as<AccSlot>(), qslots - 1,
-                                                        c->gbuf.as<double>(), c->stream), "contract");
-      HIP_TRY(c, launch_gather_scaled(c->gbuf.as<double>(), nullptr, count, norm2,
-                                      c->gbuf.as<double>(), c->stream), "scale");
-    } else {
-      TIMED(c, SWCS_K_POOL_CONTRACT, launch_pool_contract_det(c->st, c->exc, c->n, n, c->opmap.as<int>(), c->npairs,
-                                          d_sel, c->acc_tab.as<AccSlot>(), qslots - 1, 1, 0,
-                                          c->gacc.as<double>(), sigma_grid(c, n), c->stream), "contract");
-      HIP_TRY(c, launch_gather_scaled(c->gacc.as<double>(), d_subset, count, norm2, c->gbuf.as<double>(),
-                                      c->stream), "gather");
-    }
+  }
+  const u64 qslots = next_pow2(std::max<u64>(64, 2 * std::min<u64>(nq, c->sector)));
+  HIP_TRY(c, c->acc_tab.ensure(qslots * sizeof(AccSlot)), "alloc sigma table");
+  HIP_TRY(c, hipMemsetAsync(c->acc_tab.p, 0, qslots * sizeof(AccSlot), c->stream), "clear table");
+  if (op_major)
+    HIP_TRY(c, launch_query_ops(c->st, n, c->ops.as<OpDesc>(), d_subset, n_subset,
+                                c->acc_tab.as<AccSlot>(), qslots - 1, 0, nullptr, c->stream), "query set");
+  else
+    HIP_TRY(c, launch_query_set(c->st, c->exc, c->n, n, c->opmap.as<int>(), c->npairs, d_sel,
+                                c->acc_tab.as<AccSlot>(), qslots - 1, 0, nullptr, sigma_grid(c, n),
+                                c->stream), "query set");
+  TIMED(c, SWCS_K_SIGMA_PUSH_INTO, launch_sigma_push_into(c->st, ints_view(c), c->exc, n, c->acc_tab.as<AccSlot>(), qslots - 1,
+                                    sigma_grid(c, n), c->stream), "sigma push");
+  if (op_major) {
+    HIP_TRY(c, hipMemsetAsync(d_out, 0, (size_t)n_subset * 8, c->stream), "zero g");
+    TIMED(c, SWCS_K_CONTRACT_OPS, launch_contract_ops(c->st, n, c->ops.as<OpDesc>(), d_subset, n_subset,
+                                                      c->acc_tab.as<AccSlot>(), qslots - 1, d_out, c->stream), "contract");
+    HIP_TRY(c, launch_gather_scaled(d_out, nullptr, n_subset, norm2, d_out, c->stream), "scale");
+  } else {
+    TIMED(c, SWCS_K_POOL_CONTRACT, launch_pool_contract_det(c->st, c->exc, c->n, n, c->opmap.as<int>(), c->npairs,
+                                        d_sel, c->acc_tab.as<AccSlot>(), qslots - 1, 1, 0,
+                                        c->gacc.as<double>(), sigma_grid(c, n), c->stream), "contract");
+    HIP_TRY(c, launch_gather_scaled(c->gacc.as<double>(), d_subset, n_subset, norm2, d_out, c->stream), "gather");
+  }
+  return SWCS_OK;
+}
+
+// Shared set-up of both pool-gradient entry points: counters, norm, zeroed
+// accumulator and (for a subset) the selected-operator flags.
+static int pool_setup(swcs_ctx* c, Counters* h) {
+  int r = check_ready(c);
+  if (r) return r;
+  if (!c->have_state) return fail(c, SWCS_E_STATE, "no current state");
+  HIP_TRY(c, hipSetDevice(c->device), "hipSetDevice");
+  hipError_t e;
+  *h = get_counters(c, &e);
+  if (e != hipSuccess) return hip_fail(c, e, "read counters");
+  if (h->alive == 0) return fail(c, SWCS_E_STATE, "state is empty");
+  r = norm2_enqueue(c, h->n);
+  if (r) return r;
+  HIP_TRY(c, c->gacc.ensure((size_t)c->K_pool * 8), "alloc g accumulator");
+  HIP_TRY(c, hipMemsetAsync(c->gacc.p, 0, (size_t)c->K_pool * 8, c->stream), "zero g");
+  return SWCS_OK;
+}
+
+static int mark_subset(swcs_ctx* c, const int* d_subset, int64_t n_subset) {
+  HIP_TRY(c, c->selected.ensure((size_t)c->K_pool), "alloc selection");
+  HIP_TRY(c, hipMemsetAsync(c->selected.p, 0, (size_t)c->K_pool, c->stream), "zero selection");
+  HIP_TRY(c, launch_mark_selected(d_subset, n_subset, c->selected.as<unsigned char>(), c->stream), "mark");
+  return SWCS_OK;
+}
+
+int swcs_pool_gradients_device(swcs_ctx* c, const int32_t* d_subset, int64_t n_subset, double* d_g) {
+  if (!c) return SWCS_E_INVALID;
+  if (n_subset < 0) return fail(c, SWCS_E_INVALID, "n_subset < 0");
+  if (n_subset > 0 && (!d_subset || !d_g)) return fail(c, SWCS_E_INVALID, "null device pointer");
+  if (n_subset == 0) return SWCS_OK;
+  Counters h;
+  int r = pool_setup(c, &h);
+  if (r) return r;
+  HIP_TRY(c, c->subset_buf.ensure((size_t)n_subset * 4), "alloc subset");
+  HIP_TRY(c, launch_sanitize_subset(d_subset, n_subset, c->K_pool, c->subset_buf.as<int>(), c->stream), "subset");
+  const int* sub = c->subset_buf.as<int>();
+  r = mark_subset(c, sub, n_subset);
+  if (r) return r;
+  const double* norm2 = c->scalars.as<double>() + 2;
+  r = screened_gradients(c, h.n, h.alive, sub, n_subset, c->selected.as<unsigned char>(), norm2, d_g);
+  if (r) return r;
+  HIP_TRY(c, launch_nan_invalid(d_subset, n_subset, c->K_pool, d_g, c->stream), "flag invalid");
+  return SWCS_OK;
+}
+
+int swcs_pool_gradients(swcs_ctx* c, const int32_t* subset, int64_t n_subset, double* g_out) {
+  if (!c) return SWCS_E_INVALID;
+  if (!g_out) return fail(c, SWCS_E_INVALID, "null g_out");
+  const int64_t count = subset ? n_subset : c->K_pool;
+  if (subset) {
+    if (n_subset < 0) return fail(c, SWCS_E_INVALID, "n_subset < 0");
+    for (int64_t t = 0; t < n_subset; ++t)
+      if (subset[t] < 0 || subset[t] >= c->K_pool) return fail(c, SWCS_E_INVALID, "subset index out of range");
+  }
+  int r = check_ready(c);
+  if (r) return r;
+  if (!c->have_state) return fail(c, SWCS_E_STATE, "no current state");
+  if (count == 0) return SWCS_OK;
+  Counters h;
+  r = pool_setup(c, &h);
+  if (r) return r;
+  hipError_t e;
+  const u64 n = h.n;
+  const double* norm2 = c->scalars.as<double>() + 2;
+  HIP_TRY(c, c->gbuf.ensure((size_t)count * 8), "alloc g");
+  const int* d_subset = nullptr;
+  const unsigned char* d_sel = nullptr;
+  if (subset) {
+    HIP_TRY(c, c->subset_buf.ensure((size_t)n_subset * 4), "alloc subset");
+    HIP_TRY(c, hipMemcpyAsync(c->subset_buf.p, subset, (size_t)n_subset * 4, hipMemcpyHostToDevice, c->stream), "copy subset");
+    d_subset = c->subset_buf.as<int>();
+    r = mark_subset(c, d_subset, n_subset);
+    if (r) return r;
+    d_sel = c->selected.as<unsigned char>();
+  }
+  if (subset && 2 * n_subset < c->K_pool) {
+    r = screened_gradients(c, n, h.alive, d_subset, n_subset, d_sel, norm2, c->gbuf.as<double>());
+    if (r) return r;
     HIP_TRY(c, hipMemcpyAsync(g_out, c->gbuf.p, (size_t)count * 8, hipMemcpyDeviceToHost, c->stream), "copy g");
     Counters hq = read_counters(c, &e);
     if (e != hipSuccess) return hip_fail(c, e, "read counters");
@@ -1250,6 +1307,14 @@ int swcs_mse(swcs_ctx* c, const float* d_y, const float* d_t, int64_t B, float* 
   HIP_TRY(c, hipSetDevice(c->device), "hipSetDevice");
   HIP_TRY(c, c->mse_partial.ensure((size_t)mse_partial_count(B) * 4), "alloc partial");
   HIP_TRY(c, launch_mse(d_y, d_t, B, d_dy, d_loss, c->mse_partial.as<float>(), c->stream), "mse");
+  return SWCS_OK;
+}
+
+int swcs_log_abs(swcs_ctx* c, const double* d_g, int64_t n, float* d_t) {
+  if (!c) return SWCS_E_INVALID;
+  if (n < 0 || (n > 0 && (!d_g || !d_t))) return fail(c, SWCS_E_INVALID, "bad log_abs arguments");
+  HIP_TRY(c, hipSetDevice(c->device), "hipSetDevice");
+  HIP_TRY(c, launch_log_abs(d_g, n, d_t, c->stream), "log_abs");
   return SWCS_OK;
 }
 

@@ -400,6 +400,11 @@ hipError_t launch_mlp_backward(const float* W, const float* x, const float* act,
 int mse_partial_count(long long B);
 hipError_t launch_mse(const float* y, const float* t, long long B, float* dy, float* loss,
                       float* partial, hipStream_t stream);
+hipError_t launch_log_abs(const double* g, long long n, float* t, hipStream_t stream);
+hipError_t launch_sanitize_subset(const int* in, long long count, long long K, int* out,
+                                  hipStream_t stream);
+hipError_t launch_nan_invalid(const int* in, long long count, long long K, double* g,
+                              hipStream_t stream);
 hipError_t launch_adam(float* W, float* m, float* v, const float* g, long long P, float lr,
                        float b1, float b2, float eps, int step, hipStream_t stream);
 hipError_t launch_select(const float* score, const uint32_t* rnd, long long K, long long n_top,

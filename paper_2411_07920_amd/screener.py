@@ -70,22 +70,32 @@ class Screener:
         return self.score
 
     def select(self):
+        """Selected pool indices: (int32 device tensor, host array)."""
         torch = self.torch
         rnd = self.rng.integers(0, 2 ** 32, self.K, dtype=np.uint64).astype(np.uint32)
         rnd_d = torch.from_numpy(rnd.view(np.int32)).cuda()
         out = torch.zeros(self.n_top + self.n_rand, dtype=torch.int32, device="cuda")
         self.ctx.select(self.score, rnd_d, self.n_top, self.n_rand, out)
-        return out.cpu().numpy()
+        return out
+
+    def exact_gradients(self, idx_d):
+        """Exact pool gradients of the selection (float64 device tensor)."""
+        g = self.torch.zeros(idx_d.shape[0], dtype=self.torch.float64, device="cuda")
+        self.ctx.pool_gradients_device(idx_d, g)
+        return g
 
     def record(self, idx, g):
-        """Exact gradients g for pool indices idx (features of this iteration)."""
+        """Exact gradients g for pool indices idx (features of this iteration);
+        device tensors or host arrays."""
         torch = self.torch
-        idx = np.asarray(idx, dtype=np.int64)
-        absg = np.abs(np.asarray(g, dtype=np.float64))
-        rows = torch.from_numpy(idx).cuda()
+        rows = torch.as_tensor(np.asarray(idx) if not torch.is_tensor(idx) else idx,
+                               device="cuda").long()
+        g_d = torch.as_tensor(np.asarray(g, dtype=np.float64) if not torch.is_tensor(g) else g,
+                              device="cuda").double()
         x = self.feat.index_select(0, rows)
-        t = torch.from_numpy(np.log10(absg + 1e-12).astype(np.float32)).cuda()
-        n = len(idx)
+        t = torch.empty(len(rows), dtype=torch.float32, device="cuda")
+        self.ctx.log_abs(g_d, t)
+        n = len(rows)
         for s in range(0, n, self.buffer_rows):
             xs, ts = x[s:s + self.buffer_rows], t[s:s + self.buffer_rows]
             m = len(ts)
@@ -104,7 +114,7 @@ class Screener:
         # per-operator history used by the features
         self.age += 1.0
         self.age[rows] = 0.0
-        self.prev_absg[rows] = torch.from_numpy(absg.astype(np.float32)).cuda()
+        self.prev_absg[rows] = g_d.abs().float()
 
     def train(self):
         """Full-batch Adam steps on the replay buffer; returns the last loss."""

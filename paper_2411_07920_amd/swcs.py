@@ -67,6 +67,8 @@ SIGNATURES = {
     "swcs_energy": (ctypes.c_int, [_vp, _dp, _dp, _dp]),
     "swcs_sigma_projected": (ctypes.c_int, [_vp, _u64p, _dp, _i64, _i64p]),
     "swcs_pool_gradients": (ctypes.c_int, [_vp, _i32p, _i64, _dp]),
+    "swcs_pool_gradients_device": (ctypes.c_int, [_vp, _vp, _i64, _vp]),
+    "swcs_log_abs": (ctypes.c_int, [_vp, _vp, _i64, _vp]),
     "swcs_param_gradients": (ctypes.c_int, [_vp, _dp, _dp]),
     "swcs_gate_sizes": (ctypes.c_int, [_vp, _i64p, _i64]),
     "swcs_occupations": (ctypes.c_int, [_vp, _dp]),
@@ -317,6 +319,15 @@ class Context:
     def mse(self, y, t, dy, loss):
         self._check(self._lib.swcs_mse(self._h, _dev(y), _dev(t), int(y.shape[0]), _dev(dy),
                                        _dev(loss)))
+
+    def pool_gradients_device(self, subset, g):
+        """Pool gradients of the int32 device tensor `subset` into the float64
+        device tensor `g`, stream-ordered (no host synchronization)."""
+        self._check(self._lib.swcs_pool_gradients_device(self._h, _dev(subset), int(subset.shape[0]),
+                                                         _dev(g)))
+
+    def log_abs(self, g, t):
+        self._check(self._lib.swcs_log_abs(self._h, _dev(g), int(g.shape[0]), _dev(t)))
 
     def adam_step(self, W, m, v, dW, lr, b1, b2, eps, step):
         self._check(self._lib.swcs_adam_step(self._h, _dev(W), _dev(m), _dev(v), _dev(dW),

@@ -171,6 +171,33 @@ def test_c2_subset_paths(swcs, c2):
     ctx.close()
 
 
+def test_pool_gradients_device(swcs, c2):
+    """The device-resident subset entry point against the oracle: operator-
+    major, determinant-major and above half the pool; out-of-range indices
+    give NaN without disturbing the others."""
+    import torch
+    ctx = make_ctx(swcs, c2)
+    ctx.apply_ansatz(c2.ops, c2.theta, c2.eps)
+    rng = np.random.default_rng(13)
+    K = len(c2.pool)
+    for size in (500, 6000, 13000):
+        subset = np.sort(rng.choice(K, size, replace=False)).astype(np.int32)
+        g = torch.zeros(size, dtype=torch.float64, device="cuda")
+        ctx.pool_gradients_device(torch.from_numpy(subset).cuda(), g)
+        torch.cuda.synchronize()
+        g_ref = c2.orc.pool_gradients(c2.st, c2.pool, subset=subset)
+        assert np.abs(g.cpu().numpy() - g_ref).max() < TOL
+    bad = np.array([3, -1, 7, K, 11], dtype=np.int32)
+    g = torch.zeros(len(bad), dtype=torch.float64, device="cuda")
+    ctx.pool_gradients_device(torch.from_numpy(bad).cuda(), g)
+    torch.cuda.synchronize()
+    gh = g.cpu().numpy()
+    assert np.isnan(gh[1]) and np.isnan(gh[3])
+    good = np.array([3, 7, 11], dtype=np.int32)
+    assert np.abs(gh[[0, 2, 4]] - c2.orc.pool_gradients(c2.st, c2.pool, subset=good)).max() < TOL
+    ctx.close()
+
+
 def test_c3_parity_sampled_pool(swcs):
     case = config_case("c3")
     rng = np.random.default_rng(3)
