@@ -339,6 +339,124 @@ __global__ void k_select_clear(unsigned char* flags, long long K) {
   if (i < K) flags[i] = 0;
 }
 
+// Whole selection in one workgroup (pools up to kSelectBlockMax operators).
+// Each choice is a radix select of the kth largest 64-bit key, most
+// significant 8 bits first: top key = (score order, complemented index), so
+// ties go to the smaller index; random key = complement of (rand, index) for
+// operators not already chosen and 0 for chosen ones, so the smallest
+// (rand, index) pairs rank first.  Keys are distinct, so after eight passes
+// the prefix is the kth largest key itself and "key >= it" selects exactly k.
+constexpr long long kSelectBlockMax = 1 << 17;
+
+__device__ inline u64 select_key_top(const float* score, long long k) {
+  return ((u64)float_code(score[k]) << 32) | (u64)(0xffffffffu - (unsigned)k);
+}
+
+__device__ inline u64 select_key_rand(const uint32_t* rnd, long long k, bool chosen) {
+  return chosen ? 0ULL : ~(((u64)rnd[k] << 32) | (u64)(unsigned)k);
+}
+
+struct SelectState {
+  u64 prefix, mask;
+  unsigned long long remaining;
+  int all;  // fewer candidates than requested: every candidate is taken
+  unsigned hist[256];
+};
+
+// Radix select over keys produced by key_of(k); returns the threshold.
+template <class KeyOf>
+__device__ u64 block_radix_select(long long K, unsigned long long kth, KeyOf key_of,
+                                  SelectState& st) {
+  if (threadIdx.x == 0) {
+    st.prefix = 0;
+    st.mask = 0;
+    st.remaining = kth;
+    st.all = 0;
+  }
+  for (int d = 7; d >= 0; --d) {
+    if (threadIdx.x < 256) st.hist[threadIdx.x] = 0;
+    __syncthreads();
+    if (!st.all) {
+      const u64 prefix = st.prefix, mask = st.mask;
+      for (long long k = threadIdx.x; k < K; k += blockDim.x) {
+        const u64 key = key_of(k);
+        if ((key & mask) == prefix) atomicAdd(&st.hist[(unsigned)(key >> (8 * d)) & 255u], 1u);
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x < 64 && !st.all) {
+      // lane l holds bins 255-4l .. 252-4l (descending); wavefront prefix sums
+      const int l = (int)threadIdx.x;
+      unsigned b[4], sum = 0;
+      for (int q = 0; q < 4; ++q) {
+        b[q] = st.hist[255 - 4 * l - q];
+        sum += b[q];
+      }
+      unsigned long long incl = sum;
+      for (int off = 1; off < 64; off <<= 1) {
+        const unsigned long long v = __shfl_up(incl, off);
+        if (l >= off) incl += v;
+      }
+      const unsigned long long need = st.remaining;
+      const u64 hit = __ballot(incl >= need);
+      if (hit == 0ULL) {
+        if (l == 0) st.all = 1;
+      } else if (l == __ffsll((long long)hit) - 1) {
+        unsigned long long cum = incl - sum;
+        for (int q = 0; q < 4; ++q) {
+          if (cum + b[q] >= need) {
+            const u64 digit = (u64)(255 - 4 * l - q);
+            st.prefix |= digit << (8 * d);
+            st.mask |= 255ULL << (8 * d);
+            st.remaining = need - cum;
+            break;
+          }
+          cum += b[q];
+        }
+      }
+    }
+    __syncthreads();
+  }
+  return st.all ? 0ULL : st.prefix;
+}
+
+__global__ void __launch_bounds__(1024)
+k_select_block(const float* __restrict__ score, const uint32_t* __restrict__ rnd, long long K,
+               long long n_top, long long n_rand, int* __restrict__ idx) {
+  __shared__ SelectState st;
+  __shared__ unsigned long long part[1024];
+  const u64 t_top = (n_top > 0)
+      ? block_radix_select(K, (unsigned long long)n_top, [&](long long k) { return select_key_top(score, k); }, st)
+      : ~0ULL;
+  const bool top_none = (n_top == 0);
+  auto chosen_top = [&](long long k) { return !top_none && select_key_top(score, k) >= t_top; };
+  const u64 t_rand = (n_rand > 0)
+      ? block_radix_select(K, (unsigned long long)n_rand,
+                           [&](long long k) { return select_key_rand(rnd, k, chosen_top(k)); }, st)
+      : ~0ULL;
+  auto chosen = [&](long long k) {
+    if (chosen_top(k)) return true;
+    return n_rand > 0 && select_key_rand(rnd, k, false) >= t_rand && t_rand != 0ULL;
+  };
+  // ascending output: contiguous index ranges per thread, block scan of counts
+  const long long per = (K + blockDim.x - 1) / blockDim.x;
+  const long long lo = (long long)threadIdx.x * per;
+  const long long hi = (lo + per < K) ? lo + per : K;
+  unsigned long long cnt = 0;
+  for (long long k = lo; k < hi; ++k) cnt += chosen(k) ? 1 : 0;
+  part[threadIdx.x] = cnt;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    const unsigned long long v = (threadIdx.x >= (unsigned)off) ? part[threadIdx.x - off] : 0;
+    __syncthreads();
+    part[threadIdx.x] += v;
+    __syncthreads();
+  }
+  long long pos = (long long)(part[threadIdx.x] - cnt);
+  for (long long k = lo; k < hi; ++k)
+    if (chosen(k)) idx[pos++] = (int)k;
+}
+
 // Ascending list of flagged indices: per-tile counts, scan, ordered scatter.
 __global__ void __launch_bounds__(kSortThreads)
 k_flag_count(const unsigned char* __restrict__ flags, long long K, u64* __restrict__ counts) {
@@ -391,6 +509,11 @@ u64 select_scratch_elems(long long K) {
 hipError_t launch_select(const float* score, const uint32_t* rnd, long long K, long long n_top,
                          long long n_rand, int* idx, u64* scratch, u64 scratch_elems,
                          hipStream_t stream) {
+  if (K <= kSelectBlockMax) {
+    hipLaunchKernelGGL(k_select_block, dim3(1), dim3(1024), 0, stream, score, rnd, K, n_top, n_rand,
+                       idx);
+    return hipGetLastError();
+  }
   if (scratch_elems < select_scratch_elems(K)) return hipErrorInvalidValue;
   u64* keys = scratch;
   u64* ids = scratch + K;

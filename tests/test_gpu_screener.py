@@ -113,15 +113,20 @@ def test_mse_and_adam(env):
 
 def test_select_matches_oracle(env):
     torch, ctx = env["torch"], env["ctx"]
-    for K in (10, 1000, 22750):
+    # single-workgroup path up to 131,072 operators, sort-based path above;
+    # ties in both keys; no top or no random share
+    cases = [(10, 0.05, 0.01), (1000, 0.05, 0.01), (22750, 0.05, 0.01), (22750, 0.0, 0.02),
+             (22750, 0.03, 0.0), (101650, 0.05, 0.01), (150000, 0.05, 0.01)]
+    for K, ft, fr in cases:
         rng = np.random.default_rng(K)
         score = rng.normal(size=K).astype(np.float32)
         score[::7] = score[3]  # ties
         rnd = draw_random_keys(K, 99)
-        n_top, n_rand = int(np.ceil(0.05 * K)), int(np.ceil(0.01 * K))
+        rnd[::5] = rnd[2]  # ties
+        n_top, n_rand = int(np.ceil(ft * K)), int(np.ceil(fr * K))
         out = torch.zeros(n_top + n_rand, dtype=torch.int32, device="cuda")
         ctx.select(torch.from_numpy(score).cuda(), torch.from_numpy(rnd.astype(np.int32)).cuda(),
                    n_top, n_rand, out)
         torch.cuda.synchronize()
-        ref = oracle.select_subset(score, rnd, 0.05, 0.01)
-        assert out.cpu().numpy().tolist() == ref.tolist()
+        ref = oracle.select_subset(score, rnd, ft, fr)
+        assert out.cpu().numpy().tolist() == ref.tolist(), (K, ft, fr)
