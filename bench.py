@@ -207,7 +207,7 @@ def gpu_bench(args, wl):
     # context stream around every launch of the selected kernel.
     kern = {}
     reps = max(3, args.steps // 2)
-    for kname in ("chain_lds", "gate", "adjoint_lds", "gate_replay", "adjoint_rec", "sigma_proj",
+    for kname in ("chain_lds", "gate", "adjoint_lds", "adjoint_replay_lds", "gate_replay", "adjoint_rec", "sigma_proj",
                   "sigma_push", "sigma_push_into", "pool_contract", "contract_ops"):
         ctx.timer_start(kname)
         for _ in range(reps):
@@ -223,8 +223,8 @@ def gpu_bench(args, wl):
 
 def algorithmic_bytes(kname, wl, r):
     """Lower-bound bytes the method must move per launch of a kernel: 8 B per
-    stored determinant scanned by a gate (the key test; the single-workgroup
-    adjoint counts a replay and a reverse step per gate); 16 B per (source,
+    stored determinant scanned by a gate (the key test; also per determinant
+    and gate for the LDS adjoint's replay and reverse sweeps); 16 B per (source,
     connection) read-modify-write of the external sigma table; 8 B per probe
     of a hash table and 16 B per source determinant read."""
     from paper_2411_07920_amd.inputs import sector_size  # noqa: F401
@@ -239,8 +239,8 @@ def algorithmic_bytes(kname, wl, r):
         return 8.0 * n_in.sum()                      # whole chain per launch
     if kname in ("gate", "gate_replay", "adjoint_rec"):
         return 8.0 * n_in.sum() / M                  # one gate per launch
-    if kname == "adjoint_lds":
-        return 2 * 8.0 * n_in.sum()                  # replay + reverse per gate
+    if kname in ("adjoint_lds", "adjoint_replay_lds"):
+        return 8.0 * n_in.sum()                      # reverse sweep / all segment replays
     if kname == "sigma_proj":
         return n * (C * 8.0 + 16.0)
     if kname in ("sigma_push", "sigma_push_into"):

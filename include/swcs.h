@@ -190,12 +190,13 @@ enum {
   SWCS_K_SIGMA_PROJ = 3,    /* projected sigma vector + energy partial sums     */
   SWCS_K_SIGMA_PUSH = 4,    /* external sigma vector accumulation               */
   SWCS_K_POOL_CONTRACT = 5, /* pool-gradient contraction                        */
-  SWCS_K_ADJOINT_LDS = 6,   /* whole adjoint sweep in one LDS-resident workgroup */
+  SWCS_K_ADJOINT_LDS = 6,   /* reverse adjoint sweep in one LDS-resident workgroup */
   SWCS_K_GATE_REPLAY = 7,   /* one replayed gate with pair logging (adjoint)    */
   SWCS_K_ADJOINT_REC = 8,   /* one reverse step over logged pairs (adjoint)     */
   SWCS_K_SIGMA_PUSH_INTO = 9, /* external sigma on the screened query set        */
   SWCS_K_CONTRACT_OPS = 10,  /* operator-major contraction of a small subset     */
-  SWCS_K_HOLEPAIR = 11       /* sigma_P pair evaluation inside hole-pair groups  */
+  SWCS_K_HOLEPAIR = 11,      /* sigma_P pair evaluation inside hole-pair groups  */
+  SWCS_K_ADJOINT_REPLAY_LDS = 12 /* segment replays of the LDS adjoint, one workgroup each */
 };
 
 /* From now on record HIP events on the context stream around every launch

@@ -196,91 +196,126 @@ k_chain_lds(u64* __restrict__ keys, double* __restrict__ amps, Counters* __restr
   }
 }
 
-// Whole frozen-support adjoint sweep for a final state of n <= CAP stored
-// determinants.  For each segment (last first): restore the checkpoint into
-// LDS, replay the segment's gates logging one PairRec per active pair (HBM
-// scratch, seg * n records at most), then run the reverse steps over the
-// logged pairs with the adjoint vector mu held in LDS.  dE[g] is a block sum
-// in a fixed wave order.
-constexpr int kMaxSeg = 256;
+// Frozen-support adjoint sweep for a final state of n <= CAP stored
+// determinants, in two launches.  (1) One workgroup per checkpoint segment
+// restores the segment's checkpoint into LDS and replays its gates, logging
+// one PairRec per active pair of gate g in logbuf[g * n ...] and the count in
+// logcnt[g]; segments are independent, so they run side by side.  (2) One
+// workgroup walks all gates backwards with the adjoint vector mu in LDS:
+// one barrier per gate orders the mu updates, each wavefront's share of
+// dE/dtheta_g goes to dE_part[g * 16 + wave], and the 16 shares are added in
+// wave order at the end.
+constexpr int kMaxSeg = 256;  // gate descriptors a segment stages in LDS at a time
+constexpr int kWaves = kChainThreads / 64;
 
 template <int CAP>
 __global__ void __launch_bounds__(kChainThreads)
-k_adjoint_lds(const u64* __restrict__ keys, unsigned n, const GateDesc* __restrict__ gates, int M,
-              int seg, double eps, const double* const* __restrict__ ckpt,
-              const u64* __restrict__ ckpt_n, const double* __restrict__ mu_init,
-              PairRec* __restrict__ logbuf, double* __restrict__ dE, unsigned* __restrict__ flags,
-              unsigned ncut) {
+k_adjoint_replay_lds(const u64* __restrict__ keys, unsigned n, const GateDesc* __restrict__ gates,
+                     int M, int seg, double eps, const double* const* __restrict__ ckpt,
+                     const u64* __restrict__ ckpt_n, PairRec* __restrict__ logbuf,
+                     unsigned* __restrict__ logcnt, unsigned* __restrict__ flags, unsigned ncut) {
   __shared__ NcutState nst;
   __shared__ u64 skeys[CAP];
   __shared__ double sW[CAP];
-  __shared__ double smu[CAP];
   __shared__ int sslots[2 * CAP];
-  __shared__ double wsum[kChainThreads / 64];
-  __shared__ unsigned cnt[kMaxSeg];
   __shared__ GateDesc sg[kMaxSeg];
+  __shared__ unsigned s_cnt;
   const int tid = threadIdx.x;
+  const int j = blockIdx.x;
+  const int g_lo = j * seg;
+  const int g_hi = (g_lo + seg < M) ? g_lo + seg : M;
+  const unsigned nj = (unsigned)ckpt_n[j];
+  const double* src = ckpt[j];
   for (int t = tid; t < 2 * CAP; t += kChainThreads) sslots[t] = 0;
-  for (int t = tid; t < kMaxSeg; t += kChainThreads) cnt[t] = 0;
   for (unsigned i = tid; i < n; i += kChainThreads) {
     skeys[i] = keys[i];
-    smu[i] = mu_init[i];
+    sW[i] = (i < nj) ? src[i] : dead_value();
   }
+  if (tid == 0) s_cnt = 0;
   __syncthreads();
   LdsStore L{skeys, sW, sslots, 2u * CAP - 1u};
   for (unsigned i = tid; i < n; i += kChainThreads) L.insert(skeys[i], (int)i);
-  __syncthreads();
+  const int lane = tid & 63;
+  const u64 below = (1ULL << lane) - 1ULL;
+  for (int g = g_lo; g < g_hi; ++g) {
+    if ((g - g_lo) % kMaxSeg == 0) {
+      __syncthreads();
+      for (int t = tid; t < kMaxSeg && g + t < g_hi; t += kChainThreads) sg[t] = gates[g + t];
+    }
+    __syncthreads();
+    const GateDesc gd = sg[(g - g_lo) % kMaxSeg];
+    PairRec* lg = logbuf + (size_t)g * n;
+    for (unsigned i0 = 0; i0 < n; i0 += kChainThreads) {
+      const unsigned i = i0 + tid;
+      GateOut o{false, 0ULL, 0.0, 0, false, kNoEntry, kNoEntry, 0.0, 0.0, 0};
+      if (i < n) o = gate_entry(L, i, gd.op, gd.c, gd.s, eps);
+      if (o.append) atomicOr(flags, kFlagOverflow);  // cannot happen: all keys are stored
+      const u64 m = __ballot(o.active);
+      if (m) {
+        const int leader = __ffsll((long long)m) - 1;
+        unsigned b = 0;
+        if (lane == leader) b = atomicAdd(&s_cnt, (unsigned)__popcll(m));
+        b = __shfl(b, leader);
+        if (o.active) lg[b + (unsigned)__popcll(m & below)] = make_rec(o);
+      }
+    }
+    __syncthreads();
+    if (tid == 0) {
+      logcnt[g] = s_cnt;
+      s_cnt = 0;
+    }
+    if (ncut) lds_ncut(sW, skeys, n, ncut, nst);
+  }
+}
+
+template <int CAP>
+__global__ void __launch_bounds__(kChainThreads)
+k_adjoint_reverse_lds(unsigned n, const GateDesc* __restrict__ gates, int M,
+                      const double* __restrict__ mu_init, const PairRec* __restrict__ logbuf,
+                      const unsigned* __restrict__ logcnt, double* __restrict__ dE_part,
+                      double* __restrict__ dE) {
+  __shared__ double smu[CAP];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  for (unsigned i = tid; i < n; i += kChainThreads) smu[i] = mu_init[i];
   LdsMu mu{smu};
-  const int nseg = (M + seg - 1) / seg;
-  for (int j = nseg - 1; j >= 0; --j) {
-    const int g_lo = j * seg;
-    const int g_hi = (g_lo + seg < M) ? g_lo + seg : M;
-    const int len = g_hi - g_lo;
-    const unsigned nj = (unsigned)ckpt_n[j];
-    const double* src = ckpt[j];
-    for (unsigned i = tid; i < n; i += kChainThreads) sW[i] = (i < nj) ? src[i] : dead_value();
-    for (int t = tid; t < len; t += kChainThreads) sg[t] = gates[g_lo + t];
-    __syncthreads();
-    for (int t = 0; t < len; ++t) {
-      const GateDesc gd = sg[t];
-      PairRec* lg = logbuf + (size_t)t * n;
-      for (unsigned i = tid; i < n; i += kChainThreads) {
-        const GateOut o = gate_entry(L, i, gd.op, gd.c, gd.s, eps);
-        if (o.append) atomicOr(flags, kFlagOverflow);  // cannot happen: all keys are stored
-        if (o.active) lg[atomicAdd(&cnt[t], 1u)] = make_rec(o);
-      }
-      __syncthreads();
-      if (ncut) lds_ncut(sW, skeys, n, ncut, nst);
+  // The first record of this thread, the count and the descriptor of the
+  // next (earlier) gate are loaded while the current gate is processed.
+  PairRec cur{};
+  unsigned c_cur = 0;
+  GateDesc gd_cur{};
+  if (M > 0) {
+    gd_cur = gates[M - 1];
+    c_cur = logcnt[M - 1];
+    if ((unsigned)tid < n) cur = logbuf[(size_t)(M - 1) * n + tid];
+  }
+  __syncthreads();
+  for (int g = M - 1; g >= 0; --g) {
+    PairRec nxt{};
+    unsigned c_nxt = 0;
+    GateDesc gd_nxt{};
+    if (g > 0) {
+      gd_nxt = gates[g - 1];
+      c_nxt = logcnt[g - 1];
+      if ((unsigned)tid < n) nxt = logbuf[(size_t)(g - 1) * n + tid];
     }
-    // Reverse over the segment's logs; each thread's first record of the
-    // next (earlier) gate is loaded while the current gate is processed.
-    PairRec cur{};
-    bool has = false;
-    if (len > 0 && (unsigned)tid < cnt[len - 1]) {
-      cur = logbuf[(size_t)(len - 1) * n + tid];
-      has = true;
-    }
-    for (int t = len - 1; t >= 0; --t) {
-      const GateDesc gd = sg[t];
-      const PairRec* lg = logbuf + (size_t)t * n;
-      const unsigned c = cnt[t];
-      PairRec nxt{};
-      bool has_next = false;
-      if (t > 0 && (unsigned)tid < cnt[t - 1]) {
-        nxt = logbuf[(size_t)(t - 1) * n + tid];
-        has_next = true;
-      }
-      double acc = 0.0;
-      if (has) acc += adjoint_pair(cur, mu, gd.c, gd.s);
-      for (unsigned r = tid + kChainThreads; r < c; r += kChainThreads) acc += adjoint_pair(lg[r], mu, gd.c, gd.s);
-      __syncthreads();
-      const double tot = block_sum_1024(acc, wsum);
-      if (tid == 0) dE[g_lo + t] = tot;
-      cur = nxt;
-      has = has_next;
-    }
-    for (int t = tid; t < len; t += kChainThreads) cnt[t] = 0;
-    __syncthreads();
+    double acc = 0.0;
+    if ((unsigned)tid < c_cur) acc += adjoint_pair(cur, mu, gd_cur.c, gd_cur.s);
+    const PairRec* lg = logbuf + (size_t)g * n;
+    for (unsigned r = tid + kChainThreads; r < c_cur; r += kChainThreads)
+      acc += adjoint_pair(lg[r], mu, gd_cur.c, gd_cur.s);
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    if (lane == 0) dE_part[(size_t)g * kWaves + wave] = acc;
+    __syncthreads();  // every mu update of gate g precedes gate g - 1
+    cur = nxt;
+    c_cur = c_nxt;
+    gd_cur = gd_nxt;
+  }
+  __syncthreads();
+  for (int g = tid; g < M; g += kChainThreads) {
+    double t = 0.0;
+    for (int w = 0; w < kWaves; ++w) t += dE_part[(size_t)g * kWaves + w];
+    dE[g] = t;
   }
 }
 
@@ -295,16 +330,27 @@ hipError_t launch_chain_lds(const DeviceState& st, const GateDesc* gates, int g0
   return hipGetLastError();
 }
 
-int lds_adjoint_max_segment() { return kMaxSeg; }
-
-hipError_t launch_adjoint_lds(const u64* keys, unsigned n, const GateDesc* gates, int M, int seg,
-                              double eps, const double* const* ckpt, const u64* ckpt_n,
-                              const double* mu_init, PairRec* logbuf, double* dE, unsigned* flags,
-                              unsigned ncut, hipStream_t stream) {
-  if (seg > kMaxSeg) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_adjoint_lds<kLdsCap>, dim3(1), dim3(kChainThreads), 0, stream, keys, n, gates,
-                     M, seg, eps, ckpt, ckpt_n, mu_init, logbuf, dE, flags, ncut);
+hipError_t launch_adjoint_replay_lds(const u64* keys, unsigned n, const GateDesc* gates, int M,
+                                     int seg, double eps, const double* const* ckpt,
+                                     const u64* ckpt_n, PairRec* logbuf, unsigned* logcnt,
+                                     unsigned* flags, unsigned ncut, hipStream_t stream) {
+  if (M <= 0) return hipSuccess;
+  const int nseg = (M + seg - 1) / seg;
+  hipLaunchKernelGGL(k_adjoint_replay_lds<kLdsCap>, dim3(nseg), dim3(kChainThreads), 0, stream, keys,
+                     n, gates, M, seg, eps, ckpt, ckpt_n, logbuf, logcnt, flags, ncut);
   return hipGetLastError();
 }
+
+hipError_t launch_adjoint_reverse_lds(unsigned n, const GateDesc* gates, int M,
+                                      const double* mu_init, const PairRec* logbuf,
+                                      const unsigned* logcnt, double* dE_part, double* dE,
+                                      hipStream_t stream) {
+  if (M <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_adjoint_reverse_lds<kLdsCap>, dim3(1), dim3(kChainThreads), 0, stream, n,
+                     gates, M, mu_init, logbuf, logcnt, dE_part, dE);
+  return hipGetLastError();
+}
+
+size_t adjoint_lds_part_elems(int M) { return (size_t)M * kWaves; }
 
 }  // namespace swcs

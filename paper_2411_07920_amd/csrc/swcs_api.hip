@@ -1069,9 +1069,13 @@ int swcs_pool_gradients(swcs_ctx* c, const int32_t* subset, int64_t n_subset, do
   double guess = bound_d;
   if (c->ext_count > 0.0 && c->ext_alive > 0.0)
     guess = std::min(bound_d, 1.5 * c->ext_count * std::max(1.0, (double)h.alive / c->ext_alive));
-  size_t free_b = 0, total_b = 0;
-  if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) free_b = 0;
-  const double budget = std::max<double>(64.0 * 1024 * 1024, 0.4 * (double)(free_b + c->acc_tab.bytes));
+  // Tables up to 256 MB need no free-memory query.
+  double budget = 256.0 * 1024 * 1024;
+  if (4.0 * guess * sizeof(AccSlot) > budget) {
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) free_b = 0;
+    budget = std::max<double>(64.0 * 1024 * 1024, 0.4 * (double)(free_b + c->acc_tab.bytes));
+  }
   const int sgrid = sigma_grid(c, n);
   for (int attempt = 0;; ++attempt) {
     int nbatch = 1;
@@ -1096,12 +1100,15 @@ int swcs_pool_gradients(swcs_ctx* c, const int32_t* subset, int64_t n_subset, do
                                       c->stream), "count");
     double distinct = 0.0;
     HIP_TRY(c, hipMemcpyAsync(&distinct, c->scalars.as<double>() + 24, 8, hipMemcpyDeviceToHost, c->stream), "copy");
+    HIP_TRY(c, launch_gather_scaled(c->gacc.as<double>(), d_subset, count, norm2, c->gbuf.as<double>(),
+                                    c->stream), "gather");
+    HIP_TRY(c, hipMemcpyAsync(g_out, c->gbuf.p, (size_t)count * 8, hipMemcpyDeviceToHost, c->stream), "copy g");
     Counters h2 = read_counters(c, &e);  // synchronizes
     if (e != hipSuccess) return hip_fail(c, e, "read counters");
     if (!(h2.flags & kFlagOverflow)) {
       c->ext_count = distinct;
       c->ext_alive = (double)h.alive;
-      break;
+      return SWCS_OK;
     }
     if (guess >= bound_d || attempt >= 16) return fail(c, SWCS_E_DEVICE, "sigma table overflow");
     guess = std::min(bound_d, 2.0 * guess);
@@ -1109,11 +1116,6 @@ int swcs_pool_gradients(swcs_ctx* c, const int32_t* subset, int64_t n_subset, do
     HIP_TRY(c, hipMemcpyAsync(c->ctr.p, &h2, sizeof(h2), hipMemcpyHostToDevice, c->stream), "counters");
     c->hc = h2;
   }
-  HIP_TRY(c, launch_gather_scaled(c->gacc.as<double>(), d_subset, count, norm2, c->gbuf.as<double>(),
-                                  c->stream), "gather");
-  HIP_TRY(c, hipMemcpyAsync(g_out, c->gbuf.p, (size_t)count * 8, hipMemcpyDeviceToHost, c->stream), "copy g");
-  HIP_TRY(c, hipStreamSynchronize(c->stream), "sync");
-  return SWCS_OK;
 }
 
 int swcs_param_gradients(swcs_ctx* c, double* dE, double* E_out) {
@@ -1142,19 +1144,28 @@ int swcs_param_gradients(swcs_ctx* c, double* dE, double* E_out) {
   const int grid = grid_blocks(c, n, 256);
   HIP_TRY(c, c->mu.ensure(n * 8), "alloc mu");
   HIP_TRY(c, c->gbuf.ensure((size_t)M * 8), "alloc dE");
-  // Pair logs of one segment: at most one record per stored entry per gate.
-  HIP_TRY(c, c->seg_states.ensure((size_t)seg * n * sizeof(PairRec)), "alloc pair logs");
+  const bool lds = n <= (u64)lds_chain_capacity();
+  // Pair logs: at most one record per stored entry per gate, for every gate
+  // (single-workgroup path, all segments replayed at once) or for one
+  // segment at a time (HBM path).
+  HIP_TRY(c, c->seg_states.ensure((size_t)(lds ? M : seg) * n * sizeof(PairRec)), "alloc pair logs");
   PairRec* logs = c->seg_states.as<PairRec>();
   HIP_TRY(c, launch_mu_init(c->st, c->sigma.as<double>(), n, nn, c->mu.as<double>(), c->stream), "mu init");
-  if (n <= (u64)lds_chain_capacity() && seg <= lds_adjoint_max_segment()) {
-    // Whole sweep in one single-workgroup launch with mu and the replayed
-    // amplitudes in LDS; the gate table of the last apply call is reused.
+  if (lds) {
+    // Segments replayed side by side (one workgroup each), then one
+    // workgroup walks every gate back with mu in LDS; the gate table of the
+    // last apply call is reused.
     int r2 = upload_ckpt_table(c, nseg);
     if (r2) return r2;
-    TIMED(c, SWCS_K_ADJOINT_LDS, launch_adjoint_lds(c->st.keys, (unsigned)n, c->gate_tab.as<GateDesc>(), (int)M, seg,
-                                  c->a_ncut ? 0.0 : c->a_eps, c->ckpt_ptrs.as<double*>(), c->ckpt_n.as<u64>(),
-                                  c->mu.as<double>(), logs, c->gbuf.as<double>(),
-                                  &c->st.ctr->flags, (unsigned)c->a_ncut, c->stream), "adjoint");
+    HIP_TRY(c, c->ctr_r.ensure((size_t)M * sizeof(unsigned)), "alloc log counters");
+    HIP_TRY(c, c->partial2.ensure(adjoint_lds_part_elems((int)M) * sizeof(double)), "alloc partials");
+    TIMED(c, SWCS_K_ADJOINT_REPLAY_LDS, launch_adjoint_replay_lds(c->st.keys, (unsigned)n, c->gate_tab.as<GateDesc>(), (int)M, seg,
+                                          c->a_ncut ? 0.0 : c->a_eps, c->ckpt_ptrs.as<double*>(), c->ckpt_n.as<u64>(),
+                                          logs, c->ctr_r.as<unsigned>(), &c->st.ctr->flags, (unsigned)c->a_ncut,
+                                          c->stream), "adjoint replay");
+    TIMED(c, SWCS_K_ADJOINT_LDS, launch_adjoint_reverse_lds((unsigned)n, c->gate_tab.as<GateDesc>(), (int)M, c->mu.as<double>(),
+                                  logs, c->ctr_r.as<unsigned>(), c->partial2.as<double>(), c->gbuf.as<double>(),
+                                  c->stream), "adjoint");
   } else {
     // Per segment: restore the checkpoint into a working copy, replay the
     // segment's gates logging their active pairs, then walk the logs back.
@@ -1235,7 +1246,7 @@ int swcs_occupations(swcs_ctx* c, double* n_out) {
 
 int swcs_timer_start(swcs_ctx* c, int kernel_id) {
   if (!c) return SWCS_E_INVALID;
-  if (kernel_id < SWCS_K_CHAIN_LDS || kernel_id > SWCS_K_HOLEPAIR)
+  if (kernel_id < SWCS_K_CHAIN_LDS || kernel_id > SWCS_K_ADJOINT_REPLAY_LDS)
     return fail(c, SWCS_E_INVALID, "unknown kernel id");
   c->timer_kernel = kernel_id;
   c->ev_used = 0;

@@ -321,11 +321,15 @@ int lds_chain_capacity();
 hipError_t launch_chain_lds(const DeviceState& st, const GateDesc* gates, int g0, int M, double eps,
                             int prune_first, double* const* ckpt, u64* ckpt_n, int seg,
                             u64* gate_n_in, u64 max_keys, unsigned ncut, hipStream_t stream);
-int lds_adjoint_max_segment();
-hipError_t launch_adjoint_lds(const u64* keys, unsigned n, const GateDesc* gates, int M, int seg,
-                              double eps, const double* const* ckpt, const u64* ckpt_n,
-                              const double* mu_init, PairRec* logbuf, double* dE, unsigned* flags,
-                              unsigned ncut, hipStream_t stream);
+hipError_t launch_adjoint_replay_lds(const u64* keys, unsigned n, const GateDesc* gates, int M,
+                                     int seg, double eps, const double* const* ckpt,
+                                     const u64* ckpt_n, PairRec* logbuf, unsigned* logcnt,
+                                     unsigned* flags, unsigned ncut, hipStream_t stream);
+hipError_t launch_adjoint_reverse_lds(unsigned n, const GateDesc* gates, int M,
+                                      const double* mu_init, const PairRec* logbuf,
+                                      const unsigned* logcnt, double* dE_part, double* dE,
+                                      hipStream_t stream);
+size_t adjoint_lds_part_elems(int M);
 hipError_t launch_gate_replay(const DeviceState& st, double* amps, u64 n, const OpDesc& op,
                              double c, double sn, double eps, PairRec* log, u64* log_count, int grid,
                              hipStream_t stream);
