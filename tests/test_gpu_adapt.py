@@ -38,6 +38,27 @@ def test_adapt_follows_oracle_driver(swcs):
     gpu.close()
 
 
+@pytest.mark.parametrize("optimizer", ["bfgs", "bfgs2", "bfgs2f"])
+def test_adapt_optimizers_follow_oracle_driver(swcs, optimizer):
+    """BFGS (Sec. II.B) and the BFGS-2 / BFGS-2F variants (Sec. IV.D) with
+    energies and gradients from the GPU library choose the same operators and
+    reach the same energies as with the oracle."""
+    from test_adapt_host import OracleContext
+    c = CONFIGS["c1"]
+    h, eri = make_integrals(c.n, c.rank, c.seed_int)
+    pool = enumerate_pool(c.n)
+    ref = reference_key(c.n_elec)
+    cfg = adapt.AdaptConfig(eps=1e-6, max_iter=5, grad_tol=None, optimizer=optimizer)
+    gpu = swcs.make_context(c.n, 2, 2, h, eri, pool, ref)
+    ops_g, th_g, hist_g = adapt.run_adapt(gpu, len(pool), cfg)
+    cpu = OracleContext(c.n, c.n_elec, h, eri, pool)
+    ops_c, th_c, hist_c = adapt.run_adapt(cpu, len(pool), cfg)
+    assert ops_g.tolist() == ops_c.tolist()
+    for a, b in zip(hist_g, hist_c):
+        assert abs(a["E_after"] - b["E_after"]) < 1e-7
+    gpu.close()
+
+
 def test_screened_subset_gradients_equal_full_pool(swcs):
     c = CONFIGS["c2"]
     h, eri = make_integrals(c.n, c.rank, c.seed_int)
