@@ -402,6 +402,74 @@ def test_synthetic_state_gates_bit_exact(swcs):
     ctx.close()
 
 
+def _pair_mask(row):
+    P, Q, R, S = (int(x) for x in row)
+    m = (1 << P) | (1 << Q)
+    if R >= 0:
+        m |= (1 << R) | (1 << S)
+    return m
+
+
+def test_large_state_16M_sampled(swcs):
+    """The large-state configuration of the step benchmark at full size: 16M
+    determinants in the 52-spin-orbital, 16-electron sector, eight double
+    gates at eps = 0 on the HBM path (the state grows to about 33M).  A gate
+    only mixes D with D xor its pair mask, so the final amplitude of D depends
+    only on the initial amplitudes of the at most 2^8 keys D xor (any xor of
+    the masks); the oracle applies the same gates to that light cone and every
+    sampled amplitude must match bit for bit.  Then sigma_P of the initial
+    state by hole-pair grouping: sampled rows against the oracle."""
+    c = CONFIGS["c5"]
+    N = 16_000_000
+    h, eri = make_integrals(c.n, c.rank, c.seed_int)
+    pool = enumerate_pool(c.n)
+    keys, amps = draw_synthetic_state(c.n, 8, 8, N, 4005)
+    rng = np.random.default_rng(4005)
+    doubles = np.flatnonzero(pool[:, 2] >= 0)
+    ops = rng.choice(doubles, 8).astype(np.int32)
+    theta = rng.uniform(-0.3, 0.3, len(ops))
+    _say("[parity] 16M: gpu gates")
+    ctx = swcs.make_context(c.n, 8, 8, h, eri, pool, reference_key(16))
+    ctx.set_state(keys, amps)
+    n_out = ctx.apply_gates(ops, theta, 0.0)
+    kg, ag = ctx.get_state()
+    assert len(kg) == n_out and n_out > N
+    order = np.argsort(keys)
+    ks0, as0 = keys[order], amps[order]
+    masks = [_pair_mask(pool[k]) for k in ops]
+    span = [0]
+    for m in masks:
+        span = span + [x ^ m for x in span]
+    span = np.unique(np.array(span, dtype=np.uint64))
+    srng = np.random.default_rng(16)
+    sample = np.concatenate([srng.choice(len(kg), 96, replace=False),
+                             np.argsort(-np.abs(ag))[:32]])
+    _say("[parity] 16M: light cones")
+    for i in sample:
+        D = kg[i]
+        cone = np.bitwise_xor(span, D)
+        pos = np.searchsorted(ks0, cone)
+        pos = np.minimum(pos, len(ks0) - 1)
+        hit = ks0[pos] == cone
+        st = oracle.OracleState.from_arrays(cone[hit], as0[pos[hit]])
+        for k, t in zip(ops, theta):
+            st, _ = oracle.Oracle.apply_gate_truncate(st, pool[k], math.cos(t), math.sin(t), 0.0)
+        ko, ao = st.export()
+        j = np.searchsorted(ko, D)
+        assert j < len(ko) and ko[j] == D
+        assert ao[j] == ag[i] or (np.isnan(ao[j]) and np.isnan(ag[i]))
+    _say("[parity] 16M: sigma rows (hole pairs)")
+    ctx.set_state(keys, amps)
+    ctx.set_sigma_method("hole_pairs")
+    ks, sig = ctx.sigma_projected()
+    assert np.array_equal(ks, ks0)
+    full = oracle.OracleState.from_arrays(ks0, as0)
+    orc = oracle.Oracle(c.n, 8, 8, h, eri)
+    rows = np.concatenate([np.argsort(-np.abs(sig))[:16], srng.choice(N, 32, replace=False)])
+    assert np.abs(sig[rows] - orc.sigma_at(full, ks[rows])).max() < TOL
+    ctx.close()
+
+
 def test_determinism(swcs, c2):
     ctx = make_ctx(swcs, c2)
     ctx.apply_ansatz(c2.ops, c2.theta, c2.eps)
