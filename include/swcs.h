@@ -94,12 +94,16 @@ int swcs_set_capacity(swcs_ctx* ctx, int64_t max_dets);
  * every single and double excitation of every alive determinant (alive * C
  * probes).  HOLE_PAIRS groups the determinants by their subsets of N_e - 2
  * electrons (a sort of n * C(N_e, 2) records) and evaluates only pairs that
- * share one, which are exactly the pairs within a double excitation.  AUTO
- * (default) takes HOLE_PAIRS when the probe count would exceed 3e7.  Both
- * give the same sigma up to summation order.  Returns SWCS_E_INVALID for an
- * unknown method. */
-enum { SWCS_SIGMA_AUTO = 0, SWCS_SIGMA_ENUMERATE = 1, SWCS_SIGMA_HOLE_PAIRS = 2 };
+ * share one, which are exactly the pairs within a double excitation.  PAIRS
+ * (states of at most 4,096 stored determinants; larger ones fall back to
+ * AUTO's choice among the others) tests every pair of stored determinants in
+ * LDS by popcount.  AUTO (default) takes PAIRS when the state
+ * fits and n <= 8 C, otherwise HOLE_PAIRS when the probe count would exceed
+ * 3e7, otherwise ENUMERATE.  All give the same sigma up to summation order.
+ * Returns SWCS_E_INVALID for an unknown method. */
+enum { SWCS_SIGMA_AUTO = 0, SWCS_SIGMA_ENUMERATE = 1, SWCS_SIGMA_HOLE_PAIRS = 2, SWCS_SIGMA_PAIRS = 3 };
 int swcs_set_sigma_method(swcs_ctx* ctx, int method);
+
 
 /* Step 1 of the ADAPT procedure (Sec. II.C): molecular integrals.  h[n*n] and
  * eri[n^4] (host, float64, layouts above).  Rejects non-finite values, an

@@ -88,109 +88,111 @@ k_chain_lds(u64* __restrict__ keys, double* __restrict__ amps, Counters* __restr
   __shared__ u64 skeys[CAP];
   __shared__ double samps[CAP];
   __shared__ int sslots[2 * CAP];
-  __shared__ unsigned s_n, s_app, s_alive;
-  __shared__ int s_dalive;
-  __shared__ int s_stop;
+  // Per-gate append and alive-change counters, three in rotation: gate g
+  // uses slot g % 3; after the gate's barrier every thread reads it, and
+  // thread 0 clears slot (g + 2) % 3, last read before the previous barrier
+  // and next used after the following one.
+  __shared__ unsigned s_app[3];
+  __shared__ int s_dal[3];
+  __shared__ unsigned s_n0, s_alive0;
   __shared__ GateDesc sg[kGateChunk];
   const int tid = threadIdx.x;
   if (tid == 0) {
-    s_n = (unsigned)ctr->n;
-    s_alive = (unsigned)ctr->alive;
-    s_app = 0;
-    s_dalive = 0;
-    s_stop = -1;
+    s_n0 = (unsigned)ctr->n;
+    s_alive0 = (unsigned)ctr->alive;
+  }
+  if (tid < 3) {
+    s_app[tid] = 0;
+    s_dal[tid] = 0;
   }
   for (int t = tid; t < 2 * CAP; t += kChainThreads) sslots[t] = 0;
   __syncthreads();
-  const unsigned n0 = s_n;
-  if (n0 > (unsigned)CAP) {
+  unsigned n = s_n0, alive = s_alive0;  // block-uniform, kept in every thread
+  if (n > (unsigned)CAP) {
     if (tid == 0) {
       ctr->stop_gate = (u64)g0;
       atomicOr(&ctr->flags, kFlagStopped);
     }
     return;
   }
-  for (unsigned i = tid; i < n0; i += kChainThreads) {
+  for (unsigned i = tid; i < n; i += kChainThreads) {
     skeys[i] = keys[i];
     samps[i] = amps[i];
   }
   __syncthreads();
   LdsStore S{skeys, samps, sslots, 2u * CAP - 1u};
-  for (unsigned i = tid; i < n0; i += kChainThreads) S.insert(skeys[i], (int)i);
-  __syncthreads();
+  for (unsigned i = tid; i < n; i += kChainThreads) S.insert(skeys[i], (int)i);
+  int stop = -1;
   for (int g = g0; g < M; ++g) {
+    // Every earlier read of sg and every write of the previous gate happened
+    // before the previous gate's barrier (or the index build's).
     if ((g - g0) % kGateChunk == 0) {
-      // stage the next chunk of gate descriptors (all earlier reads of sg done)
-      __syncthreads();
       for (int t = tid; t < kGateChunk && g + t < M; t += kChainThreads) sg[t] = gates[g + t];
       __syncthreads();
     }
-    const unsigned n = s_n, alive = s_alive;
     if (ckpt && g % seg == 0) {
       double* dst = ckpt[g / seg];
       for (unsigned i = tid; i < n; i += kChainThreads) dst[i] = samps[i];
       if (tid == 0) ckpt_n[g / seg] = n;
+      __syncthreads();  // the copy precedes the gate's updates
     }
     const u64 room = max_keys > n ? max_keys - n : 0;
     if ((u64)n + ((u64)alive < room ? (u64)alive : room) > (u64)CAP) {
-      if (tid == 0) s_stop = g;
-      break;  // uniform: every thread read the same n and alive
+      stop = g;
+      break;  // uniform: every thread holds the same n and alive
     }
+    const int slot = g % 3;
     const GateDesc gd = sg[(g - g0) % kGateChunk];
     int dal = 0;
     for (unsigned i = tid; i < n; i += kChainThreads) {
       const GateOut o = gate_entry(S, i, gd.op, gd.c, gd.s, eps);
       dal += (int)o.dalive;
       if (o.append) {
-        const unsigned idx = n + atomicAdd(&s_app, 1u);
+        const unsigned idx = n + atomicAdd(&s_app[slot], 1u);
         skeys[idx] = o.key;
         samps[idx] = o.val;
         __threadfence_block();
         S.insert(o.key, (int)idx);
       }
     }
-    if (dal) atomicAdd(&s_dalive, dal);
+    if (dal) atomicAdd(&s_dal[slot], dal);
     __syncthreads();
     if (tid == 0) {
       if (gate_n_in) gate_n_in[g] = alive;
-      s_n = n + s_app;
-      s_alive = (unsigned)((int)alive + s_dalive);
-      s_app = 0;
-      s_dalive = 0;
+      s_app[(g + 2) % 3] = 0;
+      s_dal[(g + 2) % 3] = 0;
     }
-    __syncthreads();
-    if (ncut && s_alive > ncut) {
-      const unsigned dropped = lds_ncut(samps, skeys, s_n, ncut, nst);
-      if (tid == 0) s_alive -= dropped;
-      __syncthreads();
-    }
+    n += s_app[slot];
+    alive = (unsigned)((int)alive + s_dal[slot]);
+    if (ncut && alive > ncut) alive -= lds_ncut(samps, skeys, n, ncut, nst);
     if (g == 0 && prune_first) {
       // Entries of a caller-supplied starting state that the first gate did
       // not touch have not been tested against eps yet.
-      const unsigned n1 = s_n;
-      int dropped = 0;
-      for (unsigned i = tid; i < n1; i += kChainThreads) {
+      if (tid == 0) nst.pad[1] = 0;
+      __syncthreads();
+      unsigned dropped = 0;
+      for (unsigned i = tid; i < n; i += kChainThreads) {
         const double a = samps[i];
         if (!is_dead(a) && fabs(a) < eps) {
           samps[i] = dead_value();
           ++dropped;
         }
       }
-      if (dropped) atomicSub(&s_alive, (unsigned)dropped);
+      if (dropped) atomicAdd(&nst.pad[1], dropped);
       __syncthreads();
+      alive -= nst.pad[1];
     }
   }
   __syncthreads();
-  const unsigned n = s_n;
   for (unsigned i = tid; i < n; i += kChainThreads) {
     keys[i] = skeys[i];
     amps[i] = samps[i];
   }
   if (tid == 0) {
     ctr->n = n;
-    ctr->alive = s_alive;
-    if (s_stop >= 0) {
-      ctr->stop_gate = (u64)s_stop;
+    ctr->alive = alive;
+    if (stop >= 0) {
+      ctr->stop_gate = (u64)stop;
       atomicOr(&ctr->flags, kFlagStopped);
     }
   }

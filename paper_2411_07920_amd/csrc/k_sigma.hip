@@ -356,6 +356,77 @@ k_sigma_dots(const double* __restrict__ amps, const double* __restrict__ sigma, 
   }
 }
 
+// ---------------------------------------------------------------- small states
+// sigma_P for states of at most kPairCap stored determinants: every pair is tested;
+// two determinants of one sector have a nonzero Slater-Condon element only
+// if they differ in at most four spin-orbitals, which a popcount decides.
+// The whole state sits in LDS (dynamic, at most 64 KB), so there is no index
+// or accumulation table and no atomics; each output is a fixed-order sum.
+constexpr int kPairCap = 4096;  // sigma_P by pairs: 16 B of LDS per entry
+
+// <X|H|D> for X, D of one sector differing in at most four spin-orbitals.
+__device__ inline double pair_element(const Ints& I, u64 X, u64 D) {
+  const u64 diff = X ^ D;
+  const int pc = __popcll(diff);
+  if (pc == 0) return diag_element(I, X);
+  const u64 holes = D & diff, parts = X & diff;
+  if (pc == 2) return single_element(I, D, __ffsll((long long)holes) - 1, __ffsll((long long)parts) - 1);
+  return double_element(I, D, __ffsll((long long)holes) - 1, 63 - __clzll((long long)holes),
+                        __ffsll((long long)parts) - 1, 63 - __clzll((long long)parts));
+}
+
+__device__ inline void stage_state(const u64* __restrict__ keys, const double* __restrict__ amps,
+                                   unsigned n, u64* sk, double* sa) {
+  for (unsigned i = threadIdx.x; i < n; i += blockDim.x) {
+    const double a = amps[i];
+    sk[i] = keys[i];
+    sa[i] = is_dead(a) ? 0.0 : a;
+  }
+}
+
+// sigma_P by pairs: one wavefront per row D, lanes over the columns D'.
+// Dead rows get 0; per-block partial sums of psi*sigma and psi^2.
+__global__ void __launch_bounds__(256)
+k_sigma_pairwise(const u64* __restrict__ keys, const double* __restrict__ amps, unsigned n, Ints I,
+                 double* __restrict__ sigma, double* __restrict__ partial) {
+  extern __shared__ __align__(16) unsigned char pair_dyn[];
+  u64* sk = (u64*)pair_dyn;      // n keys
+  double* sa = (double*)(sk + n);  // n amplitudes (0 for dead entries)
+  __shared__ double r1[4], r2[4];
+  stage_state(keys, amps, n, sk, sa);
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double num = 0.0, nrm = 0.0;
+  for (unsigned d = blockIdx.x * 4 + wave; d < n; d += gridDim.x * 4) {
+    const double psiD = sa[d];
+    const bool alive = !is_dead(amps[d]);
+    const u64 D = sk[d];
+    double acc = 0.0;
+    if (alive) {
+      for (unsigned j = lane; j < n; j += 64) {
+        const double pj = sa[j];
+        if (pj == 0.0 || __popcll(D ^ sk[j]) > 4) continue;
+        acc += pair_element(I, D, sk[j]) * pj;
+      }
+    }
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    if (lane == 0) {
+      sigma[d] = alive ? acc : 0.0;
+      num += psiD * acc;
+      nrm += psiD * psiD;
+    }
+  }
+  if (lane == 0) {
+    r1[wave] = num;
+    r2[wave] = nrm;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    partial[blockIdx.x] = r1[0] + r1[1] + r1[2] + r1[3];
+    partial[gridDim.x + blockIdx.x] = r2[0] + r2[1] + r2[2] + r2[3];
+  }
+}
+
 // Batch of an external determinant when the accumulation table is split.
 __device__ inline int batch_of(u64 X, int nbatch) {
   return (int)((mix64(X ^ 0x9e3779b97f4a7c15ULL) >> 32) % (u64)nbatch);
@@ -709,6 +780,16 @@ __global__ void k_mu_init(const double* __restrict__ amps, const double* __restr
     const double a = amps[i];
     mu[i] = is_dead(a) ? 0.0 : scale * (sigma[i] - E * a);
   }
+}
+
+int pairwise_capacity() { return kPairCap; }
+
+hipError_t launch_sigma_pairwise(const DeviceState& st, const Ints& I, u64 n, double* sigma,
+                                 double* partial, int grid, hipStream_t stream) {
+  if (n > (u64)kPairCap) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_sigma_pairwise, dim3(grid), dim3(256), (size_t)n * 16, stream, st.keys,
+                     st.amps, (unsigned)n, I, sigma, partial);
+  return hipGetLastError();
 }
 
 hipError_t launch_sigma_proj(const DeviceState& st, const Ints& I, const ExcSpace& E, u64 n,

@@ -545,7 +545,8 @@ int swcs_set_capacity(swcs_ctx* c, int64_t max_dets) {
 
 int swcs_set_sigma_method(swcs_ctx* c, int method) {
   if (!c) return SWCS_E_INVALID;
-  if (method != SWCS_SIGMA_AUTO && method != SWCS_SIGMA_ENUMERATE && method != SWCS_SIGMA_HOLE_PAIRS)
+  if (method != SWCS_SIGMA_AUTO && method != SWCS_SIGMA_ENUMERATE && method != SWCS_SIGMA_HOLE_PAIRS &&
+      method != SWCS_SIGMA_PAIRS)
     return fail(c, SWCS_E_INVALID, "unknown sigma method");
   c->sigma_method = method;
   return SWCS_OK;
@@ -826,6 +827,16 @@ static bool use_holepair(swcs_ctx* c, u64 alive) {
   return (double)alive * (double)c->exc.total > kHolePairProbes;
 }
 
+// Small states: every pair of stored determinants is tested in LDS.  The
+// automatic choice takes it when the pair count is at most 8 probes' worth
+// of enumeration per determinant.
+static bool use_sigma_pairs(swcs_ctx* c, u64 n) {
+  if (n == 0 || n > (u64)pairwise_capacity()) return false;
+  if (c->sigma_method == SWCS_SIGMA_PAIRS) return true;
+  if (c->sigma_method != SWCS_SIGMA_AUTO) return false;
+  return (double)n <= 8.0 * (double)c->exc.total;
+}
+
 // sigma_P over the stored entries; (numer, norm2) land in scalars[0..1] on
 // the device, without synchronizing.
 static int energy_enqueue(swcs_ctx* c, u64 n) {
@@ -835,6 +846,14 @@ static int energy_enqueue(swcs_ctx* c, u64 n) {
   hipError_t e;
   const Counters h = get_counters(c, &e);
   if (e != hipSuccess) return hip_fail(c, e, "read counters");
+  if (use_sigma_pairs(c, n)) {
+    const int pgrid = (int)std::min<u64>((n + 3) / 4, (u64)c->num_cu * 8);
+    HIP_TRY(c, c->partial.ensure((size_t)2 * pgrid * 8), "alloc partial");
+    TIMED(c, SWCS_K_SIGMA_PROJ, launch_sigma_pairwise(c->st, ints_view(c), n, c->sigma.as<double>(),
+                                 c->partial.as<double>(), pgrid, c->stream), "sigma pairs");
+    HIP_TRY(c, launch_reduce_partials(c->partial.as<double>(), pgrid, pgrid, 2, c->scalars.as<double>(), c->stream), "reduce");
+    return SWCS_OK;
+  }
   if (n > 0 && use_holepair(c, h.alive)) {
     const int ne = c->na + c->nb;
     const u64 total = n * ((u64)ne * (u64)(ne - 1) / 2);

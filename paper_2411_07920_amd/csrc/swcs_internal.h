@@ -343,6 +343,9 @@ hipError_t launch_mark_dead_range(double* amps, u64 lo, u64 hi, hipStream_t stre
 hipError_t launch_sigma_proj(const DeviceState& st, const Ints& I, const ExcSpace& E, u64 n,
                              double* sigma, double* partial_num, double* partial_norm, int grid,
                              hipStream_t stream);
+int pairwise_capacity();
+hipError_t launch_sigma_pairwise(const DeviceState& st, const Ints& I, u64 n, double* sigma,
+                                 double* partial, int grid, hipStream_t stream);
 hipError_t launch_holepair_emit(const DeviceState& st, u64 n, int ne, u64* out_key, u64* out_val,
                                 int grid, hipStream_t stream);
 hipError_t launch_sigma_diag(const DeviceState& st, const Ints& I, u64 n, double* sigma, int grid,

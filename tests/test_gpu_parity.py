@@ -241,7 +241,7 @@ def two_electron_case():
     return Case(n, ne, h, eri, pool, ops, theta, 0.0, "ne2")
 
 
-@pytest.mark.parametrize("method", ["enumerate", "hole_pairs"])
+@pytest.mark.parametrize("method", ["enumerate", "hole_pairs", "pairs"])
 def test_sigma_methods(swcs, spread, method):
     """Both ways of forming sigma_P against the oracle: energy, sigma rows and
     the adjoint gradients that start from sigma_P."""
@@ -380,25 +380,28 @@ def test_synthetic_state_gates_bit_exact(swcs):
     c = CONFIGS["c5"]
     h, eri = make_integrals(c.n, c.rank, c.seed_int)
     pool = enumerate_pool(c.n)
-    keys, amps = draw_synthetic_state(c.n, 8, 8, 200_000, 4005)
     rng = np.random.default_rng(9)
     singles = np.flatnonzero(pool[:, 2] < 0)
     doubles = np.flatnonzero(pool[:, 2] >= 0)
     ops = np.concatenate([rng.choice(singles, 4), rng.choice(doubles, 8)]).astype(np.int32)
     theta = rng.uniform(-0.3, 0.3, len(ops))
     ctx = swcs.make_context(c.n, 8, 8, h, eri, pool, reference_key(16))
-    st = oracle.OracleState.from_arrays(keys, amps)
-    for eps in (0.0, 1e-5):
-        _say(f"[parity] synthetic 200k, eps={eps}")
-        ctx.set_state(keys, amps)
-        ctx.apply_gates(ops, theta, eps)
-        cur = st
-        for k, t in zip(ops, theta):
-            cur, _ = oracle.Oracle.apply_gate_truncate(cur, pool[k], math.cos(t), math.sin(t), eps)
-        k_ref, a_ref = cur.export()
-        k_gpu, a_gpu = ctx.get_state()
-        assert np.array_equal(k_gpu, k_ref)
-        assert np.array_equal(a_gpu, a_ref)
+    # 1,500 entries run in the single-workgroup chain (starting state pruned
+    # after the first gate), 200,000 on the HBM path
+    for N in (1_500, 200_000):
+        keys, amps = draw_synthetic_state(c.n, 8, 8, N, 4005)
+        st = oracle.OracleState.from_arrays(keys, amps)
+        for eps in (0.0, 1e-5):
+            _say(f"[parity] synthetic {N}, eps={eps}")
+            ctx.set_state(keys, amps)
+            ctx.apply_gates(ops, theta, eps)
+            cur = st
+            for k, t in zip(ops, theta):
+                cur, _ = oracle.Oracle.apply_gate_truncate(cur, pool[k], math.cos(t), math.sin(t), eps)
+            k_ref, a_ref = cur.export()
+            k_gpu, a_gpu = ctx.get_state()
+            assert np.array_equal(k_gpu, k_ref)
+            assert np.array_equal(a_gpu, a_ref)
     ctx.close()
 
 
