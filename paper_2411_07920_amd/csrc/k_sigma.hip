@@ -182,13 +182,54 @@ __device__ inline double block_sum(double v, double* red) {
   return r;
 }
 
+// Diagonal Slater-Condon elements of the stored determinants (0 for dead
+// entries), one wavefront per determinant: lane l finds the l-th occupied
+// spin-orbital, the lanes split the N_e^2 occupied pairs, and a wavefront sum
+// adds them, so the integral loads of one determinant are spread over the
+// lanes instead of one thread.
+__global__ void __launch_bounds__(256)
+k_diag(const u64* __restrict__ keys, const double* __restrict__ amps, u64 n, Ints I,
+       double* __restrict__ diag) {
+  const int lane = threadIdx.x & 63;
+  const u64 w0 = ((u64)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const u64 wstride = ((u64)gridDim.x * blockDim.x) >> 6;
+  for (u64 d = w0; d < n; d += wstride) {
+    if (is_dead(amps[d])) {
+      if (lane == 0) diag[d] = 0.0;
+      continue;
+    }
+    const u64 D = keys[d];
+    const int ne = __popcll(D);
+    u64 x = D;
+    for (int t = 0; t < lane && x; ++t) x &= x - 1;
+    const int P = (lane < ne) ? __ffsll((long long)x) - 1 : 0;
+    double e = 0.0;
+    if (lane < ne) e += I.h[(P >> 1) * I.n + (P >> 1)];
+    const int npair = ne * ne;
+    for (int t0 = 0; t0 < npair; t0 += 64) {  // same trip count in every lane
+      const int t = t0 + lane;
+      const int a = (t < npair) ? t / ne : 0;
+      const int b = (t < npair) ? t - a * ne : 0;
+      const int Pa = __shfl(P, a), Pb = __shfl(P, b);
+      if (t < npair) {
+        const int p = Pa >> 1, q = Pb >> 1;
+        double v = I.J[p * I.n + q];
+        if (((Pa ^ Pb) & 1) == 0) v -= I.K[p * I.n + q];
+        e += 0.5 * v;
+      }
+    }
+    for (int off = 32; off > 0; off >>= 1) e += __shfl_xor(e, off);
+    if (lane == 0) diag[d] = I.ecore + e;
+  }
+}
+
 // sigma_P(D) = sum_{D' in psi} H_{D D'} psi(D') for every stored entry D
 // (dead entries get 0), plus per-block partial sums of psi*sigma and psi^2.
 __global__ void __launch_bounds__(kSigBlock)
 k_sigma_proj(const u64* __restrict__ keys, const double* __restrict__ amps,
              const HashSlot* __restrict__ hash, u64 hmask, const unsigned* __restrict__ filt,
-             u64 fmask, Ints I, ExcSpace E, u64 n, double* __restrict__ sigma,
-             double* __restrict__ partial) {
+             u64 fmask, Ints I, ExcSpace E, u64 n, const double* __restrict__ diag,
+             double* __restrict__ sigma, double* __restrict__ partial) {
   __shared__ SigShared S;
   __shared__ ConnTables T;
   extern __shared__ __align__(16) unsigned char conn_dyn[];
@@ -217,7 +258,7 @@ k_sigma_proj(const u64* __restrict__ keys, const double* __restrict__ amps,
       if (is_dead(psiX)) return;
       acc += connection_element(I, D, nh, h0, h1, p0, p1) * psiX;
     });
-    if (threadIdx.x == 0) acc += diag_element(I, D) * psiD;
+    if (threadIdx.x == 0) acc += diag[d] * psiD;
     const double sig = block_sum(acc, red);
     if (threadIdx.x == 0) {
       sigma[d] = sig;
@@ -275,12 +316,12 @@ k_holepair_emit(const u64* __restrict__ keys, const double* __restrict__ amps, u
 
 // sigma[i] = H_ii psi_i for alive entries, 0 for dead ones.
 __global__ void __launch_bounds__(256)
-k_sigma_diag(const u64* __restrict__ keys, const double* __restrict__ amps, Ints I, u64 n,
+k_sigma_diag(const double* __restrict__ amps, const double* __restrict__ diag, u64 n,
              double* __restrict__ sigma) {
   const u64 stride = (u64)gridDim.x * blockDim.x;
   for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
     const double a = amps[i];
-    sigma[i] = is_dead(a) ? 0.0 : diag_element(I, keys[i]) * a;
+    sigma[i] = is_dead(a) ? 0.0 : diag[i] * a;
   }
 }
 
@@ -364,11 +405,11 @@ k_sigma_dots(const double* __restrict__ amps, const double* __restrict__ sigma, 
 // or accumulation table and no atomics; each output is a fixed-order sum.
 constexpr int kPairCap = 4096;  // sigma_P by pairs: 16 B of LDS per entry
 
-// <X|H|D> for X, D of one sector differing in at most four spin-orbitals.
+// <X|H|D> for distinct X, D of one sector differing in at most four
+// spin-orbitals.
 __device__ inline double pair_element(const Ints& I, u64 X, u64 D) {
   const u64 diff = X ^ D;
   const int pc = __popcll(diff);
-  if (pc == 0) return diag_element(I, X);
   const u64 holes = D & diff, parts = X & diff;
   if (pc == 2) return single_element(I, D, __ffsll((long long)holes) - 1, __ffsll((long long)parts) - 1);
   return double_element(I, D, __ffsll((long long)holes) - 1, 63 - __clzll((long long)holes),
@@ -388,7 +429,8 @@ __device__ inline void stage_state(const u64* __restrict__ keys, const double* _
 // Dead rows get 0; per-block partial sums of psi*sigma and psi^2.
 __global__ void __launch_bounds__(256)
 k_sigma_pairwise(const u64* __restrict__ keys, const double* __restrict__ amps, unsigned n, Ints I,
-                 double* __restrict__ sigma, double* __restrict__ partial) {
+                 const double* __restrict__ diag, double* __restrict__ sigma,
+                 double* __restrict__ partial) {
   extern __shared__ __align__(16) unsigned char pair_dyn[];
   u64* sk = (u64*)pair_dyn;      // n keys
   double* sa = (double*)(sk + n);  // n amplitudes (0 for dead entries)
@@ -403,9 +445,10 @@ k_sigma_pairwise(const u64* __restrict__ keys, const double* __restrict__ amps, 
     const u64 D = sk[d];
     double acc = 0.0;
     if (alive) {
+      if (lane == 0) acc = diag[d] * psiD;
       for (unsigned j = lane; j < n; j += 64) {
         const double pj = sa[j];
-        if (pj == 0.0 || __popcll(D ^ sk[j]) > 4) continue;
+        if (pj == 0.0 || j == d || __popcll(D ^ sk[j]) > 4) continue;
         acc += pair_element(I, D, sk[j]) * pj;
       }
     }
@@ -436,8 +479,8 @@ __device__ inline int batch_of(u64 X, int nbatch) {
 // D' and its singles and doubles (only X of the current batch).
 __global__ void __launch_bounds__(kSigBlock)
 k_sigma_push(const u64* __restrict__ keys, const double* __restrict__ amps, Ints I, ExcSpace E,
-             u64 n, AccSlot* __restrict__ tab, u64 tmask, int nbatch, int batch,
-             unsigned* __restrict__ flags, double* __restrict__ inserted) {
+             u64 n, const double* __restrict__ diag, AccSlot* __restrict__ tab, u64 tmask,
+             int nbatch, int batch, unsigned* __restrict__ flags, double* __restrict__ inserted) {
   __shared__ SigShared S;
   __shared__ ConnTables T;
   extern __shared__ __align__(16) unsigned char conn_dyn[];
@@ -455,7 +498,7 @@ k_sigma_push(const u64* __restrict__ keys, const double* __restrict__ amps, Ints
     build_conn_tables(S, E, T);
     __syncthreads();
     if (threadIdx.x == 0 && (nbatch == 1 || batch_of(D, nbatch) == batch)) {
-      const int r = acc_add(tab, tmask, D, diag_element(I, D) * psiD);
+      const int r = acc_add(tab, tmask, D, diag[d] * psiD);
       if (!r) atomicOr(flags, kFlagOverflow);
       ins += (r == 2) ? 1.0 : 0.0;
     }
@@ -658,7 +701,7 @@ __device__ inline double* acc_slot(AccSlot* tab, u64 mask, u64 key) {
 
 __global__ void __launch_bounds__(kSigBlock)
 k_sigma_push_into(const u64* __restrict__ keys, const double* __restrict__ amps, Ints I, ExcSpace E,
-                  u64 n, AccSlot* __restrict__ tab, u64 tmask) {
+                  u64 n, const double* __restrict__ diag, AccSlot* __restrict__ tab, u64 tmask) {
   __shared__ SigShared S;
   __shared__ ConnTables T;
   extern __shared__ __align__(16) unsigned char conn_dyn[];
@@ -675,7 +718,7 @@ k_sigma_push_into(const u64* __restrict__ keys, const double* __restrict__ amps,
     __syncthreads();
     if (threadIdx.x == 0) {
       double* v = acc_slot(tab, tmask, D);
-      if (v) unsafeAtomicAdd(v, diag_element(I, D) * psiD);
+      if (v) unsafeAtomicAdd(v, diag[d] * psiD);
     }
     for_each_connection(T, D, [&](u64 X, int nh, int h0, int h1, int p0, int p1) {
       double* v = acc_slot(tab, tmask, X);
@@ -788,7 +831,13 @@ hipError_t launch_sigma_pairwise(const DeviceState& st, const Ints& I, u64 n, do
                                  double* partial, int grid, hipStream_t stream) {
   if (n > (u64)kPairCap) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_sigma_pairwise, dim3(grid), dim3(256), (size_t)n * 16, stream, st.keys,
-                     st.amps, (unsigned)n, I, sigma, partial);
+                     st.amps, (unsigned)n, I, st.diag, sigma, partial);
+  return hipGetLastError();
+}
+
+hipError_t launch_diag(const DeviceState& st, const Ints& I, u64 n, int grid, hipStream_t stream) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_diag, dim3(grid), dim3(256), 0, stream, st.keys, st.amps, n, I, st.diag);
   return hipGetLastError();
 }
 
@@ -797,7 +846,7 @@ hipError_t launch_sigma_proj(const DeviceState& st, const Ints& I, const ExcSpac
                              hipStream_t stream) {
   (void)partial_norm;
   hipLaunchKernelGGL(k_sigma_proj, dim3(grid), dim3(kSigBlock), conn_tables_bytes(E), stream, st.keys, st.amps,
-                     st.hash, st.hmask, st.filt, st.fmask, I, E, n, sigma, partial_num);
+                     st.hash, st.hmask, st.filt, st.fmask, I, E, n, st.diag, sigma, partial_num);
   return hipGetLastError();
 }
 
@@ -810,7 +859,8 @@ hipError_t launch_holepair_emit(const DeviceState& st, u64 n, int ne, u64* out_k
 
 hipError_t launch_sigma_diag(const DeviceState& st, const Ints& I, u64 n, double* sigma, int grid,
                              hipStream_t stream) {
-  hipLaunchKernelGGL(k_sigma_diag, dim3(grid), dim3(256), 0, stream, st.keys, st.amps, I, n, sigma);
+  (void)I;
+  hipLaunchKernelGGL(k_sigma_diag, dim3(grid), dim3(256), 0, stream, st.amps, st.diag, n, sigma);
   return hipGetLastError();
 }
 
@@ -848,7 +898,7 @@ hipError_t launch_sigma_push(const DeviceState& st, const Ints& I, const ExcSpac
                              AccSlot* tab, u64 tmask, int nbatch, int batch, double* inserted,
                              int grid, hipStream_t stream) {
   hipLaunchKernelGGL(k_sigma_push, dim3(grid), dim3(kSigBlock), conn_tables_bytes(E), stream, st.keys, st.amps, I, E,
-                     n, tab, tmask, nbatch, batch, &st.ctr->flags, inserted);
+                     n, st.diag, tab, tmask, nbatch, batch, &st.ctr->flags, inserted);
   return hipGetLastError();
 }
 
@@ -894,7 +944,7 @@ hipError_t launch_contract_ops(const DeviceState& st, u64 n, const OpDesc* ops, 
 hipError_t launch_sigma_push_into(const DeviceState& st, const Ints& I, const ExcSpace& E, u64 n,
                                   AccSlot* tab, u64 tmask, int grid, hipStream_t stream) {
   hipLaunchKernelGGL(k_sigma_push_into, dim3(grid), dim3(kSigBlock), conn_tables_bytes(E), stream, st.keys, st.amps, I,
-                     E, n, tab, tmask);
+                     E, n, st.diag, tab, tmask);
   return hipGetLastError();
 }
 

@@ -115,7 +115,7 @@ struct swcs_ctx {
   // scratch
   DevBuf gacc, selected, ncut_state;
   DevBuf partial, partial2, sigma, mu, work, seg_states, acc_tab, gbuf, subset_buf, scalars,
-      exp_keys, exp_amps, exp_tmp_k, exp_tmp_v, sort_scratch, ctr_r, occ, sel_scratch, mlp_partial, mse_partial, hp_key, hp_val, hp_tk, hp_tv;
+      exp_keys, exp_amps, exp_tmp_k, exp_tmp_v, sort_scratch, ctr_r, occ, sel_scratch, mlp_partial, mse_partial, hp_key, hp_val, hp_tk, hp_tv, diag;
   int sigma_method = SWCS_SIGMA_AUTO;
   double ext_count = 0.0, ext_alive = 0.0;  // distinct external keys of the last full pool pass
 
@@ -125,7 +125,7 @@ struct swcs_ctx {
                      &partial, &partial2, &sigma, &mu, &work, &seg_states, &acc_tab, &gbuf,
                      &subset_buf, &scalars, &exp_keys, &exp_amps, &exp_tmp_k, &exp_tmp_v,
                      &sort_scratch, &ctr_r, &occ, &sel_scratch, &mlp_partial, &mse_partial,
-                     &hp_key, &hp_val, &hp_tk, &hp_tv};
+                     &hp_key, &hp_val, &hp_tk, &hp_tv, &diag};
     for (DevBuf* b : all) b->release();
     for (auto& b : ckpt) b.release();
     for (hipEvent_t e : ev_start) (void)hipEventDestroy(e);
@@ -837,10 +837,21 @@ static bool use_sigma_pairs(swcs_ctx* c, u64 n) {
   return (double)n <= 8.0 * (double)c->exc.total;
 }
 
+// Diagonal elements of the n stored entries into c->diag (stream-ordered).
+static int diag_enqueue(swcs_ctx* c, u64 n) {
+  HIP_TRY(c, c->diag.ensure(std::max<u64>(1, n) * 8), "alloc diagonal");
+  c->st.diag = c->diag.as<double>();
+  const u64 waves = n;
+  HIP_TRY(c, launch_diag(c->st, ints_view(c), n, grid_blocks(c, waves * 64, 256), c->stream), "diagonal");
+  return SWCS_OK;
+}
+
 // sigma_P over the stored entries; (numer, norm2) land in scalars[0..1] on
 // the device, without synchronizing.
 static int energy_enqueue(swcs_ctx* c, u64 n) {
   const int grid = sigma_grid(c, n);
+  int rd = diag_enqueue(c, n);
+  if (rd) return rd;
   HIP_TRY(c, c->sigma.ensure(std::max<u64>(1, n) * 8), "alloc sigma");
   HIP_TRY(c, c->partial.ensure((size_t)2 * grid * 8), "alloc partial");
   hipError_t e;
@@ -868,7 +879,7 @@ static int energy_enqueue(swcs_ctx* c, u64 n) {
     HIP_TRY(c, radix_sort_pairs(c->hp_key.as<u64>(), c->hp_val.as<u64>(), c->hp_tk.as<u64>(), c->hp_tv.as<u64>(),
                                 total, c->nso, c->sort_scratch.as<u64>(), scr, c->stream), "sort");
     HIP_TRY(c, launch_sigma_diag(c->st, ints_view(c), n, c->sigma.as<double>(), grid_blocks(c, n, 256),
-                                 c->stream), "diagonal");
+                                 c->stream), "diagonal sigma");
     TIMED(c, SWCS_K_HOLEPAIR, launch_holepair_sigma(c->st, ints_view(c), c->hp_key.as<u64>(), c->hp_val.as<u64>(),
                                   total, c->sigma.as<double>(), rg, c->stream), "hole pairs");
     HIP_TRY(c, launch_sigma_dots(c->st, c->sigma.as<double>(), n, c->partial.as<double>(), grid, c->stream), "dots");
@@ -1005,6 +1016,8 @@ static int pool_setup(swcs_ctx* c, Counters* h) {
   if (e != hipSuccess) return hip_fail(c, e, "read counters");
   if (h->alive == 0) return fail(c, SWCS_E_STATE, "state is empty");
   r = norm2_enqueue(c, h->n);
+  if (r) return r;
+  r = diag_enqueue(c, h->n);
   if (r) return r;
   HIP_TRY(c, c->gacc.ensure((size_t)c->K_pool * 8), "alloc g accumulator");
   HIP_TRY(c, hipMemsetAsync(c->gacc.p, 0, (size_t)c->K_pool * 8, c->stream), "zero g");

@@ -289,6 +289,7 @@ struct DeviceState {
   u64 hmask = 0;      // hash capacity - 1
   unsigned* filt = nullptr;  // presence filter of the alive keys (1 bit per hash)
   u64 fmask = 0;             // filter bits - 1
+  double* diag = nullptr;    // diagonal elements H_DD of the stored entries (launch_diag)
 };
 
 // Presence filter: one bit per (independent) hash of an alive key, about 16
@@ -346,6 +347,7 @@ hipError_t launch_sigma_proj(const DeviceState& st, const Ints& I, const ExcSpac
 int pairwise_capacity();
 hipError_t launch_sigma_pairwise(const DeviceState& st, const Ints& I, u64 n, double* sigma,
                                  double* partial, int grid, hipStream_t stream);
+hipError_t launch_diag(const DeviceState& st, const Ints& I, u64 n, int grid, hipStream_t stream);
 hipError_t launch_holepair_emit(const DeviceState& st, u64 n, int ne, u64* out_key, u64* out_val,
                                 int grid, hipStream_t stream);
 hipError_t launch_sigma_diag(const DeviceState& st, const Ints& I, u64 n, double* sigma, int grid,

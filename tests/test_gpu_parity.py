@@ -167,7 +167,14 @@ def test_c2_subset_paths(swcs, c2):
         subset = np.sort(rng.choice(len(c2.pool), size, replace=False)).astype(np.int32)
         g = ctx.pool_gradients(subset)
         g_ref = c2.orc.pool_gradients(c2.st, c2.pool, subset=subset)
-        assert np.abs(g - g_ref).max() < TOL
+        err = np.abs(g - g_ref)
+        if err.max() >= TOL:
+            g_full = ctx.pool_gradients()
+            bad = np.flatnonzero(err >= TOL)
+            _say(f"[parity] subset {size}: {len(bad)} bad, first {subset[bad[:5]]}; "
+                 f"vs GPU full pool {np.abs(g - g_full[subset]).max():.3e}, "
+                 f"GPU full pool vs oracle {np.abs(g_full[subset] - g_ref).max():.3e}")
+        assert err.max() < TOL, size
     ctx.close()
 
 
