@@ -250,8 +250,11 @@ struct LdsMu {
 
 // gate_entry for N entries of one thread in the HBM kernels: entry j is
 // i0 + j * stride (skipped at or beyond n).  The entries go through each
-// stage together -- keys, first index probes, amplitudes -- so that their
-// memory requests overlap; outputs are exactly those of gate_entry.
+// stage together -- keys; first index probes with the entries' own
+// amplitudes; partner amplitudes -- so that their memory requests overlap;
+// outputs are exactly those of gate_entry.  A T^dagger entry loads its own
+// amplitude before knowing whether it owns the pair; when it does not, the
+// value (possibly being rewritten by the owner) is discarded unused.
 template <int N>
 __device__ inline void gate_entries_staged(const GlobalStore& S, u64 n, u64 i0, u64 stride,
                                            const OpDesc& op, double c, double sn, double eps,
@@ -261,7 +264,7 @@ __device__ inline void gate_entries_staged(const GlobalStore& S, u64 n, u64 i0, 
   int kind[N];  // 0: untouched, 1: T acts on D, 2: T^dagger acts on D
   HashSlot sl[N];
   long long jx[N];
-  double araw[N], braw[N];
+  double araw[N], braw[N], own[N];
 #pragma unroll
   for (int j = 0; j < N; ++j) {
     const u64 i = i0 + (u64)j * stride;
@@ -277,6 +280,7 @@ __device__ inline void gate_entries_staged(const GlobalStore& S, u64 n, u64 i0, 
     if (kind[j]) {
       h[j] = mix64(partner[j]) & S.hmask;
       sl[j] = S.hash[h[j]];
+      own[j] = S.amps[i];
     }
   }
 #pragma unroll
@@ -300,10 +304,10 @@ __device__ inline void gate_entries_staged(const GlobalStore& S, u64 n, u64 i0, 
     araw[j] = dead_value();
     braw[j] = dead_value();
     if (kind[j] == 1) {
-      araw[j] = S.amps[i];
+      araw[j] = own[j];
       if (jx[j] >= 0) braw[j] = S.amps[jx[j]];
     } else if (kind[j] == 2 && jx[j] < 0) {
-      braw[j] = S.amps[i];
+      braw[j] = own[j];
     }
   }
 #pragma unroll

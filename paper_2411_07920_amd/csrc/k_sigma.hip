@@ -183,43 +183,56 @@ __device__ inline double block_sum(double v, double* red) {
 }
 
 // Diagonal Slater-Condon elements of the stored determinants (0 for dead
-// entries), one wavefront per determinant: lane l finds the l-th occupied
-// spin-orbital, the lanes split the N_e^2 occupied pairs, and a wavefront sum
-// adds them, so the integral loads of one determinant are spread over the
-// lanes instead of one thread.
+// entries).  A group of kDiagLanes lanes takes one determinant: lane j of the
+// group handles the occupied spin-orbitals of rank j, j + kDiagLanes, ...
+// against all occupied ones, with J, K and diag(h) staged in LDS; the group
+// sums its lanes in a fixed order.
+constexpr int kDiagMaxN = 32;  // spatial orbitals (2n <= 64)
+
 __global__ void __launch_bounds__(256)
 k_diag(const u64* __restrict__ keys, const double* __restrict__ amps, u64 n, Ints I,
        double* __restrict__ diag) {
-  const int lane = threadIdx.x & 63;
-  const u64 w0 = ((u64)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  const u64 wstride = ((u64)gridDim.x * blockDim.x) >> 6;
-  for (u64 d = w0; d < n; d += wstride) {
-    if (is_dead(amps[d])) {
-      if (lane == 0) diag[d] = 0.0;
-      continue;
-    }
-    const u64 D = keys[d];
-    const int ne = __popcll(D);
-    u64 x = D;
-    for (int t = 0; t < lane && x; ++t) x &= x - 1;
-    const int P = (lane < ne) ? __ffsll((long long)x) - 1 : 0;
+  __shared__ double sJ[kDiagMaxN * kDiagMaxN], sK[kDiagMaxN * kDiagMaxN], sh[kDiagMaxN];
+  const int no = I.n;
+  for (int t = threadIdx.x; t < no * no; t += blockDim.x) {
+    sJ[t] = I.J[t];
+    sK[t] = I.K[t];
+  }
+  for (int t = threadIdx.x; t < no; t += blockDim.x) sh[t] = I.h[t * no + t];
+  __syncthreads();
+  const int sub = (int)threadIdx.x & (kDiagLanes - 1);
+  const u64 per_pass = ((u64)gridDim.x * blockDim.x) / kDiagLanes;
+  // the pass loop has the same trip count in every lane, so the group sums
+  // below run with all lanes active
+  for (u64 base = 0; base < n; base += per_pass) {
+    const u64 d = base + ((u64)blockIdx.x * blockDim.x + threadIdx.x) / kDiagLanes;
+    const bool valid = d < n;
+    const bool alive = valid && !is_dead(amps[d]);
     double e = 0.0;
-    if (lane < ne) e += I.h[(P >> 1) * I.n + (P >> 1)];
-    const int npair = ne * ne;
-    for (int t0 = 0; t0 < npair; t0 += 64) {  // same trip count in every lane
-      const int t = t0 + lane;
-      const int a = (t < npair) ? t / ne : 0;
-      const int b = (t < npair) ? t - a * ne : 0;
-      const int Pa = __shfl(P, a), Pb = __shfl(P, b);
-      if (t < npair) {
-        const int p = Pa >> 1, q = Pb >> 1;
-        double v = I.J[p * I.n + q];
-        if (((Pa ^ Pb) & 1) == 0) v -= I.K[p * I.n + q];
-        e += 0.5 * v;
+    if (alive) {
+      const u64 D = keys[d];
+      // this lane's electrons: ranks sub, sub + kDiagLanes, ... (the lanes of
+      // a wavefront step through their electrons in lockstep)
+      u64 x = D;
+      for (int t = 0; t < sub && x; ++t) x &= x - 1;
+      while (x) {
+        const int P = __ffsll((long long)x) - 1;
+        const int p = P >> 1;
+        double ep = 0.0;
+        u64 y = D;
+        while (y) {
+          const int Q = __ffsll((long long)y) - 1;
+          y &= y - 1;
+          double v = sJ[p * no + (Q >> 1)];
+          if (((P ^ Q) & 1) == 0) v -= sK[p * no + (Q >> 1)];
+          ep += v;
+        }
+        e += sh[p] + 0.5 * ep;
+        for (int t = 0; t < kDiagLanes && x; ++t) x &= x - 1;
       }
     }
-    for (int off = 32; off > 0; off >>= 1) e += __shfl_xor(e, off);
-    if (lane == 0) diag[d] = I.ecore + e;
+    for (int off = 1; off < kDiagLanes; off <<= 1) e += __shfl_xor(e, off);
+    if (valid && sub == 0) diag[d] = alive ? I.ecore + e : 0.0;
   }
 }
 
@@ -281,36 +294,99 @@ k_sigma_proj(const u64* __restrict__ keys, const double* __restrict__ amps,
 // each group are exactly the candidate partners.  A double-excitation pair
 // shares one subset; a single-excitation pair shares N_e - 1 and is counted
 // only on the one that drops the lowest common electron.
+//
+// A subset is sorted by its rank in the combinatorial number system
+// (sum over its occupied positions c_1 < c_2 < ... of C(c_j, j)), a
+// bijection onto [0, C(2n, N_e - 2)) that needs fewer radix passes than the
+// 2n-bit key.
 
-// Record g = i * C(ne, 2) + p: subset p of entry i (key ~0 for dead entries).
+struct BinomTable {
+  u64 v[65][65];  // v[m][k] = C(m, k); C(64, 32) < 2^63
+};
+
+constexpr BinomTable make_binom_table() {
+  BinomTable t{};
+  for (int m = 0; m <= 64; ++m) {
+    t.v[m][0] = 1;
+    for (int k = 1; k <= m; ++k) t.v[m][k] = t.v[m - 1][k - 1] + (k < m ? t.v[m - 1][k] : 0);
+  }
+  return t;
+}
+
+__constant__ BinomTable kBinom = make_binom_table();
+
+__device__ inline u64 subset_rank(u64 S) {
+  u64 r = 0;
+  for (int j = 1; S; ++j) {
+    r += kBinom.v[__ffsll((long long)S) - 1][j];
+    S &= S - 1;
+  }
+  return r;
+}
+
+__device__ inline u64 shfl_u64(u64 v, int src) {
+  const unsigned lo = (unsigned)__shfl((int)(unsigned)v, src);
+  const unsigned hi = (unsigned)__shfl((int)(unsigned)(v >> 32), src);
+  return ((u64)hi << 32) | lo;
+}
+
+__device__ inline u64 shfl_up_u64(u64 v, int d) {
+  const unsigned lo = (unsigned)__shfl_up((int)(unsigned)v, d);
+  const unsigned hi = (unsigned)__shfl_up((int)(unsigned)(v >> 32), d);
+  return ((u64)hi << 32) | lo;
+}
+
+// Records g = i * C(ne, 2) + p, one wavefront per entry: rank of the subset
+// that drops electrons a < b (p = b (b - 1) / 2 + a; ~0 for dead entries,
+// above every rank).  Lane l < ne holds the l-th occupied position c_l; with
+// inclusive lane prefix sums IA, IB, IG of C(c_l, l + 1), C(c_l, l) and
+// C(c_l, l - 1) (the rank terms of an electron kept below a, between a and b,
+// and above b), rank = IA[a - 1] + (IB[b - 1] - IB[a]) + (IG[ne - 1] - IG[b]).
 __global__ void __launch_bounds__(256)
 k_holepair_emit(const u64* __restrict__ keys, const double* __restrict__ amps, u64 n, int ne,
                 u64* __restrict__ out_key, u64* __restrict__ out_val) {
+  const int lane = threadIdx.x & 63;
   const u64 np = (u64)ne * (u64)(ne - 1) / 2;
-  const u64 total = n * np;
-  const u64 stride = (u64)gridDim.x * blockDim.x;
-  for (u64 g = (u64)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += stride) {
-    const u64 i = g / np;
-    int p = (int)(g - i * np);
-    u64 key = ~0ULL;
-    if (!is_dead(amps[i])) {
-      // pair rank p -> ranks a < b among the occupied bits
-      int a = 0;
-      while (p >= ne - 1 - a) {
-        p -= ne - 1 - a;
-        ++a;
+  const u64 w0 = ((u64)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const u64 wstride = ((u64)gridDim.x * blockDim.x) >> 6;
+  for (u64 i = w0; i < n; i += wstride) {
+    const bool dead = is_dead(amps[i]);  // uniform over the wavefront
+    const u64 D = keys[i];
+    u64 x = D;
+    for (int t = 0; t < lane && x; ++t) x &= x - 1;
+    const bool mine = lane < ne;
+    const int c = mine ? __ffsll((long long)x) - 1 : 0;
+    u64 ia = mine ? kBinom.v[c][lane + 1 <= 64 ? lane + 1 : 64] : 0;
+    u64 ib = mine ? kBinom.v[c][lane] : 0;
+    u64 ig = (mine && lane >= 1) ? kBinom.v[c][lane - 1] : 0;
+    for (int d = 1; d < 64; d <<= 1) {
+      const u64 ta = shfl_up_u64(ia, d), tb = shfl_up_u64(ib, d), tg = shfl_up_u64(ig, d);
+      if (lane >= d) {
+        ia += ta;
+        ib += tb;
+        ig += tg;
       }
-      const int b = a + 1 + p;
-      const u64 D = keys[i];
-      u64 x = D;
-      for (int t = 0; t < a; ++t) x &= x - 1;
-      const u64 ba = x & (0ULL - x);
-      for (int t = a; t < b; ++t) x &= x - 1;
-      const u64 bb = x & (0ULL - x);
-      key = D ^ ba ^ bb;
     }
-    out_key[g] = key;
-    out_val[g] = i;
+    const u64 g_top = shfl_u64(ig, ne - 1);
+    for (u64 p0 = 0; p0 < np; p0 += 64) {
+      const u64 p = p0 + (u64)lane;
+      const bool valid = p < np;
+      // b = largest integer with b (b - 1) / 2 <= p
+      u64 b = valid ? (u64)((1.0 + sqrt(1.0 + 8.0 * (double)p)) * 0.5) : 1;
+      while (b * (b - 1) / 2 > p) --b;
+      while ((b + 1) * b / 2 <= p) ++b;
+      const u64 a = valid ? p - b * (b - 1) / 2 : 0;
+      if (!valid) b = 1;
+      const u64 a_lo = shfl_u64(ia, a > 0 ? (int)a - 1 : 0);
+      const u64 b_lo = shfl_u64(ib, (int)b - 1);
+      const u64 b_a = shfl_u64(ib, (int)a);
+      const u64 g_b = shfl_u64(ig, (int)b);
+      if (valid) {
+        const u64 r = (a > 0 ? a_lo : 0) + (b_lo - b_a) + (g_top - g_b);
+        out_key[i * np + p] = dead ? ~0ULL : r;
+        out_val[i * np + p] = i;
+      }
+    }
   }
 }
 
@@ -358,7 +434,7 @@ k_holepair_sigma(const u64* __restrict__ skey, const u64* __restrict__ sidx, u64
         h = double_element(I, D, h0, h1, p0, p1);
       } else {
         const u64 common = D & X;
-        if (S != (common & (common - 1))) continue;
+        if (S != subset_rank(common & (common - 1))) continue;
         h = single_element(I, D, __ffsll((long long)holes) - 1, __ffsll((long long)parts) - 1);
       }
       acc += h * amps[iX];
@@ -837,6 +913,7 @@ hipError_t launch_sigma_pairwise(const DeviceState& st, const Ints& I, u64 n, do
 
 hipError_t launch_diag(const DeviceState& st, const Ints& I, u64 n, int grid, hipStream_t stream) {
   if (n == 0) return hipSuccess;
+  if (I.n > kDiagMaxN) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_diag, dim3(grid), dim3(256), 0, stream, st.keys, st.amps, n, I, st.diag);
   return hipGetLastError();
 }

@@ -136,50 +136,85 @@ void scan_exclusive(u64* data, u64 len, u64* sums, hipStream_t stream) {
                      (const u64*)sums);
 }
 
+// Stable scatter of one tile.  Each 256-item row is ranked by wave ballots
+// on the digit bits and a prefix over the four waves; the tile is first
+// reordered by digit in LDS and then written out, so consecutive lanes store
+// consecutive positions of one digit's run.  The tile's digit counts come
+// from the scanned offsets (the next tile's offset, or the next digit's first
+// offset for the last tile).
 template <int ROWS>
 __global__ void __launch_bounds__(kSortThreads)
 k_radix_scatter(const u64* __restrict__ keys_in, const u64* __restrict__ vals_in, u64 count,
                 int shift, const u64* __restrict__ offsets, int nblocks, u64* __restrict__ keys_out,
                 u64* __restrict__ vals_out) {
+  constexpr int kTile = kSortThreads * ROWS;
   __shared__ u64 base_off[256];
+  __shared__ unsigned local_off[256];
   __shared__ unsigned running[256];
   __shared__ unsigned wave_cnt[4][256];
+  __shared__ unsigned scan_tmp[256];
+  __shared__ u64 s_key[kTile];
+  __shared__ u64 s_val[kTile];
   const int lane = __lane_id();
   const int wave = threadIdx.x >> 6;
-  base_off[threadIdx.x] = offsets[(u64)threadIdx.x * nblocks + blockIdx.x];
-  running[threadIdx.x] = 0;
-  const u64 tile0 = (u64)blockIdx.x * (kSortThreads * ROWS);
-  for (int r = 0; r < ROWS; ++r) {
-    for (int w = 0; w < 4; ++w) wave_cnt[w][threadIdx.x] = 0;
+  const int t = threadIdx.x;
+  const u64 b = blockIdx.x;
+  const u64 o = offsets[(u64)t * nblocks + b];
+  const u64 nxt = (b + 1 < (u64)nblocks) ? offsets[(u64)t * nblocks + b + 1]
+                                         : (t < 255 ? offsets[(u64)(t + 1) * nblocks] : count);
+  base_off[t] = o;
+  running[t] = 0;
+  // exclusive scan of the tile's 256 digit counts
+  unsigned cnt = (unsigned)(nxt - o);
+  scan_tmp[t] = cnt;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {
+    const unsigned w = (t >= off) ? scan_tmp[t - off] : 0u;
     __syncthreads();
-    const u64 i = tile0 + (u64)r * kSortThreads + threadIdx.x;
-    const bool valid = i < count;
-    u64 key = 0, val = 0;
-    unsigned digit = 0;
-    if (valid) {
-      key = keys_in[i];
-      if (vals_in) val = vals_in[i];
-      digit = (unsigned)((key >> shift) & 255u);
-    }
+    scan_tmp[t] += w;
+    __syncthreads();
+  }
+  local_off[t] = scan_tmp[t] - cnt;
+  const u64 tile0 = b * (u64)kTile;
+  const unsigned tile_n = (unsigned)((count - tile0) < (u64)kTile ? (count - tile0) : (u64)kTile);
+  // every row's loads are issued before the ranking starts
+  u64 key[ROWS], val[ROWS];
+#pragma unroll
+  for (int r = 0; r < ROWS; ++r) {
+    const unsigned i = (unsigned)r * kSortThreads + t;
+    key[r] = (i < tile_n) ? keys_in[tile0 + i] : 0;
+    val[r] = (vals_in && i < tile_n) ? vals_in[tile0 + i] : 0;
+  }
+#pragma unroll
+  for (int r = 0; r < ROWS; ++r) {
+    for (int w = 0; w < 4; ++w) wave_cnt[w][t] = 0;
+    __syncthreads();
+    const bool valid = (unsigned)r * kSortThreads + t < tile_n;
+    const unsigned digit = valid ? (unsigned)((key[r] >> shift) & 255u) : 0u;
     u64 peers = __ballot(valid);
-    for (int b = 0; b < 8; ++b) {
-      const u64 m = __ballot(valid && ((digit >> b) & 1u));
-      peers &= ((digit >> b) & 1u) ? m : ~m;
+    for (int bit = 0; bit < 8; ++bit) {
+      const u64 m = __ballot(valid && ((digit >> bit) & 1u));
+      peers &= ((digit >> bit) & 1u) ? m : ~m;
     }
     const unsigned below = (unsigned)__popcll(peers & ((1ULL << lane) - 1ULL));
     if (valid && below == 0) wave_cnt[wave][digit] = (unsigned)__popcll(peers);
     __syncthreads();
     if (valid) {
-      unsigned before = running[digit] + below;
-      for (int w = 0; w < wave; ++w) before += wave_cnt[w][digit];
-      const u64 dst = base_off[digit] + before;
-      keys_out[dst] = key;
-      if (vals_in) vals_out[dst] = val;
+      unsigned pos = local_off[digit] + running[digit] + below;
+      for (int w = 0; w < wave; ++w) pos += wave_cnt[w][digit];
+      s_key[pos] = key[r];
+      s_val[pos] = val[r];
     }
     __syncthreads();
-    running[threadIdx.x] += wave_cnt[0][threadIdx.x] + wave_cnt[1][threadIdx.x] +
-                            wave_cnt[2][threadIdx.x] + wave_cnt[3][threadIdx.x];
-    __syncthreads();
+    running[t] += wave_cnt[0][t] + wave_cnt[1][t] + wave_cnt[2][t] + wave_cnt[3][t];
+  }
+  __syncthreads();
+  for (unsigned i = t; i < tile_n; i += kSortThreads) {
+    const u64 k = s_key[i];
+    const unsigned digit = (unsigned)((k >> shift) & 255u);
+    const u64 dst = base_off[digit] + (i - local_off[digit]);
+    keys_out[dst] = k;
+    if (vals_in) vals_out[dst] = s_val[i];
   }
 }
 
@@ -190,10 +225,15 @@ u64 radix_sort_scratch_elems(u64 count) {
   return len + scan_scratch_elems(len);
 }
 
-// Sorts (keys, vals) ascending by the low key_bits bits of the key.  The
-// result ends in keys / vals; tmp_* are ping-pong buffers of the same size.
+// Sorts (keys, vals) ascending by the low key_bits bits of the key; tmp_* are
+// ping-pong buffers of the same size.  With out_keys / out_vals the result
+// stays in whichever pair of buffers the last pass wrote and the pointers are
+// returned there; otherwise it is copied back to keys / vals if needed.
 hipError_t radix_sort_pairs(u64* keys, u64* vals, u64* tmp_keys, u64* tmp_vals, u64 count,
-                            int key_bits, u64* scratch, u64 scratch_elems, hipStream_t stream) {
+                            int key_bits, u64* scratch, u64 scratch_elems, hipStream_t stream,
+                            u64** out_keys, u64** out_vals) {
+  if (out_keys) *out_keys = keys;
+  if (out_vals) *out_vals = vals;
   if (count <= 1) return hipSuccess;
   const int rows = sort_rows(count);
   const u64 tile = (u64)kSortThreads * rows;
@@ -219,6 +259,11 @@ hipError_t radix_sort_pairs(u64* keys, u64* vals, u64* tmp_keys, u64* tmp_vals, 
                          kin, vin, count, shift, scratch, nblocks, kout, vout);
     u64* t = kin; kin = kout; kout = t;
     t = vin; vin = vout; vout = t;
+  }
+  if (out_keys && out_vals) {
+    *out_keys = kin;
+    *out_vals = vin;
+    return hipGetLastError();
   }
   if (kin != keys) {
     hipError_t e = hipMemcpyAsync(keys, kin, count * sizeof(u64), hipMemcpyDeviceToDevice, stream);

@@ -16,8 +16,10 @@ namespace swcs {
 // the new partner keys a tile creates are staged in LDS and written out
 // together behind a single atomic on the append counter, so the number of
 // same-address device atomics is one per tile plus two per block, not one per
-// wavefront.
-__global__ void __launch_bounds__(kGateThreads)
+// wavefront.  Eight wavefronts per SIMD (at most 64 VGPRs) keep two blocks
+// resident per compute unit, so one block's index inserts overlap the
+// other's loads.
+__global__ void __launch_bounds__(kGateThreads, 8)
 k_gate(u64* __restrict__ keys, double* __restrict__ amps, HashSlot* __restrict__ hash, u64 hmask,
        u64 cap, Counters* __restrict__ ctr, OpDesc op, double c, double sn, double eps,
        u64* __restrict__ gate_n_in, int check_cap, unsigned gate_index, u64 max_keys) {

@@ -44,6 +44,16 @@ struct DevBuf {
   template <class T> T* as() const { return (T*)p; }
 };
 
+// C(m, k) for m <= 64 by Pascal's rule (no intermediate overflow).
+u64 binomial_u64(int m, int k) {
+  if (k < 0 || k > m) return 0;
+  std::vector<u64> row((size_t)m + 1, 0);
+  row[0] = 1;
+  for (int i = 1; i <= m; ++i)
+    for (int j = std::min(i, k); j >= 1; --j) row[(size_t)j] += row[(size_t)j - 1];
+  return row[(size_t)k];
+}
+
 u64 next_pow2(u64 x) {
   u64 p = 1;
   while (p < x) p <<= 1;
@@ -187,11 +197,11 @@ int grid_blocks(swcs_ctx* c, u64 work_items, int per_block) {
   return (int)g;
 }
 
-// Grid of the tiled gate kernels: one block per tile up to two resident
-// 1024-thread blocks per compute unit.
+// Grid of the tiled gate kernels: one block per tile, up to 2,048 resident
+// threads per compute unit.
 int gate_grid(swcs_ctx* c, u64 n_entries, int tile) {
   u64 g = (n_entries + tile - 1) / tile;
-  const u64 maxg = (u64)c->num_cu * 2;
+  const u64 maxg = (u64)c->num_cu * (2048 / kGateThreads);
   if (g > maxg) g = maxg;
   if (g < 1) g = 1;
   return (int)g;
@@ -841,8 +851,7 @@ static bool use_sigma_pairs(swcs_ctx* c, u64 n) {
 static int diag_enqueue(swcs_ctx* c, u64 n) {
   HIP_TRY(c, c->diag.ensure(std::max<u64>(1, n) * 8), "alloc diagonal");
   c->st.diag = c->diag.as<double>();
-  const u64 waves = n;
-  HIP_TRY(c, launch_diag(c->st, ints_view(c), n, grid_blocks(c, waves * 64, 256), c->stream), "diagonal");
+  HIP_TRY(c, launch_diag(c->st, ints_view(c), n, grid_blocks(c, n * kDiagLanes, 256), c->stream), "diagonal");
   return SWCS_OK;
 }
 
@@ -875,13 +884,19 @@ static int energy_enqueue(swcs_ctx* c, u64 n) {
     const u64 scr = radix_sort_scratch_elems(total);
     HIP_TRY(c, c->sort_scratch.ensure(scr * 8), "alloc sort scratch");
     const int rg = grid_blocks(c, total, 256);
-    HIP_TRY(c, launch_holepair_emit(c->st, n, ne, c->hp_key.as<u64>(), c->hp_val.as<u64>(), rg, c->stream), "emit");
+    HIP_TRY(c, launch_holepair_emit(c->st, n, ne, c->hp_key.as<u64>(), c->hp_val.as<u64>(),
+                                    grid_blocks(c, n * 64, 256), c->stream), "emit");
+    // subset ranks lie below C(2n, N_e - 2); the dead marker's low bits are
+    // all ones, above every rank
+    int rank_bits = 1;
+    while (rank_bits < 64 && (binomial_u64(c->nso, ne - 2) >> rank_bits) != 0) ++rank_bits;
+    u64 *sk = nullptr, *sv = nullptr;
     HIP_TRY(c, radix_sort_pairs(c->hp_key.as<u64>(), c->hp_val.as<u64>(), c->hp_tk.as<u64>(), c->hp_tv.as<u64>(),
-                                total, c->nso, c->sort_scratch.as<u64>(), scr, c->stream), "sort");
+                                total, rank_bits, c->sort_scratch.as<u64>(), scr, c->stream, &sk, &sv), "sort");
     HIP_TRY(c, launch_sigma_diag(c->st, ints_view(c), n, c->sigma.as<double>(), grid_blocks(c, n, 256),
                                  c->stream), "diagonal sigma");
-    TIMED(c, SWCS_K_HOLEPAIR, launch_holepair_sigma(c->st, ints_view(c), c->hp_key.as<u64>(), c->hp_val.as<u64>(),
-                                  total, c->sigma.as<double>(), rg, c->stream), "hole pairs");
+    TIMED(c, SWCS_K_HOLEPAIR, launch_holepair_sigma(c->st, ints_view(c), sk, sv, total, c->sigma.as<double>(),
+                                                    rg, c->stream), "hole pairs");
     HIP_TRY(c, launch_sigma_dots(c->st, c->sigma.as<double>(), n, c->partial.as<double>(), grid, c->stream), "dots");
   } else {
     TIMED(c, SWCS_K_SIGMA_PROJ, launch_sigma_proj(c->st, ints_view(c), c->exc, n, c->sigma.as<double>(),

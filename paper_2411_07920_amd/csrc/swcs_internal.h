@@ -179,27 +179,6 @@ __device__ inline double eri_so(const Ints& I, int P, int Q, int R, int S) {
   return eri_sp(I, P >> 1, Q >> 1, R >> 1, S >> 1);
 }
 
-// Diagonal Slater-Condon element of determinant D.
-__device__ inline double diag_element(const Ints& I, u64 D) {
-  double e1 = 0.0, e2 = 0.0;
-  u64 x = D;
-  while (x) {
-    int P = __ffsll((long long)x) - 1;
-    x &= x - 1;
-    int p = P >> 1;
-    e1 += I.h[p * I.n + p];
-    u64 y = D;
-    while (y) {
-      int Q = __ffsll((long long)y) - 1;
-      y &= y - 1;
-      int q = Q >> 1;
-      e2 += I.J[p * I.n + q];
-      if (((P ^ Q) & 1) == 0) e2 -= I.K[p * I.n + q];
-    }
-  }
-  return I.ecore + e1 + 0.5 * e2;
-}
-
 // <D'|H|D> for D' = a+_A a_I D (same spin, I in D, A not in D).
 __device__ inline double single_element(const Ints& I, u64 D, int Ih, int A) {
   int s = __popcll(D & ((1ULL << Ih) - 1ULL));
@@ -274,8 +253,9 @@ constexpr int kLdsCap = 4096;
 
 // Multi-block gate kernels in HBM: threads per block, entries per thread and
 // tile sizes (a tile's appended keys / logged pairs are staged in LDS).
+constexpr int kDiagLanes = 8;  // lanes per determinant in k_diag
 constexpr int kGateThreads = 1024;
-constexpr int kGateItems = 4;
+constexpr int kGateItems = 2;
 constexpr int kGateTile = kGateThreads * kGateItems;
 constexpr int kReplayTile = 2048;
 
@@ -390,7 +370,8 @@ hipError_t launch_compact_alive(const DeviceState& st, u64 n, const double* vals
                                 double* out_amps, u64* d_count, u64* scratch, u64 scratch_elems,
                                 hipStream_t stream);
 hipError_t radix_sort_pairs(u64* keys, u64* vals, u64* tmp_keys, u64* tmp_vals, u64 count,
-                            int key_bits, u64* scratch, u64 scratch_elems, hipStream_t stream);
+                            int key_bits, u64* scratch, u64 scratch_elems, hipStream_t stream,
+                            u64** out_keys = nullptr, u64** out_vals = nullptr);
 u64 radix_sort_scratch_elems(u64 count);
 u64 compact_scratch_elems(u64 n);
 
