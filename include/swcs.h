@@ -93,8 +93,10 @@ int swcs_set_capacity(swcs_ctx* ctx, int64_t max_dets);
 /* How sigma_P (energy, parameter gradients) is formed.  ENUMERATE probes
  * every single and double excitation of every alive determinant (alive * C
  * probes).  HOLE_PAIRS groups the determinants by their subsets of N_e - 2
- * electrons (a sort of n * C(N_e, 2) records) and evaluates only pairs that
- * share one, which are exactly the pairs within a double excitation.  PAIRS
+ * electrons (a sort of n * C(N_e, 2) 12-byte records) and evaluates only
+ * pairs that share one, which are exactly the pairs within a double
+ * excitation; it needs fewer than 2^32 stored entries (larger states use
+ * ENUMERATE).  PAIRS
  * (states of at most 4,096 stored determinants; larger ones fall back to
  * AUTO's choice among the others) tests every pair of stored determinants in
  * LDS by popcount.  AUTO (default) takes PAIRS when the state

@@ -344,7 +344,7 @@ __device__ inline u64 shfl_up_u64(u64 v, int d) {
 // and above b), rank = IA[a - 1] + (IB[b - 1] - IB[a]) + (IG[ne - 1] - IG[b]).
 __global__ void __launch_bounds__(256)
 k_holepair_emit(const u64* __restrict__ keys, const double* __restrict__ amps, u64 n, int ne,
-                u64* __restrict__ out_key, u64* __restrict__ out_val) {
+                u64* __restrict__ out_key, unsigned* __restrict__ out_val) {
   const int lane = threadIdx.x & 63;
   const u64 np = (u64)ne * (u64)(ne - 1) / 2;
   const u64 w0 = ((u64)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
@@ -384,7 +384,7 @@ k_holepair_emit(const u64* __restrict__ keys, const double* __restrict__ amps, u
       if (valid) {
         const u64 r = (a > 0 ? a_lo : 0) + (b_lo - b_a) + (g_top - g_b);
         out_key[i * np + p] = dead ? ~0ULL : r;
-        out_val[i * np + p] = i;
+        out_val[i * np + p] = (unsigned)i;
       }
     }
   }
@@ -404,7 +404,7 @@ k_sigma_diag(const double* __restrict__ amps, const double* __restrict__ diag, u
 // One thread per sorted record: adds H_{D X} psi(X) over the other members X
 // of its group to sigma(D).
 __global__ void __launch_bounds__(256)
-k_holepair_sigma(const u64* __restrict__ skey, const u64* __restrict__ sidx, u64 total,
+k_holepair_sigma(const u64* __restrict__ skey, const unsigned* __restrict__ sidx, u64 total,
                  const u64* __restrict__ keys, const double* __restrict__ amps, Ints I,
                  double* __restrict__ sigma) {
   const u64 stride = (u64)gridDim.x * blockDim.x;
@@ -927,7 +927,7 @@ hipError_t launch_sigma_proj(const DeviceState& st, const Ints& I, const ExcSpac
   return hipGetLastError();
 }
 
-hipError_t launch_holepair_emit(const DeviceState& st, u64 n, int ne, u64* out_key, u64* out_val,
+hipError_t launch_holepair_emit(const DeviceState& st, u64 n, int ne, u64* out_key, unsigned* out_val,
                                 int grid, hipStream_t stream) {
   hipLaunchKernelGGL(k_holepair_emit, dim3(grid), dim3(256), 0, stream, st.keys, st.amps, n, ne,
                      out_key, out_val);
@@ -942,7 +942,7 @@ hipError_t launch_sigma_diag(const DeviceState& st, const Ints& I, u64 n, double
 }
 
 hipError_t launch_holepair_sigma(const DeviceState& st, const Ints& I, const u64* skey,
-                                 const u64* sidx, u64 total, double* sigma, int grid,
+                                 const unsigned* sidx, u64 total, double* sigma, int grid,
                                  hipStream_t stream) {
   hipLaunchKernelGGL(k_holepair_sigma, dim3(grid), dim3(256), 0, stream, skey, sidx, total, st.keys,
                      st.amps, I, sigma);

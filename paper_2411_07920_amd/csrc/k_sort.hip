@@ -142,11 +142,11 @@ void scan_exclusive(u64* data, u64 len, u64* sums, hipStream_t stream) {
 // consecutive positions of one digit's run.  The tile's digit counts come
 // from the scanned offsets (the next tile's offset, or the next digit's first
 // offset for the last tile).
-template <int ROWS>
+template <int ROWS, class V>
 __global__ void __launch_bounds__(kSortThreads)
-k_radix_scatter(const u64* __restrict__ keys_in, const u64* __restrict__ vals_in, u64 count,
+k_radix_scatter(const u64* __restrict__ keys_in, const V* __restrict__ vals_in, u64 count,
                 int shift, const u64* __restrict__ offsets, int nblocks, u64* __restrict__ keys_out,
-                u64* __restrict__ vals_out) {
+                V* __restrict__ vals_out) {
   constexpr int kTile = kSortThreads * ROWS;
   __shared__ u64 base_off[256];
   __shared__ unsigned local_off[256];
@@ -154,7 +154,7 @@ k_radix_scatter(const u64* __restrict__ keys_in, const u64* __restrict__ vals_in
   __shared__ unsigned wave_cnt[4][256];
   __shared__ unsigned scan_tmp[256];
   __shared__ u64 s_key[kTile];
-  __shared__ u64 s_val[kTile];
+  __shared__ V s_val[kTile];
   const int lane = __lane_id();
   const int wave = threadIdx.x >> 6;
   const int t = threadIdx.x;
@@ -178,7 +178,8 @@ k_radix_scatter(const u64* __restrict__ keys_in, const u64* __restrict__ vals_in
   const u64 tile0 = b * (u64)kTile;
   const unsigned tile_n = (unsigned)((count - tile0) < (u64)kTile ? (count - tile0) : (u64)kTile);
   // every row's loads are issued before the ranking starts
-  u64 key[ROWS], val[ROWS];
+  u64 key[ROWS];
+  V val[ROWS];
 #pragma unroll
   for (int r = 0; r < ROWS; ++r) {
     const unsigned i = (unsigned)r * kSortThreads + t;
@@ -229,9 +230,10 @@ u64 radix_sort_scratch_elems(u64 count) {
 // ping-pong buffers of the same size.  With out_keys / out_vals the result
 // stays in whichever pair of buffers the last pass wrote and the pointers are
 // returned there; otherwise it is copied back to keys / vals if needed.
-hipError_t radix_sort_pairs(u64* keys, u64* vals, u64* tmp_keys, u64* tmp_vals, u64 count,
-                            int key_bits, u64* scratch, u64 scratch_elems, hipStream_t stream,
-                            u64** out_keys, u64** out_vals) {
+template <class V>
+hipError_t radix_sort_impl(u64* keys, V* vals, u64* tmp_keys, V* tmp_vals, u64 count, int key_bits,
+                           u64* scratch, u64 scratch_elems, hipStream_t stream, u64** out_keys,
+                           V** out_vals) {
   if (out_keys) *out_keys = keys;
   if (out_vals) *out_vals = vals;
   if (count <= 1) return hipSuccess;
@@ -241,7 +243,8 @@ hipError_t radix_sort_pairs(u64* keys, u64* vals, u64* tmp_keys, u64* tmp_vals, 
   const u64 len = (u64)256 * nblocks;
   if (len + scan_scratch_elems(len) > scratch_elems) return hipErrorInvalidValue;
   const int passes = (key_bits + 7) / 8;
-  u64 *kin = keys, *vin = vals, *kout = tmp_keys, *vout = tmp_vals;
+  u64 *kin = keys, *kout = tmp_keys;
+  V *vin = vals, *vout = tmp_vals;
   for (int p = 0; p < passes; ++p) {
     const int shift = 8 * p;
     if (rows == 1)
@@ -252,13 +255,13 @@ hipError_t radix_sort_pairs(u64* keys, u64* vals, u64* tmp_keys, u64* tmp_vals, 
                          count, shift, scratch, nblocks);
     scan_exclusive(scratch, len, scratch + len, stream);
     if (rows == 1)
-      hipLaunchKernelGGL(k_radix_scatter<1>, dim3(nblocks), dim3(kSortThreads), 0, stream, kin, vin,
+      hipLaunchKernelGGL((k_radix_scatter<1, V>), dim3(nblocks), dim3(kSortThreads), 0, stream, kin, vin,
                          count, shift, scratch, nblocks, kout, vout);
     else
-      hipLaunchKernelGGL(k_radix_scatter<kSortRows>, dim3(nblocks), dim3(kSortThreads), 0, stream,
+      hipLaunchKernelGGL((k_radix_scatter<kSortRows, V>), dim3(nblocks), dim3(kSortThreads), 0, stream,
                          kin, vin, count, shift, scratch, nblocks, kout, vout);
     u64* t = kin; kin = kout; kout = t;
-    t = vin; vin = vout; vout = t;
+    V* tv = vin; vin = vout; vout = tv;
   }
   if (out_keys && out_vals) {
     *out_keys = kin;
@@ -268,10 +271,24 @@ hipError_t radix_sort_pairs(u64* keys, u64* vals, u64* tmp_keys, u64* tmp_vals, 
   if (kin != keys) {
     hipError_t e = hipMemcpyAsync(keys, kin, count * sizeof(u64), hipMemcpyDeviceToDevice, stream);
     if (e == hipSuccess && vals)
-      e = hipMemcpyAsync(vals, vin, count * sizeof(u64), hipMemcpyDeviceToDevice, stream);
+      e = hipMemcpyAsync(vals, vin, count * sizeof(V), hipMemcpyDeviceToDevice, stream);
     if (e != hipSuccess) return e;
   }
   return hipGetLastError();
+}
+
+hipError_t radix_sort_pairs(u64* keys, u64* vals, u64* tmp_keys, u64* tmp_vals, u64 count,
+                            int key_bits, u64* scratch, u64 scratch_elems, hipStream_t stream,
+                            u64** out_keys, u64** out_vals) {
+  return radix_sort_impl<u64>(keys, vals, tmp_keys, tmp_vals, count, key_bits, scratch, scratch_elems,
+                              stream, out_keys, out_vals);
+}
+
+hipError_t radix_sort_pairs32(u64* keys, unsigned* vals, u64* tmp_keys, unsigned* tmp_vals, u64 count,
+                              int key_bits, u64* scratch, u64 scratch_elems, hipStream_t stream,
+                              u64** out_keys, unsigned** out_vals) {
+  return radix_sort_impl<unsigned>(keys, vals, tmp_keys, tmp_vals, count, key_bits, scratch,
+                                   scratch_elems, stream, out_keys, out_vals);
 }
 
 // ---------------------------------------------------------------- compaction

@@ -874,25 +874,27 @@ static int energy_enqueue(swcs_ctx* c, u64 n) {
     HIP_TRY(c, launch_reduce_partials(c->partial.as<double>(), pgrid, pgrid, 2, c->scalars.as<double>(), c->stream), "reduce");
     return SWCS_OK;
   }
-  if (n > 0 && use_holepair(c, h.alive)) {
+  if (n > 0 && n < (1ULL << 32) && use_holepair(c, h.alive)) {
     const int ne = c->na + c->nb;
     const u64 total = n * ((u64)ne * (u64)(ne - 1) / 2);
     HIP_TRY(c, c->hp_key.ensure(total * 8), "alloc hole-pair keys");
-    HIP_TRY(c, c->hp_val.ensure(total * 8), "alloc hole-pair values");
+    HIP_TRY(c, c->hp_val.ensure(total * 4), "alloc hole-pair values");
     HIP_TRY(c, c->hp_tk.ensure(total * 8), "alloc hole-pair keys");
-    HIP_TRY(c, c->hp_tv.ensure(total * 8), "alloc hole-pair values");
+    HIP_TRY(c, c->hp_tv.ensure(total * 4), "alloc hole-pair values");
     const u64 scr = radix_sort_scratch_elems(total);
     HIP_TRY(c, c->sort_scratch.ensure(scr * 8), "alloc sort scratch");
     const int rg = grid_blocks(c, total, 256);
-    HIP_TRY(c, launch_holepair_emit(c->st, n, ne, c->hp_key.as<u64>(), c->hp_val.as<u64>(),
+    HIP_TRY(c, launch_holepair_emit(c->st, n, ne, c->hp_key.as<u64>(), c->hp_val.as<unsigned>(),
                                     grid_blocks(c, n * 64, 256), c->stream), "emit");
     // subset ranks lie below C(2n, N_e - 2); the dead marker's low bits are
     // all ones, above every rank
     int rank_bits = 1;
     while (rank_bits < 64 && (binomial_u64(c->nso, ne - 2) >> rank_bits) != 0) ++rank_bits;
-    u64 *sk = nullptr, *sv = nullptr;
-    HIP_TRY(c, radix_sort_pairs(c->hp_key.as<u64>(), c->hp_val.as<u64>(), c->hp_tk.as<u64>(), c->hp_tv.as<u64>(),
-                                total, rank_bits, c->sort_scratch.as<u64>(), scr, c->stream, &sk, &sv), "sort");
+    u64* sk = nullptr;
+    unsigned* sv = nullptr;
+    HIP_TRY(c, radix_sort_pairs32(c->hp_key.as<u64>(), c->hp_val.as<unsigned>(), c->hp_tk.as<u64>(),
+                                  c->hp_tv.as<unsigned>(), total, rank_bits, c->sort_scratch.as<u64>(), scr,
+                                  c->stream, &sk, &sv), "sort");
     HIP_TRY(c, launch_sigma_diag(c->st, ints_view(c), n, c->sigma.as<double>(), grid_blocks(c, n, 256),
                                  c->stream), "diagonal sigma");
     TIMED(c, SWCS_K_HOLEPAIR, launch_holepair_sigma(c->st, ints_view(c), sk, sv, total, c->sigma.as<double>(),
