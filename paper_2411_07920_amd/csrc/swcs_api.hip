@@ -128,6 +128,10 @@ struct swcs_ctx {
       exp_keys, exp_amps, exp_tmp_k, exp_tmp_v, sort_scratch, ctr_r, occ, sel_scratch, mlp_partial, mse_partial, hp_key, hp_val, hp_tk, hp_tv, diag;
   int sigma_method = SWCS_SIGMA_AUTO;
   double ext_count = 0.0, ext_alive = 0.0;  // distinct external keys of the last full pool pass
+  // The state (and integrals) version, bumped by every call that may change
+  // them; the diagonal elements and <psi|psi> on the device are reused while
+  // they were computed for the current version.
+  u64 state_version = 1, diag_version = 0, norm_version = 0;
 
   ~swcs_ctx() {
     DevBuf* all[] = {&h, &eri, &J, &K, &fock, &ops, &opmap, &gacc, &selected, &ncut_state, &filt, &keys, &amps, &hash, &ctr, &ckpt_n, &ckpt_ptrs,
@@ -542,6 +546,7 @@ const char* swcs_last_error(const swcs_ctx* ctx) {
 
 int swcs_set_stream(swcs_ctx* c, void* hip_stream) {
   if (!c) return SWCS_E_INVALID;
+  ++c->state_version;  // cached device results belong to the old stream's order
   c->stream = (hipStream_t)hip_stream;
   return SWCS_OK;
 }
@@ -564,6 +569,7 @@ int swcs_set_sigma_method(swcs_ctx* c, int method) {
 
 int swcs_set_integrals(swcs_ctx* c, const double* h, const double* eri, double e_core) {
   if (!c) return SWCS_E_INVALID;
+  ++c->state_version;
   if (!h || !eri) return fail(c, SWCS_E_INVALID, "null integrals");
   HIP_TRY(c, hipSetDevice(c->device), "hipSetDevice");
   const int n = c->n;
@@ -695,6 +701,7 @@ static int apply_common(swcs_ctx* c, const int32_t* op_idx, const double* theta,
   if (r) return r;
   if (!from_reference && !c->have_state) return fail(c, SWCS_E_STATE, "no current state");
   HIP_TRY(c, hipSetDevice(c->device), "hipSetDevice");
+  ++c->state_version;
   std::vector<double> cs((size_t)M), sn((size_t)M);
   for (int64_t i = 0; i < M; ++i) {
     cs[(size_t)i] = std::cos(theta[i]);
@@ -752,6 +759,7 @@ int swcs_apply_gates(swcs_ctx* c, const int32_t* op_idx, const double* theta, in
 
 int swcs_set_state(swcs_ctx* c, const uint64_t* keys, const double* amps, int64_t n) {
   if (!c) return SWCS_E_INVALID;
+  ++c->state_version;
   if (n < 0 || (n > 0 && (!keys || !amps))) return fail(c, SWCS_E_INVALID, "bad state arguments");
   HIP_TRY(c, hipSetDevice(c->device), "hipSetDevice");
   std::vector<u64> sorted(keys, keys + n);
@@ -847,11 +855,15 @@ static bool use_sigma_pairs(swcs_ctx* c, u64 n) {
   return (double)n <= 8.0 * (double)c->exc.total;
 }
 
-// Diagonal elements of the n stored entries into c->diag (stream-ordered).
+// Diagonal elements of the n stored entries into c->diag (stream-ordered),
+// unless already computed for the current state.
 static int diag_enqueue(swcs_ctx* c, u64 n) {
+  if (c->diag_version == c->state_version && c->diag.bytes >= n * 8 && c->st.diag == c->diag.p)
+    return SWCS_OK;
   HIP_TRY(c, c->diag.ensure(std::max<u64>(1, n) * 8), "alloc diagonal");
   c->st.diag = c->diag.as<double>();
   HIP_TRY(c, launch_diag(c->st, ints_view(c), n, grid_blocks(c, n * kDiagLanes, 256), c->stream), "diagonal");
+  c->diag_version = c->state_version;
   return SWCS_OK;
 }
 
@@ -955,12 +967,15 @@ int swcs_sigma_projected(swcs_ctx* c, uint64_t* keys, double* sigma, int64_t cap
   return export_sorted(c, h.n, h.alive, c->sigma.as<double>(), keys, sigma);
 }
 
-// <psi|psi> into scalars[2] on the device, without synchronizing.
+// <psi|psi> into scalars[2] on the device, without synchronizing (kept while
+// the state is unchanged).
 static int norm2_enqueue(swcs_ctx* c, u64 n) {
+  if (c->norm_version == c->state_version) return SWCS_OK;
   const int grid = grid_blocks(c, n, 256);
   HIP_TRY(c, c->partial.ensure((size_t)grid * 8 * 2), "alloc partial");
   HIP_TRY(c, launch_occupations(c->st, n, 0, c->partial.as<double>(), grid, c->stream), "norm");
   HIP_TRY(c, launch_reduce_partials(c->partial.as<double>(), grid, grid, 1, c->scalars.as<double>() + 2, c->stream), "reduce");
+  c->norm_version = c->state_version;
   return SWCS_OK;
 }
 
@@ -975,9 +990,20 @@ constexpr double kQueryBoundBytes = 512.0 * 1024 * 1024;
 // operator-major (|psi| x n_subset activity tests), larger ones
 // determinant-major through the generator table.  Synchronizes only when the
 // query table has to be sized by an exact count.
+static int mark_subset(swcs_ctx* c, const int* d_subset, int64_t n_subset);
+
 static int screened_gradients(swcs_ctx* c, u64 n, u64 alive, const int* d_subset, int64_t n_subset,
-                              const unsigned char* d_sel, const double* norm2, double* d_out) {
+                              const double* norm2, double* d_out) {
   const bool op_major = n_subset <= c->exc.total;
+  const unsigned char* d_sel = nullptr;
+  if (!op_major) {
+    // the determinant-major passes test the operator flags and accumulate
+    // into the pool-wide g
+    int r = mark_subset(c, d_subset, n_subset);
+    if (r) return r;
+    d_sel = c->selected.as<unsigned char>();
+    HIP_TRY(c, hipMemsetAsync(c->gacc.p, 0, (size_t)c->K_pool * 8, c->stream), "zero g");
+  }
   const double bound = std::min<double>((double)c->sector,
                                         (double)alive * (double)(op_major ? n_subset : c->exc.total));
   u64 nq;
@@ -1021,8 +1047,8 @@ static int screened_gradients(swcs_ctx* c, u64 n, u64 alive, const int* d_subset
   return SWCS_OK;
 }
 
-// Shared set-up of both pool-gradient entry points: counters, norm, zeroed
-// accumulator and (for a subset) the selected-operator flags.
+// Shared set-up of both pool-gradient entry points: counters, norm, diagonal
+// elements and the pool-wide accumulator's allocation.
 static int pool_setup(swcs_ctx* c, Counters* h) {
   int r = check_ready(c);
   if (r) return r;
@@ -1037,7 +1063,6 @@ static int pool_setup(swcs_ctx* c, Counters* h) {
   r = diag_enqueue(c, h->n);
   if (r) return r;
   HIP_TRY(c, c->gacc.ensure((size_t)c->K_pool * 8), "alloc g accumulator");
-  HIP_TRY(c, hipMemsetAsync(c->gacc.p, 0, (size_t)c->K_pool * 8, c->stream), "zero g");
   return SWCS_OK;
 }
 
@@ -1059,10 +1084,8 @@ int swcs_pool_gradients_device(swcs_ctx* c, const int32_t* d_subset, int64_t n_s
   HIP_TRY(c, c->subset_buf.ensure((size_t)n_subset * 4), "alloc subset");
   HIP_TRY(c, launch_sanitize_subset(d_subset, n_subset, c->K_pool, c->subset_buf.as<int>(), c->stream), "subset");
   const int* sub = c->subset_buf.as<int>();
-  r = mark_subset(c, sub, n_subset);
-  if (r) return r;
   const double* norm2 = c->scalars.as<double>() + 2;
-  r = screened_gradients(c, h.n, h.alive, sub, n_subset, c->selected.as<unsigned char>(), norm2, d_g);
+  r = screened_gradients(c, h.n, h.alive, sub, n_subset, norm2, d_g);
   if (r) return r;
   HIP_TRY(c, launch_nan_invalid(d_subset, n_subset, c->K_pool, d_g, c->stream), "flag invalid");
   return SWCS_OK;
@@ -1094,18 +1117,20 @@ int swcs_pool_gradients(swcs_ctx* c, const int32_t* subset, int64_t n_subset, do
     HIP_TRY(c, c->subset_buf.ensure((size_t)n_subset * 4), "alloc subset");
     HIP_TRY(c, hipMemcpyAsync(c->subset_buf.p, subset, (size_t)n_subset * 4, hipMemcpyHostToDevice, c->stream), "copy subset");
     d_subset = c->subset_buf.as<int>();
-    r = mark_subset(c, d_subset, n_subset);
-    if (r) return r;
-    d_sel = c->selected.as<unsigned char>();
   }
   if (subset && 2 * n_subset < c->K_pool) {
-    r = screened_gradients(c, n, h.alive, d_subset, n_subset, d_sel, norm2, c->gbuf.as<double>());
+    r = screened_gradients(c, n, h.alive, d_subset, n_subset, norm2, c->gbuf.as<double>());
     if (r) return r;
     HIP_TRY(c, hipMemcpyAsync(g_out, c->gbuf.p, (size_t)count * 8, hipMemcpyDeviceToHost, c->stream), "copy g");
     Counters hq = read_counters(c, &e);
     if (e != hipSuccess) return hip_fail(c, e, "read counters");
     if (hq.flags & kFlagOverflow) return fail(c, SWCS_E_DEVICE, "sigma table overflow");
     return SWCS_OK;
+  }
+  if (subset) {
+    r = mark_subset(c, d_subset, n_subset);
+    if (r) return r;
+    d_sel = c->selected.as<unsigned char>();
   }
   // External-space table.  At most alive * (C + 1) distinct keys (and never
   // more than the sector) can occur, but states built by gate chains overlap
@@ -1134,7 +1159,7 @@ int swcs_pool_gradients(swcs_ctx* c, const int32_t* subset, int64_t n_subset, do
     if (nbatch == 1 && 2.0 * (double)slots * sizeof(AccSlot) <= budget) slots *= 2;
     HIP_TRY(c, c->acc_tab.ensure(slots * sizeof(AccSlot)), "alloc sigma table");
     HIP_TRY(c, c->partial2.ensure((size_t)sgrid * nbatch * 8), "alloc partials");
-    if (attempt > 0) HIP_TRY(c, hipMemsetAsync(c->gacc.p, 0, (size_t)c->K_pool * 8, c->stream), "zero g");
+    HIP_TRY(c, hipMemsetAsync(c->gacc.p, 0, (size_t)c->K_pool * 8, c->stream), "zero g");
     double* ins = c->partial2.as<double>();
     for (int b = 0; b < nbatch; ++b) {
       HIP_TRY(c, hipMemsetAsync(c->acc_tab.p, 0, slots * sizeof(AccSlot), c->stream), "clear table");
