@@ -136,22 +136,25 @@ void scan_exclusive(u64* data, u64 len, u64* sums, hipStream_t stream) {
                      (const u64*)sums);
 }
 
-// Stable scatter of one tile.  Each 256-item row is ranked by wave ballots
-// on the digit bits and a prefix over the four waves; the tile is first
-// reordered by digit in LDS and then written out, so consecutive lanes store
-// consecutive positions of one digit's run.  The tile's digit counts come
-// from the scanned offsets (the next tile's offset, or the next digit's first
-// offset for the last tile).
-template <int ROWS, class V>
-__global__ void __launch_bounds__(kSortThreads)
+// Stable scatter of one tile of THREADS * ROWS items (the histogram's tile).
+// Each THREADS-item row is ranked by wave ballots on the digit bits and a
+// prefix over the row's waves; the tile is first reordered by digit in LDS
+// and then written out, so consecutive lanes store consecutive positions of
+// one digit's run.  The tile's digit counts come from the scanned offsets
+// (the next tile's offset, or the next digit's first offset for the last
+// tile).  Threads below 256 own one digit each in the per-digit arrays.
+template <int THREADS, int ROWS, class V>
+__global__ void __launch_bounds__(THREADS)
 k_radix_scatter(const u64* __restrict__ keys_in, const V* __restrict__ vals_in, u64 count,
                 int shift, const u64* __restrict__ offsets, int nblocks, u64* __restrict__ keys_out,
                 V* __restrict__ vals_out) {
-  constexpr int kTile = kSortThreads * ROWS;
+  constexpr int kTile = THREADS * ROWS;
+  constexpr int kWaves = THREADS / 64;
+  static_assert(THREADS >= 256, "one thread per digit");
   __shared__ u64 base_off[256];
   __shared__ unsigned local_off[256];
   __shared__ unsigned running[256];
-  __shared__ unsigned wave_cnt[4][256];
+  __shared__ unsigned wave_cnt[kWaves][256];
   __shared__ unsigned scan_tmp[256];
   __shared__ u64 s_key[kTile];
   __shared__ V s_val[kTile];
@@ -159,22 +162,25 @@ k_radix_scatter(const u64* __restrict__ keys_in, const V* __restrict__ vals_in, 
   const int wave = threadIdx.x >> 6;
   const int t = threadIdx.x;
   const u64 b = blockIdx.x;
-  const u64 o = offsets[(u64)t * nblocks + b];
-  const u64 nxt = (b + 1 < (u64)nblocks) ? offsets[(u64)t * nblocks + b + 1]
-                                         : (t < 255 ? offsets[(u64)(t + 1) * nblocks] : count);
-  base_off[t] = o;
-  running[t] = 0;
-  // exclusive scan of the tile's 256 digit counts
-  unsigned cnt = (unsigned)(nxt - o);
-  scan_tmp[t] = cnt;
+  unsigned cnt = 0;
+  if (t < 256) {
+    const u64 o = offsets[(u64)t * nblocks + b];
+    const u64 nxt = (b + 1 < (u64)nblocks) ? offsets[(u64)t * nblocks + b + 1]
+                                           : (t < 255 ? offsets[(u64)(t + 1) * nblocks] : count);
+    base_off[t] = o;
+    running[t] = 0;
+    cnt = (unsigned)(nxt - o);
+    scan_tmp[t] = cnt;
+  }
   __syncthreads();
+  // exclusive scan of the tile's 256 digit counts
   for (int off = 1; off < 256; off <<= 1) {
-    const unsigned w = (t >= off) ? scan_tmp[t - off] : 0u;
+    const unsigned w = (t < 256 && t >= off) ? scan_tmp[t - off] : 0u;
     __syncthreads();
-    scan_tmp[t] += w;
+    if (t < 256) scan_tmp[t] += w;
     __syncthreads();
   }
-  local_off[t] = scan_tmp[t] - cnt;
+  if (t < 256) local_off[t] = scan_tmp[t] - cnt;
   const u64 tile0 = b * (u64)kTile;
   const unsigned tile_n = (unsigned)((count - tile0) < (u64)kTile ? (count - tile0) : (u64)kTile);
   // every row's loads are issued before the ranking starts
@@ -182,15 +188,18 @@ k_radix_scatter(const u64* __restrict__ keys_in, const V* __restrict__ vals_in, 
   V val[ROWS];
 #pragma unroll
   for (int r = 0; r < ROWS; ++r) {
-    const unsigned i = (unsigned)r * kSortThreads + t;
+    const unsigned i = (unsigned)r * THREADS + t;
     key[r] = (i < tile_n) ? keys_in[tile0 + i] : 0;
     val[r] = (vals_in && i < tile_n) ? vals_in[tile0 + i] : 0;
   }
 #pragma unroll
   for (int r = 0; r < ROWS; ++r) {
-    for (int w = 0; w < 4; ++w) wave_cnt[w][t] = 0;
+    // column t is cleared by the thread that summed it at the end of the
+    // previous row
+    if (t < 256)
+      for (int w = 0; w < kWaves; ++w) wave_cnt[w][t] = 0;
     __syncthreads();
-    const bool valid = (unsigned)r * kSortThreads + t < tile_n;
+    const bool valid = (unsigned)r * THREADS + t < tile_n;
     const unsigned digit = valid ? (unsigned)((key[r] >> shift) & 255u) : 0u;
     u64 peers = __ballot(valid);
     for (int bit = 0; bit < 8; ++bit) {
@@ -207,10 +216,14 @@ k_radix_scatter(const u64* __restrict__ keys_in, const V* __restrict__ vals_in, 
       s_val[pos] = val[r];
     }
     __syncthreads();
-    running[t] += wave_cnt[0][t] + wave_cnt[1][t] + wave_cnt[2][t] + wave_cnt[3][t];
+    if (t < 256) {
+      unsigned add = 0;
+      for (int w = 0; w < kWaves; ++w) add += wave_cnt[w][t];
+      running[t] += add;
+    }
   }
   __syncthreads();
-  for (unsigned i = t; i < tile_n; i += kSortThreads) {
+  for (unsigned i = t; i < tile_n; i += THREADS) {
     const u64 k = s_key[i];
     const unsigned digit = (unsigned)((k >> shift) & 255u);
     const u64 dst = base_off[digit] + (i - local_off[digit]);
@@ -254,12 +267,13 @@ hipError_t radix_sort_impl(u64* keys, V* vals, u64* tmp_keys, V* tmp_vals, u64 c
       hipLaunchKernelGGL(k_radix_hist<kSortRows>, dim3(nblocks), dim3(kSortThreads), 0, stream, kin,
                          count, shift, scratch, nblocks);
     scan_exclusive(scratch, len, scratch + len, stream);
+    // the scatter tile equals the histogram tile (kSortThreads * rows items)
     if (rows == 1)
-      hipLaunchKernelGGL((k_radix_scatter<1, V>), dim3(nblocks), dim3(kSortThreads), 0, stream, kin, vin,
-                         count, shift, scratch, nblocks, kout, vout);
-    else
-      hipLaunchKernelGGL((k_radix_scatter<kSortRows, V>), dim3(nblocks), dim3(kSortThreads), 0, stream,
+      hipLaunchKernelGGL((k_radix_scatter<kSortThreads, 1, V>), dim3(nblocks), dim3(kSortThreads), 0, stream,
                          kin, vin, count, shift, scratch, nblocks, kout, vout);
+    else
+      hipLaunchKernelGGL((k_radix_scatter<2 * kSortThreads, kSortRows / 2, V>), dim3(nblocks),
+                         dim3(2 * kSortThreads), 0, stream, kin, vin, count, shift, scratch, nblocks, kout, vout);
     u64* t = kin; kin = kout; kout = t;
     V* tv = vin; vin = vout; vout = tv;
   }
