@@ -208,7 +208,7 @@ def gpu_bench(args, wl):
     kern = {}
     reps = max(3, args.steps // 2)
     for kname in ("chain_lds", "gate", "adjoint_lds", "adjoint_replay_lds", "gate_replay", "adjoint_rec", "sigma_proj",
-                  "sigma_push", "sigma_push_into", "pool_contract", "contract_ops"):
+                  "sigma_push", "sigma_push_into", "pool_contract", "contract_ops", "select"):
         ctx.timer_start(kname)
         for _ in range(reps):
             step()
@@ -226,7 +226,8 @@ def algorithmic_bytes(kname, wl, r):
     stored determinant scanned by a gate (the key test; also per determinant
     and gate for the LDS adjoint's replay and reverse sweeps); 16 B per (source,
     connection) read-modify-write of the external sigma table; 8 B per probe
-    of a hash table and 16 B per source determinant read."""
+    of a hash table and 16 B per source determinant read; for the selection,
+    a score and a random key per operator in and the chosen indices out."""
     from paper_2411_07920_amd.inputs import sector_size  # noqa: F401
     n_in = r["n_in"]
     M = len(n_in)
@@ -249,6 +250,8 @@ def algorithmic_bytes(kname, wl, r):
         return n * (C * 8.0 + 16.0)
     if kname == "contract_ops":
         return n * 16.0 + wl.n_top * 0.0
+    if kname == "select":
+        return wl.K * 8.0 + (wl.n_top + wl.n_rand) * 4.0  # scores and random keys in, indices out
     return 0.0
 
 
@@ -361,7 +364,9 @@ def large_state_bench(N, sigma=True):
     on the HBM path, then sigma_P by hole-pair grouping (and by enumeration
     when N <= 2,000,000).  Gate bytes per launch: 16 B per alive input entry
     (key scan and amplitude) plus 32 B per appended entry (key, amplitude,
-    index slot)."""
+    index slot).  At 16M determinants the counter-measured HBM traffic of a
+    gate and of one sigma_P call (profiles/pmc_traffic.txt) is divided by the
+    measured times as well."""
     import torch
     from math import comb
     from paper_2411_07920_amd import swcs
@@ -391,6 +396,13 @@ def large_state_bench(N, sigma=True):
         torch.cuda.synchronize()
         ms = t0.elapsed_time(t1)
         out["sigma_" + method] = {"ms": ms, "rows_per_s": N / (ms * 1e-3), "connections_per_row": C}
+        if method == "hole_pairs" and N == 16_000_000:
+            tb = measured_traffic("sigma_hole_pairs", "synthetic16M")
+            out["sigma_" + method]["traffic_bytes_per_call"] = tb
+            if tb is not None:
+                gbps = tb / (ms * 1e-3) / 1e9
+                out["sigma_" + method]["traffic_GBps"] = gbps
+                out["sigma_" + method]["traffic_frac_hbm"] = gbps / HBM_PEAK_GBS
     ctx.set_sigma_method("auto")
     rng = np.random.default_rng(4005)
     doubles = np.flatnonzero(wl.pool[:, 2] >= 0)
@@ -412,7 +424,12 @@ def large_state_bench(N, sigma=True):
                    "achieved_GBps": gbps, "frac_hbm": gbps / HBM_PEAK_GBS,
                    "n_det_in": int(n_in[0]), "n_det_out": int(n_out)}
     if N == 16_000_000:
-        out["gate"]["traffic_bytes_per_launch"] = measured_traffic("gate", "synthetic16M")
+        tb = measured_traffic("gate", "synthetic16M")
+        out["gate"]["traffic_bytes_per_launch"] = tb
+        if tb is not None:
+            gbps = tb / (us * 1e-6) / 1e9
+            out["gate"]["traffic_GBps"] = gbps
+            out["gate"]["traffic_frac_hbm"] = gbps / HBM_PEAK_GBS
     ctx.close()
     return out
 

@@ -202,7 +202,8 @@ enum {
   SWCS_K_SIGMA_PUSH_INTO = 9, /* external sigma on the screened query set        */
   SWCS_K_CONTRACT_OPS = 10,  /* operator-major contraction of a small subset     */
   SWCS_K_HOLEPAIR = 11,      /* sigma_P pair evaluation inside hole-pair groups  */
-  SWCS_K_ADJOINT_REPLAY_LDS = 12 /* segment replays of the LDS adjoint, one workgroup each */
+  SWCS_K_ADJOINT_REPLAY_LDS = 12, /* segment replays of the LDS adjoint, one workgroup each */
+  SWCS_K_SELECT = 13         /* screener selection (top + random), swcs_select   */
 };
 
 /* From now on record HIP events on the context stream around every launch

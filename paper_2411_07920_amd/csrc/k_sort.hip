@@ -432,31 +432,77 @@ __device__ inline u64 select_key_rand(const uint32_t* rnd, long long k, bool cho
   return chosen ? 0ULL : ~(((u64)rnd[k] << 32) | (u64)(unsigned)k);
 }
 
+constexpr int kSelBatch = 8;  // keys in flight per thread in the selection passes
+
+constexpr unsigned kSelCand = 4096;  // candidate keys kept in LDS once few enough remain
+
 struct SelectState {
   u64 prefix, mask;
   unsigned long long remaining;
-  int all;  // fewer candidates than requested: every candidate is taken
+  int all;        // fewer candidates than requested: every candidate is taken
+  int compacted;  // the candidates are in the LDS list
+  unsigned ncand;
+  unsigned bin;   // count of the chosen digit's bin in the last pass
   unsigned hist[256];
 };
 
-// Radix select over keys produced by key_of(k); returns the threshold.
+// Adds 1 to hist[digit] for every lane with v set; lanes of a wavefront with
+// the same digit combine their count into one atomic.  Called by every lane
+// of the wavefront.
+__device__ inline void hist_add(unsigned* hist, bool v, unsigned dg) {
+  u64 peers = __ballot(v);
+  if (peers == 0ULL) return;  // uniform over the wavefront
+  for (int bit = 0; bit < 8; ++bit) {
+    const u64 m = __ballot(v && ((dg >> bit) & 1u));
+    peers &= ((dg >> bit) & 1u) ? m : ~m;
+  }
+  if (v && (peers & ((1ULL << __lane_id()) - 1ULL)) == 0ULL) atomicAdd(&hist[dg], (unsigned)__popcll(peers));
+}
+
+// Radix select over keys produced by key_of(k): the kth largest key (or 0
+// when there are fewer than kth keys).  Eight 8-bit digit passes from the
+// top; the keys are read through key_of until the chosen bin holds at most
+// kSelCand keys, which are then copied to an LDS list that the remaining
+// passes read instead.  Every thread of the block calls it.
 template <class KeyOf>
 __device__ u64 block_radix_select(long long K, unsigned long long kth, KeyOf key_of,
-                                  SelectState& st) {
+                                  SelectState& st, u64* cand) {
+  __syncthreads();  // every thread has read the previous call's result
   if (threadIdx.x == 0) {
     st.prefix = 0;
     st.mask = 0;
     st.remaining = kth;
     st.all = 0;
+    st.compacted = 0;
+    st.ncand = 0;
   }
+  __syncthreads();
   for (int d = 7; d >= 0; --d) {
     if (threadIdx.x < 256) st.hist[threadIdx.x] = 0;
     __syncthreads();
     if (!st.all) {
       const u64 prefix = st.prefix, mask = st.mask;
-      for (long long k = threadIdx.x; k < K; k += blockDim.x) {
-        const u64 key = key_of(k);
-        if ((key & mask) == prefix) atomicAdd(&st.hist[(unsigned)(key >> (8 * d)) & 255u], 1u);
+      if (st.compacted) {
+        const unsigned nc = st.ncand;
+        for (unsigned i = threadIdx.x; i < nc; i += blockDim.x) {
+          const u64 key = cand[i];
+          if ((key & mask) == prefix) atomicAdd(&st.hist[(unsigned)(key >> (8 * d)) & 255u], 1u);
+        }
+      } else {
+        // kSelBatch keys per thread are loaded before any is counted
+        for (long long k0 = threadIdx.x; k0 < K; k0 += (long long)kSelBatch * blockDim.x) {
+          u64 key[kSelBatch];
+#pragma unroll
+          for (int j = 0; j < kSelBatch; ++j) {
+            const long long k = k0 + (long long)j * blockDim.x;
+            key[j] = (k < K) ? key_of(k) : 0ULL;
+          }
+#pragma unroll
+          for (int j = 0; j < kSelBatch; ++j) {
+            const long long k = k0 + (long long)j * blockDim.x;
+            hist_add(st.hist, k < K && (key[j] & mask) == prefix, (unsigned)(key[j] >> (8 * d)) & 255u);
+          }
+        }
       }
     }
     __syncthreads();
@@ -485,6 +531,7 @@ __device__ u64 block_radix_select(long long K, unsigned long long kth, KeyOf key
             st.prefix |= digit << (8 * d);
             st.mask |= 255ULL << (8 * d);
             st.remaining = need - cum;
+            st.bin = b[q];
             break;
           }
           cum += b[q];
@@ -492,6 +539,33 @@ __device__ u64 block_radix_select(long long K, unsigned long long kth, KeyOf key
       }
     }
     __syncthreads();
+    if (d > 0 && !st.all && !st.compacted && st.bin <= kSelCand) {
+      // copy the keys of the chosen bin to the LDS list
+      const u64 prefix = st.prefix, mask = st.mask;
+      for (long long k0 = threadIdx.x; k0 < K; k0 += (long long)kSelBatch * blockDim.x) {
+        u64 key[kSelBatch];
+#pragma unroll
+        for (int j = 0; j < kSelBatch; ++j) {
+          const long long k = k0 + (long long)j * blockDim.x;
+          key[j] = (k < K) ? key_of(k) : 0ULL;
+        }
+#pragma unroll
+        for (int j = 0; j < kSelBatch; ++j) {
+          const long long k = k0 + (long long)j * blockDim.x;
+          const bool v = k < K && (key[j] & mask) == prefix;
+          const u64 m = __ballot(v);
+          if (m == 0ULL) continue;  // uniform over the wavefront
+          const int leader = __ffsll((long long)m) - 1;
+          unsigned base = 0;
+          if (__lane_id() == leader) base = atomicAdd(&st.ncand, (unsigned)__popcll(m));
+          base = __shfl(base, leader);
+          if (v) cand[base + (unsigned)__popcll(m & ((1ULL << __lane_id()) - 1ULL))] = key[j];
+        }
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) st.compacted = 1;
+      __syncthreads();
+    }
   }
   return st.all ? 0ULL : st.prefix;
 }
@@ -501,25 +575,41 @@ k_select_block(const float* __restrict__ score, const uint32_t* __restrict__ rnd
                long long n_top, long long n_rand, int* __restrict__ idx) {
   __shared__ SelectState st;
   __shared__ unsigned long long part[1024];
+  __shared__ u64 cand[kSelCand];
   const u64 t_top = (n_top > 0)
-      ? block_radix_select(K, (unsigned long long)n_top, [&](long long k) { return select_key_top(score, k); }, st)
+      ? block_radix_select(K, (unsigned long long)n_top, [&](long long k) { return select_key_top(score, k); }, st, cand)
       : ~0ULL;
   const bool top_none = (n_top == 0);
   auto chosen_top = [&](long long k) { return !top_none && select_key_top(score, k) >= t_top; };
   const u64 t_rand = (n_rand > 0)
       ? block_radix_select(K, (unsigned long long)n_rand,
-                           [&](long long k) { return select_key_rand(rnd, k, chosen_top(k)); }, st)
+                           [&](long long k) { return select_key_rand(rnd, k, chosen_top(k)); }, st, cand)
       : ~0ULL;
   auto chosen = [&](long long k) {
     if (chosen_top(k)) return true;
     return n_rand > 0 && select_key_rand(rnd, k, false) >= t_rand && t_rand != 0ULL;
   };
-  // ascending output: contiguous index ranges per thread, block scan of counts
+  // ascending output: contiguous index ranges per thread (at most 128
+  // entries, K <= kSelectBlockMax), flags evaluated kSelBatch at a time into
+  // two 64-bit masks, block scan of counts
   const long long per = (K + blockDim.x - 1) / blockDim.x;
   const long long lo = (long long)threadIdx.x * per;
   const long long hi = (lo + per < K) ? lo + per : K;
+  u64 f0 = 0, f1 = 0;
   unsigned long long cnt = 0;
-  for (long long k = lo; k < hi; ++k) cnt += chosen(k) ? 1 : 0;
+  for (long long j0 = 0; j0 < per; j0 += kSelBatch) {
+    bool c[kSelBatch];
+#pragma unroll
+    for (int j = 0; j < kSelBatch; ++j) c[j] = (lo + j0 + j < hi) && chosen(lo + j0 + j);
+#pragma unroll
+    for (int j = 0; j < kSelBatch; ++j) {
+      if (!c[j]) continue;
+      const long long jj = j0 + j;
+      if (jj < 64) f0 |= 1ULL << jj;
+      else f1 |= 1ULL << (jj - 64);
+      ++cnt;
+    }
+  }
   part[threadIdx.x] = cnt;
   __syncthreads();
   for (int off = 1; off < 1024; off <<= 1) {
@@ -529,8 +619,14 @@ k_select_block(const float* __restrict__ score, const uint32_t* __restrict__ rnd
     __syncthreads();
   }
   long long pos = (long long)(part[threadIdx.x] - cnt);
-  for (long long k = lo; k < hi; ++k)
-    if (chosen(k)) idx[pos++] = (int)k;
+  while (f0) {
+    idx[pos++] = (int)(lo + __ffsll((long long)f0) - 1);
+    f0 &= f0 - 1;
+  }
+  while (f1) {
+    idx[pos++] = (int)(lo + 64 + __ffsll((long long)f1) - 1);
+    f1 &= f1 - 1;
+  }
 }
 
 // Ascending list of flagged indices: per-tile counts, scan, ordered scatter.

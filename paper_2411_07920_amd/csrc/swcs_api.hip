@@ -1320,7 +1320,7 @@ int swcs_occupations(swcs_ctx* c, double* n_out) {
 
 int swcs_timer_start(swcs_ctx* c, int kernel_id) {
   if (!c) return SWCS_E_INVALID;
-  if (kernel_id < SWCS_K_CHAIN_LDS || kernel_id > SWCS_K_ADJOINT_REPLAY_LDS)
+  if (kernel_id < SWCS_K_CHAIN_LDS || kernel_id > SWCS_K_SELECT)
     return fail(c, SWCS_E_INVALID, "unknown kernel id");
   c->timer_kernel = kernel_id;
   c->ev_used = 0;
@@ -1422,8 +1422,8 @@ int swcs_select(swcs_ctx* c, const float* d_score, const uint32_t* d_rand, int64
   HIP_TRY(c, hipSetDevice(c->device), "hipSetDevice");
   const u64 need = select_scratch_elems(K);
   HIP_TRY(c, c->sel_scratch.ensure(need * 8), "alloc select scratch");
-  HIP_TRY(c, launch_select(d_score, d_rand, K, n_top, n_rand, d_idx, c->sel_scratch.as<u64>(), need,
-                           c->stream), "select");
+  TIMED(c, SWCS_K_SELECT, launch_select(d_score, d_rand, K, n_top, n_rand, d_idx, c->sel_scratch.as<u64>(), need,
+                                        c->stream), "select");
   return SWCS_OK;
 }
 

@@ -25,7 +25,7 @@ SWCS_E_DEVICE = -5
 SWCS_E_UNSUPPORTED = -6
 KERNELS = {"chain_lds": 1, "gate": 2, "sigma_proj": 3, "sigma_push": 4, "pool_contract": 5,
            "adjoint_lds": 6, "gate_replay": 7, "adjoint_rec": 8, "sigma_push_into": 9,
-           "contract_ops": 10, "holepair": 11, "adjoint_replay_lds": 12}
+           "contract_ops": 10, "holepair": 11, "adjoint_replay_lds": 12, "select": 13}
 SIGMA_METHODS = {"auto": 0, "enumerate": 1, "hole_pairs": 2, "pairs": 3}
 _NAMES = {0: "SWCS_OK", -1: "SWCS_E_INVALID", -2: "SWCS_E_STATE", -3: "SWCS_E_OOM",
           -4: "SWCS_E_CAPACITY", -5: "SWCS_E_DEVICE", -6: "SWCS_E_UNSUPPORTED"}
