@@ -130,3 +130,24 @@ def test_select_matches_oracle(env):
         torch.cuda.synchronize()
         ref = oracle.select_subset(score, rnd, ft, fr)
         assert out.cpu().numpy().tolist() == ref.tolist(), (K, ft, fr)
+
+
+def test_select_degenerate_scores(env):
+    """Scores that share their leading digits: all equal (the candidates stay
+    above the LDS list size until the index digits), three distinct values,
+    and one value per 5,000 operators; random keys with heavy ties."""
+    torch, ctx = env["torch"], env["ctx"]
+    K = 22750
+    rng = np.random.default_rng(77)
+    cases = [np.full(K, 0.25, dtype=np.float32),
+             rng.choice(np.array([-1.5, 0.5, 0.75], dtype=np.float32), K),
+             (np.arange(K) // 5000).astype(np.float32) * np.float32(0.001)]
+    for c_i, score in enumerate(cases):
+        for rnd in (draw_random_keys(K, 5 + c_i), np.full(K, 7, dtype=np.uint32)):
+            n_top, n_rand = int(np.ceil(0.05 * K)), int(np.ceil(0.01 * K))
+            out = torch.zeros(n_top + n_rand, dtype=torch.int32, device="cuda")
+            ctx.select(torch.from_numpy(score).cuda(), torch.from_numpy(rnd.astype(np.int32)).cuda(),
+                       n_top, n_rand, out)
+            torch.cuda.synchronize()
+            ref = oracle.select_subset(score, rnd, 0.05, 0.01)
+            assert out.cpu().numpy().tolist() == ref.tolist(), c_i
