@@ -480,6 +480,44 @@ def test_large_state_16M_sampled(swcs):
     ctx.close()
 
 
+def test_cached_diagonal_and_norm_follow_changes(swcs, c2):
+    """Diagonal elements and <psi|psi> are kept on the device between calls on
+    one state; new integrals, a new state and a new stream must each replace
+    them.  Every energy and gradient is checked against the oracle."""
+    import torch
+    ctx = make_ctx(swcs, c2)
+    ctx.apply_ansatz(c2.ops, c2.theta, c2.eps)
+    rng = np.random.default_rng(31)
+    sub = np.sort(rng.choice(len(c2.pool), 500, replace=False)).astype(np.int32)
+    E1 = ctx.energy()[0]
+    assert abs(E1 - c2.orc.energy(c2.st)[0]) < TOL
+    # new integrals on the same state
+    h2, eri2 = 0.5 * c2.h, 0.75 * c2.eri
+    ctx.set_integrals(h2, eri2)
+    orc2 = oracle.Oracle(c2.n, c2.na, c2.na, h2, eri2)
+    assert abs(ctx.energy()[0] - orc2.energy(c2.st)[0]) < TOL
+    g = ctx.pool_gradients(sub)
+    assert np.abs(g - orc2.pool_gradients(c2.st, c2.pool, subset=sub)).max() < TOL
+    # a new state (half the entries, rescaled) under the same integrals
+    k, a = c2.st.export()
+    keep = np.arange(len(k)) % 2 == 0
+    ks, as_ = k[keep], 3.0 * a[keep]
+    ctx.set_state(ks, as_)
+    st3 = oracle.OracleState.from_arrays(ks, as_)
+    assert abs(ctx.energy()[0] - orc2.energy(st3)[0]) < TOL
+    g = ctx.pool_gradients(sub)
+    assert np.abs(g - orc2.pool_gradients(st3, c2.pool, subset=sub)).max() < TOL
+    # a new stream, then the original integrals again
+    stream = torch.cuda.Stream()  # kept alive until the context is closed
+    ctx.set_stream(stream)
+    ctx.set_integrals(c2.h, c2.eri)
+    assert abs(ctx.energy()[0] - c2.orc.energy(st3)[0]) < TOL
+    g = ctx.pool_gradients()
+    assert np.abs(g - c2.orc.pool_gradients(st3, c2.pool)).max() < TOL
+    ctx.close()
+    stream.synchronize()
+
+
 def test_determinism(swcs, c2):
     ctx = make_ctx(swcs, c2)
     ctx.apply_ansatz(c2.ops, c2.theta, c2.eps)
