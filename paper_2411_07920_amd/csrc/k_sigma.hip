@@ -295,10 +295,15 @@ k_sigma_proj(const u64* __restrict__ keys, const double* __restrict__ amps,
 // shares one subset; a single-excitation pair shares N_e - 1 and is counted
 // only on the one that drops the lowest common electron.
 //
-// A subset is sorted by its rank in the combinatorial number system
-// (sum over its occupied positions c_1 < c_2 < ... of C(c_j, j)), a
-// bijection onto [0, C(2n, N_e - 2)) that needs fewer radix passes than the
-// 2n-bit key.
+// A subset removes two alpha electrons (class 0), one of each spin (class 1)
+// or two beta electrons (class 2); subsets of different classes never
+// coincide.  Within a class a subset is keyed by
+//   rank(alpha string) * C(n, beta count) + rank(beta string),
+// with the rank of a string of occupied spatial orbitals p_1 < p_2 < ... in
+// the combinatorial number system (sum over j of C(p_j, j)), a bijection onto
+// [0, C(n, alpha count) C(n, beta count)); the class sits in bits 60 and up.
+// Each class's records form one segment that is sorted on its own, on
+// fewer key bits than a rank over all 2n spin-orbitals would need.
 
 struct BinomTable {
   u64 v[65][65];  // v[m][k] = C(m, k); C(64, 32) < 2^63
@@ -314,14 +319,34 @@ constexpr BinomTable make_binom_table() {
 }
 
 __constant__ BinomTable kBinom = make_binom_table();
+constexpr int kClassShift = 60;
 
-__device__ inline u64 subset_rank(u64 S) {
+// Spatial string of one spin of an interleaved key (bit p = orbital p).
+__device__ inline u64 spin_string(u64 D, int spin) {
+  u64 x = (D >> spin) & 0x5555555555555555ULL;
+  x = (x | (x >> 1)) & 0x3333333333333333ULL;
+  x = (x | (x >> 2)) & 0x0F0F0F0F0F0F0F0FULL;
+  x = (x | (x >> 4)) & 0x00FF00FF00FF00FFULL;
+  x = (x | (x >> 8)) & 0x0000FFFF0000FFFFULL;
+  x = (x | (x >> 16)) & 0x00000000FFFFFFFFULL;
+  return x;
+}
+
+__device__ inline u64 string_rank(u64 S) {
   u64 r = 0;
   for (int j = 1; S; ++j) {
     r += kBinom.v[__ffsll((long long)S) - 1][j];
     S &= S - 1;
   }
   return r;
+}
+
+// Key of a subset of na + nb - 2 electrons (na, nb: the sector's counts).
+__device__ inline u64 subset_key(u64 S, int n_spatial, int na) {
+  const u64 sa = spin_string(S, 0), sb = spin_string(S, 1);
+  const int ca = __popcll(sa), cb = __popcll(sb);
+  const u64 cls = (ca == na - 2) ? 0 : (ca == na - 1 ? 1 : 2);
+  return (cls << kClassShift) | (string_rank(sa) * kBinom.v[n_spatial][cb] + string_rank(sb));
 }
 
 __device__ inline u64 shfl_u64(u64 v, int src) {
@@ -331,60 +356,100 @@ __device__ inline u64 shfl_u64(u64 v, int src) {
 }
 
 __device__ inline u64 shfl_up_u64(u64 v, int d) {
-  const unsigned lo = (unsigned)__shfl_up((int)(unsigned)v, d);
-  const unsigned hi = (unsigned)__shfl_up((int)(unsigned)(v >> 32), d);
+  const unsigned lo = (unsigned)__shfl_up((int)(unsigned)v, d, 32);
+  const unsigned hi = (unsigned)__shfl_up((int)(unsigned)(v >> 32), d, 32);
   return ((u64)hi << 32) | lo;
 }
 
-// Records g = i * C(ne, 2) + p, one wavefront per entry: rank of the subset
-// that drops electrons a < b (p = b (b - 1) / 2 + a; ~0 for dead entries,
-// above every rank).  Lane l < ne holds the l-th occupied position c_l; with
-// inclusive lane prefix sums IA, IB, IG of C(c_l, l + 1), C(c_l, l) and
-// C(c_l, l - 1) (the rank terms of an electron kept below a, between a and b,
-// and above b), rank = IA[a - 1] + (IB[b - 1] - IB[a]) + (IG[ne - 1] - IG[b]).
+// Triangular index p = b (b - 1) / 2 + a, a < b.
+__device__ inline void tri_decode(u64 p, u64* a, u64* b) {
+  u64 bb = (u64)((1.0 + sqrt(1.0 + 8.0 * (double)p)) * 0.5);
+  while (bb * (bb - 1) / 2 > p) --bb;
+  while ((bb + 1) * bb / 2 <= p) ++bb;
+  *b = bb;
+  *a = p - bb * (bb - 1) / 2;
+}
+
+// One wavefront per entry; records of class 0, 1, 2 go to the segments that
+// start at 0, n r0 and n (r0 + r1) (r0 = C(na, 2), r1 = na nb), entry i's at
+// i r_c + p.  Lanes 0..31 hold the alpha electrons and 32..63 the beta ones:
+// lane s + l holds the orbital c_l of electron l of its spin and, as
+// inclusive prefix sums over l within the half, IA, IB, IG of C(c_l, l + 1),
+// C(c_l, l) and C(c_l, l - 1) -- the rank terms of an electron kept with
+// none, one or two removed electrons below it.  A string's rank is then
+//   none removed:  IA[cnt - 1]
+//   a removed:     IA[a - 1] + IB[cnt - 1] - IB[a]
+//   a < b removed: IA[a - 1] + IB[b - 1] - IB[a] + IG[cnt - 1] - IG[b].
+// Dead entries emit the key ~0 (class bits 3, low bits above every rank).
 __global__ void __launch_bounds__(256)
-k_holepair_emit(const u64* __restrict__ keys, const double* __restrict__ amps, u64 n, int ne,
-                u64* __restrict__ out_key, unsigned* __restrict__ out_val) {
-  const int lane = threadIdx.x & 63;
-  const u64 np = (u64)ne * (u64)(ne - 1) / 2;
+k_holepair_emit(const u64* __restrict__ keys, const double* __restrict__ amps, u64 n, int n_spatial,
+                int na, int nb, u64* __restrict__ out_key, unsigned* __restrict__ out_val) {
+  const int lane = threadIdx.x & 63, half = lane >> 5, hl = lane & 31;
+  const u64 r0 = (u64)na * (u64)(na - 1) / 2, r1 = (u64)na * (u64)nb, r2 = (u64)nb * (u64)(nb - 1) / 2;
+  const u64 seg1 = n * r0, seg2 = n * (r0 + r1);
+  const u64 mul0 = kBinom.v[n_spatial][nb], mul1 = kBinom.v[n_spatial][nb > 0 ? nb - 1 : 0],
+            mul2 = kBinom.v[n_spatial][nb > 1 ? nb - 2 : 0];
   const u64 w0 = ((u64)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const u64 wstride = ((u64)gridDim.x * blockDim.x) >> 6;
   for (u64 i = w0; i < n; i += wstride) {
     const bool dead = is_dead(amps[i]);  // uniform over the wavefront
     const u64 D = keys[i];
-    u64 x = D;
-    for (int t = 0; t < lane && x; ++t) x &= x - 1;
-    const bool mine = lane < ne;
+    u64 x = spin_string(D, half);
+    const int cnt = half ? nb : na;
+    for (int t = 0; t < hl && x; ++t) x &= x - 1;
+    const bool mine = hl < cnt;
     const int c = mine ? __ffsll((long long)x) - 1 : 0;
-    u64 ia = mine ? kBinom.v[c][lane + 1 <= 64 ? lane + 1 : 64] : 0;
-    u64 ib = mine ? kBinom.v[c][lane] : 0;
-    u64 ig = (mine && lane >= 1) ? kBinom.v[c][lane - 1] : 0;
-    for (int d = 1; d < 64; d <<= 1) {
+    u64 ia = mine ? kBinom.v[c][hl + 1] : 0;
+    u64 ib = mine ? kBinom.v[c][hl] : 0;
+    u64 ig = (mine && hl >= 1) ? kBinom.v[c][hl - 1] : 0;
+    for (int d = 1; d < 32; d <<= 1) {
       const u64 ta = shfl_up_u64(ia, d), tb = shfl_up_u64(ib, d), tg = shfl_up_u64(ig, d);
-      if (lane >= d) {
+      if (hl >= d) {
         ia += ta;
         ib += tb;
         ig += tg;
       }
     }
-    const u64 g_top = shfl_u64(ig, ne - 1);
-    for (u64 p0 = 0; p0 < np; p0 += 64) {
+    // whole strings and the top prefix values (uniform)
+    const u64 full_a = na > 0 ? shfl_u64(ia, na - 1) : 0, full_b = nb > 0 ? shfl_u64(ia, 32 + nb - 1) : 0;
+    const u64 ib_top_a = na > 0 ? shfl_u64(ib, na - 1) : 0, ib_top_b = nb > 0 ? shfl_u64(ib, 32 + nb - 1) : 0;
+    const u64 ig_top_a = na > 0 ? shfl_u64(ig, na - 1) : 0, ig_top_b = nb > 0 ? shfl_u64(ig, 32 + nb - 1) : 0;
+    // class 0 and 2: two electrons of one spin removed (s = 0 alpha, 32 beta)
+    for (int cls = 0; cls < 3; cls += 2) {
+      const int s = cls ? 32 : 0;
+      const u64 rc = cls ? r2 : r0, base = (cls ? seg2 : 0) + i * rc;
+      const u64 ig_top = cls ? ig_top_b : ig_top_a, other = cls ? full_a : full_b;
+      for (u64 p0 = 0; p0 < rc; p0 += 64) {
+        const u64 p = p0 + (u64)lane;
+        const bool valid = p < rc;
+        u64 a = 0, b = 1;
+        if (valid) tri_decode(p, &a, &b);
+        const u64 a_lo = shfl_u64(ia, s + (a > 0 ? (int)a - 1 : 0));
+        const u64 b_lo = shfl_u64(ib, s + (int)b - 1);
+        const u64 b_a = shfl_u64(ib, s + (int)a);
+        const u64 g_b = shfl_u64(ig, s + (int)b);
+        if (valid) {
+          const u64 r = (a > 0 ? a_lo : 0) + (b_lo - b_a) + (ig_top - g_b);
+          const u64 key = cls ? (other * mul2 + r) : (r * mul0 + other);
+          out_key[base + p] = dead ? ~0ULL : (((u64)cls << kClassShift) | key);
+          out_val[base + p] = (unsigned)i;
+        }
+      }
+    }
+    // class 1: alpha electron a and beta electron b removed
+    for (u64 p0 = 0; p0 < r1; p0 += 64) {
       const u64 p = p0 + (u64)lane;
-      const bool valid = p < np;
-      // b = largest integer with b (b - 1) / 2 <= p
-      u64 b = valid ? (u64)((1.0 + sqrt(1.0 + 8.0 * (double)p)) * 0.5) : 1;
-      while (b * (b - 1) / 2 > p) --b;
-      while ((b + 1) * b / 2 <= p) ++b;
-      const u64 a = valid ? p - b * (b - 1) / 2 : 0;
-      if (!valid) b = 1;
-      const u64 a_lo = shfl_u64(ia, a > 0 ? (int)a - 1 : 0);
-      const u64 b_lo = shfl_u64(ib, (int)b - 1);
-      const u64 b_a = shfl_u64(ib, (int)a);
-      const u64 g_b = shfl_u64(ig, (int)b);
+      const bool valid = p < r1;
+      const u64 a = valid ? p / (u64)nb : 0, b = valid ? p - a * (u64)nb : 0;
+      const u64 aa_lo = shfl_u64(ia, a > 0 ? (int)a - 1 : 0);
+      const u64 ab = shfl_u64(ib, (int)a);
+      const u64 ba_lo = shfl_u64(ia, 32 + (b > 0 ? (int)b - 1 : 0));
+      const u64 bb = shfl_u64(ib, 32 + (int)b);
       if (valid) {
-        const u64 r = (a > 0 ? a_lo : 0) + (b_lo - b_a) + (g_top - g_b);
-        out_key[i * np + p] = dead ? ~0ULL : r;
-        out_val[i * np + p] = (unsigned)i;
+        const u64 ra = (a > 0 ? aa_lo : 0) + (ib_top_a - ab);
+        const u64 rb = (b > 0 ? ba_lo : 0) + (ib_top_b - bb);
+        out_key[seg1 + i * r1 + p] = dead ? ~0ULL : ((1ULL << kClassShift) | (ra * mul1 + rb));
+        out_val[seg1 + i * r1 + p] = (unsigned)i;
       }
     }
   }
@@ -405,7 +470,7 @@ k_sigma_diag(const double* __restrict__ amps, const double* __restrict__ diag, u
 // of its group to sigma(D).
 __global__ void __launch_bounds__(256)
 k_holepair_sigma(const u64* __restrict__ skey, const unsigned* __restrict__ sidx, u64 total,
-                 const u64* __restrict__ keys, const double* __restrict__ amps, Ints I,
+                 const u64* __restrict__ keys, const double* __restrict__ amps, Ints I, int na,
                  double* __restrict__ sigma) {
   const u64 stride = (u64)gridDim.x * blockDim.x;
   for (u64 g = (u64)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += stride) {
@@ -434,7 +499,7 @@ k_holepair_sigma(const u64* __restrict__ skey, const unsigned* __restrict__ sidx
         h = double_element(I, D, h0, h1, p0, p1);
       } else {
         const u64 common = D & X;
-        if (S != subset_rank(common & (common - 1))) continue;
+        if (S != subset_key(common & (common - 1), I.n, na)) continue;
         h = single_element(I, D, __ffsll((long long)holes) - 1, __ffsll((long long)parts) - 1);
       }
       acc += h * amps[iX];
@@ -927,9 +992,10 @@ hipError_t launch_sigma_proj(const DeviceState& st, const Ints& I, const ExcSpac
   return hipGetLastError();
 }
 
-hipError_t launch_holepair_emit(const DeviceState& st, u64 n, int ne, u64* out_key, unsigned* out_val,
-                                int grid, hipStream_t stream) {
-  hipLaunchKernelGGL(k_holepair_emit, dim3(grid), dim3(256), 0, stream, st.keys, st.amps, n, ne,
+hipError_t launch_holepair_emit(const DeviceState& st, u64 n, int n_spatial, int na, int nb, u64* out_key,
+                                unsigned* out_val, int grid, hipStream_t stream) {
+  if (na > 32 || nb > 32) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_holepair_emit, dim3(grid), dim3(256), 0, stream, st.keys, st.amps, n, n_spatial, na, nb,
                      out_key, out_val);
   return hipGetLastError();
 }
@@ -941,11 +1007,11 @@ hipError_t launch_sigma_diag(const DeviceState& st, const Ints& I, u64 n, double
   return hipGetLastError();
 }
 
-hipError_t launch_holepair_sigma(const DeviceState& st, const Ints& I, const u64* skey,
+hipError_t launch_holepair_sigma(const DeviceState& st, const Ints& I, int na, const u64* skey,
                                  const unsigned* sidx, u64 total, double* sigma, int grid,
                                  hipStream_t stream) {
   hipLaunchKernelGGL(k_holepair_sigma, dim3(grid), dim3(256), 0, stream, skey, sidx, total, st.keys,
-                     st.amps, I, sigma);
+                     st.amps, I, na, sigma);
   return hipGetLastError();
 }
 

@@ -328,11 +328,11 @@ int pairwise_capacity();
 hipError_t launch_sigma_pairwise(const DeviceState& st, const Ints& I, u64 n, double* sigma,
                                  double* partial, int grid, hipStream_t stream);
 hipError_t launch_diag(const DeviceState& st, const Ints& I, u64 n, int grid, hipStream_t stream);
-hipError_t launch_holepair_emit(const DeviceState& st, u64 n, int ne, u64* out_key, unsigned* out_val,
-                                int grid, hipStream_t stream);
+hipError_t launch_holepair_emit(const DeviceState& st, u64 n, int n_spatial, int na, int nb, u64* out_key,
+                                unsigned* out_val, int grid, hipStream_t stream);
 hipError_t launch_sigma_diag(const DeviceState& st, const Ints& I, u64 n, double* sigma, int grid,
                              hipStream_t stream);
-hipError_t launch_holepair_sigma(const DeviceState& st, const Ints& I, const u64* skey,
+hipError_t launch_holepair_sigma(const DeviceState& st, const Ints& I, int na, const u64* skey,
                                  const unsigned* sidx, u64 total, double* sigma, int grid,
                                  hipStream_t stream);
 hipError_t launch_sigma_dots(const DeviceState& st, const double* sigma, u64 n, double* partial,
