@@ -40,8 +40,9 @@ class Case:
         self.n, self.ne, self.h, self.eri, self.pool = n, ne, h, eri, pool
         self.ops, self.theta, self.eps, self.name = ops, theta, eps, name
         self.ref = reference_key(ne)
-        self.na = ne // 2
-        self.orc = oracle.Oracle(n, self.na, self.na, h, eri)
+        # the reference fills the lowest spin-orbitals, alpha first
+        self.na, self.nb = (ne + 1) // 2, ne // 2
+        self.orc = oracle.Oracle(n, self.na, self.nb, h, eri)
         self.st = oracle.Oracle.apply_ansatz(pool, ops, theta, eps, self.ref)
 
 
@@ -97,7 +98,7 @@ def spread():
 
 
 def make_ctx(swcs, case):
-    return swcs.make_context(case.n, case.na, case.na, case.h, case.eri, case.pool, case.ref)
+    return swcs.make_context(case.n, case.na, case.nb, case.h, case.eri, case.pool, case.ref)
 
 
 def check_state(ctx, case):
@@ -248,11 +249,22 @@ def two_electron_case():
     return Case(n, ne, h, eri, pool, ops, theta, 0.0, "ne2")
 
 
+def open_shell_case():
+    """5 electrons (3 alpha, 2 beta) in 7 spatial orbitals: unequal spin
+    counts, so the three hole-pair classes differ in size and key range."""
+    n, ne = 7, 5
+    h, eri = make_integrals(n, n, 1301)
+    pool = enumerate_pool(n)
+    ops, theta = draw_ansatz(len(pool), 40, -0.5, 0.5, 1302)
+    return Case(n, ne, h, eri, pool, ops, theta, 0.0, "open5")
+
+
 @pytest.mark.parametrize("method", ["enumerate", "hole_pairs", "pairs"])
 def test_sigma_methods(swcs, spread, method):
-    """Both ways of forming sigma_P against the oracle: energy, sigma rows and
-    the adjoint gradients that start from sigma_P."""
-    for case in (spread, config_case("c3"), two_electron_case()):
+    """All ways of forming sigma_P against the oracle: energy, sigma rows, the
+    adjoint gradients that start from sigma_P, and (open shell) the pool
+    gradients."""
+    for case in (spread, config_case("c3"), two_electron_case(), open_shell_case()):
         _say(f"[parity] sigma via {method}: {case.name}")
         ctx = make_ctx(swcs, case)
         ctx.set_sigma_method(method)
@@ -266,6 +278,9 @@ def test_sigma_methods(swcs, spread, method):
         dE, E2 = ctx.param_gradients(len(case.ops))
         dE_ref, _ = case.orc.param_gradients(case.pool, case.ops, case.theta, case.eps, case.ref)
         assert abs(E2 - E_ref) < TOL and np.abs(dE - dE_ref).max() < TOL
+        if case.na != case.nb:
+            g = ctx.pool_gradients()
+            assert np.abs(g - case.orc.pool_gradients(case.st, case.pool)).max() < TOL
         ctx.close()
 
 
