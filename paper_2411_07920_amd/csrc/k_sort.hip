@@ -137,12 +137,13 @@ void scan_exclusive(u64* data, u64 len, u64* sums, hipStream_t stream) {
 }
 
 // Stable scatter of one tile of THREADS * ROWS items (the histogram's tile).
-// Each THREADS-item row is ranked by wave ballots on the digit bits and a
-// prefix over the row's waves; the tile is first reordered by digit in LDS
-// and then written out, so consecutive lanes store consecutive positions of
-// one digit's run.  The tile's digit counts come from the scanned offsets
-// (the next tile's offset, or the next digit's first offset for the last
-// tile).  Threads below 256 own one digit each in the per-digit arrays.
+// Rows of THREADS items are ranked two at a time by wave ballots on the digit
+// bits and prefixes over the waves (and over the first row of the pair for
+// the second); the tile is first reordered by digit in LDS and then written
+// out, so consecutive lanes store consecutive positions of one digit's run.
+// The tile's digit counts come from the scanned offsets (the next tile's
+// offset, or the next digit's first offset for the last tile).  Threads below
+// 256 own one digit each in the per-digit arrays.
 template <int THREADS, int ROWS, class V>
 __global__ void __launch_bounds__(THREADS)
 k_radix_scatter(const u64* __restrict__ keys_in, const V* __restrict__ vals_in, u64 count,
@@ -154,15 +155,17 @@ k_radix_scatter(const u64* __restrict__ keys_in, const V* __restrict__ vals_in, 
   __shared__ u64 base_off[256];
   __shared__ unsigned local_off[256];
   __shared__ unsigned running[256];
-  __shared__ unsigned wave_cnt[kWaves][256];
-  __shared__ unsigned scan_tmp[256];
+  __shared__ unsigned wave_cnt[2][kWaves][256];
+  __shared__ unsigned wave_tot[4];
   __shared__ u64 s_key[kTile];
   __shared__ V s_val[kTile];
   const int lane = __lane_id();
   const int wave = threadIdx.x >> 6;
   const int t = threadIdx.x;
   const u64 b = blockIdx.x;
-  unsigned cnt = 0;
+  // digit counts of the tile and their exclusive scan (waves 0-3 hold the
+  // 256 digits; a wavefront scan, then the wave totals)
+  unsigned cnt = 0, incl = 0;
   if (t < 256) {
     const u64 o = offsets[(u64)t * nblocks + b];
     const u64 nxt = (b + 1 < (u64)nblocks) ? offsets[(u64)t * nblocks + b + 1]
@@ -170,17 +173,19 @@ k_radix_scatter(const u64* __restrict__ keys_in, const V* __restrict__ vals_in, 
     base_off[t] = o;
     running[t] = 0;
     cnt = (unsigned)(nxt - o);
-    scan_tmp[t] = cnt;
+    incl = cnt;
+    for (int off = 1; off < 64; off <<= 1) {
+      const unsigned v = __shfl_up(incl, off);
+      if (lane >= off) incl += v;
+    }
+    if (lane == 63) wave_tot[wave] = incl;
   }
   __syncthreads();
-  // exclusive scan of the tile's 256 digit counts
-  for (int off = 1; off < 256; off <<= 1) {
-    const unsigned w = (t < 256 && t >= off) ? scan_tmp[t - off] : 0u;
-    __syncthreads();
-    if (t < 256) scan_tmp[t] += w;
-    __syncthreads();
+  if (t < 256) {
+    unsigned before = 0;
+    for (int w = 0; w < wave; ++w) before += wave_tot[w];
+    local_off[t] = before + incl - cnt;
   }
-  if (t < 256) local_off[t] = scan_tmp[t] - cnt;
   const u64 tile0 = b * (u64)kTile;
   const unsigned tile_n = (unsigned)((count - tile0) < (u64)kTile ? (count - tile0) : (u64)kTile);
   // every row's loads are issued before the ranking starts
@@ -193,32 +198,44 @@ k_radix_scatter(const u64* __restrict__ keys_in, const V* __restrict__ vals_in, 
     val[r] = (vals_in && i < tile_n) ? vals_in[tile0 + i] : 0;
   }
 #pragma unroll
-  for (int r = 0; r < ROWS; ++r) {
+  for (int r = 0; r < ROWS; r += 2) {
     // column t is cleared by the thread that summed it at the end of the
-    // previous row
+    // previous pair of rows
     if (t < 256)
-      for (int w = 0; w < kWaves; ++w) wave_cnt[w][t] = 0;
+      for (int w = 0; w < kWaves; ++w) wave_cnt[0][w][t] = wave_cnt[1][w][t] = 0;
     __syncthreads();
-    const bool valid = (unsigned)r * THREADS + t < tile_n;
-    const unsigned digit = valid ? (unsigned)((key[r] >> shift) & 255u) : 0u;
-    u64 peers = __ballot(valid);
-    for (int bit = 0; bit < 8; ++bit) {
-      const u64 m = __ballot(valid && ((digit >> bit) & 1u));
-      peers &= ((digit >> bit) & 1u) ? m : ~m;
+    bool valid[2];
+    unsigned digit[2], below[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int rr = (r + h < ROWS) ? r + h : r;  // an odd last row has no partner
+      valid[h] = r + h < ROWS && (unsigned)(r + h) * THREADS + t < tile_n;
+      digit[h] = valid[h] ? (unsigned)((key[rr] >> shift) & 255u) : 0u;
+      u64 peers = __ballot(valid[h]);
+      for (int bit = 0; bit < 8; ++bit) {
+        const u64 m = __ballot(valid[h] && ((digit[h] >> bit) & 1u));
+        peers &= ((digit[h] >> bit) & 1u) ? m : ~m;
+      }
+      below[h] = (unsigned)__popcll(peers & ((1ULL << lane) - 1ULL));
+      if (valid[h] && below[h] == 0) wave_cnt[h][wave][digit[h]] = (unsigned)__popcll(peers);
     }
-    const unsigned below = (unsigned)__popcll(peers & ((1ULL << lane) - 1ULL));
-    if (valid && below == 0) wave_cnt[wave][digit] = (unsigned)__popcll(peers);
     __syncthreads();
-    if (valid) {
-      unsigned pos = local_off[digit] + running[digit] + below;
-      for (int w = 0; w < wave; ++w) pos += wave_cnt[w][digit];
-      s_key[pos] = key[r];
-      s_val[pos] = val[r];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      if (!valid[h]) continue;
+      const unsigned d = digit[h];
+      unsigned pos = local_off[d] + running[d] + below[h];
+      for (int w = 0; w < wave; ++w) pos += wave_cnt[h][w][d];
+      if (h == 1)
+        for (int w = 0; w < kWaves; ++w) pos += wave_cnt[0][w][d];
+      const int rr = (r + h < ROWS) ? r + h : r;
+      s_key[pos] = key[rr];
+      s_val[pos] = val[rr];
     }
     __syncthreads();
     if (t < 256) {
       unsigned add = 0;
-      for (int w = 0; w < kWaves; ++w) add += wave_cnt[w][t];
+      for (int w = 0; w < kWaves; ++w) add += wave_cnt[0][w][t] + wave_cnt[1][w][t];
       running[t] += add;
     }
   }
@@ -232,11 +249,20 @@ k_radix_scatter(const u64* __restrict__ keys_in, const V* __restrict__ vals_in, 
   }
 }
 
-u64 radix_sort_scratch_elems(u64 count) {
+// Scratch (u64 elements) for sorting any count up to `count`: the tiling
+// switches from one-row to 16-row tiles at 2^20 items, so just below the
+// switch a sort needs more scratch than just above it.
+static u64 radix_sort_scratch_exact(u64 count) {
   const u64 tile = (u64)kSortThreads * sort_rows(count);
   const u64 nblocks = (count + tile - 1) / tile;
   const u64 len = 256 * (nblocks < 1 ? 1 : nblocks);
   return len + scan_scratch_elems(len);
+}
+
+u64 radix_sort_scratch_elems(u64 count) {
+  u64 r = radix_sort_scratch_exact(count);
+  if (count >= (1ULL << 20)) r = std::max(r, radix_sort_scratch_exact((1ULL << 20) - 1));
+  return r;
 }
 
 // Sorts (keys, vals) ascending by the low key_bits bits of the key; tmp_* are

@@ -893,7 +893,12 @@ static int energy_enqueue(swcs_ctx* c, u64 n) {
     HIP_TRY(c, c->hp_val.ensure(total * 4), "alloc hole-pair values");
     HIP_TRY(c, c->hp_tk.ensure(total * 8), "alloc hole-pair keys");
     HIP_TRY(c, c->hp_tv.ensure(total * 4), "alloc hole-pair values");
-    const u64 scr = radix_sort_scratch_elems(total);
+    // the three class segments are sorted one by one; a short segment uses
+    // small tiles and can need more scratch than a longer one
+    const u64 na = (u64)c->na, nb = (u64)c->nb;
+    const u64 seg_len[3] = {n * (na * (na - 1) / 2), n * na * nb, n * (nb * (nb - 1) / 2)};
+    u64 scr = 0;
+    for (u64 len : seg_len) scr = std::max(scr, radix_sort_scratch_elems(len));
     HIP_TRY(c, c->sort_scratch.ensure(scr * 8), "alloc sort scratch");
     const int rg = grid_blocks(c, total, 256);
     u64* key = c->hp_key.as<u64>();
@@ -905,8 +910,6 @@ static int energy_enqueue(swcs_ctx* c, u64 n) {
     // Segments of the three removal classes (alpha-alpha, alpha-beta,
     // beta-beta), sorted one by one on the key bits of the largest class;
     // the dead marker's low bits are all ones, above every key.
-    const u64 na = (u64)c->na, nb = (u64)c->nb;
-    const u64 seg_len[3] = {n * (na * (na - 1) / 2), n * na * nb, n * (nb * (nb - 1) / 2)};
     u64 cmax = 1;
     if (na >= 2) cmax = std::max(cmax, binomial_u64(c->n, c->na - 2) * binomial_u64(c->n, c->nb));
     if (na >= 1 && nb >= 1) cmax = std::max(cmax, binomial_u64(c->n, c->na - 1) * binomial_u64(c->n, c->nb - 1));

@@ -312,6 +312,40 @@ def test_sigma_hole_pairs_synthetic_state(swcs):
     ctx.close()
 
 
+def test_sort_tilings_below_and_above_2_20(swcs):
+    """Radix sorts switch tilings at 2^20 items.  (a) sigma_P by hole pairs on
+    10,000 determinants of the 52-spin-orbital, 16-electron sector: 1.2M
+    records in class segments of 280k / 640k / 280k; (b) the sorted export of
+    a state with 1.1M stored but fewer than 2^20 alive entries."""
+    c = CONFIGS["c5"]
+    h, eri = make_integrals(c.n, c.rank, c.seed_int)
+    pool = enumerate_pool(c.n)
+    orc = oracle.Oracle(c.n, 8, 8, h, eri)
+    ctx = swcs.make_context(c.n, 8, 8, h, eri, pool, reference_key(16))
+    keys, amps = draw_synthetic_state(c.n, 8, 8, 10_000, 4007)
+    ctx.set_state(keys, amps)
+    ctx.set_sigma_method("hole_pairs")
+    ks, sig = ctx.sigma_projected()
+    ctx.set_sigma_method("enumerate")
+    ks2, sig2 = ctx.sigma_projected()
+    assert np.array_equal(ks, ks2) and np.abs(sig - sig2).max() < 1e-15
+    st = oracle.OracleState.from_arrays(keys, amps)
+    rows = np.random.default_rng(8).choice(len(ks), 40, replace=False)
+    assert np.abs(sig[rows] - orc.sigma_at(st, ks[rows])).max() < TOL
+    # (b) one gate with pruning keeps about a third of 1.1M entries
+    keys, amps = draw_synthetic_state(c.n, 8, 8, 1_100_000, 4008)
+    ctx.set_state(keys, amps)
+    op = int(np.flatnonzero(pool[:, 2] >= 0)[123])
+    n_out = ctx.apply_gates(np.array([op], dtype=np.int32), np.array([0.3]), 1e-4)
+    kg, ag = ctx.get_state()
+    assert len(kg) == n_out < (1 << 20)
+    st, _ = oracle.Oracle.apply_gate_truncate(oracle.OracleState.from_arrays(keys, amps), pool[op],
+                                              math.cos(0.3), math.sin(0.3), 1e-4)
+    kr, ar = st.export()
+    assert np.array_equal(kg, kr) and np.array_equal(ag, ar)
+    ctx.close()
+
+
 def test_last_parameter_identity_two_paths(swcs, c2):
     """Adjoint dE/dtheta_M equals the pool gradient of the last operator at
     eps = 0 (two independent GPU code paths agreeing with the oracle)."""
