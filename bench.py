@@ -149,12 +149,14 @@ def gpu_bench(args, wl):
     def phase_screener():
         ctx.features(prev, age, count, feat)
         ctx.mlp_forward(W, feat, score)
+        ctx.add_feature(score, feat, 10, +1)  # score = log10 last |g| + network
         ctx.select(score, rnd, wl.n_top, wl.n_rand, sel)
-        # exact gradients of the selection and their targets log10(|g| + 1e-12),
-        # stream-ordered on the device
+        # exact gradients of the selection and the network's residual targets
+        # log10(|g| + 1e-12) - feature 10, stream-ordered on the device
         ctx.pool_gradients_device(sel, gsel)
         ctx.log_abs(gsel, tgt)
         torch.index_select(feat, 0, sel.long(), out=xs)
+        ctx.add_feature(tgt, xs, 10, -1)
         ctx.mlp_forward(W, xs, ys, act)
         ctx.mse(ys, tgt, dy, loss)
         ctx.mlp_backward(W, xs, act, dy, dW)
@@ -291,8 +293,9 @@ def adapt_bench(args):
     """ADAPT-VQE from the reference: full-pool arm, screened arm (both timed)
     and a screened validation arm that also evaluates the full pool on every
     iteration (untimed) to measure selection agreement and two baselines at
-    the same exact-gradient budget (a random subset, and the top operators by
-    their last exact |g|)."""
+    the same exact-gradient budget: the fraction of screened iterations whose
+    full-pool choice lies in a random subset, or among the operators with the
+    largest last exact |g| (the choice a stale ranking would find)."""
     import torch
     from paper_2411_07920_amd import adapt, swcs
 
@@ -351,6 +354,10 @@ def adapt_bench(args):
                      "E_final": E_scr, "n_det_final": nd_scr},
         "validation": {"screened_iterations": len(match),
                        "same_operator_frac": float(np.mean(match)) if match else None,
+                       "random_subset_hit_frac": (float(np.mean([r["random_hit"] for r in screened_iters]))
+                                                  if match else None),
+                       "stale_top_hit_frac": (float(np.mean([r["stale_hit"] for r in screened_iters]))
+                                              if match else None),
                        "E_final": E_val},
         "dE_final_screened_minus_full": E_scr - E_full,
     }

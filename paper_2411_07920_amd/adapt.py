@@ -178,6 +178,9 @@ def run_adapt(ctx, K: int, cfg: AdaptConfig, ops0=None, theta0=None, log=None):
     scr = Screener(ctx, K, cfg.seed, cfg.frac_top, cfg.frac_rand,
                    train_steps=cfg.train_steps) if cfg.screener else None
     history = []
+    # last exact |g| of every operator (the information a stale-ranking
+    # heuristic would select with; shadow runs only)
+    last_absg = np.zeros(K) if cfg.shadow_full else None
     for it in range(cfg.max_iter):
         rec = {"iter": it}
         t0 = time.perf_counter()
@@ -217,6 +220,15 @@ def run_adapt(ctx, K: int, cfg: AdaptConfig, ops0=None, theta0=None, log=None):
             rec["shadow_kstar"] = ks
             rec["shadow_match"] = bool(ks == kstar)
             rec["shadow_gnorm"] = float(np.linalg.norm(g_all))
+            # baselines with the same number of exact gradients: a random
+            # subset, and the operators with the largest last exact |g|
+            budget = len(idx)
+            rnd = np.random.default_rng((cfg.seed, it)).choice(K, budget, replace=False)
+            stale = np.argsort(-last_absg, kind="stable")[:budget]
+            rec["random_hit"] = bool(np.any(rnd == ks))
+            rec["stale_hit"] = bool(np.any(stale == ks))
+        if last_absg is not None:
+            last_absg[np.asarray(idx)] = np.abs(np.asarray(gsel))
         if cfg.grad_tol is not None and full and gnorm < cfg.grad_tol:
             rec["converged"] = True
             history.append(rec)

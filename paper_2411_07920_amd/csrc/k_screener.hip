@@ -299,6 +299,14 @@ __global__ void k_mse_finish(const float* __restrict__ partial, int nblocks, lon
 }
 
 // Screener targets t = log10(|g| + 1e-12) (float64 arithmetic, float32 result).
+// v[i] += sign * feat[i * 16 + col]: the screener's score and target offset
+// by one feature column (log10 of the last exact |g|).
+__global__ void k_add_feature(float* __restrict__ v, const float* __restrict__ feat, long long n, int col,
+                              float sign) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) v[i] += sign * feat[i * 16 + col];
+}
+
 __global__ void k_log_abs(const double* __restrict__ g, long long n, float* __restrict__ t) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) t[i] = (float)log10(fabs(g[i]) + 1e-12);
@@ -376,6 +384,14 @@ hipError_t launch_mse(const float* y, const float* t, long long B, float* dy, fl
 hipError_t launch_log_abs(const double* g, long long n, float* t, hipStream_t stream) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_log_abs, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, g, n, t);
+  return hipGetLastError();
+}
+
+hipError_t launch_add_feature(float* v, const float* feat, long long n, int col, float sign,
+                              hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_add_feature, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, v, feat, n, col,
+                     sign);
   return hipGetLastError();
 }
 

@@ -1432,6 +1432,15 @@ int swcs_log_abs(swcs_ctx* c, const double* d_g, int64_t n, float* d_t) {
   return SWCS_OK;
 }
 
+int swcs_add_feature(swcs_ctx* c, float* d_v, const float* d_feat, int64_t n, int col, int sign) {
+  if (!c) return SWCS_E_INVALID;
+  if (n < 0 || (n > 0 && (!d_v || !d_feat)) || col < 0 || col >= 16 || (sign != 1 && sign != -1))
+    return fail(c, SWCS_E_INVALID, "bad add_feature arguments");
+  HIP_TRY(c, hipSetDevice(c->device), "hipSetDevice");
+  HIP_TRY(c, launch_add_feature(d_v, d_feat, n, col, (float)sign, c->stream), "add_feature");
+  return SWCS_OK;
+}
+
 int swcs_adam_step(swcs_ctx* c, float* d_W, float* d_m, float* d_v, const float* d_dW, int64_t P,
                    float lr, float b1, float b2, float eps, int step) {
   if (!c) return SWCS_E_INVALID;

@@ -2,10 +2,13 @@
 
 The ADAPT step ranks the pool by the derivative of the energy with respect to
 each operator appended at the end of the ansatz (Sec. II.C, step 4).  The
-screener predicts log10 |g_k| from sixteen cheap per-operator features with a
-16 -> 128 -> 128 -> 1 ReLU network, so that exact gradients are evaluated
-only for the top-scored fraction plus a random share; the exact gradients
-that result are its training data (online, Adam, mean squared error).
+screener predicts log10 |g_k| from sixteen cheap per-operator features, so
+that exact gradients are evaluated only for the top-scored fraction plus a
+random share; the exact gradients that result are its training data (online,
+Adam, mean squared error).  The prediction is feature 10 -- log10 of the
+operator's last exact |g| -- plus the output of a 16 -> 128 -> 128 -> 1 ReLU
+network, which therefore learns how each gradient has changed since it was
+last evaluated; an untrained network ranks by the last exact gradients.
 
 All arithmetic runs in libswcs kernels (features, forward, MSE, backward,
 Adam, selection); torch only holds the device buffers.
@@ -34,12 +37,11 @@ class Screener:
         self.rng = np.random.default_rng(seed)
         P = swcs.mlp_param_count()
         w = np.zeros(P, dtype=np.float32)
-        # He-normal weights, zero biases
+        # He-normal hidden layers, zero biases and a zero output layer: the
+        # untrained network adds nothing to the last exact log10 |g|
         w[: 16 * 128] = self.rng.normal(0, math.sqrt(2 / 16), 16 * 128)
         o = 16 * 128 + 128
         w[o: o + 128 * 128] = self.rng.normal(0, math.sqrt(2 / 128), 128 * 128)
-        o += 128 * 128 + 128
-        w[o: o + 128] = self.rng.normal(0, math.sqrt(2 / 128), 128)
         dev = "cuda"
         self.W = torch.from_numpy(w).to(dev)
         self.m = torch.zeros(P, device=dev)
@@ -65,8 +67,11 @@ class Screener:
         self.count.copy_(torch.from_numpy(cnt))
         self.ctx.features(self.prev_absg, self.age, self.count, self.feat)
 
+    RESIDUAL_COL = 10  # log10 of the last exact |g|
+
     def scores(self):
         self.ctx.mlp_forward(self.W, self.feat, self.score)
+        self.ctx.add_feature(self.score, self.feat, self.RESIDUAL_COL, +1)
         return self.score
 
     def select(self):
@@ -95,6 +100,7 @@ class Screener:
         x = self.feat.index_select(0, rows)
         t = torch.empty(len(rows), dtype=torch.float32, device="cuda")
         self.ctx.log_abs(g_d, t)
+        self.ctx.add_feature(t, x, self.RESIDUAL_COL, -1)  # residual target of the network
         n = len(rows)
         for s in range(0, n, self.buffer_rows):
             xs, ts = x[s:s + self.buffer_rows], t[s:s + self.buffer_rows]

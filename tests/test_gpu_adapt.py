@@ -88,6 +88,10 @@ def test_screener_beats_random_subset(swcs):
     assert len(scr) >= 15
     match = np.mean([r["shadow_match"] for r in scr])
     frac = scr[0]["n_exact"] / len(pool)
-    print(f"screener match {match:.3f} vs random-subset expectation {frac:.3f}")
+    rnd = np.mean([r["random_hit"] for r in scr])
+    stale = np.mean([r["stale_hit"] for r in scr])
+    print(f"screener match {match:.3f}; same budget: random subset {rnd:.3f} "
+          f"(expectation {frac:.3f}), top by last exact |g| {stale:.3f}")
     assert match >= 0.8 and match > 5 * frac
+    assert match > rnd
     ctx.close()

@@ -151,3 +151,17 @@ def test_select_degenerate_scores(env):
             torch.cuda.synchronize()
             ref = oracle.select_subset(score, rnd, 0.05, 0.01)
             assert out.cpu().numpy().tolist() == ref.tolist(), c_i
+
+
+def test_add_feature(env):
+    """Score / target offset by one feature column, both signs, ragged length."""
+    torch, ctx = env["torch"], env["ctx"]
+    rng = np.random.default_rng(9)
+    for n in (1, 255, 1000):
+        feat = rng.normal(size=(n, 16)).astype(np.float32)
+        v0 = rng.normal(size=n).astype(np.float32)
+        for col, sign in ((10, 1), (3, -1)):
+            v = torch.from_numpy(v0.copy()).cuda()
+            ctx.add_feature(v, torch.from_numpy(feat).cuda(), col, sign)
+            torch.cuda.synchronize()
+            assert np.array_equal(v.cpu().numpy(), v0 + np.float32(sign) * feat[:, col])
