@@ -381,9 +381,13 @@ __device__ inline void tri_decode(u64 p, u64* a, u64* b) {
 //   a removed:     IA[a - 1] + IB[cnt - 1] - IB[a]
 //   a < b removed: IA[a - 1] + IB[b - 1] - IB[a] + IG[cnt - 1] - IG[b].
 // Dead entries emit the key ~0 (class bits 3, low bits above every rank).
+// With shift > 0 a record is one word instead: the key without its class in
+// the low `shift` bits (all ones for dead entries) and the entry index above
+// them, and out_val is not used.
 __global__ void __launch_bounds__(256)
 k_holepair_emit(const u64* __restrict__ keys, const double* __restrict__ amps, u64 n, int n_spatial,
-                int na, int nb, u64* __restrict__ out_key, unsigned* __restrict__ out_val) {
+                int na, int nb, int shift, u64* __restrict__ out_key, unsigned* __restrict__ out_val) {
+  const u64 rmask = shift ? (1ULL << shift) - 1ULL : 0ULL;
   const int lane = threadIdx.x & 63, half = lane >> 5, hl = lane & 31;
   const u64 r0 = (u64)na * (u64)(na - 1) / 2, r1 = (u64)na * (u64)nb, r2 = (u64)nb * (u64)(nb - 1) / 2;
   const u64 seg1 = n * r0, seg2 = n * (r0 + r1);
@@ -431,8 +435,12 @@ k_holepair_emit(const u64* __restrict__ keys, const double* __restrict__ amps, u
         if (valid) {
           const u64 r = (a > 0 ? a_lo : 0) + (b_lo - b_a) + (ig_top - g_b);
           const u64 key = cls ? (other * mul2 + r) : (r * mul0 + other);
-          out_key[base + p] = dead ? ~0ULL : (((u64)cls << kClassShift) | key);
-          out_val[base + p] = (unsigned)i;
+          if (shift) {
+            out_key[base + p] = (dead ? rmask : key) | (i << shift);
+          } else {
+            out_key[base + p] = dead ? ~0ULL : (((u64)cls << kClassShift) | key);
+            out_val[base + p] = (unsigned)i;
+          }
         }
       }
     }
@@ -448,8 +456,12 @@ k_holepair_emit(const u64* __restrict__ keys, const double* __restrict__ amps, u
       if (valid) {
         const u64 ra = (a > 0 ? aa_lo : 0) + (ib_top_a - ab);
         const u64 rb = (b > 0 ? ba_lo : 0) + (ib_top_b - bb);
-        out_key[seg1 + i * r1 + p] = dead ? ~0ULL : ((1ULL << kClassShift) | (ra * mul1 + rb));
-        out_val[seg1 + i * r1 + p] = (unsigned)i;
+        if (shift) {
+          out_key[seg1 + i * r1 + p] = (dead ? rmask : (ra * mul1 + rb)) | (i << shift);
+        } else {
+          out_key[seg1 + i * r1 + p] = dead ? ~0ULL : ((1ULL << kClassShift) | (ra * mul1 + rb));
+          out_val[seg1 + i * r1 + p] = (unsigned)i;
+        }
       }
     }
   }
@@ -466,29 +478,42 @@ k_sigma_diag(const double* __restrict__ amps, const double* __restrict__ diag, u
   }
 }
 
-// One thread per sorted record: adds H_{D X} psi(X) over the other members X
-// of its group to sigma(D).
+// Sorted records of one class segment: a full key (class in bits 60 and up)
+// with a separate entry index, or (shift > 0) one word holding the key
+// without its class in the low `shift` bits and the entry index above.
+struct HoleRecords {
+  const u64* key;
+  const unsigned* idx;
+  int shift;
+  __device__ u64 subset(u64 g) const { return shift ? key[g] & ((1ULL << shift) - 1ULL) : key[g]; }
+  __device__ u64 entry(u64 g) const { return shift ? key[g] >> shift : (u64)idx[g]; }
+  __device__ bool dead(u64 S) const { return shift ? S == (1ULL << shift) - 1ULL : S == ~0ULL; }
+};
+
+// One thread per sorted record of segment `cls`: adds H_{D X} psi(X) over
+// the other members X of its group to sigma(D).
 __global__ void __launch_bounds__(256)
-k_holepair_sigma(const u64* __restrict__ skey, const unsigned* __restrict__ sidx, u64 total,
-                 const u64* __restrict__ keys, const double* __restrict__ amps, Ints I, int na,
-                 double* __restrict__ sigma) {
+k_holepair_sigma(HoleRecords R, u64 total, int cls, const u64* __restrict__ keys,
+                 const double* __restrict__ amps, Ints I, int na, double* __restrict__ sigma) {
   const u64 stride = (u64)gridDim.x * blockDim.x;
   for (u64 g = (u64)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += stride) {
-    const u64 S = skey[g];
-    if (S == ~0ULL) continue;
-    const bool prev = g > 0 && skey[g - 1] == S;
-    const bool next = g + 1 < total && skey[g + 1] == S;
+    const u64 S = R.subset(g);
+    if (R.dead(S)) continue;
+    const bool prev = g > 0 && R.subset(g - 1) == S;
+    const bool next = g + 1 < total && R.subset(g + 1) == S;
     if (!prev && !next) continue;
     u64 lo = g;
-    while (lo > 0 && skey[lo - 1] == S) --lo;
+    while (lo > 0 && R.subset(lo - 1) == S) --lo;
     u64 hi = g + 1;
-    while (hi < total && skey[hi] == S) ++hi;
-    const u64 iD = sidx[g];
+    while (hi < total && R.subset(hi) == S) ++hi;
+    const u64 iD = R.entry(g);
     const u64 D = keys[iD];
+    // the key of the subset as subset_key forms it
+    const u64 S_full = R.shift ? (((u64)cls << kClassShift) | S) : S;
     double acc = 0.0;
     for (u64 f = lo; f < hi; ++f) {
       if (f == g) continue;
-      const u64 iX = sidx[f];
+      const u64 iX = R.entry(f);
       const u64 X = keys[iX];
       const u64 diff = D ^ X;
       const u64 holes = D & diff, parts = X & diff;
@@ -499,7 +524,7 @@ k_holepair_sigma(const u64* __restrict__ skey, const unsigned* __restrict__ sidx
         h = double_element(I, D, h0, h1, p0, p1);
       } else {
         const u64 common = D & X;
-        if (S != subset_key(common & (common - 1), I.n, na)) continue;
+        if (S_full != subset_key(common & (common - 1), I.n, na)) continue;
         h = single_element(I, D, __ffsll((long long)holes) - 1, __ffsll((long long)parts) - 1);
       }
       acc += h * amps[iX];
@@ -992,11 +1017,11 @@ hipError_t launch_sigma_proj(const DeviceState& st, const Ints& I, const ExcSpac
   return hipGetLastError();
 }
 
-hipError_t launch_holepair_emit(const DeviceState& st, u64 n, int n_spatial, int na, int nb, u64* out_key,
-                                unsigned* out_val, int grid, hipStream_t stream) {
+hipError_t launch_holepair_emit(const DeviceState& st, u64 n, int n_spatial, int na, int nb, int shift,
+                                u64* out_key, unsigned* out_val, int grid, hipStream_t stream) {
   if (na > 32 || nb > 32) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_holepair_emit, dim3(grid), dim3(256), 0, stream, st.keys, st.amps, n, n_spatial, na, nb,
-                     out_key, out_val);
+                     shift, out_key, out_val);
   return hipGetLastError();
 }
 
@@ -1008,10 +1033,12 @@ hipError_t launch_sigma_diag(const DeviceState& st, const Ints& I, u64 n, double
 }
 
 hipError_t launch_holepair_sigma(const DeviceState& st, const Ints& I, int na, const u64* skey,
-                                 const unsigned* sidx, u64 total, double* sigma, int grid,
+                                 const unsigned* sidx, int shift, u64 total, int cls, double* sigma, int grid,
                                  hipStream_t stream) {
-  hipLaunchKernelGGL(k_holepair_sigma, dim3(grid), dim3(256), 0, stream, skey, sidx, total, st.keys,
-                     st.amps, I, na, sigma);
+  if (total == 0) return hipSuccess;
+  const HoleRecords R{skey, sidx, shift};
+  hipLaunchKernelGGL(k_holepair_sigma, dim3(grid), dim3(256), 0, stream, R, total, cls, st.keys, st.amps, I, na,
+                     sigma);
   return hipGetLastError();
 }
 

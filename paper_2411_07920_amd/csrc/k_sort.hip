@@ -5,6 +5,8 @@
 // scan over (digit, tile) in digit-major order, (3) a stable scatter in which
 // each 256-item row of a tile ranks its items by wave ballots on the digit
 // bits and a prefix over the four waves.  Only ceil(key_bits / 8) passes run.
+#include <type_traits>
+
 #include "swcs_internal.h"
 
 namespace swcs {
@@ -144,6 +146,9 @@ void scan_exclusive(u64* data, u64 len, u64* sums, hipStream_t stream) {
 // The tile's digit counts come from the scanned offsets (the next tile's
 // offset, or the next digit's first offset for the last tile).  Threads below
 // 256 own one digit each in the per-digit arrays.
+// Value type of a key-only sort: no value loads, stores or LDS staging.
+struct NoVal {};
+
 template <int THREADS, int ROWS, class V>
 __global__ void __launch_bounds__(THREADS)
 k_radix_scatter(const u64* __restrict__ keys_in, const V* __restrict__ vals_in, u64 count,
@@ -157,8 +162,9 @@ k_radix_scatter(const u64* __restrict__ keys_in, const V* __restrict__ vals_in, 
   __shared__ unsigned running[256];
   __shared__ unsigned wave_cnt[2][kWaves][256];
   __shared__ unsigned wave_tot[4];
+  constexpr bool kVals = !std::is_same<V, NoVal>::value;
   __shared__ u64 s_key[kTile];
-  __shared__ V s_val[kTile];
+  __shared__ V s_val[kVals ? kTile : 1];
   const int lane = __lane_id();
   const int wave = threadIdx.x >> 6;
   const int t = threadIdx.x;
@@ -195,7 +201,7 @@ k_radix_scatter(const u64* __restrict__ keys_in, const V* __restrict__ vals_in, 
   for (int r = 0; r < ROWS; ++r) {
     const unsigned i = (unsigned)r * THREADS + t;
     key[r] = (i < tile_n) ? keys_in[tile0 + i] : 0;
-    val[r] = (vals_in && i < tile_n) ? vals_in[tile0 + i] : 0;
+    if constexpr (kVals) val[r] = (vals_in && i < tile_n) ? vals_in[tile0 + i] : V(0);
   }
 #pragma unroll
   for (int r = 0; r < ROWS; r += 2) {
@@ -230,7 +236,7 @@ k_radix_scatter(const u64* __restrict__ keys_in, const V* __restrict__ vals_in, 
         for (int w = 0; w < kWaves; ++w) pos += wave_cnt[0][w][d];
       const int rr = (r + h < ROWS) ? r + h : r;
       s_key[pos] = key[rr];
-      s_val[pos] = val[rr];
+      if constexpr (kVals) s_val[pos] = val[rr];
     }
     __syncthreads();
     if (t < 256) {
@@ -245,7 +251,8 @@ k_radix_scatter(const u64* __restrict__ keys_in, const V* __restrict__ vals_in, 
     const unsigned digit = (unsigned)((k >> shift) & 255u);
     const u64 dst = base_off[digit] + (i - local_off[digit]);
     keys_out[dst] = k;
-    if (vals_in) vals_out[dst] = s_val[i];
+    if constexpr (kVals)
+      if (vals_in) vals_out[dst] = s_val[i];
   }
 }
 
@@ -310,8 +317,9 @@ hipError_t radix_sort_impl(u64* keys, V* vals, u64* tmp_keys, V* tmp_vals, u64 c
   }
   if (kin != keys) {
     hipError_t e = hipMemcpyAsync(keys, kin, count * sizeof(u64), hipMemcpyDeviceToDevice, stream);
-    if (e == hipSuccess && vals)
-      e = hipMemcpyAsync(vals, vin, count * sizeof(V), hipMemcpyDeviceToDevice, stream);
+    if constexpr (!std::is_same<V, NoVal>::value)
+      if (e == hipSuccess && vals)
+        e = hipMemcpyAsync(vals, vin, count * sizeof(V), hipMemcpyDeviceToDevice, stream);
     if (e != hipSuccess) return e;
   }
   return hipGetLastError();
@@ -322,6 +330,14 @@ hipError_t radix_sort_pairs(u64* keys, u64* vals, u64* tmp_keys, u64* tmp_vals, 
                             u64** out_keys, u64** out_vals) {
   return radix_sort_impl<u64>(keys, vals, tmp_keys, tmp_vals, count, key_bits, scratch, scratch_elems,
                               stream, out_keys, out_vals);
+}
+
+hipError_t radix_sort_keys(u64* keys, u64* tmp_keys, u64 count, int key_bits, u64* scratch,
+                           u64 scratch_elems, hipStream_t stream, u64** out_keys) {
+  NoVal* none = nullptr;
+  NoVal* out_none = nullptr;
+  return radix_sort_impl<NoVal>(keys, none, tmp_keys, none, count, key_bits, scratch, scratch_elems, stream,
+                                out_keys, out_keys ? &out_none : nullptr);
 }
 
 hipError_t radix_sort_pairs32(u64* keys, unsigned* vals, u64* tmp_keys, unsigned* tmp_vals, u64 count,

@@ -889,33 +889,42 @@ static int energy_enqueue(swcs_ctx* c, u64 n) {
   if (n > 0 && n < (1ULL << 32) && use_holepair(c, h.alive)) {
     const int ne = c->na + c->nb;
     const u64 total = n * ((u64)ne * (u64)(ne - 1) / 2);
-    HIP_TRY(c, c->hp_key.ensure(total * 8), "alloc hole-pair keys");
-    HIP_TRY(c, c->hp_val.ensure(total * 4), "alloc hole-pair values");
-    HIP_TRY(c, c->hp_tk.ensure(total * 8), "alloc hole-pair keys");
-    HIP_TRY(c, c->hp_tv.ensure(total * 4), "alloc hole-pair values");
-    // the three class segments are sorted one by one; a short segment uses
-    // small tiles and can need more scratch than a longer one
+    // Segments of the three removal classes (alpha-alpha, alpha-beta,
+    // beta-beta), each sorted on its own on the key bits of the largest
+    // class; the dead marker's low bits are all ones, above every key.
     const u64 na = (u64)c->na, nb = (u64)c->nb;
     const u64 seg_len[3] = {n * (na * (na - 1) / 2), n * na * nb, n * (nb * (nb - 1) / 2)};
-    u64 scr = 0;
-    for (u64 len : seg_len) scr = std::max(scr, radix_sort_scratch_elems(len));
-    HIP_TRY(c, c->sort_scratch.ensure(scr * 8), "alloc sort scratch");
-    const int rg = grid_blocks(c, total, 256);
-    u64* key = c->hp_key.as<u64>();
-    unsigned* val = c->hp_val.as<unsigned>();
-    u64* tkey = c->hp_tk.as<u64>();
-    unsigned* tval = c->hp_tv.as<unsigned>();
-    HIP_TRY(c, launch_holepair_emit(c->st, n, c->n, c->na, c->nb, key, val, grid_blocks(c, n * 64, 256),
-                                    c->stream), "emit");
-    // Segments of the three removal classes (alpha-alpha, alpha-beta,
-    // beta-beta), sorted one by one on the key bits of the largest class;
-    // the dead marker's low bits are all ones, above every key.
     u64 cmax = 1;
     if (na >= 2) cmax = std::max(cmax, binomial_u64(c->n, c->na - 2) * binomial_u64(c->n, c->nb));
     if (na >= 1 && nb >= 1) cmax = std::max(cmax, binomial_u64(c->n, c->na - 1) * binomial_u64(c->n, c->nb - 1));
     if (nb >= 2) cmax = std::max(cmax, binomial_u64(c->n, c->na) * binomial_u64(c->n, c->nb - 2));
     int rank_bits = 1;
     while (rank_bits < 60 && (cmax >> rank_bits) != 0) ++rank_bits;
+    // Records are single words when key and entry index fit: the key in the
+    // low bytes that the radix passes read (rank_bits rounded up to whole
+    // digits, so no pass sees index bits), the index above.  Otherwise a
+    // 64-bit key plus a 32-bit index.
+    int idx_bits = 1;
+    while (idx_bits < 63 && ((n - 1) >> idx_bits) != 0) ++idx_bits;
+    const int digit_bits = (rank_bits + 7) / 8 * 8;
+    const int shift = (digit_bits + idx_bits <= 64) ? digit_bits : 0;
+    HIP_TRY(c, c->hp_key.ensure(total * 8), "alloc hole-pair keys");
+    HIP_TRY(c, c->hp_tk.ensure(total * 8), "alloc hole-pair keys");
+    if (!shift) {
+      HIP_TRY(c, c->hp_val.ensure(total * 4), "alloc hole-pair values");
+      HIP_TRY(c, c->hp_tv.ensure(total * 4), "alloc hole-pair values");
+    }
+    // the segments are sorted one by one; a short segment uses small tiles
+    // and can need more scratch than a longer one
+    u64 scr = 0;
+    for (u64 len : seg_len) scr = std::max(scr, radix_sort_scratch_elems(len));
+    HIP_TRY(c, c->sort_scratch.ensure(scr * 8), "alloc sort scratch");
+    u64* key = c->hp_key.as<u64>();
+    u64* tkey = c->hp_tk.as<u64>();
+    unsigned* val = shift ? nullptr : c->hp_val.as<unsigned>();
+    unsigned* tval = shift ? nullptr : c->hp_tv.as<unsigned>();
+    HIP_TRY(c, launch_holepair_emit(c->st, n, c->n, c->na, c->nb, shift, key, val, grid_blocks(c, n * 64, 256),
+                                    c->stream), "emit");
     // every segment of two or more records ends in the same buffers (same
     // pass count); a single record stays put and is copied if needed
     const bool in_tmp = ((rank_bits + 7) / 8) % 2 == 1;
@@ -924,22 +933,33 @@ static int energy_enqueue(swcs_ctx* c, u64 n) {
       const u64 len = seg_len[sgm];
       if (len >= 2) {
         u64* ok = nullptr;  // where the last pass left the segment (not copied back)
-        unsigned* ov = nullptr;
-        HIP_TRY(c, radix_sort_pairs32(key + off, val + off, tkey + off, tval + off, len, rank_bits,
-                                      c->sort_scratch.as<u64>(), scr, c->stream, &ok, &ov), "sort");
+        if (shift) {
+          HIP_TRY(c, radix_sort_keys(key + off, tkey + off, len, shift, c->sort_scratch.as<u64>(), scr,
+                                     c->stream, &ok), "sort");
+        } else {
+          unsigned* ov = nullptr;
+          HIP_TRY(c, radix_sort_pairs32(key + off, val + off, tkey + off, tval + off, len, rank_bits,
+                                        c->sort_scratch.as<u64>(), scr, c->stream, &ok, &ov), "sort");
+        }
         if (ok != (in_tmp ? tkey + off : key + off)) return fail(c, SWCS_E_DEVICE, "sort parity");
       } else if (len == 1 && in_tmp) {
         HIP_TRY(c, hipMemcpyAsync(tkey + off, key + off, 8, hipMemcpyDeviceToDevice, c->stream), "copy");
-        HIP_TRY(c, hipMemcpyAsync(tval + off, val + off, 4, hipMemcpyDeviceToDevice, c->stream), "copy");
+        if (!shift) HIP_TRY(c, hipMemcpyAsync(tval + off, val + off, 4, hipMemcpyDeviceToDevice, c->stream), "copy");
       }
       off += len;
     }
     u64* sk = in_tmp ? tkey : key;
-    unsigned* sv = in_tmp ? tval : val;
+    unsigned* sv = shift ? nullptr : (in_tmp ? tval : val);
     HIP_TRY(c, launch_sigma_diag(c->st, ints_view(c), n, c->sigma.as<double>(), grid_blocks(c, n, 256),
                                  c->stream), "diagonal sigma");
-    TIMED(c, SWCS_K_HOLEPAIR, launch_holepair_sigma(c->st, ints_view(c), c->na, sk, sv, total,
-                                                    c->sigma.as<double>(), rg, c->stream), "hole pairs");
+    off = 0;
+    for (int sgm = 0; sgm < 3; ++sgm) {
+      const u64 len = seg_len[sgm];
+      TIMED(c, SWCS_K_HOLEPAIR, launch_holepair_sigma(c->st, ints_view(c), c->na, sk + off, sv ? sv + off : nullptr,
+                                                      shift, len, sgm, c->sigma.as<double>(),
+                                                      grid_blocks(c, len, 256), c->stream), "hole pairs");
+      off += len;
+    }
     HIP_TRY(c, launch_sigma_dots(c->st, c->sigma.as<double>(), n, c->partial.as<double>(), grid, c->stream), "dots");
   } else {
     TIMED(c, SWCS_K_SIGMA_PROJ, launch_sigma_proj(c->st, ints_view(c), c->exc, n, c->sigma.as<double>(),

@@ -328,12 +328,12 @@ int pairwise_capacity();
 hipError_t launch_sigma_pairwise(const DeviceState& st, const Ints& I, u64 n, double* sigma,
                                  double* partial, int grid, hipStream_t stream);
 hipError_t launch_diag(const DeviceState& st, const Ints& I, u64 n, int grid, hipStream_t stream);
-hipError_t launch_holepair_emit(const DeviceState& st, u64 n, int n_spatial, int na, int nb, u64* out_key,
-                                unsigned* out_val, int grid, hipStream_t stream);
+hipError_t launch_holepair_emit(const DeviceState& st, u64 n, int n_spatial, int na, int nb, int shift,
+                                u64* out_key, unsigned* out_val, int grid, hipStream_t stream);
 hipError_t launch_sigma_diag(const DeviceState& st, const Ints& I, u64 n, double* sigma, int grid,
                              hipStream_t stream);
 hipError_t launch_holepair_sigma(const DeviceState& st, const Ints& I, int na, const u64* skey,
-                                 const unsigned* sidx, u64 total, double* sigma, int grid,
+                                 const unsigned* sidx, int shift, u64 total, int cls, double* sigma, int grid,
                                  hipStream_t stream);
 hipError_t launch_sigma_dots(const DeviceState& st, const double* sigma, u64 n, double* partial,
                              int grid, hipStream_t stream);
@@ -376,6 +376,9 @@ hipError_t radix_sort_pairs(u64* keys, u64* vals, u64* tmp_keys, u64* tmp_vals, 
 hipError_t radix_sort_pairs32(u64* keys, unsigned* vals, u64* tmp_keys, unsigned* tmp_vals, u64 count,
                               int key_bits, u64* scratch, u64 scratch_elems, hipStream_t stream,
                               u64** out_keys, unsigned** out_vals);
+// Keys only (no LDS or traffic for values); out_keys as above.
+hipError_t radix_sort_keys(u64* keys, u64* tmp_keys, u64 count, int key_bits, u64* scratch,
+                           u64 scratch_elems, hipStream_t stream, u64** out_keys);
 u64 radix_sort_scratch_elems(u64 count);
 u64 compact_scratch_elems(u64 n);
 

@@ -312,6 +312,29 @@ def test_sigma_hole_pairs_synthetic_state(swcs):
     ctx.close()
 
 
+def test_hole_pairs_unpacked_records(swcs):
+    """64 spin-orbitals, 8 alpha and 8 beta electrons, 1.1M determinants:
+    subset keys need 44 bits and entry indices 21, so a record cannot hold
+    both in one word and the two-array layout (key word + index word) is
+    used.  Sampled rows (the largest and random ones) against the oracle;
+    enumeration would need about 50,000 connections per determinant here."""
+    n, na = 32, 8
+    h, eri = make_integrals(n, 8, 1401)
+    pool = enumerate_pool(n)
+    keys, amps = draw_synthetic_state(n, na, na, 1_100_000, 1402)
+    ctx = swcs.make_context(n, na, na, h, eri, pool, reference_key(2 * na))
+    ctx.set_state(keys, amps)
+    ctx.set_sigma_method("hole_pairs")
+    ks, sig = ctx.sigma_projected()
+    assert np.array_equal(ks, np.sort(keys))
+    orc = oracle.Oracle(n, na, na, h, eri)
+    st = oracle.OracleState.from_arrays(keys, amps)
+    rng = np.random.default_rng(3)
+    rows = np.concatenate([np.argsort(-np.abs(sig))[:10], rng.choice(len(ks), 30, replace=False)])
+    assert np.abs(sig[rows] - orc.sigma_at(st, ks[rows])).max() < TOL
+    ctx.close()
+
+
 def test_sort_tilings_below_and_above_2_20(swcs):
     """Radix sorts switch tilings at 2^20 items.  (a) sigma_P by hole pairs on
     10,000 determinants of the 52-spin-orbital, 16-electron sector: 1.2M
