@@ -349,18 +349,6 @@ __device__ inline u64 subset_key(u64 S, int n_spatial, int na) {
   return (cls << kClassShift) | (string_rank(sa) * kBinom.v[n_spatial][cb] + string_rank(sb));
 }
 
-__device__ inline u64 shfl_u64(u64 v, int src) {
-  const unsigned lo = (unsigned)__shfl((int)(unsigned)v, src);
-  const unsigned hi = (unsigned)__shfl((int)(unsigned)(v >> 32), src);
-  return ((u64)hi << 32) | lo;
-}
-
-__device__ inline u64 shfl_up_u64(u64 v, int d) {
-  const unsigned lo = (unsigned)__shfl_up((int)(unsigned)v, d, 32);
-  const unsigned hi = (unsigned)__shfl_up((int)(unsigned)(v >> 32), d, 32);
-  return ((u64)hi << 32) | lo;
-}
-
 // Triangular index p = b (b - 1) / 2 + a, a < b.
 __device__ inline void tri_decode(u64 p, u64* a, u64* b) {
   u64 bb = (u64)((1.0 + sqrt(1.0 + 8.0 * (double)p)) * 0.5);
@@ -368,6 +356,24 @@ __device__ inline void tri_decode(u64 p, u64* a, u64* b) {
   while ((bb + 1) * bb / 2 <= p) ++bb;
   *b = bb;
   *a = p - bb * (bb - 1) / 2;
+}
+
+__device__ inline u64 readlane_u64(u64 v, int l) {
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)v, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(v >> 32), l);
+  return ((u64)hi << 32) | lo;
+}
+
+// Inclusive prefix sum over each 32-lane half of the wavefront by DPP row
+// shifts (1, 2, 4, 8 within 16-lane rows) and a broadcast of lane 15 of rows
+// 0 and 2 into rows 1 and 3.
+__device__ inline unsigned half_scan_u32(unsigned v) {
+  v += (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false);  // row_shr:1
+  v += (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false);  // row_shr:2
+  v += (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false);  // row_shr:4
+  v += (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false);  // row_shr:8
+  v += (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false);  // row_bcast:15
+  return v;
 }
 
 // One wavefront per entry; records of class 0, 1, 2 go to the segments that
@@ -380,87 +386,128 @@ __device__ inline void tri_decode(u64 p, u64* a, u64* b) {
 //   none removed:  IA[cnt - 1]
 //   a removed:     IA[a - 1] + IB[cnt - 1] - IB[a]
 //   a < b removed: IA[a - 1] + IB[b - 1] - IB[a] + IG[cnt - 1] - IG[b].
+// Every partial sum is a rank of some string of at most 32 orbitals, below
+// C(32, 16) < 2^32, so the sums are 32-bit.
 // Dead entries emit the key ~0 (class bits 3, low bits above every rank).
 // With shift > 0 a record is one word instead: the key without its class in
 // the low `shift` bits (all ones for dead entries) and the entry index above
 // them, and out_val is not used.
+// A wavefront takes `cw` (1..64) consecutive entries at a time, loaded by
+// one coalesced read (the next chunk's read is issued before this chunk's
+// work), and handles them one after another; the removed pairs of record
+// p < 64 are decoded once.
 __global__ void __launch_bounds__(256)
 k_holepair_emit(const u64* __restrict__ keys, const double* __restrict__ amps, u64 n, int n_spatial,
-                int na, int nb, int shift, u64* __restrict__ out_key, unsigned* __restrict__ out_val) {
+                int na, int nb, int shift, int cw, u64* __restrict__ out_key, unsigned* __restrict__ out_val) {
   const u64 rmask = shift ? (1ULL << shift) - 1ULL : 0ULL;
   const int lane = threadIdx.x & 63, half = lane >> 5, hl = lane & 31;
   const u64 r0 = (u64)na * (u64)(na - 1) / 2, r1 = (u64)na * (u64)nb, r2 = (u64)nb * (u64)(nb - 1) / 2;
   const u64 seg1 = n * r0, seg2 = n * (r0 + r1);
   const u64 mul0 = kBinom.v[n_spatial][nb], mul1 = kBinom.v[n_spatial][nb > 0 ? nb - 1 : 0],
             mul2 = kBinom.v[n_spatial][nb > 1 ? nb - 2 : 0];
+  // removed pairs of record p = lane (first 64 records of each class)
+  u64 ta0, tb0;
+  tri_decode((u64)lane, &ta0, &tb0);
+  const unsigned xa0 = nb > 0 ? (unsigned)lane / (unsigned)nb : 0u;
+  const unsigned xb0 = (unsigned)lane - xa0 * (unsigned)nb;
+  const u64 nchunk = (n + (u64)cw - 1) / (u64)cw;
   const u64 w0 = ((u64)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const u64 wstride = ((u64)gridDim.x * blockDim.x) >> 6;
-  for (u64 i = w0; i < n; i += wstride) {
-    const bool dead = is_dead(amps[i]);  // uniform over the wavefront
-    const u64 D = keys[i];
-    u64 x = spin_string(D, half);
-    const int cnt = half ? nb : na;
-    for (int t = 0; t < hl && x; ++t) x &= x - 1;
-    const bool mine = hl < cnt;
-    const int c = mine ? __ffsll((long long)x) - 1 : 0;
-    u64 ia = mine ? kBinom.v[c][hl + 1] : 0;
-    u64 ib = mine ? kBinom.v[c][hl] : 0;
-    u64 ig = (mine && hl >= 1) ? kBinom.v[c][hl - 1] : 0;
-    for (int d = 1; d < 32; d <<= 1) {
-      const u64 ta = shfl_up_u64(ia, d), tb = shfl_up_u64(ib, d), tg = shfl_up_u64(ig, d);
-      if (hl >= d) {
-        ia += ta;
-        ib += tb;
-        ig += tg;
-      }
+  u64 next_key = 0, next_amp = kDeadBits;
+  if (w0 < nchunk && lane < cw && w0 * cw + lane < n) {
+    next_key = keys[w0 * cw + lane];
+    next_amp = (u64)__double_as_longlong(amps[w0 * cw + lane]);
+  }
+  for (u64 ch = w0; ch < nchunk; ch += wstride) {
+    const u64 ck = next_key, ca = next_amp;
+    const u64 nx = ch + wstride;
+    if (nx < nchunk && lane < cw && nx * cw + lane < n) {
+      next_key = keys[nx * cw + lane];
+      next_amp = (u64)__double_as_longlong(amps[nx * cw + lane]);
     }
-    // whole strings and the top prefix values (uniform)
-    const u64 full_a = na > 0 ? shfl_u64(ia, na - 1) : 0, full_b = nb > 0 ? shfl_u64(ia, 32 + nb - 1) : 0;
-    const u64 ib_top_a = na > 0 ? shfl_u64(ib, na - 1) : 0, ib_top_b = nb > 0 ? shfl_u64(ib, 32 + nb - 1) : 0;
-    const u64 ig_top_a = na > 0 ? shfl_u64(ig, na - 1) : 0, ig_top_b = nb > 0 ? shfl_u64(ig, 32 + nb - 1) : 0;
-    // class 0 and 2: two electrons of one spin removed (s = 0 alpha, 32 beta)
-    for (int cls = 0; cls < 3; cls += 2) {
-      const int s = cls ? 32 : 0;
-      const u64 rc = cls ? r2 : r0, base = (cls ? seg2 : 0) + i * rc;
-      const u64 ig_top = cls ? ig_top_b : ig_top_a, other = cls ? full_a : full_b;
-      for (u64 p0 = 0; p0 < rc; p0 += 64) {
-        const u64 p = p0 + (u64)lane;
-        const bool valid = p < rc;
-        u64 a = 0, b = 1;
-        if (valid) tri_decode(p, &a, &b);
-        const u64 a_lo = shfl_u64(ia, s + (a > 0 ? (int)a - 1 : 0));
-        const u64 b_lo = shfl_u64(ib, s + (int)b - 1);
-        const u64 b_a = shfl_u64(ib, s + (int)a);
-        const u64 g_b = shfl_u64(ig, s + (int)b);
-        if (valid) {
-          const u64 r = (a > 0 ? a_lo : 0) + (b_lo - b_a) + (ig_top - g_b);
-          const u64 key = cls ? (other * mul2 + r) : (r * mul0 + other);
-          if (shift) {
-            out_key[base + p] = (dead ? rmask : key) | (i << shift);
-          } else {
-            out_key[base + p] = dead ? ~0ULL : (((u64)cls << kClassShift) | key);
-            out_val[base + p] = (unsigned)i;
+    const u64 i0 = ch * (u64)cw;
+    const int m = (int)((n - i0) < (u64)cw ? (n - i0) : (u64)cw);
+    for (int j = 0; j < m; ++j) {
+      const u64 i = i0 + (u64)j;
+      const bool dead = readlane_u64(ca, j) == kDeadBits;  // uniform
+      const u64 D = readlane_u64(ck, j);
+      u64 x = spin_string(D, half);
+      const int cnt = half ? nb : na;
+      for (int t = 0; t < hl && x; ++t) x &= x - 1;
+      const bool mine = hl < cnt;
+      const int c = mine ? __ffsll((long long)x) - 1 : 0;
+      const unsigned ia = half_scan_u32(mine ? (unsigned)kBinom.v[c][hl + 1] : 0u);
+      const unsigned ib = half_scan_u32(mine ? (unsigned)kBinom.v[c][hl] : 0u);
+      const unsigned ig = half_scan_u32((mine && hl >= 1) ? (unsigned)kBinom.v[c][hl - 1] : 0u);
+      // whole strings and the top prefix values (uniform lanes)
+      const u64 full_a = na > 0 ? (unsigned)__builtin_amdgcn_readlane((int)ia, na - 1) : 0u;
+      const u64 full_b = nb > 0 ? (unsigned)__builtin_amdgcn_readlane((int)ia, 32 + nb - 1) : 0u;
+      const unsigned ib_top_a = na > 0 ? (unsigned)__builtin_amdgcn_readlane((int)ib, na - 1) : 0u;
+      const unsigned ib_top_b = nb > 0 ? (unsigned)__builtin_amdgcn_readlane((int)ib, 32 + nb - 1) : 0u;
+      const unsigned ig_top_a = na > 0 ? (unsigned)__builtin_amdgcn_readlane((int)ig, na - 1) : 0u;
+      const unsigned ig_top_b = nb > 0 ? (unsigned)__builtin_amdgcn_readlane((int)ig, 32 + nb - 1) : 0u;
+      // class 0 and 2: two electrons of one spin removed (s = 0 alpha, 32 beta)
+      for (int cls = 0; cls < 3; cls += 2) {
+        const int s = cls ? 32 : 0;
+        const u64 rc = cls ? r2 : r0, base = (cls ? seg2 : 0) + i * rc;
+        const unsigned ig_top = cls ? ig_top_b : ig_top_a;
+        const u64 other = cls ? full_a : full_b;
+        for (u64 p0 = 0; p0 < rc; p0 += 64) {
+          const u64 p = p0 + (u64)lane;
+          const bool valid = p < rc;
+          u64 a = ta0, b = tb0;
+          if (p0 > 0) {
+            a = 0;
+            b = 1;
+            if (valid) tri_decode(p, &a, &b);
+          } else if (!valid) {
+            a = 0;
+            b = 1;
+          }
+          const unsigned a_lo = (unsigned)__shfl((int)ia, s + (a > 0 ? (int)a - 1 : 0));
+          const unsigned b_lo = (unsigned)__shfl((int)ib, s + (int)b - 1);
+          const unsigned b_a = (unsigned)__shfl((int)ib, s + (int)a);
+          const unsigned g_b = (unsigned)__shfl((int)ig, s + (int)b);
+          if (valid) {
+            const u64 r = (u64)((a > 0 ? a_lo : 0u) + (b_lo - b_a) + (ig_top - g_b));
+            const u64 key = cls ? (other * mul2 + r) : (r * mul0 + other);
+            if (shift) {
+              out_key[base + p] = (dead ? rmask : (key & rmask)) | (i << shift);
+            } else {
+              out_key[base + p] = dead ? ~0ULL : (((u64)cls << kClassShift) | key);
+              out_val[base + p] = (unsigned)i;
+            }
           }
         }
       }
-    }
-    // class 1: alpha electron a and beta electron b removed
-    for (u64 p0 = 0; p0 < r1; p0 += 64) {
-      const u64 p = p0 + (u64)lane;
-      const bool valid = p < r1;
-      const u64 a = valid ? p / (u64)nb : 0, b = valid ? p - a * (u64)nb : 0;
-      const u64 aa_lo = shfl_u64(ia, a > 0 ? (int)a - 1 : 0);
-      const u64 ab = shfl_u64(ib, (int)a);
-      const u64 ba_lo = shfl_u64(ia, 32 + (b > 0 ? (int)b - 1 : 0));
-      const u64 bb = shfl_u64(ib, 32 + (int)b);
-      if (valid) {
-        const u64 ra = (a > 0 ? aa_lo : 0) + (ib_top_a - ab);
-        const u64 rb = (b > 0 ? ba_lo : 0) + (ib_top_b - bb);
-        if (shift) {
-          out_key[seg1 + i * r1 + p] = (dead ? rmask : (ra * mul1 + rb)) | (i << shift);
-        } else {
-          out_key[seg1 + i * r1 + p] = dead ? ~0ULL : ((1ULL << kClassShift) | (ra * mul1 + rb));
-          out_val[seg1 + i * r1 + p] = (unsigned)i;
+      // class 1: alpha electron a and beta electron b removed
+      for (u64 p0 = 0; p0 < r1; p0 += 64) {
+        const u64 p = p0 + (u64)lane;
+        const bool valid = p < r1;
+        unsigned a = 0, b = 0;
+        if (valid) {
+          if (p0 == 0) {
+            a = xa0;
+            b = xb0;
+          } else {
+            a = (unsigned)p / (unsigned)nb;
+            b = (unsigned)p - a * (unsigned)nb;
+          }
+        }
+        const unsigned aa_lo = (unsigned)__shfl((int)ia, a > 0 ? (int)a - 1 : 0);
+        const unsigned ab = (unsigned)__shfl((int)ib, (int)a);
+        const unsigned ba_lo = (unsigned)__shfl((int)ia, 32 + (b > 0 ? (int)b - 1 : 0));
+        const unsigned bb = (unsigned)__shfl((int)ib, 32 + (int)b);
+        if (valid) {
+          const u64 ra = (u64)((a > 0 ? aa_lo : 0u) + (ib_top_a - ab));
+          const u64 rb = (u64)((b > 0 ? ba_lo : 0u) + (ib_top_b - bb));
+          const u64 key = ra * mul1 + rb;
+          if (shift) {
+            out_key[seg1 + i * r1 + p] = (dead ? rmask : (key & rmask)) | (i << shift);
+          } else {
+            out_key[seg1 + i * r1 + p] = dead ? ~0ULL : ((1ULL << kClassShift) | key);
+            out_val[seg1 + i * r1 + p] = (unsigned)i;
+          }
         }
       }
     }
@@ -494,7 +541,7 @@ struct HoleRecords {
 // the other members X of its group to sigma(D).
 __global__ void __launch_bounds__(256)
 k_holepair_sigma(HoleRecords R, u64 total, int cls, const u64* __restrict__ keys,
-                 const double* __restrict__ amps, Ints I, int na, double* __restrict__ sigma) {
+                 const double* __restrict__ amps, u64 n, Ints I, int na, double* __restrict__ sigma) {
   const u64 stride = (u64)gridDim.x * blockDim.x;
   for (u64 g = (u64)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += stride) {
     const u64 S = R.subset(g);
@@ -507,6 +554,7 @@ k_holepair_sigma(HoleRecords R, u64 total, int cls, const u64* __restrict__ keys
     u64 hi = g + 1;
     while (hi < total && R.subset(hi) == S) ++hi;
     const u64 iD = R.entry(g);
+    if (iD >= n) continue;  // never for records of the emit kernel
     const u64 D = keys[iD];
     // the key of the subset as subset_key forms it
     const u64 S_full = R.shift ? (((u64)cls << kClassShift) | S) : S;
@@ -514,6 +562,7 @@ k_holepair_sigma(HoleRecords R, u64 total, int cls, const u64* __restrict__ keys
     for (u64 f = lo; f < hi; ++f) {
       if (f == g) continue;
       const u64 iX = R.entry(f);
+      if (iX >= n) continue;
       const u64 X = keys[iX];
       const u64 diff = D ^ X;
       const u64 holes = D & diff, parts = X & diff;
@@ -1019,9 +1068,12 @@ hipError_t launch_sigma_proj(const DeviceState& st, const Ints& I, const ExcSpac
 
 hipError_t launch_holepair_emit(const DeviceState& st, u64 n, int n_spatial, int na, int nb, int shift,
                                 u64* out_key, unsigned* out_val, int grid, hipStream_t stream) {
-  if (na > 32 || nb > 32) return hipErrorInvalidValue;
+  if (na > 32 || nb > 32 || grid < 1) return hipErrorInvalidValue;
+  // entries per wavefront chunk: enough chunks for every wavefront of the grid
+  const u64 waves = (u64)grid * 4;
+  const int cw = (int)std::min<u64>(64, std::max<u64>(1, (n + waves - 1) / waves));
   hipLaunchKernelGGL(k_holepair_emit, dim3(grid), dim3(256), 0, stream, st.keys, st.amps, n, n_spatial, na, nb,
-                     shift, out_key, out_val);
+                     shift, cw, out_key, out_val);
   return hipGetLastError();
 }
 
@@ -1032,13 +1084,13 @@ hipError_t launch_sigma_diag(const DeviceState& st, const Ints& I, u64 n, double
   return hipGetLastError();
 }
 
-hipError_t launch_holepair_sigma(const DeviceState& st, const Ints& I, int na, const u64* skey,
+hipError_t launch_holepair_sigma(const DeviceState& st, const Ints& I, int na, u64 n, const u64* skey,
                                  const unsigned* sidx, int shift, u64 total, int cls, double* sigma, int grid,
                                  hipStream_t stream) {
   if (total == 0) return hipSuccess;
   const HoleRecords R{skey, sidx, shift};
-  hipLaunchKernelGGL(k_holepair_sigma, dim3(grid), dim3(256), 0, stream, R, total, cls, st.keys, st.amps, I, na,
-                     sigma);
+  hipLaunchKernelGGL(k_holepair_sigma, dim3(grid), dim3(256), 0, stream, R, total, cls, st.keys, st.amps, n, I,
+                     na, sigma);
   return hipGetLastError();
 }
 

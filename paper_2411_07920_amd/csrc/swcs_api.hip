@@ -955,7 +955,7 @@ static int energy_enqueue(swcs_ctx* c, u64 n) {
     off = 0;
     for (int sgm = 0; sgm < 3; ++sgm) {
       const u64 len = seg_len[sgm];
-      TIMED(c, SWCS_K_HOLEPAIR, launch_holepair_sigma(c->st, ints_view(c), c->na, sk + off, sv ? sv + off : nullptr,
+      TIMED(c, SWCS_K_HOLEPAIR, launch_holepair_sigma(c->st, ints_view(c), c->na, n, sk + off, sv ? sv + off : nullptr,
                                                       shift, len, sgm, c->sigma.as<double>(),
                                                       grid_blocks(c, len, 256), c->stream), "hole pairs");
       off += len;

@@ -332,7 +332,7 @@ hipError_t launch_holepair_emit(const DeviceState& st, u64 n, int n_spatial, int
                                 u64* out_key, unsigned* out_val, int grid, hipStream_t stream);
 hipError_t launch_sigma_diag(const DeviceState& st, const Ints& I, u64 n, double* sigma, int grid,
                              hipStream_t stream);
-hipError_t launch_holepair_sigma(const DeviceState& st, const Ints& I, int na, const u64* skey,
+hipError_t launch_holepair_sigma(const DeviceState& st, const Ints& I, int na, u64 n, const u64* skey,
                                  const unsigned* sidx, int shift, u64 total, int cls, double* sigma, int grid,
                                  hipStream_t stream);
 hipError_t launch_sigma_dots(const DeviceState& st, const double* sigma, u64 n, double* partial,
