@@ -93,7 +93,8 @@ int swcs_set_capacity(swcs_ctx* ctx, int64_t max_dets);
 /* How sigma_P (energy, parameter gradients) is formed.  ENUMERATE probes
  * every single and double excitation of every alive determinant (alive * C
  * probes).  HOLE_PAIRS groups the determinants by their subsets of N_e - 2
- * electrons (a sort of n * C(N_e, 2) 12-byte records) and evaluates only
+ * electrons (a sort of n * C(N_e, 2) records of 8 bytes, or 12 when the
+ * subset key and the entry index do not fit one word) and evaluates only
  * pairs that share one, which are exactly the pairs within a double
  * excitation; it needs fewer than 2^32 stored entries (larger states use
  * ENUMERATE).  PAIRS
