@@ -58,6 +58,13 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy a 1 GiB device buffer five times (reference kernel for the "
                          "FETCH_SIZE / WRITE_SIZE counters)")
+    ap.add_argument("--uccsd", default=None, choices=sorted(CONFIGS),
+                    help="instead of the step benchmark: MP2-ordered UCCSD on this workload "
+                         "(ansatz build, energy + adjoint gradient evaluation, L-BFGS steps)")
+    ap.add_argument("--eps", type=float, default=None,
+                    help="pruning threshold for --uccsd (default: the workload's)")
+    ap.add_argument("--vqe-iters", type=int, default=20,
+                    help="L-BFGS iterations for --uccsd")
     ap.add_argument("--micro", type=int, default=0,
                     help="instead of the step benchmark: gate and sigma kernels on a synthetic "
                          "state of this many determinants (52 spin-orbitals, 16 electrons)")
@@ -441,6 +448,63 @@ def large_state_bench(N, sigma=True):
     return out
 
 
+def uccsd_bench(args):
+    """MP2-ordered UCCSD (Sec. II.A) on one workload: the ansatz from the
+    library's pool gradients at the reference and its Fock diagonal (doubles by
+    decreasing MP2 amplitude, then singles), the time of one energy + adjoint
+    gradient evaluation at the MP2 parameters (apply of the whole ansatz with
+    pruning, sigma_P, reverse sweep; mean of three after one untimed), and the
+    energy after each of up to --vqe-iters L-BFGS iterations."""
+    import torch
+    from paper_2411_07920_amd import adapt, swcs, uccsd
+
+    torch.cuda.set_device(0)
+    wl = Workload(args.uccsd)
+    c = wl.c
+    eps = c.eps if args.eps is None else args.eps
+    ctx = swcs.make_context(c.n, wl.na, wl.na, wl.h, wl.eri, wl.pool, wl.ref,
+                            stream=torch.cuda.current_stream())
+    t = time.perf_counter()
+    ans = uccsd.mp2_ordered_uccsd(ctx, wl.pool, wl.ref, c.n)
+    t_build = time.perf_counter() - t
+    print(f"[uccsd] {args.uccsd}: {len(ans.ops)} operators ({ans.n_doubles} doubles), "
+          f"E_ref {ans.e_ref:.10f}, E2 {ans.e2:.10f}, build {t_build:.3f} s", file=sys.stderr, flush=True)
+    n_det = ctx.apply_ansatz(ans.ops, ans.theta, eps)
+    f = adapt.Energy(ctx, ans.ops, eps, 0)
+    E0, _ = f(ans.theta)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(3):
+        f(ans.theta)
+    torch.cuda.synchronize()
+    t_eval = (time.perf_counter() - t) / 3
+    print(f"[uccsd] {n_det} determinants, E(MP2 parameters) {E0:.10f}, "
+          f"{1e3 * t_eval:.1f} ms per energy + gradient", file=sys.stderr, flush=True)
+    cfg = adapt.AdaptConfig(eps=eps, optimizer="lbfgs", vqe_maxiter=args.vqe_iters)
+
+    def log(r):
+        print(f"[uccsd] L-BFGS step {r['step']}: E {r['E']:.10f}", file=sys.stderr, flush=True)
+
+    t = time.perf_counter()
+    theta, E, trace, evals = adapt.preoptimize(ctx, ans.ops, ans.theta, cfg, log=log)
+    t_vqe = time.perf_counter() - t
+    n_final = ctx.apply_ansatz(ans.ops, theta, eps)
+    out = {
+        "metric": "MP2-ordered UCCSD: energy + adjoint gradient evaluation time and VQE energies",
+        "workload": f"{args.uccsd}: {c.n_so} spin-orbitals, {c.n_elec} electrons, eps={eps:g}, "
+                    f"{len(ans.ops)} operators ({ans.n_doubles} doubles, {ans.n_singles} singles)",
+        "e_ref": ans.e_ref, "e2": ans.e2, "e_mp2": ans.e_ref + ans.e2,
+        "ansatz_build_s": t_build,
+        "E_mp2_parameters": E0, "n_det_mp2_parameters": int(n_det),
+        "eval_ms": 1e3 * t_eval,
+        "vqe": {"iterations": len(trace), "evaluations": evals, "wall_s": t_vqe,
+                "energy_per_step": trace, "E_final": E, "n_det_final": int(n_final)},
+    }
+    print(json.dumps(out))
+    ctx.close()
+    return out
+
+
 def micro_bench(args):
     out = large_state_bench(args.micro)
     out["metric"] = "kernel rates on a synthetic state"
@@ -500,6 +564,9 @@ def main():
         sys.exit(2)
     if args.adapt:
         adapt_bench(args)
+        return
+    if args.uccsd:
+        uccsd_bench(args)
         return
     if args.micro:
         micro_bench(args)

@@ -188,6 +188,14 @@ int swcs_gate_sizes(swcs_ctx* ctx, int64_t* n_in, int64_t M);
  * current state, n_out[2n] (host). */
 int swcs_occupations(swcs_ctx* ctx, double* n_out);
 
+/* Diagonal of the closed-shell Fock matrix of the reference occupation,
+ * f_pp = h_pp + sum_{j < n_alpha} [2 (pp|jj) - (pj|jp)], for the n spatial
+ * orbitals, f_out[n] (host).  These are the orbital energies of the
+ * Moller-Plesset partition that orders the UCCSD ansatz (Sec. II.A) with
+ * H0 = sum_P f_{P/2,P/2} n_P.  Needs integrals; SWCS_E_UNSUPPORTED when
+ * n_alpha != n_beta (no closed-shell reference). */
+int swcs_fock_diagonal(swcs_ctx* ctx, double* f_out);
+
 /* ---- measurement ---- */
 
 /* Kernels that swcs_timer_start can time. */

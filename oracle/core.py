@@ -22,6 +22,8 @@ param_gradients             central FD (eps = 0); trigonometric 5-point fit;
                             last-parameter identity; masked FD (eps > 0)
 mlp_forward / mlp_backward  finite differences in float64
 features / select_subset    parity unpinned beyond hand-computed small cases
+mp2_uccsd                   closed-shell spatial MP2 energy formula; first-
+                            order coefficients of the dense Hamiltonian
 ==========================  ===================================================
 """
 from __future__ import annotations
@@ -35,7 +37,7 @@ import numpy as np
 __all__ = [
     "build", "load", "Oracle", "OracleState",
     "mlp_init", "mlp_forward", "mlp_backward", "mlp_loss_grad", "adam_step",
-    "fock_spatial", "features", "select_subset", "N_PARAMS", "LAYOUT",
+    "fock_spatial", "features", "select_subset", "mp2_uccsd", "N_PARAMS", "LAYOUT",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -401,3 +403,77 @@ def select_subset(score, rand_key, frac_top=0.05, frac_rand=0.01):
     rest.sort(key=lambda k: (int(rand_key[k]), k))
     chosen = sorted(top | set(rest[:n_rand]))
     return np.array(chosen, dtype=np.int32)
+
+
+def mp2_uccsd(orc, pool, ref, rel_tol=1e-9):
+    """MP2-ordered UCCSD ansatz of a closed-shell reference (Sec. II.A, Eqs. 1-3).
+
+    Zeroth-order Hamiltonian: H0 = sum_P f_{P/2, P/2} n_P with f the
+    closed-shell Fock matrix of the reference (fock_spatial), so every
+    determinant is an eigenvector of H0 with E0(D) = sum of f_pp over its
+    spin-orbitals.  The first-order coefficient of a doubly excited D is
+    t_D = <D|H|ref> / (E0(ref) - E0(D)) and the MP2 energy is
+    E2 = sum_D <D|H|ref>^2 / (E0(ref) - E0(D)) over the doubles.  The pool
+    operator k whose generator takes ref to D (A_k|ref> = s_k|D>, s_k = +-1,
+    either orientation of T_k) gets theta_k = s_k t_D, so that
+    exp(theta_k A_k)|ref> equals ref + t_D D to first order.  Singles get 0
+    (the paper's MP2 has no single amplitudes).
+
+    Order (index 0 is applied first): doubles by decreasing |theta| (values
+    within rel_tol * max |theta| of the first of a run count as equal and go
+    by pool index), then the singles by ascending (occupied, virtual)
+    spin-orbital.  Returns (ops int32, theta float64, e2)."""
+    if orc.n_alpha != orc.n_beta:
+        raise ValueError("closed-shell reference needed")
+    f = np.diag(fock_spatial(orc._h_arr, orc._eri_arr, orc.n_alpha))
+    nso = 2 * orc.n
+    ref = int(ref)
+    occ = {P for P in range(nso) if (ref >> P) & 1}
+
+    def e0(key):
+        return sum(f[P >> 1] for P in range(nso) if (key >> P) & 1)
+
+    ref_state = OracleState.from_arrays(np.array([ref], dtype=np.uint64), np.array([1.0]))
+    doubles, singles, e2 = [], [], 0.0
+    for k, row in enumerate(np.asarray(pool).tolist()):
+        P, Q, R, S = row
+        cre = [P, Q] if R >= 0 else [P]
+        ann = [R, S] if R >= 0 else [Q]
+        fwd = all(a in occ for a in ann) and not any(c in occ for c in cre)
+        rev = all(c in occ for c in cre) and not any(a in occ for a in ann)
+        if not (fwd or rev):
+            continue
+        o, v = (ann, cre) if fwd else (cre, ann)
+        if R < 0:
+            singles.append((o[0], v[0], k))
+            continue
+        D = ref
+        for x in o + v:
+            D ^= 1 << x
+        keys, amps = Oracle.apply_generator(ref_state, np.asarray(row)).export()
+        hit = np.flatnonzero(keys == np.uint64(D))
+        if len(hit) != 1 or abs(abs(amps[hit[0]]) - 1.0) > 0.0:
+            raise AssertionError("generator does not take the reference to D")
+        s = float(amps[hit[0]])
+        hDr = orc.hmat(D, ref)
+        dE = e0(ref) - e0(D)
+        doubles.append((s * hDr / dE, k))
+        e2 += hDr * hDr / dE
+    # doubles: |theta| descending, near-equal runs by pool index
+    a = {k: abs(t) for t, k in doubles}
+    theta_of = {k: t for t, k in doubles}
+    order = sorted(a, key=lambda k: (-a[k], k))
+    tol = rel_tol * (max(a.values()) if a else 0.0)
+    ops = []
+    i = 0
+    while i < len(order):
+        j = i + 1
+        while j < len(order) and a[order[i]] - a[order[j]] <= tol:
+            j += 1
+        ops += sorted(order[i:j])
+        i = j
+    theta = [theta_of[k] for k in ops]
+    for _, _, k in sorted(singles):
+        ops.append(k)
+        theta.append(0.0)
+    return np.array(ops, dtype=np.int32), np.array(theta, dtype=np.float64), e2

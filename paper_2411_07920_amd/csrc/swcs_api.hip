@@ -1395,6 +1395,21 @@ int swcs_timer_stop(swcs_ctx* c, int64_t* launches, double* total_ms) {
 
 int64_t swcs_mlp_param_count(void) { return kMlpParams; }
 
+int swcs_fock_diagonal(swcs_ctx* c, double* f_out) {
+  if (!c) return SWCS_E_INVALID;
+  if (!c->have_ints) return fail(c, SWCS_E_STATE, "integrals not set");
+  if (!f_out) return fail(c, SWCS_E_INVALID, "null f_out");
+  if (c->na != c->nb) return fail(c, SWCS_E_UNSUPPORTED, "closed-shell Fock needs n_alpha == n_beta");
+  HIP_TRY(c, hipSetDevice(c->device), "hipSetDevice");
+  const int n = c->n;
+  std::vector<double> f((size_t)n * n);
+  HIP_TRY(c, hipMemcpyAsync(f.data(), c->fock.p, f.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream),
+          "copy");
+  HIP_TRY(c, hipStreamSynchronize(c->stream), "sync");
+  for (int p = 0; p < n; ++p) f_out[p] = f[(size_t)p * n + p];
+  return SWCS_OK;
+}
+
 int swcs_features(swcs_ctx* c, const float* d_prev_absg, const float* d_age, const float* d_count,
                   float* d_feat) {
   if (!c) return SWCS_E_INVALID;

@@ -73,6 +73,7 @@ SIGNATURES = {
     "swcs_param_gradients": (ctypes.c_int, [_vp, _dp, _dp]),
     "swcs_gate_sizes": (ctypes.c_int, [_vp, _i64p, _i64]),
     "swcs_occupations": (ctypes.c_int, [_vp, _dp]),
+    "swcs_fock_diagonal": (ctypes.c_int, [_vp, _dp]),
     "swcs_timer_start": (ctypes.c_int, [_vp, ctypes.c_int]),
     "swcs_timer_stop": (ctypes.c_int, [_vp, _i64p, _dp]),
     "swcs_mlp_param_count": (ctypes.c_int64, []),
@@ -290,6 +291,12 @@ class Context:
     def occupations(self):
         out = np.zeros(2 * self.n)
         self._check(self._lib.swcs_occupations(self._h, _ptr(out, ctypes.c_double)))
+        return out
+
+    def fock_diagonal(self):
+        """Closed-shell Fock diagonal f_pp of the n spatial orbitals."""
+        out = np.zeros(self.n)
+        self._check(self._lib.swcs_fock_diagonal(self._h, _ptr(out, ctypes.c_double)))
         return out
 
     # -- measurement ----------------------------------------------------
