@@ -65,6 +65,12 @@ def parse():
                     help="pruning threshold for --uccsd (default: the workload's)")
     ap.add_argument("--vqe-iters", type=int, default=20,
                     help="L-BFGS iterations for --uccsd")
+    ap.add_argument("--preopt", default=None, choices=sorted(CONFIGS),
+                    help="instead of the step benchmark: classical pre-optimization (L-BFGS with "
+                         "adjoint gradients) of this workload's fixed ansatz at its eps and at "
+                         "--ref-eps")
+    ap.add_argument("--ref-eps", type=float, default=1e-8,
+                    help="reference pruning threshold for --preopt")
     ap.add_argument("--micro", type=int, default=0,
                     help="instead of the step benchmark: gate and sigma kernels on a synthetic "
                          "state of this many determinants (52 spin-orbitals, 16 electrons)")
@@ -448,6 +454,69 @@ def large_state_bench(N, sigma=True):
     return out
 
 
+def preopt_bench(args):
+    """Classical pre-optimization of a fixed ansatz (the workload's operators
+    and starting angles): L-BFGS over all parameters with adjoint gradients
+    and sqrt(M) checkpoints, at the workload's eps and at --ref-eps, up to
+    --vqe-iters iterations each.  Reports the energy after every optimizer
+    step, the state size and the time per energy + gradient evaluation (mean
+    of three at the starting angles after one untimed), and the error of the
+    eps run against the --ref-eps run: final energies, and the eps optimum
+    re-evaluated at --ref-eps."""
+    import torch
+    from paper_2411_07920_amd import adapt, swcs
+
+    torch.cuda.set_device(0)
+    wl = Workload(args.preopt)
+    c = wl.c
+    ctx = swcs.make_context(c.n, wl.na, wl.na, wl.h, wl.eri, wl.pool, wl.ref,
+                            stream=torch.cuda.current_stream())
+    runs = {}
+    for eps in (c.eps if args.eps is None else args.eps, args.ref_eps):
+        n_det = ctx.apply_ansatz(wl.ops, wl.theta, eps)
+        _, E0 = ctx.param_gradients(len(wl.ops))
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(3):
+            ctx.apply_ansatz(wl.ops, wl.theta, eps)
+            ctx.param_gradients(len(wl.ops))
+        torch.cuda.synchronize()
+        t_eval = (time.perf_counter() - t) / 3
+        print(f"[preopt eps={eps:g}] {n_det} determinants at the starting angles, E {E0:.10f}, "
+              f"{1e3 * t_eval:.1f} ms per energy + gradient", file=sys.stderr, flush=True)
+        cfg = adapt.AdaptConfig(eps=eps, optimizer="lbfgs", vqe_maxiter=args.vqe_iters)
+
+        def log(r, eps=eps):
+            print(f"[preopt eps={eps:g}] L-BFGS step {r['step']}: E {r['E']:.10f}", file=sys.stderr,
+                  flush=True)
+
+        t = time.perf_counter()
+        theta, E, trace, evals = adapt.preoptimize(ctx, wl.ops, wl.theta, cfg, log=log)
+        wall = time.perf_counter() - t
+        n_final = ctx.apply_ansatz(wl.ops, theta, eps)
+        runs[eps] = {"eps": eps, "n_det_start": int(n_det), "E_start": E0, "eval_ms": 1e3 * t_eval,
+                     "iterations": len(trace), "evaluations": evals, "wall_s": wall,
+                     "energy_per_step": trace, "E_final": E, "n_det_final": int(n_final),
+                     "theta": theta}
+    e_main, e_ref = list(runs)
+    ctx.apply_ansatz(wl.ops, runs[e_main]["theta"], e_ref)
+    E_cross = ctx.energy()[0]
+    for r in runs.values():
+        r.pop("theta")
+    out = {
+        "metric": "classical pre-optimization: energy per L-BFGS step and time per energy + gradient",
+        "workload": f"{args.preopt}: {c.n_so} spin-orbitals, {c.n_elec} electrons, {len(wl.ops)}-operator "
+                    f"ansatz, theta0 in [{c.theta_lo:g}, {c.theta_hi:g}], L-BFGS with adjoint gradients",
+        "runs": list(runs.values()),
+        "E_final_minus_ref_run": runs[e_main]["E_final"] - runs[e_ref]["E_final"],
+        "eps_optimum_at_ref_eps": E_cross,
+        "eps_optimum_at_ref_eps_minus_ref_run": E_cross - runs[e_ref]["E_final"],
+    }
+    print(json.dumps(out))
+    ctx.close()
+    return out
+
+
 def uccsd_bench(args):
     """MP2-ordered UCCSD (Sec. II.A) on one workload: the ansatz from the
     library's pool gradients at the reference and its Fock diagonal (doubles by
@@ -470,12 +539,12 @@ def uccsd_bench(args):
     print(f"[uccsd] {args.uccsd}: {len(ans.ops)} operators ({ans.n_doubles} doubles), "
           f"E_ref {ans.e_ref:.10f}, E2 {ans.e2:.10f}, build {t_build:.3f} s", file=sys.stderr, flush=True)
     n_det = ctx.apply_ansatz(ans.ops, ans.theta, eps)
-    f = adapt.Energy(ctx, ans.ops, eps, 0)
-    E0, _ = f(ans.theta)
+    _, E0 = ctx.param_gradients(len(ans.ops))
     torch.cuda.synchronize()
     t = time.perf_counter()
     for _ in range(3):
-        f(ans.theta)
+        ctx.apply_ansatz(ans.ops, ans.theta, eps)
+        ctx.param_gradients(len(ans.ops))
     torch.cuda.synchronize()
     t_eval = (time.perf_counter() - t) / 3
     print(f"[uccsd] {n_det} determinants, E(MP2 parameters) {E0:.10f}, "
@@ -506,7 +575,9 @@ def uccsd_bench(args):
 
 
 def micro_bench(args):
-    out = large_state_bench(args.micro)
+    # above 32M determinants the hole-pair records (and their sort buffer) no
+    # longer fit beside the state, and enumeration would take minutes
+    out = large_state_bench(args.micro, sigma=args.micro <= 32_000_000)
     out["metric"] = "kernel rates on a synthetic state"
     print(json.dumps(out))
 
@@ -567,6 +638,9 @@ def main():
         return
     if args.uccsd:
         uccsd_bench(args)
+        return
+    if args.preopt:
+        preopt_bench(args)
         return
     if args.micro:
         micro_bench(args)

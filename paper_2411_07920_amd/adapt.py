@@ -53,19 +53,27 @@ class AdaptConfig:
 
 
 class Energy:
-    """E(theta) and dE/dtheta of a fixed operator list on a context."""
+    """E(theta) and dE/dtheta of a fixed operator list on a context.  A call
+    at exactly the angles of the previous call returns its result without
+    touching the context, whose current state is then still the one at
+    those angles (optimizer callbacks re-query the accepted point)."""
 
     def __init__(self, ctx, ops, eps, ncut):
         self.ctx, self.ops, self.eps, self.ncut = ctx, np.asarray(ops, dtype=np.int32), eps, ncut
         self.evals = 0
         self.time = 0.0
+        self._last = None
 
     def __call__(self, theta):
+        theta = np.array(theta, dtype=np.float64)
+        if self._last is not None and np.array_equal(theta, self._last[0]):
+            return self._last[1], self._last[2].copy()
         t = time.perf_counter()
-        self.ctx.apply_ansatz(self.ops, np.asarray(theta, dtype=np.float64), self.eps, self.ncut)
+        self.ctx.apply_ansatz(self.ops, theta, self.eps, self.ncut)
         dE, E = self.ctx.param_gradients(len(self.ops))
         self.evals += 1
         self.time += time.perf_counter() - t
+        self._last = (theta, E, np.array(dE))
         return E, dE
 
 
