@@ -19,6 +19,17 @@ constexpr int kSortTile = kSortThreads * kSortRows;
 // tiles, shorter serial row loop per tile).
 inline int sort_rows(u64 count) { return count < (1ULL << 20) ? 1 : kSortRows; }
 
+// Tile handled by workgroup `block` of `nblocks`: workgroups are dispatched to
+// the eight XCDs in turn, so XCD x (blocks x, x + 8, ...) is given a
+// contiguous range of tiles.  Neighbouring tiles write neighbouring pieces of
+// each digit's output run (scatter) and neighbouring counts of each digit
+// (histogram), and these then meet in the same L2.
+__device__ inline u64 xcd_tile(u64 block, u64 nblocks) {
+  const u64 x = block & 7u, k = block >> 3;
+  const u64 q = nblocks >> 3, r = nblocks & 7u;
+  return x * q + (x < r ? x : r) + k;
+}
+
 template <int ROWS>
 __global__ void __launch_bounds__(kSortThreads)
 k_radix_hist(const u64* __restrict__ keys, u64 count, int shift, u64* __restrict__ counts,
@@ -26,13 +37,14 @@ k_radix_hist(const u64* __restrict__ keys, u64 count, int shift, u64* __restrict
   __shared__ unsigned hist[256];
   hist[threadIdx.x] = 0;
   __syncthreads();
-  const u64 base = (u64)blockIdx.x * (kSortThreads * ROWS);
+  const u64 b = xcd_tile(blockIdx.x, (u64)nblocks);
+  const u64 base = b * (kSortThreads * ROWS);
   for (int r = 0; r < ROWS; ++r) {
     const u64 i = base + (u64)r * kSortThreads + threadIdx.x;
     if (i < count) atomicAdd(&hist[(keys[i] >> shift) & 255u], 1u);
   }
   __syncthreads();
-  counts[(u64)threadIdx.x * nblocks + blockIdx.x] = hist[threadIdx.x];
+  counts[(u64)threadIdx.x * nblocks + b] = hist[threadIdx.x];
 }
 
 // Exclusive scans.  Tiles of kScanChunk elements are loaded coalesced into
@@ -168,7 +180,7 @@ k_radix_scatter(const u64* __restrict__ keys_in, const V* __restrict__ vals_in, 
   const int lane = __lane_id();
   const int wave = threadIdx.x >> 6;
   const int t = threadIdx.x;
-  const u64 b = blockIdx.x;
+  const u64 b = xcd_tile(blockIdx.x, (u64)nblocks);
   // digit counts of the tile and their exclusive scan (waves 0-3 hold the
   // 256 digits; a wavefront scan, then the wave totals)
   unsigned cnt = 0, incl = 0;
@@ -203,13 +215,15 @@ k_radix_scatter(const u64* __restrict__ keys_in, const V* __restrict__ vals_in, 
     key[r] = (i < tile_n) ? keys_in[tile0 + i] : 0;
     if constexpr (kVals) val[r] = (vals_in && i < tile_n) ? vals_in[tile0 + i] : V(0);
   }
+  // wave_cnt entries hold either a count of row pair p tagged (p + 1) << 16
+  // or an offset tagged 0xffff << 16, so a stale count is never taken for a
+  // current one and the table needs no clearing between pairs.
+  if (t < 256)
+    for (int w = 0; w < kWaves; ++w) wave_cnt[0][w][t] = wave_cnt[1][w][t] = 0xffff0000u;
+  __syncthreads();
 #pragma unroll
   for (int r = 0; r < ROWS; r += 2) {
-    // column t is cleared by the thread that summed it at the end of the
-    // previous pair of rows
-    if (t < 256)
-      for (int w = 0; w < kWaves; ++w) wave_cnt[0][w][t] = wave_cnt[1][w][t] = 0;
-    __syncthreads();
+    const unsigned tag = (unsigned)(r / 2 + 1) << 16;
     bool valid[2];
     unsigned digit[2], below[2];
 #pragma unroll
@@ -223,27 +237,32 @@ k_radix_scatter(const u64* __restrict__ keys_in, const V* __restrict__ vals_in, 
         peers &= ((digit[h] >> bit) & 1u) ? m : ~m;
       }
       below[h] = (unsigned)__popcll(peers & ((1ULL << lane) - 1ULL));
-      if (valid[h] && below[h] == 0) wave_cnt[h][wave][digit[h]] = (unsigned)__popcll(peers);
+      if (valid[h] && below[h] == 0) wave_cnt[h][wave][digit[h]] = tag | (unsigned)__popcll(peers);
+    }
+    __syncthreads();
+    // column t (digit t): counts in (row, wave) order become the exclusive
+    // positions of each (row, wave) run in the reordered tile
+    if (t < 256) {
+      const unsigned start = local_off[t] + running[t];
+      unsigned at = start;
+      for (int h = 0; h < 2; ++h)
+        for (int w = 0; w < kWaves; ++w) {
+          const unsigned v = wave_cnt[h][w][t];
+          wave_cnt[h][w][t] = 0xffff0000u | at;
+          at += ((v & 0xffff0000u) == tag) ? (v & 0xffffu) : 0u;
+        }
+      running[t] += at - start;
     }
     __syncthreads();
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       if (!valid[h]) continue;
-      const unsigned d = digit[h];
-      unsigned pos = local_off[d] + running[d] + below[h];
-      for (int w = 0; w < wave; ++w) pos += wave_cnt[h][w][d];
-      if (h == 1)
-        for (int w = 0; w < kWaves; ++w) pos += wave_cnt[0][w][d];
+      const unsigned pos = (wave_cnt[h][wave][digit[h]] & 0xffffu) + below[h];
       const int rr = (r + h < ROWS) ? r + h : r;
       s_key[pos] = key[rr];
       if constexpr (kVals) s_val[pos] = val[rr];
     }
-    __syncthreads();
-    if (t < 256) {
-      unsigned add = 0;
-      for (int w = 0; w < kWaves; ++w) add += wave_cnt[0][w][t] + wave_cnt[1][w][t];
-      running[t] += add;
-    }
+    __syncthreads();  // positions are read before the next pair's counts land
   }
   __syncthreads();
   for (unsigned i = t; i < tile_n; i += THREADS) {
