@@ -410,6 +410,12 @@ k_holepair_emit(const u64* __restrict__ keys, const double* __restrict__ amps, u
   tri_decode((u64)lane, &ta0, &tb0);
   const unsigned xa0 = nb > 0 ? (unsigned)lane / (unsigned)nb : 0u;
   const unsigned xb0 = (unsigned)lane - xa0 * (unsigned)nb;
+  // C(m, k) for the m < 32 orbitals and k <= 33 the prefix terms use, in LDS
+  // (all below 2^32), so that the three lookups of a determinant are issued
+  // together
+  __shared__ unsigned sbin[32 * 34];
+  for (int t = threadIdx.x; t < 32 * 34; t += blockDim.x) sbin[t] = (unsigned)kBinom.v[t / 34][t % 34];
+  __syncthreads();
   const u64 nchunk = (n + (u64)cw - 1) / (u64)cw;
   const u64 w0 = ((u64)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const u64 wstride = ((u64)gridDim.x * blockDim.x) >> 6;
@@ -436,9 +442,11 @@ k_holepair_emit(const u64* __restrict__ keys, const double* __restrict__ amps, u
       for (int t = 0; t < hl && x; ++t) x &= x - 1;
       const bool mine = hl < cnt;
       const int c = mine ? __ffsll((long long)x) - 1 : 0;
-      const unsigned ia = half_scan_u32(mine ? (unsigned)kBinom.v[c][hl + 1] : 0u);
-      const unsigned ib = half_scan_u32(mine ? (unsigned)kBinom.v[c][hl] : 0u);
-      const unsigned ig = half_scan_u32((mine && hl >= 1) ? (unsigned)kBinom.v[c][hl - 1] : 0u);
+      const unsigned* row = sbin + c * 34;
+      const unsigned va = row[hl + 1], vb = row[hl], vg = row[hl >= 1 ? hl - 1 : 0];
+      const unsigned ia = half_scan_u32(mine ? va : 0u);
+      const unsigned ib = half_scan_u32(mine ? vb : 0u);
+      const unsigned ig = half_scan_u32((mine && hl >= 1) ? vg : 0u);
       // whole strings and the top prefix values (uniform lanes)
       const u64 full_a = na > 0 ? (unsigned)__builtin_amdgcn_readlane((int)ia, na - 1) : 0u;
       const u64 full_b = nb > 0 ? (unsigned)__builtin_amdgcn_readlane((int)ia, 32 + nb - 1) : 0u;
