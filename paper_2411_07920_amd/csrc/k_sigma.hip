@@ -546,17 +546,20 @@ struct HoleRecords {
 };
 
 // One thread per sorted record of segment `cls`: adds H_{D X} psi(X) over
-// the other members X of its group to sigma(D).
+// the other members X of its group to sigma(D).  The record and both
+// neighbours are loaded before any test (clamped at the ends), so a record
+// that is a group of one -- nearly all of them -- costs one round trip.
 __global__ void __launch_bounds__(256)
 k_holepair_sigma(HoleRecords R, u64 total, int cls, const u64* __restrict__ keys,
                  const double* __restrict__ amps, u64 n, Ints I, int na, double* __restrict__ sigma) {
   const u64 stride = (u64)gridDim.x * blockDim.x;
   for (u64 g = (u64)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += stride) {
     const u64 S = R.subset(g);
-    if (R.dead(S)) continue;
-    const bool prev = g > 0 && R.subset(g - 1) == S;
-    const bool next = g + 1 < total && R.subset(g + 1) == S;
-    if (!prev && !next) continue;
+    const u64 Sp = R.subset(g > 0 ? g - 1 : g);
+    const u64 Sn = R.subset(g + 1 < total ? g + 1 : g);
+    const bool prev = (g > 0) & (Sp == S);
+    const bool next = (g + 1 < total) & (Sn == S);
+    if (!(!R.dead(S) & (prev | next))) continue;  // bitwise: no test before the loads
     u64 lo = g;
     while (lo > 0 && R.subset(lo - 1) == S) --lo;
     u64 hi = g + 1;
