@@ -547,16 +547,26 @@ struct HoleRecords {
 
 // One thread per sorted record of segment `cls`: adds H_{D X} psi(X) over
 // the other members X of its group to sigma(D).  The record and both
-// neighbours are loaded before any test (clamped at the ends), so a record
-// that is a group of one -- nearly all of them -- costs one round trip.
+// neighbours are loaded before any test (clamped at the ends), one grid
+// stride ahead, so a record that is a group of one -- nearly all of them --
+// costs less than one round trip.
 __global__ void __launch_bounds__(256)
 k_holepair_sigma(HoleRecords R, u64 total, int cls, const u64* __restrict__ keys,
                  const double* __restrict__ amps, u64 n, Ints I, int na, double* __restrict__ sigma) {
   const u64 stride = (u64)gridDim.x * blockDim.x;
-  for (u64 g = (u64)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += stride) {
-    const u64 S = R.subset(g);
-    const u64 Sp = R.subset(g > 0 ? g - 1 : g);
-    const u64 Sn = R.subset(g + 1 < total ? g + 1 : g);
+  const u64 g0 = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+  u64 nS = 0, nSp = 0, nSn = 0;  // the next record's three words, loaded one step ahead
+  if (g0 < total) {
+    nS = R.subset(g0);
+    nSp = R.subset(g0 > 0 ? g0 - 1 : g0);
+    nSn = R.subset(g0 + 1 < total ? g0 + 1 : g0);
+  }
+  for (u64 g = g0; g < total; g += stride) {
+    const u64 S = nS, Sp = nSp, Sn = nSn;
+    const u64 gn = g + stride < total ? g + stride : g;
+    nS = R.subset(gn);
+    nSp = R.subset(gn > 0 ? gn - 1 : gn);
+    nSn = R.subset(gn + 1 < total ? gn + 1 : gn);
     const bool prev = (g > 0) & (Sp == S);
     const bool next = (g + 1 < total) & (Sn == S);
     if (!(!R.dead(S) & (prev | next))) continue;  // bitwise: no test before the loads
