@@ -39,10 +39,17 @@ k_radix_hist(const u64* __restrict__ keys, u64 count, int shift, u64* __restrict
   __syncthreads();
   const u64 b = xcd_tile(blockIdx.x, (u64)nblocks);
   const u64 base = b * (kSortThreads * ROWS);
+  // all rows are loaded (indices clamped to the last key) before the first
+  // LDS atomic, so the loads are in flight together
+  u64 k[ROWS];
+#pragma unroll
   for (int r = 0; r < ROWS; ++r) {
     const u64 i = base + (u64)r * kSortThreads + threadIdx.x;
-    if (i < count) atomicAdd(&hist[(keys[i] >> shift) & 255u], 1u);
+    k[r] = keys[i < count ? i : count - 1];
   }
+#pragma unroll
+  for (int r = 0; r < ROWS; ++r)
+    if (base + (u64)r * kSortThreads + threadIdx.x < count) atomicAdd(&hist[(k[r] >> shift) & 255u], 1u);
   __syncthreads();
   counts[(u64)threadIdx.x * nblocks + b] = hist[threadIdx.x];
 }
