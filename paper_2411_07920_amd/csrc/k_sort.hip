@@ -250,24 +250,30 @@ k_radix_scatter(const u64* __restrict__ keys_in, const V* __restrict__ vals_in, 
     // column t (digit t): counts in (row, wave) order become the exclusive
     // positions of each (row, wave) run in the reordered tile
     if (t < 256) {
+      // every count of the column is read before the first offset is
+      // written back, so the reads are in flight together
+      unsigned v[2 * kWaves];
+#pragma unroll
+      for (int j = 0; j < 2 * kWaves; ++j) v[j] = wave_cnt[j / kWaves][j % kWaves][t];
       const unsigned start = local_off[t] + running[t];
       unsigned at = start;
-      for (int h = 0; h < 2; ++h)
-        for (int w = 0; w < kWaves; ++w) {
-          const unsigned v = wave_cnt[h][w][t];
-          wave_cnt[h][w][t] = 0xffff0000u | at;
-          at += ((v & 0xffff0000u) == tag) ? (v & 0xffffu) : 0u;
-        }
+#pragma unroll
+      for (int j = 0; j < 2 * kWaves; ++j) {
+        wave_cnt[j / kWaves][j % kWaves][t] = 0xffff0000u | at;
+        at += ((v[j] & 0xffff0000u) == tag) ? (v[j] & 0xffffu) : 0u;
+      }
       running[t] += at - start;
     }
     __syncthreads();
+    unsigned pos[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) pos[h] = (wave_cnt[h][wave][digit[h]] & 0xffffu) + below[h];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       if (!valid[h]) continue;
-      const unsigned pos = (wave_cnt[h][wave][digit[h]] & 0xffffu) + below[h];
       const int rr = (r + h < ROWS) ? r + h : r;
-      s_key[pos] = key[rr];
-      if constexpr (kVals) s_val[pos] = val[rr];
+      s_key[pos[h]] = key[rr];
+      if constexpr (kVals) s_val[pos[h]] = val[rr];
     }
     __syncthreads();  // positions are read before the next pair's counts land
   }
