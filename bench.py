@@ -61,6 +61,8 @@ def parse():
     ap.add_argument("--uccsd", default=None, choices=sorted(CONFIGS),
                     help="instead of the step benchmark: MP2-ordered UCCSD on this workload "
                          "(ansatz build, energy + adjoint gradient evaluation, L-BFGS steps)")
+    ap.add_argument("--spin", action="store_true",
+                    help="with --uccsd: spin-complemented generators (one angle per commuting pair)")
     ap.add_argument("--eps", type=float, default=None,
                     help="pruning threshold for --uccsd (default: the workload's)")
     ap.add_argument("--vqe-iters", type=int, default=20,
@@ -555,13 +557,35 @@ def uccsd_bench(args):
         print(f"[uccsd] L-BFGS step {r['step']}: E {r['E']:.10f}", file=sys.stderr, flush=True)
 
     t = time.perf_counter()
-    theta, E, trace, evals = adapt.preoptimize(ctx, ans.ops, ans.theta, cfg, log=log)
+    n_params = len(ans.ops)
+    if args.spin:
+        # one angle per spin-complemented generator (commuting pairs tied)
+        import scipy.optimize
+        from paper_2411_07920_amd import spin
+        gp = spin.spin_complemented(wl.pool)
+        gens, th0 = uccsd.spin_complemented_uccsd(ans, gp)
+        n_params = len(gens)
+        f = spin.TiedEnergy(ctx, gp, gens, eps)
+        trace = []
+
+        def cb(xk):
+            trace.append(float(f(xk)[0]))
+            log({"step": len(trace), "E": trace[-1]})
+
+        r = scipy.optimize.minimize(f, th0, jac=True, method="L-BFGS-B", callback=cb,
+                                    options={"gtol": 1e-6, "ftol": 1e-15, "maxiter": args.vqe_iters})
+        E, evals = float(r.fun), f.evals
+        ops_f, ang_f = spin.expand(gp, gens, r.x)
+        n_final = ctx.apply_ansatz(ops_f, ang_f, eps)
+    else:
+        theta, E, trace, evals = adapt.preoptimize(ctx, ans.ops, ans.theta, cfg, log=log)
+        n_final = ctx.apply_ansatz(ans.ops, theta, eps)
     t_vqe = time.perf_counter() - t
-    n_final = ctx.apply_ansatz(ans.ops, theta, eps)
     out = {
         "metric": "MP2-ordered UCCSD: energy + adjoint gradient evaluation time and VQE energies",
         "workload": f"{args.uccsd}: {c.n_so} spin-orbitals, {c.n_elec} electrons, eps={eps:g}, "
-                    f"{len(ans.ops)} operators ({ans.n_doubles} doubles, {ans.n_singles} singles)",
+                    f"{len(ans.ops)} operators ({ans.n_doubles} doubles, {ans.n_singles} singles), "
+                    f"{n_params} parameters" + (" (spin-complemented)" if args.spin else ""),
         "e_ref": ans.e_ref, "e2": ans.e2, "e_mp2": ans.e_ref + ans.e2,
         "ansatz_build_s": t_build,
         "E_mp2_parameters": E0, "n_det_mp2_parameters": int(n_det),

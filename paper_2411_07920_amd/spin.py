@@ -117,18 +117,26 @@ def contract(gp: GeneratorPool, gens, dE_gates) -> np.ndarray:
 
 
 class TiedEnergy:
-    """E and dE/dtheta over generator parameters (each expanded into its gates)."""
+    """E and dE/dtheta over generator parameters (each expanded into its
+    gates).  A call at exactly the previous angles returns the previous result
+    without touching the context, whose state is then still at those angles."""
 
     def __init__(self, ctx, gp: GeneratorPool, gens, eps=0.0):
         self.ctx, self.gp, self.gens, self.eps = ctx, gp, list(gens), eps
         self.evals = 0
+        self._last = None
 
     def __call__(self, theta):
+        theta = np.array(theta, dtype=np.float64)
+        if self._last is not None and np.array_equal(theta, self._last[0]):
+            return self._last[1], self._last[2].copy()
         ops, ang = expand(self.gp, self.gens, theta)
         self.ctx.apply_ansatz(ops, ang, self.eps)
         dE, E = self.ctx.param_gradients(len(ops))
         self.evals += 1
-        return E, contract(self.gp, self.gens, np.asarray(dE))
+        d = contract(self.gp, self.gens, np.asarray(dE))
+        self._last = (theta, E, d)
+        return E, d.copy()
 
 
 _FIT9 = (np.arange(9) - 4) * (2.0 * np.pi / 9.0)

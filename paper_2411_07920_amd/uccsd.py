@@ -101,3 +101,33 @@ def mp2_ordered_uccsd(ctx, pool, ref, n_spatial, rel_tol=1e-9) -> UccsdAnsatz:
     theta = np.concatenate([theta_d[pos], np.zeros(len(singles))])
     return UccsdAnsatz(ops=ops.astype(np.int32), theta=theta, e_ref=e_ref, e2=e2,
                        n_doubles=len(doubles), n_singles=len(singles))
+
+
+def spin_complemented_uccsd(ans: UccsdAnsatz, gp):
+    """The UCCSD ansatz over spin-complemented generators (Sec. III; see
+    ``spin.py``).  For a closed-shell reference the complement of an
+    occupied -> virtual excitation is one as well, with the MP2 amplitude of
+    the same excitation read with flipped spins, so a commuting pair becomes
+    one generator with one parameter at the first member's position in the
+    MP2 order; the other rows stay single.  Returns (generators, theta) for
+    ``spin.expand`` / ``spin.TiedEnergy``."""
+    ops = np.asarray(ans.ops).tolist()
+    pos = {k: i for i, k in enumerate(ops)}
+    gen_of = {}
+    for j in range(len(gp)):
+        gen_of[int(gp.first[j])] = j
+        if gp.second[j] >= 0:
+            gen_of[int(gp.second[j])] = j
+    gens, theta, taken = [], [], set()
+    for i, k in enumerate(ops):
+        j = gen_of[k]
+        if j in taken:
+            continue
+        if gp.second[j] >= 0 and (int(gp.first[j]) not in pos or int(gp.second[j]) not in pos):
+            raise ValueError("a complement pair is not within the UCCSD operators")
+        taken.add(j)
+        gens.append(j)
+        # the generator's angle multiplies its first gate
+        k1 = int(gp.first[j])
+        theta.append(float(ans.theta[pos[k1]]))
+    return np.array(gens, dtype=np.int64), np.array(theta, dtype=np.float64)

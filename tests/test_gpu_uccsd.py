@@ -100,3 +100,30 @@ def test_c5_uccsd_ansatz_matches_oracle(swcs):
     _same_ansatz(ans, orc, pool, ref)
     assert ans.n_doubles == 29304 and ans.n_singles == 288
     ctx.close()
+
+
+def test_c1_spin_complemented_uccsd(swcs):
+    """The tied (spin-complemented) UCCSD ansatz of c1: energy and tied
+    gradients at the MP2 start against the oracle, and an L-BFGS run between
+    that energy and dense FCI."""
+    import scipy.optimize
+    from dense_jw import DenseProblem
+    from paper_2411_07920_amd import spin, uccsd
+    from test_spin_cpu import OracleContext as SpinOracle
+
+    c, h, eri, na, pool, ref, ctx, orc = _setup(swcs, "c1")
+    ans = uccsd.mp2_ordered_uccsd(ctx, pool, ref, c.n)
+    gp = spin.spin_complemented(pool)
+    gens, theta = uccsd.spin_complemented_uccsd(ans, gp)
+    f_gpu = spin.TiedEnergy(ctx, gp, gens)
+    f_cpu = spin.TiedEnergy(SpinOracle(c.n, c.n_elec, h, eri, pool), gp, gens)
+    E0, d0 = f_gpu(theta)
+    E0c, d0c = f_cpu(theta)
+    assert abs(E0 - E0c) < TOL and np.abs(d0 - d0c).max() < TOL
+    r = scipy.optimize.minimize(f_gpu, theta, jac=True, method="L-BFGS-B",
+                                options={"gtol": 1e-6, "ftol": 1e-15, "maxiter": 200})
+    fci = DenseProblem(c.n, na, na, h, eri).fci()
+    assert r.fun <= E0 + 1e-12 and r.fun >= fci - 1e-10
+    _say(f"[uccsd] c1 spin-complemented: {len(gens)} generators, E(MP2) {E0:.8f}, "
+         f"E_VQE {r.fun:.10f}, FCI {fci:.10f}")
+    ctx.close()

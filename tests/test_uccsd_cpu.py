@@ -163,3 +163,21 @@ def test_driver_host_logic_matches_oracle(name):
     assert np.all(np.abs(ans.theta - theta) <= 1e-12 * np.maximum(1.0, np.abs(theta)))
     assert abs(ans.e2 - e2) < 1e-12 * max(1.0, abs(e2))
     assert abs(ans.e_ref - ctx.orc.hmat(ref, ref)) < 1e-12
+
+
+@pytest.mark.parametrize("name", ["c1", "c2"])
+def test_spin_complemented_uccsd(name):
+    """Complement pairs of UCCSD operators carry amplitudes theta_k' =
+    sign * theta_k, so the tied ansatz starts from the MP2 amplitudes of every
+    operator; each UCCSD operator appears in exactly one generator."""
+    from paper_2411_07920_amd import spin
+    n, na, h, eri, pool, ref = _problem(name)
+    ctx = OracleContext(n, na, h, eri, pool, ref)
+    ans = uccsd.mp2_ordered_uccsd(ctx, pool, ref, n)
+    gp = spin.spin_complemented(pool)
+    gens, theta = uccsd.spin_complemented_uccsd(ans, gp)
+    ops, ang = spin.expand(gp, gens, theta)
+    assert sorted(ops.tolist()) == sorted(ans.ops.tolist())
+    mp2 = dict(zip(ans.ops.tolist(), ans.theta.tolist()))
+    assert all(abs(a - mp2[k]) <= 1e-12 * max(1.0, abs(mp2[k])) for k, a in zip(ops.tolist(), ang.tolist()))
+    assert len(gens) < len(ans.ops)
