@@ -258,11 +258,13 @@ int swcs_mse(swcs_ctx* ctx, const float* d_y, const float* d_t, int64_t B, float
 /* Screener targets: d_t[i] = log10(|d_g[i]| + 1e-12) as float32 (device). */
 int swcs_log_abs(swcs_ctx* ctx, const double* d_g, int64_t n, float* d_t);
 
-/* d_v[i] += sign * d_feat[i * 16 + col] for i < n (float32, device; sign is
- * +1 or -1, 0 <= col < 16).  The screener scores an operator by feature 10,
- * log10 of its last exact |g|, plus the network output, and trains the
- * network on the matching residual target. */
-int swcs_add_feature(swcs_ctx* ctx, float* d_v, const float* d_feat, int64_t n, int col, int sign);
+/* d_v[i] = scale * d_v[i] + sign * d_feat[i * 16 + col] for i < n (float32,
+ * device; sign is +1 or -1, 0 <= col < 16, 0 <= scale <= 1).  The screener
+ * scores an operator by feature 10, log10 of its last exact |g|, plus the
+ * network output shrunk by its out-of-sample fit (scale), and trains the
+ * network on the matching residual target (scale 1). */
+int swcs_add_feature(swcs_ctx* ctx, float* d_v, const float* d_feat, int64_t n, int col, int sign,
+                     float scale);
 
 /* One Adam step with bias correction (step >= 1) on P parameters. */
 int swcs_adam_step(swcs_ctx* ctx, float* d_W, float* d_m, float* d_v, const float* d_dW,

@@ -222,6 +222,7 @@ def run_adapt(ctx, K: int, cfg: AdaptConfig, ops0=None, theta0=None, log=None):
             t3 = time.perf_counter()
             rec["loss"] = scr.train()
             rec["t_train"] = time.perf_counter() - t3
+            rec["lam"] = scr.lam
         if cfg.shadow_full and not full:
             g_all = ctx.pool_gradients()
             ks = int(select_operator(g_all, np.arange(K)))

@@ -302,9 +302,9 @@ __global__ void k_mse_finish(const float* __restrict__ partial, int nblocks, lon
 // v[i] += sign * feat[i * 16 + col]: the screener's score and target offset
 // by one feature column (log10 of the last exact |g|).
 __global__ void k_add_feature(float* __restrict__ v, const float* __restrict__ feat, long long n, int col,
-                              float sign) {
+                              float sign, float scale) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) v[i] += sign * feat[i * 16 + col];
+  if (i < n) v[i] = scale * v[i] + sign * feat[i * 16 + col];
 }
 
 __global__ void k_log_abs(const double* __restrict__ g, long long n, float* __restrict__ t) {
@@ -387,11 +387,11 @@ hipError_t launch_log_abs(const double* g, long long n, float* t, hipStream_t st
   return hipGetLastError();
 }
 
-hipError_t launch_add_feature(float* v, const float* feat, long long n, int col, float sign,
+hipError_t launch_add_feature(float* v, const float* feat, long long n, int col, float sign, float scale,
                               hipStream_t stream) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_add_feature, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, v, feat, n, col,
-                     sign);
+                     sign, scale);
   return hipGetLastError();
 }
 

@@ -1467,12 +1467,13 @@ int swcs_log_abs(swcs_ctx* c, const double* d_g, int64_t n, float* d_t) {
   return SWCS_OK;
 }
 
-int swcs_add_feature(swcs_ctx* c, float* d_v, const float* d_feat, int64_t n, int col, int sign) {
+int swcs_add_feature(swcs_ctx* c, float* d_v, const float* d_feat, int64_t n, int col, int sign, float scale) {
   if (!c) return SWCS_E_INVALID;
-  if (n < 0 || (n > 0 && (!d_v || !d_feat)) || col < 0 || col >= 16 || (sign != 1 && sign != -1))
+  if (n < 0 || (n > 0 && (!d_v || !d_feat)) || col < 0 || col >= 16 || (sign != 1 && sign != -1) ||
+      !(scale >= 0.0f && scale <= 1.0f))
     return fail(c, SWCS_E_INVALID, "bad add_feature arguments");
   HIP_TRY(c, hipSetDevice(c->device), "hipSetDevice");
-  HIP_TRY(c, launch_add_feature(d_v, d_feat, n, col, (float)sign, c->stream), "add_feature");
+  HIP_TRY(c, launch_add_feature(d_v, d_feat, n, col, (float)sign, scale, c->stream), "add_feature");
   return SWCS_OK;
 }
 

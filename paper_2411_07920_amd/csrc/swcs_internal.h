@@ -397,7 +397,7 @@ hipError_t launch_mlp_backward(const float* W, const float* x, const float* act,
 int mse_partial_count(long long B);
 hipError_t launch_mse(const float* y, const float* t, long long B, float* dy, float* loss,
                       float* partial, hipStream_t stream);
-hipError_t launch_add_feature(float* v, const float* feat, long long n, int col, float sign,
+hipError_t launch_add_feature(float* v, const float* feat, long long n, int col, float sign, float scale,
                               hipStream_t stream);
 hipError_t launch_log_abs(const double* g, long long n, float* t, hipStream_t stream);
 hipError_t launch_sanitize_subset(const int* in, long long count, long long K, int* out,

@@ -8,7 +8,14 @@ random share; the exact gradients that result are its training data (online,
 Adam, mean squared error).  The prediction is feature 10 -- log10 of the
 operator's last exact |g| -- plus the output of a 16 -> 128 -> 128 -> 1 ReLU
 network, which therefore learns how each gradient has changed since it was
-last evaluated; an untrained network ranks by the last exact gradients.
+last evaluated; an untrained network ranks by the last exact gradients.  The
+network output enters the score multiplied by lam in {0, 1/4, 1/2, 3/4, 1},
+chosen on held-out data for the job the score does: at every full-pool
+iteration, before the network is trained on it, each lam's score ranks all
+operators and the number ranked above the one ADAPT selects is recorded; lam
+is the value with the smallest sum of log(1 + rank) so far (ties to the
+smaller).  A network that does not help find the selected operator leaves the
+ranking by the last exact gradients unchanged.
 
 All arithmetic runs in libswcs kernels (features, forward, MSE, backward,
 Adam, selection); torch only holds the device buffers.
@@ -59,6 +66,10 @@ class Screener:
         self.buf_pos = 0
         self.buffer_rows = buffer_rows
         self.loss = torch.zeros(1, device=dev)
+        self.lam = 0.0  # weight of the network in the score (see module docstring)
+        self.lam_grid = np.array([0.0, 0.25, 0.5, 0.75, 1.0])
+        self.lam_cost = np.zeros(len(self.lam_grid))
+        self.lam_history = []
 
     # -- per-iteration bookkeeping ------------------------------------------
     def compute_features(self, ansatz_ops):
@@ -71,7 +82,7 @@ class Screener:
 
     def scores(self):
         self.ctx.mlp_forward(self.W, self.feat, self.score)
-        self.ctx.add_feature(self.score, self.feat, self.RESIDUAL_COL, +1)
+        self.ctx.add_feature(self.score, self.feat, self.RESIDUAL_COL, +1, self.lam)
         return self.score
 
     def select(self):
@@ -101,6 +112,8 @@ class Screener:
         t = torch.empty(len(rows), dtype=torch.float32, device="cuda")
         self.ctx.log_abs(g_d, t)
         self.ctx.add_feature(t, x, self.RESIDUAL_COL, -1)  # residual target of the network
+        if len(rows) == self.K:
+            self._update_lam(rows, g_d)
         n = len(rows)
         for s in range(0, n, self.buffer_rows):
             xs, ts = x[s:s + self.buffer_rows], t[s:s + self.buffer_rows]
@@ -121,6 +134,25 @@ class Screener:
         self.age += 1.0
         self.age[rows] = 0.0
         self.prev_absg[rows] = g_d.abs().float()
+
+    def _update_lam(self, rows, g_d):
+        """Held-out choice of lam at a full-pool iteration (rows = every
+        operator, g_d their exact gradients), before training on it: for each
+        lam on the grid, the number of operators whose score f10 + lam * y
+        exceeds that of the operator of largest |g|."""
+        torch = self.torch
+        y = torch.zeros(self.K, device="cuda")
+        self.ctx.mlp_forward(self.W, self.feat, y)
+        yh = y.cpu().numpy().astype(np.float64)
+        f10 = self.feat[:, self.RESIDUAL_COL].cpu().numpy().astype(np.float64)
+        absg = np.zeros(self.K)
+        absg[rows.cpu().numpy()] = g_d.abs().cpu().numpy()
+        k = int(np.argmax(absg))
+        for j, lam in enumerate(self.lam_grid):
+            s = f10 + lam * yh
+            self.lam_cost[j] += np.log1p(np.count_nonzero(s > s[k]))
+        self.lam = float(self.lam_grid[int(np.argmin(self.lam_cost))])
+        self.lam_history.append(self.lam)
 
     def train(self):
         """Full-batch Adam steps on the replay buffer; returns the last loss."""

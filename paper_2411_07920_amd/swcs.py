@@ -69,7 +69,7 @@ SIGNATURES = {
     "swcs_pool_gradients": (ctypes.c_int, [_vp, _i32p, _i64, _dp]),
     "swcs_pool_gradients_device": (ctypes.c_int, [_vp, _vp, _i64, _vp]),
     "swcs_log_abs": (ctypes.c_int, [_vp, _vp, _i64, _vp]),
-    "swcs_add_feature": (ctypes.c_int, [_vp, _vp, _vp, _i64, ctypes.c_int, ctypes.c_int]),
+    "swcs_add_feature": (ctypes.c_int, [_vp, _vp, _vp, _i64, ctypes.c_int, ctypes.c_int, ctypes.c_float]),
     "swcs_param_gradients": (ctypes.c_int, [_vp, _dp, _dp]),
     "swcs_gate_sizes": (ctypes.c_int, [_vp, _i64p, _i64]),
     "swcs_occupations": (ctypes.c_int, [_vp, _dp]),
@@ -337,12 +337,13 @@ class Context:
     def log_abs(self, g, t):
         self._check(self._lib.swcs_log_abs(self._h, _dev(g), int(g.shape[0]), _dev(t)))
 
-    def add_feature(self, v, feat, col, sign):
-        """v += sign * feat[:, col] (float32 device tensors, feat of 16 columns)."""
+    def add_feature(self, v, feat, col, sign, scale=1.0):
+        """v = scale * v + sign * feat[:, col] (float32 device tensors, feat of
+        16 columns, 0 <= scale <= 1)."""
         if feat.shape[0] < v.shape[0] or feat.shape[1] != 16:
             raise ValueError("feat must have 16 columns and at least len(v) rows")
         self._check(self._lib.swcs_add_feature(self._h, _dev(v), _dev(feat), int(v.shape[0]), int(col),
-                                               int(sign)))
+                                               int(sign), float(scale)))
 
     def adam_step(self, W, m, v, dW, lr, b1, b2, eps, step):
         self._check(self._lib.swcs_adam_step(self._h, _dev(W), _dev(m), _dev(v), _dev(dW),

@@ -154,14 +154,16 @@ def test_select_degenerate_scores(env):
 
 
 def test_add_feature(env):
-    """Score / target offset by one feature column, both signs, ragged length."""
+    """Score / target offset by one feature column, both signs, ragged
+    length, with and without shrinking the existing values."""
     torch, ctx = env["torch"], env["ctx"]
     rng = np.random.default_rng(9)
     for n in (1, 255, 1000):
         feat = rng.normal(size=(n, 16)).astype(np.float32)
         v0 = rng.normal(size=n).astype(np.float32)
-        for col, sign in ((10, 1), (3, -1)):
+        for col, sign, scale in ((10, 1, 1.0), (3, -1, 1.0), (10, 1, 0.375), (10, 1, 0.0)):
             v = torch.from_numpy(v0.copy()).cuda()
-            ctx.add_feature(v, torch.from_numpy(feat).cuda(), col, sign)
+            ctx.add_feature(v, torch.from_numpy(feat).cuda(), col, sign, scale)
             torch.cuda.synchronize()
-            assert np.array_equal(v.cpu().numpy(), v0 + np.float32(sign) * feat[:, col])
+            expect = np.float32(scale) * v0 + np.float32(sign) * feat[:, col]
+            assert np.array_equal(v.cpu().numpy(), expect)
