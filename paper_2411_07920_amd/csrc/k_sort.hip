@@ -569,7 +569,7 @@ __device__ u64 block_radix_select(long long K, unsigned long long kth, KeyOf key
 #pragma unroll
           for (int j = 0; j < kSelBatch; ++j) {
             const long long k = k0 + (long long)j * blockDim.x;
-            key[j] = (k < K) ? key_of(k) : 0ULL;
+            key[j] = key_of(k < K ? k : K - 1);  // clamped: no branch between the loads
           }
 #pragma unroll
           for (int j = 0; j < kSelBatch; ++j) {
@@ -621,7 +621,7 @@ __device__ u64 block_radix_select(long long K, unsigned long long kth, KeyOf key
 #pragma unroll
         for (int j = 0; j < kSelBatch; ++j) {
           const long long k = k0 + (long long)j * blockDim.x;
-          key[j] = (k < K) ? key_of(k) : 0ULL;
+          key[j] = key_of(k < K ? k : K - 1);  // clamped: no branch between the loads
         }
 #pragma unroll
         for (int j = 0; j < kSelBatch; ++j) {
