@@ -80,9 +80,18 @@ __device__ inline u64 block_exclusive_1024(u64 v, u64* part, u64* total) {
 // `carry`; returns the tile total.  Every thread of the block calls it.
 __device__ inline u64 scan_tile(u64* __restrict__ data, u64 len, u64 base, u64 carry, u64* stage,
                                 u64* part) {
+  // loads first (indices clamped, zeroed after), so the kScanItems loads of
+  // a thread are in flight together
+  u64 ld[kScanItems];
+#pragma unroll
   for (int j = 0; j < kScanItems; ++j) {
     const u64 i = base + (u64)j * kScanThreads + threadIdx.x;
-    stage[(u64)j * kScanThreads + threadIdx.x] = (i < len) ? data[i] : 0;
+    ld[j] = data[i < len ? i : len - 1];
+  }
+#pragma unroll
+  for (int j = 0; j < kScanItems; ++j) {
+    const u64 i = base + (u64)j * kScanThreads + threadIdx.x;
+    stage[(u64)j * kScanThreads + threadIdx.x] = (i < len) ? ld[j] : 0;
   }
   __syncthreads();
   u64 v[kScanItems], t = 0;
@@ -120,11 +129,16 @@ __global__ void __launch_bounds__(kScanThreads)
 k_scan_chunk_sums(const u64* __restrict__ data, u64 len, u64* __restrict__ sums) {
   __shared__ u64 red[kScanThreads];
   const u64 base = (u64)blockIdx.x * kScanChunk;
-  u64 s = 0;
+  u64 ld[kScanItems];
+#pragma unroll
   for (int j = 0; j < kScanItems; ++j) {
     const u64 i = base + (u64)j * kScanThreads + threadIdx.x;
-    if (i < len) s += data[i];
+    ld[j] = data[i < len ? i : len - 1];  // clamped: the loads issue together
   }
+  u64 s = 0;
+#pragma unroll
+  for (int j = 0; j < kScanItems; ++j)
+    if (base + (u64)j * kScanThreads + threadIdx.x < len) s += ld[j];
   red[threadIdx.x] = s;
   __syncthreads();
   for (int w = kScanThreads / 2; w > 0; w >>= 1) {
