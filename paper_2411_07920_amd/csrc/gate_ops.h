@@ -265,11 +265,16 @@ __device__ inline void gate_entries_staged(const GlobalStore& S, u64 n, u64 i0, 
   HashSlot sl[N];
   long long jx[N];
   double araw[N], braw[N], own[N];
+  // The entries' keys, then every entry's kind and probe position, then the
+  // probes: key loads behind a branch, or a probe issued before the next
+  // entry's key is used, would make the loads wait for each other (callers
+  // pass i0 < n, so the clamped index is valid).
 #pragma unroll
   for (int j = 0; j < N; ++j) {
     const u64 i = i0 + (u64)j * stride;
-    D[j] = (i < n) ? S.keys[i] : 0ULL;
+    D[j] = S.keys[i < n ? i : n - 1];
   }
+  __builtin_amdgcn_sched_barrier(0);  // every key load before the first use of a key
 #pragma unroll
   for (int j = 0; j < N; ++j) {
     const u64 i = i0 + (u64)j * stride;
@@ -277,8 +282,16 @@ __device__ inline void gate_entries_staged(const GlobalStore& S, u64 n, u64 i0, 
     const bool isTd = ((D[j] & op.cre) == op.cre) && ((D[j] & op.ann) == 0);
     kind[j] = (i < n) ? (isT ? 1 : (isTd ? 2 : 0)) : 0;
     partner[j] = D[j] ^ pair_mask;
+    h[j] = mix64(partner[j]) & S.hmask;
+  }
+  // an empty asm statement taking the positions and kinds as inputs keeps
+  // them computed here instead of sunk behind an earlier entry's probe
+#pragma unroll
+  for (int j = 0; j < N; ++j) asm volatile("" : : "v"(h[j]), "v"(kind[j]));
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    const u64 i = i0 + (u64)j * stride;
     if (kind[j]) {
-      h[j] = mix64(partner[j]) & S.hmask;
       sl[j] = S.hash[h[j]];
       own[j] = S.amps[i];
     }
