@@ -143,3 +143,22 @@ def test_select_operator_ties_go_to_smallest_index():
     idx = np.array([9, 4, 7, 1])
     assert adapt.select_operator(np.array([0.5, 0.1, -0.5, 0.0]), idx) == 2
     assert adapt.select_operator(np.array([0.3, 0.5, 0.1]), np.arange(3)) == 1
+
+
+def test_bootstrap_ncut_restart(problem):
+    """Bootstrap N_CUT (Sec. IV): ADAPT at a small N_CUT, then a restart at a
+    larger N_CUT from the final ansatz (ops0 / theta0).  The restart's first
+    energy is the seeded ansatz's energy at the larger N_CUT, and the energy
+    keeps decreasing."""
+    n, ne, h, eri, pool = problem
+    ctx = OracleContext(n, ne, h, eri, pool)
+    cfg1 = adapt.AdaptConfig(ncut=6, max_iter=4, grad_tol=None, optimizer="lbfgs")
+    ops1, th1, hist1 = adapt.run_adapt(ctx, len(pool), cfg1)
+    cfg2 = adapt.AdaptConfig(ncut=30, max_iter=3, grad_tol=None, optimizer="lbfgs")
+    ops2, th2, hist2 = adapt.run_adapt(ctx, len(pool), cfg2, ops0=ops1, theta0=th1)
+    assert ops2[: len(ops1)].tolist() == ops1.tolist() and len(ops2) == len(ops1) + 3
+    ctx.apply_ansatz(ops1, th1, 0.0, 30)
+    assert abs(hist2[0]["E"] - ctx.energy()[0]) < 1e-12
+    Es = [r["E_after"] for r in hist2]
+    assert all(b <= a + 1e-10 for a, b in zip([hist2[0]["E"]] + Es, Es))
+    assert hist1[0]["n_det"] <= 6 and hist2[-1]["n_det"] <= 30

@@ -95,3 +95,27 @@ def test_screener_beats_random_subset(swcs):
     assert match >= 0.8 and match > 5 * frac
     assert match > rnd
     ctx.close()
+
+
+def test_bootstrap_ncut_follows_oracle_driver(swcs):
+    """Bootstrap N_CUT (Sec. IV) on the GPU: ADAPT at N_CUT = 40, then a restart
+    at N_CUT = 150 from its final ansatz, operator by operator as with the
+    oracle (12 spin-orbitals, 4 electrons: 225 determinants)."""
+    from test_adapt_host import OracleContext
+    c = CONFIGS["c1"]
+    h, eri = make_integrals(c.n, c.rank, c.seed_int)
+    pool = enumerate_pool(c.n)
+    ref = reference_key(c.n_elec)
+    cfg1 = adapt.AdaptConfig(ncut=40, max_iter=4, grad_tol=None, optimizer="lbfgs")
+    cfg2 = adapt.AdaptConfig(ncut=150, max_iter=3, grad_tol=None, optimizer="lbfgs")
+    gpu = swcs.make_context(c.n, 2, 2, h, eri, pool, ref)
+    cpu = OracleContext(c.n, c.n_elec, h, eri, pool)
+    runs = []
+    for ctx in (gpu, cpu):
+        o1, t1, h1 = adapt.run_adapt(ctx, len(pool), cfg1)
+        o2, t2, h2 = adapt.run_adapt(ctx, len(pool), cfg2, ops0=o1, theta0=t1)
+        runs.append((o2, h1 + h2))
+    assert runs[0][0].tolist() == runs[1][0].tolist()
+    for a, b in zip(runs[0][1], runs[1][1]):
+        assert abs(a["E"] - b["E"]) < 1e-8 and abs(a["E_after"] - b["E_after"]) < 1e-7
+    gpu.close()
