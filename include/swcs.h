@@ -90,6 +90,14 @@ int swcs_set_stream(swcs_ctx* ctx, void* hip_stream);
  * device memory).  Growth past it fails with SWCS_E_CAPACITY. */
 int swcs_set_capacity(swcs_ctx* ctx, int64_t max_dets);
 
+/* Upper bound, in bytes, on the hash table that pool gradients accumulate
+ * sigma_P(X) in over the external space (Sec. II.C).  Keys that would not fit
+ * are split by key hash into batches, each a full pass over the state, and
+ * the gradients are summed over the batches.  0 (default) = 40% of the free
+ * device memory; 1 to 4095 fail with SWCS_E_INVALID.  Batched results agree
+ * with unbatched ones up to the order of floating-point summation. */
+int swcs_set_table_budget(swcs_ctx* ctx, int64_t bytes);
+
 /* How sigma_P (energy, parameter gradients) is formed.  ENUMERATE probes
  * every single and double excitation of every alive determinant (alive * C
  * probes).  HOLE_PAIRS groups the determinants by their subsets of N_e - 2

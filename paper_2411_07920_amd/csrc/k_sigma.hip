@@ -819,7 +819,7 @@ __global__ void __launch_bounds__(kSigBlock)
 k_query_set(const u64* __restrict__ keys, const double* __restrict__ amps, ExcSpace E, int n_spatial,
             u64 n, const int* __restrict__ optab, int npairs,
             const unsigned char* __restrict__ selected, AccSlot* __restrict__ tab, u64 tmask,
-            int count_only, u64* __restrict__ counter, unsigned* __restrict__ flags) {
+            int count_only, u64* __restrict__ counter, unsigned* __restrict__ flags, int nbatch, int batch) {
   __shared__ SigShared S;
   __shared__ ConnTables T;
   extern __shared__ __align__(16) unsigned char conn_dyn[];
@@ -843,6 +843,7 @@ k_query_set(const u64* __restrict__ keys, const double* __restrict__ amps, ExcSp
         ++mine;
         return;
       }
+      if (nbatch > 1 && batch_of(X, nbatch) != batch) return;
       if (!acc_add(tab, tmask, X, 0.0)) atomicOr(flags, kFlagOverflow);
     });
   }
@@ -862,7 +863,7 @@ __global__ void __launch_bounds__(256)
 k_query_ops(const u64* __restrict__ keys, const double* __restrict__ amps, u64 n,
             const OpDesc* __restrict__ ops, const int* __restrict__ subset, long long n_sub,
             AccSlot* __restrict__ tab, u64 tmask, int count_only, u64* __restrict__ counter,
-            unsigned* __restrict__ flags) {
+            unsigned* __restrict__ flags, int nbatch, int batch) {
   __shared__ u64 skey[kOpTile];
   const u64 t0 = (u64)blockIdx.x * kOpTile;
   const int tile = (int)((n - t0) < (u64)kOpTile ? (n - t0) : (u64)kOpTile);
@@ -881,6 +882,7 @@ k_query_ops(const u64* __restrict__ keys, const double* __restrict__ amps, u64 n
                        (((D & op.cre) == op.cre) && ((D & op.ann) == 0));
       if (!act) continue;
       if (count_only) ++mine;
+      else if (nbatch > 1 && batch_of(D ^ pm, nbatch) != batch) continue;
       else if (!acc_add(tab, tmask, D ^ pm, 0.0)) atomicOr(flags, kFlagOverflow);
     }
   }
@@ -893,7 +895,8 @@ k_query_ops(const u64* __restrict__ keys, const double* __restrict__ amps, u64 n
 __global__ void __launch_bounds__(256)
 k_contract_ops(const u64* __restrict__ keys, const double* __restrict__ amps, u64 n,
                const OpDesc* __restrict__ ops, const int* __restrict__ subset, long long n_sub,
-               const AccSlot* __restrict__ tab, u64 tmask, double* __restrict__ gslot) {
+               const AccSlot* __restrict__ tab, u64 tmask, double* __restrict__ gslot, int nbatch,
+               int batch) {
   __shared__ u64 skey[kOpTile];
   __shared__ double samp[kOpTile];
   const u64 t0 = (u64)blockIdx.x * kOpTile;
@@ -916,6 +919,7 @@ k_contract_ops(const u64* __restrict__ keys, const double* __restrict__ amps, u6
     const bool isTd = ((D & op.cre) == op.cre) && ((D & op.ann) == 0);
     if (!(isT || isTd)) continue;
     const u64 X = D ^ pm;
+    if (nbatch > 1 && batch_of(X, nbatch) != batch) continue;
     double sx;
     if (!acc_find(tab, tmask, X, &sx)) continue;
     const double a = isT ? (double)phase_of_T(op, D) : -(double)phase_of_T(op, X);
@@ -937,7 +941,8 @@ __device__ inline double* acc_slot(AccSlot* tab, u64 mask, u64 key) {
 
 __global__ void __launch_bounds__(kSigBlock)
 k_sigma_push_into(const u64* __restrict__ keys, const double* __restrict__ amps, Ints I, ExcSpace E,
-                  u64 n, const double* __restrict__ diag, AccSlot* __restrict__ tab, u64 tmask) {
+                  u64 n, const double* __restrict__ diag, AccSlot* __restrict__ tab, u64 tmask, int nbatch,
+                  int batch) {
   __shared__ SigShared S;
   __shared__ ConnTables T;
   extern __shared__ __align__(16) unsigned char conn_dyn[];
@@ -952,11 +957,12 @@ k_sigma_push_into(const u64* __restrict__ keys, const double* __restrict__ amps,
     __syncthreads();
     build_conn_tables(S, E, T);
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (threadIdx.x == 0 && (nbatch == 1 || batch_of(D, nbatch) == batch)) {
       double* v = acc_slot(tab, tmask, D);
       if (v) unsafeAtomicAdd(v, diag[d] * psiD);
     }
     for_each_connection(T, D, [&](u64 X, int nh, int h0, int h1, int p0, int p1) {
+      if (nbatch > 1 && batch_of(X, nbatch) != batch) return;
       double* v = acc_slot(tab, tmask, X);
       if (v) unsafeAtomicAdd(v, connection_element(I, D, nh, h0, h1, p0, p1) * psiD);
     });
@@ -1157,37 +1163,41 @@ hipError_t launch_pool_contract_det(const DeviceState& st, const ExcSpace& E, in
 hipError_t launch_query_set(const DeviceState& st, const ExcSpace& E, int n_spatial, u64 n,
                             const int* optab, int npairs, const unsigned char* selected,
                             AccSlot* tab, u64 tmask, int count_only, u64* counter, int grid,
-                            hipStream_t stream) {
+                            hipStream_t stream, int nbatch, int batch) {
+  if (nbatch < 1 || batch < 0 || batch >= nbatch) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_query_set, dim3(grid), dim3(kSigBlock), conn_tables_bytes(E), stream, st.keys, st.amps, E,
                      n_spatial, n, optab, npairs, selected, tab, tmask, count_only, counter,
-                     &st.ctr->flags);
+                     &st.ctr->flags, nbatch, batch);
   return hipGetLastError();
 }
 
 hipError_t launch_query_ops(const DeviceState& st, u64 n, const OpDesc* ops, const int* subset,
                             long long n_sub, AccSlot* tab, u64 tmask, int count_only, u64* counter,
-                            hipStream_t stream) {
+                            hipStream_t stream, int nbatch, int batch) {
+  if (nbatch < 1 || batch < 0 || batch >= nbatch) return hipErrorInvalidValue;
   if (n == 0 || n_sub == 0) return hipSuccess;
   const dim3 grid((unsigned)((n + kOpTile - 1) / kOpTile), (unsigned)((n_sub + 255) / 256));
   hipLaunchKernelGGL(k_query_ops, grid, dim3(256), 0, stream, st.keys, st.amps, n, ops, subset,
-                     n_sub, tab, tmask, count_only, counter, &st.ctr->flags);
+                     n_sub, tab, tmask, count_only, counter, &st.ctr->flags, nbatch, batch);
   return hipGetLastError();
 }
 
 hipError_t launch_contract_ops(const DeviceState& st, u64 n, const OpDesc* ops, const int* subset,
                                long long n_sub, const AccSlot* tab, u64 tmask, double* gslot,
-                               hipStream_t stream) {
+                               hipStream_t stream, int nbatch, int batch) {
+  if (nbatch < 1 || batch < 0 || batch >= nbatch) return hipErrorInvalidValue;
   if (n == 0 || n_sub == 0) return hipSuccess;
   const dim3 grid((unsigned)((n + kOpTile - 1) / kOpTile), (unsigned)((n_sub + 255) / 256));
   hipLaunchKernelGGL(k_contract_ops, grid, dim3(256), 0, stream, st.keys, st.amps, n, ops, subset,
-                     n_sub, tab, tmask, gslot);
+                     n_sub, tab, tmask, gslot, nbatch, batch);
   return hipGetLastError();
 }
 
 hipError_t launch_sigma_push_into(const DeviceState& st, const Ints& I, const ExcSpace& E, u64 n,
-                                  AccSlot* tab, u64 tmask, int grid, hipStream_t stream) {
+                                  AccSlot* tab, u64 tmask, int grid, hipStream_t stream, int nbatch, int batch) {
+  if (nbatch < 1 || batch < 0 || batch >= nbatch) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_sigma_push_into, dim3(grid), dim3(kSigBlock), conn_tables_bytes(E), stream, st.keys, st.amps, I,
-                     E, n, st.diag, tab, tmask);
+                     E, n, st.diag, tab, tmask, nbatch, batch);
   return hipGetLastError();
 }
 

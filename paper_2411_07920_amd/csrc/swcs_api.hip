@@ -74,6 +74,7 @@ struct swcs_ctx {
   hipStream_t stream = nullptr;
   std::string err;
   int64_t max_dets = 0;
+  int64_t table_budget = 0;  // bytes for one sigma accumulation table (0 = from free memory)
   u64 sector = 0;
   ExcSpace exc;
 
@@ -252,6 +253,15 @@ Counters get_counters(swcs_ctx* c, hipError_t* e) {
   return read_counters(c, e);
 }
 
+// Buffers that hold nothing from one call to the next (the external sigma
+// table, hole-pair records, sort and export scratch): given back to the device
+// when the state needs the memory, and allocated again on their next use.
+void release_scratch(swcs_ctx* c) {
+  DevBuf* bufs[] = {&c->acc_tab, &c->hp_key, &c->hp_val, &c->hp_tk, &c->hp_tv, &c->sort_scratch,
+                    &c->exp_keys, &c->exp_amps, &c->exp_tmp_k, &c->exp_tmp_v};
+  for (DevBuf* b : bufs) b->release();
+}
+
 u64 max_capacity(swcs_ctx* c) {
   u64 cap = c->sector;
   if (c->max_dets > 0 && (u64)c->max_dets < cap) cap = (u64)c->max_dets;
@@ -316,6 +326,7 @@ int build_filter(swcs_ctx* c, u64 n, u64 alive) {
 // Reset the state to the single reference determinant.
 int state_reset_to_reference(swcs_ctx* c) {
   u64 cap = next_pow2(std::max<u64>(4096, 4 * c->peak_n));
+  if (cap > c->st.cap && cap > max_capacity(c)) release_scratch(c);
   cap = std::min<u64>(cap, max_capacity(c));
   if (cap < 2) cap = 2;
   if (!c->keys.p || c->st.cap != cap) {
@@ -459,7 +470,11 @@ int run_chain(swcs_ctx* c, const int32_t* op_idx, const double* cs, const double
     // Grow so that the stopped gate (and a few more) fit, then resume.
     const u64 need = h.n + std::min<u64>(h.alive, c->sector > h.n ? c->sector - h.n : 0);
     u64 cap = next_pow2(std::max<u64>(2 * c->st.cap, 2 * need));
-    const u64 maxc = max_capacity(c);
+    u64 maxc = max_capacity(c);
+    if (maxc < cap) {
+      release_scratch(c);
+      maxc = max_capacity(c);
+    }
     if (cap > maxc) cap = maxc;
     if (cap < need) return fail(c, SWCS_E_CAPACITY, "state exceeds the maximum capacity");
     int r = state_reserve(c, cap, h.n);
@@ -555,6 +570,14 @@ int swcs_set_capacity(swcs_ctx* c, int64_t max_dets) {
   if (!c) return SWCS_E_INVALID;
   if (max_dets < 0) return fail(c, SWCS_E_INVALID, "max_dets < 0");
   c->max_dets = max_dets;
+  return SWCS_OK;
+}
+
+int swcs_set_table_budget(swcs_ctx* c, int64_t bytes) {
+  if (!c) return SWCS_E_INVALID;
+  if (bytes < 0) return fail(c, SWCS_E_INVALID, "bytes < 0");
+  if (bytes > 0 && bytes < 4096) return fail(c, SWCS_E_INVALID, "table budget below 4096 bytes");
+  c->table_budget = bytes;
   return SWCS_OK;
 }
 
@@ -1070,29 +1093,68 @@ static int screened_gradients(swcs_ctx* c, u64 n, u64 alive, const int* d_subset
     HIP_TRY(c, hipMemcpyAsync(&nq, qcount, 8, hipMemcpyDeviceToHost, c->stream), "copy");
     HIP_TRY(c, hipStreamSynchronize(c->stream), "sync");
   }
-  const u64 qslots = next_pow2(std::max<u64>(64, 2 * std::min<u64>(nq, c->sector)));
-  HIP_TRY(c, c->acc_tab.ensure(qslots * sizeof(AccSlot)), "alloc sigma table");
-  HIP_TRY(c, hipMemsetAsync(c->acc_tab.p, 0, qslots * sizeof(AccSlot), c->stream), "clear table");
-  if (op_major)
-    HIP_TRY(c, launch_query_ops(c->st, n, c->ops.as<OpDesc>(), d_subset, n_subset,
-                                c->acc_tab.as<AccSlot>(), qslots - 1, 0, nullptr, c->stream), "query set");
-  else
-    HIP_TRY(c, launch_query_set(c->st, c->exc, c->n, n, c->opmap.as<int>(), c->npairs, d_sel,
-                                c->acc_tab.as<AccSlot>(), qslots - 1, 0, nullptr, sigma_grid(c, n),
-                                c->stream), "query set");
-  TIMED(c, SWCS_K_SIGMA_PUSH_INTO, launch_sigma_push_into(c->st, ints_view(c), c->exc, n, c->acc_tab.as<AccSlot>(), qslots - 1,
-                                    sigma_grid(c, n), c->stream), "sigma push");
-  if (op_major) {
-    HIP_TRY(c, hipMemsetAsync(d_out, 0, (size_t)n_subset * 8, c->stream), "zero g");
-    TIMED(c, SWCS_K_CONTRACT_OPS, launch_contract_ops(c->st, n, c->ops.as<OpDesc>(), d_subset, n_subset,
-                                                      c->acc_tab.as<AccSlot>(), qslots - 1, d_out, c->stream), "contract");
-    HIP_TRY(c, launch_gather_scaled(d_out, nullptr, n_subset, norm2, d_out, c->stream), "scale");
-  } else {
-    TIMED(c, SWCS_K_POOL_CONTRACT, launch_pool_contract_det(c->st, c->exc, c->n, n, c->opmap.as<int>(), c->npairs,
-                                        d_sel, c->acc_tab.as<AccSlot>(), qslots - 1, 1, 0,
-                                        c->gacc.as<double>(), sigma_grid(c, n), c->stream), "contract");
-    HIP_TRY(c, launch_gather_scaled(c->gacc.as<double>(), d_subset, n_subset, norm2, d_out, c->stream), "gather");
+  // The query keys number at most q; a table for all of them that would
+  // not fit in 40% of the free device memory is split by key hash into
+  // batches, each a full query / push / contract pass over its own keys.
+  const double q = (double)std::min<u64>(nq, c->sector);
+  auto slots_for = [&](int nb) { return next_pow2((u64)std::max(64.0, (nb > 1 ? 2.5 : 2.0) * q / nb)); };
+  int nbatch = 1;
+  if (c->table_budget > 0 || (double)slots_for(1) * sizeof(AccSlot) > kQueryBoundBytes) {
+    double budget = (double)c->table_budget;
+    if (budget <= 0.0) {
+      size_t free_b = 0, total_b = 0;
+      if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) free_b = 0;
+      budget = std::max<double>(64.0 * 1024 * 1024, 0.4 * (double)(free_b + c->acc_tab.bytes));
+    }
+    while (nbatch < 4096 && (double)slots_for(nbatch) * sizeof(AccSlot) > budget) nbatch *= 2;
   }
+  for (;;) {
+    const u64 qslots = slots_for(nbatch);
+    HIP_TRY(c, c->acc_tab.ensure(qslots * sizeof(AccSlot)), "alloc sigma table");
+    if (op_major)
+      HIP_TRY(c, hipMemsetAsync(d_out, 0, (size_t)n_subset * 8, c->stream), "zero g");
+    else if (nbatch > 1)
+      HIP_TRY(c, hipMemsetAsync(c->gacc.p, 0, (size_t)c->K_pool * 8, c->stream), "zero g");
+    for (int b = 0; b < nbatch; ++b) {
+      HIP_TRY(c, hipMemsetAsync(c->acc_tab.p, 0, qslots * sizeof(AccSlot), c->stream), "clear table");
+      if (op_major)
+        HIP_TRY(c, launch_query_ops(c->st, n, c->ops.as<OpDesc>(), d_subset, n_subset,
+                                    c->acc_tab.as<AccSlot>(), qslots - 1, 0, nullptr, c->stream, nbatch, b),
+                "query set");
+      else
+        HIP_TRY(c, launch_query_set(c->st, c->exc, c->n, n, c->opmap.as<int>(), c->npairs, d_sel,
+                                    c->acc_tab.as<AccSlot>(), qslots - 1, 0, nullptr, sigma_grid(c, n),
+                                    c->stream, nbatch, b), "query set");
+      TIMED(c, SWCS_K_SIGMA_PUSH_INTO, launch_sigma_push_into(c->st, ints_view(c), c->exc, n, c->acc_tab.as<AccSlot>(),
+                                                              qslots - 1, sigma_grid(c, n), c->stream, nbatch, b),
+            "sigma push");
+      if (op_major)
+        TIMED(c, SWCS_K_CONTRACT_OPS, launch_contract_ops(c->st, n, c->ops.as<OpDesc>(), d_subset, n_subset,
+                                                          c->acc_tab.as<AccSlot>(), qslots - 1, d_out, c->stream,
+                                                          nbatch, b), "contract");
+      else
+        TIMED(c, SWCS_K_POOL_CONTRACT, launch_pool_contract_det(c->st, c->exc, c->n, n, c->opmap.as<int>(), c->npairs,
+                                                                d_sel, c->acc_tab.as<AccSlot>(), qslots - 1, nbatch, b,
+                                                                c->gacc.as<double>(), sigma_grid(c, n), c->stream),
+              "contract");
+    }
+    if (nbatch == 1) break;
+    // a batch holds about q / nbatch keys; one that filled its table is
+    // repeated with twice the batches
+    hipError_t e;
+    Counters h2 = read_counters(c, &e);  // synchronizes
+    if (e != hipSuccess) return hip_fail(c, e, "read counters");
+    if (!(h2.flags & kFlagOverflow)) break;
+    if (nbatch >= 4096) return fail(c, SWCS_E_DEVICE, "sigma table overflow");
+    nbatch *= 2;
+    h2.flags &= ~kFlagOverflow;
+    HIP_TRY(c, hipMemcpyAsync(c->ctr.p, &h2, sizeof(h2), hipMemcpyHostToDevice, c->stream), "counters");
+    c->hc = h2;
+  }
+  if (op_major)
+    HIP_TRY(c, launch_gather_scaled(d_out, nullptr, n_subset, norm2, d_out, c->stream), "scale");
+  else
+    HIP_TRY(c, launch_gather_scaled(c->gacc.as<double>(), d_subset, n_subset, norm2, d_out, c->stream), "gather");
   return SWCS_OK;
 }
 
@@ -1194,7 +1256,9 @@ int swcs_pool_gradients(swcs_ctx* c, const int32_t* subset, int64_t n_subset, do
     guess = std::min(bound_d, 1.5 * c->ext_count * std::max(1.0, (double)h.alive / c->ext_alive));
   // Tables up to 256 MB need no free-memory query.
   double budget = 256.0 * 1024 * 1024;
-  if (4.0 * guess * sizeof(AccSlot) > budget) {
+  if (c->table_budget > 0) {
+    budget = (double)c->table_budget;
+  } else if (4.0 * guess * sizeof(AccSlot) > budget) {
     size_t free_b = 0, total_b = 0;
     if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) free_b = 0;
     budget = std::max<double>(64.0 * 1024 * 1024, 0.4 * (double)(free_b + c->acc_tab.bytes));

@@ -56,6 +56,7 @@ SIGNATURES = {
     "swcs_last_error": (ctypes.c_char_p, [_vp]),
     "swcs_set_stream": (ctypes.c_int, [_vp, _vp]),
     "swcs_set_capacity": (ctypes.c_int, [_vp, _i64]),
+    "swcs_set_table_budget": (ctypes.c_int, [_vp, _i64]),
     "swcs_set_sigma_method": (ctypes.c_int, [_vp, ctypes.c_int]),
     "swcs_set_integrals": (ctypes.c_int, [_vp, _dp, _dp, ctypes.c_double]),
     "swcs_set_reference": (ctypes.c_int, [_vp, ctypes.c_uint64]),
@@ -175,6 +176,10 @@ class Context:
 
     def set_capacity(self, max_dets: int):
         self._check(self._lib.swcs_set_capacity(self._h, int(max_dets)))
+
+    def set_table_budget(self, nbytes: int):
+        """Cap on the pool-gradient sigma table in bytes (0 = from free memory)."""
+        self._check(self._lib.swcs_set_table_budget(self._h, int(nbytes)))
 
     def set_sigma_method(self, method: str):
         """'auto', 'enumerate' or 'hole_pairs' (how sigma_P is formed)."""

@@ -206,6 +206,33 @@ def test_pool_gradients_device(swcs, c2):
     ctx.close()
 
 
+@pytest.mark.parametrize("budget", [4096, 1 << 18])
+def test_table_budget_batches(swcs, c2, budget):
+    """A sigma-table budget far below the external space splits pool
+    gradients into key-hash batches on all three paths (full pool, operator-
+    major and determinant-major subsets); the sums over the batches match the
+    oracle, and budget 0 returns to one table."""
+    import torch
+    ctx = make_ctx(swcs, c2)
+    ctx.apply_ansatz(c2.ops, c2.theta, c2.eps)
+    ctx.set_table_budget(budget)
+    _say(f"[parity] table budget {budget}: full pool")
+    assert np.abs(ctx.pool_gradients() - c2.orc.pool_gradients(c2.st, c2.pool)).max() < TOL
+    rng = np.random.default_rng(14)
+    for size in (500, 6000):
+        _say(f"[parity] table budget {budget}: subset {size}")
+        subset = np.sort(rng.choice(len(c2.pool), size, replace=False)).astype(np.int32)
+        g_ref = c2.orc.pool_gradients(c2.st, c2.pool, subset=subset)
+        assert np.abs(ctx.pool_gradients(subset) - g_ref).max() < TOL
+        g = torch.zeros(size, dtype=torch.float64, device="cuda")
+        ctx.pool_gradients_device(torch.from_numpy(subset).cuda(), g)
+        torch.cuda.synchronize()
+        assert np.abs(g.cpu().numpy() - g_ref).max() < TOL
+    ctx.set_table_budget(0)
+    assert np.abs(ctx.pool_gradients() - c2.orc.pool_gradients(c2.st, c2.pool)).max() < TOL
+    ctx.close()
+
+
 def test_c3_parity_sampled_pool(swcs):
     case = config_case("c3")
     rng = np.random.default_rng(3)
@@ -443,6 +470,11 @@ def test_errors_and_capacity(swcs, c1):
         ctx.apply_ansatz(c1.ops[:1], np.array([np.nan]), 0.0)
     with pytest.raises(swcs.SwcsError):
         ctx.param_gradients(3)  # no ansatz applied yet
+    # cached sigma / sort scratch exists before the capacity failure, which
+    # gives it back; the next calls allocate it again
+    ctx.apply_ansatz(c1.ops, c1.theta, 0.0)
+    ctx.energy()
+    ctx.pool_gradients()
     ctx.set_capacity(8)
     with pytest.raises(swcs.SwcsError) as ei:
         ctx.apply_ansatz(c1.ops, c1.theta, 0.0)
@@ -450,6 +482,10 @@ def test_errors_and_capacity(swcs, c1):
     ctx.set_capacity(0)
     ctx.apply_ansatz(c1.ops, c1.theta, 0.0)
     assert np.array_equal(ctx.get_state()[1], c1.st.export()[1])
+    assert abs(ctx.energy()[0] - c1.orc.energy(c1.st)[0]) < TOL
+    assert np.abs(ctx.pool_gradients() - c1.orc.pool_gradients(c1.st, c1.pool)).max() < TOL
+    with pytest.raises(swcs.SwcsError):
+        ctx.set_table_budget(100)
     ctx.close()
 
 
