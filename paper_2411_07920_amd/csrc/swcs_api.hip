@@ -1052,8 +1052,8 @@ static int norm2_enqueue(swcs_ctx* c, u64 n) {
 }
 
 // The screened query table is sized from a bound on its key count (no host
-// round trip) when that table stays below this size, otherwise from an exact
-// count.
+// round trip) when that table stays below this size and no table budget is
+// set, otherwise from an exact count.
 constexpr double kQueryBoundBytes = 512.0 * 1024 * 1024;
 
 // Screened pool gradients of the n_subset operators d_subset (valid device
@@ -1079,9 +1079,11 @@ static int screened_gradients(swcs_ctx* c, u64 n, u64 alive, const int* d_subset
   const double bound = std::min<double>((double)c->sector,
                                         (double)alive * (double)(op_major ? n_subset : c->exc.total));
   u64 nq;
-  if (2.0 * bound * sizeof(AccSlot) <= kQueryBoundBytes) {
+  bool counted = false;
+  if (c->table_budget == 0 && 2.0 * bound * sizeof(AccSlot) <= kQueryBoundBytes) {
     nq = (u64)bound;
   } else {
+    counted = true;
     u64* qcount = c->scalars.as<u64>() + 16;
     HIP_TRY(c, hipMemsetAsync(qcount, 0, 8, c->stream), "zero counter");
     if (op_major)
@@ -1096,24 +1098,39 @@ static int screened_gradients(swcs_ctx* c, u64 n, u64 alive, const int* d_subset
   // The query keys number at most q; a table for all of them that would
   // not fit in 40% of the free device memory is split by key hash into
   // batches, each a full query / push / contract pass over its own keys.
-  const double q = (double)std::min<u64>(nq, c->sector);
+  // Counted pairs repeat keys many times over: the query keys are external
+  // determinants, so the distinct external count of the last full-pool call
+  // (scaled by the alive count) caps the estimate, and a pass that
+  // overflows is repeated with twice the estimate.
+  double q = (double)std::min<u64>(nq, c->sector);
+  bool estimated = false;
+  if (counted && c->ext_count > 0.0 && c->ext_alive > 0.0) {
+    const double est = 1.5 * c->ext_count * std::max(1.0, (double)alive / c->ext_alive);
+    if (est < q) {
+      q = est;
+      estimated = true;
+    }
+  }
+  double budget = (double)c->table_budget;
   auto slots_for = [&](int nb) { return next_pow2((u64)std::max(64.0, (nb > 1 ? 2.5 : 2.0) * q / nb)); };
-  int nbatch = 1;
-  if (c->table_budget > 0 || (double)slots_for(1) * sizeof(AccSlot) > kQueryBoundBytes) {
-    double budget = (double)c->table_budget;
+  auto batches = [&]() {
+    int nb = 1;
+    if (budget <= 0.0 && (double)slots_for(1) * sizeof(AccSlot) <= kQueryBoundBytes) return nb;
     if (budget <= 0.0) {
       size_t free_b = 0, total_b = 0;
       if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) free_b = 0;
       budget = std::max<double>(64.0 * 1024 * 1024, 0.4 * (double)(free_b + c->acc_tab.bytes));
     }
-    while (nbatch < 4096 && (double)slots_for(nbatch) * sizeof(AccSlot) > budget) nbatch *= 2;
-  }
-  for (;;) {
+    while (nb < 4096 && (double)slots_for(nb) * sizeof(AccSlot) > budget) nb *= 2;
+    return nb;
+  };
+  int nbatch = batches();
+  for (int attempt = 0;;) {
     const u64 qslots = slots_for(nbatch);
     HIP_TRY(c, c->acc_tab.ensure(qslots * sizeof(AccSlot)), "alloc sigma table");
     if (op_major)
       HIP_TRY(c, hipMemsetAsync(d_out, 0, (size_t)n_subset * 8, c->stream), "zero g");
-    else if (nbatch > 1)
+    else if (nbatch > 1 || attempt > 0)
       HIP_TRY(c, hipMemsetAsync(c->gacc.p, 0, (size_t)c->K_pool * 8, c->stream), "zero g");
     for (int b = 0; b < nbatch; ++b) {
       HIP_TRY(c, hipMemsetAsync(c->acc_tab.p, 0, qslots * sizeof(AccSlot), c->stream), "clear table");
@@ -1138,15 +1155,16 @@ static int screened_gradients(swcs_ctx* c, u64 n, u64 alive, const int* d_subset
                                                                 c->gacc.as<double>(), sigma_grid(c, n), c->stream),
               "contract");
     }
-    if (nbatch == 1) break;
-    // a batch holds about q / nbatch keys; one that filled its table is
-    // repeated with twice the batches
+    if (nbatch == 1 && !estimated) break;
+    // a batch holds about q / nbatch keys; a pass in which one filled its
+    // table is repeated with twice the estimate
     hipError_t e;
     Counters h2 = read_counters(c, &e);  // synchronizes
     if (e != hipSuccess) return hip_fail(c, e, "read counters");
     if (!(h2.flags & kFlagOverflow)) break;
-    if (nbatch >= 4096) return fail(c, SWCS_E_DEVICE, "sigma table overflow");
-    nbatch *= 2;
+    if (++attempt > 16) return fail(c, SWCS_E_DEVICE, "sigma table overflow");
+    q *= 2.0;
+    nbatch = batches();
     h2.flags &= ~kFlagOverflow;
     HIP_TRY(c, hipMemcpyAsync(c->ctr.p, &h2, sizeof(h2), hipMemcpyHostToDevice, c->stream), "counters");
     c->hc = h2;
