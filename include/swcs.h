@@ -177,7 +177,12 @@ int swcs_pool_gradients(swcs_ctx* ctx, const int32_t* subset, int64_t n_subset, 
  * stream has synchronized).  Indices outside [0, K) give NaN in d_g.  The
  * query table of the selected operators is sized from the bound
  * (alive determinants x min(n_subset, C)) when that table stays below
- * 512 MB, otherwise from an exact count, which synchronizes once. */
+ * 512 MB and no table budget is set (swcs_set_table_budget); otherwise from
+ * an exact count of (determinant, operator) pairs, capped by the distinct
+ * external count of the last full-pool call, which synchronizes once, and
+ * again after each pass that was split into key-hash batches or sized by
+ * that cap (a pass whose table filled is repeated with twice the estimate).
+ * Returns SWCS_E_OOM if even 4,096 batches do not fit the table memory. */
 int swcs_pool_gradients_device(swcs_ctx* ctx, const int32_t* d_subset, int64_t n_subset,
                                double* d_g);
 
