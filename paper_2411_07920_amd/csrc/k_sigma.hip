@@ -928,9 +928,12 @@ k_contract_ops(const u64* __restrict__ keys, const double* __restrict__ amps, u6
   if (acc != 0.0) unsafeAtomicAdd(&gslot[slot], acc);
 }
 
+// Inserts stop kAccMaxProbes slots from a key's home, and so does this
+// lookup: a table that overflowed is not walked end to end on every miss.
 __device__ inline double* acc_slot(AccSlot* tab, u64 mask, u64 key) {
   u64 h = mix64(key) & mask;
-  for (u64 probes = 0; probes <= mask; ++probes) {
+  const u64 lim = mask < kAccMaxProbes ? mask : kAccMaxProbes;
+  for (u64 probes = 0; probes <= lim; ++probes) {
     const u64 k = tab[h].key;
     if (k == key) return &tab[h].val;
     if (k == kEmptyKey) return nullptr;
