@@ -20,8 +20,18 @@ pool_gradients              closed form at HF; FD of an appended gate; dense
                             <psi|[H, A_k]|psi>
 param_gradients             central FD (eps = 0); trigonometric 5-point fit;
                             last-parameter identity; masked FD (eps > 0)
+apply_ansatz with ncut      dense expm chain pruned by a full sort after every
+                            gate; exact ties (theta = 0 gates) keep the
+                            smaller keys for every ncut
+occupations                 dense Jordan-Wigner number operators; sums equal
+                            the alpha and beta electron counts
 mlp_forward / mlp_backward  finite differences in float64
-features / select_subset    parity unpinned beyond hand-computed small cases
+adam_step                   closed forms for a constant gradient and for a
+                            single gradient followed by zeros (steps 1-6)
+features / fock_spatial     every feature of every c1 operator against its
+                            definition written out per operator, occupations
+                            from the dense vector
+select_subset               hand-computed case with ties
 mp2_uccsd                   closed-shell spatial MP2 energy formula; first-
                             order coefficients of the dense Hamiltonian
 ==========================  ===================================================

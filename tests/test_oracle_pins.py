@@ -481,3 +481,180 @@ def test_features_hand_case():
 def test_sector_size_counts():
     assert sector_size(6, 2, 2) == 225
     assert sector_size(14, 5, 5) == 4008004
+
+
+# ---------------------------------------------------------------- N_CUT
+def _top_ncut_dense(v, ncut):
+    """Brute-force N_CUT rule on a dense sector vector (basis ascending by
+    key): keep the ncut entries of largest |c|, equal magnitudes going to the
+    smaller key, zero the rest."""
+    order = sorted(range(len(v)), key=lambda i: (-abs(v[i]), i))
+    out = np.zeros_like(v)
+    keep = order[:ncut]
+    out[keep] = v[keep]
+    return out, set(keep)
+
+
+def test_ncut_chain_matches_dense_brute_force(medium):
+    """Sec. II.B (N_CUT pruning after every unitary): the oracle's chain
+    against a dense expm chain pruned by a full sort after every gate.  ncut is
+    below the number of nonzero amplitudes at every gate, so the dense vector
+    (which holds every determinant of the sector) and the sparse state prune
+    among the same candidates."""
+    s = medium
+    dense = s["dense"]
+    ncut = 60
+    v = dense.ref_vec(s["ref"])
+    for k, t in zip(s["ops"], s["theta"]):
+        v = scipy.sparse.linalg.expm_multiply(t * dense.generator_sparse(s["pool"][k]), v)
+        if np.count_nonzero(np.abs(v) > 1e-14) > ncut:
+            mags = np.sort(np.abs(v))[::-1]
+            # the cut must not fall inside a run of magnitudes that rounding
+            # could reorder between the dense and the sparse evaluation
+            assert mags[ncut - 1] - mags[ncut] > 1e-11
+            v, _ = _top_ncut_dense(v, ncut)
+    st = oracle.Oracle.apply_ansatz(s["pool"], s["ops"], s["theta"], 0.0, s["ref"], ncut=ncut)
+    keys, amps = st.export()
+    nz = {int(dense.basis[i]) for i in np.flatnonzero(v)}
+    assert set(keys.tolist()) == nz and len(keys) == ncut
+    assert np.abs(dense.vec(st.as_dict()) - v).max() < 1e-12
+
+
+def test_ncut_ties_keep_smaller_keys(medium):
+    """Exact ties: a state whose amplitudes repeat the same magnitudes, passed
+    through a theta = 0 gate (c = 1, sn = 0 leaves every amplitude unchanged
+    and adds exact-zero partners).  Exactly the ncut largest |c| survive and,
+    within a run of equal |c|, the smaller keys; checked against a brute-force
+    sort for every ncut from 1 to the state size."""
+    s = medium
+    basis = s["dense"].basis
+    rng = np.random.default_rng(5)
+    keys = np.sort(rng.choice(basis, 24, replace=False)).astype(np.uint64)
+    mags = np.array([0.5, 0.25, 0.25, 0.125] * 6)
+    signs = rng.choice([-1.0, 1.0], 24)
+    amps = mags[rng.permutation(24)] * signs
+    st = oracle.OracleState.from_arrays(keys, amps)
+    row = None
+    for r in s["pool"]:
+        acts = [_acts(r, int(k)) for k in keys]
+        if 0 < sum(acts) < 24:
+            row = r
+            break
+    assert row is not None
+    full = oracle.Oracle.apply_gate(st, row, 1.0, 0.0)
+    fk, fa = full.export()
+    assert len(fk) > 24 and np.count_nonzero(fa == 0.0) == len(fk) - 24
+    for ncut in range(1, len(fk) + 1):
+        out, d2 = oracle.Oracle.apply_gate_truncate(st, row, 1.0, 0.0, 0.0, ncut)
+        ok, oa = out.export()
+        order = sorted(range(len(fk)), key=lambda i: (-abs(fa[i]), int(fk[i])))
+        want = sorted(order[:ncut])
+        assert ok.tolist() == fk[want].tolist(), ncut
+        assert np.array_equal(oa, fa[want])
+        assert d2 == float((fa[sorted(order[ncut:])] ** 2).sum())
+
+
+# ---------------------------------------------------------------- occupations
+def test_occupations_match_dense_number_operators(medium):
+    """<n_P> = <psi|a+_P a_P|psi> / <psi|psi> with the number operators built
+    from the Jordan-Wigner ladder matrices, on a pruned (unnormalized) state;
+    the occupations sum to the electron count and each spin sums to its
+    electron count."""
+    s = medium
+    dense = s["dense"]
+    st = oracle.Oracle.apply_ansatz(s["pool"], s["ops"], s["theta"], 2e-3, s["ref"])
+    v = dense.vec(st.as_dict())
+    norm2 = v @ v
+    assert abs(norm2 - 1.0) > 1e-6          # pruning left it unnormalized
+    idx = dense.basis
+    occ = s["orc"].occupations(st)
+    for P in range(dense.nso):
+        nP = (dense.ad[P] @ dense.a[P]).tocsr()[idx][:, idx]
+        assert abs(occ[P] - (v @ (nP @ v)) / norm2) < 1e-14
+    assert abs(occ.sum() - s["ne"]) < 1e-13
+    assert abs(occ[0::2].sum() - s["ne"] // 2) < 1e-13
+    assert abs(occ[1::2].sum() - s["ne"] // 2) < 1e-13
+
+
+# ---------------------------------------------------------------- Adam
+def test_adam_constant_gradient_moves_lr_per_step():
+    """With a constant gradient g the bias-corrected moments are exactly g and
+    g^2 at every step (m_t = (1 - b1^t) g, v_t = (1 - b2^t) g^2), so step t
+    moves by -lr g / (|g| + eps).  A bias correction with the wrong power of
+    b1 or b2 at steps >= 2 fails this."""
+    g = np.array([0.7, -3.0, 2e-3])
+    lr, b1, b2, eps = 0.05, 0.9, 0.999, 1e-8
+    w, m, v = np.zeros(3), np.zeros(3), np.zeros(3)
+    for t in range(1, 7):
+        w, m, v = oracle.adam_step(w, m, v, g, lr, b1, b2, eps, t)
+        assert np.allclose(m, (1 - b1 ** t) * g, rtol=1e-14, atol=0)
+        assert np.allclose(v, (1 - b2 ** t) * g * g, rtol=1e-13, atol=0)
+        assert np.allclose(w, -t * lr * g / (np.abs(g) + eps), rtol=1e-10, atol=0)
+
+
+def test_adam_impulse_closed_form():
+    """A gradient g at step 1 and zero afterwards: m_t = b1^(t-1) (1 - b1) g,
+    v_t = b2^(t-1) (1 - b2) g^2, so the step-t update is
+    -lr * [b1^(t-1) (1-b1) / (1-b1^t)] g / (sqrt(b2^(t-1) (1-b2) / (1-b2^t)) |g| + eps)."""
+    g = np.array([1.5, -0.25])
+    lr, b1, b2, eps = 0.01, 0.8, 0.99, 1e-12
+    w, m, v = np.zeros(2), np.zeros(2), np.zeros(2)
+    want = np.zeros(2)
+    for t in range(1, 6):
+        gt = g if t == 1 else np.zeros(2)
+        w, m, v = oracle.adam_step(w, m, v, gt, lr, b1, b2, eps, t)
+        mh = b1 ** (t - 1) * (1 - b1) / (1 - b1 ** t) * g
+        vh = b2 ** (t - 1) * (1 - b2) / (1 - b2 ** t) * g * g
+        want = want - lr * mh / (np.sqrt(vh) + eps)
+        assert np.allclose(w, want, rtol=1e-12, atol=0), t
+
+
+# ---------------------------------------------------------------- features
+def test_features_match_per_operator_definitions(small):
+    """Every feature of every c1 pool operator against its definition written
+    out per operator: Fock diagonal f_pp = h_pp + sum_{j occ} [2 (pp|jj) -
+    (pj|jp)] with explicit loops, (pr|qs) of the spatial indices of a double,
+    |f_pq| of a single, occupations from the dense vector of a pruned state."""
+    s = small
+    dense = s["dense"]
+    n = s["n"]
+    h, eri, pool = s["h"], s["eri"], s["pool"]
+    st = oracle.Oracle.apply_ansatz(pool, s["ops"], s["theta"], 1e-3, s["ref"])
+    v = dense.vec(st.as_dict())
+    idx = dense.basis
+    occ_dense = np.array([(v @ ((dense.ad[P] @ dense.a[P]).tocsr()[idx][:, idx] @ v)) / (v @ v)
+                          for P in range(2 * n)])
+    n_occ = s["ne"] // 2
+    fock = np.zeros((n, n))
+    for p in range(n):
+        for q in range(n):
+            acc = h[p, q]
+            for j in range(n_occ):
+                acc += 2.0 * eri[p, q, j, j] - eri[p, j, j, q]
+            fock[p, q] = acc
+    assert np.abs(oracle.fock_spatial(h, eri, n_occ) - fock).max() < 1e-14
+    rng = np.random.default_rng(9)
+    K = len(pool)
+    prev = np.abs(rng.normal(size=K)) * (rng.random(K) < 0.7)
+    age = rng.integers(0, 20, K)
+    count = rng.integers(0, 3, K)
+    F = oracle.features(pool, fock, eri, s["orc"].occupations(st), prev, age, count)
+    for k in range(K):
+        P, Q, R, S = (int(x) for x in pool[k])
+        spins = [x & 1 for x in (P, Q, R, S) if x >= 0]
+        want = np.zeros(16)
+        for t, X in enumerate((P, Q, R, S)):
+            if X >= 0:
+                want[t] = fock[X // 2, X // 2]
+                want[5 + t] = occ_dense[X]
+        if R < 0:
+            want[4] = abs(fock[P // 2, Q // 2])
+            want[12] = 1.0
+        else:
+            want[4] = abs(eri[P // 2, R // 2, Q // 2, S // 2])
+            want[13 if spins[0] == spins[1] else 14] = 1.0
+        want[9] = prev[k]
+        want[10] = math.log10(prev[k] + 1e-16)
+        want[11] = age[k] / 10.0
+        want[15] = count[k]
+        assert np.abs(F[k] - want).max() < 1e-13, (k, np.abs(F[k] - want).argmax())
