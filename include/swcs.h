@@ -34,7 +34,8 @@
  * Energy.  E = <psi|H|psi> / <psi|psi> (Rayleigh quotient of the pruned state).
  * Memory.  Unless stated otherwise, pointer arguments are HOST pointers that
  *   are read (or written) during the call only; the library copies inputs to
- *   its own device memory, which it allocates with hipMalloc and frees in
+ *   its own device memory, which it obtains from the allocator set with
+ *   swcs_set_allocator (default hipMalloc / hipFree) and releases in
  *   swcs_destroy.  Screener calls (swcs_features .. swcs_select) take DEVICE
  *   pointers owned by the caller and enqueue work on the context stream
  *   without synchronizing.
@@ -58,6 +59,13 @@ extern "C" {
 #endif
 
 typedef struct swcs_ctx swcs_ctx;
+
+/* Device memory routines a caller may supply (swcs_set_allocator), e.g. a
+ * framework's caching allocator.  alloc_fn returns at least `bytes` of device
+ * memory on the context's device, 256-byte aligned, or NULL on failure;
+ * free_fn returns a block that alloc_fn gave.  `user` is passed through. */
+typedef void* (*swcs_alloc_fn)(size_t bytes, void* user);
+typedef void (*swcs_free_fn)(void* p, void* user);
 
 enum {
   SWCS_OK = 0,
@@ -86,9 +94,30 @@ const char* swcs_last_error(const swcs_ctx* ctx);
 /* Run all later work on `hip_stream` (a hipStream_t; NULL = null stream). */
 int swcs_set_stream(swcs_ctx* ctx, void* hip_stream);
 
+/* Route every later device allocation of the context through alloc_fn /
+ * free_fn (both NULL: hipMalloc / hipFree again).  Blocks allocated before
+ * the call are freed with the routines that allocated them.  The library
+ * calls them on the calling thread inside any entry point that needs memory,
+ * and may free a block while work it enqueued earlier on the context stream
+ * still reads it: the allocator must keep a freed block from other use until
+ * that stream has passed the free (a caching allocator bound to the context
+ * stream does; otherwise synchronize in free_fn).  An alloc_fn failure
+ * returns SWCS_E_OOM from the call that needed the memory.  Budgets the
+ * library derives from free device memory (state capacity, pool-gradient
+ * tables) count hipMemGetInfo's free bytes plus the bytes the library has
+ * handed back to free_fn; memory the allocator caches for others is not
+ * seen, so set swcs_set_capacity / swcs_set_table_budget to size them
+ * exactly.  SWCS_E_INVALID if only one routine is given. */
+int swcs_set_allocator(swcs_ctx* ctx, swcs_alloc_fn alloc_fn, swcs_free_fn free_fn, void* user);
+
 /* Upper bound on stored determinants (0 = library default, sized from free
- * device memory).  Growth past it fails with SWCS_E_CAPACITY. */
-int swcs_set_capacity(swcs_ctx* ctx, int64_t max_dets);
+ * device memory).  With allow_regrow != 0 the state arrays grow on demand up
+ * to that bound; growth past it fails with SWCS_E_CAPACITY.  With
+ * allow_regrow == 0 (max_dets > 0 required, else SWCS_E_INVALID) the arrays
+ * are reserved once at max_dets on the next apply or set_state and then kept:
+ * no state allocation happens inside later applies, and a chain that would
+ * need more fails with SWCS_E_CAPACITY and leaves no current state. */
+int swcs_set_capacity(swcs_ctx* ctx, int64_t max_dets, int allow_regrow);
 
 /* Upper bound, in bytes, on the hash table that pool gradients accumulate
  * sigma_P(X) in over the external space (Sec. II.C).  Keys that would not fit
@@ -182,6 +211,8 @@ int swcs_pool_gradients(swcs_ctx* ctx, const int32_t* subset, int64_t n_subset, 
  * external count of the last full-pool call, which synchronizes once, and
  * again after each pass that was split into key-hash batches or sized by
  * that cap (a pass whose table filled is repeated with twice the estimate).
+ * A bound-sized table is not checked on the host: if an insert found it full
+ * (more than 4,096 probes at load <= 1/2), every entry of d_g is NaN.
  * Returns SWCS_E_OOM if even 4,096 batches do not fit the table memory. */
 int swcs_pool_gradients_device(swcs_ctx* ctx, const int32_t* d_subset, int64_t n_subset,
                                double* d_g);

@@ -1008,6 +1008,16 @@ __global__ void k_nan_invalid(const int* __restrict__ in, long long count, long 
   }
 }
 
+// All of out[0, count) set to NaN when the counters carry flag `bit` (an
+// accumulation table that filled up), read on the device so that a call
+// that does not synchronize still cannot return partial sums as results.
+__global__ void k_nan_if_flag(const Counters* __restrict__ ctr, unsigned bit, double* __restrict__ out,
+                              long long count) {
+  if (!(ctr->flags & bit)) return;
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < count) out[t] = __longlong_as_double(0x7ff8000000000000LL);
+}
+
 // Per-block partial sums of psi^2 [P in D] for P < nso and of psi^2.
 __global__ void __launch_bounds__(256)
 k_occupations(const u64* __restrict__ keys, const double* __restrict__ amps, u64 n, int nso,
@@ -1233,6 +1243,14 @@ hipError_t launch_nan_invalid(const int* in, long long count, long long K, doubl
   if (count == 0) return hipSuccess;
   hipLaunchKernelGGL(k_nan_invalid, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, stream,
                      in, count, K, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_nan_if_flag(const Counters* ctr, unsigned bit, double* out, long long count,
+                              hipStream_t stream) {
+  if (count == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_nan_if_flag, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, stream,
+                     ctr, bit, out, count);
   return hipGetLastError();
 }
 

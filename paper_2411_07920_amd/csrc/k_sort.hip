@@ -453,7 +453,7 @@ hipError_t launch_compact_alive(const DeviceState& st, u64 n, const double* vals
                                 hipStream_t stream) {
   if (!vals) vals = st.amps;
   const int nblocks = (int)((n + kSortTile - 1) / kSortTile);
-  if (n == 0) return hipMemsetAsync(d_count, 0, sizeof(u64), stream);
+  if (n == 0) return launch_fill_u32(d_count, 0u, 2, stream);
   if ((u64)nblocks + scan_scratch_elems((u64)nblocks) > scratch_elems) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_alive_count, dim3(nblocks), dim3(kSortThreads), 0, stream, st.amps, n,
                      scratch);

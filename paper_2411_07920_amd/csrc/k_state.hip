@@ -7,6 +7,8 @@
 //   keys[cap]  uint64 determinant bit strings (never reordered within a run)
 //   amps[cap]  float64 amplitudes, kDeadBits for entries not in the state
 //   hash[2^k]  16-byte slots {key, index}, linear probing, load <= 1/2
+#include <algorithm>
+
 #include "gate_ops.h"
 
 namespace swcs {
@@ -483,6 +485,42 @@ hipError_t launch_mark_dead_range(double* amps, u64 lo, u64 hi, hipStream_t stre
   if (hi <= lo) return hipSuccess;
   hipLaunchKernelGGL(k_mark_dead_range, dim3(grid_for(hi - lo, 256, 8192)), dim3(256), 0, stream,
                      amps, lo, hi);
+  return hipGetLastError();
+}
+
+}  // namespace swcs
+
+namespace swcs {
+
+// Buffer clears and small host-to-device writes as kernels on the stream
+// (fills instead of runtime memsets, counters passed as kernel arguments), so
+// every step of a call is one of the library's own launches, in stream order,
+// and a caller may capture it.
+__global__ void k_fill_u32(unsigned* __restrict__ p, unsigned v, u64 words) {
+  const u64 stride = (u64)gridDim.x * blockDim.x;
+  for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += stride) p[i] = v;
+}
+
+__global__ void k_store_counters(Counters* __restrict__ ctr, Counters v) { *ctr = v; }
+
+__global__ void k_clear_flag(Counters* __restrict__ ctr, unsigned bit) {
+  atomicAnd(&ctr->flags, ~bit);
+}
+
+hipError_t launch_fill_u32(void* p, unsigned v, u64 words, hipStream_t stream) {
+  if (words == 0) return hipSuccess;
+  const u64 blocks = std::min<u64>((words + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, stream, (unsigned*)p, v, words);
+  return hipGetLastError();
+}
+
+hipError_t launch_store_counters(Counters* ctr, const Counters& v, hipStream_t stream) {
+  hipLaunchKernelGGL(k_store_counters, dim3(1), dim3(1), 0, stream, ctr, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_clear_flag(Counters* ctr, unsigned bit, hipStream_t stream) {
+  hipLaunchKernelGGL(k_clear_flag, dim3(1), dim3(1), 0, stream, ctr, bit);
   return hipGetLastError();
 }
 

@@ -18,28 +18,64 @@ namespace {
 
 thread_local std::string g_create_error;
 
+// Device memory routines of a context: the caller's (swcs_set_allocator)
+// or, when none is set, hipMalloc / hipFree.  `cached` counts the bytes the
+// library has handed back to the caller's allocator and not taken again, an
+// estimate of what a caching allocator holds for it beyond hipMemGetInfo's
+// free figure.
+struct Allocator {
+  swcs_alloc_fn alloc = nullptr;
+  swcs_free_fn free = nullptr;
+  void* user = nullptr;
+  size_t cached = 0;
+};
+
 // Device buffer that grows on demand (contents are not preserved on growth).
+// It is freed by the routines that allocated it, even if the context's
+// allocator has been replaced since.
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  Allocator* cur = nullptr;             // allocator of the next allocation
+  swcs_free_fn owner_free = nullptr;    // how p is freed (null: hipFree)
+  void* owner_user = nullptr;
+  Allocator* owner = nullptr;
   hipError_t ensure(size_t want) {
     if (want <= bytes && p) return hipSuccess;
-    if (p) (void)hipFree(p);
-    p = nullptr;
-    bytes = 0;
+    release();
     if (want == 0) want = 8;
-    hipError_t e = hipMalloc(&p, want);
-    if (e != hipSuccess) {
-      p = nullptr;
-      return e;
+    if (cur && cur->alloc) {
+      p = cur->alloc(want, cur->user);
+      if (!p) return hipErrorOutOfMemory;
+      owner_free = cur->free;
+      owner_user = cur->user;
+      owner = cur;
+      cur->cached = cur->cached > want ? cur->cached - want : 0;
+    } else {
+      hipError_t e = hipMalloc(&p, want);
+      if (e != hipSuccess) {
+        p = nullptr;
+        return e;
+      }
+      owner_free = nullptr;
+      owner = nullptr;
     }
     bytes = want;
     return hipSuccess;
   }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) {
+      if (owner_free) {
+        owner_free(p, owner_user);
+        if (owner) owner->cached += bytes;
+      } else {
+        (void)hipFree(p);
+      }
+    }
     p = nullptr;
     bytes = 0;
+    owner_free = nullptr;
+    owner = nullptr;
   }
   template <class T> T* as() const { return (T*)p; }
 };
@@ -73,7 +109,9 @@ struct swcs_ctx {
   int n = 0, na = 0, nb = 0, nso = 0, device = 0, num_cu = 1;
   hipStream_t stream = nullptr;
   std::string err;
+  Allocator alloc;          // device memory routines (swcs_set_allocator)
   int64_t max_dets = 0;
+  bool allow_regrow = true;  // false: state arrays reserved once at max_dets
   int64_t table_budget = 0;  // bytes for one sigma accumulation table (0 = from free memory)
   u64 sector = 0;
   ExcSpace exc;
@@ -134,15 +172,23 @@ struct swcs_ctx {
   // they were computed for the current version.
   u64 state_version = 1, diag_version = 0, norm_version = 0;
 
-  ~swcs_ctx() {
+  template <class F> void for_each_buf(F&& f) {
     DevBuf* all[] = {&h, &eri, &J, &K, &fock, &ops, &opmap, &gacc, &selected, &ncut_state, &filt, &keys, &amps, &hash, &ctr, &ckpt_n, &ckpt_ptrs,
                      &gate_tab, &gate_n_in,
                      &partial, &partial2, &sigma, &mu, &work, &seg_states, &acc_tab, &gbuf,
                      &subset_buf, &scalars, &exp_keys, &exp_amps, &exp_tmp_k, &exp_tmp_v,
                      &sort_scratch, &ctr_r, &occ, &sel_scratch, &mlp_partial, &mse_partial,
                      &hp_key, &hp_val, &hp_tk, &hp_tv, &diag};
-    for (DevBuf* b : all) b->release();
-    for (auto& b : ckpt) b.release();
+    for (DevBuf* b : all) f(*b);
+    for (auto& b : ckpt) f(b);
+  }
+  // Point every buffer's next allocation at the context's allocator.
+  void bind_buffers() {
+    for_each_buf([this](DevBuf& b) { b.cur = &alloc; });
+  }
+
+  ~swcs_ctx() {
+    for_each_buf([](DevBuf& b) { b.release(); });
     for (hipEvent_t e : ev_start) (void)hipEventDestroy(e);
     for (hipEvent_t e : ev_stop) (void)hipEventDestroy(e);
   }
@@ -253,6 +299,14 @@ Counters get_counters(swcs_ctx* c, hipError_t* e) {
   return read_counters(c, e);
 }
 
+// Device memory the context may still claim: hipMemGetInfo's free bytes plus
+// what it has given back to a caching allocator of the caller.
+size_t avail_bytes(swcs_ctx* c) {
+  size_t free_b = 0, total_b = 0;
+  if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) free_b = 0;
+  return free_b + c->alloc.cached;
+}
+
 // Buffers that hold nothing from one call to the next (the external sigma
 // table, hole-pair records, sort and export scratch): given back to the device
 // when the state needs the memory, and allocated again on their next use.
@@ -266,14 +320,17 @@ u64 max_capacity(swcs_ctx* c) {
   u64 cap = c->sector;
   if (c->max_dets > 0 && (u64)c->max_dets < cap) cap = (u64)c->max_dets;
   if (c->max_dets <= 0) {
-    size_t free_b = 0, total_b = 0;
-    if (hipMemGetInfo(&free_b, &total_b) == hipSuccess) {
-      u64 lim = (u64)(free_b / 96);  // keys + amps + 2 hash slots + headroom
-      if (lim < cap) cap = lim;
-    }
+    u64 lim = (u64)(avail_bytes(c) / 96);  // keys + amps + 2 hash slots + headroom
+    if (lim < cap) cap = lim;
   }
   if (cap < 16) cap = 16;
   return cap;
+}
+
+// Capacity of the state arrays when they may not be regrown: the configured
+// maximum (never more than the sector).
+u64 fixed_capacity(swcs_ctx* c) {
+  return std::max<u64>(16, std::min<u64>(c->sector, (u64)c->max_dets));
 }
 
 // (Re)allocate the state arrays with capacity `cap`, preserving the first
@@ -281,6 +338,8 @@ u64 max_capacity(swcs_ctx* c) {
 int state_reserve(swcs_ctx* c, u64 cap, u64 n_keep) {
   const u64 hslots = next_pow2(2 * cap);
   DevBuf nk, na;
+  nk.cur = &c->alloc;
+  na.cur = &c->alloc;
   HIP_TRY(c, nk.ensure(cap * sizeof(u64)), "alloc keys");
   HIP_TRY(c, na.ensure(cap * sizeof(double)), "alloc amps");
   if (n_keep > 0) {
@@ -325,9 +384,14 @@ int build_filter(swcs_ctx* c, u64 n, u64 alive) {
 
 // Reset the state to the single reference determinant.
 int state_reset_to_reference(swcs_ctx* c) {
-  u64 cap = next_pow2(std::max<u64>(4096, 4 * c->peak_n));
-  if (cap > c->st.cap && cap > max_capacity(c)) release_scratch(c);
-  cap = std::min<u64>(cap, max_capacity(c));
+  u64 cap;
+  if (!c->allow_regrow) {
+    cap = fixed_capacity(c);
+  } else {
+    cap = next_pow2(std::max<u64>(4096, 4 * c->peak_n));
+    if (cap > c->st.cap && cap > max_capacity(c)) release_scratch(c);
+    cap = std::min<u64>(cap, max_capacity(c));
+  }
   if (cap < 2) cap = 2;
   if (!c->keys.p || c->st.cap != cap) {
     int r = state_reserve(c, cap, 0);
@@ -436,7 +500,7 @@ int run_chain(swcs_ctx* c, const int32_t* op_idx, const double* cs, const double
     g0 = (int64_t)h.stop_gate;
     h.flags &= ~kFlagStopped;
     h.stop_gate = 0;
-    HIP_TRY(c, hipMemcpyAsync(c->ctr.p, &h, sizeof(h), hipMemcpyHostToDevice, c->stream), "counters");
+    HIP_TRY(c, launch_store_counters(c->st.ctr, h, c->stream), "counters");
   }
   for (int attempt = 0; attempt < 64; ++attempt) {
     for (int64_t g = g0; g < M; ++g) {
@@ -462,10 +526,19 @@ int run_chain(swcs_ctx* c, const int32_t* op_idx, const double* cs, const double
     hipError_t e;
     Counters h = read_counters(c, &e);
     if (e != hipSuccess) return hip_fail(c, e, "read counters");
-    if (h.flags & kFlagOverflow) return fail(c, SWCS_E_DEVICE, "internal overflow in gate chain");
+    if (h.flags & kFlagOverflow) {
+      h.flags &= ~(kFlagOverflow | kFlagStopped);
+      HIP_TRY(c, launch_store_counters(c->st.ctr, h, c->stream), "counters");
+      c->hc_valid = false;
+      return fail(c, SWCS_E_DEVICE, "internal overflow in gate chain");
+    }
     if (!(h.flags & kFlagStopped)) {
       *out = h;
       return SWCS_OK;
+    }
+    if (!c->allow_regrow) {
+      c->have_state = false;  // the chain stopped part way
+      return fail(c, SWCS_E_CAPACITY, "state exceeds the fixed capacity (regrowth disabled)");
     }
     // Grow so that the stopped gate (and a few more) fit, then resume.
     const u64 need = h.n + std::min<u64>(h.alive, c->sector > h.n ? c->sector - h.n : 0);
@@ -482,8 +555,7 @@ int run_chain(swcs_ctx* c, const int32_t* op_idx, const double* cs, const double
     g0 = (int64_t)h.stop_gate;
     h.flags &= ~kFlagStopped;
     h.stop_gate = 0;
-    HIP_TRY(c, hipMemcpyAsync(c->ctr.p, &h, sizeof(h), hipMemcpyHostToDevice, c->stream), "counters");
-    HIP_TRY(c, hipStreamSynchronize(c->stream), "sync");
+    HIP_TRY(c, launch_store_counters(c->st.ctr, h, c->stream), "counters");
     // Checkpoint of the gate where the chain resumes was skipped if it lies
     // on a segment boundary: the loop above re-enqueues it.
   }
@@ -531,6 +603,7 @@ int swcs_create(int n_spatial, int n_alpha, int n_beta, int device, swcs_ctx** o
   double sec = binom(n_spatial, n_alpha) * binom(n_spatial, n_beta);
   c->sector = sec > 1e18 ? (u64)1e18 : (u64)sec;
   c->exc = make_exc_space(n_spatial, n_alpha, n_beta);
+  c->bind_buffers();
   if (c->ctr.ensure(sizeof(Counters)) != hipSuccess || c->scalars.ensure(64 * sizeof(double)) != hipSuccess) {
     g_create_error = "device allocation failed";
     delete c;
@@ -566,10 +639,23 @@ int swcs_set_stream(swcs_ctx* c, void* hip_stream) {
   return SWCS_OK;
 }
 
-int swcs_set_capacity(swcs_ctx* c, int64_t max_dets) {
+int swcs_set_capacity(swcs_ctx* c, int64_t max_dets, int allow_regrow) {
   if (!c) return SWCS_E_INVALID;
   if (max_dets < 0) return fail(c, SWCS_E_INVALID, "max_dets < 0");
+  if (!allow_regrow && max_dets == 0) return fail(c, SWCS_E_INVALID, "a fixed capacity needs max_dets > 0");
   c->max_dets = max_dets;
+  c->allow_regrow = allow_regrow != 0;
+  return SWCS_OK;
+}
+
+int swcs_set_allocator(swcs_ctx* c, swcs_alloc_fn alloc_fn, swcs_free_fn free_fn, void* user) {
+  if (!c) return SWCS_E_INVALID;
+  if ((alloc_fn == nullptr) != (free_fn == nullptr))
+    return fail(c, SWCS_E_INVALID, "alloc_fn and free_fn must both be set or both be NULL");
+  c->alloc.alloc = alloc_fn;
+  c->alloc.free = free_fn;
+  c->alloc.user = user;
+  c->alloc.cached = 0;
   return SWCS_OK;
 }
 
@@ -626,10 +712,10 @@ int swcs_set_integrals(swcs_ctx* c, const double* h, const double* eri, double e
   HIP_TRY(c, c->J.ensure(n2 * 8), "alloc J");
   HIP_TRY(c, c->K.ensure(n2 * 8), "alloc K");
   HIP_TRY(c, c->fock.ensure(n2 * 8), "alloc fock");
-  HIP_TRY(c, hipMemcpy(c->h.p, h, n2 * 8, hipMemcpyHostToDevice), "copy h");
-  HIP_TRY(c, hipMemcpy(c->eri.p, eri, n4 * 8, hipMemcpyHostToDevice), "copy eri");
-  HIP_TRY(c, hipMemcpy(c->J.p, Jh.data(), n2 * 8, hipMemcpyHostToDevice), "copy J");
-  HIP_TRY(c, hipMemcpy(c->K.p, Kh.data(), n2 * 8, hipMemcpyHostToDevice), "copy K");
+  HIP_TRY(c, hipMemcpyAsync(c->h.p, h, n2 * 8, hipMemcpyHostToDevice, c->stream), "copy h");
+  HIP_TRY(c, hipMemcpyAsync(c->eri.p, eri, n4 * 8, hipMemcpyHostToDevice, c->stream), "copy eri");
+  HIP_TRY(c, hipMemcpyAsync(c->J.p, Jh.data(), n2 * 8, hipMemcpyHostToDevice, c->stream), "copy J");
+  HIP_TRY(c, hipMemcpyAsync(c->K.p, Kh.data(), n2 * 8, hipMemcpyHostToDevice, c->stream), "copy K");
   HIP_TRY(c, launch_fock(c->h.as<double>(), c->eri.as<double>(), n, c->na, c->fock.as<double>(),
                          c->stream), "fock");
   HIP_TRY(c, hipStreamSynchronize(c->stream), "sync");
@@ -703,11 +789,17 @@ int swcs_set_pool(swcs_ctx* c, const int32_t* rows, int64_t K) {
       return fail(c, SWCS_E_INVALID, "pool row " + std::to_string(k) + " duplicates an earlier row");
     optab[(size_t)slot] = (int)k;
   }
+  // earlier work of the stream may still read the old tables
+  HIP_TRY(c, hipStreamSynchronize(c->stream), "sync");
   HIP_TRY(c, c->opmap.ensure(optab.size() * sizeof(int)), "alloc generator table");
-  HIP_TRY(c, hipMemcpy(c->opmap.p, optab.data(), optab.size() * sizeof(int), hipMemcpyHostToDevice), "copy generator table");
+  HIP_TRY(c, hipMemcpyAsync(c->opmap.p, optab.data(), optab.size() * sizeof(int), hipMemcpyHostToDevice, c->stream),
+          "copy generator table");
   c->npairs = (int)npairs;
   HIP_TRY(c, c->ops.ensure(std::max<size_t>(1, (size_t)K) * sizeof(OpDesc)), "alloc pool");
-  if (K > 0) HIP_TRY(c, hipMemcpy(c->ops.p, ops.data(), (size_t)K * sizeof(OpDesc), hipMemcpyHostToDevice), "copy pool");
+  if (K > 0)
+    HIP_TRY(c, hipMemcpyAsync(c->ops.p, ops.data(), (size_t)K * sizeof(OpDesc), hipMemcpyHostToDevice, c->stream),
+            "copy pool");
+  HIP_TRY(c, hipStreamSynchronize(c->stream), "sync");
   c->ops_host.swap(ops);
   c->pool_rows.assign(rows, rows + 4 * K);
   c->K_pool = K;
@@ -737,7 +829,10 @@ static int apply_common(swcs_ctx* c, const int32_t* op_idx, const double* theta,
     if (r) return r;
     c->seg = std::max<int>(1, (int)std::ceil(std::sqrt((double)std::max<int64_t>(1, M))));
     const int nck = (int)((M + c->seg - 1) / c->seg) + 1;
-    if ((int)c->ckpt.size() < nck) c->ckpt.resize(nck);
+    if ((int)c->ckpt.size() < nck) {
+      c->ckpt.resize(nck);
+      c->bind_buffers();
+    }
     HIP_TRY(c, c->ckpt_n.ensure((size_t)nck * sizeof(u64)), "alloc ckpt sizes");
   }
   Counters h;
@@ -797,19 +892,24 @@ int swcs_set_state(swcs_ctx* c, const uint64_t* keys, const double* amps, int64_
     if (i > 0 && sorted[(size_t)i] == sorted[(size_t)i - 1]) return fail(c, SWCS_E_INVALID, "duplicate key");
   }
   u64 cap = next_pow2(std::max<u64>(4096, 2 * (u64)n));
-  cap = std::min<u64>(cap, max_capacity(c));
+  cap = c->allow_regrow ? std::min<u64>(cap, max_capacity(c)) : fixed_capacity(c);
   if (cap < (u64)n) return fail(c, SWCS_E_CAPACITY, "state exceeds the maximum capacity");
-  int r = state_reserve(c, cap, 0);
-  if (r) return r;
+  int r;
+  if (!c->keys.p || c->st.cap != cap) {
+    r = state_reserve(c, cap, 0);
+    if (r) return r;
+  } else {
+    HIP_TRY(c, launch_hash_clear(c->st.hash, c->st.hmask + 1, c->stream), "hash clear");
+  }
   if (n > 0) {
-    HIP_TRY(c, hipMemcpy(c->keys.p, keys, n * sizeof(u64), hipMemcpyHostToDevice), "copy keys");
-    HIP_TRY(c, hipMemcpy(c->amps.p, amps, n * sizeof(double), hipMemcpyHostToDevice), "copy amps");
+    HIP_TRY(c, hipMemcpyAsync(c->keys.p, keys, n * sizeof(u64), hipMemcpyHostToDevice, c->stream), "copy keys");
+    HIP_TRY(c, hipMemcpyAsync(c->amps.p, amps, n * sizeof(double), hipMemcpyHostToDevice, c->stream), "copy amps");
   }
   Counters h;
   std::memset(&h, 0, sizeof(h));
   h.n = (u64)n;
   h.alive = (u64)n;
-  HIP_TRY(c, hipMemcpy(c->ctr.p, &h, sizeof(h), hipMemcpyHostToDevice), "counters");
+  HIP_TRY(c, launch_store_counters(c->st.ctr, h, c->stream), "counters");
   if (n > 0) HIP_TRY(c, launch_hash_build(c->st, (u64)n, c->stream), "hash build");
   r = build_filter(c, (u64)n, (u64)n);
   if (r) return r;
@@ -1065,7 +1165,7 @@ constexpr double kQueryBoundBytes = 512.0 * 1024 * 1024;
 static int mark_subset(swcs_ctx* c, const int* d_subset, int64_t n_subset);
 
 static int screened_gradients(swcs_ctx* c, u64 n, u64 alive, const int* d_subset, int64_t n_subset,
-                              const double* norm2, double* d_out) {
+                              const double* norm2, double* d_out, bool may_sync) {
   const bool op_major = n_subset <= c->exc.total;
   const unsigned char* d_sel = nullptr;
   if (!op_major) {
@@ -1074,7 +1174,6 @@ static int screened_gradients(swcs_ctx* c, u64 n, u64 alive, const int* d_subset
     int r = mark_subset(c, d_subset, n_subset);
     if (r) return r;
     d_sel = c->selected.as<unsigned char>();
-    HIP_TRY(c, hipMemsetAsync(c->gacc.p, 0, (size_t)c->K_pool * 8, c->stream), "zero g");
   }
   const double bound = std::min<double>((double)c->sector,
                                         (double)alive * (double)(op_major ? n_subset : c->exc.total));
@@ -1085,7 +1184,7 @@ static int screened_gradients(swcs_ctx* c, u64 n, u64 alive, const int* d_subset
   } else {
     counted = true;
     u64* qcount = c->scalars.as<u64>() + 16;
-    HIP_TRY(c, hipMemsetAsync(qcount, 0, 8, c->stream), "zero counter");
+    HIP_TRY(c, launch_fill_u32(qcount, 0u, 2, c->stream), "zero counter");
     if (op_major)
       HIP_TRY(c, launch_query_ops(c->st, n, c->ops.as<OpDesc>(), d_subset, n_subset, nullptr, 0, 1,
                                   qcount, c->stream), "count");
@@ -1116,24 +1215,22 @@ static int screened_gradients(swcs_ctx* c, u64 n, u64 alive, const int* d_subset
   auto batches = [&]() {
     int nb = 1;
     if (budget <= 0.0 && (double)slots_for(1) * sizeof(AccSlot) <= kQueryBoundBytes) return nb;
-    if (budget <= 0.0) {
-      size_t free_b = 0, total_b = 0;
-      if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) free_b = 0;
-      budget = std::max<double>(64.0 * 1024 * 1024, 0.4 * (double)(free_b + c->acc_tab.bytes));
-    }
+    if (budget <= 0.0)
+      budget = std::max<double>(64.0 * 1024 * 1024, 0.4 * (double)(avail_bytes(c) + c->acc_tab.bytes));
     while (nb < 4096 && (double)slots_for(nb) * sizeof(AccSlot) > budget) nb *= 2;
     return nb;
   };
   int nbatch = batches();
+  bool checked = false;
   for (int attempt = 0;;) {
     const u64 qslots = slots_for(nbatch);
     HIP_TRY(c, c->acc_tab.ensure(qslots * sizeof(AccSlot)), "alloc sigma table");
     if (op_major)
-      HIP_TRY(c, hipMemsetAsync(d_out, 0, (size_t)n_subset * 8, c->stream), "zero g");
-    else if (nbatch > 1 || attempt > 0)
-      HIP_TRY(c, hipMemsetAsync(c->gacc.p, 0, (size_t)c->K_pool * 8, c->stream), "zero g");
+      HIP_TRY(c, launch_fill_u32(d_out, 0u, (u64)n_subset * 2, c->stream), "zero g");
+    else
+      HIP_TRY(c, launch_fill_u32(c->gacc.p, 0u, (u64)c->K_pool * 2, c->stream), "zero g");
     for (int b = 0; b < nbatch; ++b) {
-      HIP_TRY(c, hipMemsetAsync(c->acc_tab.p, 0, qslots * sizeof(AccSlot), c->stream), "clear table");
+      HIP_TRY(c, launch_fill_u32(c->acc_tab.p, 0u, qslots * (sizeof(AccSlot) / 4), c->stream), "clear table");
       if (op_major)
         HIP_TRY(c, launch_query_ops(c->st, n, c->ops.as<OpDesc>(), d_subset, n_subset,
                                     c->acc_tab.as<AccSlot>(), qslots - 1, 0, nullptr, c->stream, nbatch, b),
@@ -1155,24 +1252,32 @@ static int screened_gradients(swcs_ctx* c, u64 n, u64 alive, const int* d_subset
                                                                 c->gacc.as<double>(), sigma_grid(c, n), c->stream),
               "contract");
     }
-    if (nbatch == 1 && !estimated) break;
-    // a batch holds about q / nbatch keys; a pass in which one filled its
-    // table is repeated with twice the estimate
+    // A single bound-sized table (at most half full) is checked on the
+    // device when the caller does not synchronize (below); otherwise a pass
+    // in which a table filled is repeated with twice the estimate.
+    if (!may_sync && nbatch == 1 && !estimated) break;
+    checked = true;
     hipError_t e;
     Counters h2 = read_counters(c, &e);  // synchronizes
     if (e != hipSuccess) return hip_fail(c, e, "read counters");
     if (!(h2.flags & kFlagOverflow)) break;
+    h2.flags &= ~kFlagOverflow;
+    HIP_TRY(c, launch_store_counters(c->st.ctr, h2, c->stream), "counters");
+    c->hc = h2;
     if (++attempt > 16) return fail(c, SWCS_E_DEVICE, "sigma table overflow");
     q *= 2.0;
     nbatch = batches();
-    h2.flags &= ~kFlagOverflow;
-    HIP_TRY(c, hipMemcpyAsync(c->ctr.p, &h2, sizeof(h2), hipMemcpyHostToDevice, c->stream), "counters");
-    c->hc = h2;
   }
   if (op_major)
     HIP_TRY(c, launch_gather_scaled(d_out, nullptr, n_subset, norm2, d_out, c->stream), "scale");
   else
     HIP_TRY(c, launch_gather_scaled(c->gacc.as<double>(), d_subset, n_subset, norm2, d_out, c->stream), "gather");
+  if (!checked) {
+    // unchecked pass: a table that filled turns every result into NaN, and
+    // the flag is cleared for later calls
+    HIP_TRY(c, launch_nan_if_flag(c->st.ctr, kFlagOverflow, d_out, n_subset, c->stream), "overflow check");
+    HIP_TRY(c, launch_clear_flag(c->st.ctr, kFlagOverflow, c->stream), "overflow clear");
+  }
   return SWCS_OK;
 }
 
@@ -1196,8 +1301,9 @@ static int pool_setup(swcs_ctx* c, Counters* h) {
 }
 
 static int mark_subset(swcs_ctx* c, const int* d_subset, int64_t n_subset) {
-  HIP_TRY(c, c->selected.ensure((size_t)c->K_pool), "alloc selection");
-  HIP_TRY(c, hipMemsetAsync(c->selected.p, 0, (size_t)c->K_pool, c->stream), "zero selection");
+  const u64 words = ((u64)c->K_pool + 3) / 4;
+  HIP_TRY(c, c->selected.ensure(words * 4), "alloc selection");
+  HIP_TRY(c, launch_fill_u32(c->selected.p, 0u, words, c->stream), "zero selection");
   HIP_TRY(c, launch_mark_selected(d_subset, n_subset, c->selected.as<unsigned char>(), c->stream), "mark");
   return SWCS_OK;
 }
@@ -1214,7 +1320,7 @@ int swcs_pool_gradients_device(swcs_ctx* c, const int32_t* d_subset, int64_t n_s
   HIP_TRY(c, launch_sanitize_subset(d_subset, n_subset, c->K_pool, c->subset_buf.as<int>(), c->stream), "subset");
   const int* sub = c->subset_buf.as<int>();
   const double* norm2 = c->scalars.as<double>() + 2;
-  r = screened_gradients(c, h.n, h.alive, sub, n_subset, norm2, d_g);
+  r = screened_gradients(c, h.n, h.alive, sub, n_subset, norm2, d_g, false);
   if (r) return r;
   HIP_TRY(c, launch_nan_invalid(d_subset, n_subset, c->K_pool, d_g, c->stream), "flag invalid");
   return SWCS_OK;
@@ -1245,15 +1351,16 @@ int swcs_pool_gradients(swcs_ctx* c, const int32_t* subset, int64_t n_subset, do
   if (subset) {
     HIP_TRY(c, c->subset_buf.ensure((size_t)n_subset * 4), "alloc subset");
     HIP_TRY(c, hipMemcpyAsync(c->subset_buf.p, subset, (size_t)n_subset * 4, hipMemcpyHostToDevice, c->stream), "copy subset");
+    // the host array is pageable: wait for the copy before the kernels that
+    // read it are enqueued
+    HIP_TRY(c, hipStreamSynchronize(c->stream), "sync");
     d_subset = c->subset_buf.as<int>();
   }
   if (subset && 2 * n_subset < c->K_pool) {
-    r = screened_gradients(c, n, h.alive, d_subset, n_subset, norm2, c->gbuf.as<double>());
+    r = screened_gradients(c, n, h.alive, d_subset, n_subset, norm2, c->gbuf.as<double>(), true);
     if (r) return r;
     HIP_TRY(c, hipMemcpyAsync(g_out, c->gbuf.p, (size_t)count * 8, hipMemcpyDeviceToHost, c->stream), "copy g");
-    Counters hq = read_counters(c, &e);
-    if (e != hipSuccess) return hip_fail(c, e, "read counters");
-    if (hq.flags & kFlagOverflow) return fail(c, SWCS_E_DEVICE, "sigma table overflow");
+    HIP_TRY(c, hipStreamSynchronize(c->stream), "sync");
     return SWCS_OK;
   }
   if (subset) {
@@ -1277,9 +1384,7 @@ int swcs_pool_gradients(swcs_ctx* c, const int32_t* subset, int64_t n_subset, do
   if (c->table_budget > 0) {
     budget = (double)c->table_budget;
   } else if (4.0 * guess * sizeof(AccSlot) > budget) {
-    size_t free_b = 0, total_b = 0;
-    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) free_b = 0;
-    budget = std::max<double>(64.0 * 1024 * 1024, 0.4 * (double)(free_b + c->acc_tab.bytes));
+    budget = std::max<double>(64.0 * 1024 * 1024, 0.4 * (double)(avail_bytes(c) + c->acc_tab.bytes));
   }
   const int sgrid = sigma_grid(c, n);
   for (int attempt = 0;; ++attempt) {
@@ -1290,10 +1395,10 @@ int swcs_pool_gradients(swcs_ctx* c, const int32_t* subset, int64_t n_subset, do
     if (nbatch == 1 && 2.0 * (double)slots * sizeof(AccSlot) <= budget) slots *= 2;
     HIP_TRY(c, c->acc_tab.ensure(slots * sizeof(AccSlot)), "alloc sigma table");
     HIP_TRY(c, c->partial2.ensure((size_t)sgrid * nbatch * 8), "alloc partials");
-    HIP_TRY(c, hipMemsetAsync(c->gacc.p, 0, (size_t)c->K_pool * 8, c->stream), "zero g");
+    HIP_TRY(c, launch_fill_u32(c->gacc.p, 0u, (u64)c->K_pool * 2, c->stream), "zero g");
     double* ins = c->partial2.as<double>();
     for (int b = 0; b < nbatch; ++b) {
-      HIP_TRY(c, hipMemsetAsync(c->acc_tab.p, 0, slots * sizeof(AccSlot), c->stream), "clear table");
+      HIP_TRY(c, launch_fill_u32(c->acc_tab.p, 0u, slots * (sizeof(AccSlot) / 4), c->stream), "clear table");
       TIMED(c, SWCS_K_SIGMA_PUSH, launch_sigma_push(c->st, ints_view(c), c->exc, n, c->acc_tab.as<AccSlot>(), slots - 1,
                                    nbatch, b, ins + (size_t)b * sgrid, sgrid, c->stream), "sigma push");
       TIMED(c, SWCS_K_POOL_CONTRACT, launch_pool_contract_det(c->st, c->exc, c->n, n, c->opmap.as<int>(), c->npairs,
@@ -1315,11 +1420,11 @@ int swcs_pool_gradients(swcs_ctx* c, const int32_t* subset, int64_t n_subset, do
       c->ext_alive = (double)h.alive;
       return SWCS_OK;
     }
+    h2.flags &= ~kFlagOverflow;
+    HIP_TRY(c, launch_store_counters(c->st.ctr, h2, c->stream), "counters");
+    c->hc = h2;
     if (guess >= bound_d || attempt >= 16) return fail(c, SWCS_E_DEVICE, "sigma table overflow");
     guess = std::min(bound_d, 2.0 * guess);
-    h2.flags &= ~kFlagOverflow;
-    HIP_TRY(c, hipMemcpyAsync(c->ctr.p, &h2, sizeof(h2), hipMemcpyHostToDevice, c->stream), "counters");
-    c->hc = h2;
   }
 }
 
@@ -1384,7 +1489,7 @@ int swcs_param_gradients(swcs_ctx* c, double* dE, double* E_out) {
       const int64_t g_hi = std::min<int64_t>(M, g_lo + seg);
       const int len = (int)(g_hi - g_lo);
       HIP_TRY(c, launch_restore(W, c->ckpt[j].as<double>(), c->ckpt_n.as<u64>() + j, n, c->stream), "restore");
-      HIP_TRY(c, hipMemsetAsync(lc, 0, (size_t)len * sizeof(u64), c->stream), "zero log counters");
+      HIP_TRY(c, launch_fill_u32(lc, 0u, (u64)len * 2, c->stream), "zero log counters");
       for (int t = 0; t < len; ++t) {
         const int64_t g = g_lo + t;
         TIMED(c, SWCS_K_GATE_REPLAY, launch_gate_replay(c->st, W, n, c->ops_host[c->a_ops[g]], c->a_c[g], c->a_s[g],
@@ -1407,7 +1512,12 @@ int swcs_param_gradients(swcs_ctx* c, double* dE, double* E_out) {
   HIP_TRY(c, hipMemcpyAsync(nn_host, nn, 16, hipMemcpyDeviceToHost, c->stream), "copy energy");
   Counters hchk = read_counters(c, &e);  // synchronizes
   if (e != hipSuccess) return hip_fail(c, e, "sync");
-  if (hchk.flags & kFlagOverflow) return fail(c, SWCS_E_DEVICE, "recomputation diverged from the forward run");
+  if (hchk.flags & kFlagOverflow) {
+    hchk.flags &= ~kFlagOverflow;
+    HIP_TRY(c, launch_store_counters(c->st.ctr, hchk, c->stream), "counters");
+    c->hc = hchk;
+    return fail(c, SWCS_E_DEVICE, "recomputation diverged from the forward run");
+  }
   if (E_out) *E_out = nn_host[0] / nn_host[1];
   return SWCS_OK;
 }

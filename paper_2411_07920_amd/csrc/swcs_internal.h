@@ -286,6 +286,11 @@ __device__ inline bool filter_maybe(const unsigned* __restrict__ filt, u64 fmask
 
 // Launch wrappers (defined in the .hip files).  All enqueue on `stream`.
 struct PairRec;
+hipError_t launch_fill_u32(void* p, unsigned v, u64 words, hipStream_t stream);
+hipError_t launch_store_counters(Counters* ctr, const Counters& v, hipStream_t stream);
+hipError_t launch_clear_flag(Counters* ctr, unsigned bit, hipStream_t stream);
+hipError_t launch_nan_if_flag(const Counters* ctr, unsigned bit, double* out, long long count,
+                              hipStream_t stream);
 hipError_t launch_hash_clear(HashSlot* tab, u64 slots, hipStream_t stream);
 hipError_t launch_hash_build(const DeviceState& st, u64 n, hipStream_t stream);
 hipError_t launch_gate(const DeviceState& st, const OpDesc& op, double c, double sn, double eps,

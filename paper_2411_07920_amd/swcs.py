@@ -7,9 +7,11 @@ the built library fails loudly: there is no CPU fallback.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import math
 import os
+import weakref
 
 import numpy as np
 
@@ -55,7 +57,8 @@ SIGNATURES = {
     "swcs_destroy": (None, [_vp]),
     "swcs_last_error": (ctypes.c_char_p, [_vp]),
     "swcs_set_stream": (ctypes.c_int, [_vp, _vp]),
-    "swcs_set_capacity": (ctypes.c_int, [_vp, _i64]),
+    "swcs_set_capacity": (ctypes.c_int, [_vp, _i64, ctypes.c_int]),
+    "swcs_set_allocator": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "swcs_set_table_budget": (ctypes.c_int, [_vp, _i64]),
     "swcs_set_sigma_method": (ctypes.c_int, [_vp, ctypes.c_int]),
     "swcs_set_integrals": (ctypes.c_int, [_vp, _dp, _dp, ctypes.c_double]),
@@ -121,6 +124,24 @@ def _dev(t):
     return t.data_ptr()
 
 
+# Device memory callbacks (include/swcs.h: swcs_alloc_fn, swcs_free_fn).
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+# Contexts still open; closed at interpreter exit while torch (whose
+# allocator may own their memory) is still alive.
+_OPEN = weakref.WeakSet()
+
+
+@atexit.register
+def _close_all():
+    for ctx in list(_OPEN):
+        try:
+            ctx.close()
+        except Exception:
+            pass
+
+
 def version() -> str:
     return load().swcs_version().decode()
 
@@ -140,12 +161,16 @@ class Context:
             raise SwcsError(rc, self._lib.swcs_last_error(None).decode())
         self._h = h
         self.n, self.n_alpha, self.n_beta = n_spatial, n_alpha, n_beta
+        self.device = device
         self._keep = []
+        self._alloc_cb = None
+        _OPEN.add(self)
 
     def close(self):
         if getattr(self, "_h", None):
             self._lib.swcs_destroy(self._h)
             self._h = None
+        self._alloc_cb = None
 
     def __del__(self):
         try:
@@ -174,8 +199,55 @@ class Context:
             ptr = stream.cuda_stream
         self._check(self._lib.swcs_set_stream(self._h, ptr))
 
-    def set_capacity(self, max_dets: int):
-        self._check(self._lib.swcs_set_capacity(self._h, int(max_dets)))
+    def set_capacity(self, max_dets: int, allow_regrow: bool = True):
+        self._check(self._lib.swcs_set_capacity(self._h, int(max_dets), 1 if allow_regrow else 0))
+
+    def set_allocator(self, alloc, free):
+        """Route the library's device allocations through Python callables
+        alloc(nbytes) -> int address (0 on failure) and free(address);
+        (None, None) restores hipMalloc / hipFree."""
+        if alloc is None and free is None:
+            self._check(self._lib.swcs_set_allocator(self._h, None, None, None))
+            self._alloc_cb = None
+            return
+
+        def _a(nbytes, _user):
+            try:
+                return int(alloc(int(nbytes))) or None
+            except Exception:  # reported to the library as an allocation failure
+                return None
+
+        def _f(ptr, _user):
+            try:
+                free(int(ptr))
+            except Exception:
+                pass
+
+        cbs = (ALLOC_FN(_a), FREE_FN(_f))
+        self._check(self._lib.swcs_set_allocator(self._h, ctypes.cast(cbs[0], _vp),
+                                                 ctypes.cast(cbs[1], _vp), None))
+        # blocks allocated through these callbacks are freed through them, up
+        # to swcs_destroy: keep every pair alive for the context's lifetime
+        self._keep.append(cbs)
+        self._alloc_cb = cbs
+
+    def use_torch_allocator(self, stream=None):
+        """Device memory from PyTorch's caching allocator, bound to `stream`
+        (default: the current torch stream of the context's device), which is
+        also made the context stream, so blocks the library frees are reused
+        only in that stream's order."""
+        import torch
+        dev = self.device
+        st = stream if stream is not None else torch.cuda.current_stream(dev)
+        self.set_stream(st)
+
+        def alloc(nbytes):
+            return torch.cuda.caching_allocator_alloc(nbytes, dev, st)
+
+        def free(ptr):
+            torch.cuda.caching_allocator_delete(ptr)
+
+        self.set_allocator(alloc, free)
 
     def set_table_budget(self, nbytes: int):
         """Cap on the pool-gradient sigma table in bytes (0 = from free memory)."""
@@ -361,9 +433,15 @@ class Context:
                                           int(n_rand), _dev(out_idx)))
 
 
-def make_context(n, n_alpha, n_beta, h, eri, pool, ref, device=0, e_core=0.0, stream=None):
+def make_context(n, n_alpha, n_beta, h, eri, pool, ref, device=0, e_core=0.0, stream=None,
+                 torch_memory=True):
+    """A context with integrals, reference and pool set.  By default its device
+    memory comes from PyTorch's caching allocator on `stream` (default: the
+    current torch stream); torch_memory=False keeps hipMalloc."""
     ctx = Context(n, n_alpha, n_beta, device)
-    if stream is not None:
+    if torch_memory:
+        ctx.use_torch_allocator(stream)
+    elif stream is not None:
         ctx.set_stream(stream)
     ctx.set_integrals(h, eri, e_core)
     ctx.set_reference(ref)

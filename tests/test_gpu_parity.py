@@ -250,8 +250,9 @@ def test_screened_estimate_overflow_retry(swcs, c2):
     the last full-pool call.  After a full pool over the 3,136 determinants of
     an 8-orbital CAS (heavy overlap: ~3.2e5 external keys), a random state of
     the same size queries ~1.8e6 keys with 6,000 operators, so the first
-    table fills and the pass is repeated with a larger estimate; the result
-    equals the bound-sized pass (oracle-checked by the subset tests)."""
+    table fills and the pass is repeated with a larger estimate.  Both the
+    bound-sized pass and the repeated counted pass agree with the oracle on
+    that random state (300 of the operators)."""
     import itertools
     na = c2.na
     cas = list(itertools.combinations(range(8), na))
@@ -264,15 +265,29 @@ def test_screened_estimate_overflow_retry(swcs, c2):
     ia = rng.choice(len(sets), len(keys))
     ib = rng.choice(len(sets), len(keys))
     rkeys = _spin_keys([(sets[i], sets[j]) for i, j in zip(ia, ib)])
-    ctx.set_state(rkeys, rng.standard_normal(len(rkeys)))
+    ramps = rng.standard_normal(len(rkeys))
+    ctx.set_state(rkeys, ramps)
     subset = np.sort(rng.choice(len(c2.pool), 6000, replace=False)).astype(np.int32)
     _say(f"[parity] estimate retry: {len(rkeys)} random determinants, bound-sized pass")
     g0 = ctx.pool_gradients(subset)
     ctx.set_table_budget(1 << 30)
     _say("[parity] estimate retry: counted pass")
+    ctx.timer_start("sigma_push_into")
     g1 = ctx.pool_gradients(subset)
-    assert np.abs(g0).max() > 1e-3
-    assert np.abs(g1 - g0).max() < 1e-12
+    launches, _ = ctx.timer_stop()
+    assert launches >= 2, launches        # the first table filled and the pass was repeated
+    pick = np.sort(rng.choice(len(subset), 300, replace=False))
+    _say("[parity] estimate retry: oracle on the random state")
+    rst = oracle.OracleState.from_arrays(rkeys, ramps)
+    g_ref = c2.orc.pool_gradients(rst, c2.pool, subset=subset[pick])
+    assert np.abs(g_ref).max() > 1e-3
+    assert np.abs(g0[pick] - g_ref).max() < TOL
+    assert np.abs(g1[pick] - g_ref).max() < TOL
+    # the overflow of the first counted table was cleared: later calls on the
+    # context report no error of their own
+    ctx.set_table_budget(0)
+    ctx.apply_ansatz(c2.ops, c2.theta, c2.eps)
+    assert abs(ctx.energy()[0] - c2.orc.energy(c2.st)[0]) < TOL
     ctx.close()
 
 
@@ -307,6 +322,130 @@ def test_c5_state_and_sampled_sigma_rows(swcs):
     E, numer, norm2 = ctx.energy()
     assert abs(numer - float(a @ sig)) < 1e-9 and abs(norm2 - float(a @ a)) < 1e-12
     ctx.close()
+
+
+def test_c5_full_parity_scaled_eps(swcs):
+    """The 52-spin-orbital workload (26 orbitals, 16 electrons, 300 gates) at
+    a threshold of 1e-5, where the oracle can evaluate everything: the state
+    bit for bit, the energy, 200 random pool gradients plus the 50 largest of
+    the GPU's full pool, and all 300 adjoint parameter gradients."""
+    c = CONFIGS["c5"]
+    eps = 1e-5
+    h, eri = make_integrals(c.n, c.rank, c.seed_int)
+    pool = enumerate_pool(c.n)
+    ops, theta = draw_ansatz(len(pool), c.n_ops, c.theta_lo, c.theta_hi, c.seed_ansatz)
+    ref = reference_key(c.n_elec)
+    st = oracle.Oracle.apply_ansatz(pool, ops, theta, eps, ref)
+    orc = oracle.Oracle(c.n, 8, 8, h, eri)
+    ctx = swcs.make_context(c.n, 8, 8, h, eri, pool, ref)
+    _say(f"[parity] c5 eps=1e-5: apply ({len(st)} dets in the oracle state)")
+    assert ctx.apply_ansatz(ops, theta, eps) == len(st)
+    k, a = ctx.get_state()
+    k_ref, a_ref = st.export()
+    assert np.array_equal(k, k_ref) and np.array_equal(a, a_ref)
+    E, _, norm2 = ctx.energy()
+    E_ref, _, norm_ref = orc.energy(st)
+    assert abs(E - E_ref) < TOL and abs(norm2 - norm_ref) < TOL
+    _say("[parity] c5 eps=1e-5: full pool on the GPU, sampled on the oracle")
+    g = ctx.pool_gradients()
+    rng = np.random.default_rng(55)
+    top = np.argsort(-np.abs(g))[:50]
+    rest = np.setdiff1d(np.arange(len(pool)), top)
+    sub = np.sort(np.concatenate([top, rng.choice(rest, 200, replace=False)])).astype(np.int32)
+    g_ref = orc.pool_gradients(st, pool, subset=sub)
+    assert np.abs(g_ref).max() > 1e-2
+    assert np.abs(g[sub] - g_ref).max() < TOL
+    _say("[parity] c5 eps=1e-5: 300 parameter gradients")
+    dE, E2 = ctx.param_gradients(len(ops))
+    dE_ref, _ = orc.param_gradients(pool, ops, theta, eps, ref)
+    assert abs(E2 - E_ref) < TOL
+    assert np.abs(dE - dE_ref).max() < TOL
+    ctx.close()
+
+
+def test_ansatz_energy_autograd(swcs, c1):
+    """The torch.autograd entry: forward gives E, backward the adjoint
+    gradients, against the oracle and central finite differences (eps = 0,
+    h = 1e-5) of the forward itself; an upstream factor scales the
+    gradient."""
+    import torch
+    ctx = make_ctx(swcs, c1)
+    th = torch.tensor(c1.theta, dtype=torch.float64, requires_grad=True)
+    E = swcs.ansatz_energy(th, ctx, c1.ops, 0.0)
+    (3.0 * E).backward()
+    dE_ref, E_ref = c1.orc.param_gradients(c1.pool, c1.ops, c1.theta, 0.0, c1.ref)
+    assert abs(E.item() - E_ref) < TOL
+    assert np.abs(th.grad.numpy() - 3.0 * dE_ref).max() < 3 * TOL
+    hstep = 1e-5
+    for i in (0, 7, 15, 29):
+        tp = th.detach().clone()
+        tm = th.detach().clone()
+        tp[i] += hstep
+        tm[i] -= hstep
+        fd = (swcs.ansatz_energy(tp, ctx, c1.ops, 0.0).item()
+              - swcs.ansatz_energy(tm, ctx, c1.ops, 0.0).item()) / (2 * hstep)
+        assert abs(fd - dE_ref[i]) < 1e-8, (i, fd, dE_ref[i])
+    ctx.close()
+
+
+def test_allocators_and_fixed_capacity(swcs, spread):
+    """Device memory through PyTorch's caching allocator (the binding's
+    default) and through hipMalloc give identical results; torch accounts for
+    the library's memory while the context lives.  A failing allocator
+    surfaces as SWCS_E_OOM.  A fixed capacity (no regrowth) holds the state of
+    a chain that would otherwise grow, and one too small for it fails with
+    SWCS_E_CAPACITY and leaves no state."""
+    import torch
+    base = torch.cuda.memory_allocated()
+    ctx_t = make_ctx(swcs, spread)
+    ctx_h = swcs.make_context(spread.n, spread.na, spread.nb, spread.h, spread.eri, spread.pool,
+                              spread.ref, torch_memory=False)
+    out = []
+    for ctx in (ctx_t, ctx_h):
+        ctx.apply_ansatz(spread.ops, spread.theta, 0.0)
+        out.append((ctx.get_state(), ctx.energy(), ctx.pool_gradients()))
+    assert torch.cuda.memory_allocated() > base + 8 * len(spread.st)
+    (k0, a0), e0, g0 = out[0]
+    (k1, a1), e1, g1 = out[1]
+    assert np.array_equal(k0, k1) and np.array_equal(a0, a1) and e0 == e1
+    assert np.abs(g0 - g1).max() < 1e-13
+    assert np.array_equal(a0, spread.st.export()[1])
+    ctx_t.close()
+    assert torch.cuda.memory_allocated() <= base + (1 << 20)
+
+    n_final = len(spread.st)
+    ctx_f = swcs.make_context(spread.n, spread.na, spread.nb, spread.h, spread.eri, spread.pool,
+                              spread.ref)
+    with pytest.raises(swcs.SwcsError):
+        ctx_f.set_capacity(0, allow_regrow=False)
+    ctx_f.set_capacity(2 * n_final, allow_regrow=False)
+    for _ in range(2):
+        ctx_f.apply_ansatz(spread.ops, spread.theta, 0.0)
+        assert np.array_equal(ctx_f.get_state()[1], spread.st.export()[1])
+    ctx_f.set_capacity(n_final // 4, allow_regrow=False)
+    with pytest.raises(swcs.SwcsError) as ei:
+        ctx_f.apply_ansatz(spread.ops, spread.theta, 0.0)
+    assert ei.value.code == swcs.SWCS_E_CAPACITY
+    with pytest.raises(swcs.SwcsError) as ei:
+        ctx_f.energy()
+    assert ei.value.code == swcs.SWCS_E_STATE
+    ctx_f.set_capacity(0)
+    ctx_f.apply_ansatz(spread.ops, spread.theta, 0.0)
+    assert np.array_equal(ctx_f.get_state()[1], spread.st.export()[1])
+    ctx_f.close()
+
+    calls = []
+
+    def refuse(nbytes):
+        calls.append(nbytes)
+        return 0
+
+    ctx_h.set_allocator(refuse, lambda ptr: None)
+    ctx_h.set_capacity(1 << 22, allow_regrow=False)   # new state arrays are needed
+    with pytest.raises(swcs.SwcsError) as ei:
+        ctx_h.apply_ansatz(spread.ops, spread.theta, 0.0)
+    assert ei.value.code == swcs.SWCS_E_OOM and calls
+    ctx_h.close()
 
 
 def two_electron_case():
