@@ -1,11 +1,11 @@
 """Benchmark of the SWCS hot path on one MI355X.
 
-One step = one pass of the whole hot path over the synthetic 28-spin-orbital
-workload (14 spatial orbitals, 10 electrons, (pq|rs) of rank 14, 100-gate
-ansatz with theta ~ U(-0.05, 0.05), eps = 1e-6, generalized singles and
-doubles pool of 22,750 operators):
+One step = one pass of the whole hot path over the synthetic 52-spin-orbital
+workload (26 spatial orbitals, 16 electrons, (pq|rs) of rank 26, 300-gate
+ansatz with theta ~ U(-0.05, 0.05), eps = 1e-8, generalized singles and
+doubles pool of 301,600 operators; --workload picks another):
 
-  1. apply the ansatz from the reference with pruning (100 gates),
+  1. apply the ansatz from the reference with pruning (300 gates),
   2. energy through the projected sigma vector,
   3. exact pool gradients of the full pool (external sigma + contraction),
   4. adjoint parameter gradients (sqrt(M) checkpoints, recompute, reverse),
@@ -17,6 +17,8 @@ Prints one JSON line.  `value` is determinant-excitation applies per second
 over the whole step: the number of (determinant, gate) applications the step
 performs (forward gates, adjoint recompute gates and reverse gates, each
 counted by the kept determinants entering the gate) divided by the step time.
+The same step on the 28-spin-orbital workload and the HBM-path kernels on a
+16M-determinant synthetic state are reported beside it.
 """
 from __future__ import annotations
 
@@ -39,13 +41,21 @@ from paper_2411_07920_amd.inputs import (CONFIGS, array_digest, draw_ansatz,  # 
 HBM_PEAK_GBS = 8000.0
 
 
+def progress(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c2", choices=sorted(CONFIGS))
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="c5", choices=sorted(CONFIGS))
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the 28-spin-orbital step and the large-state kernels")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-kernel-times", dest="kernel_times", action="store_false",
+                    help="skip the per-kernel HIP-event passes")
     ap.add_argument("--profile-phase", default=None,
                     help="run only this phase in a loop (for counter collection)")
     ap.add_argument("--adapt", default=None, choices=sorted(CONFIGS),
@@ -96,15 +106,18 @@ class Workload:
         self.digest = array_digest(self.h, self.eri, self.pool, self.ops, self.theta)
 
 
-def applies_in_step(n_in, seg):
-    """(forward, adjoint) determinant-gate applications of one step."""
+def applies_in_step(n_in, seg, lds):
+    """(forward, adjoint) determinant-gate applications of one step: the
+    forward chain, then the adjoint's recomputation (every gate of a segment
+    is replayed from its checkpoint on the HBM path; the single-workgroup path
+    stops a segment's replay before its last gate) and its reverse sweep."""
     M = len(n_in)
     fwd = int(n_in.sum())
     recompute = 0
     for g in range(M):
         seg_lo = (g // seg) * seg
         seg_hi = min(M, seg_lo + seg)
-        if g < seg_hi - 1:  # gates g_lo .. g_hi-2 are recomputed per segment
+        if not lds or g < seg_hi - 1:
             recompute += int(n_in[g])
     return fwd, recompute + fwd
 
@@ -198,9 +211,10 @@ def gpu_bench(args, wl):
             if events is not None:
                 events[i][1].record(stream)
 
-    for _ in range(args.warmup):
+    for i in range(args.warmup):
         step()
-    torch.cuda.synchronize()
+        torch.cuda.synchronize()
+        progress(f"{wl.c.name}: warm-up step {i + 1} done")
     ev = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
            for _ in phases] for _ in range(args.steps)]
     torch.cuda.synchronize()
@@ -210,6 +224,7 @@ def gpu_bench(args, wl):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_step = (t1 - t0) * 1e3 / args.steps
+    progress(f"{wl.c.name}: {args.steps} timed steps, {ms_step:.2f} ms per step")
     phase_ms = {name: float(np.mean([ev[s][i][0].elapsed_time(ev[s][i][1]) for s in range(args.steps)]))
                 for i, (name, _) in enumerate(phases)}
 
@@ -217,19 +232,22 @@ def gpu_bench(args, wl):
     n_det = phase_apply()
     n_in = ctx.gate_sizes(M)
     seg = max(1, int(math.ceil(math.sqrt(M))))
-    fwd_applies, adj_applies = applies_in_step(n_in, seg)
+    fwd_applies, adj_applies = applies_in_step(n_in, seg, int(n_in.max(initial=1)) <= 4096)
     applies = fwd_applies + adj_applies
 
     # Per-kernel GPU time of one step: the library records HIP events on the
     # context stream around every launch of the selected kernel.
     kern = {}
-    reps = max(3, args.steps // 2)
+    reps = 3
     for kname in ("chain_lds", "gate", "adjoint_lds", "adjoint_replay_lds", "gate_replay", "adjoint_rec", "sigma_proj",
-                  "sigma_push", "sigma_push_into", "pool_contract", "contract_ops", "select"):
+                  "holepair", "sigma_push", "sigma_push_into", "pool_contract", "contract_ops", "select"):
+        if not args.kernel_times:
+            break
         ctx.timer_start(kname)
         for _ in range(reps):
             step()
         launches, total = ctx.timer_stop()
+        progress(f"{wl.c.name}: kernel times of {kname}")
         if launches:
             kern[kname] = {"launches_per_step": launches / reps, "ms_per_step": total / reps,
                            "us_per_launch": 1e3 * total / launches}
@@ -272,35 +290,54 @@ def algorithmic_bytes(kname, wl, r):
     return 0.0
 
 
-def cpu_baseline(wl, fwd_applies, adj_applies, budget_s=20.0):
-    """The oracle timed on the host on a bounded sample of one step."""
+def cpu_baseline(wl, fwd_applies, adj_applies):
+    """The oracle timed on the host on a bounded sample of one step, scaled
+    to the whole step.  The forward chain runs in full.  The other parts are
+    timed on samples of the final state and scaled by its size: sigma_P rows
+    (energy), the external sigma of sampled source determinants and the
+    generator applications of sampled operators (pool gradients, full pool
+    plus the screener's 6 % subset); the adjoint is the oracle's forward
+    states, one sigma_P and a reverse sweep of one more chain."""
     import oracle
     orc = oracle.Oracle(wl.c.n, wl.na, wl.na, wl.h, wl.eri)
     t = time.perf_counter()
     st = oracle.Oracle.apply_ansatz(wl.pool, wl.ops, wl.theta, wl.c.eps, wl.ref)
     t_apply = time.perf_counter() - t
-    t = time.perf_counter()
-    orc.energy(st)
-    t_energy = time.perf_counter() - t
-    t = time.perf_counter()
-    orc.param_gradients(wl.pool, wl.ops, wl.theta, wl.c.eps, wl.ref)
-    t_adj = time.perf_counter() - t
-    # pool gradients on a sample of operators, scaled to the full pool
+    keys, amps = st.export()
+    n = len(keys)
     rng = np.random.default_rng(0)
-    sample = np.sort(rng.choice(wl.K, min(wl.K, 2000), replace=False)).astype(np.int32)
+    rows = rng.choice(n, min(n, 1000), replace=False)
     t = time.perf_counter()
-    orc.pool_gradients(st, wl.pool, subset=sample)
-    t_pool_sample = time.perf_counter() - t
-    t_pool = t_pool_sample * wl.K / len(sample)
-    t_step = t_apply + t_energy + t_adj + t_pool * (1.0 + (wl.n_top + wl.n_rand) / wl.K)
+    orc.sigma_at(st, keys[rows])
+    t_energy = (time.perf_counter() - t) * n / len(rows)
+    # pool gradients: external sigma of n_src sources (one operator), then
+    # the same plus n_ops more operators, whose difference is the generator
+    # applications of n_ops operators over the n_src determinants
+    src = np.sort(rng.choice(n, min(n, 100), replace=False))
+    sub = oracle.OracleState.from_arrays(keys[src], amps[src])
+    n_ops = min(wl.K, 3000)
+    ops_s = np.sort(rng.choice(wl.K, n_ops + 1, replace=False)).astype(np.int32)
+    t = time.perf_counter()
+    orc.pool_gradients(sub, wl.pool, subset=ops_s[:1])
+    t_ext = time.perf_counter() - t
+    t = time.perf_counter()
+    orc.pool_gradients(sub, wl.pool, subset=ops_s)
+    t_both = time.perf_counter() - t
+    t_gen = max(t_both - t_ext, 0.0) / n_ops          # one operator over len(src) determinants
+    frac = 1.0 + (wl.n_top + wl.n_rand) / wl.K
+    t_pool = t_ext * n / len(src) + frac * t_gen * wl.K * n / len(src)
+    t_adj = 2.0 * t_apply + t_energy
+    t_step = t_apply + t_energy + t_pool + t_adj
     return {
         "value": (fwd_applies + adj_applies) / t_step,
         "unit": "determinant-excitation applies/s",
         "cores": 1,
         "kind": "oracle",
-        "sample": (f"one step of the same workload: full apply, energy and adjoint; pool gradients "
-                   f"of {len(sample)} of {wl.K} operators scaled by {wl.K / len(sample):.2f}; "
-                   f"step {t_step:.2f} s"),
+        "sample": (f"one step of the same workload ({n} determinants): forward chain in full "
+                   f"({t_apply:.2f} s); energy from {len(rows)} sigma_P rows; pool gradients from the "
+                   f"external sigma of {len(src)} sources and {n_ops} operators' generator "
+                   f"applications over them; adjoint as two chains plus one sigma_P; every part "
+                   f"scaled to the full state and pool; estimated step {t_step:.1f} s"),
     }
 
 
@@ -384,11 +421,13 @@ def large_state_bench(N, sigma=True):
     determinants in the 52-spin-orbital, 16-electron sector (uniform alpha and
     beta strings, log-uniform |c|): eight double-excitation gates at eps = 0
     on the HBM path, then sigma_P by hole-pair grouping (and by enumeration
-    when N <= 2,000,000).  Gate bytes per launch: 16 B per alive input entry
-    (key scan and amplitude) plus 32 B per appended entry (key, amplitude,
-    index slot).  At 16M determinants the counter-measured HBM traffic of a
-    gate and of one sigma_P call (profiles/pmc_traffic.txt) is divided by the
-    measured times as well."""
+    when N <= 2,000,000).  Gate bytes per gate: 8 B per input entry (the key
+    test every entry needs), 16 B per entry the operator acts on (amplitude
+    read and written) and 16 B per new entry (key and amplitude); the active
+    count of each gate is taken from the state exported before it.  At 16M
+    determinants the counter-measured HBM traffic of a gate and of one
+    sigma_P call (profiles/pmc_traffic.txt) is divided by the measured times
+    as well."""
     import torch
     from math import comb
     from paper_2411_07920_amd import swcs
@@ -430,18 +469,37 @@ def large_state_bench(N, sigma=True):
     doubles = np.flatnonzero(wl.pool[:, 2] >= 0)
     ops = rng.choice(doubles, 8).astype(np.int32)
     theta = rng.uniform(-0.3, 0.3, len(ops))
-    # A gate that would overflow the capacity returns at once and is launched
-    # again after the host grows the state, so time is averaged per gate.
-    ctx.timer_start("gate")
-    n_out = ctx.apply_gates(ops, theta, 0.0)
-    launches, ms = ctx.timer_stop()
-    n_in = ctx.gate_sizes(len(ops)).astype(np.float64)
+    # One gate per call, the state exported before each to count the entries
+    # the operator acts on.  A gate that would overflow the capacity returns
+    # at once and is launched again after the host grows the state, so time
+    # is summed per gate.
+    n_in, n_act, ms = [], [], 0.0
+    n_out = None
+    launches = 0
+    for g in range(len(ops)):
+        k, _ = ctx.get_state()
+        P, Q, R, S = (int(x) for x in wl.pool[ops[g]])
+        cre = np.uint64((1 << P) | (1 << Q))
+        ann = np.uint64((1 << R) | (1 << S))
+        acts = (((k & ann) == ann) & ((k & cre) == 0)) | (((k & cre) == cre) & ((k & ann) == 0))
+        n_in.append(float(len(k)))
+        n_act.append(float(np.count_nonzero(acts)))
+        ctx.timer_start("gate")
+        n_out = ctx.apply_gates(ops[g:g + 1], theta[g:g + 1], 0.0)
+        nl, t = ctx.timer_stop()
+        launches += nl
+        ms += t
+    n_in = np.array(n_in)
+    n_act = np.array(n_act)
     after = np.append(n_in[1:], n_out)
-    nbytes = float((16.0 * n_in + 32.0 * np.maximum(after - n_in, 0.0)).sum())
+    n_new = np.maximum(after - n_in, 0.0)
+    nbytes = float((8.0 * n_in + 16.0 * n_act + 16.0 * n_new).sum())
     us = 1e3 * ms / len(ops)
     gbps = nbytes / len(ops) / (us * 1e-6) / 1e9
     out["gate"] = {"gates": len(ops), "launches": launches, "us_per_gate": us,
                    "dets_per_s": float(n_in.sum()) / (ms * 1e-3),
+                   "active_frac": float(n_act.sum() / n_in.sum()),
+                   "new_per_gate": float(n_new.mean()),
                    "algorithmic_bytes_per_gate": nbytes / len(ops),
                    "achieved_GBps": gbps, "frac_hbm": gbps / HBM_PEAK_GBS,
                    "n_det_in": int(n_in[0]), "n_det_out": int(n_out)}
@@ -452,6 +510,7 @@ def large_state_bench(N, sigma=True):
             gbps = tb / (us * 1e-6) / 1e9
             out["gate"]["traffic_GBps"] = gbps
             out["gate"]["traffic_frac_hbm"] = gbps / HBM_PEAK_GBS
+            out["gate"]["traffic_over_algorithmic"] = tb / (nbytes / len(ops))
     ctx.close()
     return out
 
@@ -678,10 +737,6 @@ def main():
         return
     M = len(wl.ops)
     kern = r["kernels"]
-    dom = max(kern, key=lambda k: kern[k]["ms_per_step"])
-    per_launch_s = kern[dom]["us_per_launch"] * 1e-6
-    bytes_launch = algorithmic_bytes(dom, wl, r)
-    achieved = bytes_launch / per_launch_s / 1e9
     line = {
         "metric": "determinant-excitation applies/s",
         "value": r["applies"] / (r["ms_step"] * 1e-3),
@@ -700,15 +755,34 @@ def main():
                    "n_det_final": r["n_det"], "applies_per_step": r["applies"],
                    "input_sha256": wl.digest[:16]},
         "phases_ms": {k: round(v, 4) for k, v in r["phase_ms"].items()},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom, args.workload),
-                     "kernel": dom, "us_per_launch": kern[dom]["us_per_launch"],
-                     "algorithmic_bytes_per_launch": bytes_launch},
-        "kernels_ms_per_step": {k: round(v["ms_per_step"], 4) for k, v in kern.items()},
     }
+    if kern:
+        dom = max(kern, key=lambda k: kern[k]["ms_per_step"])
+        per_launch_s = kern[dom]["us_per_launch"] * 1e-6
+        bytes_launch = algorithmic_bytes(dom, wl, r)
+        achieved = bytes_launch / per_launch_s / 1e9
+        tb = measured_traffic(dom, args.workload)
+        line["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                            "frac": achieved / HBM_PEAK_GBS, "traffic": tb,
+                            "kernel": dom, "us_per_launch": kern[dom]["us_per_launch"],
+                            "algorithmic_bytes_per_launch": bytes_launch,
+                            "traffic_over_algorithmic": (tb / bytes_launch) if tb else None}
+        line["kernels_ms_per_step"] = {k: round(v["ms_per_step"], 4) for k, v in kern.items()}
     if not args.no_cpu_baseline:
+        progress("oracle baseline")
         line["cpu_baseline"] = cpu_baseline(wl, r["fwd_applies"], r["adj_applies"])
-    if args.large_state:
+    if not args.no_extras and args.workload != "c2":
+        a2 = argparse.Namespace(steps=20, warmup=3, profile_phase=None, kernel_times=False)
+        wl2 = Workload("c2")
+        r2 = gpu_bench(a2, wl2)
+        line["extra_c2_step"] = {"workload": f"c2: {wl2.c.n_so} spin-orbitals, {wl2.c.n_elec} electrons, "
+                                             f"{len(wl2.ops)}-gate ansatz, eps={wl2.c.eps:g}, pool {wl2.K}",
+                                 "ms_per_step": r2["ms_step"],
+                                 "applies_per_s": r2["applies"] / (r2["ms_step"] * 1e-3),
+                                 "n_det_final": r2["n_det"],
+                                 "phases_ms": {k: round(v, 4) for k, v in r2["phase_ms"].items()}}
+    if args.large_state and not args.no_extras:
+        progress("large state")
         line["large_state"] = large_state_bench(args.large_state)
     print(json.dumps(line))
 

@@ -27,6 +27,8 @@ with the full pool every `full_every` iterations and in the first
 from __future__ import annotations
 
 import dataclasses
+import json
+import os
 import time
 
 import numpy as np
@@ -175,10 +177,45 @@ def select_operator(g, idx, rel_tol=1e-9):
     return int(cand[np.argmin(np.asarray(idx)[cand])])
 
 
-def run_adapt(ctx, K: int, cfg: AdaptConfig, ops0=None, theta0=None, log=None):
+def save_checkpoint(path, it_next, ops, theta, history, last_absg, scr, finished):
+    """Write the state of an ADAPT run after an iteration: ansatz, parameters,
+    history, the stale-ranking record and the screener (arrays in an .npz,
+    scalars as JSON; nothing pickled).  Written to a temporary file and
+    renamed, so an interrupted write leaves the previous checkpoint."""
+    arrays = {"ops": np.asarray(ops, dtype=np.int32), "theta": np.asarray(theta, dtype=np.float64)}
+    if last_absg is not None:
+        arrays["last_absg"] = last_absg
+    meta = {"it_next": it_next, "history": history, "finished": finished, "screener": None}
+    if scr is not None:
+        sa, ss = scr.state()
+        arrays.update({"scr_" + k: v for k, v in sa.items()})
+        meta["screener"] = ss
+    arrays["meta_json"] = np.frombuffer(json.dumps(meta).encode(), dtype=np.uint8)
+    tmp = path + ".tmp.npz"
+    np.savez(tmp, **arrays)
+    os.replace(tmp, path)
+
+
+def load_checkpoint(path):
+    with np.load(path, allow_pickle=False) as z:
+        arrays = {k: z[k] for k in z.files}
+    meta = json.loads(arrays.pop("meta_json").tobytes().decode())
+    return arrays, meta
+
+
+def run_adapt(ctx, K: int, cfg: AdaptConfig, ops0=None, theta0=None, log=None, checkpoint=None,
+              time_limit=None):
     """ADAPT-VQE; returns (ops, theta, history).  `ctx` has integrals, pool
     (K operators) and reference set.  ops0 / theta0 seed the ansatz (bootstrap
-    restarts reuse a previous final ansatz)."""
+    restarts reuse a previous final ansatz).
+
+    checkpoint: path of an .npz file written after every iteration; if it
+    exists when the run starts, the run continues from it (operators,
+    parameters, history, screener weights, Adam moments, replay buffer and
+    random generator state) up to cfg.max_iter iterations in all, so a long
+    run can proceed in segments; a run that converged is not continued.
+    time_limit: seconds after which the run stops at the end of an iteration
+    (the checkpoint then holds everything needed to continue)."""
     from .screener import Screener
 
     ops = list(ops0) if ops0 is not None else []
@@ -189,7 +226,23 @@ def run_adapt(ctx, K: int, cfg: AdaptConfig, ops0=None, theta0=None, log=None):
     # last exact |g| of every operator (the information a stale-ranking
     # heuristic would select with; shadow runs only)
     last_absg = np.zeros(K) if cfg.shadow_full else None
-    for it in range(cfg.max_iter):
+    it0 = 0
+    if checkpoint is not None and os.path.exists(checkpoint):
+        arrays, meta = load_checkpoint(checkpoint)
+        ops = arrays["ops"].astype(np.int64).tolist()
+        theta = arrays["theta"].astype(np.float64)
+        history = meta["history"]
+        it0 = int(meta["it_next"])
+        if last_absg is not None and "last_absg" in arrays:
+            last_absg = arrays["last_absg"].astype(np.float64)
+        if scr is not None and meta["screener"] is not None:
+            scr.load_state({k[4:]: v for k, v in arrays.items() if k.startswith("scr_")}, meta["screener"])
+        if meta["finished"]:
+            return np.array(ops, dtype=np.int32), theta, history
+    t_start = time.perf_counter()
+    for it in range(it0, cfg.max_iter):
+        if time_limit is not None and it > it0 and time.perf_counter() - t_start > time_limit:
+            break
         rec = {"iter": it}
         t0 = time.perf_counter()
         n_det = ctx.apply_ansatz(np.array(ops, dtype=np.int32), theta, cfg.eps, cfg.ncut)
@@ -243,6 +296,8 @@ def run_adapt(ctx, K: int, cfg: AdaptConfig, ops0=None, theta0=None, log=None):
             history.append(rec)
             if log:
                 log(rec)
+            if checkpoint is not None:
+                save_checkpoint(checkpoint, it + 1, ops, theta, history, last_absg, scr, True)
             break
         ops.append(kstar)
         theta = np.append(theta, 0.0)
@@ -254,6 +309,8 @@ def run_adapt(ctx, K: int, cfg: AdaptConfig, ops0=None, theta0=None, log=None):
         history.append(rec)
         if log:
             log(rec)
+        if checkpoint is not None:
+            save_checkpoint(checkpoint, it + 1, ops, theta, history, last_absg, scr, False)
     return np.array(ops, dtype=np.int32), theta, history
 
 

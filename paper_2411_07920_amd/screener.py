@@ -154,6 +154,36 @@ class Screener:
         self.lam = float(self.lam_grid[int(np.argmin(self.lam_cost))])
         self.lam_history.append(self.lam)
 
+    # -- checkpoint / resume ------------------------------------------------
+    def state(self):
+        """Everything that decides later iterations: network, Adam moments and
+        step, replay buffer, per-operator history, lam bookkeeping and the
+        random generator (arrays and JSON-able scalars)."""
+        arrays = {
+            "W": self.W.cpu().numpy(), "m": self.m.cpu().numpy(), "v": self.v.cpu().numpy(),
+            "prev_absg": self.prev_absg.cpu().numpy(), "age": self.age.cpu().numpy(),
+            "buf_x": self.buf_x[: self.buf_n].cpu().numpy(), "buf_t": self.buf_t[: self.buf_n].cpu().numpy(),
+            "lam_cost": self.lam_cost.copy(),
+        }
+        scalars = {"adam_t": self.adam_t, "buf_n": self.buf_n, "buf_pos": self.buf_pos, "lam": self.lam,
+                   "lam_history": list(self.lam_history), "rng": self.rng.bit_generator.state}
+        return arrays, scalars
+
+    def load_state(self, arrays, scalars):
+        torch = self.torch
+        for name in ("W", "m", "v", "prev_absg", "age"):
+            getattr(self, name).copy_(torch.from_numpy(np.asarray(arrays[name], dtype=np.float32)))
+        n = int(scalars["buf_n"])
+        if n:
+            self.buf_x[:n] = torch.from_numpy(np.asarray(arrays["buf_x"], dtype=np.float32))
+            self.buf_t[:n] = torch.from_numpy(np.asarray(arrays["buf_t"], dtype=np.float32))
+        self.buf_n, self.buf_pos = n, int(scalars["buf_pos"])
+        self.adam_t = int(scalars["adam_t"])
+        self.lam = float(scalars["lam"])
+        self.lam_cost = np.asarray(arrays["lam_cost"], dtype=np.float64).copy()
+        self.lam_history = list(scalars["lam_history"])
+        self.rng.bit_generator.state = scalars["rng"]
+
     def train(self):
         """Full-batch Adam steps on the replay buffer; returns the last loss."""
         torch = self.torch

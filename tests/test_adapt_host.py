@@ -162,3 +162,35 @@ def test_bootstrap_ncut_restart(problem):
     Es = [r["E_after"] for r in hist2]
     assert all(b <= a + 1e-10 for a, b in zip([hist2[0]["E"]] + Es, Es))
     assert hist1[0]["n_det"] <= 6 and hist2[-1]["n_det"] <= 30
+
+
+def test_adapt_checkpoint_resume(problem, tmp_path):
+    """A run split into segments through its checkpoint (3 iterations, then
+    the rest up to 6) chooses the same operators and reaches the same
+    parameters and energies as one uninterrupted run; a time limit stops a
+    segment at an iteration boundary; a converged run is not continued."""
+    import dataclasses
+    n, ne, h, eri, pool = problem
+    cfg = adapt.AdaptConfig(eps=1e-4, max_iter=6, grad_tol=None, optimizer="lbfgs")
+    ops_a, th_a, hist_a = adapt.run_adapt(OracleContext(n, ne, h, eri, pool), len(pool), cfg)
+    path = str(tmp_path / "adapt.npz")
+    o1, _, h1 = adapt.run_adapt(OracleContext(n, ne, h, eri, pool), len(pool),
+                                dataclasses.replace(cfg, max_iter=3), checkpoint=path)
+    assert len(h1) == 3 and o1.tolist() == ops_a[:3].tolist()
+    # a segment with a zero time limit still completes one iteration
+    o2, _, h2 = adapt.run_adapt(OracleContext(n, ne, h, eri, pool), len(pool), cfg,
+                                checkpoint=path, time_limit=0.0)
+    assert len(h2) == 4
+    ops_b, th_b, hist_b = adapt.run_adapt(OracleContext(n, ne, h, eri, pool), len(pool), cfg,
+                                          checkpoint=path)
+    assert ops_b.tolist() == ops_a.tolist()
+    assert np.array_equal(th_b, th_a)
+    assert [r["E_after"] for r in hist_b] == [r["E_after"] for r in hist_a]
+    # converged runs are final
+    path2 = str(tmp_path / "conv.npz")
+    cfg_c = adapt.AdaptConfig(eps=0.0, max_iter=40, grad_tol=1e-1, optimizer="lbfgs")
+    oc, tc, hc = adapt.run_adapt(OracleContext(n, ne, h, eri, pool), len(pool), cfg_c, checkpoint=path2)
+    assert hc[-1].get("converged")
+    ctx = OracleContext(n, ne, h, eri, pool)
+    od, td, hd = adapt.run_adapt(ctx, len(pool), cfg_c, checkpoint=path2)
+    assert od.tolist() == oc.tolist() and ctx.calls["apply"] == 0

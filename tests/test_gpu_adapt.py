@@ -126,3 +126,28 @@ def test_bootstrap_ncut_follows_oracle_driver(swcs):
     for a, b in zip(runs[0][1], runs[1][1]):
         assert abs(a["E"] - b["E"]) < 1e-8 and abs(a["E_after"] - b["E_after"]) < 1e-7
     gpu.close()
+
+
+def test_adapt_checkpoint_resume_with_screener(swcs, tmp_path):
+    """A screened ADAPT run continued from its checkpoint (network weights,
+    Adam moments, replay buffer, random generator) picks the same operators
+    as the same run without interruption."""
+    c = CONFIGS["c1"]
+    h, eri = make_integrals(c.n, c.rank, c.seed_int)
+    pool = enumerate_pool(c.n)
+    ref = reference_key(c.n_elec)
+    cfg = adapt.AdaptConfig(eps=1e-6, max_iter=9, grad_tol=None, optimizer="lbfgs", screener=True,
+                            full_every=4, warm_full=2, frac_top=0.03, frac_rand=0.01)
+    ctx = swcs.make_context(c.n, 2, 2, h, eri, pool, ref)
+    ops_a, th_a, hist_a = adapt.run_adapt(ctx, len(pool), cfg)
+    ctx.close()
+    path = str(tmp_path / "screened.npz")
+    import dataclasses
+    for m in (4, 9):
+        ctx = swcs.make_context(c.n, 2, 2, h, eri, pool, ref)
+        ops_b, th_b, hist_b = adapt.run_adapt(ctx, len(pool), dataclasses.replace(cfg, max_iter=m),
+                                              checkpoint=path)
+        ctx.close()
+    assert ops_b.tolist() == ops_a.tolist()
+    assert np.abs(th_b - th_a).max() < 1e-7
+    assert [r["full"] for r in hist_b] == [r["full"] for r in hist_a]

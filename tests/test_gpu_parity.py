@@ -407,7 +407,10 @@ def test_allocators_and_fixed_capacity(swcs, spread):
     assert torch.cuda.memory_allocated() > base + 8 * len(spread.st)
     (k0, a0), e0, g0 = out[0]
     (k1, a1), e1, g1 = out[1]
-    assert np.array_equal(k0, k1) and np.array_equal(a0, a1) and e0 == e1
+    # states bit for bit; sums may run in another order (entries appended by
+    # the multi-block gates are stored in the order their tiles reserved room)
+    assert np.array_equal(k0, k1) and np.array_equal(a0, a1)
+    assert np.abs(np.array(e0) - np.array(e1)).max() < 1e-13
     assert np.abs(g0 - g1).max() < 1e-13
     assert np.array_equal(a0, spread.st.export()[1])
     ctx_t.close()
