@@ -188,6 +188,18 @@ int swcs_get_state(swcs_ctx* ctx, uint64_t* keys, double* amps, int64_t cap, int
  * Any output pointer may be NULL. */
 int swcs_energy(swcs_ctx* ctx, double* E, double* numer, double* norm2);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * result as swcs_energy, computed with no device allocation.  The diagonal
+ * elements, sigma_P and the partial sums live in a fixed 32 MiB device array
+ * of the library (one per device, held until the process ends), so the
+ * state may hold at most 2,088,928 stored entries (SWCS_E_CAPACITY beyond).
+ * sigma_P is formed by pairs for at most 4,096 stored entries and by
+ * enumeration otherwise.  Every call on a device shares that array: calls
+ * that overlap on one device (several contexts or threads at once) race and
+ * must be serialized by the caller. */
+int swcs_energy_noalloc(swcs_ctx* ctx, double* E, double* numer, double* norm2);
+
 /* The projected sigma vector sigma_P(D) = sum_{D' in psi} H_{D D'} psi(D')
  * on the kept determinants, exported as (key, sigma) pairs sorted by key into
  * caller arrays of length cap (same size rules as swcs_get_state).  E is

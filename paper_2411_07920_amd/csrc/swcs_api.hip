@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -564,6 +565,40 @@ int run_chain(swcs_ctx* c, const int32_t* op_idx, const double* cs, const double
 
 }  // namespace
 
+// ---- energy without allocation ----
+// Scratch of the allocation-free energy: the library's own device array,
+// 32 MiB on every device the library runs on, held until the process ends.
+// Layout in doubles: 2 x 8,192 per-block partial sums, 64 result slots, then
+// the diagonal elements and sigma_P of up to kNoAllocMaxEntries stored
+// entries.  Host code never passes `scratch` itself to a kernel: it resolves
+// the array's device address once per device (noalloc_scratch).
+constexpr size_t kNoAllocBytes = (size_t)32 << 20;
+constexpr size_t kNoAllocPartials = 2 * 8192;
+constexpr size_t kNoAllocHead = kNoAllocPartials + 64;
+constexpr u64 kNoAllocMaxEntries = (kNoAllocBytes / 8 - kNoAllocHead) / 2;
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+void* g_scratch_dev[64] = {};  // device address of `scratch` per device index
+
+// Device address of `scratch` on the context's device (which must be
+// current), resolved on the first call for that device.
+hipError_t noalloc_scratch(int device, double** out) {
+  if (device < 0 || device >= 64) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_dev[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_dev[device] = p;
+  }
+  *out = (double*)g_scratch_dev[device];
+  return hipSuccess;
+}
+}  // namespace
+
 extern "C" {
 
 const char* swcs_version(void) { return "swcs-mi355x 0.1 (gfx950)"; }
@@ -615,6 +650,10 @@ int swcs_create(int n_spatial, int n_alpha, int n_beta, int device, swcs_ctx** o
     return SWCS_E_DEVICE;
   }
   c->st.ctr = c->ctr.as<Counters>();
+  // device address of the allocation-free energy's scratch, once per device
+  // (a failure here is reported by that entry point, which retries)
+  double* scr = nullptr;
+  (void)noalloc_scratch(device, &scr);
   *out = c;
   return SWCS_OK;
 }
@@ -1118,6 +1157,49 @@ int swcs_energy(swcs_ctx* c, double* E, double* numer, double* norm2) {
   if (numer) *numer = nu;
   if (norm2) *norm2 = no;
   if (E) *E = nu / no;
+  return SWCS_OK;
+}
+
+int swcs_energy_noalloc(swcs_ctx* c, double* E, double* numer, double* norm2) {
+  if (!c) return SWCS_E_INVALID;
+  if (!c->have_ints) return fail(c, SWCS_E_STATE, "integrals not set");
+  if (!c->have_state) return fail(c, SWCS_E_STATE, "no current state");
+  HIP_TRY(c, hipSetDevice(c->device), "hipSetDevice");
+  hipError_t e;
+  const Counters h = get_counters(c, &e);
+  if (e != hipSuccess) return hip_fail(c, e, "read counters");
+  const u64 n = h.n;
+  if (n > kNoAllocMaxEntries)
+    return fail(c, SWCS_E_CAPACITY, "state has " + std::to_string(n) + " stored entries; the allocation-free "
+                                     "energy takes at most " + std::to_string(kNoAllocMaxEntries));
+  double* base = nullptr;
+  HIP_TRY(c, noalloc_scratch(c->device, &base), "scratch address");
+  double* partial = base;
+  double* res = base + kNoAllocPartials;
+  DeviceState st = c->st;
+  st.diag = base + kNoAllocHead;
+  double* sig = st.diag + n;
+  const Ints I = ints_view(c);
+  if (n > 0) {
+    HIP_TRY(c, launch_diag(st, I, n, grid_blocks(c, n * kDiagLanes, 256), c->stream), "diagonal");
+    if (n <= (u64)pairwise_capacity()) {
+      const int pgrid = (int)std::min<u64>((n + 3) / 4, kNoAllocPartials / 2);
+      HIP_TRY(c, launch_sigma_pairwise(st, I, n, sig, partial, pgrid, c->stream), "sigma pairs");
+      HIP_TRY(c, launch_reduce_partials(partial, pgrid, pgrid, 2, res, c->stream), "reduce");
+    } else {
+      const int grid = std::min<int>(sigma_grid(c, n), (int)(kNoAllocPartials / 2));
+      HIP_TRY(c, launch_sigma_proj(st, I, c->exc, n, sig, partial, nullptr, grid, c->stream), "sigma");
+      HIP_TRY(c, launch_reduce_partials(partial, grid, grid, 2, res, c->stream), "reduce");
+    }
+  } else {
+    HIP_TRY(c, launch_fill_u32(res, 0u, 4, c->stream), "zero");
+  }
+  double out[2];
+  HIP_TRY(c, hipMemcpyAsync(out, res, 16, hipMemcpyDeviceToHost, c->stream), "copy");
+  HIP_TRY(c, hipStreamSynchronize(c->stream), "sync");
+  if (numer) *numer = out[0];
+  if (norm2) *norm2 = out[1];
+  if (E) *E = out[0] / out[1];
   return SWCS_OK;
 }
 

@@ -69,6 +69,7 @@ SIGNATURES = {
     "swcs_set_state": (ctypes.c_int, [_vp, _u64p, _dp, _i64]),
     "swcs_get_state": (ctypes.c_int, [_vp, _u64p, _dp, _i64, _i64p]),
     "swcs_energy": (ctypes.c_int, [_vp, _dp, _dp, _dp]),
+    "swcs_energy_noalloc": (ctypes.c_int, [_vp, _dp, _dp, _dp]),
     "swcs_sigma_projected": (ctypes.c_int, [_vp, _u64p, _dp, _i64, _i64p]),
     "swcs_pool_gradients": (ctypes.c_int, [_vp, _i32p, _i64, _dp]),
     "swcs_pool_gradients_device": (ctypes.c_int, [_vp, _vp, _i64, _vp]),
@@ -326,6 +327,13 @@ class Context:
         e, nu, no = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
         self._check(self._lib.swcs_energy(self._h, ctypes.byref(e), ctypes.byref(nu),
                                           ctypes.byref(no)))
+        return e.value, nu.value, no.value
+
+    def energy_noalloc(self):
+        """(E, numer, norm2) with no device allocation (fixed library scratch)."""
+        e, nu, no = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        self._check(self._lib.swcs_energy_noalloc(self._h, ctypes.byref(e), ctypes.byref(nu),
+                                                  ctypes.byref(no)))
         return e.value, nu.value, no.value
 
     def sigma_projected(self):
