@@ -72,7 +72,7 @@ def parse():
                     help="instead of the step benchmark: MP2-ordered UCCSD on this workload "
                          "(ansatz build, energy + adjoint gradient evaluation, L-BFGS steps)")
     ap.add_argument("--spin", action="store_true",
-                    help="with --uccsd: spin-complemented generators (one angle per commuting pair)")
+                    help="with --uccsd: spin-complemented generators (one angle per complement pair)")
     ap.add_argument("--eps", type=float, default=None,
                     help="pruning threshold for --uccsd (default: the workload's)")
     ap.add_argument("--vqe-iters", type=int, default=20,
@@ -618,7 +618,7 @@ def uccsd_bench(args):
     t = time.perf_counter()
     n_params = len(ans.ops)
     if args.spin:
-        # one angle per spin-complemented generator (commuting pairs tied)
+        # one angle per spin-complemented generator
         import scipy.optimize
         from paper_2411_07920_amd import spin
         gp = spin.spin_complemented(wl.pool)
@@ -634,8 +634,7 @@ def uccsd_bench(args):
         r = scipy.optimize.minimize(f, th0, jac=True, method="L-BFGS-B", callback=cb,
                                     options={"gtol": 1e-6, "ftol": 1e-15, "maxiter": args.vqe_iters})
         E, evals = float(r.fun), f.evals
-        ops_f, ang_f = spin.expand(gp, gens, r.x)
-        n_final = ctx.apply_ansatz(ops_f, ang_f, eps)
+        n_final = ctx.apply_generators(spin.gen_rows(gp, gens), r.x, eps)
     else:
         theta, E, trace, evals = adapt.preoptimize(ctx, ans.ops, ans.theta, cfg, log=log)
         n_final = ctx.apply_ansatz(ans.ops, theta, eps)

@@ -168,6 +168,24 @@ int swcs_set_pool(swcs_ctx* ctx, const int32_t* ops, int64_t K);
 int swcs_apply_ansatz(swcs_ctx* ctx, const int32_t* op_idx, const double* theta, int64_t M,
                       double eps, int64_t ncut, int64_t* n_det_out);
 
+/* Eq. (1) over spin-complemented generators (Sec. III): row i of
+ * gens[M x 3] (host int32) is (k1, k2, s).  k2 = -1: the unitary
+ * exp(theta_i A_k1).  Otherwise exp(theta_i (A_k1 + s A_k2)), s = +1 or -1,
+ * one parameter for two pool rows:
+ *   - rows acting on disjoint spin-orbitals commute and are applied as two
+ *     unitaries, exp(theta A_k1) then exp(s theta A_k2), each followed by
+ *     pruning;
+ *   - a double and its spin flip that share spin-orbitals (an opposite-spin
+ *     double with two indices on one spatial orbital) are applied as one
+ *     exact unitary: on a determinant both rows act on, exp(theta G) rotates
+ *     it and its two images at frequency sqrt(2) theta; other overlapping
+ *     rows fail with SWCS_E_UNSUPPORTED.
+ * Otherwise as swcs_apply_ansatz; swcs_param_gradients then returns one
+ * derivative per generator (M entries) and swcs_gate_sizes refers to the
+ * unitaries (a commuting pair counts two). */
+int swcs_apply_generators(swcs_ctx* ctx, const int32_t* gens, const double* theta, int64_t M,
+                          double eps, int64_t ncut, int64_t* n_det_out);
+
 /* Continue from the current state: apply M more unitaries with the same
  * pruning rule without resetting to the reference.  Parameter gradients are
  * not available after this call (they need an ansatz started from psi_0). */

@@ -99,6 +99,10 @@ def load():
         "orc_forward_sizes": (None, [i32p, i32p, dp, i64, ctypes.c_double, i64, u64,
                                      ctypes.POINTER(ctypes.c_int64)]),
         "orc_occupations": (None, [vp, vp, dp]),
+        "orc_apply_gen": (vp, [vp, i32p, i32p, ctypes.c_double, ctypes.c_double, i64, dp]),
+        "orc_apply_gen_sum": (vp, [vp, i32p, i32p]),
+        "orc_apply_gen_ansatz": (vp, [i32p, i32p, dp, i64, ctypes.c_double, i64, u64]),
+        "orc_gen_param_gradients": (None, [vp, i32p, i32p, dp, i64, ctypes.c_double, i64, u64, dp, dp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -263,6 +267,38 @@ class Oracle:
                                                  _p(ops, ctypes.c_int32), _p(tr, ctypes.c_double),
                                                  _p(te, ctypes.c_double), len(ops), float(eps),
                                                  int(ncut), int(ref)))
+
+    # -- spin-complemented generators (rows (k1, k2, s); k2 < 0: k1 alone) --
+    @staticmethod
+    def apply_gen(state, pool, gen3, theta, eps=0.0, ncut=0):
+        pool, g = _i32(pool), _i32(gen3)
+        d2 = ctypes.c_double(0.0)
+        h = load().orc_apply_gen(state._h, _p(pool, ctypes.c_int32), _p(g, ctypes.c_int32), float(theta),
+                                 float(eps), int(ncut), ctypes.byref(d2))
+        return OracleState(h)
+
+    @staticmethod
+    def apply_gen_sum(state, pool, gen3):
+        pool, g = _i32(pool), _i32(gen3)
+        return OracleState(load().orc_apply_gen_sum(state._h, _p(pool, ctypes.c_int32),
+                                                    _p(g, ctypes.c_int32)))
+
+    @staticmethod
+    def apply_gen_ansatz(pool, gens, theta, eps, ref, ncut=0):
+        pool, gens, theta = _i32(pool), _i32(gens), _f64(theta)
+        h = load().orc_apply_gen_ansatz(_p(pool, ctypes.c_int32), _p(gens, ctypes.c_int32),
+                                        _p(theta, ctypes.c_double), len(theta), float(eps), int(ncut),
+                                        int(ref))
+        return OracleState(h)
+
+    def gen_param_gradients(self, pool, gens, theta, eps, ref, ncut=0):
+        pool, gens, theta = _i32(pool), _i32(gens), _f64(theta)
+        out = np.zeros(len(theta))
+        e = ctypes.c_double()
+        self._lib.orc_gen_param_gradients(self._h, _p(pool, ctypes.c_int32), _p(gens, ctypes.c_int32),
+                                          _p(theta, ctypes.c_double), len(theta), float(eps), int(ncut),
+                                          int(ref), _p(out, ctypes.c_double), ctypes.byref(e))
+        return out, e.value
 
     def occupations(self, state):
         out = np.zeros(2 * self.n)

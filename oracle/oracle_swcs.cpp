@@ -34,6 +34,9 @@
 //                       the adjoint (reverse) recursion over stored states.
 //   orc_energy_frozen   Energy of the chain with every gate's support frozen to
 //                       that of a reference run (masked finite differences).
+//   orc_*_gen_*         The same for chains of spin-complemented generators
+//                       (Sec. III): a generator is a pool row, or two rows with
+//                       one shared parameter, G = A_k1 + s A_k2.
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -356,6 +359,180 @@ static double dot(const State& x, const State& y) {
   return acc;
 }
 
+// ---------------------------------------------------------------- generators
+// Spin-complemented generator G = A1 + s A2 (A_i = T_i - T_i^dagger of pool
+// rows 1 and 2, s = +-1) with one parameter theta (Sec. III).
+//
+// When T1 and T2 act on disjoint spin-orbitals they commute and
+// exp(theta G) = exp(theta A1) exp(s theta A2): the generator is applied as
+// those two unitaries (row 1 first), each followed by pruning.
+//
+// When T1 and T2 share their created pair (or their annihilated pair) and
+// are otherwise disjoint -- an opposite-spin double with p = q (or r = s) and
+// its complement -- G connects each determinant to at most two others, and
+// only in one of two shapes:
+//   * a pair {D, X}: exactly one of T1, T2 (or their adjoints) acts on D and
+//     X has no other connection -- the usual rotation at angle theta (at
+//     s theta for row 2);
+//   * a star {C, L1, L2}: T1 and T2 both act on C (or both adjoints do), with
+//     G C = alpha L1 + beta L2 (alpha, beta = +-1), G L1 = -alpha C,
+//     G L2 = -beta C.  G^2 C = -2 C, so on the star exp(theta G) rotates C
+//     and u = (alpha x1 + beta x2) / sqrt(2) at frequency sqrt(2) theta and
+//     leaves the leaf combination orthogonal to u unchanged:
+//       xc' = c2 xc - s2 u,   u' = s2 xc + c2 u,
+//       xi' = xi + (coef_i / sqrt(2)) (u' - u),  coef_1 = alpha, coef_2 = beta,
+//     with c2 = cos(sqrt(2) theta), s2 = sin(sqrt(2) theta).
+
+// Pool row's operator acting on D: +1 T, -1 T^dagger, 0 neither (it cannot
+// be both).  *X receives the image, *ph the sign of <X|T|D> or <X|T^dagger|D>.
+static int row_action(const int32_t* row, uint64_t D, uint64_t* X, int* ph) {
+  uint64_t Y = D;
+  int s = apply_string(excitation_string(row), Y);
+  if (s) {
+    *X = Y;
+    *ph = s;
+    return 1;
+  }
+  Y = D;
+  s = apply_string(deexcitation_string(row), Y);
+  if (s) {
+    *X = Y;
+    *ph = s;
+    return -1;
+  }
+  return 0;
+}
+
+static bool rows_share_spin_orbitals(const int32_t* r1, const int32_t* r2) {
+  for (int a = 0; a < 4; ++a)
+    for (int b = 0; b < 4; ++b)
+      if (r1[a] >= 0 && r1[a] == r2[b]) return true;
+  return false;
+}
+
+// <X|G|D> restricted to one row: the G-coefficient of X in G|D> for the row
+// acting on D (act = +1: +<X|T|D>, act = -1: -<X|T^dagger|D>), times its factor.
+static double gen_coef(int act, int ph, double factor) { return factor * (act > 0 ? ph : -ph); }
+
+// exp(theta G) for two rows sharing their created (or annihilated) pair.
+static State apply_star_gate(const int32_t* r1, const int32_t* r2, double sg, double c, double sn,
+                             double c2, double s2, double rt, const State& psi) {
+  State out = psi;
+  std::set<uint64_t> done;  // components already rotated, by their first member
+  auto val = [&](uint64_t k) {
+    auto it = psi.find(k);
+    return it == psi.end() ? 0.0 : it->second;
+  };
+  for (const auto& kv : psi) {
+    const uint64_t D = kv.first;
+    uint64_t X1 = 0, X2 = 0;
+    int p1 = 0, p2 = 0;
+    const int a1 = row_action(r1, D, &X1, &p1);
+    const int a2 = row_action(r2, D, &X2, &p2);
+    if (!a1 && !a2) continue;
+    // the component: a star centred at C, or a pair
+    uint64_t C = 0, L1 = 0, L2 = 0;
+    double al = 0.0, be = 0.0;
+    bool star = false;
+    if (a1 && a2) {
+      star = true;
+      C = D, L1 = X1, L2 = X2;
+      al = gen_coef(a1, p1, 1.0);
+      be = gen_coef(a2, p2, sg);
+    } else {
+      const int32_t* row = a1 ? r1 : r2;
+      const int32_t* other = a1 ? r2 : r1;
+      const uint64_t P = a1 ? X1 : X2;
+      uint64_t Q = 0;
+      int pq = 0, po = 0;
+      uint64_t Po = 0;
+      // the partner is a star centre if the other row acts on it as well
+      if (row_action(other, P, &Po, &po)) {
+        star = true;
+        C = P;
+        int pr = 0;
+        const int ar = row_action(row, C, &Q, &pr);
+        const int ao = row_action(other, C, &Po, &po);
+        L1 = a1 ? Q : Po;
+        L2 = a1 ? Po : Q;
+        al = a1 ? gen_coef(ar, pr, 1.0) : gen_coef(ao, po, 1.0);
+        be = a1 ? gen_coef(ao, po, sg) : gen_coef(ar, pr, sg);
+      } else {
+        // pair: the source is the member T acts on
+        const int act = a1 ? a1 : a2;
+        const int ph = a1 ? p1 : p2;
+        const uint64_t src = act > 0 ? D : P;
+        const uint64_t dst = act > 0 ? P : D;
+        if (done.count(src)) continue;
+        done.insert(src);
+        const double f = a1 ? 1.0 : sg;  // row 2 turns by s theta
+        const double sn_r = f * sn;
+        const double a = val(src), b = val(dst);
+        const double sp = (double)ph;  // <dst|T|src> either way
+        out[src] = c * a - sp * (sn_r * b);
+        out[dst] = c * b + sp * (sn_r * a);
+        continue;
+      }
+      (void)pq;
+    }
+    if (!star || done.count(C)) continue;
+    done.insert(C);
+    const double xc = val(C), x1 = val(L1), x2 = val(L2);
+    const double u = (al * x1 + be * x2) * rt;
+    const double nc = c2 * xc - s2 * u;
+    const double nu = s2 * xc + c2 * u;
+    const double du = nu - u;
+    out[C] = nc;
+    out[L1] = x1 + al * (rt * du);
+    out[L2] = x2 + be * (rt * du);
+  }
+  return out;
+}
+
+// One generator of a chain: pool rows r1 and r2 (r2 == NULL: the single row
+// r1), factor sg.
+struct Gen {
+  const int32_t* r1;
+  const int32_t* r2;
+  double sg;
+};
+
+static bool gen_is_star(const Gen& g) { return g.r2 && rows_share_spin_orbitals(g.r1, g.r2); }
+
+// exp(theta G) psi followed by pruning (after each unitary of a commuting pair).
+static State apply_gen(const Gen& g, double theta, double eps, int64_t ncut, const State& psi,
+                       double* dropped_sq) {
+  const double c = std::cos(theta), sn = std::sin(theta);
+  if (!g.r2) return truncate(apply_gate(g.r1, c, sn, psi), eps, ncut, dropped_sq);
+  if (!gen_is_star(g)) {
+    State mid = truncate(apply_gate(g.r1, c, sn, psi), eps, ncut, dropped_sq);
+    return truncate(apply_gate(g.r2, c, g.sg * sn, mid), eps, ncut, dropped_sq);
+  }
+  const double w = std::sqrt(2.0) * theta;
+  return truncate(apply_star_gate(g.r1, g.r2, g.sg, c, sn, std::cos(w), std::sin(w), 1.0 / std::sqrt(2.0), psi),
+                  eps, ncut, dropped_sq);
+}
+
+// G psi = A1 psi + s A2 psi.
+static State apply_gen_sum(const Gen& g, const State& psi) {
+  State out = apply_generator(g.r1, psi);
+  if (g.r2)
+    for (const auto& kv : apply_generator(g.r2, psi)) out[kv.first] += g.sg * kv.second;
+  return out;
+}
+
+static std::vector<Gen> gen_list(const int32_t* pool, const int32_t* gens, int64_t M) {
+  std::vector<Gen> v;
+  for (int64_t i = 0; i < M; ++i) {
+    Gen g;
+    g.r1 = pool + 4 * (int64_t)gens[3 * i];
+    g.r2 = gens[3 * i + 1] >= 0 ? pool + 4 * (int64_t)gens[3 * i + 1] : nullptr;
+    g.sg = (double)gens[3 * i + 2];
+    v.push_back(g);
+  }
+  return v;
+}
+
 // ---------------------------------------------------------------- C ABI
 struct OracleState {
   State psi;
@@ -536,6 +713,94 @@ double orc_energy_frozen(void* p, const int32_t* pool, const int32_t* ops,
   double numer, norm2, E;
   energy_of(pb, psi, &numer, &norm2, &E);
   return E;
+}
+
+// One generator on a state: gens3 = (k1, k2, s) rows of `pool` (k2 < 0: row
+// k1 alone), then pruning.
+void* orc_apply_gen(void* st, const int32_t* pool, const int32_t* gens3, double theta, double eps,
+                    int64_t ncut, double* dropped_sq) {
+  std::vector<Gen> g = gen_list(pool, gens3, 1);
+  OracleState* out = new OracleState;
+  double d2 = 0.0;
+  out->psi = apply_gen(g[0], theta, eps, ncut, ((OracleState*)st)->psi, &d2);
+  if (dropped_sq) *dropped_sq = d2;
+  return out;
+}
+
+// G|psi> of one generator.
+void* orc_apply_gen_sum(void* st, const int32_t* pool, const int32_t* gens3) {
+  std::vector<Gen> g = gen_list(pool, gens3, 1);
+  OracleState* out = new OracleState;
+  out->psi = apply_gen_sum(g[0], ((OracleState*)st)->psi);
+  return out;
+}
+
+// Chain of M generators gens[M x 3] from the reference, generator 0 first.
+void* orc_apply_gen_ansatz(const int32_t* pool, const int32_t* gens, const double* theta, int64_t M,
+                           double eps, int64_t ncut, uint64_t ref) {
+  std::vector<Gen> g = gen_list(pool, gens, M);
+  State psi;
+  psi[ref] = 1.0;
+  for (int64_t i = 0; i < M; ++i) psi = apply_gen(g[(size_t)i], theta[i], eps, ncut, psi, nullptr);
+  OracleState* out = new OracleState;
+  out->psi = psi;
+  return out;
+}
+
+// Frozen-support adjoint over a chain of generators.  A generator applied as
+// two commuting unitaries is two steps of the recursion (the second at angle
+// s theta, whose derivative enters with the factor s); an overlapping pair is
+// one step, nu = exp(-theta G) mu, dE/dtheta = <nu | G psi_{i-1}>.
+void orc_gen_param_gradients(void* p, const int32_t* pool, const int32_t* gens, const double* theta,
+                             int64_t M, double eps, int64_t ncut, uint64_t ref, double* dE,
+                             double* E_out) {
+  const Problem& pb = *(Problem*)p;
+  std::vector<Gen> g = gen_list(pool, gens, M);
+  // unit steps: (row or star generator, angle, generator index, factor)
+  struct Unit {
+    Gen gen;
+    double angle;
+    int64_t owner;
+    double factor;
+  };
+  std::vector<Unit> units;
+  for (int64_t i = 0; i < M; ++i) {
+    const Gen& gi = g[(size_t)i];
+    if (gi.r2 && !gen_is_star(gi)) {
+      units.push_back({Gen{gi.r1, nullptr, 1.0}, theta[i], i, 1.0});
+      units.push_back({Gen{gi.r2, nullptr, 1.0}, gi.sg * theta[i], i, gi.sg});
+    } else {
+      units.push_back({gi, theta[i], i, 1.0});
+    }
+  }
+  std::vector<State> st;
+  State psi;
+  psi[ref] = 1.0;
+  st.push_back(psi);
+  for (const Unit& u : units) {
+    psi = apply_gen(u.gen, u.angle, eps, ncut, psi, nullptr);
+    st.push_back(psi);
+  }
+  const State& psiN = st.back();
+  double numer, norm2, E;
+  energy_of(pb, psiN, &numer, &norm2, &E);
+  State sig = sigma_projected(pb, psiN);
+  State mu;
+  for (const auto& kv : psiN) mu[kv.first] = (2.0 / norm2) * (sig[kv.first] - E * kv.second);
+  for (int64_t i = 0; i < M; ++i) dE[i] = 0.0;
+  for (int64_t j = (int64_t)units.size() - 1; j >= 0; --j) {
+    const Unit& u = units[(size_t)j];
+    // nu = exp(-angle G) mu without pruning
+    State nu = apply_gen(u.gen, -u.angle, 0.0, 0, mu, nullptr);
+    dE[u.owner] += u.factor * dot(nu, apply_gen_sum(u.gen, st[(size_t)j]));
+    State next;
+    for (const auto& kv : st[(size_t)j]) {
+      auto it = nu.find(kv.first);
+      next[kv.first] = (it == nu.end()) ? 0.0 : it->second;
+    }
+    mu = next;
+  }
+  if (E_out) *E_out = E;
 }
 
 // Sizes of every intermediate state (|psi_0| .. |psi_M|) of a forward run.

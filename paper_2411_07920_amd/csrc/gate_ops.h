@@ -45,6 +45,17 @@ struct PairRec {
   double a_old, b_old;
 };
 
+// One logged star {C, L1, L2} of a generator gate whose rows overlap
+// (k_generator.hip): stored positions (0xffffffff = not stored), the signs
+// alpha, beta of G C = alpha L1 + beta L2, and the values before the gate
+// (dead if not in the state).
+struct StarRec {
+  unsigned iC, i1, i2;
+  signed char al, be;
+  unsigned short pad;
+  double xc, x1, x2;
+};
+
 // Store: key(i), amp(i), set_amp(i, v), find(key) -> index or -1.
 template <class Store>
 __device__ inline GateOut gate_entry(Store& S, u64 i, const OpDesc& op, double c, double sn,

@@ -143,8 +143,13 @@ struct swcs_ctx {
 
   // last ansatz (for parameter gradients)
   bool ansatz_valid = false;
-  std::vector<int32_t> a_ops;
-  std::vector<double> a_theta, a_c, a_s;
+  std::vector<int32_t> a_ops;           // per unitary: pool row (row 1 of a star gate)
+  std::vector<double> a_theta, a_c, a_s;  // parameters; cos / sin of each unitary's angle
+  std::vector<int> a_kind;              // per unitary: 0 one row, 1 overlapping generator
+  std::vector<GenGate> a_gen;           // per unitary (kind 1)
+  std::vector<int64_t> a_owner;         // per unitary: its parameter
+  std::vector<double> a_factor;         // d(angle) / d(parameter)
+  bool a_has_star = false;
   double a_eps = 0.0;
   int64_t a_ncut = 0;
   int seg = 1;
@@ -452,7 +457,10 @@ int upload_ckpt_table(swcs_ctx* c, int nck) {
 // (LDS-resident) for as long as it fits; the rest runs one multi-block
 // launch per gate in HBM, growing the arrays when a gate would not fit.
 int run_chain(swcs_ctx* c, const int32_t* op_idx, const double* cs, const double* sn, int64_t M,
-              double eps, unsigned ncut, bool ckpt, u64 n_start, Counters* out) {
+              double eps, unsigned ncut, bool ckpt, u64 n_start, Counters* out,
+              const int* kind = nullptr, const GenGate* gen = nullptr) {
+  bool has_star = false;
+  for (int64_t g = 0; kind && g < M; ++g) has_star |= kind[g] != 0;
   // With N_CUT the gates keep everything and the selection prunes.
   if (ncut) eps = 0.0;
   int64_t g0 = 0;
@@ -483,7 +491,9 @@ int run_chain(swcs_ctx* c, const int32_t* op_idx, const double* cs, const double
     int r = upload_ckpt_table(c, nck);
     if (r) return r;
   }
-  if (n_start <= (u64)lds_chain_capacity() && c->st.cap >= (u64)lds_chain_capacity() &&
+  // overlapping generators have no single-workgroup kernel: such chains run
+  // in HBM from the first gate
+  if (!has_star && n_start <= (u64)lds_chain_capacity() && c->st.cap >= (u64)lds_chain_capacity() &&
       M <= (int64_t)1 << 30) {
     TIMED(c, SWCS_K_CHAIN_LDS, launch_chain_lds(c->st, c->gate_tab.as<GateDesc>(), 0, (int)M, eps, eps > 0.0 ? 1 : 0,
                                 ckpt ? c->ckpt_ptrs.as<double*>() : nullptr, c->ckpt_n.as<u64>(),
@@ -512,9 +522,13 @@ int run_chain(swcs_ctx* c, const int32_t* op_idx, const double* cs, const double
                                     grid_blocks(c, c->st.cap / 4, 256), c->stream), "checkpoint");
       }
       const OpDesc& op = c->ops_host[op_idx[g]];
-      TIMED(c, SWCS_K_GATE, launch_gate(c->st, op, cs[g], sn[g], eps, c->gate_n_in.as<u64>() + g, 1,
-                             (unsigned)g, c->sector, gate_grid(c, c->st.cap / 2, kGateTile), c->stream),
-              "gate");
+      if (kind && kind[g])
+        HIP_TRY(c, launch_gen_gate(c->st, gen[g], eps, c->gate_n_in.as<u64>() + g, (unsigned)g, c->sector,
+                                   grid_blocks(c, c->st.cap / 2, 256), c->stream), "generator gate");
+      else
+        TIMED(c, SWCS_K_GATE, launch_gate(c->st, op, cs[g], sn[g], eps, c->gate_n_in.as<u64>() + g, 1,
+                               (unsigned)g, c->sector, gate_grid(c, c->st.cap / 2, kGateTile), c->stream),
+                "gate");
       // The gates only test the entries they touch; entries of a starting
       // state that were never tested against eps are pruned once, after the
       // first gate, so every later state is exactly P(U psi).
@@ -541,8 +555,10 @@ int run_chain(swcs_ctx* c, const int32_t* op_idx, const double* cs, const double
       c->have_state = false;  // the chain stopped part way
       return fail(c, SWCS_E_CAPACITY, "state exceeds the fixed capacity (regrowth disabled)");
     }
-    // Grow so that the stopped gate (and a few more) fit, then resume.
-    const u64 need = h.n + std::min<u64>(h.alive, c->sector > h.n ? c->sector - h.n : 0);
+    // Grow so that the stopped gate (and a few more) fit, then resume (a star
+    // gate appends up to two entries per alive one).
+    const u64 grow = (kind && kind[h.stop_gate]) ? 2 * h.alive : h.alive;
+    const u64 need = h.n + std::min<u64>(grow, c->sector > h.n ? c->sector - h.n : 0);
     u64 cap = next_pow2(std::max<u64>(2 * c->st.cap, 2 * need));
     u64 maxc = max_capacity(c);
     if (maxc < cap) {
@@ -847,24 +863,44 @@ int swcs_set_pool(swcs_ctx* c, const int32_t* rows, int64_t K) {
   return SWCS_OK;
 }
 
-static int apply_common(swcs_ctx* c, const int32_t* op_idx, const double* theta, int64_t M,
-                        double eps, int64_t ncut, int64_t* n_det_out, bool from_reference) {
-  int r = check_ready(c);
-  if (r) return r;
-  r = validate_gates(c, op_idx, theta, M, eps, ncut);
-  if (r) return r;
+// The unitaries of one apply call and the parameters they depend on.
+struct ChainSpec {
+  std::vector<int32_t> ops;    // pool row (row 1 of a star gate)
+  std::vector<double> cs, sn;  // cos and sin of each unitary's angle
+  std::vector<int> kind;       // 0 one row, 1 overlapping generator
+  std::vector<GenGate> gen;    // kind 1
+  std::vector<int64_t> owner;  // parameter of each unitary
+  std::vector<double> factor;  // d(angle) / d(parameter)
+  std::vector<double> theta;   // the parameters
+  bool has_star = false;
+};
+
+static void spec_plain(const int32_t* op_idx, const double* theta, int64_t M, ChainSpec* sp) {
+  sp->ops.assign(op_idx, op_idx + M);
+  sp->theta.assign(theta, theta + M);
+  sp->cs.resize((size_t)M);
+  sp->sn.resize((size_t)M);
+  for (int64_t i = 0; i < M; ++i) {
+    sp->cs[(size_t)i] = std::cos(theta[i]);
+    sp->sn[(size_t)i] = std::sin(theta[i]);
+  }
+  sp->kind.assign((size_t)M, 0);
+  sp->gen.assign((size_t)M, GenGate{});
+  sp->owner.resize((size_t)M);
+  for (int64_t i = 0; i < M; ++i) sp->owner[(size_t)i] = i;
+  sp->factor.assign((size_t)M, 1.0);
+}
+
+static int apply_common(swcs_ctx* c, ChainSpec& sp, double eps, int64_t ncut, int64_t* n_det_out,
+                        bool from_reference) {
+  const int64_t M = (int64_t)sp.ops.size();
   if (!from_reference && !c->have_state) return fail(c, SWCS_E_STATE, "no current state");
   HIP_TRY(c, hipSetDevice(c->device), "hipSetDevice");
   ++c->state_version;
-  std::vector<double> cs((size_t)M), sn((size_t)M);
-  for (int64_t i = 0; i < M; ++i) {
-    cs[(size_t)i] = std::cos(theta[i]);
-    sn[(size_t)i] = std::sin(theta[i]);
-  }
   HIP_TRY(c, c->gate_n_in.ensure(std::max<int64_t>(1, M) * sizeof(u64)), "alloc stats");
   c->ansatz_valid = false;
   if (from_reference) {
-    r = state_reset_to_reference(c);
+    int r = state_reset_to_reference(c);
     if (r) return r;
     c->seg = std::max<int>(1, (int)std::ceil(std::sqrt((double)std::max<int64_t>(1, M))));
     const int nck = (int)((M + c->seg - 1) / c->seg) + 1;
@@ -883,17 +919,23 @@ static int apply_common(swcs_ctx* c, const int32_t* op_idx, const double* theta,
     n_start = h0.n;
   }
   HIP_TRY(c, c->ncut_state.ensure(sizeof(NcutState)), "alloc ncut state");
-  r = run_chain(c, op_idx, cs.data(), sn.data(), M, eps, (unsigned)ncut, from_reference, n_start, &h);
+  int r = run_chain(c, sp.ops.data(), sp.cs.data(), sp.sn.data(), M, eps, (unsigned)ncut, from_reference,
+                    n_start, &h, sp.kind.data(), sp.gen.data());
   if (r) return r;
   r = build_filter(c, h.n, h.alive);
   if (r) return r;
   c->peak_n = std::max<u64>(c->peak_n, h.n);
   c->last_M = M;
   if (from_reference) {
-    c->a_ops.assign(op_idx, op_idx + M);
-    c->a_theta.assign(theta, theta + M);
-    c->a_c = cs;
-    c->a_s = sn;
+    c->a_ops = sp.ops;
+    c->a_theta = sp.theta;
+    c->a_c = sp.cs;
+    c->a_s = sp.sn;
+    c->a_kind = sp.kind;
+    c->a_gen = sp.gen;
+    c->a_owner = sp.owner;
+    c->a_factor = sp.factor;
+    c->a_has_star = sp.has_star;
     c->a_eps = eps;
     c->a_ncut = ncut;
     c->ansatz_valid = true;
@@ -905,13 +947,93 @@ static int apply_common(swcs_ctx* c, const int32_t* op_idx, const double* theta,
 int swcs_apply_ansatz(swcs_ctx* c, const int32_t* op_idx, const double* theta, int64_t M,
                       double eps, int64_t ncut, int64_t* n_det_out) {
   if (!c) return SWCS_E_INVALID;
-  return apply_common(c, op_idx, theta, M, eps, ncut, n_det_out, true);
+  int r = check_ready(c);
+  if (r) return r;
+  r = validate_gates(c, op_idx, theta, M, eps, ncut);
+  if (r) return r;
+  ChainSpec sp;
+  spec_plain(op_idx, theta, M, &sp);
+  return apply_common(c, sp, eps, ncut, n_det_out, true);
+}
+
+// Row k2 is the spin flip of row k1 (every spin-orbital P -> P ^ 1, in the
+// same or the adjoint orientation).
+static bool is_spin_flip(const OpDesc& a, const OpDesc& b) {
+  auto flip = [](u64 m) { return ((m & 0x5555555555555555ULL) << 1) | ((m >> 1) & 0x5555555555555555ULL); };
+  return (flip(a.cre) == b.cre && flip(a.ann) == b.ann) || (flip(a.cre) == b.ann && flip(a.ann) == b.cre);
+}
+
+int swcs_apply_generators(swcs_ctx* c, const int32_t* gens, const double* theta, int64_t M, double eps,
+                          int64_t ncut, int64_t* n_det_out) {
+  if (!c) return SWCS_E_INVALID;
+  int r = check_ready(c);
+  if (r) return r;
+  if (M < 0) return fail(c, SWCS_E_INVALID, "M < 0");
+  if (M > 0 && (!gens || !theta)) return fail(c, SWCS_E_INVALID, "null gens/theta");
+  if (!(eps >= 0.0) || !std::isfinite(eps)) return fail(c, SWCS_E_INVALID, "eps must be finite and >= 0");
+  if (ncut < 0 || ncut > 0x7fffffffLL) return fail(c, SWCS_E_INVALID, "ncut out of range");
+  ChainSpec sp;
+  const double rt = 1.0 / std::sqrt(2.0);
+  for (int64_t i = 0; i < M; ++i) {
+    const int32_t k1 = gens[3 * i], k2 = gens[3 * i + 1], sg = gens[3 * i + 2];
+    const std::string at = "generator " + std::to_string(i) + ": ";
+    if (k1 < 0 || k1 >= c->K_pool) return fail(c, SWCS_E_INVALID, at + "row 1 out of range");
+    if (k2 < -1 || k2 >= c->K_pool || k2 == k1) return fail(c, SWCS_E_INVALID, at + "bad row 2");
+    if (k2 >= 0 && sg != 1 && sg != -1) return fail(c, SWCS_E_INVALID, at + "sign must be +1 or -1");
+    if (!std::isfinite(theta[i])) return fail(c, SWCS_E_INVALID, at + "non-finite theta");
+    const double cth = std::cos(theta[i]), sth = std::sin(theta[i]);
+    auto push = [&](int32_t k, double sn_u, double factor, int kd, const GenGate& g) {
+      sp.ops.push_back(k);
+      sp.cs.push_back(cth);
+      sp.sn.push_back(sn_u);
+      sp.kind.push_back(kd);
+      sp.gen.push_back(g);
+      sp.owner.push_back(i);
+      sp.factor.push_back(factor);
+    };
+    if (k2 < 0) {
+      push(k1, sth, 1.0, 0, GenGate{});
+    } else {
+      const OpDesc& o1 = c->ops_host[k1];
+      const OpDesc& o2 = c->ops_host[k2];
+      const bool overlap = ((o1.ann | o1.cre) & (o2.ann | o2.cre)) != 0;
+      if (!overlap) {
+        // commuting parts: two unitaries, row 2 at s theta
+        push(k1, sth, 1.0, 0, GenGate{});
+        push(k2, (double)sg * sth, (double)sg, 0, GenGate{});
+      } else {
+        if (o1.R < 0 || o2.R < 0 || !is_spin_flip(o1, o2))
+          return fail(c, SWCS_E_UNSUPPORTED, at + "overlapping rows must be a double and its spin flip");
+        GenGate g;
+        g.op1 = o1;
+        g.op2 = o2;
+        g.c = cth;
+        g.sn = sth;
+        g.sn2 = (double)sg * sth;
+        const double w = std::sqrt(2.0) * theta[i];
+        g.c2 = std::cos(w);
+        g.s2 = std::sin(w);
+        g.rt = rt;
+        g.sg = (double)sg;
+        push(k1, sth, 1.0, 1, g);
+        sp.has_star = true;
+      }
+    }
+  }
+  sp.theta.assign(theta, theta + M);
+  return apply_common(c, sp, eps, ncut, n_det_out, true);
 }
 
 int swcs_apply_gates(swcs_ctx* c, const int32_t* op_idx, const double* theta, int64_t M,
                      double eps, int64_t ncut, int64_t* n_det_out) {
   if (!c) return SWCS_E_INVALID;
-  return apply_common(c, op_idx, theta, M, eps, ncut, n_det_out, false);
+  int r = check_ready(c);
+  if (r) return r;
+  r = validate_gates(c, op_idx, theta, M, eps, ncut);
+  if (r) return r;
+  ChainSpec sp;
+  spec_plain(op_idx, theta, M, &sp);
+  return apply_common(c, sp, eps, ncut, n_det_out, false);
 }
 
 int swcs_set_state(swcs_ctx* c, const uint64_t* keys, const double* amps, int64_t n) {
@@ -1513,9 +1635,10 @@ int swcs_pool_gradients(swcs_ctx* c, const int32_t* subset, int64_t n_subset, do
 int swcs_param_gradients(swcs_ctx* c, double* dE, double* E_out) {
   if (!c) return SWCS_E_INVALID;
   if (!c->ansatz_valid) return fail(c, SWCS_E_STATE, "no ansatz applied from the reference");
-  if (!dE && c->a_ops.size() > 0) return fail(c, SWCS_E_INVALID, "null dE_dtheta");
+  if (!dE && c->a_theta.size() > 0) return fail(c, SWCS_E_INVALID, "null dE_dtheta");
   HIP_TRY(c, hipSetDevice(c->device), "hipSetDevice");
-  const int64_t M = (int64_t)c->a_ops.size();
+  const int64_t M = (int64_t)c->a_ops.size();  // unitaries (a parameter may drive two)
+  const int64_t M_par = (int64_t)c->a_theta.size();
   hipError_t e;
   Counters hfin = get_counters(c, &e);
   if (e != hipSuccess) return hip_fail(c, e, "read counters");
@@ -1536,12 +1659,18 @@ int swcs_param_gradients(swcs_ctx* c, double* dE, double* E_out) {
   const int grid = grid_blocks(c, n, 256);
   HIP_TRY(c, c->mu.ensure(n * 8), "alloc mu");
   HIP_TRY(c, c->gbuf.ensure((size_t)M * 8), "alloc dE");
-  const bool lds = n <= (u64)lds_chain_capacity();
+  const bool lds = !c->a_has_star && n <= (u64)lds_chain_capacity();
   // Pair logs: at most one record per stored entry per gate, for every gate
   // (single-workgroup path, all segments replayed at once) or for one
-  // segment at a time (HBM path).
-  HIP_TRY(c, c->seg_states.ensure((size_t)(lds ? M : seg) * n * sizeof(PairRec)), "alloc pair logs");
+  // segment at a time (HBM path); with overlapping generators each gate's
+  // slot also holds up to one star record per stored entry.
+  const size_t gate_log_bytes = n * (sizeof(PairRec) + (c->a_has_star ? sizeof(StarRec) : 0));
+  HIP_TRY(c, c->seg_states.ensure((size_t)(lds ? M : seg) * gate_log_bytes), "alloc pair logs");
   PairRec* logs = c->seg_states.as<PairRec>();
+  auto plog_of = [&](int t) { return (PairRec*)((char*)c->seg_states.p + (size_t)t * gate_log_bytes); };
+  auto slog_of = [&](int t) {
+    return (StarRec*)((char*)c->seg_states.p + (size_t)t * gate_log_bytes + n * sizeof(PairRec));
+  };
   HIP_TRY(c, launch_mu_init(c->st, c->sigma.as<double>(), n, nn, c->mu.as<double>(), c->stream), "mu init");
   if (lds) {
     // Segments replayed side by side (one workgroup each), then one
@@ -1563,33 +1692,42 @@ int swcs_param_gradients(swcs_ctx* c, double* dE, double* E_out) {
     // segment's gates logging their active pairs, then walk the logs back.
     HIP_TRY(c, c->partial2.ensure((size_t)M * grid * 8), "alloc partials");
     HIP_TRY(c, c->work.ensure(n * 8), "alloc working amplitudes");
-    HIP_TRY(c, c->ctr_r.ensure((size_t)seg * sizeof(u64)), "alloc log counters");
+    HIP_TRY(c, c->ctr_r.ensure((size_t)2 * seg * sizeof(u64)), "alloc log counters");
     double* W = c->work.as<double>();
-    u64* lc = c->ctr_r.as<u64>();
+    u64* lc = c->ctr_r.as<u64>();   // pair records per gate of the segment
+    u64* sc = lc + seg;             // star records per gate
     for (int j = nseg - 1; j >= 0; --j) {
       const int64_t g_lo = (int64_t)j * seg;
       const int64_t g_hi = std::min<int64_t>(M, g_lo + seg);
       const int len = (int)(g_hi - g_lo);
       HIP_TRY(c, launch_restore(W, c->ckpt[j].as<double>(), c->ckpt_n.as<u64>() + j, n, c->stream), "restore");
-      HIP_TRY(c, launch_fill_u32(lc, 0u, (u64)len * 2, c->stream), "zero log counters");
+      HIP_TRY(c, launch_fill_u32(lc, 0u, (u64)seg * 4, c->stream), "zero log counters");
       for (int t = 0; t < len; ++t) {
         const int64_t g = g_lo + t;
-        TIMED(c, SWCS_K_GATE_REPLAY, launch_gate_replay(c->st, W, n, c->ops_host[c->a_ops[g]], c->a_c[g], c->a_s[g],
-                                      c->a_ncut ? 0.0 : c->a_eps, logs + (size_t)t * n, lc + t,
-                                      gate_grid(c, n, kReplayTile), c->stream), "replay");
+        if (c->a_kind[g])
+          HIP_TRY(c, launch_gen_replay(c->st, W, n, c->a_gen[g], c->a_ncut ? 0.0 : c->a_eps, plog_of(t), lc + t,
+                                       slog_of(t), sc + t, grid_blocks(c, n, 256), c->stream), "generator replay");
+        else
+          TIMED(c, SWCS_K_GATE_REPLAY, launch_gate_replay(c->st, W, n, c->ops_host[c->a_ops[g]], c->a_c[g], c->a_s[g],
+                                        c->a_ncut ? 0.0 : c->a_eps, plog_of(t), lc + t,
+                                        gate_grid(c, n, kReplayTile), c->stream), "replay");
         if (c->a_ncut)
           HIP_TRY(c, launch_ncut(W, c->st.keys, n, nullptr, c->ncut_state.as<NcutState>(), (unsigned)c->a_ncut,
                                  grid, c->stream), "ncut");
       }
       for (int t = len - 1; t >= 0; --t) {
         const int64_t g = g_lo + t;
-        TIMED(c, SWCS_K_ADJOINT_REC, launch_adjoint_rec(logs + (size_t)t * n, lc + t, c->mu.as<double>(), c->a_c[g], c->a_s[g],
+        TIMED(c, SWCS_K_ADJOINT_REC, launch_adjoint_rec(plog_of(t), lc + t, c->mu.as<double>(), c->a_c[g], c->a_s[g],
                                       c->partial2.as<double>() + (size_t)g * grid, grid, c->stream), "reverse");
+        if (c->a_kind[g])
+          HIP_TRY(c, launch_adjoint_star(slog_of(t), sc + t, c->mu.as<double>(), c->a_gen[g],
+                                         c->partial2.as<double>() + (size_t)g * grid, grid, c->stream), "reverse stars");
       }
     }
     HIP_TRY(c, launch_reduce_partials(c->partial2.as<double>(), grid, grid, (int)M, c->gbuf.as<double>(), c->stream), "reduce");
   }
-  HIP_TRY(c, hipMemcpyAsync(dE, c->gbuf.p, (size_t)M * 8, hipMemcpyDeviceToHost, c->stream), "copy dE");
+  std::vector<double> d_unit((size_t)M);
+  HIP_TRY(c, hipMemcpyAsync(d_unit.data(), c->gbuf.p, (size_t)M * 8, hipMemcpyDeviceToHost, c->stream), "copy dE");
   double nn_host[2];
   HIP_TRY(c, hipMemcpyAsync(nn_host, nn, 16, hipMemcpyDeviceToHost, c->stream), "copy energy");
   Counters hchk = read_counters(c, &e);  // synchronizes
@@ -1600,6 +1738,9 @@ int swcs_param_gradients(swcs_ctx* c, double* dE, double* E_out) {
     c->hc = hchk;
     return fail(c, SWCS_E_DEVICE, "recomputation diverged from the forward run");
   }
+  // per parameter: the unitaries it drives, each scaled by d(angle)/d(parameter)
+  for (int64_t i = 0; i < M_par; ++i) dE[i] = 0.0;
+  for (int64_t g = 0; g < M; ++g) dE[c->a_owner[(size_t)g]] += c->a_factor[(size_t)g] * d_unit[(size_t)g];
   if (E_out) *E_out = nn_host[0] / nn_host[1];
   return SWCS_OK;
 }

@@ -247,6 +247,17 @@ struct GateDesc {
   double s;  // sin(theta)
 };
 
+// A spin-complemented generator G = A1 + s A2 whose rows share spin-orbitals,
+// applied as one gate exp(theta G) (k_generator.hip).
+struct GenGate {
+  OpDesc op1, op2;
+  double c, sn;   // cos theta, sin theta: pairs of row 1
+  double sn2;     // s sin theta: pairs of row 2
+  double c2, s2;  // cos(sqrt(2) theta), sin(sqrt(2) theta): stars
+  double rt;      // 1 / sqrt(2)
+  double sg;      // s = +-1
+};
+
 // Largest state the single-workgroup LDS kernels hold (24 B per entry for
 // the forward chain, 32 B for the adjoint sweep: 128 KB of LDS).
 constexpr int kLdsCap = 4096;
@@ -286,6 +297,14 @@ __device__ inline bool filter_maybe(const unsigned* __restrict__ filt, u64 fmask
 
 // Launch wrappers (defined in the .hip files).  All enqueue on `stream`.
 struct PairRec;
+struct StarRec;
+hipError_t launch_gen_gate(const DeviceState& st, const GenGate& g, double eps, u64* gate_n_in,
+                           unsigned gate_index, u64 max_keys, int grid, hipStream_t stream);
+hipError_t launch_gen_replay(const DeviceState& st, double* amps, u64 n, const GenGate& g, double eps,
+                             PairRec* plog, u64* pcount, StarRec* slog, u64* scount, int grid,
+                             hipStream_t stream);
+hipError_t launch_adjoint_star(const StarRec* slog, const u64* scount, double* mu, const GenGate& g,
+                               double* partial, int grid, hipStream_t stream);
 hipError_t launch_fill_u32(void* p, unsigned v, u64 words, hipStream_t stream);
 hipError_t launch_store_counters(Counters* ctr, const Counters& v, hipStream_t stream);
 hipError_t launch_clear_flag(Counters* ctr, unsigned bit, hipStream_t stream);

@@ -7,18 +7,19 @@ G = A(T) + A(T'), A(X) = X - X^dagger.  The pool holds T' in canonical form
 as row k' with A(T') = sign * A_k'.
 
 When T and T' touch disjoint spin-orbitals (singles, same-spin doubles, and
-opposite-spin doubles whose two spatial pairs share no orbital) the two parts
+opposite-spin doubles whose spatial indices are all distinct) the two parts
 are even operators on disjoint modes and commute, so
 exp(theta G) = exp(theta A_k) exp(sign theta A_k'): two gates with one shared
 parameter.  A row that is its own complement is one gate.  An opposite-spin
-double with p = q or r = s (not both) overlaps its complement; the parts do
-not commute and the exact exponential is not a product of two gates, so such
-rows stay separate generators here.
+double with two indices on one spatial orbital (p = q, r = s, p = s or q = r,
+not a self-complement) shares spin-orbitals with its complement; the parts do
+not commute, and the library applies exp(theta G) as one exact gate (a
+determinant both parts act on turns with its two images at frequency
+sqrt(2) theta).
 
-All arithmetic on states runs in the library; this module maps generators to
-gates and combines per-gate results:
-  pool gradient of G   g_G = g_k + sign * g_k'   (linear in the generator)
-  parameter gradient   dE/dtheta = dE/dtheta_k + sign * dE/dtheta_k'
+All arithmetic on states runs in the library (swcs_apply_generators with rows
+(k, k', sign)); this module builds the generator list and combines the pool
+gradients, which are linear in the generator: g_G = g_k + sign * g_k'.
 """
 from __future__ import annotations
 
@@ -31,9 +32,10 @@ import scipy.optimize
 
 @dataclasses.dataclass
 class GeneratorPool:
-    first: np.ndarray    # int32 [G] pool row of the first gate
-    second: np.ndarray   # int32 [G] pool row of the second gate, -1 for one-gate generators
-    sign: np.ndarray     # float64 [G] angle factor of the second gate (0 when there is none)
+    first: np.ndarray    # int32 [G] first pool row
+    second: np.ndarray   # int32 [G] second pool row, -1 for one-row generators
+    sign: np.ndarray     # float64 [G] factor of the second row (0 when there is none)
+    overlap: np.ndarray  # bool [G] the two rows share spin-orbitals (one exact gate)
 
     def __len__(self):
         return len(self.first)
@@ -57,11 +59,14 @@ def complement_row(row):
     return (C, D, A, B), -sign
 
 
-def spin_complemented(pool) -> GeneratorPool:
+def spin_complemented(pool, overlapping=True) -> GeneratorPool:
+    """Every pool row paired with its spin complement.  overlapping=False
+    keeps rows that share spin-orbitals with their complement as separate
+    one-row generators (the commuting pairs only)."""
     pool = np.asarray(pool)
     index = {tuple(int(x) for x in r): k for k, r in enumerate(pool)}
     seen = np.zeros(len(pool), dtype=bool)
-    first, second, sign = [], [], []
+    first, second, sign, over = [], [], [], []
     for k, r in enumerate(pool):
         if seen[k]:
             continue
@@ -71,14 +76,25 @@ def spin_complemented(pool) -> GeneratorPool:
         modes = {int(x) for x in r if x >= 0}
         modes2 = {int(x) for x in row2 if x >= 0}
         if k2 == k:
-            first.append(k), second.append(-1), sign.append(0.0)
-        elif modes & modes2:
+            first.append(k), second.append(-1), sign.append(0.0), over.append(False)
+        elif modes & modes2 and not overlapping:
             for kk in (k, k2):
-                first.append(kk), second.append(-1), sign.append(0.0)
+                first.append(kk), second.append(-1), sign.append(0.0), over.append(False)
         else:
-            first.append(k), second.append(k2), sign.append(s)
+            first.append(k), second.append(k2), sign.append(s), over.append(bool(modes & modes2))
     return GeneratorPool(np.array(first, dtype=np.int32), np.array(second, dtype=np.int32),
-                         np.array(sign, dtype=np.float64))
+                         np.array(sign, dtype=np.float64), np.array(over, dtype=bool))
+
+
+def gen_rows(gp: GeneratorPool, gens) -> np.ndarray:
+    """int32 [M, 3] rows (k, k', sign) of generators `gens` for the library's
+    generator chain (k' = -1 for one-row generators)."""
+    g = np.asarray(gens, dtype=np.int64)
+    rows = np.empty((len(g), 3), dtype=np.int32)
+    rows[:, 0] = gp.first[g]
+    rows[:, 1] = gp.second[g]
+    rows[:, 2] = np.where(gp.second[g] >= 0, gp.sign[g], 1.0).astype(np.int32)
+    return rows
 
 
 def generator_gradients(gp: GeneratorPool, g_pool) -> np.ndarray:
@@ -90,9 +106,12 @@ def generator_gradients(gp: GeneratorPool, g_pool) -> np.ndarray:
 
 
 def expand(gp: GeneratorPool, gens, theta):
-    """Gate list (pool rows, angles) of generators `gens` with angles `theta`,
-    first generator applied first."""
+    """Gate list (pool rows, angles) of commuting generators `gens` with
+    angles `theta`, first generator applied first (a generator whose rows
+    overlap is not a product of gates: use gen_rows)."""
     ops, ang = [], []
+    if np.any(gp.overlap[np.asarray(gens, dtype=np.int64)]):
+        raise ValueError("generators with overlapping rows are one gate each: use gen_rows")
     for j, t in zip(np.asarray(gens, dtype=np.int64).tolist(), np.asarray(theta, dtype=np.float64).tolist()):
         ops.append(int(gp.first[j]))
         ang.append(t)
@@ -117,12 +136,13 @@ def contract(gp: GeneratorPool, gens, dE_gates) -> np.ndarray:
 
 
 class TiedEnergy:
-    """E and dE/dtheta over generator parameters (each expanded into its
-    gates).  A call at exactly the previous angles returns the previous result
+    """E and dE/dtheta over generator parameters (the library's generator
+    chain).  A call at exactly the previous angles returns the previous result
     without touching the context, whose state is then still at those angles."""
 
     def __init__(self, ctx, gp: GeneratorPool, gens, eps=0.0):
         self.ctx, self.gp, self.gens, self.eps = ctx, gp, list(gens), eps
+        self.rows = gen_rows(gp, self.gens)
         self.evals = 0
         self._last = None
 
@@ -130,11 +150,10 @@ class TiedEnergy:
         theta = np.array(theta, dtype=np.float64)
         if self._last is not None and np.array_equal(theta, self._last[0]):
             return self._last[1], self._last[2].copy()
-        ops, ang = expand(self.gp, self.gens, theta)
-        self.ctx.apply_ansatz(ops, ang, self.eps)
-        dE, E = self.ctx.param_gradients(len(ops))
+        self.ctx.apply_generators(self.rows, theta, self.eps)
+        dE, E = self.ctx.param_gradients(len(theta))
         self.evals += 1
-        d = contract(self.gp, self.gens, np.asarray(dE))
+        d = np.array(dE, dtype=np.float64)
         self._last = (theta, E, d)
         return E, d.copy()
 
@@ -148,13 +167,15 @@ def seed_new_angle(ctx, gp: GeneratorPool, gens, theta, eps):
     angles are dropped), where a gradient optimizer does not move.  Without
     pruning E is a trigonometric polynomial of degree 2 per gate in this
     angle, so at most 4 for a two-gate generator; nine samples fit it and
-    its minimum on a grid is the start.  Returns (theta, evaluations)."""
+    its minimum on a grid is the start (for a generator whose rows overlap
+    the frequencies are not integers and the fit is only a guide).  Returns
+    (theta, evaluations)."""
     Es = []
+    rows = gen_rows(gp, gens)
     for t in _FIT9:
         th = np.array(theta, dtype=np.float64)
         th[-1] = t
-        ops, ang = expand(gp, gens, th)
-        ctx.apply_ansatz(ops, ang, eps)
+        ctx.apply_generators(rows, th, eps)
         Es.append(ctx.energy()[0])
     X = np.stack([np.ones(9)] + [f(m * _FIT9) for m in range(1, 5) for f in (np.cos, np.sin)], axis=1)
     coef = np.linalg.solve(X, np.array(Es))
@@ -175,8 +196,7 @@ def run_adapt_spin(ctx, gp: GeneratorPool, eps=0.0, max_iter=20, grad_tol=1e-2, 
     gens, theta, hist = [], np.zeros(0), []
     for it in range(max_iter):
         t0 = time.perf_counter()
-        ops, ang = expand(gp, gens, theta)
-        n_det = ctx.apply_ansatz(ops, ang, eps)
+        n_det = ctx.apply_generators(gen_rows(gp, gens), theta, eps)
         E = ctx.energy()[0]
         g = generator_gradients(gp, ctx.pool_gradients())
         a = np.abs(g)

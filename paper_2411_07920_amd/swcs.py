@@ -66,6 +66,7 @@ SIGNATURES = {
     "swcs_set_pool": (ctypes.c_int, [_vp, _i32p, _i64]),
     "swcs_apply_ansatz": (ctypes.c_int, [_vp, _i32p, _dp, _i64, ctypes.c_double, _i64, _i64p]),
     "swcs_apply_gates": (ctypes.c_int, [_vp, _i32p, _dp, _i64, ctypes.c_double, _i64, _i64p]),
+    "swcs_apply_generators": (ctypes.c_int, [_vp, _i32p, _dp, _i64, ctypes.c_double, _i64, _i64p]),
     "swcs_set_state": (ctypes.c_int, [_vp, _u64p, _dp, _i64]),
     "swcs_get_state": (ctypes.c_int, [_vp, _u64p, _dp, _i64, _i64p]),
     "swcs_energy": (ctypes.c_int, [_vp, _dp, _dp, _dp]),
@@ -298,6 +299,19 @@ class Context:
         self._check(self._lib.swcs_apply_gates(self._h, _ptr(ops, ctypes.c_int32),
                                                _ptr(theta, ctypes.c_double), len(ops), float(eps),
                                                int(ncut), ctypes.byref(out)))
+        return int(out.value)
+
+    def apply_generators(self, gens, theta, eps: float = 0.0, ncut: int = 0) -> int:
+        """Chain of spin-complemented generators: int32 rows (k1, k2, s), k2 = -1
+        for a single pool row (include/swcs.h: swcs_apply_generators)."""
+        gens = np.ascontiguousarray(gens, dtype=np.int32).reshape(-1, 3)
+        theta = np.ascontiguousarray(theta, dtype=np.float64)
+        if len(gens) != len(theta) or theta.ndim != 1:
+            raise ValueError("gens must be [M, 3] and theta [M]")
+        out = ctypes.c_int64()
+        self._check(self._lib.swcs_apply_generators(self._h, _ptr(gens, ctypes.c_int32),
+                                                    _ptr(theta, ctypes.c_double), len(theta), float(eps),
+                                                    int(ncut), ctypes.byref(out)))
         return int(out.value)
 
     def set_state(self, keys, amps):

@@ -107,10 +107,10 @@ def spin_complemented_uccsd(ans: UccsdAnsatz, gp):
     """The UCCSD ansatz over spin-complemented generators (Sec. III; see
     ``spin.py``).  For a closed-shell reference the complement of an
     occupied -> virtual excitation is one as well, with the MP2 amplitude of
-    the same excitation read with flipped spins, so a commuting pair becomes
+    the same excitation read with flipped spins, so a complement pair becomes
     one generator with one parameter at the first member's position in the
-    MP2 order; the other rows stay single.  Returns (generators, theta) for
-    ``spin.expand`` / ``spin.TiedEnergy``."""
+    MP2 order; self-complementary rows stay single.  Returns (generators,
+    theta) for ``spin.gen_rows`` / ``spin.TiedEnergy``."""
     ops = np.asarray(ans.ops).tolist()
     pos = {k: i for i, k in enumerate(ops)}
     gen_of = {}

@@ -65,26 +65,26 @@ def test_complement_sign_matches_definition(setup):
         assert abs(lhs - rhs).max() == 0.0, (pool[k], pool[k2], s)
 
 
-def test_paired_parts_commute_and_split_ones_do_not(setup):
+def test_paired_parts_commute_exactly_when_disjoint(setup):
+    """Pairs on disjoint spin-orbitals commute; pairs marked overlapping do
+    not (so they need the one-gate exponential); keeping the overlapping ones
+    apart leaves only commuting pairs."""
     pool, a, ad, gp = setup
+    n_over = 0
     for j in range(len(gp)):
         if gp.second[j] < 0:
             continue
         A1 = _A(_T(pool[gp.first[j]], a, ad))
         A2 = _A(_T(pool[gp.second[j]], a, ad))
-        assert abs(A1 @ A2 - A2 @ A1).max() == 0.0
-    # rows kept apart because they overlap their complement
-    index = {tuple(int(x) for x in r): k for k, r in enumerate(pool)}
-    split = 0
-    for k in gp.first[gp.second < 0]:
-        row2, s = spin.complement_row(pool[k])
-        k2 = index[row2]
-        if k2 == k:
-            continue
-        A1, A2 = _A(_T(pool[k], a, ad)), _A(_T(pool[k2], a, ad))
-        if abs(A1 @ A2 - A2 @ A1).max() > 0.0:
-            split += 1
-    assert split > 0
+        comm = abs(A1 @ A2 - A2 @ A1).max()
+        if gp.overlap[j]:
+            n_over += 1
+            assert comm > 0.0
+        else:
+            assert comm == 0.0
+    assert n_over > 0
+    gp2 = spin.spin_complemented(pool, overlapping=False)
+    assert not gp2.overlap.any() and len(gp2) == len(gp) + n_over
 
 
 def test_product_formula_and_singlet_singles(setup):
@@ -98,7 +98,7 @@ def test_product_formula_and_singlet_singles(setup):
     I = sp.identity(1 << (2 * N), format="csr")
     S2 = (Sp.T @ Sp + Sz @ (Sz + I)).tocsr()
     theta = 0.37
-    for j in rng.choice(np.flatnonzero(gp.second >= 0), 12, replace=False):
+    for j in rng.choice(np.flatnonzero((gp.second >= 0) & ~gp.overlap), 12, replace=False):
         A1 = _A(_T(pool[gp.first[j]], a, ad)).toarray()
         A2 = _A(_T(pool[gp.second[j]], a, ad)).toarray()
         G = A1 + gp.sign[j] * A2
@@ -118,8 +118,13 @@ class OracleContext:
         self.pool, self.ref = pool, reference_key(ne)
 
     def apply_ansatz(self, ops, theta, eps=0.0, ncut=0):
-        self.ops, self.theta, self.eps = np.array(ops), np.array(theta), eps
+        self.ops, self.theta, self.eps, self.gens = np.array(ops), np.array(theta), eps, None
         self.st = oracle.Oracle.apply_ansatz(self.pool, self.ops, self.theta, eps, self.ref)
+        return len(self.st)
+
+    def apply_generators(self, gens, theta, eps=0.0, ncut=0):
+        self.gens, self.theta, self.eps = np.array(gens, dtype=np.int32), np.array(theta), eps
+        self.st = oracle.Oracle.apply_gen_ansatz(self.pool, self.gens, self.theta, eps, self.ref)
         return len(self.st)
 
     def energy(self):
@@ -129,6 +134,8 @@ class OracleContext:
         return self.orc.pool_gradients(self.st, self.pool, subset=subset)
 
     def param_gradients(self, M):
+        if self.gens is not None:
+            return self.orc.gen_param_gradients(self.pool, self.gens, self.theta, self.eps, self.ref)
         return self.orc.param_gradients(self.pool, self.ops, self.theta, self.eps, self.ref)
 
 
@@ -139,9 +146,9 @@ def test_generator_gradients_are_dense_commutators(setup):
     pool = enumerate_pool(n)
     gp = spin.spin_complemented(pool)
     ctx = OracleContext(n, ne, h, eri, pool)
-    gens = [int(x) for x in np.flatnonzero(gp.second >= 0)[:6]]
-    ops, ang = spin.expand(gp, gens, np.linspace(0.1, 0.6, len(gens)))
-    ctx.apply_ansatz(ops, ang)
+    gens = [int(x) for x in np.flatnonzero(gp.second >= 0)[:6]] + \
+        [int(x) for x in np.flatnonzero(gp.overlap)[:3]]
+    ctx.apply_generators(spin.gen_rows(gp, gens), np.linspace(0.1, 0.6, len(gens)))
     g = spin.generator_gradients(gp, ctx.pool_gradients())
     dense = DenseProblem(n, ne // 2, ne // 2, h, eri)
     keys, amps = ctx.st.export()

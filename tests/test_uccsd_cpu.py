@@ -176,8 +176,14 @@ def test_spin_complemented_uccsd(name):
     ans = uccsd.mp2_ordered_uccsd(ctx, pool, ref, n)
     gp = spin.spin_complemented(pool)
     gens, theta = uccsd.spin_complemented_uccsd(ans, gp)
-    ops, ang = spin.expand(gp, gens, theta)
-    assert sorted(ops.tolist()) == sorted(ans.ops.tolist())
+    rows = spin.gen_rows(gp, gens)
+    ops, ang = [], []
+    for (k1, k2, sg), t in zip(rows.tolist(), theta.tolist()):
+        ops.append(k1), ang.append(t)
+        if k2 >= 0:
+            ops.append(k2), ang.append(sg * t)
+    assert sorted(ops) == sorted(ans.ops.tolist())
     mp2 = dict(zip(ans.ops.tolist(), ans.theta.tolist()))
-    assert all(abs(a - mp2[k]) <= 1e-12 * max(1.0, abs(mp2[k])) for k, a in zip(ops.tolist(), ang.tolist()))
+    assert all(abs(a - mp2[k]) <= 1e-12 * max(1.0, abs(mp2[k])) for k, a in zip(ops, ang))
     assert len(gens) < len(ans.ops)
+    assert gp.overlap[gens].any()     # overlapping complement pairs are tied too
