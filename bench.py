@@ -231,6 +231,9 @@ def gpu_bench(args, wl):
     # Work counts of one step.
     n_det = phase_apply()
     n_in = ctx.gate_sizes(M)
+    stored, alive = ctx.state_counts()
+    phase_pool()
+    pool_table = ctx.pool_stats()
     seg = max(1, int(math.ceil(math.sqrt(M))))
     fwd_applies, adj_applies = applies_in_step(n_in, seg, int(n_in.max(initial=1)) <= 4096)
     applies = fwd_applies + adj_applies
@@ -253,7 +256,8 @@ def gpu_bench(args, wl):
                            "us_per_launch": 1e3 * total / launches}
     ctx.close()
     return dict(ms_step=ms_step, phase_ms=phase_ms, n_det=n_det, n_in=n_in, applies=applies,
-                fwd_applies=fwd_applies, adj_applies=adj_applies, kernels=kern, seg=seg)
+                fwd_applies=fwd_applies, adj_applies=adj_applies, kernels=kern, seg=seg,
+                stored=stored, pool_table=pool_table)
 
 
 def algorithmic_bytes(kname, wl, r):
@@ -751,8 +755,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {wl.c.n_so} spin-orbitals, {wl.c.n_elec} electrons, "
                                f"{M}-gate ansatz, eps={wl.c.eps:g}, pool {wl.K}",
-                   "n_det_final": r["n_det"], "applies_per_step": r["applies"],
-                   "input_sha256": wl.digest[:16]},
+                   "n_det_final": r["n_det"], "n_stored_final": r["stored"],
+                   "applies_per_step": r["applies"], "input_sha256": wl.digest[:16]},
+        "pool_table": r["pool_table"],
         "phases_ms": {k: round(v, 4) for k, v in r["phase_ms"].items()},
     }
     if kern:

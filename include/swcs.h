@@ -258,6 +258,19 @@ int swcs_param_gradients(swcs_ctx* ctx, double* dE_dtheta, double* E_out);
  * determinants entering each gate.  Returns SWCS_E_INVALID if M differs. */
 int swcs_gate_sizes(swcs_ctx* ctx, int64_t* n_in, int64_t M);
 
+/* Stored entries (alive or pruned; every gate scans them) and alive
+ * entries of the current state. */
+int swcs_state_counts(swcs_ctx* ctx, int64_t* stored, int64_t* alive);
+
+/* The last pool-gradient pass: *keys the key count its accumulation table
+ * was sized for (after a full-pool pass: the distinct external determinants
+ * it met), *table_slots the slots of one table, *batches the key-hash
+ * batches, *passes how many times the pass ran (a pass whose table filled is
+ * repeated), *screened 1 for a subset pass.  Any pointer may be NULL;
+ * SWCS_E_STATE before the first pass. */
+int swcs_pool_stats(swcs_ctx* ctx, double* keys, int64_t* table_slots, int32_t* batches,
+                    int32_t* passes, int32_t* screened);
+
 /* Spin-orbital occupations <n_P> = sum_D psi(D)^2 [P in D] / norm2 of the
  * current state, n_out[2n] (host). */
 int swcs_occupations(swcs_ctx* ctx, double* n_out);

@@ -812,21 +812,44 @@ k_pool_contract_det(const u64* __restrict__ keys, const double* __restrict__ amp
 }
 
 // Screened pool gradients need sigma only on Q = {X_k(D): k selected, D in
-// psi}.  Pass 1 counts (count_only) or inserts Q into the table; pass 2
+// psi}.  Pass 1 counts (count_only = s >= 1: the (D, k) pairs of every s-th
+// determinant, or tile of determinants) or inserts Q into the table; pass 2
 // (k_sigma_push_into) adds H_{X D'} psi(D') only for X already in the table,
-// evaluating the matrix element only on those hits.
+// evaluating the matrix element only on those hits.  With a presence filter
+// of Q (one bit per hash of each query key, set by pass 1 on the key's
+// first insert), pass 2 looks a connection up in the table only when its
+// bit is set: most connections are not in Q, and the filter is a small
+// fraction of the table.
+__device__ inline void qfilter_set(unsigned* qf, u64 qfmask, u64 key) {
+  const u64 b = filter_bit(key, qfmask);
+  atomicOr(&qf[b >> 5], 1u << (b & 31));
+}
+
+__device__ inline bool qfilter_maybe(const unsigned* __restrict__ qf, u64 qfmask, u64 key) {
+  return !qf || filter_maybe(qf, qfmask, key);
+}
+
+// Insert a query key; sets its filter bit on the first insert.
+__device__ inline void query_insert(AccSlot* tab, u64 tmask, u64 X, unsigned* qf, u64 qfmask,
+                                    unsigned* flags) {
+  const int r = acc_add(tab, tmask, X, 0.0);
+  if (!r) atomicOr(flags, kFlagOverflow);
+  else if (r == 2 && qf) qfilter_set(qf, qfmask, X);
+}
 __global__ void __launch_bounds__(kSigBlock)
 k_query_set(const u64* __restrict__ keys, const double* __restrict__ amps, ExcSpace E, int n_spatial,
             u64 n, const int* __restrict__ optab, int npairs,
             const unsigned char* __restrict__ selected, AccSlot* __restrict__ tab, u64 tmask,
-            int count_only, u64* __restrict__ counter, unsigned* __restrict__ flags, int nbatch, int batch) {
+            int count_only, u64* __restrict__ counter, unsigned* __restrict__ flags, int nbatch, int batch,
+            unsigned* __restrict__ qf, u64 qfmask) {
   __shared__ SigShared S;
   __shared__ ConnTables T;
   extern __shared__ __align__(16) unsigned char conn_dyn[];
   build_pair_table(S);
   if (threadIdx.x == 0) attach_conn_tables(T, conn_dyn, E);
   unsigned long long mine = 0;
-  for (u64 d = blockIdx.x; d < n; d += gridDim.x) {
+  const u64 dstep = count_only ? (u64)count_only : 1ULL;
+  for (u64 d = blockIdx.x * dstep; d < n; d += gridDim.x * dstep) {
     if (is_dead(amps[d])) continue;
     const u64 D = keys[d];
     __syncthreads();
@@ -844,7 +867,7 @@ k_query_set(const u64* __restrict__ keys, const double* __restrict__ amps, ExcSp
         return;
       }
       if (nbatch > 1 && batch_of(X, nbatch) != batch) return;
-      if (!acc_add(tab, tmask, X, 0.0)) atomicOr(flags, kFlagOverflow);
+      query_insert(tab, tmask, X, qf, qfmask, flags);
     });
   }
   if (count_only) {
@@ -863,9 +886,9 @@ __global__ void __launch_bounds__(256)
 k_query_ops(const u64* __restrict__ keys, const double* __restrict__ amps, u64 n,
             const OpDesc* __restrict__ ops, const int* __restrict__ subset, long long n_sub,
             AccSlot* __restrict__ tab, u64 tmask, int count_only, u64* __restrict__ counter,
-            unsigned* __restrict__ flags, int nbatch, int batch) {
+            unsigned* __restrict__ flags, int nbatch, int batch, unsigned* __restrict__ qf, u64 qfmask) {
   __shared__ u64 skey[kOpTile];
-  const u64 t0 = (u64)blockIdx.x * kOpTile;
+  const u64 t0 = (u64)blockIdx.x * kOpTile * (count_only ? (u64)count_only : 1ULL);
   const int tile = (int)((n - t0) < (u64)kOpTile ? (n - t0) : (u64)kOpTile);
   for (int t = threadIdx.x; t < tile; t += blockDim.x)
     skey[t] = is_dead(amps[t0 + t]) ? 0ULL : keys[t0 + t];
@@ -883,7 +906,7 @@ k_query_ops(const u64* __restrict__ keys, const double* __restrict__ amps, u64 n
       if (!act) continue;
       if (count_only) ++mine;
       else if (nbatch > 1 && batch_of(D ^ pm, nbatch) != batch) continue;
-      else if (!acc_add(tab, tmask, D ^ pm, 0.0)) atomicOr(flags, kFlagOverflow);
+      else query_insert(tab, tmask, D ^ pm, qf, qfmask, flags);
     }
   }
   if (count_only) {
@@ -945,7 +968,7 @@ __device__ inline double* acc_slot(AccSlot* tab, u64 mask, u64 key) {
 __global__ void __launch_bounds__(kSigBlock)
 k_sigma_push_into(const u64* __restrict__ keys, const double* __restrict__ amps, Ints I, ExcSpace E,
                   u64 n, const double* __restrict__ diag, AccSlot* __restrict__ tab, u64 tmask, int nbatch,
-                  int batch) {
+                  int batch, const unsigned* __restrict__ qf, u64 qfmask) {
   __shared__ SigShared S;
   __shared__ ConnTables T;
   extern __shared__ __align__(16) unsigned char conn_dyn[];
@@ -961,11 +984,12 @@ k_sigma_push_into(const u64* __restrict__ keys, const double* __restrict__ amps,
     build_conn_tables(S, E, T);
     __syncthreads();
     if (threadIdx.x == 0 && (nbatch == 1 || batch_of(D, nbatch) == batch)) {
-      double* v = acc_slot(tab, tmask, D);
+      double* v = qfilter_maybe(qf, qfmask, D) ? acc_slot(tab, tmask, D) : nullptr;
       if (v) unsafeAtomicAdd(v, diag[d] * psiD);
     }
     for_each_connection(T, D, [&](u64 X, int nh, int h0, int h1, int p0, int p1) {
       if (nbatch > 1 && batch_of(X, nbatch) != batch) return;
+      if (!qfilter_maybe(qf, qfmask, X)) return;
       double* v = acc_slot(tab, tmask, X);
       if (v) unsafeAtomicAdd(v, connection_element(I, D, nh, h0, h1, p0, p1) * psiD);
     });
@@ -1176,22 +1200,23 @@ hipError_t launch_pool_contract_det(const DeviceState& st, const ExcSpace& E, in
 hipError_t launch_query_set(const DeviceState& st, const ExcSpace& E, int n_spatial, u64 n,
                             const int* optab, int npairs, const unsigned char* selected,
                             AccSlot* tab, u64 tmask, int count_only, u64* counter, int grid,
-                            hipStream_t stream, int nbatch, int batch) {
+                            hipStream_t stream, int nbatch, int batch, unsigned* qf, u64 qfmask) {
   if (nbatch < 1 || batch < 0 || batch >= nbatch) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_query_set, dim3(grid), dim3(kSigBlock), conn_tables_bytes(E), stream, st.keys, st.amps, E,
                      n_spatial, n, optab, npairs, selected, tab, tmask, count_only, counter,
-                     &st.ctr->flags, nbatch, batch);
+                     &st.ctr->flags, nbatch, batch, qf, qfmask);
   return hipGetLastError();
 }
 
 hipError_t launch_query_ops(const DeviceState& st, u64 n, const OpDesc* ops, const int* subset,
                             long long n_sub, AccSlot* tab, u64 tmask, int count_only, u64* counter,
-                            hipStream_t stream, int nbatch, int batch) {
+                            hipStream_t stream, int nbatch, int batch, unsigned* qf, u64 qfmask) {
   if (nbatch < 1 || batch < 0 || batch >= nbatch) return hipErrorInvalidValue;
   if (n == 0 || n_sub == 0) return hipSuccess;
-  const dim3 grid((unsigned)((n + kOpTile - 1) / kOpTile), (unsigned)((n_sub + 255) / 256));
+  const u64 tiles = (n + kOpTile - 1) / kOpTile, stride = count_only > 0 ? (u64)count_only : 1ULL;
+  const dim3 grid((unsigned)((tiles + stride - 1) / stride), (unsigned)((n_sub + 255) / 256));
   hipLaunchKernelGGL(k_query_ops, grid, dim3(256), 0, stream, st.keys, st.amps, n, ops, subset,
-                     n_sub, tab, tmask, count_only, counter, &st.ctr->flags, nbatch, batch);
+                     n_sub, tab, tmask, count_only, counter, &st.ctr->flags, nbatch, batch, qf, qfmask);
   return hipGetLastError();
 }
 
@@ -1207,10 +1232,11 @@ hipError_t launch_contract_ops(const DeviceState& st, u64 n, const OpDesc* ops, 
 }
 
 hipError_t launch_sigma_push_into(const DeviceState& st, const Ints& I, const ExcSpace& E, u64 n,
-                                  AccSlot* tab, u64 tmask, int grid, hipStream_t stream, int nbatch, int batch) {
+                                  AccSlot* tab, u64 tmask, int grid, hipStream_t stream, int nbatch, int batch,
+                                  const unsigned* qf, u64 qfmask) {
   if (nbatch < 1 || batch < 0 || batch >= nbatch) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_sigma_push_into, dim3(grid), dim3(kSigBlock), conn_tables_bytes(E), stream, st.keys, st.amps, I,
-                     E, n, st.diag, tab, tmask, nbatch, batch);
+                     E, n, st.diag, tab, tmask, nbatch, batch, qf, qfmask);
   return hipGetLastError();
 }
 

@@ -168,11 +168,16 @@ struct swcs_ctx {
   size_t ev_used = 0;
 
   // scratch
-  DevBuf gacc, selected, ncut_state;
+  DevBuf gacc, selected, ncut_state, qfilt;
   DevBuf partial, partial2, sigma, mu, work, seg_states, acc_tab, gbuf, subset_buf, scalars,
       exp_keys, exp_amps, exp_tmp_k, exp_tmp_v, sort_scratch, ctr_r, occ, sel_scratch, mlp_partial, mse_partial, hp_key, hp_val, hp_tk, hp_tv, diag;
   int sigma_method = SWCS_SIGMA_AUTO;
   double ext_count = 0.0, ext_alive = 0.0;  // distinct external keys of the last full pool pass
+  // the last pool-gradient pass (swcs_pool_stats): keys the table was sized
+  // for (distinct external keys after a full pass), slots, batches, passes
+  double ps_keys = 0.0;
+  u64 ps_slots = 0;
+  int ps_batches = 0, ps_passes = 0, ps_screened = 0;
   // The state (and integrals) version, bumped by every call that may change
   // them; the diagonal elements and <psi|psi> on the device are reused while
   // they were computed for the current version.
@@ -184,7 +189,7 @@ struct swcs_ctx {
                      &partial, &partial2, &sigma, &mu, &work, &seg_states, &acc_tab, &gbuf,
                      &subset_buf, &scalars, &exp_keys, &exp_amps, &exp_tmp_k, &exp_tmp_v,
                      &sort_scratch, &ctr_r, &occ, &sel_scratch, &mlp_partial, &mse_partial,
-                     &hp_key, &hp_val, &hp_tk, &hp_tv, &diag};
+                     &hp_key, &hp_val, &hp_tk, &hp_tv, &diag, &qfilt};
     for (DevBuf* b : all) f(*b);
     for (auto& b : ckpt) f(b);
   }
@@ -318,7 +323,7 @@ size_t avail_bytes(swcs_ctx* c) {
 // when the state needs the memory, and allocated again on their next use.
 void release_scratch(swcs_ctx* c) {
   DevBuf* bufs[] = {&c->acc_tab, &c->hp_key, &c->hp_val, &c->hp_tk, &c->hp_tv, &c->sort_scratch,
-                    &c->exp_keys, &c->exp_amps, &c->exp_tmp_k, &c->exp_tmp_v};
+                    &c->exp_keys, &c->exp_amps, &c->exp_tmp_k, &c->exp_tmp_v, &c->qfilt};
   for (DevBuf* b : bufs) b->release();
 }
 
@@ -1382,21 +1387,27 @@ static int screened_gradients(swcs_ctx* c, u64 n, u64 alive, const int* d_subset
   const double bound = std::min<double>((double)c->sector,
                                         (double)alive * (double)(op_major ? n_subset : c->exc.total));
   u64 nq;
-  bool counted = false;
+  bool counted = false, sampled = false;
   if (c->table_budget == 0 && 2.0 * bound * sizeof(AccSlot) <= kQueryBoundBytes) {
     nq = (u64)bound;
   } else {
+    // count the (determinant, operator) pairs, on every 16th determinant
+    // (or tile) of a large state: the scaled sample sizes the table, and a
+    // pass whose table fills is repeated with twice the estimate
     counted = true;
+    const int stride = n >= 16 * 4096 ? 16 : 1;
+    sampled = stride > 1;
     u64* qcount = c->scalars.as<u64>() + 16;
     HIP_TRY(c, launch_fill_u32(qcount, 0u, 2, c->stream), "zero counter");
     if (op_major)
-      HIP_TRY(c, launch_query_ops(c->st, n, c->ops.as<OpDesc>(), d_subset, n_subset, nullptr, 0, 1,
+      HIP_TRY(c, launch_query_ops(c->st, n, c->ops.as<OpDesc>(), d_subset, n_subset, nullptr, 0, stride,
                                   qcount, c->stream), "count");
     else
       HIP_TRY(c, launch_query_set(c->st, c->exc, c->n, n, c->opmap.as<int>(), c->npairs, d_sel,
-                                  nullptr, 0, 1, qcount, sigma_grid(c, n), c->stream), "count");
+                                  nullptr, 0, stride, qcount, sigma_grid(c, n), c->stream), "count");
     HIP_TRY(c, hipMemcpyAsync(&nq, qcount, 8, hipMemcpyDeviceToHost, c->stream), "copy");
     HIP_TRY(c, hipStreamSynchronize(c->stream), "sync");
+    if (sampled) nq = (u64)(1.25 * (double)nq * stride) + 4096;
   }
   // The query keys number at most q; a table for all of them that would
   // not fit in 40% of the free device memory is split by key hash into
@@ -1406,7 +1417,7 @@ static int screened_gradients(swcs_ctx* c, u64 n, u64 alive, const int* d_subset
   // (scaled by the alive count) caps the estimate, and a pass that
   // overflows is repeated with twice the estimate.
   double q = (double)std::min<u64>(nq, c->sector);
-  bool estimated = false;
+  bool estimated = sampled;
   if (counted && c->ext_count > 0.0 && c->ext_alive > 0.0) {
     const double est = 1.5 * c->ext_count * std::max(1.0, (double)alive / c->ext_alive);
     if (est < q) {
@@ -1426,25 +1437,35 @@ static int screened_gradients(swcs_ctx* c, u64 n, u64 alive, const int* d_subset
   };
   int nbatch = batches();
   bool checked = false;
+  int passes = 0;
   for (int attempt = 0;;) {
     const u64 qslots = slots_for(nbatch);
     HIP_TRY(c, c->acc_tab.ensure(qslots * sizeof(AccSlot)), "alloc sigma table");
+    // presence filter of the batch's query keys: 8 bits per table slot (1/16
+    // of the table's bytes), at least 4,096 bits and at most 2^30 (128 MB,
+    // so that it stays in the last-level cache)
+    const u64 qbits = std::min<u64>((u64)1 << 30, next_pow2(std::max<u64>(4096, 8 * qslots)));
+    HIP_TRY(c, c->qfilt.ensure(qbits / 8), "alloc query filter");
+    unsigned* qf = c->qfilt.as<unsigned>();
+    ++passes;
     if (op_major)
       HIP_TRY(c, launch_fill_u32(d_out, 0u, (u64)n_subset * 2, c->stream), "zero g");
     else
       HIP_TRY(c, launch_fill_u32(c->gacc.p, 0u, (u64)c->K_pool * 2, c->stream), "zero g");
     for (int b = 0; b < nbatch; ++b) {
       HIP_TRY(c, launch_fill_u32(c->acc_tab.p, 0u, qslots * (sizeof(AccSlot) / 4), c->stream), "clear table");
+      HIP_TRY(c, launch_fill_u32(qf, 0u, qbits / 32, c->stream), "clear filter");
       if (op_major)
         HIP_TRY(c, launch_query_ops(c->st, n, c->ops.as<OpDesc>(), d_subset, n_subset,
-                                    c->acc_tab.as<AccSlot>(), qslots - 1, 0, nullptr, c->stream, nbatch, b),
-                "query set");
+                                    c->acc_tab.as<AccSlot>(), qslots - 1, 0, nullptr, c->stream, nbatch, b,
+                                    qf, qbits - 1), "query set");
       else
         HIP_TRY(c, launch_query_set(c->st, c->exc, c->n, n, c->opmap.as<int>(), c->npairs, d_sel,
                                     c->acc_tab.as<AccSlot>(), qslots - 1, 0, nullptr, sigma_grid(c, n),
-                                    c->stream, nbatch, b), "query set");
+                                    c->stream, nbatch, b, qf, qbits - 1), "query set");
       TIMED(c, SWCS_K_SIGMA_PUSH_INTO, launch_sigma_push_into(c->st, ints_view(c), c->exc, n, c->acc_tab.as<AccSlot>(),
-                                                              qslots - 1, sigma_grid(c, n), c->stream, nbatch, b),
+                                                              qslots - 1, sigma_grid(c, n), c->stream, nbatch, b,
+                                                              qf, qbits - 1),
             "sigma push");
       if (op_major)
         TIMED(c, SWCS_K_CONTRACT_OPS, launch_contract_ops(c->st, n, c->ops.as<OpDesc>(), d_subset, n_subset,
@@ -1472,6 +1493,11 @@ static int screened_gradients(swcs_ctx* c, u64 n, u64 alive, const int* d_subset
     q *= 2.0;
     nbatch = batches();
   }
+  c->ps_keys = q;
+  c->ps_slots = slots_for(nbatch);
+  c->ps_batches = nbatch;
+  c->ps_passes = passes;
+  c->ps_screened = 1;
   if (op_major)
     HIP_TRY(c, launch_gather_scaled(d_out, nullptr, n_subset, norm2, d_out, c->stream), "scale");
   else
@@ -1622,6 +1648,11 @@ int swcs_pool_gradients(swcs_ctx* c, const int32_t* subset, int64_t n_subset, do
     if (!(h2.flags & kFlagOverflow)) {
       c->ext_count = distinct;
       c->ext_alive = (double)h.alive;
+      c->ps_keys = distinct;
+      c->ps_slots = slots;
+      c->ps_batches = nbatch;
+      c->ps_passes = attempt + 1;
+      c->ps_screened = 0;
       return SWCS_OK;
     }
     h2.flags &= ~kFlagOverflow;
@@ -1742,6 +1773,30 @@ int swcs_param_gradients(swcs_ctx* c, double* dE, double* E_out) {
   for (int64_t i = 0; i < M_par; ++i) dE[i] = 0.0;
   for (int64_t g = 0; g < M; ++g) dE[c->a_owner[(size_t)g]] += c->a_factor[(size_t)g] * d_unit[(size_t)g];
   if (E_out) *E_out = nn_host[0] / nn_host[1];
+  return SWCS_OK;
+}
+
+int swcs_state_counts(swcs_ctx* c, int64_t* stored, int64_t* alive) {
+  if (!c) return SWCS_E_INVALID;
+  if (!c->have_state) return fail(c, SWCS_E_STATE, "no current state");
+  HIP_TRY(c, hipSetDevice(c->device), "hipSetDevice");
+  hipError_t e;
+  const Counters h = get_counters(c, &e);
+  if (e != hipSuccess) return hip_fail(c, e, "read counters");
+  if (stored) *stored = (int64_t)h.n;
+  if (alive) *alive = (int64_t)h.alive;
+  return SWCS_OK;
+}
+
+int swcs_pool_stats(swcs_ctx* c, double* keys, int64_t* table_slots, int32_t* batches, int32_t* passes,
+                    int32_t* screened) {
+  if (!c) return SWCS_E_INVALID;
+  if (!c->ps_passes) return fail(c, SWCS_E_STATE, "no pool-gradient pass yet");
+  if (keys) *keys = c->ps_keys;
+  if (table_slots) *table_slots = (int64_t)c->ps_slots;
+  if (batches) *batches = c->ps_batches;
+  if (passes) *passes = c->ps_passes;
+  if (screened) *screened = c->ps_screened;
   return SWCS_OK;
 }
 

@@ -375,15 +375,18 @@ hipError_t launch_pool_contract_det(const DeviceState& st, const ExcSpace& E, in
 hipError_t launch_query_set(const DeviceState& st, const ExcSpace& E, int n_spatial, u64 n,
                             const int* optab, int npairs, const unsigned char* selected,
                             AccSlot* tab, u64 tmask, int count_only, u64* counter, int grid,
-                            hipStream_t stream, int nbatch = 1, int batch = 0);
+                            hipStream_t stream, int nbatch = 1, int batch = 0, unsigned* qf = nullptr,
+                            u64 qfmask = 0);
 hipError_t launch_query_ops(const DeviceState& st, u64 n, const OpDesc* ops, const int* subset,
                             long long n_sub, AccSlot* tab, u64 tmask, int count_only, u64* counter,
-                            hipStream_t stream, int nbatch = 1, int batch = 0);
+                            hipStream_t stream, int nbatch = 1, int batch = 0, unsigned* qf = nullptr,
+                            u64 qfmask = 0);
 hipError_t launch_contract_ops(const DeviceState& st, u64 n, const OpDesc* ops, const int* subset,
                                long long n_sub, const AccSlot* tab, u64 tmask, double* gslot,
                                hipStream_t stream, int nbatch = 1, int batch = 0);
 hipError_t launch_sigma_push_into(const DeviceState& st, const Ints& I, const ExcSpace& E, u64 n,
-                                  AccSlot* tab, u64 tmask, int grid, hipStream_t stream, int nbatch = 1, int batch = 0);
+                                  AccSlot* tab, u64 tmask, int grid, hipStream_t stream, int nbatch = 1, int batch = 0,
+                                  const unsigned* qf = nullptr, u64 qfmask = 0);
 hipError_t launch_gather_scaled(const double* gacc, const int* subset, long long count,
                                 const double* norm2, double* out, hipStream_t stream);
 hipError_t launch_mark_selected(const int* subset, long long count, unsigned char* selected,

@@ -78,6 +78,9 @@ SIGNATURES = {
     "swcs_add_feature": (ctypes.c_int, [_vp, _vp, _vp, _i64, ctypes.c_int, ctypes.c_int, ctypes.c_float]),
     "swcs_param_gradients": (ctypes.c_int, [_vp, _dp, _dp]),
     "swcs_gate_sizes": (ctypes.c_int, [_vp, _i64p, _i64]),
+    "swcs_state_counts": (ctypes.c_int, [_vp, _i64p, _i64p]),
+    "swcs_pool_stats": (ctypes.c_int, [_vp, _dp, _i64p, ctypes.POINTER(ctypes.c_int32),
+                                       ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
     "swcs_occupations": (ctypes.c_int, [_vp, _dp]),
     "swcs_fock_diagonal": (ctypes.c_int, [_vp, _dp]),
     "swcs_timer_start": (ctypes.c_int, [_vp, ctypes.c_int]),
@@ -386,6 +389,21 @@ class Context:
         out = np.zeros(max(M, 1), dtype=np.int64)
         self._check(self._lib.swcs_gate_sizes(self._h, _ptr(out, ctypes.c_int64), M))
         return out[:M]
+
+    def state_counts(self):
+        """(stored entries, alive entries) of the current state."""
+        st, al = ctypes.c_int64(), ctypes.c_int64()
+        self._check(self._lib.swcs_state_counts(self._h, ctypes.byref(st), ctypes.byref(al)))
+        return int(st.value), int(al.value)
+
+    def pool_stats(self):
+        """Sizing of the last pool-gradient pass (include/swcs.h: swcs_pool_stats)."""
+        k, sl = ctypes.c_double(), ctypes.c_int64()
+        b, p, sc = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        self._check(self._lib.swcs_pool_stats(self._h, ctypes.byref(k), ctypes.byref(sl), ctypes.byref(b),
+                                              ctypes.byref(p), ctypes.byref(sc)))
+        return {"keys": k.value, "table_slots": int(sl.value), "batches": int(b.value),
+                "passes": int(p.value), "screened": bool(sc.value)}
 
     def occupations(self):
         out = np.zeros(2 * self.n)

@@ -868,3 +868,32 @@ def test_ncut_ties_at_zero(swcs, c1):
     case = Case(c1.n, c1.ne, c1.h, c1.eri, c1.pool, c1.ops, th, 0.0, "c1-zeros")
     for ncut in (5, 20, 40):
         _ncut_case(swcs, case, ncut)
+
+
+def test_screened_sampled_count_and_filter_large_state(swcs, c2):
+    """A 150,000-determinant random state of the 28-spin-orbital sector: the
+    screened passes size their table from a 1-in-16 sample of the query pairs
+    and skip table probes through the query-key filter.  Both screened paths
+    (operator-major, 1,000 operators; determinant-major, 6,000) equal the
+    full pool at the subset (the full-pool path is checked against the oracle
+    on the smaller states), and the pool statistics record the passes."""
+    import itertools
+    rng = np.random.default_rng(31)
+    sets = list(itertools.combinations(range(c2.n), c2.na))
+    ia = rng.choice(len(sets), 160000)
+    ib = rng.choice(len(sets), 160000)
+    keys = _spin_keys([(sets[i], sets[j]) for i, j in zip(ia, ib)])[:150000]
+    ctx = make_ctx(swcs, c2)
+    ctx.set_state(keys, rng.standard_normal(len(keys)) * 1e-2)
+    _say(f"[parity] sampled screened passes: {len(keys)} determinants")
+    g_full = ctx.pool_gradients()
+    st_full = ctx.pool_stats()
+    assert not st_full["screened"] and st_full["keys"] > len(keys)
+    for size in (1000, 6000):
+        subset = np.sort(rng.choice(len(c2.pool), size, replace=False)).astype(np.int32)
+        g = ctx.pool_gradients(subset)
+        st = ctx.pool_stats()
+        assert st["screened"] and st["passes"] >= 1
+        assert np.abs(g - g_full[subset]).max() < 1e-12 * max(1.0, np.abs(g_full).max())
+    assert ctx.state_counts() == (len(keys), len(keys))
+    ctx.close()
