@@ -65,6 +65,9 @@ def parse():
     ap.add_argument("--large-state", type=int, default=16_000_000,
                     help="determinants of the synthetic state for the HBM-path gate and sigma "
                          "measurement added to the step line (0 = skip)")
+    ap.add_argument("--huge-state", type=int, default=100_000_000,
+                    help="determinants of a second synthetic state for the gate alone, added to the "
+                         "step line (0 = skip)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy a 1 GiB device buffer five times (reference kernel for the "
                          "FETCH_SIZE / WRITE_SIZE counters)")
@@ -428,7 +431,7 @@ def large_state_bench(N, sigma=True):
     when N <= 2,000,000).  Gate bytes per gate: 8 B per input entry (the key
     test every entry needs), 16 B per entry the operator acts on (amplitude
     read and written) and 16 B per new entry (key and amplitude); the active
-    count of each gate is taken from the state exported before it.  At 16M
+    count of each gate is counted by the gate kernel.  At 16M
     determinants the counter-measured HBM traffic of a gate and of one
     sigma_P call (profiles/pmc_traffic.txt) is divided by the measured times
     as well."""
@@ -473,28 +476,14 @@ def large_state_bench(N, sigma=True):
     doubles = np.flatnonzero(wl.pool[:, 2] >= 0)
     ops = rng.choice(doubles, 8).astype(np.int32)
     theta = rng.uniform(-0.3, 0.3, len(ops))
-    # One gate per call, the state exported before each to count the entries
-    # the operator acts on.  A gate that would overflow the capacity returns
-    # at once and is launched again after the host grows the state, so time
-    # is summed per gate.
-    n_in, n_act, ms = [], [], 0.0
-    n_out = None
-    launches = 0
-    for g in range(len(ops)):
-        k, _ = ctx.get_state()
-        P, Q, R, S = (int(x) for x in wl.pool[ops[g]])
-        cre = np.uint64((1 << P) | (1 << Q))
-        ann = np.uint64((1 << R) | (1 << S))
-        acts = (((k & ann) == ann) & ((k & cre) == 0)) | (((k & cre) == cre) & ((k & ann) == 0))
-        n_in.append(float(len(k)))
-        n_act.append(float(np.count_nonzero(acts)))
-        ctx.timer_start("gate")
-        n_out = ctx.apply_gates(ops[g:g + 1], theta[g:g + 1], 0.0)
-        nl, t = ctx.timer_stop()
-        launches += nl
-        ms += t
-    n_in = np.array(n_in)
-    n_act = np.array(n_act)
+    # The gates' active counts come from the gate kernels themselves.  A gate
+    # that would overflow the capacity returns at once and is launched again
+    # after the host grows the state, so time is summed per gate.
+    ctx.timer_start("gate")
+    n_out = ctx.apply_gates(ops, theta, 0.0)
+    launches, ms = ctx.timer_stop()
+    n_in = ctx.gate_sizes(len(ops)).astype(np.float64)
+    n_act = ctx.gate_active(len(ops)).astype(np.float64)
     after = np.append(n_in[1:], n_out)
     n_new = np.maximum(after - n_in, 0.0)
     nbytes = float((8.0 * n_in + 16.0 * n_act + 16.0 * n_new).sum())
@@ -507,8 +496,8 @@ def large_state_bench(N, sigma=True):
                    "algorithmic_bytes_per_gate": nbytes / len(ops),
                    "achieved_GBps": gbps, "frac_hbm": gbps / HBM_PEAK_GBS,
                    "n_det_in": int(n_in[0]), "n_det_out": int(n_out)}
-    if N == 16_000_000:
-        tb = measured_traffic("gate", "synthetic16M")
+    if N % 1_000_000 == 0:
+        tb = measured_traffic("gate", f"synthetic{N // 1_000_000}M")
         out["gate"]["traffic_bytes_per_launch"] = tb
         if tb is not None:
             gbps = tb / (us * 1e-6) / 1e9
@@ -788,6 +777,9 @@ def main():
     if args.large_state and not args.no_extras:
         progress("large state")
         line["large_state"] = large_state_bench(args.large_state)
+    if args.huge_state and not args.no_extras:
+        progress("huge state")
+        line["huge_state_gate"] = large_state_bench(args.huge_state, sigma=False)
     print(json.dumps(line))
 
 

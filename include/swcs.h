@@ -258,6 +258,12 @@ int swcs_param_gradients(swcs_ctx* ctx, double* dE_dtheta, double* E_out);
  * determinants entering each gate.  Returns SWCS_E_INVALID if M differs. */
 int swcs_gate_sizes(swcs_ctx* ctx, int64_t* n_in, int64_t M);
 
+/* Per-gate active counts of the last apply call: n_act[M] receives the number
+ * of stored entries the gate's operator (or its adjoint) acts on, counted by
+ * the multi-block gate kernels (0 for gates run in the single-workgroup chain
+ * of small states).  Returns SWCS_E_INVALID if M differs. */
+int swcs_gate_active(swcs_ctx* ctx, int64_t* n_act, int64_t M);
+
 /* Stored entries (alive or pruned; every gate scans them) and alive
  * entries of the current state. */
 int swcs_state_counts(swcs_ctx* ctx, int64_t* stored, int64_t* alive);

@@ -33,6 +33,7 @@ struct GateOut {
   u64 iD, iX;
   double a_old, b_old;
   int s;
+  bool acts;  // T or T^dagger acts on this thread's entry (the gate's active count)
 };
 
 constexpr u64 kNoEntry = ~0ULL;
@@ -60,10 +61,11 @@ struct StarRec {
 template <class Store>
 __device__ inline GateOut gate_entry(Store& S, u64 i, const OpDesc& op, double c, double sn,
                                      double eps) {
-  GateOut o{false, 0ULL, 0.0, 0, false, kNoEntry, kNoEntry, 0.0, 0.0, 0};
+  GateOut o{false, 0ULL, 0.0, 0, false, kNoEntry, kNoEntry, 0.0, 0.0, 0, false};
   const u64 D = S.key(i);
   const bool isT = ((D & op.ann) == op.ann) && ((D & op.cre) == 0);
   const bool isTd = ((D & op.cre) == op.cre) && ((D & op.ann) == 0);
+  o.acts = isT || isTd;
   const u64 pair_mask = op.ann | op.cre;
   if (isT) {
     const u64 X = D ^ pair_mask;
@@ -338,7 +340,7 @@ __device__ inline void gate_entries_staged(const GlobalStore& S, u64 n, u64 i0, 
   for (int j = 0; j < N; ++j) {
     const u64 i = i0 + (u64)j * stride;
     GateOut& r = o[j];
-    r = GateOut{false, 0ULL, 0.0, 0, false, kNoEntry, kNoEntry, 0.0, 0.0, 0};
+    r = GateOut{false, 0ULL, 0.0, 0, false, kNoEntry, kNoEntry, 0.0, 0.0, 0, kind[j] != 0};
     if (kind[j] == 1) {
       const bool aliveD = !is_dead(araw[j]), aliveX = !is_dead(braw[j]);
       if (aliveD || aliveX) {

@@ -181,7 +181,7 @@ constexpr int kGenThreads = 256;
 __global__ void __launch_bounds__(kGenThreads)
 k_gen_gate(u64* __restrict__ keys, double* __restrict__ amps, HashSlot* __restrict__ hash, u64 hmask,
            u64 cap, Counters* __restrict__ ctr, GenGate g, double eps, u64* __restrict__ gate_n_in,
-           int check_cap, unsigned gate_index, u64 max_keys) {
+           int check_cap, unsigned gate_index, u64 max_keys, u64* __restrict__ gate_n_act) {
   __shared__ int s_run;
   __shared__ u64 s_n_in;
   __shared__ long long s_wsum[kGenThreads / 64];
@@ -211,13 +211,18 @@ k_gen_gate(u64* __restrict__ keys, double* __restrict__ amps, HashSlot* __restri
   const u64 n_in = s_n_in;
   GlobalStore S{keys, amps, hash, hmask};
   long long dalive = 0;
+  unsigned nact = 0;
   const u64 stride = (u64)gridDim.x * kGenThreads;
   for (u64 base = (u64)blockIdx.x * kGenThreads; base < n_in; base += stride) {
     const u64 i = base + threadIdx.x;
     GenOut o;
     o.napp = 0;
     o.dalive = 0;
-    if (i < n_in) o = gen_entry(S, i, g, eps);
+    if (i < n_in) {
+      const u64 D = keys[i];
+      nact += (op_acts(g.op1, D) || op_acts(g.op2, D)) ? 1u : 0u;
+      o = gen_entry(S, i, g, eps);
+    }
     dalive += o.dalive;
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
@@ -235,12 +240,24 @@ k_gen_gate(u64* __restrict__ keys, double* __restrict__ amps, HashSlot* __restri
       }
     }
   }
-  for (int off = 32; off > 0; off >>= 1) dalive += __shfl_xor(dalive, off);
-  if (__lane_id() == 0) s_wsum[threadIdx.x / 64] = dalive;
+  for (int off = 32; off > 0; off >>= 1) {
+    dalive += __shfl_xor(dalive, off);
+    nact += __shfl_xor(nact, off);
+  }
+  __shared__ unsigned s_nact[kGenThreads / 64];
+  if (__lane_id() == 0) {
+    s_wsum[threadIdx.x / 64] = dalive;
+    s_nact[threadIdx.x / 64] = nact;
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
     long long d = 0;
-    for (int w = 0; w < kGenThreads / 64; ++w) d += s_wsum[w];
+    u64 na = 0;
+    for (int w = 0; w < kGenThreads / 64; ++w) {
+      d += s_wsum[w];
+      na += s_nact[w];
+    }
+    if (gate_n_act && na) atomicAdd((unsigned long long*)gate_n_act, (unsigned long long)na);
     if (d != 0) atomicAdd((unsigned long long*)&ctr->dalive, (unsigned long long)d);
     __threadfence();
     const unsigned tk = atomicAdd(&ctr->ticket, 1u);
@@ -330,9 +347,9 @@ k_adjoint_star(const StarRec* __restrict__ slog, const u64* __restrict__ scount,
 }
 
 hipError_t launch_gen_gate(const DeviceState& st, const GenGate& g, double eps, u64* gate_n_in,
-                           unsigned gate_index, u64 max_keys, int grid, hipStream_t stream) {
+                           unsigned gate_index, u64 max_keys, int grid, hipStream_t stream, u64* gate_n_act) {
   hipLaunchKernelGGL(k_gen_gate, dim3(grid), dim3(kGenThreads), 0, stream, st.keys, st.amps, st.hash,
-                     st.hmask, st.cap, st.ctr, g, eps, gate_n_in, 1, gate_index, max_keys);
+                     st.hmask, st.cap, st.ctr, g, eps, gate_n_in, 1, gate_index, max_keys, gate_n_act);
   return hipGetLastError();
 }
 

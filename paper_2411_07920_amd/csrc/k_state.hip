@@ -24,7 +24,8 @@ namespace swcs {
 __global__ void __launch_bounds__(kGateThreads, 8)
 k_gate(u64* __restrict__ keys, double* __restrict__ amps, HashSlot* __restrict__ hash, u64 hmask,
        u64 cap, Counters* __restrict__ ctr, OpDesc op, double c, double sn, double eps,
-       u64* __restrict__ gate_n_in, int check_cap, unsigned gate_index, u64 max_keys) {
+       u64* __restrict__ gate_n_in, int check_cap, unsigned gate_index, u64 max_keys,
+       u64* __restrict__ gate_n_act) {
   __shared__ u64 s_key[kGateTile];
   __shared__ double s_val[kGateTile];
   __shared__ unsigned s_cnt;
@@ -63,6 +64,7 @@ k_gate(u64* __restrict__ keys, double* __restrict__ amps, HashSlot* __restrict__
   if (!s_run) return;
   const u64 n_in = s_n_in;
   long long dalive = 0;
+  unsigned nact = 0;
   const int lane = __lane_id();
   const u64 below = (1ULL << lane) - 1ULL;
   const u64 ntiles = (n_in + kGateTile - 1) / kGateTile;
@@ -74,6 +76,7 @@ k_gate(u64* __restrict__ keys, double* __restrict__ amps, HashSlot* __restrict__
 #pragma unroll
     for (int j = 0; j < kGateItems; ++j) {
       dalive += o[j].dalive;
+      nact += o[j].acts ? 1u : 0u;
       const u64 m = __ballot(o[j].append);
       if (m) {
         const int leader = __ffsll((long long)m) - 1;
@@ -108,13 +111,26 @@ k_gate(u64* __restrict__ keys, double* __restrict__ amps, HashSlot* __restrict__
       __syncthreads();
     }
   }
-  // Block reduction of the alive-count change, then last-block finalization.
-  for (int off = 32; off > 0; off >>= 1) dalive += __shfl_xor(dalive, off);
-  if (lane == 0) s_wsum[threadIdx.x / 64] = dalive;
+  // Block reduction of the alive-count change (and of the active count),
+  // then last-block finalization.
+  for (int off = 32; off > 0; off >>= 1) {
+    dalive += __shfl_xor(dalive, off);
+    nact += __shfl_xor(nact, off);
+  }
+  __shared__ unsigned s_nact[kGateThreads / 64];
+  if (lane == 0) {
+    s_wsum[threadIdx.x / 64] = dalive;
+    s_nact[threadIdx.x / 64] = nact;
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
     long long d = 0;
-    for (int w = 0; w < kGateThreads / 64; ++w) d += s_wsum[w];
+    u64 na = 0;
+    for (int w = 0; w < kGateThreads / 64; ++w) {
+      d += s_wsum[w];
+      na += s_nact[w];
+    }
+    if (gate_n_act && na) atomicAdd((unsigned long long*)gate_n_act, (unsigned long long)na);
     if (d != 0) atomicAdd((unsigned long long*)&ctr->dalive, (unsigned long long)d);
     __threadfence();
     const unsigned tk = atomicAdd(&ctr->ticket, 1u);
@@ -442,9 +458,9 @@ hipError_t launch_hash_build_dev(const DeviceState& st, int grid, hipStream_t st
 
 hipError_t launch_gate(const DeviceState& st, const OpDesc& op, double c, double sn, double eps,
                        u64* gate_n_in, int check_cap, unsigned gate_index, u64 max_keys, int grid,
-                       hipStream_t stream) {
+                       hipStream_t stream, u64* gate_n_act) {
   hipLaunchKernelGGL(k_gate, dim3(grid), dim3(kGateThreads), 0, stream, st.keys, st.amps, st.hash, st.hmask,
-                     st.cap, st.ctr, op, c, sn, eps, gate_n_in, check_cap, gate_index, max_keys);
+                     st.cap, st.ctr, op, c, sn, eps, gate_n_in, check_cap, gate_index, max_keys, gate_n_act);
   return hipGetLastError();
 }
 

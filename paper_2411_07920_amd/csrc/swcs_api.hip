@@ -160,6 +160,7 @@ struct swcs_ctx {
   std::vector<GateDesc> gate_tab_host;  // source of the last gate-table upload
   DevBuf gate_tab;    // GateDesc per gate of the last apply call
   DevBuf gate_n_in;   // u64 per gate of the last apply call
+  DevBuf gate_n_act;  // u64 per gate: stored entries the gate's operator acts on
   int64_t last_M = 0;
 
   // kernel timer: HIP events around every launch of one kernel
@@ -185,7 +186,7 @@ struct swcs_ctx {
 
   template <class F> void for_each_buf(F&& f) {
     DevBuf* all[] = {&h, &eri, &J, &K, &fock, &ops, &opmap, &gacc, &selected, &ncut_state, &filt, &keys, &amps, &hash, &ctr, &ckpt_n, &ckpt_ptrs,
-                     &gate_tab, &gate_n_in,
+                     &gate_tab, &gate_n_in, &gate_n_act,
                      &partial, &partial2, &sigma, &mu, &work, &seg_states, &acc_tab, &gbuf,
                      &subset_buf, &scalars, &exp_keys, &exp_amps, &exp_tmp_k, &exp_tmp_v,
                      &sort_scratch, &ctr_r, &occ, &sel_scratch, &mlp_partial, &mse_partial,
@@ -529,10 +530,12 @@ int run_chain(swcs_ctx* c, const int32_t* op_idx, const double* cs, const double
       const OpDesc& op = c->ops_host[op_idx[g]];
       if (kind && kind[g])
         HIP_TRY(c, launch_gen_gate(c->st, gen[g], eps, c->gate_n_in.as<u64>() + g, (unsigned)g, c->sector,
-                                   grid_blocks(c, c->st.cap / 2, 256), c->stream), "generator gate");
+                                   grid_blocks(c, c->st.cap / 2, 256), c->stream, c->gate_n_act.as<u64>() + g),
+                "generator gate");
       else
         TIMED(c, SWCS_K_GATE, launch_gate(c->st, op, cs[g], sn[g], eps, c->gate_n_in.as<u64>() + g, 1,
-                               (unsigned)g, c->sector, gate_grid(c, c->st.cap / 2, kGateTile), c->stream),
+                               (unsigned)g, c->sector, gate_grid(c, c->st.cap / 2, kGateTile), c->stream,
+                               c->gate_n_act.as<u64>() + g),
                 "gate");
       // The gates only test the entries they touch; entries of a starting
       // state that were never tested against eps are pruned once, after the
@@ -903,6 +906,8 @@ static int apply_common(swcs_ctx* c, ChainSpec& sp, double eps, int64_t ncut, in
   HIP_TRY(c, hipSetDevice(c->device), "hipSetDevice");
   ++c->state_version;
   HIP_TRY(c, c->gate_n_in.ensure(std::max<int64_t>(1, M) * sizeof(u64)), "alloc stats");
+  HIP_TRY(c, c->gate_n_act.ensure(std::max<int64_t>(1, M) * sizeof(u64)), "alloc stats");
+  HIP_TRY(c, launch_fill_u32(c->gate_n_act.p, 0u, (u64)std::max<int64_t>(1, M) * 2, c->stream), "zero stats");
   c->ansatz_valid = false;
   if (from_reference) {
     int r = state_reset_to_reference(c);
@@ -1773,6 +1778,17 @@ int swcs_param_gradients(swcs_ctx* c, double* dE, double* E_out) {
   for (int64_t i = 0; i < M_par; ++i) dE[i] = 0.0;
   for (int64_t g = 0; g < M; ++g) dE[c->a_owner[(size_t)g]] += c->a_factor[(size_t)g] * d_unit[(size_t)g];
   if (E_out) *E_out = nn_host[0] / nn_host[1];
+  return SWCS_OK;
+}
+
+int swcs_gate_active(swcs_ctx* c, int64_t* n_act, int64_t M) {
+  if (!c) return SWCS_E_INVALID;
+  if (M != c->last_M) return fail(c, SWCS_E_INVALID, "M differs from the last apply call");
+  if (M == 0) return SWCS_OK;
+  if (!n_act) return fail(c, SWCS_E_INVALID, "null n_act");
+  HIP_TRY(c, hipSetDevice(c->device), "hipSetDevice");
+  HIP_TRY(c, hipMemcpyAsync(n_act, c->gate_n_act.p, (size_t)M * 8, hipMemcpyDeviceToHost, c->stream), "copy");
+  HIP_TRY(c, hipStreamSynchronize(c->stream), "sync");
   return SWCS_OK;
 }
 

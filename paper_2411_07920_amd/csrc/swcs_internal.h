@@ -299,7 +299,8 @@ __device__ inline bool filter_maybe(const unsigned* __restrict__ filt, u64 fmask
 struct PairRec;
 struct StarRec;
 hipError_t launch_gen_gate(const DeviceState& st, const GenGate& g, double eps, u64* gate_n_in,
-                           unsigned gate_index, u64 max_keys, int grid, hipStream_t stream);
+                           unsigned gate_index, u64 max_keys, int grid, hipStream_t stream,
+                           u64* gate_n_act = nullptr);
 hipError_t launch_gen_replay(const DeviceState& st, double* amps, u64 n, const GenGate& g, double eps,
                              PairRec* plog, u64* pcount, StarRec* slog, u64* scount, int grid,
                              hipStream_t stream);
@@ -314,7 +315,7 @@ hipError_t launch_hash_clear(HashSlot* tab, u64 slots, hipStream_t stream);
 hipError_t launch_hash_build(const DeviceState& st, u64 n, hipStream_t stream);
 hipError_t launch_gate(const DeviceState& st, const OpDesc& op, double c, double sn, double eps,
                        u64* gate_n_in, int check_cap, unsigned gate_index, u64 max_keys, int grid,
-                       hipStream_t stream);
+                       hipStream_t stream, u64* gate_n_act = nullptr);
 hipError_t launch_prune_all(const DeviceState& st, double eps, int grid, hipStream_t stream);
 hipError_t launch_hash_build_dev(const DeviceState& st, int grid, hipStream_t stream);
 hipError_t launch_filter_build(const DeviceState& st, u64 n, int grid, hipStream_t stream);

@@ -79,6 +79,7 @@ SIGNATURES = {
     "swcs_param_gradients": (ctypes.c_int, [_vp, _dp, _dp]),
     "swcs_gate_sizes": (ctypes.c_int, [_vp, _i64p, _i64]),
     "swcs_state_counts": (ctypes.c_int, [_vp, _i64p, _i64p]),
+    "swcs_gate_active": (ctypes.c_int, [_vp, _i64p, _i64]),
     "swcs_pool_stats": (ctypes.c_int, [_vp, _dp, _i64p, ctypes.POINTER(ctypes.c_int32),
                                        ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
     "swcs_occupations": (ctypes.c_int, [_vp, _dp]),
@@ -388,6 +389,12 @@ class Context:
     def gate_sizes(self, M: int):
         out = np.zeros(max(M, 1), dtype=np.int64)
         self._check(self._lib.swcs_gate_sizes(self._h, _ptr(out, ctypes.c_int64), M))
+        return out[:M]
+
+    def gate_active(self, M: int):
+        """Entries each gate's operator acted on (multi-block gates; 0 in the LDS chain)."""
+        out = np.zeros(max(M, 1), dtype=np.int64)
+        self._check(self._lib.swcs_gate_active(self._h, _ptr(out, ctypes.c_int64), M))
         return out[:M]
 
     def state_counts(self):
