@@ -246,7 +246,8 @@ def gpu_bench(args, wl):
     kern = {}
     reps = 3
     for kname in ("chain_lds", "gate", "adjoint_lds", "adjoint_replay_lds", "gate_replay", "adjoint_rec", "sigma_proj",
-                  "holepair", "sigma_push", "sigma_push_into", "pool_contract", "contract_ops", "select"):
+                  "holepair", "sigma_push", "sigma_push_into", "pool_contract", "contract_ops", "select",
+                  "join_emit", "join_sort", "join_reduce"):
         if not args.kernel_times:
             break
         ctx.timer_start(kname)
@@ -269,7 +270,11 @@ def algorithmic_bytes(kname, wl, r):
     and gate for the LDS adjoint's replay and reverse sweeps); 16 B per (source,
     connection) read-modify-write of the external sigma table; 8 B per probe
     of a hash table and 16 B per source determinant read; for the selection,
-    a score and a random key per operator in and the chosen indices out."""
+    a score and a random key per operator in and the chosen indices out.
+    Whole-pool gradients by sort and join: 8 B per (source, connection)
+    record written (plus 16 B per source read) by the emit; 16 B per record
+    and radix pass (read and written once) by the sort; 8 B per record read
+    and 8 B per gradient update by the join."""
     from paper_2411_07920_amd.inputs import sector_size  # noqa: F401
     n_in = r["n_in"]
     M = len(n_in)
@@ -292,6 +297,16 @@ def algorithmic_bytes(kname, wl, r):
         return n * (C * 8.0 + 16.0)
     if kname == "contract_ops":
         return n * 16.0 + wl.n_top * 0.0
+    if kname in ("join_emit", "join_sort", "join_reduce"):
+        R = n * (C + 1)
+        if kname == "join_emit":
+            return R * 8.0 + n * 16.0
+        if kname == "join_sort":
+            kb = 8
+            while kb < 24 and (R >> kb) > 256:
+                kb += 8
+            return R * 16.0 * (kb // 8)
+        return R * 8.0 + n * C * 8.0
     if kname == "select":
         return wl.K * 8.0 + (wl.n_top + wl.n_rand) * 4.0  # scores and random keys in, indices out
     return 0.0

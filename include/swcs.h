@@ -144,6 +144,24 @@ int swcs_set_table_budget(swcs_ctx* ctx, int64_t bytes);
 enum { SWCS_SIGMA_AUTO = 0, SWCS_SIGMA_ENUMERATE = 1, SWCS_SIGMA_HOLE_PAIRS = 2, SWCS_SIGMA_PAIRS = 3 };
 int swcs_set_sigma_method(swcs_ctx* ctx, int method);
 
+/* How the pool gradients of a whole pool, or of a subset of at least half
+ * of it, are formed (ADAPT step 4, Sec. II.C: g_k = <psi|[H, A_k]|psi> /
+ * <psi|psi> = 2 <sigma|A_k psi> / <psi|psi> with sigma = H psi on the
+ * external space).  TABLE pushes H_{X D} psi(D) for every alive D and
+ * connection X into a device-wide hash table of sigma(X), then contracts
+ * (swcs_set_table_budget applies).  JOIN writes one 8-byte record per
+ * (D, X) pair (alive * (C + 1) records, C the connections per determinant),
+ * sorts them by a hash of X and forms sigma(X) and the gradients per group
+ * in LDS; it needs 16 bytes per record of device memory and storage index,
+ * connection ordinal and 8 to 24 hash bits within one 64-bit word.  AUTO
+ * (default) takes JOIN when no table budget is set, the records fit within
+ * half of the free device memory and the word, else TABLE; a JOIN pass whose
+ * hash group overflows its LDS table is redone by TABLE.  Forced JOIN that
+ * does not fit returns SWCS_E_CAPACITY.  Both agree up to summation order.
+ * Returns SWCS_E_INVALID for an unknown method. */
+enum { SWCS_POOL_AUTO = 0, SWCS_POOL_TABLE = 1, SWCS_POOL_JOIN = 2 };
+int swcs_set_pool_method(swcs_ctx* ctx, int method);
+
 
 /* Step 1 of the ADAPT procedure (Sec. II.C): molecular integrals.  h[n*n] and
  * eri[n^4] (host, float64, layouts above).  Rejects non-finite values, an
@@ -268,12 +286,27 @@ int swcs_gate_active(swcs_ctx* ctx, int64_t* n_act, int64_t M);
  * entries of the current state. */
 int swcs_state_counts(swcs_ctx* ctx, int64_t* stored, int64_t* alive);
 
+/* Rebuild of the current state without its pruned entries (Sec. II.B, the
+ * truncated state keeps only amplitudes at or above eps): the alive entries
+ * move to the front of the storage arrays in their storage order and the
+ * index is rebuilt; keys, amplitudes and every later result are unchanged
+ * (sums over the state may differ in rounding order).  Storage positions
+ * change, so the record that swcs_param_gradients needs is dropped (it
+ * then returns SWCS_E_STATE until the next ansatz is applied from the
+ * reference).  Gate chains that keep no such record (swcs_apply_gates)
+ * rebuild by themselves when pruned entries outnumber alive ones, or are a
+ * quarter of them when the arrays would otherwise grow.  *stored (may be
+ * NULL) receives the stored count afterwards.  SWCS_E_STATE without a
+ * state. */
+int swcs_compact(swcs_ctx* ctx, int64_t* stored);
+
 /* The last pool-gradient pass: *keys the key count its accumulation table
- * was sized for (after a full-pool pass: the distinct external determinants
- * it met), *table_slots the slots of one table, *batches the key-hash
- * batches, *passes how many times the pass ran (a pass whose table filled is
- * repeated), *screened 1 for a subset pass.  Any pointer may be NULL;
- * SWCS_E_STATE before the first pass. */
+ * was sized for (after a full-pool pass: the distinct determinants sigma was
+ * formed on), *table_slots the slots of one table (0 for a sort-and-join
+ * pass, which has none), *batches the key-hash batches, *passes how many
+ * times the pass ran (a pass whose table filled is repeated), *screened 1
+ * for a subset pass.  Any pointer may be NULL; SWCS_E_STATE before the
+ * first pass. */
 int swcs_pool_stats(swcs_ctx* ctx, double* keys, int64_t* table_slots, int32_t* batches,
                     int32_t* passes, int32_t* screened);
 
@@ -305,7 +338,10 @@ enum {
   SWCS_K_CONTRACT_OPS = 10,  /* operator-major contraction of a small subset     */
   SWCS_K_HOLEPAIR = 11,      /* sigma_P pair evaluation inside hole-pair groups  */
   SWCS_K_ADJOINT_REPLAY_LDS = 12, /* segment replays of the LDS adjoint, one workgroup each */
-  SWCS_K_SELECT = 13         /* screener selection (top + random), swcs_select   */
+  SWCS_K_SELECT = 13,        /* screener selection (top + random), swcs_select   */
+  SWCS_K_JOIN_EMIT = 14,     /* full-pool gradients: one record per connection   */
+  SWCS_K_JOIN_SORT = 15,     /* full-pool gradients: radix sort of the records   */
+  SWCS_K_JOIN_REDUCE = 16    /* full-pool gradients: sigma and g per bucket run  */
 };
 
 /* From now on record HIP events on the context stream around every launch

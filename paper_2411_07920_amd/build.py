@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libswcs.so")
 SOURCES = ["swcs_api.hip", "k_state.hip", "k_chain.hip", "k_sigma.hip", "k_sort.hip",
-           "k_screener.hip", "k_generator.hip"]
+           "k_screener.hip", "k_generator.hip", "k_join.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

@@ -262,16 +262,16 @@ struct LdsMu {
 };
 
 // gate_entry for N entries of one thread in the HBM kernels: entry j is
-// i0 + j * stride (skipped at or beyond n).  The entries go through each
+// idx[j] when use[j] (idx[j] < n always).  The entries go through each
 // stage together -- keys; first index probes with the entries' own
 // amplitudes; partner amplitudes -- so that their memory requests overlap;
 // outputs are exactly those of gate_entry.  A T^dagger entry loads its own
 // amplitude before knowing whether it owns the pair; when it does not, the
 // value (possibly being rewritten by the owner) is discarded unused.
 template <int N>
-__device__ inline void gate_entries_staged(const GlobalStore& S, u64 n, u64 i0, u64 stride,
-                                           const OpDesc& op, double c, double sn, double eps,
-                                           GateOut (&o)[N]) {
+__device__ inline void gate_entries_list(const GlobalStore& S, const u64 (&idx)[N], const bool (&use)[N],
+                                         const OpDesc& op, double c, double sn, double eps,
+                                         GateOut (&o)[N]) {
   const u64 pair_mask = op.ann | op.cre;
   u64 D[N], partner[N], h[N];
   int kind[N];  // 0: untouched, 1: T acts on D, 2: T^dagger acts on D
@@ -280,20 +280,15 @@ __device__ inline void gate_entries_staged(const GlobalStore& S, u64 n, u64 i0, 
   double araw[N], braw[N], own[N];
   // The entries' keys, then every entry's kind and probe position, then the
   // probes: key loads behind a branch, or a probe issued before the next
-  // entry's key is used, would make the loads wait for each other (callers
-  // pass i0 < n, so the clamped index is valid).
+  // entry's key is used, would make the loads wait for each other.
 #pragma unroll
-  for (int j = 0; j < N; ++j) {
-    const u64 i = i0 + (u64)j * stride;
-    D[j] = S.keys[i < n ? i : n - 1];
-  }
+  for (int j = 0; j < N; ++j) D[j] = S.keys[idx[j]];
   __builtin_amdgcn_sched_barrier(0);  // every key load before the first use of a key
 #pragma unroll
   for (int j = 0; j < N; ++j) {
-    const u64 i = i0 + (u64)j * stride;
     const bool isT = ((D[j] & op.ann) == op.ann) && ((D[j] & op.cre) == 0);
     const bool isTd = ((D[j] & op.cre) == op.cre) && ((D[j] & op.ann) == 0);
-    kind[j] = (i < n) ? (isT ? 1 : (isTd ? 2 : 0)) : 0;
+    kind[j] = use[j] ? (isT ? 1 : (isTd ? 2 : 0)) : 0;
     partner[j] = D[j] ^ pair_mask;
     h[j] = mix64(partner[j]) & S.hmask;
   }
@@ -303,7 +298,7 @@ __device__ inline void gate_entries_staged(const GlobalStore& S, u64 n, u64 i0, 
   for (int j = 0; j < N; ++j) asm volatile("" : : "v"(h[j]), "v"(kind[j]));
 #pragma unroll
   for (int j = 0; j < N; ++j) {
-    const u64 i = i0 + (u64)j * stride;
+    const u64 i = idx[j];
     if (kind[j]) {
       sl[j] = S.hash[h[j]];
       own[j] = S.amps[i];
@@ -326,7 +321,6 @@ __device__ inline void gate_entries_staged(const GlobalStore& S, u64 n, u64 i0, 
   }
 #pragma unroll
   for (int j = 0; j < N; ++j) {
-    const u64 i = i0 + (u64)j * stride;
     araw[j] = dead_value();
     braw[j] = dead_value();
     if (kind[j] == 1) {
@@ -338,7 +332,7 @@ __device__ inline void gate_entries_staged(const GlobalStore& S, u64 n, u64 i0, 
   }
 #pragma unroll
   for (int j = 0; j < N; ++j) {
-    const u64 i = i0 + (u64)j * stride;
+    const u64 i = idx[j];
     GateOut& r = o[j];
     r = GateOut{false, 0ULL, 0.0, 0, false, kNoEntry, kNoEntry, 0.0, 0.0, 0, kind[j] != 0};
     if (kind[j] == 1) {
@@ -392,6 +386,23 @@ __device__ inline void gate_entries_staged(const GlobalStore& S, u64 n, u64 i0, 
   }
 }
 
+
+// The strided form: entry j is i0 + j * stride, skipped at or beyond n
+// (callers pass i0 < n, so the clamped index is valid).
+template <int N>
+__device__ inline void gate_entries_staged(const GlobalStore& S, u64 n, u64 i0, u64 stride,
+                                           const OpDesc& op, double c, double sn, double eps,
+                                           GateOut (&o)[N]) {
+  u64 idx[N];
+  bool use[N];
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    const u64 i = i0 + (u64)j * stride;
+    use[j] = i < n;
+    idx[j] = use[j] ? i : n - 1;
+  }
+  gate_entries_list<N>(S, idx, use, op, c, sn, eps, o);
+}
 
 
 }  // namespace swcs

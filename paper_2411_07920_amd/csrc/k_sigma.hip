@@ -7,168 +7,9 @@
 // one determinant at a time: its occupied / virtual lists and the hole- and
 // particle-set tables of its spin-conserving singles and doubles are staged
 // in LDS, and the lanes walk the connections from those tables.
-#include "swcs_internal.h"
+#include "conn_ops.h"
 
 namespace swcs {
-
-constexpr int kSigBlock = 256;
-constexpr int kMaxPairs = 32 * 31 / 2;
-
-struct SigShared {
-  int occ_a[32], occ_b[32], vir_a[32], vir_b[32];
-  unsigned char px[kMaxPairs], py[kMaxPairs];
-};
-
-__device__ inline void build_pair_table(SigShared& S) {
-  for (int t = threadIdx.x; t < kMaxPairs; t += blockDim.x) {
-    int y = 1;
-    while ((y + 1) * y / 2 <= t) ++y;
-    S.py[t] = (unsigned char)y;
-    S.px[t] = (unsigned char)(t - y * (y - 1) / 2);
-  }
-}
-
-// Thread p < n places spatial orbital p in the alpha / beta lists.
-__device__ inline void build_lists_shared(u64 D, int n, SigShared& S) {
-  const int p = threadIdx.x;
-  if (p < n) {
-    const u64 below = (p == 0) ? 0ULL : ((1ULL << (2 * p)) - 1ULL);
-    const u64 amask = 0x5555555555555555ULL, bmask = 0xAAAAAAAAAAAAAAAAULL;
-    const u64 occ_below = D & below, vir_below = ~D & below;
-    if ((D >> (2 * p)) & 1ULL) S.occ_a[__popcll(occ_below & amask)] = 2 * p;
-    else S.vir_a[__popcll(vir_below & amask)] = 2 * p;
-    if ((D >> (2 * p + 1)) & 1ULL) S.occ_b[__popcll(occ_below & bmask)] = 2 * p + 1;
-    else S.vir_b[__popcll(vir_below & bmask)] = 2 * p + 1;
-  }
-}
-
-// Connection tables of one determinant, in LDS: the hole sets and particle
-// sets of the five spin-conserving classes (alpha single, beta single,
-// alpha-alpha double, beta-beta double, alpha-beta double) as bit masks plus
-// their sorted spin-orbital indices.  A connection is (hole set h, particle
-// set p) of one class, X = D ^ hmask[h] ^ pmask[p]; the lanes walk the
-// (h, p) grid of each class with a stride of the block size, stepping the
-// indices incrementally (one division per class and lane).
-struct ConnTables {
-  u64* hmask;  // arrays in dynamic LDS, sized by the launcher (conn_tables_bytes)
-  u64* pmask;
-  unsigned char *h0, *h1, *p0, *p1;
-  int hbeg[5], nh[5], pbeg[5], np[5];
-};
-
-__host__ __device__ inline void conn_set_counts(const ExcSpace& E, int* NH, int* NP) {
-  const int na = E.na, nb = E.nb, va = E.va, vb = E.vb;
-  *NH = na + nb + na * (na - 1) / 2 + nb * (nb - 1) / 2 + na * nb;
-  *NP = va + vb + va * (va - 1) / 2 + vb * (vb - 1) / 2 + va * vb;
-}
-
-size_t conn_tables_bytes(const ExcSpace& E) {
-  int NH, NP;
-  conn_set_counts(E, &NH, &NP);
-  return (size_t)(NH + NP) * 10;
-}
-
-// Carve the tables out of the dynamic LDS buffer.
-__device__ inline void attach_conn_tables(ConnTables& T, unsigned char* dyn, const ExcSpace& E) {
-  int NH, NP;
-  conn_set_counts(E, &NH, &NP);
-  T.hmask = (u64*)dyn;
-  T.pmask = T.hmask + NH;
-  T.h0 = (unsigned char*)(T.pmask + NP);
-  T.h1 = T.h0 + NH;
-  T.p0 = T.h1 + NH;
-  T.p1 = T.p0 + NP;
-}
-
-__device__ inline void build_conn_tables(const SigShared& S, const ExcSpace& E, ConnTables& T) {
-  const int na = E.na, nb = E.nb, va = E.va, vb = E.vb;
-  if (threadIdx.x == 0) {
-    int h = 0, p = 0;
-    const int nhs[5] = {na, nb, na * (na - 1) / 2, nb * (nb - 1) / 2, na * nb};
-    const int nps[5] = {va, vb, va * (va - 1) / 2, vb * (vb - 1) / 2, va * vb};
-    for (int c = 0; c < 5; ++c) {
-      T.hbeg[c] = h;
-      T.nh[c] = nhs[c];
-      T.pbeg[c] = p;
-      T.np[c] = nps[c];
-      h += nhs[c];
-      p += nps[c];
-    }
-  }
-  __syncthreads();
-  const int tid = threadIdx.x;
-  // holes
-  for (int t = tid; t < na; t += blockDim.x) {
-    const int P = S.occ_a[t];
-    T.hmask[T.hbeg[0] + t] = 1ULL << P; T.h0[T.hbeg[0] + t] = P; T.h1[T.hbeg[0] + t] = P;
-  }
-  for (int t = tid; t < nb; t += blockDim.x) {
-    const int P = S.occ_b[t];
-    T.hmask[T.hbeg[1] + t] = 1ULL << P; T.h0[T.hbeg[1] + t] = P; T.h1[T.hbeg[1] + t] = P;
-  }
-  for (int t = tid; t < T.nh[2]; t += blockDim.x) {
-    const int x = S.occ_a[S.px[t]], y = S.occ_a[S.py[t]];
-    T.hmask[T.hbeg[2] + t] = (1ULL << x) | (1ULL << y); T.h0[T.hbeg[2] + t] = x; T.h1[T.hbeg[2] + t] = y;
-  }
-  for (int t = tid; t < T.nh[3]; t += blockDim.x) {
-    const int x = S.occ_b[S.px[t]], y = S.occ_b[S.py[t]];
-    T.hmask[T.hbeg[3] + t] = (1ULL << x) | (1ULL << y); T.h0[T.hbeg[3] + t] = x; T.h1[T.hbeg[3] + t] = y;
-  }
-  for (int t = tid; t < T.nh[4]; t += blockDim.x) {
-    const int i = t / nb, j = t - (t / nb) * nb;
-    const int x = S.occ_a[i], y = S.occ_b[j];
-    T.hmask[T.hbeg[4] + t] = (1ULL << x) | (1ULL << y);
-    T.h0[T.hbeg[4] + t] = min(x, y); T.h1[T.hbeg[4] + t] = max(x, y);
-  }
-  // particles
-  for (int t = tid; t < va; t += blockDim.x) {
-    const int P = S.vir_a[t];
-    T.pmask[T.pbeg[0] + t] = 1ULL << P; T.p0[T.pbeg[0] + t] = P; T.p1[T.pbeg[0] + t] = P;
-  }
-  for (int t = tid; t < vb; t += blockDim.x) {
-    const int P = S.vir_b[t];
-    T.pmask[T.pbeg[1] + t] = 1ULL << P; T.p0[T.pbeg[1] + t] = P; T.p1[T.pbeg[1] + t] = P;
-  }
-  for (int t = tid; t < T.np[2]; t += blockDim.x) {
-    const int x = S.vir_a[S.px[t]], y = S.vir_a[S.py[t]];
-    T.pmask[T.pbeg[2] + t] = (1ULL << x) | (1ULL << y); T.p0[T.pbeg[2] + t] = x; T.p1[T.pbeg[2] + t] = y;
-  }
-  for (int t = tid; t < T.np[3]; t += blockDim.x) {
-    const int x = S.vir_b[S.px[t]], y = S.vir_b[S.py[t]];
-    T.pmask[T.pbeg[3] + t] = (1ULL << x) | (1ULL << y); T.p0[T.pbeg[3] + t] = x; T.p1[T.pbeg[3] + t] = y;
-  }
-  for (int t = tid; t < T.np[4]; t += blockDim.x) {
-    const int a = t / vb, b = t - (t / vb) * vb;
-    const int x = S.vir_a[a], y = S.vir_b[b];
-    T.pmask[T.pbeg[4] + t] = (1ULL << x) | (1ULL << y);
-    T.p0[T.pbeg[4] + t] = min(x, y); T.p1[T.pbeg[4] + t] = max(x, y);
-  }
-}
-
-// Calls f(X, nh, h0, h1, p0, p1) for every single (nh = 1) and double
-// (nh = 2) connection X of D assigned to this lane; holes h0 < h1 and
-// particles p0 < p1 are spin-orbital indices.
-template <class F>
-__device__ inline void for_each_connection(const ConnTables& T, u64 D, F&& f) {
-  for (int c = 0; c < 5; ++c) {
-    const int nh = T.nh[c], np = T.np[c];
-    if (nh == 0 || np == 0) continue;
-    const int hb = T.hbeg[c], pb = T.pbeg[c];
-    int hi = (int)threadIdx.x / np;
-    int pi = (int)threadIdx.x - hi * np;
-    const int nholes = c < 2 ? 1 : 2;
-    while (hi < nh) {
-      const int H = hb + hi, Pp = pb + pi;
-      const u64 X = D ^ T.hmask[H] ^ T.pmask[Pp];
-      f(X, nholes, (int)T.h0[H], (int)T.h1[H], (int)T.p0[Pp], (int)T.p1[Pp]);
-      pi += blockDim.x;
-      while (pi >= np) {
-        pi -= np;
-        ++hi;
-      }
-    }
-  }
-}
 
 __device__ inline double block_sum(double v, double* red) {
   red[threadIdx.x] = v;
@@ -747,31 +588,6 @@ k_sigma_push(const u64* __restrict__ keys, const double* __restrict__ amps, Ints
   }
   const double tot = block_sum(ins, red);
   if (threadIdx.x == 0) inserted[blockIdx.x] = tot;
-}
-
-// Operator of the pool that links D to its connection (holes h0 < h1,
-// particles p0 < p1): returns its index (or -1), whether T (rather than
-// T^dagger) acts on D, and the operator's (P, Q, R, S).  The generator table
-// is indexed directly: singles at pair(P, Q), doubles at npairs +
-// tri(pair(P, Q)) + pair(R, S) with pair(a, b) = a (a - 1) / 2 + b.
-__device__ inline int pair_index(int a, int b) { return a * (a - 1) / 2 + b; }
-
-__device__ inline int linking_operator(const int* __restrict__ optab, int npairs, int nh, int h0,
-                                       int h1, int p0, int p1, bool* t_acts, OpDesc* op) {
-  if (nh == 1) {
-    *t_acts = p0 > h0;
-    op->P = *t_acts ? p0 : h0;
-    op->Q = *t_acts ? h0 : p0;
-    op->R = op->S = -1;
-    return optab[pair_index(op->P, op->Q)];
-  }
-  *t_acts = p1 > h1;
-  op->P = *t_acts ? p1 : h1;
-  op->Q = *t_acts ? p0 : h0;
-  op->R = *t_acts ? h1 : p1;
-  op->S = *t_acts ? h0 : p0;
-  const int pq = pair_index(op->P, op->Q), rs = pair_index(op->R, op->S);
-  return optab[npairs + pq * (pq - 1) / 2 + rs];
 }
 
 // g_k accumulation, determinant-major: every connection X of every alive D

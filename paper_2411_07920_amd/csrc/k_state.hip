@@ -13,22 +13,35 @@
 
 namespace swcs {
 
-// One gate over the stored entries.  Each block of kGateThreads threads walks
-// tiles of kGateTile consecutive entries (kGateItems per thread, coalesced);
-// the new partner keys a tile creates are staged in LDS and written out
-// together behind a single atomic on the append counter, so the number of
-// same-address device atomics is one per tile plus two per block, not one per
-// wavefront.  Eight wavefronts per SIMD (at most 64 VGPRs) keep two blocks
-// resident per compute unit, so one block's index inserts overlap the
-// other's loads.
+// One gate over the stored entries, in three phases per tile of
+// kGateThreads * SCAN entries:
+//   scan   -- every thread loads SCAN keys (coalesced) and the
+//             entries the operator or its adjoint acts on are listed in LDS
+//             (16-bit tile offsets), so that the next phase runs on full
+//             wavefronts whatever the active fraction;
+//   update -- rounds of kGateTile listed entries, kGateItems per thread
+//             staged together (gate_entries_list): index probe, amplitudes,
+//             update with fused pruning; the new partner keys of a round are
+//             staged in LDS;
+//   append -- one atomic on the append counter per round, then coalesced
+//             writes of the new keys and amplitudes.
+// The index entries of the appended keys are inserted afterwards by
+// k_hash_insert_appended: no probe of this gate can look for a key the gate
+// itself appends (its partner under this operator is the entry that appends
+// it), so the inserts leave the critical path of the gate.
+// SCAN = 16 for large states (more entries in flight per block), 2 for
+// states of up to a few hundred thousand entries (more blocks).
+template <int SCAN>
 __global__ void __launch_bounds__(kGateThreads, 8)
 k_gate(u64* __restrict__ keys, double* __restrict__ amps, HashSlot* __restrict__ hash, u64 hmask,
        u64 cap, Counters* __restrict__ ctr, OpDesc op, double c, double sn, double eps,
        u64* __restrict__ gate_n_in, int check_cap, unsigned gate_index, u64 max_keys,
        u64* __restrict__ gate_n_act) {
+  constexpr int kScan = kGateThreads * SCAN;  // entries per tile (< 2^16)
+  __shared__ unsigned short s_act[kScan];
   __shared__ u64 s_key[kGateTile];
   __shared__ double s_val[kGateTile];
-  __shared__ unsigned s_cnt;
+  __shared__ unsigned s_nact, s_cnt;
   __shared__ int s_run;
   __shared__ u64 s_n_in, s_base;
   __shared__ long long s_wsum[kGateThreads / 64];
@@ -58,79 +71,108 @@ k_gate(u64* __restrict__ keys, double* __restrict__ amps, HashSlot* __restrict__
     }
     s_run = run;
     s_n_in = n_in;
+    s_nact = 0;
     s_cnt = 0;
   }
   __syncthreads();
   if (!s_run) return;
   const u64 n_in = s_n_in;
   long long dalive = 0;
-  unsigned nact = 0;
+  u64 nact = 0;
   const int lane = __lane_id();
   const u64 below = (1ULL << lane) - 1ULL;
-  const u64 ntiles = (n_in + kGateTile - 1) / kGateTile;
+  const u64 ntiles = (n_in + kScan - 1) / kScan;
   const GlobalStore S{keys, amps, hash, hmask};
   for (u64 t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    GateOut o[kGateItems];
-    gate_entries_staged<kGateItems>(S, n_in, t * (u64)kGateTile + threadIdx.x, kGateThreads, op, c, sn,
-                                    eps, o);
+    const u64 base = t * (u64)kScan;
+    // scan: keys of the tile, active entries listed in LDS
+    {
+      u64 D[SCAN];
 #pragma unroll
-    for (int j = 0; j < kGateItems; ++j) {
-      dalive += o[j].dalive;
-      nact += o[j].acts ? 1u : 0u;
-      const u64 m = __ballot(o[j].append);
-      if (m) {
-        const int leader = __ffsll((long long)m) - 1;
-        unsigned b = 0;
-        if (lane == leader) b = atomicAdd(&s_cnt, (unsigned)__popcll(m));
-        b = __shfl(b, leader);
-        if (o[j].append) {
-          const unsigned slot = b + (unsigned)__popcll(m & below);
-          s_key[slot] = o[j].key;
-          s_val[slot] = o[j].val;
+      for (int j = 0; j < SCAN; ++j) {
+        const u64 i = base + (u64)j * kGateThreads + threadIdx.x;
+        D[j] = (i < n_in) ? keys[i] : 0ULL;
+      }
+#pragma unroll
+      for (int j = 0; j < SCAN; ++j) {
+        const unsigned off = (unsigned)j * kGateThreads + threadIdx.x;
+        const bool in = base + off < n_in;
+        const bool isT = ((D[j] & op.ann) == op.ann) && ((D[j] & op.cre) == 0);
+        const bool isTd = ((D[j] & op.cre) == op.cre) && ((D[j] & op.ann) == 0);
+        const bool act = in && (isT || isTd);
+        const u64 m = __ballot(act);
+        if (m) {
+          const int leader = __ffsll((long long)m) - 1;
+          unsigned b = 0;
+          if (lane == leader) b = atomicAdd(&s_nact, (unsigned)__popcll(m));
+          b = __shfl(b, leader);
+          if (act) s_act[b + (unsigned)__popcll(m & below)] = (unsigned short)off;
         }
       }
     }
     __syncthreads();
-    const unsigned cnt = s_cnt;
-    if (cnt) {
-      if (threadIdx.x == 0) s_base = atomicAdd(&ctr->app, (u64)cnt);
-      __syncthreads();
-      const u64 gb = n_in + s_base;
-      for (unsigned j = threadIdx.x; j < cnt; j += kGateThreads) {
-        const u64 idx = gb + j;
-        if (idx < cap) {
-          keys[idx] = s_key[j];
-          amps[idx] = s_val[j];
-          hash_insert_new(hash, hmask, s_key[j], idx);
-        } else {
-          atomicOr(&ctr->flags, kFlagOverflow);
+    const unsigned na = s_nact;
+    nact += na;
+    for (unsigned r0 = 0; r0 < na; r0 += kGateTile) {
+      // update: kGateItems listed entries per thread
+      u64 idx[kGateItems];
+      bool use[kGateItems];
+#pragma unroll
+      for (int j = 0; j < kGateItems; ++j) {
+        const unsigned q = r0 + (unsigned)j * kGateThreads + threadIdx.x;
+        use[j] = q < na;
+        idx[j] = base + (use[j] ? (u64)s_act[q] : 0ULL);
+      }
+      GateOut o[kGateItems];
+      gate_entries_list<kGateItems>(S, idx, use, op, c, sn, eps, o);
+#pragma unroll
+      for (int j = 0; j < kGateItems; ++j) {
+        dalive += o[j].dalive;
+        const u64 m = __ballot(o[j].append);
+        if (m) {
+          const int leader = __ffsll((long long)m) - 1;
+          unsigned b = 0;
+          if (lane == leader) b = atomicAdd(&s_cnt, (unsigned)__popcll(m));
+          b = __shfl(b, leader);
+          if (o[j].append) {
+            const unsigned slot = b + (unsigned)__popcll(m & below);
+            s_key[slot] = o[j].key;
+            s_val[slot] = o[j].val;
+          }
         }
       }
       __syncthreads();
-      if (threadIdx.x == 0) s_cnt = 0;
+      // append: one counter atomic, coalesced writes
+      const unsigned cnt = s_cnt;
+      if (cnt) {
+        if (threadIdx.x == 0) s_base = atomicAdd(&ctr->app, (u64)cnt);
+        __syncthreads();
+        const u64 gb = n_in + s_base;
+        for (unsigned j = threadIdx.x; j < cnt; j += kGateThreads) {
+          const u64 i = gb + j;
+          if (i < cap) {
+            keys[i] = s_key[j];
+            amps[i] = s_val[j];
+          } else {
+            atomicOr(&ctr->flags, kFlagOverflow);
+          }
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) s_cnt = 0;
+      }
       __syncthreads();
     }
+    if (threadIdx.x == 0) s_nact = 0;
+    __syncthreads();
   }
-  // Block reduction of the alive-count change (and of the active count),
-  // then last-block finalization.
-  for (int off = 32; off > 0; off >>= 1) {
-    dalive += __shfl_xor(dalive, off);
-    nact += __shfl_xor(nact, off);
-  }
-  __shared__ unsigned s_nact[kGateThreads / 64];
-  if (lane == 0) {
-    s_wsum[threadIdx.x / 64] = dalive;
-    s_nact[threadIdx.x / 64] = nact;
-  }
+  // Block reduction of the alive-count change, then last-block finalization.
+  for (int off = 32; off > 0; off >>= 1) dalive += __shfl_xor(dalive, off);
+  if (lane == 0) s_wsum[threadIdx.x / 64] = dalive;
   __syncthreads();
   if (threadIdx.x == 0) {
     long long d = 0;
-    u64 na = 0;
-    for (int w = 0; w < kGateThreads / 64; ++w) {
-      d += s_wsum[w];
-      na += s_nact[w];
-    }
-    if (gate_n_act && na) atomicAdd((unsigned long long*)gate_n_act, (unsigned long long)na);
+    for (int w = 0; w < kGateThreads / 64; ++w) d += s_wsum[w];
+    if (gate_n_act && nact) atomicAdd((unsigned long long*)gate_n_act, (unsigned long long)nact);
     if (d != 0) atomicAdd((unsigned long long*)&ctr->dalive, (unsigned long long)d);
     __threadfence();
     const unsigned tk = atomicAdd(&ctr->ticket, 1u);
@@ -143,6 +185,7 @@ k_gate(u64* __restrict__ keys, double* __restrict__ amps, HashSlot* __restrict__
     const long long da = (long long)atomicAdd((unsigned long long*)&ctr->dalive, 0ULL);
     const u64 alive = ctr->alive;
     if (gate_n_in) *gate_n_in = alive;
+    ctr->n_prev = n_in;
     ctr->n = n_in + (app < cap - n_in ? app : cap - n_in);
     ctr->alive = (u64)((long long)alive + da);
     ctr->app = 0;
@@ -150,6 +193,21 @@ k_gate(u64* __restrict__ keys, double* __restrict__ amps, HashSlot* __restrict__
     __threadfence();
     ctr->ticket = 0;
   }
+}
+
+// Index entries of the keys the last gate appended, [n_prev, n).  Does
+// nothing after a gate that stopped for capacity (it appended nothing; the
+// range still names the previous gate's keys, which are indexed already).
+__global__ void __launch_bounds__(256)
+k_hash_insert_appended(const u64* __restrict__ keys, HashSlot* __restrict__ hash, u64 hmask,
+                       const Counters* __restrict__ ctr) {
+  const unsigned fl = __hip_atomic_load(&ctr->flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (fl & kFlagStopped) return;
+  const u64 lo = __hip_atomic_load(&ctr->n_prev, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const u64 hi = __hip_atomic_load(&ctr->n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const u64 stride = (u64)gridDim.x * blockDim.x;
+  for (u64 i = lo + (u64)blockIdx.x * blockDim.x + threadIdx.x; i < hi; i += stride)
+    hash_insert_new(hash, hmask, keys[i], i);
 }
 
 // Replay of one gate inside the adjoint's recomputation: the same update as
@@ -459,8 +517,18 @@ hipError_t launch_hash_build_dev(const DeviceState& st, int grid, hipStream_t st
 hipError_t launch_gate(const DeviceState& st, const OpDesc& op, double c, double sn, double eps,
                        u64* gate_n_in, int check_cap, unsigned gate_index, u64 max_keys, int grid,
                        hipStream_t stream, u64* gate_n_act) {
-  hipLaunchKernelGGL(k_gate, dim3(grid), dim3(kGateThreads), 0, stream, st.keys, st.amps, st.hash, st.hmask,
-                     st.cap, st.ctr, op, c, sn, eps, gate_n_in, check_cap, gate_index, max_keys, gate_n_act);
+  if (st.cap >= kGateWideCap)
+    hipLaunchKernelGGL(k_gate<kGateScanWide>, dim3(grid), dim3(kGateThreads), 0, stream, st.keys, st.amps,
+                       st.hash, st.hmask, st.cap, st.ctr, op, c, sn, eps, gate_n_in, check_cap, gate_index,
+                       max_keys, gate_n_act);
+  else
+    hipLaunchKernelGGL(k_gate<kGateScanNarrow>, dim3(grid), dim3(kGateThreads), 0, stream, st.keys, st.amps,
+                       st.hash, st.hmask, st.cap, st.ctr, op, c, sn, eps, gate_n_in, check_cap, gate_index,
+                       max_keys, gate_n_act);
+  // at most one append per alive entry: a grid over a quarter of the
+  // capacity, grid-strided, covers any range
+  hipLaunchKernelGGL(k_hash_insert_appended, dim3(grid_for(st.cap / 4, 256, 8192)), dim3(256), 0, stream,
+                     st.keys, st.hash, st.hmask, st.ctr);
   return hipGetLastError();
 }
 

@@ -173,6 +173,7 @@ struct swcs_ctx {
   DevBuf partial, partial2, sigma, mu, work, seg_states, acc_tab, gbuf, subset_buf, scalars,
       exp_keys, exp_amps, exp_tmp_k, exp_tmp_v, sort_scratch, ctr_r, occ, sel_scratch, mlp_partial, mse_partial, hp_key, hp_val, hp_tk, hp_tv, diag;
   int sigma_method = SWCS_SIGMA_AUTO;
+  int pool_method = SWCS_POOL_AUTO;
   double ext_count = 0.0, ext_alive = 0.0;  // distinct external keys of the last full pool pass
   // the last pool-gradient pass (swcs_pool_stats): keys the table was sized
   // for (distinct external keys after a full pass), slots, batches, passes
@@ -394,6 +395,44 @@ int build_filter(swcs_ctx* c, u64 n, u64 alive) {
   return SWCS_OK;
 }
 
+// Rebuild of the state without its pruned entries (tombstones): the alive
+// entries are moved, in storage order, to the front of the arrays and the
+// index is rebuilt over them.  Storage positions change, so a gate record
+// that refers to them (the checkpoints of a chain applied from the
+// reference) no longer matches the state: callers compact only states that
+// carry no such record, or drop it.  *h is updated to the new counters.
+int state_compact(swcs_ctx* c, Counters* h) {
+  const u64 n = h->n, alive = h->alive;
+  if (alive >= n) return SWCS_OK;
+  HIP_TRY(c, c->exp_keys.ensure(std::max<u64>(1, alive) * 8), "alloc");
+  HIP_TRY(c, c->exp_amps.ensure(std::max<u64>(1, alive) * 8), "alloc");
+  const u64 scr = compact_scratch_elems(n);
+  HIP_TRY(c, c->sort_scratch.ensure(scr * 8), "alloc");
+  HIP_TRY(c, launch_compact_alive(c->st, n, nullptr, c->exp_keys.as<u64>(), c->exp_amps.as<double>(),
+                                  c->scalars.as<u64>() + 8, c->sort_scratch.as<u64>(), scr, c->stream), "compact");
+  if (alive > 0) {
+    HIP_TRY(c, hipMemcpyAsync(c->st.keys, c->exp_keys.p, alive * 8, hipMemcpyDeviceToDevice, c->stream), "copy keys");
+    HIP_TRY(c, hipMemcpyAsync(c->st.amps, c->exp_amps.p, alive * 8, hipMemcpyDeviceToDevice, c->stream), "copy amps");
+  }
+  HIP_TRY(c, launch_hash_clear(c->st.hash, c->st.hmask + 1, c->stream), "hash clear");
+  if (alive > 0) HIP_TRY(c, launch_hash_build(c->st, alive, c->stream), "hash build");
+  h->n = alive;
+  HIP_TRY(c, launch_store_counters(c->st.ctr, *h, c->stream), "counters");
+  c->hc = *h;
+  c->hc_valid = true;
+  ++c->state_version;
+  return SWCS_OK;
+}
+
+// Tombstones are reclaimed once they outnumber the alive entries (and are
+// at least kCompactMin), so a scan over the stored entries costs at most
+// twice one over the alive ones.
+constexpr u64 kCompactMin = 4096;
+bool compact_due(const Counters& h) {
+  const u64 dead = h.n - h.alive;
+  return dead >= kCompactMin && dead > h.alive;
+}
+
 // Reset the state to the single reference determinant.
 int state_reset_to_reference(swcs_ctx* c) {
   u64 cap;
@@ -534,7 +573,7 @@ int run_chain(swcs_ctx* c, const int32_t* op_idx, const double* cs, const double
                 "generator gate");
       else
         TIMED(c, SWCS_K_GATE, launch_gate(c->st, op, cs[g], sn[g], eps, c->gate_n_in.as<u64>() + g, 1,
-                               (unsigned)g, c->sector, gate_grid(c, c->st.cap / 2, kGateTile), c->stream,
+                               (unsigned)g, c->sector, gate_grid(c, c->st.cap / 2, gate_scan_tile(c->st.cap)), c->stream,
                                c->gate_n_act.as<u64>() + g),
                 "gate");
       // The gates only test the entries they touch; entries of a starting
@@ -556,16 +595,36 @@ int run_chain(swcs_ctx* c, const int32_t* op_idx, const double* cs, const double
       return fail(c, SWCS_E_DEVICE, "internal overflow in gate chain");
     }
     if (!(h.flags & kFlagStopped)) {
+      // a chain without checkpoints leaves no record of storage positions
+      if (!ckpt && compact_due(h)) {
+        int r = state_compact(c, &h);
+        if (r) return r;
+      }
       *out = h;
       return SWCS_OK;
     }
+    g0 = (int64_t)h.stop_gate;
+    h.flags &= ~kFlagStopped;
+    h.stop_gate = 0;
+    // A stopped gate changed nothing.  Without checkpoints, tombstones are
+    // reclaimed first when they are a quarter of the alive entries or more,
+    // and the arrays grow only if the gate still does not fit.
+    const bool star_stop = kind && kind[g0];
+    if (!ckpt && h.n - h.alive >= kCompactMin && 4 * (h.n - h.alive) >= h.alive) {
+      int r = state_compact(c, &h);
+      if (r) return r;
+      const u64 room = c->sector > h.n ? c->sector - h.n : 0;
+      const u64 grow_c = star_stop ? 2 * h.alive : h.alive;
+      if (h.n + std::min<u64>(grow_c, room) <= c->st.cap) continue;
+    }
+    HIP_TRY(c, launch_store_counters(c->st.ctr, h, c->stream), "counters");
     if (!c->allow_regrow) {
       c->have_state = false;  // the chain stopped part way
       return fail(c, SWCS_E_CAPACITY, "state exceeds the fixed capacity (regrowth disabled)");
     }
     // Grow so that the stopped gate (and a few more) fit, then resume (a star
     // gate appends up to two entries per alive one).
-    const u64 grow = (kind && kind[h.stop_gate]) ? 2 * h.alive : h.alive;
+    const u64 grow = star_stop ? 2 * h.alive : h.alive;
     const u64 need = h.n + std::min<u64>(grow, c->sector > h.n ? c->sector - h.n : 0);
     u64 cap = next_pow2(std::max<u64>(2 * c->st.cap, 2 * need));
     u64 maxc = max_capacity(c);
@@ -577,10 +636,6 @@ int run_chain(swcs_ctx* c, const int32_t* op_idx, const double* cs, const double
     if (cap < need) return fail(c, SWCS_E_CAPACITY, "state exceeds the maximum capacity");
     int r = state_reserve(c, cap, h.n);
     if (r) return r;
-    g0 = (int64_t)h.stop_gate;
-    h.flags &= ~kFlagStopped;
-    h.stop_gate = 0;
-    HIP_TRY(c, launch_store_counters(c->st.ctr, h, c->stream), "counters");
     // Checkpoint of the gate where the chain resumes was skipped if it lies
     // on a segment boundary: the loop above re-enqueues it.
   }
@@ -736,6 +791,14 @@ int swcs_set_sigma_method(swcs_ctx* c, int method) {
       method != SWCS_SIGMA_PAIRS)
     return fail(c, SWCS_E_INVALID, "unknown sigma method");
   c->sigma_method = method;
+  return SWCS_OK;
+}
+
+int swcs_set_pool_method(swcs_ctx* c, int method) {
+  if (!c) return SWCS_E_INVALID;
+  if (method != SWCS_POOL_AUTO && method != SWCS_POOL_TABLE && method != SWCS_POOL_JOIN)
+    return fail(c, SWCS_E_INVALID, "unknown pool method");
+  c->pool_method = method;
   return SWCS_OK;
 }
 
@@ -1561,6 +1624,82 @@ int swcs_pool_gradients_device(swcs_ctx* c, const int32_t* d_subset, int64_t n_s
   return SWCS_OK;
 }
 
+// Bits that hold every value in [0, v].
+static int bits_for(u64 v) {
+  int b = 1;
+  while (b < 64 && (v >> b) != 0) ++b;
+  return b;
+}
+
+// Full-pool (or large-subset) gradients by sort and join (k_join.hip).
+// Returns 1 when the join does not apply (method, memory, record word) or a
+// join step overflowed its LDS table and AUTO may fall back to the table,
+// else an SWCS status; on SWCS_OK the scaled gradients are in gbuf.
+static int join_gradients(swcs_ctx* c, const Counters& h, const unsigned char* d_sel, const int* d_subset,
+                          int64_t count, const double* norm2) {
+  if (c->pool_method == SWCS_POOL_TABLE) return 1;
+  if (c->pool_method == SWCS_POOL_AUTO && c->table_budget > 0) return 1;
+  const bool forced = c->pool_method == SWCS_POOL_JOIN;
+  const u64 n = h.n, C = (u64)c->exc.total;
+  const u64 R = h.alive * (C + 1);
+  const int bj = bits_for(C), bd = bits_for(n > 0 ? n - 1 : 0);
+  // hash bits: 8, 16 or 24, for about 256 records per bucket
+  int kb = 8;
+  while (kb < 24 && (R >> kb) > 256) kb += 8;
+  if (kb + bj + bd > 64) {
+    if (forced) return fail(c, SWCS_E_CAPACITY, "join records do not fit 64 bits");
+    return 1;
+  }
+  const u64 scr = radix_sort_scratch_elems(R);
+  const double need = 16.0 * (double)R + 8.0 * (double)scr;
+  const double have = (double)(avail_bytes(c) + c->hp_key.bytes + c->hp_tk.bytes + c->sort_scratch.bytes);
+  if (need > 0.5 * have) {
+    if (forced) return fail(c, SWCS_E_CAPACITY, "join records exceed half of the free device memory");
+    return 1;
+  }
+  HIP_TRY(c, c->hp_key.ensure(R * 8), "alloc join records");
+  HIP_TRY(c, c->hp_tk.ensure(R * 8), "alloc join records");
+  HIP_TRY(c, c->sort_scratch.ensure(scr * 8), "alloc sort scratch");
+  const int rgrid = (int)std::min<u64>((R + kJoinRunHost - 1) / kJoinRunHost, (u64)c->num_cu * 8);
+  HIP_TRY(c, c->partial2.ensure((size_t)std::max(rgrid, 1) * 8), "alloc partials");
+  u64* cursor = c->scalars.as<u64>() + 32;
+  HIP_TRY(c, launch_fill_u32(cursor, 0u, 2, c->stream), "zero cursor");
+  u64* recs = c->hp_key.as<u64>();
+  TIMED(c, SWCS_K_JOIN_EMIT, launch_join_emit(c->st, c->exc, n, recs, R, cursor, kb, bj, sigma_grid(c, n), c->stream),
+        "join emit");
+  u64* sorted = recs;
+  TIMED(c, SWCS_K_JOIN_SORT, radix_sort_keys(recs, c->hp_tk.as<u64>(), R, kb, c->sort_scratch.as<u64>(), scr,
+                                             c->stream, &sorted), "join sort");
+  HIP_TRY(c, launch_fill_u32(c->gacc.p, 0u, (u64)c->K_pool * 2, c->stream), "zero g");
+  double* ins = c->partial2.as<double>();
+  TIMED(c, SWCS_K_JOIN_REDUCE, launch_join_reduce(c->st, sorted, R, cursor, kb, bj, n, ints_view(c), c->exc, c->opmap.as<int>(),
+                                                  c->npairs, d_sel, c->gacc.as<double>(), ins, rgrid, c->stream),
+        "join reduce");
+  HIP_TRY(c, launch_reduce_partials(ins, rgrid, rgrid, 1, c->scalars.as<double>() + 24, c->stream), "count");
+  double distinct = 0.0;
+  HIP_TRY(c, hipMemcpyAsync(&distinct, c->scalars.as<double>() + 24, 8, hipMemcpyDeviceToHost, c->stream), "copy");
+  HIP_TRY(c, launch_gather_scaled(c->gacc.as<double>(), d_subset, count, norm2, c->gbuf.as<double>(), c->stream),
+          "gather");
+  hipError_t e;
+  Counters h2 = read_counters(c, &e);  // synchronizes
+  if (e != hipSuccess) return hip_fail(c, e, "read counters");
+  if (h2.flags & kFlagOverflow) {
+    h2.flags &= ~kFlagOverflow;
+    HIP_TRY(c, launch_store_counters(c->st.ctr, h2, c->stream), "counters");
+    c->hc = h2;
+    if (forced) return fail(c, SWCS_E_DEVICE, "join group overflowed its LDS table");
+    return 1;
+  }
+  c->ext_count = distinct;
+  c->ext_alive = (double)h.alive;
+  c->ps_keys = distinct;
+  c->ps_slots = 0;
+  c->ps_batches = 1;
+  c->ps_passes = 1;
+  c->ps_screened = 0;
+  return SWCS_OK;
+}
+
 int swcs_pool_gradients(swcs_ctx* c, const int32_t* subset, int64_t n_subset, double* g_out) {
   if (!c) return SWCS_E_INVALID;
   if (!g_out) return fail(c, SWCS_E_INVALID, "null g_out");
@@ -1602,6 +1741,13 @@ int swcs_pool_gradients(swcs_ctx* c, const int32_t* subset, int64_t n_subset, do
     r = mark_subset(c, d_subset, n_subset);
     if (r) return r;
     d_sel = c->selected.as<unsigned char>();
+  }
+  r = join_gradients(c, h, d_sel, d_subset, count, norm2);
+  if (r <= 0) {
+    if (r) return r;
+    HIP_TRY(c, hipMemcpyAsync(g_out, c->gbuf.p, (size_t)count * 8, hipMemcpyDeviceToHost, c->stream), "copy g");
+    HIP_TRY(c, hipStreamSynchronize(c->stream), "sync");
+    return SWCS_OK;
   }
   // External-space table.  At most alive * (C + 1) distinct keys (and never
   // more than the sector) can occur, but states built by gate chains overlap
@@ -1792,6 +1938,24 @@ int swcs_gate_active(swcs_ctx* c, int64_t* n_act, int64_t M) {
   return SWCS_OK;
 }
 
+int swcs_compact(swcs_ctx* c, int64_t* stored) {
+  if (!c) return SWCS_E_INVALID;
+  if (!c->have_state) return fail(c, SWCS_E_STATE, "no current state");
+  HIP_TRY(c, hipSetDevice(c->device), "hipSetDevice");
+  hipError_t e;
+  Counters h = get_counters(c, &e);
+  if (e != hipSuccess) return hip_fail(c, e, "read counters");
+  if (h.alive < h.n) {
+    int r = state_compact(c, &h);
+    if (r) return r;
+    r = build_filter(c, h.n, h.alive);
+    if (r) return r;
+    c->ansatz_valid = false;  // the checkpoints refer to the old positions
+  }
+  if (stored) *stored = (int64_t)h.n;
+  return SWCS_OK;
+}
+
 int swcs_state_counts(swcs_ctx* c, int64_t* stored, int64_t* alive) {
   if (!c) return SWCS_E_INVALID;
   if (!c->have_state) return fail(c, SWCS_E_STATE, "no current state");
@@ -1855,7 +2019,7 @@ int swcs_occupations(swcs_ctx* c, double* n_out) {
 
 int swcs_timer_start(swcs_ctx* c, int kernel_id) {
   if (!c) return SWCS_E_INVALID;
-  if (kernel_id < SWCS_K_CHAIN_LDS || kernel_id > SWCS_K_SELECT)
+  if (kernel_id < SWCS_K_CHAIN_LDS || kernel_id > SWCS_K_JOIN_REDUCE)
     return fail(c, SWCS_E_INVALID, "unknown kernel id");
   c->timer_kernel = kernel_id;
   c->ev_used = 0;

@@ -151,6 +151,7 @@ struct Counters {
   unsigned int ticket;
   unsigned int flags;
   u64 stop_gate;
+  u64 n_prev;  // stored count before the last multi-block gate (its appends are [n_prev, n))
 };
 
 // kFlagOverflow: an append or table insert found no room (a bug guard: the
@@ -266,8 +267,17 @@ constexpr int kLdsCap = 4096;
 // tile sizes (a tile's appended keys / logged pairs are staged in LDS).
 constexpr int kDiagLanes = 8;  // lanes per determinant in k_diag
 constexpr int kGateThreads = 1024;
-constexpr int kGateItems = 2;
-constexpr int kGateTile = kGateThreads * kGateItems;
+constexpr int kGateItems = 2;                              // listed entries per thread and round
+constexpr int kGateTile = kGateThreads * kGateItems;       // listed entries per round
+// Keys per thread in the gate's scan: wide tiles for state arrays of at least
+// kGateWideCap entries, narrow ones below (more blocks for small states).
+constexpr int kGateScanWide = 16;
+constexpr int kGateScanNarrow = 2;
+constexpr u64 kGateWideCap = 1ULL << 21;
+// entries per tile of the gate kernel for a state array of capacity cap
+__host__ __device__ inline int gate_scan_tile(u64 cap) {
+  return kGateThreads * (cap >= kGateWideCap ? kGateScanWide : kGateScanNarrow);
+}
 constexpr int kReplayTile = 2048;
 
 // ---------------------------------------------------------------- host side
@@ -366,6 +376,15 @@ hipError_t launch_mu_init(const DeviceState& st, const double* sigma, u64 n, con
                           double* mu, hipStream_t stream);
 hipError_t launch_reduce_partials(const double* partial, int count, int stride, int nvec,
                                   double* out, hipStream_t stream);
+// Full-pool gradients by sort and join (k_join.hip); kJoinRunHost records
+// per step of the join kernel.
+constexpr u64 kJoinRunHost = 2048;
+hipError_t launch_join_emit(const DeviceState& st, const ExcSpace& E, u64 n, u64* recs, u64 cap_recs,
+                            u64* cursor, int kb, int bj, int grid, hipStream_t stream);
+hipError_t launch_join_reduce(const DeviceState& st, const u64* recs, u64 R, const u64* cursor, int kb, int bj,
+                              u64 n, const Ints& I, const ExcSpace& E, const int* optab, int npairs,
+                              const unsigned char* selected, double* gacc, double* inserted, int grid,
+                              hipStream_t stream);
 hipError_t launch_sigma_push(const DeviceState& st, const Ints& I, const ExcSpace& E, u64 n,
                              AccSlot* tab, u64 tmask, int nbatch, int batch, double* inserted,
                              int grid, hipStream_t stream);

@@ -27,8 +27,10 @@ SWCS_E_DEVICE = -5
 SWCS_E_UNSUPPORTED = -6
 KERNELS = {"chain_lds": 1, "gate": 2, "sigma_proj": 3, "sigma_push": 4, "pool_contract": 5,
            "adjoint_lds": 6, "gate_replay": 7, "adjoint_rec": 8, "sigma_push_into": 9,
-           "contract_ops": 10, "holepair": 11, "adjoint_replay_lds": 12, "select": 13}
+           "contract_ops": 10, "holepair": 11, "adjoint_replay_lds": 12, "select": 13,
+           "join_emit": 14, "join_sort": 15, "join_reduce": 16}
 SIGMA_METHODS = {"auto": 0, "enumerate": 1, "hole_pairs": 2, "pairs": 3}
+POOL_METHODS = {"auto": 0, "table": 1, "join": 2}
 _NAMES = {0: "SWCS_OK", -1: "SWCS_E_INVALID", -2: "SWCS_E_STATE", -3: "SWCS_E_OOM",
           -4: "SWCS_E_CAPACITY", -5: "SWCS_E_DEVICE", -6: "SWCS_E_UNSUPPORTED"}
 
@@ -61,6 +63,7 @@ SIGNATURES = {
     "swcs_set_allocator": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "swcs_set_table_budget": (ctypes.c_int, [_vp, _i64]),
     "swcs_set_sigma_method": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "swcs_set_pool_method": (ctypes.c_int, [_vp, ctypes.c_int]),
     "swcs_set_integrals": (ctypes.c_int, [_vp, _dp, _dp, ctypes.c_double]),
     "swcs_set_reference": (ctypes.c_int, [_vp, ctypes.c_uint64]),
     "swcs_set_pool": (ctypes.c_int, [_vp, _i32p, _i64]),
@@ -79,6 +82,7 @@ SIGNATURES = {
     "swcs_param_gradients": (ctypes.c_int, [_vp, _dp, _dp]),
     "swcs_gate_sizes": (ctypes.c_int, [_vp, _i64p, _i64]),
     "swcs_state_counts": (ctypes.c_int, [_vp, _i64p, _i64p]),
+    "swcs_compact": (ctypes.c_int, [_vp, _i64p]),
     "swcs_gate_active": (ctypes.c_int, [_vp, _i64p, _i64]),
     "swcs_pool_stats": (ctypes.c_int, [_vp, _dp, _i64p, ctypes.POINTER(ctypes.c_int32),
                                        ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
@@ -263,6 +267,10 @@ class Context:
         """'auto', 'enumerate' or 'hole_pairs' (how sigma_P is formed)."""
         self._check(self._lib.swcs_set_sigma_method(self._h, SIGMA_METHODS[method]))
 
+    def set_pool_method(self, method: str):
+        """'auto', 'table' or 'join' (how whole-pool gradients are formed)."""
+        self._check(self._lib.swcs_set_pool_method(self._h, POOL_METHODS[method]))
+
     def set_integrals(self, h, eri, e_core: float = 0.0):
         h = np.ascontiguousarray(h, dtype=np.float64)
         eri = np.ascontiguousarray(eri, dtype=np.float64)
@@ -402,6 +410,13 @@ class Context:
         st, al = ctypes.c_int64(), ctypes.c_int64()
         self._check(self._lib.swcs_state_counts(self._h, ctypes.byref(st), ctypes.byref(al)))
         return int(st.value), int(al.value)
+
+    def compact(self):
+        """Drop the pruned entries from storage (include/swcs.h: swcs_compact);
+        returns the stored count afterwards."""
+        st = ctypes.c_int64()
+        self._check(self._lib.swcs_compact(self._h, ctypes.byref(st)))
+        return int(st.value)
 
     def pool_stats(self):
         """Sizing of the last pool-gradient pass (include/swcs.h: swcs_pool_stats)."""

@@ -157,6 +157,32 @@ def test_spreading_16so_full_parity(swcs, spread):
     run_full(swcs, spread)
 
 
+@pytest.mark.parametrize("name", ["c1", "c2", "spread"])
+def test_pool_methods_join_and_table(swcs, c1, c2, spread, name):
+    """Whole-pool gradients by the sort-and-join path and by the accumulation
+    table, each against the oracle: the full pool, a subset above half the
+    pool (operator flags), and the same distinct-key count from both."""
+    case = {"c1": c1, "c2": c2, "spread": spread}[name]
+    ctx = make_ctx(swcs, case)
+    ctx.apply_ansatz(case.ops, case.theta, case.eps)
+    g_ref = case.orc.pool_gradients(case.st, case.pool)
+    K = len(case.pool)
+    sub = np.sort(np.random.default_rng(14).choice(K, (3 * K) // 5, replace=False)).astype(np.int32)
+    keys = {}
+    for method in ("table", "join"):
+        _say(f"[parity] {name}: pool gradients by {method}")
+        ctx.set_pool_method(method)
+        g = ctx.pool_gradients()
+        assert np.abs(g - g_ref).max() < TOL, method
+        st = ctx.pool_stats()
+        keys[method] = st["keys"]
+        assert (st["table_slots"] == 0) == (method == "join") and not st["screened"]
+        gs = ctx.pool_gradients(sub)
+        assert np.abs(gs - g_ref[sub]).max() < TOL, method
+    assert keys["table"] == keys["join"]
+    ctx.close()
+
+
 def test_c2_subset_paths(swcs, c2):
     """Screened pool gradients on both restricted paths: a subset smaller than
     the connection count is walked operator-major, a larger one (still under
@@ -702,6 +728,101 @@ def test_synthetic_state_gates_bit_exact(swcs):
             k_gpu, a_gpu = ctx.get_state()
             assert np.array_equal(k_gpu, k_ref)
             assert np.array_equal(a_gpu, a_ref)
+    ctx.close()
+
+
+def test_compaction_keeps_state_and_results(swcs):
+    """Pruned entries are reclaimed without changing the state: automatically
+    in a chain without checkpoints once they outnumber the alive ones, and on
+    request (swcs_compact).  Keys and amplitudes stay bit-exact against the
+    oracle, energy and pool gradients within the bar, later gates too; the
+    record of an ansatz is dropped by an explicit rebuild."""
+    c = CONFIGS["c2"]
+    h, eri = make_integrals(c.n, c.rank, c.seed_int)
+    pool = enumerate_pool(c.n)
+    na = c.n_elec // 2
+    rng = np.random.default_rng(31)
+    singles = np.flatnonzero(pool[:, 2] < 0)
+    doubles = np.flatnonzero(pool[:, 2] >= 0)
+    ops = np.concatenate([rng.choice(doubles, 6), rng.choice(singles, 2)]).astype(np.int32)
+    theta = rng.uniform(-0.4, 0.4, len(ops))
+    orc = oracle.Oracle(c.n, na, na, h, eri)
+    ctx = swcs.make_context(c.n, na, na, h, eri, pool, reference_key(c.n_elec))
+    # 20,000 entries with |c| log-uniform in [1e-8, 1e-2] run on the HBM path;
+    # eps = 1e-3 prunes about five sixths of them after the first gate (the
+    # chain stores 21,911 keys, 5,081 of them alive at the end)
+    keys, amps = draw_synthetic_state(c.n, na, na, 20_000, 4006)
+    st0 = oracle.OracleState.from_arrays(keys, amps)
+
+    def oracle_chain(st, ops_, theta_, eps):
+        for k, t in zip(ops_, theta_):
+            st, _ = oracle.Oracle.apply_gate_truncate(st, pool[k], math.cos(t), math.sin(t), eps)
+        return st
+
+    _say("[parity] compaction inside a chain (c2 problem, 20,000 synthetic entries, eps=1e-3)")
+    ctx.set_state(keys, amps)
+    ctx.apply_gates(ops, theta, 1e-3)
+    stored, alive = ctx.state_counts()
+    cur = oracle_chain(st0, ops, theta, 1e-3)
+    k_ref, a_ref = cur.export()
+    assert alive == len(k_ref)
+    assert stored == alive, (stored, alive)  # rebuilt at the end of the chain
+    k_gpu, a_gpu = ctx.get_state()
+    assert np.array_equal(k_gpu, k_ref) and np.array_equal(a_gpu, a_ref)
+    assert abs(ctx.energy()[0] - orc.energy(cur)[0]) < TOL
+    # later gates run on the rebuilt index
+    more = rng.choice(doubles, 4).astype(np.int32)
+    th2 = rng.uniform(-0.4, 0.4, len(more))
+    ctx.apply_gates(more, th2, 1e-3)
+    cur = oracle_chain(cur, more, th2, 1e-3)
+    k_ref, a_ref = cur.export()
+    k_gpu, a_gpu = ctx.get_state()
+    assert np.array_equal(k_gpu, k_ref) and np.array_equal(a_gpu, a_ref)
+
+    _say("[parity] explicit compaction (few pruned entries, below the automatic threshold)")
+    ctx.set_state(keys, amps)
+    ctx.apply_gates(ops, theta, 1e-7)
+    stored, alive = ctx.state_counts()
+    assert alive < stored < 2 * alive
+    k0, a0 = ctx.get_state()
+    E0 = ctx.energy()[0]
+    sub = np.sort(rng.choice(len(pool), 400, replace=False)).astype(np.int32)
+    g0 = ctx.pool_gradients(sub)
+    assert ctx.compact() == alive
+    assert ctx.state_counts() == (alive, alive)
+    k1, a1 = ctx.get_state()
+    assert np.array_equal(k0, k1) and np.array_equal(a0, a1)
+    assert abs(ctx.energy()[0] - E0) < 1e-12
+    assert np.max(np.abs(ctx.pool_gradients(sub) - g0)) < 1e-12
+    cur = oracle_chain(st0, ops, theta, 1e-7)
+    g_ref = orc.pool_gradients(cur, pool, sub)
+    assert np.max(np.abs(g0 - g_ref)) < TOL
+    ctx.apply_gates(more, th2, 1e-7)
+    cur = oracle_chain(cur, more, th2, 1e-7)
+    k_ref, a_ref = cur.export()
+    k_gpu, a_gpu = ctx.get_state()
+    assert np.array_equal(k_gpu, k_ref) and np.array_equal(a_gpu, a_ref)
+
+    _say("[parity] explicit compaction keeps or drops the ansatz record")
+    # nothing pruned: nothing moves and the record stays
+    ctx.apply_ansatz(ops, theta, 1e-4)
+    s, a = ctx.state_counts()
+    assert s == a
+    assert ctx.compact() == a
+    ctx.param_gradients(len(ops))
+    # a double on the reference at theta = pi/2 moves all of its weight: the
+    # reference is pruned and stays stored until the rebuild, which drops the
+    # record
+    ref = reference_key(c.n_elec)
+    rows = pool.astype(np.int64)
+    on_ref = [k for k in doubles
+              if all((ref >> int(x)) & 1 for x in rows[k, 2:]) and not any((ref >> int(x)) & 1 for x in rows[k, :2])]
+    ctx.apply_ansatz(np.array(on_ref[:1], dtype=np.int32), np.array([math.pi / 2]), 1e-4)
+    assert ctx.state_counts() == (2, 1)
+    assert ctx.compact() == 1
+    with pytest.raises(swcs.SwcsError) as err:
+        ctx.param_gradients(1)
+    assert err.value.code == swcs.SWCS_E_STATE
     ctx.close()
 
 
