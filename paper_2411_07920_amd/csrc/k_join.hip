@@ -11,10 +11,12 @@
 // by X (plus H_{D D} psi(D) when X = D is stored).  So one record per pair
 // carries everything:
 //   emit   -- every alive D writes one 64-bit record per connection X and
-//             one for itself: (d << (kb + bj)) | (j << kb) | bucket(X), where
-//             d is D's storage index, j the connection's ordinal in D's
-//             enumeration (j = C for D itself) and bucket(X) the low kb bits
-//             of mix64(X); D's records are one coalesced run;
+//             one for itself: (d << (kb + bj)) | (f << kb) | bucket(X), where
+//             d is D's storage index, f = (class, hole set, particle set) of
+//             the connection as bit fields (class 7 for D itself) and
+//             bucket(X) the low kb bits of mix64(X); D's records are one
+//             coalesced run, and (D, psi(D)) goes to a 16-byte table by d,
+//             so the join reaches both with one load per record;
 //   sort   -- a stable LSD radix sort on the kb bucket bits only, so every
 //             record of one X lands in one contiguous bucket;
 //   join   -- a block takes a run of whole buckets, decodes each record
@@ -23,6 +25,8 @@
 // The device-wide traffic is streaming (records written once, sorted in
 // kb / 8 passes, read twice from L2-resident runs), where the table path
 // pays one random read-modify-write per pair in HBM.
+#include <algorithm>
+
 #include "conn_ops.h"
 
 namespace swcs {
@@ -31,74 +35,22 @@ constexpr int kJoinEmitBlock = 256;
 constexpr int kJoinBlock = 512;
 constexpr int kJoinRun = (int)kJoinRunHost;  // records per block step before bucket alignment
 constexpr int kJoinSlots = 4096;  // LDS table: keys and sums, 64 KB (two blocks per CU)
+constexpr int kJoinCache = 4;     // records per thread and step whose gradient term stays in registers
 
-// Position of the r-th (from 0) set bit of m; m has more than r set bits.
-__device__ inline int select_bit(u64 m, int r) {
-  for (int i = 0; i < r; ++i) m &= m - 1ULL;
-  return __ffsll((long long)m) - 1;
-}
+// Record layout: kb bucket bits, then the connection fields (class in 3
+// bits, hole-set index in bh bits, particle-set index in bp bits), then the
+// storage index.
+struct JoinFmt {
+  int kb, bh, bp;
+  __host__ __device__ int bj() const { return 3 + bh + bp; }
+};
+constexpr unsigned kJoinSelf = 7;  // class field of the record of D itself
 
-// (x, y), x < y, of the pair with triangular index t = y (y - 1) / 2 + x,
-// the order of the pair tables of the connection enumeration.
-__device__ inline void tri_pair(int t, int* x, int* y) {
-  int yy = (int)((1.0 + sqrt(1.0 + 8.0 * (double)t)) * 0.5);
-  while (yy * (yy - 1) / 2 > t) --yy;
-  while ((yy + 1) * yy / 2 <= t) ++yy;
-  *y = yy;
-  *x = t - yy * (yy - 1) / 2;
-}
-
-// Connection j of D in the order of for_each_connection: class (alpha
-// single, beta single, alpha-alpha, beta-beta, alpha-beta double), then hole
-// set, then particle set.  Returns X and the holes h0 <= h1, particles
-// p0 <= p1 (equal for singles), nh = 1 or 2.
-__device__ inline u64 conn_decode(const ExcSpace& E, u64 D, long long j, int* nh, int* h0, int* h1, int* p0,
-                                  int* p1) {
-  const u64 amask = 0x5555555555555555ULL, bmask = 0xAAAAAAAAAAAAAAAAULL;
-  const u64 full = (E.n >= 32) ? ~0ULL : ((1ULL << (2 * E.n)) - 1ULL);
-  const u64 occ_a = D & amask, occ_b = D & bmask;
-  const u64 vir_a = ~D & amask & full, vir_b = ~D & bmask & full;
-  const long long sz[5] = {E.s_a, E.s_b, E.d_aa, E.d_bb, E.d_ab};
-  const int nb = E.nb, va = E.va, vb = E.vb;
-  const int npar[5] = {va, vb, va * (va - 1) / 2, vb * (vb - 1) / 2, va * vb};
-  int c = 0;
-  while (c < 4 && j >= sz[c]) {
-    j -= sz[c];
-    ++c;
-  }
-  const int hi = (int)(j / npar[c]);
-  const int pi = (int)(j - (long long)hi * npar[c]);
-  if (c < 2) {
-    *nh = 1;
-    *h0 = *h1 = select_bit(c == 0 ? occ_a : occ_b, hi);
-    *p0 = *p1 = select_bit(c == 0 ? vir_a : vir_b, pi);
-  } else if (c < 4) {
-    *nh = 2;
-    const u64 o = c == 2 ? occ_a : occ_b, v = c == 2 ? vir_a : vir_b;
-    int x, y;
-    tri_pair(hi, &x, &y);
-    *h0 = select_bit(o, x);
-    *h1 = select_bit(o, y);
-    tri_pair(pi, &x, &y);
-    *p0 = select_bit(v, x);
-    *p1 = select_bit(v, y);
-  } else {
-    *nh = 2;
-    const int ha = select_bit(occ_a, hi / nb), hb = select_bit(occ_b, hi - (hi / nb) * nb);
-    const int pa = select_bit(vir_a, pi / vb), pb = select_bit(vir_b, pi - (pi / vb) * vb);
-    *h0 = min(ha, hb);
-    *h1 = max(ha, hb);
-    *p0 = min(pa, pb);
-    *p1 = max(pa, pb);
-  }
-  const u64 hm = (1ULL << *h0) | (1ULL << *h1), pm = (1ULL << *p0) | (1ULL << *p1);
-  return D ^ hm ^ pm;
-}
-
-// Calls f(X, j) for every connection of D assigned to this lane, j its
-// ordinal (class offsets + hole set * particle sets + particle set).
+// Calls f(X, ordinal, field) for every connection of D assigned to this
+// lane: ordinal = class offset + hole set * particle sets + particle set (the
+// order of for_each_connection), field = the record's connection fields.
 template <class F>
-__device__ inline void for_each_connection_ord(const ConnTables& T, u64 D, F&& f) {
+__device__ inline void for_each_connection_fields(const ConnTables& T, u64 D, const JoinFmt& fm, F&& f) {
   long long off = 0;
   for (int c = 0; c < 5; ++c) {
     const int nh = T.nh[c], np = T.np[c];
@@ -106,9 +58,10 @@ __device__ inline void for_each_connection_ord(const ConnTables& T, u64 D, F&& f
     const int hb = T.hbeg[c], pb = T.pbeg[c];
     int hi = (int)threadIdx.x / np;
     int pi = (int)threadIdx.x - hi * np;
+    const u64 cf = (u64)c << (fm.bh + fm.bp);
     while (hi < nh) {
       const u64 X = D ^ T.hmask[hb + hi] ^ T.pmask[pb + pi];
-      f(X, off + (long long)hi * np + pi);
+      f(X, off + (long long)hi * np + pi, cf | ((u64)hi << fm.bp) | (u64)pi);
       pi += blockDim.x;
       while (pi >= np) {
         pi -= np;
@@ -119,12 +72,75 @@ __device__ inline void for_each_connection_ord(const ConnTables& T, u64 D, F&& f
   }
 }
 
+// Position of the r-th (from 0) set bit of m (m has more than r set bits),
+// by halving: six popcounts instead of a walk over the bits below it.
+__device__ inline int select_bit(u64 m, unsigned r) {
+  int pos = 0;
+#pragma unroll
+  for (int w = 32; w >= 1; w >>= 1) {
+    const u64 low = m & ((1ULL << w) - 1ULL);
+    const unsigned c = (unsigned)__popcll(low);
+    if (r >= c) {
+      r -= c;
+      m >>= w;
+      pos += w;
+    } else {
+      m = low;
+    }
+  }
+  return pos;
+}
+
+// Connection of a record: holes h0 <= h1 and particles p0 <= p1
+// (spin-orbitals; equal for singles) from the class and set indices: the
+// r-th occupied or virtual spin-orbital of one spin is the r-th set bit of
+// D's (or its complement's) bits of that spin; pairs of one spin come from
+// the triangular pair tables (px, py) of the enumeration.
+__device__ inline u64 join_decode(const ExcSpace& E, u64 D, unsigned c, unsigned hi, unsigned pi,
+                                  const unsigned char* px, const unsigned char* py, int* nh, int* h0, int* h1,
+                                  int* p0, int* p1) {
+  const u64 amask = 0x5555555555555555ULL, bmask = 0xAAAAAAAAAAAAAAAAULL;
+  const u64 full = (E.n >= 32) ? ~0ULL : ((1ULL << (2 * E.n)) - 1ULL);
+  const u64 oa = D & amask, ob = D & bmask, xa = ~D & amask & full, xb = ~D & bmask & full;
+  if (c < 2) {
+    *nh = 1;
+    *h0 = *h1 = select_bit(c == 0 ? oa : ob, hi);
+    *p0 = *p1 = select_bit(c == 0 ? xa : xb, pi);
+  } else if (c < 4) {
+    *nh = 2;
+    const u64 o = c == 2 ? oa : ob, v = c == 2 ? xa : xb;
+    *h0 = select_bit(o, px[hi]);
+    *h1 = select_bit(o, py[hi]);
+    *p0 = select_bit(v, px[pi]);
+    *p1 = select_bit(v, py[pi]);
+  } else {
+    *nh = 2;
+    const unsigned nb = (unsigned)E.nb, vb = (unsigned)E.vb;
+    const unsigned i = hi / nb, a = pi / vb;
+    const int ha = select_bit(oa, i), hb = select_bit(ob, hi - i * nb);
+    const int pa = select_bit(xa, a), pb = select_bit(xb, pi - a * vb);
+    *h0 = min(ha, hb);
+    *h1 = max(ha, hb);
+    *p0 = min(pa, pb);
+    *p1 = max(pa, pb);
+  }
+  const u64 hm = (1ULL << *h0) | (1ULL << *h1), pm = (1ULL << *p0) | (1ULL << *p1);
+  return D ^ hm ^ pm;
+}
+
+// Source entry of the records: key and amplitude side by side.
+struct JoinSrc {
+  u64 key;
+  double psi;
+};
+
 // One run of C + 1 records per alive entry, at a position taken from
-// *cursor; runs past cap_recs are not written and raise kFlagOverflow.
+// *cursor, and (D, psi(D)) at src[d]; runs past cap_recs are not written
+// and raise kFlagOverflow.
 __global__ void __launch_bounds__(kJoinEmitBlock)
 k_join_emit(const u64* __restrict__ keys, const double* __restrict__ amps, ExcSpace E, u64 n,
-            u64* __restrict__ recs, u64 cap_recs, u64* __restrict__ cursor, int kb, int bj,
-            unsigned* __restrict__ flags) {
+            u64* __restrict__ recs, u64 cap_recs, u64* __restrict__ cursor, JoinFmt fm,
+            JoinSrc* __restrict__ src, unsigned* __restrict__ flags) {
   __shared__ SigShared S;
   __shared__ ConnTables T;
   extern __shared__ __align__(16) unsigned char conn_dyn[];
@@ -132,16 +148,18 @@ k_join_emit(const u64* __restrict__ keys, const double* __restrict__ amps, ExcSp
   build_pair_table(S);
   if (threadIdx.x == 0) attach_conn_tables(T, conn_dyn, E);
   const u64 C = (u64)E.total;
-  const u64 bmask = (1ULL << kb) - 1ULL;
-  const int sd = kb + bj;
+  const u64 bmask = (1ULL << fm.kb) - 1ULL;
+  const int sd = fm.kb + fm.bj();
   for (u64 d = blockIdx.x; d < n; d += gridDim.x) {
-    if (is_dead(amps[d])) continue;
+    const double psi = amps[d];
+    if (is_dead(psi)) continue;
     const u64 D = keys[d];
     __syncthreads();
     build_lists_shared(D, E.n, S);
     if (threadIdx.x == 0) s_base = atomicAdd(cursor, C + 1);
     __syncthreads();
     build_conn_tables(S, E, T);
+    if (threadIdx.x == 0) src[d] = JoinSrc{D, psi};
     __syncthreads();
     const u64 base = s_base;
     if (base + C + 1 > cap_recs) {
@@ -149,10 +167,11 @@ k_join_emit(const u64* __restrict__ keys, const double* __restrict__ amps, ExcSp
       continue;
     }
     const u64 hd = d << sd;
-    for_each_connection_ord(T, D, [&](u64 X, long long j) {
-      recs[base + (u64)j] = hd | ((u64)j << kb) | (mix64(X) & bmask);
+    for_each_connection_fields(T, D, fm, [&](u64 X, long long j, u64 field) {
+      recs[base + (u64)j] = hd | (field << fm.kb) | (mix64(X) & bmask);
     });
-    if (threadIdx.x == 0) recs[base + C] = hd | (C << kb) | (mix64(D) & bmask);
+    if (threadIdx.x == 0)
+      recs[base + C] = hd | ((u64)kJoinSelf << (fm.kb + fm.bh + fm.bp)) | (mix64(D) & bmask);
   }
 }
 
@@ -204,16 +223,83 @@ __device__ inline int join_slot(u64* tk, u64 X, bool insert, double* inserted) {
   return -1;
 }
 
-// Record fields and the source entry.
+// Fields of a record.
 struct JoinRec {
   u64 d;
-  long long j;
+  unsigned c, hi, pi;
 };
-__device__ inline JoinRec join_rec(u64 r, int kb, int bj) {
+__device__ inline JoinRec join_rec(u64 r, const JoinFmt& fm) {
   JoinRec o;
-  o.j = (long long)((r >> kb) & ((1ULL << bj) - 1ULL));
-  o.d = r >> (kb + bj);
+  const u64 f = r >> fm.kb;
+  o.pi = (unsigned)(f & ((1ULL << fm.bp) - 1ULL));
+  o.hi = (unsigned)((f >> fm.bp) & ((1ULL << fm.bh) - 1ULL));
+  o.c = (unsigned)((f >> (fm.bp + fm.bh)) & 7ULL);
+  o.d = r >> (fm.kb + fm.bj());
   return o;
+}
+
+// Whether the fields name a connection of the enumeration (a record that
+// was never written cannot index outside the pair tables or the state).
+__device__ inline bool join_fields_valid(const ExcSpace& E, const JoinRec& r) {
+  const int na = E.na, nb = E.nb, va = E.va, vb = E.vb;
+  const unsigned nh[5] = {(unsigned)na, (unsigned)nb, (unsigned)(na * (na - 1) / 2), (unsigned)(nb * (nb - 1) / 2),
+                          (unsigned)(na * nb)};
+  const unsigned np[5] = {(unsigned)va, (unsigned)vb, (unsigned)(va * (va - 1) / 2), (unsigned)(vb * (vb - 1) / 2),
+                          (unsigned)(va * vb)};
+  return r.c < 5 && r.hi < nh[r.c] && r.pi < np[r.c];
+}
+
+// First pass over one record: sigma(X) += H_{X D} psi(D) (or H_{D D} psi(D)
+// for the record of D itself) in the LDS table; *s_bad is set when the table
+// is full.  With term, also the record's gradient term: *k the linking
+// operator (-1 for none, for an operator not selected and for D itself), *sl
+// the LDS slot of X and *w = psi(D) a_k(D).
+__device__ inline void join_record_sigma(u64 rec, const JoinFmt& fm, const JoinSrc* __restrict__ src,
+                                         const double* __restrict__ diag, u64 n, const Ints& I,
+                                         const ExcSpace& E, const int* __restrict__ optab, int npairs,
+                                         const unsigned char* __restrict__ selected, const unsigned char* px,
+                                         const unsigned char* py, u64* tk, double* tv, double* ins,
+                                         unsigned* s_bad, bool term, int* k, int* sl, double* w) {
+  *k = -1;
+  *sl = 0;
+  *w = 0.0;
+  const JoinRec r = join_rec(rec, fm);
+  if (r.d >= n) return;
+  const bool self = r.c == kJoinSelf;
+  if (!self && !join_fields_valid(E, r)) return;
+  const JoinSrc sd = src[r.d];
+  const u64 D = sd.key;
+  const double psi = sd.psi;
+  u64 X;
+  double v;
+  int kk = -1;
+  double a = 0.0;
+  if (self) {
+    X = D;
+    v = diag[r.d] * psi;
+  } else {
+    int nh, h0, h1, p0, p1;
+    X = join_decode(E, D, r.c, r.hi, r.pi, px, py, &nh, &h0, &h1, &p0, &p1);
+    v = connection_element(I, D, nh, h0, h1, p0, p1) * psi;
+    if (term) {
+      bool t_acts;
+      OpDesc op;
+      kk = linking_operator(optab, npairs, nh, h0, h1, p0, p1, &t_acts, &op);
+      if (kk >= 0 && selected && !selected[kk]) kk = -1;
+      if (kk >= 0) a = t_acts ? (double)phase_of_T(op, D) : -(double)phase_of_T(op, X);
+    }
+  }
+  const int s = join_slot(tk, X, true, ins);
+  if (s < 0) {
+    *s_bad = 1;
+    return;
+  }
+  atomicAdd(&tv[s], v);
+  if (kk >= 0) {
+    *k = kk;
+    *sl = s;
+    *w = psi * a;
+  }
 }
 
 // The join over sorted records: block steps of kJoinRun records, widened to
@@ -225,18 +311,18 @@ __device__ inline JoinRec join_rec(u64 r, int kb, int bj) {
 // determinants X of the block's steps (stored ones included), so their sum
 // is the size of the space sigma is formed on.
 __global__ void __launch_bounds__(kJoinBlock)
-k_join_reduce(const u64* __restrict__ recs, u64 R, const u64* __restrict__ cursor, int kb, int bj,
-              const u64* __restrict__ keys, const double* __restrict__ amps, const double* __restrict__ diag,
-              u64 n, Ints I, ExcSpace E, const int* __restrict__ optab, int npairs,
-              const unsigned char* __restrict__ selected, double* __restrict__ gacc,
+k_join_reduce(const u64* __restrict__ recs, u64 R, const u64* __restrict__ cursor, JoinFmt fm,
+              const JoinSrc* __restrict__ src, const double* __restrict__ diag, u64 n, Ints I, ExcSpace E,
+              const int* __restrict__ optab,
+              int npairs, const unsigned char* __restrict__ selected, double* __restrict__ gacc,
               unsigned* __restrict__ flags, double* __restrict__ inserted) {
   __shared__ u64 tk[kJoinSlots];
   __shared__ double tv[kJoinSlots];
+  __shared__ unsigned char px[kMaxPairs], py[kMaxPairs];
   __shared__ unsigned s_found, s_bad;
   __shared__ u64 s_pos;
-  __shared__ double red[kJoinBlock];
-  const u64 bmask = (1ULL << kb) - 1ULL;
-  const long long C = E.total;
+  __shared__ double red[kJoinBlock / 64];
+  const u64 bmask = (1ULL << fm.kb) - 1ULL;
   double ins = 0.0;
   // The emit wrote exactly R records only if the alive count it was sized
   // by is the number of alive entries; otherwise nothing is joined and the
@@ -247,6 +333,12 @@ k_join_reduce(const u64* __restrict__ recs, u64 R, const u64* __restrict__ curso
     if (threadIdx.x == 0) inserted[blockIdx.x] = 0.0;
     return;
   }
+  for (int s = threadIdx.x; s < kMaxPairs; s += kJoinBlock) {
+    int y = 1;
+    while ((y + 1) * y / 2 <= s) ++y;
+    py[s] = (unsigned char)y;
+    px[s] = (unsigned char)(s - y * (y - 1) / 2);
+  }
   for (int s = threadIdx.x; s < kJoinSlots; s += kJoinBlock) tk[s] = kEmptyKey;
   for (u64 p = (u64)blockIdx.x * kJoinRun; p < R; p += (u64)gridDim.x * kJoinRun) {
     const u64 lo = bucket_boundary(recs, R, p, bmask, &s_found, &s_pos);
@@ -255,37 +347,42 @@ k_join_reduce(const u64* __restrict__ recs, u64 R, const u64* __restrict__ curso
     for (int s = threadIdx.x; s < kJoinSlots; s += kJoinBlock) tv[s] = 0.0;
     if (threadIdx.x == 0) s_bad = 0;
     __syncthreads();
-    // sigma(X) over the step's records
-    for (u64 i = lo + threadIdx.x; i < hi; i += kJoinBlock) {
-      const JoinRec r = join_rec(recs[i], kb, bj);
-      if (r.d >= n || r.j > C) continue;
-      const u64 D = keys[r.d];
-      const double psi = amps[r.d];
-      u64 X;
-      double v;
-      if (r.j == C) {
-        X = D;
-        v = diag[r.d] * psi;
-      } else {
-        int nh, h0, h1, p0, p1;
-        X = conn_decode(E, D, r.j, &nh, &h0, &h1, &p0, &p1);
-        v = connection_element(I, D, nh, h0, h1, p0, p1) * psi;
-      }
-      const int sl = join_slot(tk, X, true, &ins);
-      if (sl < 0) s_bad = 1;
-      else atomicAdd(&tv[sl], v);
+    // sigma(X) over the step's records.  A record's gradient term is formed
+    // here too (operator, psi(D) a_k(D), LDS slot of X) and kept in
+    // registers for the thread's first kJoinCache records of the step, so
+    // that the second pass decodes only the records beyond them.
+    int ck[kJoinCache], csl[kJoinCache];
+    double cw[kJoinCache];
+#pragma unroll
+    for (int m = 0; m < kJoinCache; ++m) {
+      const u64 i = lo + threadIdx.x + (u64)m * kJoinBlock;
+      ck[m] = -1;
+      csl[m] = 0;
+      cw[m] = 0.0;
+      if (i < hi) join_record_sigma(recs[i], fm, src, diag, n, I, E, optab, npairs, selected, px, py, tk, tv, &ins,
+                                    &s_bad, true, &ck[m], &csl[m], &cw[m]);
+    }
+    for (u64 i = lo + threadIdx.x + (u64)kJoinCache * kJoinBlock; i < hi; i += kJoinBlock) {
+      int k, sl;
+      double w;
+      join_record_sigma(recs[i], fm, src, diag, n, I, E, optab, npairs, selected, px, py, tk, tv, &ins, &s_bad,
+                        false, &k, &sl, &w);
     }
     __syncthreads();
     if (s_bad) {
       if (threadIdx.x == 0) atomicOr(flags, kFlagOverflow);
     } else {
       // psi(D) a_k(D) sigma(X) for every pair record
-      for (u64 i = lo + threadIdx.x; i < hi; i += kJoinBlock) {
-        const JoinRec r = join_rec(recs[i], kb, bj);
-        if (r.d >= n || r.j >= C) continue;
-        const u64 D = keys[r.d];
+#pragma unroll
+      for (int m = 0; m < kJoinCache; ++m)
+        if (ck[m] >= 0) unsafeAtomicAdd(&gacc[ck[m]], cw[m] * tv[csl[m]]);
+      for (u64 i = lo + threadIdx.x + (u64)kJoinCache * kJoinBlock; i < hi; i += kJoinBlock) {
+        const JoinRec r = join_rec(recs[i], fm);
+        if (r.d >= n || r.c == kJoinSelf || !join_fields_valid(E, r)) continue;
+        const JoinSrc sd = src[r.d];
+        const u64 D = sd.key;
         int nh, h0, h1, p0, p1;
-        const u64 X = conn_decode(E, D, r.j, &nh, &h0, &h1, &p0, &p1);
+        const u64 X = join_decode(E, D, r.c, r.hi, r.pi, px, py, &nh, &h0, &h1, &p0, &p1);
         bool t_acts;
         OpDesc op;
         const int k = linking_operator(optab, npairs, nh, h0, h1, p0, p1, &t_acts, &op);
@@ -293,7 +390,7 @@ k_join_reduce(const u64* __restrict__ recs, u64 R, const u64* __restrict__ curso
         const int sl = join_slot(tk, X, false, &ins);
         if (sl < 0) continue;  // not reached: pass 1 inserted every key of the step
         const double a = t_acts ? (double)phase_of_T(op, D) : -(double)phase_of_T(op, X);
-        unsafeAtomicAdd(&gacc[k], amps[r.d] * a * tv[sl]);
+        unsafeAtomicAdd(&gacc[k], sd.psi * a * tv[sl]);
       }
     }
     __syncthreads();
@@ -310,19 +407,41 @@ k_join_reduce(const u64* __restrict__ recs, u64 R, const u64* __restrict__ curso
   }
 }
 
+// Record layout for a state of n stored entries: kb bucket bits for about
+// 256 records per bucket (8, 16 or 24), the connection fields, the index.
+// Returns false when they do not fit 64 bits.
+bool join_format(const ExcSpace& E, u64 n, u64 R, int* kb, int* bh, int* bp) {
+  auto bits_for = [](u64 v) {
+    int b = 1;
+    while (b < 64 && (v >> b) != 0) ++b;
+    return b;
+  };
+  const long long nh = std::max<long long>({(long long)E.na, (long long)E.nb, (long long)E.na * (E.na - 1) / 2,
+                                            (long long)E.nb * (E.nb - 1) / 2, (long long)E.na * E.nb, 1LL});
+  const long long np = std::max<long long>({(long long)E.va, (long long)E.vb, (long long)E.va * (E.va - 1) / 2,
+                                            (long long)E.vb * (E.vb - 1) / 2, (long long)E.va * E.vb, 1LL});
+  *bh = bits_for((u64)(nh - 1));
+  *bp = bits_for((u64)(np - 1));
+  *kb = 8;
+  while (*kb < 24 && (R >> *kb) > 256) *kb += 8;
+  return *kb + 3 + *bh + *bp + bits_for(n > 0 ? n - 1 : 0) <= 64;
+}
+
 hipError_t launch_join_emit(const DeviceState& st, const ExcSpace& E, u64 n, u64* recs, u64 cap_recs,
-                            u64* cursor, int kb, int bj, int grid, hipStream_t stream) {
+                            u64* cursor, int kb, int bh, int bp, void* src, int grid, hipStream_t stream) {
+  const JoinFmt fm{kb, bh, bp};
   hipLaunchKernelGGL(k_join_emit, dim3(grid), dim3(kJoinEmitBlock), conn_tables_bytes(E), stream, st.keys, st.amps, E,
-                     n, recs, cap_recs, cursor, kb, bj, &st.ctr->flags);
+                     n, recs, cap_recs, cursor, fm, (JoinSrc*)src, &st.ctr->flags);
   return hipGetLastError();
 }
 
-hipError_t launch_join_reduce(const DeviceState& st, const u64* recs, u64 R, const u64* cursor, int kb, int bj,
-                              u64 n, const Ints& I, const ExcSpace& E, const int* optab, int npairs,
-                              const unsigned char* selected, double* gacc, double* inserted, int grid,
+hipError_t launch_join_reduce(const DeviceState& st, const u64* recs, u64 R, const u64* cursor, int kb, int bh,
+                              int bp, const void* src, u64 n, const Ints& I, const ExcSpace& E, const int* optab,
+                              int npairs, const unsigned char* selected, double* gacc, double* inserted, int grid,
                               hipStream_t stream) {
-  hipLaunchKernelGGL(k_join_reduce, dim3(grid), dim3(kJoinBlock), 0, stream, recs, R, cursor, kb, bj, st.keys,
-                     st.amps, st.diag, n, I, E, optab, npairs, selected, gacc, &st.ctr->flags, inserted);
+  const JoinFmt fm{kb, bh, bp};
+  hipLaunchKernelGGL(k_join_reduce, dim3(grid), dim3(kJoinBlock), 0, stream, recs, R, cursor, fm,
+                     (const JoinSrc*)src, st.diag, n, I, E, optab, npairs, selected, gacc, &st.ctr->flags, inserted);
   return hipGetLastError();
 }
 

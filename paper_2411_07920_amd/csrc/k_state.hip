@@ -24,11 +24,10 @@ namespace swcs {
 //             update with fused pruning; the new partner keys of a round are
 //             staged in LDS;
 //   append -- one atomic on the append counter per round, then coalesced
-//             writes of the new keys and amplitudes.
-// The index entries of the appended keys are inserted afterwards by
-// k_hash_insert_appended: no probe of this gate can look for a key the gate
-// itself appends (its partner under this operator is the entry that appends
-// it), so the inserts leave the critical path of the gate.
+//             writes of the new keys and amplitudes and their index inserts
+//             (the probe that found the key absent has just brought its
+//             slot's line into L2, so the insert's CAS hits there; inserts
+//             deferred to a separate pass cost more than they saved).
 // SCAN = 16 for large states (more entries in flight per block), 2 for
 // states of up to a few hundred thousand entries (more blocks).
 template <int SCAN>
@@ -153,6 +152,7 @@ k_gate(u64* __restrict__ keys, double* __restrict__ amps, HashSlot* __restrict__
           if (i < cap) {
             keys[i] = s_key[j];
             amps[i] = s_val[j];
+            hash_insert_new(hash, hmask, s_key[j], i);
           } else {
             atomicOr(&ctr->flags, kFlagOverflow);
           }
@@ -185,7 +185,6 @@ k_gate(u64* __restrict__ keys, double* __restrict__ amps, HashSlot* __restrict__
     const long long da = (long long)atomicAdd((unsigned long long*)&ctr->dalive, 0ULL);
     const u64 alive = ctr->alive;
     if (gate_n_in) *gate_n_in = alive;
-    ctr->n_prev = n_in;
     ctr->n = n_in + (app < cap - n_in ? app : cap - n_in);
     ctr->alive = (u64)((long long)alive + da);
     ctr->app = 0;
@@ -193,21 +192,6 @@ k_gate(u64* __restrict__ keys, double* __restrict__ amps, HashSlot* __restrict__
     __threadfence();
     ctr->ticket = 0;
   }
-}
-
-// Index entries of the keys the last gate appended, [n_prev, n).  Does
-// nothing after a gate that stopped for capacity (it appended nothing; the
-// range still names the previous gate's keys, which are indexed already).
-__global__ void __launch_bounds__(256)
-k_hash_insert_appended(const u64* __restrict__ keys, HashSlot* __restrict__ hash, u64 hmask,
-                       const Counters* __restrict__ ctr) {
-  const unsigned fl = __hip_atomic_load(&ctr->flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  if (fl & kFlagStopped) return;
-  const u64 lo = __hip_atomic_load(&ctr->n_prev, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  const u64 hi = __hip_atomic_load(&ctr->n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  const u64 stride = (u64)gridDim.x * blockDim.x;
-  for (u64 i = lo + (u64)blockIdx.x * blockDim.x + threadIdx.x; i < hi; i += stride)
-    hash_insert_new(hash, hmask, keys[i], i);
 }
 
 // Replay of one gate inside the adjoint's recomputation: the same update as
@@ -525,10 +509,6 @@ hipError_t launch_gate(const DeviceState& st, const OpDesc& op, double c, double
     hipLaunchKernelGGL(k_gate<kGateScanNarrow>, dim3(grid), dim3(kGateThreads), 0, stream, st.keys, st.amps,
                        st.hash, st.hmask, st.cap, st.ctr, op, c, sn, eps, gate_n_in, check_cap, gate_index,
                        max_keys, gate_n_act);
-  // at most one append per alive entry: a grid over a quarter of the
-  // capacity, grid-strided, covers any range
-  hipLaunchKernelGGL(k_hash_insert_appended, dim3(grid_for(st.cap / 4, 256, 8192)), dim3(256), 0, stream,
-                     st.keys, st.hash, st.hmask, st.ctr);
   return hipGetLastError();
 }
 

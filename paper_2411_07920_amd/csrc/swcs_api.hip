@@ -120,7 +120,7 @@ struct swcs_ctx {
   // integrals
   bool have_ints = false;
   double ecore = 0.0;
-  DevBuf h, eri, J, K, fock;
+  DevBuf h, eri, eri8, J, K, fock;
 
   // reference and pool
   bool have_ref = false;
@@ -171,7 +171,7 @@ struct swcs_ctx {
   // scratch
   DevBuf gacc, selected, ncut_state, qfilt;
   DevBuf partial, partial2, sigma, mu, work, seg_states, acc_tab, gbuf, subset_buf, scalars,
-      exp_keys, exp_amps, exp_tmp_k, exp_tmp_v, sort_scratch, ctr_r, occ, sel_scratch, mlp_partial, mse_partial, hp_key, hp_val, hp_tk, hp_tv, diag;
+      exp_keys, exp_amps, exp_tmp_k, exp_tmp_v, sort_scratch, ctr_r, occ, sel_scratch, mlp_partial, mse_partial, hp_key, hp_val, hp_tk, hp_tv, diag, join_src;
   int sigma_method = SWCS_SIGMA_AUTO;
   int pool_method = SWCS_POOL_AUTO;
   double ext_count = 0.0, ext_alive = 0.0;  // distinct external keys of the last full pool pass
@@ -186,12 +186,12 @@ struct swcs_ctx {
   u64 state_version = 1, diag_version = 0, norm_version = 0;
 
   template <class F> void for_each_buf(F&& f) {
-    DevBuf* all[] = {&h, &eri, &J, &K, &fock, &ops, &opmap, &gacc, &selected, &ncut_state, &filt, &keys, &amps, &hash, &ctr, &ckpt_n, &ckpt_ptrs,
+    DevBuf* all[] = {&h, &eri, &eri8, &J, &K, &fock, &ops, &opmap, &gacc, &selected, &ncut_state, &filt, &keys, &amps, &hash, &ctr, &ckpt_n, &ckpt_ptrs,
                      &gate_tab, &gate_n_in, &gate_n_act,
                      &partial, &partial2, &sigma, &mu, &work, &seg_states, &acc_tab, &gbuf,
                      &subset_buf, &scalars, &exp_keys, &exp_amps, &exp_tmp_k, &exp_tmp_v,
                      &sort_scratch, &ctr_r, &occ, &sel_scratch, &mlp_partial, &mse_partial,
-                     &hp_key, &hp_val, &hp_tk, &hp_tv, &diag, &qfilt};
+                     &hp_key, &hp_val, &hp_tk, &hp_tv, &diag, &qfilt, &join_src};
     for (DevBuf* b : all) f(*b);
     for (auto& b : ckpt) f(b);
   }
@@ -282,7 +282,7 @@ int sigma_grid(swcs_ctx* c, u64 n) {
 Ints ints_view(swcs_ctx* c) {
   Ints I;
   I.h = c->h.as<double>();
-  I.eri = c->eri.as<double>();
+  I.eri = c->eri8.as<double>();
   I.J = c->J.as<double>();
   I.K = c->K.as<double>();
   I.ecore = c->ecore;
@@ -325,7 +325,7 @@ size_t avail_bytes(swcs_ctx* c) {
 // when the state needs the memory, and allocated again on their next use.
 void release_scratch(swcs_ctx* c) {
   DevBuf* bufs[] = {&c->acc_tab, &c->hp_key, &c->hp_val, &c->hp_tk, &c->hp_tv, &c->sort_scratch,
-                    &c->exp_keys, &c->exp_amps, &c->exp_tmp_k, &c->exp_tmp_v, &c->qfilt};
+                    &c->exp_keys, &c->exp_amps, &c->exp_tmp_k, &c->exp_tmp_v, &c->qfilt, &c->join_src};
   for (DevBuf* b : bufs) b->release();
 }
 
@@ -827,6 +827,14 @@ int swcs_set_integrals(swcs_ctx* c, const double* h, const double* eri, double e
               std::fabs(v - E(r, s, p, q)) > 1e-12)
             return fail(c, SWCS_E_INVALID, "eri lacks 8-fold symmetry");
         }
+  // (pq|rs) packed by symmetry, the element at p >= q, r >= s, pq >= rs
+  const size_t m = (size_t)n * (n + 1) / 2;
+  std::vector<double> e8(m * (m + 1) / 2);
+  for (int p = 0; p < n; ++p)
+    for (int q = 0; q <= p; ++q)
+      for (int r = 0; r < n; ++r)
+        for (int s = 0; s <= r; ++s)
+          if (p * (p + 1) / 2 + q >= r * (r + 1) / 2 + s) e8[eri_packed_index(p, q, r, s)] = E(p, q, r, s);
   std::vector<double> Jh(n2), Kh(n2);
   for (int p = 0; p < n; ++p)
     for (int q = 0; q < n; ++q) {
@@ -835,11 +843,13 @@ int swcs_set_integrals(swcs_ctx* c, const double* h, const double* eri, double e
     }
   HIP_TRY(c, c->h.ensure(n2 * 8), "alloc h");
   HIP_TRY(c, c->eri.ensure(n4 * 8), "alloc eri");
+  HIP_TRY(c, c->eri8.ensure(e8.size() * 8), "alloc packed eri");
   HIP_TRY(c, c->J.ensure(n2 * 8), "alloc J");
   HIP_TRY(c, c->K.ensure(n2 * 8), "alloc K");
   HIP_TRY(c, c->fock.ensure(n2 * 8), "alloc fock");
   HIP_TRY(c, hipMemcpyAsync(c->h.p, h, n2 * 8, hipMemcpyHostToDevice, c->stream), "copy h");
   HIP_TRY(c, hipMemcpyAsync(c->eri.p, eri, n4 * 8, hipMemcpyHostToDevice, c->stream), "copy eri");
+  HIP_TRY(c, hipMemcpyAsync(c->eri8.p, e8.data(), e8.size() * 8, hipMemcpyHostToDevice, c->stream), "copy eri");
   HIP_TRY(c, hipMemcpyAsync(c->J.p, Jh.data(), n2 * 8, hipMemcpyHostToDevice, c->stream), "copy J");
   HIP_TRY(c, hipMemcpyAsync(c->K.p, Kh.data(), n2 * 8, hipMemcpyHostToDevice, c->stream), "copy K");
   HIP_TRY(c, launch_fock(c->h.as<double>(), c->eri.as<double>(), n, c->na, c->fock.as<double>(),
@@ -1624,13 +1634,6 @@ int swcs_pool_gradients_device(swcs_ctx* c, const int32_t* d_subset, int64_t n_s
   return SWCS_OK;
 }
 
-// Bits that hold every value in [0, v].
-static int bits_for(u64 v) {
-  int b = 1;
-  while (b < 64 && (v >> b) != 0) ++b;
-  return b;
-}
-
 // Full-pool (or large-subset) gradients by sort and join (k_join.hip).
 // Returns 1 when the join does not apply (method, memory, record word) or a
 // join step overflowed its LDS table and AUTO may fall back to the table,
@@ -1642,17 +1645,16 @@ static int join_gradients(swcs_ctx* c, const Counters& h, const unsigned char* d
   const bool forced = c->pool_method == SWCS_POOL_JOIN;
   const u64 n = h.n, C = (u64)c->exc.total;
   const u64 R = h.alive * (C + 1);
-  const int bj = bits_for(C), bd = bits_for(n > 0 ? n - 1 : 0);
-  // hash bits: 8, 16 or 24, for about 256 records per bucket
-  int kb = 8;
-  while (kb < 24 && (R >> kb) > 256) kb += 8;
-  if (kb + bj + bd > 64) {
+  int kb, bh, bp;
+  if (!join_format(c->exc, n, R, &kb, &bh, &bp)) {
     if (forced) return fail(c, SWCS_E_CAPACITY, "join records do not fit 64 bits");
     return 1;
   }
   const u64 scr = radix_sort_scratch_elems(R);
-  const double need = 16.0 * (double)R + 8.0 * (double)scr;
-  const double have = (double)(avail_bytes(c) + c->hp_key.bytes + c->hp_tk.bytes + c->sort_scratch.bytes);
+  const u64 list_bytes = n * 16;  // (key, psi) of every stored entry
+  const double need = 16.0 * (double)R + 8.0 * (double)scr + (double)list_bytes;
+  const double have = (double)(avail_bytes(c) + c->hp_key.bytes + c->hp_tk.bytes + c->sort_scratch.bytes +
+                               c->join_src.bytes);
   if (need > 0.5 * have) {
     if (forced) return fail(c, SWCS_E_CAPACITY, "join records exceed half of the free device memory");
     return 1;
@@ -1660,19 +1662,22 @@ static int join_gradients(swcs_ctx* c, const Counters& h, const unsigned char* d
   HIP_TRY(c, c->hp_key.ensure(R * 8), "alloc join records");
   HIP_TRY(c, c->hp_tk.ensure(R * 8), "alloc join records");
   HIP_TRY(c, c->sort_scratch.ensure(scr * 8), "alloc sort scratch");
+  HIP_TRY(c, c->join_src.ensure(std::max<u64>(16, list_bytes)), "alloc join sources");
   const int rgrid = (int)std::min<u64>((R + kJoinRunHost - 1) / kJoinRunHost, (u64)c->num_cu * 8);
   HIP_TRY(c, c->partial2.ensure((size_t)std::max(rgrid, 1) * 8), "alloc partials");
   u64* cursor = c->scalars.as<u64>() + 32;
   HIP_TRY(c, launch_fill_u32(cursor, 0u, 2, c->stream), "zero cursor");
   u64* recs = c->hp_key.as<u64>();
-  TIMED(c, SWCS_K_JOIN_EMIT, launch_join_emit(c->st, c->exc, n, recs, R, cursor, kb, bj, sigma_grid(c, n), c->stream),
+  TIMED(c, SWCS_K_JOIN_EMIT, launch_join_emit(c->st, c->exc, n, recs, R, cursor, kb, bh, bp,
+                                                c->join_src.p, sigma_grid(c, n), c->stream),
         "join emit");
   u64* sorted = recs;
   TIMED(c, SWCS_K_JOIN_SORT, radix_sort_keys(recs, c->hp_tk.as<u64>(), R, kb, c->sort_scratch.as<u64>(), scr,
                                              c->stream, &sorted), "join sort");
   HIP_TRY(c, launch_fill_u32(c->gacc.p, 0u, (u64)c->K_pool * 2, c->stream), "zero g");
   double* ins = c->partial2.as<double>();
-  TIMED(c, SWCS_K_JOIN_REDUCE, launch_join_reduce(c->st, sorted, R, cursor, kb, bj, n, ints_view(c), c->exc, c->opmap.as<int>(),
+  TIMED(c, SWCS_K_JOIN_REDUCE, launch_join_reduce(c->st, sorted, R, cursor, kb, bh, bp, c->join_src.p, n,
+                                                  ints_view(c), c->exc, c->opmap.as<int>(),
                                                   c->npairs, d_sel, c->gacc.as<double>(), ins, rgrid, c->stream),
         "join reduce");
   HIP_TRY(c, launch_reduce_partials(ins, rgrid, rgrid, 1, c->scalars.as<double>() + 24, c->stream), "count");

@@ -151,7 +151,6 @@ struct Counters {
   unsigned int ticket;
   unsigned int flags;
   u64 stop_gate;
-  u64 n_prev;  // stored count before the last multi-block gate (its appends are [n_prev, n))
 };
 
 // kFlagOverflow: an append or table insert found no room (a bug guard: the
@@ -162,16 +161,26 @@ enum : unsigned int { kFlagOverflow = 1u, kFlagStopped = 2u };
 // Integrals on the device, spin-free spatial arrays.
 struct Ints {
   const double* h;    // n*n
-  const double* eri;  // n^4
+  const double* eri;  // (pq|rs) packed by its 8-fold symmetry: eri_packed_index
   const double* J;    // n*n, J[p*n+q] = (pp|qq)
   const double* K;    // n*n, K[p*n+q] = (pq|qp)
   double ecore;
   int n;
 };
 
+// Position of (pq|rs) in the packed array: pair indices pq = p (p + 1) / 2 +
+// q (p >= q), rs likewise, then pq (pq + 1) / 2 + rs (pq >= rs).  The array
+// has m (m + 1) / 2 entries, m = n (n + 1) / 2 (61,776 doubles, 494 KB, at
+// n = 26 against 3.7 MB for n^4), so the lookups of the sigma and gradient
+// kernels stay in L2.
+__host__ __device__ inline unsigned eri_packed_index(unsigned p, unsigned q, unsigned r, unsigned s) {
+  const unsigned pq = p >= q ? p * (p + 1) / 2 + q : q * (q + 1) / 2 + p;
+  const unsigned rs = r >= s ? r * (r + 1) / 2 + s : s * (s + 1) / 2 + r;
+  return pq >= rs ? pq * (pq + 1) / 2 + rs : rs * (rs + 1) / 2 + pq;
+}
+
 __device__ inline double eri_sp(const Ints& I, int p, int q, int r, int s) {
-  int n = I.n;
-  return I.eri[((size_t)(p * n + q) * n + r) * n + s];
+  return I.eri[eri_packed_index((unsigned)p, (unsigned)q, (unsigned)r, (unsigned)s)];
 }
 
 // Spin-orbital (PQ|RS) with the spin deltas.
@@ -379,11 +388,12 @@ hipError_t launch_reduce_partials(const double* partial, int count, int stride, 
 // Full-pool gradients by sort and join (k_join.hip); kJoinRunHost records
 // per step of the join kernel.
 constexpr u64 kJoinRunHost = 2048;
+bool join_format(const ExcSpace& E, u64 n, u64 R, int* kb, int* bh, int* bp);
 hipError_t launch_join_emit(const DeviceState& st, const ExcSpace& E, u64 n, u64* recs, u64 cap_recs,
-                            u64* cursor, int kb, int bj, int grid, hipStream_t stream);
-hipError_t launch_join_reduce(const DeviceState& st, const u64* recs, u64 R, const u64* cursor, int kb, int bj,
-                              u64 n, const Ints& I, const ExcSpace& E, const int* optab, int npairs,
-                              const unsigned char* selected, double* gacc, double* inserted, int grid,
+                            u64* cursor, int kb, int bh, int bp, void* src, int grid, hipStream_t stream);
+hipError_t launch_join_reduce(const DeviceState& st, const u64* recs, u64 R, const u64* cursor, int kb, int bh,
+                              int bp, const void* src, u64 n, const Ints& I, const ExcSpace& E, const int* optab,
+                              int npairs, const unsigned char* selected, double* gacc, double* inserted, int grid,
                               hipStream_t stream);
 hipError_t launch_sigma_push(const DeviceState& st, const Ints& I, const ExcSpace& E, u64 n,
                              AccSlot* tab, u64 tmask, int nbatch, int batch, double* inserted,
