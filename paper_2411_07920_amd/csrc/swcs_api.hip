@@ -1470,10 +1470,11 @@ static int screened_gradients(swcs_ctx* c, u64 n, u64 alive, const int* d_subset
     nq = (u64)bound;
   } else {
     // count the (determinant, operator) pairs, on every 16th determinant
-    // (or tile) of a large state: the scaled sample sizes the table, and a
-    // pass whose table fills is repeated with twice the estimate
+    // (or tile) of a state of 16,384 stored entries or more: the scaled
+    // sample sizes the table, and a pass whose table fills is repeated with
+    // twice the estimate (a full count costs as much as the insert pass)
     counted = true;
-    const int stride = n >= 16 * 4096 ? 16 : 1;
+    const int stride = n >= 16384 ? 16 : 1;
     sampled = stride > 1;
     u64* qcount = c->scalars.as<u64>() + 16;
     HIP_TRY(c, launch_fill_u32(qcount, 0u, 2, c->stream), "zero counter");
