@@ -12,9 +12,11 @@
 // carries everything:
 //   emit   -- every alive D writes one 64-bit record per connection X and
 //             one for itself: (d << (kb + bj)) | (f << kb) | bucket(X), where
-//             d is D's storage index, f = (class, hole set, particle set) of
-//             the connection as bit fields (class 7 for D itself) and
-//             bucket(X) the low kb bits of mix64(X); D's records are one
+//             d is D's storage index, f the connection -- its holes and
+//             particles as four 6-bit spin-orbital indices when the word has
+//             room (all ones for D itself), else (class, hole set, particle
+//             set) as ranks -- and bucket(X) the low kb bits of mix64(X); D's
+//             records are one
 //             coalesced run, and (D, psi(D)) goes to a 16-byte table by d,
 //             so the join reaches both with one load per record;
 //   sort   -- a stable LSD radix sort on the kb bucket bits only, so every
@@ -37,14 +39,17 @@ constexpr int kJoinRun = (int)kJoinRunHost;  // records per block step before bu
 constexpr int kJoinSlots = 4096;  // LDS table: keys and sums, 64 KB (two blocks per CU)
 constexpr int kJoinCache = 4;     // records per thread and step whose gradient term stays in registers
 
-// Record layout: kb bucket bits, then the connection fields (class in 3
-// bits, hole-set index in bh bits, particle-set index in bp bits), then the
-// storage index.
+// Record layout: kb bucket bits, then the connection fields, then the
+// storage index.  Orbital fields (orb): h0 | h1 << 6 | p0 << 12 | p1 << 18,
+// 24 bits, all ones for D itself; decoding is four extractions.  Rank fields:
+// class in 3 bits (7 for D itself), hole-set index in bh bits, particle-set
+// index in bp bits; decoding selects the ranked orbitals from D's bits.
 struct JoinFmt {
-  int kb, bh, bp;
-  __host__ __device__ int bj() const { return 3 + bh + bp; }
+  int kb, bh, bp, orb;
+  __host__ __device__ int bj() const { return orb ? 24 : 3 + bh + bp; }
 };
-constexpr unsigned kJoinSelf = 7;  // class field of the record of D itself
+constexpr unsigned kJoinSelf = 7;          // class field of the record of D itself (rank fields)
+constexpr unsigned kJoinSelfOrb = 0xFFFFFFu;  // fields of the record of D itself (orbital fields)
 
 // Calls f(X, ordinal, field) for every connection of D assigned to this
 // lane: ordinal = class offset + hole set * particle sets + particle set (the
@@ -60,8 +65,11 @@ __device__ inline void for_each_connection_fields(const ConnTables& T, u64 D, co
     int pi = (int)threadIdx.x - hi * np;
     const u64 cf = (u64)c << (fm.bh + fm.bp);
     while (hi < nh) {
-      const u64 X = D ^ T.hmask[hb + hi] ^ T.pmask[pb + pi];
-      f(X, off + (long long)hi * np + pi, cf | ((u64)hi << fm.bp) | (u64)pi);
+      const int H = hb + hi, Pp = pb + pi;
+      const u64 X = D ^ T.hmask[H] ^ T.pmask[Pp];
+      const u64 field = fm.orb ? ((u64)T.h0[H] | ((u64)T.h1[H] << 6) | ((u64)T.p0[Pp] << 12) | ((u64)T.p1[Pp] << 18))
+                               : (cf | ((u64)hi << fm.bp) | (u64)pi);
+      f(X, off + (long long)hi * np + pi, field);
       pi += blockDim.x;
       while (pi >= np) {
         pi -= np;
@@ -170,8 +178,10 @@ k_join_emit(const u64* __restrict__ keys, const double* __restrict__ amps, ExcSp
     for_each_connection_fields(T, D, fm, [&](u64 X, long long j, u64 field) {
       recs[base + (u64)j] = hd | (field << fm.kb) | (mix64(X) & bmask);
     });
-    if (threadIdx.x == 0)
-      recs[base + C] = hd | ((u64)kJoinSelf << (fm.kb + fm.bh + fm.bp)) | (mix64(D) & bmask);
+    if (threadIdx.x == 0) {
+      const u64 self_field = fm.orb ? (u64)kJoinSelfOrb : ((u64)kJoinSelf << (fm.bh + fm.bp));
+      recs[base + C] = hd | (self_field << fm.kb) | (mix64(D) & bmask);
+    }
   }
 }
 
@@ -226,27 +236,50 @@ __device__ inline int join_slot(u64* tk, u64 X, bool insert, double* inserted) {
 // Fields of a record.
 struct JoinRec {
   u64 d;
-  unsigned c, hi, pi;
+  unsigned f;  // connection fields
 };
 __device__ inline JoinRec join_rec(u64 r, const JoinFmt& fm) {
   JoinRec o;
-  const u64 f = r >> fm.kb;
-  o.pi = (unsigned)(f & ((1ULL << fm.bp) - 1ULL));
-  o.hi = (unsigned)((f >> fm.bp) & ((1ULL << fm.bh) - 1ULL));
-  o.c = (unsigned)((f >> (fm.bp + fm.bh)) & 7ULL);
+  o.f = (unsigned)((r >> fm.kb) & ((1ULL << fm.bj()) - 1ULL));
   o.d = r >> (fm.kb + fm.bj());
   return o;
 }
 
-// Whether the fields name a connection of the enumeration (a record that
-// was never written cannot index outside the pair tables or the state).
-__device__ inline bool join_fields_valid(const ExcSpace& E, const JoinRec& r) {
+__device__ inline bool join_is_self(const JoinFmt& fm, const JoinRec& r) {
+  return fm.orb ? r.f == kJoinSelfOrb : (r.f >> (fm.bh + fm.bp)) == kJoinSelf;
+}
+
+// Connection of a pair record: X and its holes h0 <= h1 and particles
+// p0 <= p1 (equal for singles), or false when the fields name no connection
+// of D (a record that was never written cannot index outside the state, the
+// integrals or the tables).
+__device__ inline bool join_connection(const JoinFmt& fm, const ExcSpace& E, u64 D, const JoinRec& r,
+                                       const unsigned char* px, const unsigned char* py, u64* X, int* nh,
+                                       int* h0, int* h1, int* p0, int* p1) {
+  if (fm.orb) {
+    const unsigned n2 = 2u * (unsigned)E.n;
+    const unsigned a = r.f & 63u, b = (r.f >> 6) & 63u, c = (r.f >> 12) & 63u, d = (r.f >> 18) & 63u;
+    if (a > b || c > d || b >= n2 || d >= n2 || ((a == b) != (c == d))) return false;
+    const u64 hm = (1ULL << a) | (1ULL << b), pm = (1ULL << c) | (1ULL << d);
+    if ((D & hm) != hm || (D & pm) != 0) return false;
+    *nh = (a == b) ? 1 : 2;
+    *h0 = (int)a;
+    *h1 = (int)b;
+    *p0 = (int)c;
+    *p1 = (int)d;
+    *X = D ^ hm ^ pm;
+    return true;
+  }
+  const unsigned c = r.f >> (fm.bh + fm.bp);
+  const unsigned hi = (r.f >> fm.bp) & ((1u << fm.bh) - 1u), pi = r.f & ((1u << fm.bp) - 1u);
   const int na = E.na, nb = E.nb, va = E.va, vb = E.vb;
-  const unsigned nh[5] = {(unsigned)na, (unsigned)nb, (unsigned)(na * (na - 1) / 2), (unsigned)(nb * (nb - 1) / 2),
-                          (unsigned)(na * nb)};
-  const unsigned np[5] = {(unsigned)va, (unsigned)vb, (unsigned)(va * (va - 1) / 2), (unsigned)(vb * (vb - 1) / 2),
-                          (unsigned)(va * vb)};
-  return r.c < 5 && r.hi < nh[r.c] && r.pi < np[r.c];
+  const unsigned nhs[5] = {(unsigned)na, (unsigned)nb, (unsigned)(na * (na - 1) / 2), (unsigned)(nb * (nb - 1) / 2),
+                           (unsigned)(na * nb)};
+  const unsigned nps[5] = {(unsigned)va, (unsigned)vb, (unsigned)(va * (va - 1) / 2), (unsigned)(vb * (vb - 1) / 2),
+                           (unsigned)(va * vb)};
+  if (c >= 5 || hi >= nhs[c] || pi >= nps[c]) return false;
+  *X = join_decode(E, D, c, hi, pi, px, py, nh, h0, h1, p0, p1);
+  return true;
 }
 
 // First pass over one record: sigma(X) += H_{X D} psi(D) (or H_{D D} psi(D)
@@ -265,21 +298,19 @@ __device__ inline void join_record_sigma(u64 rec, const JoinFmt& fm, const JoinS
   *w = 0.0;
   const JoinRec r = join_rec(rec, fm);
   if (r.d >= n) return;
-  const bool self = r.c == kJoinSelf;
-  if (!self && !join_fields_valid(E, r)) return;
+  const bool self = join_is_self(fm, r);
   const JoinSrc sd = src[r.d];
   const u64 D = sd.key;
   const double psi = sd.psi;
-  u64 X;
+  u64 X = D;
   double v;
   int kk = -1;
   double a = 0.0;
   if (self) {
-    X = D;
     v = diag[r.d] * psi;
   } else {
     int nh, h0, h1, p0, p1;
-    X = join_decode(E, D, r.c, r.hi, r.pi, px, py, &nh, &h0, &h1, &p0, &p1);
+    if (!join_connection(fm, E, D, r, px, py, &X, &nh, &h0, &h1, &p0, &p1)) return;
     v = connection_element(I, D, nh, h0, h1, p0, p1) * psi;
     if (term) {
       bool t_acts;
@@ -378,11 +409,12 @@ k_join_reduce(const u64* __restrict__ recs, u64 R, const u64* __restrict__ curso
         if (ck[m] >= 0) unsafeAtomicAdd(&gacc[ck[m]], cw[m] * tv[csl[m]]);
       for (u64 i = lo + threadIdx.x + (u64)kJoinCache * kJoinBlock; i < hi; i += kJoinBlock) {
         const JoinRec r = join_rec(recs[i], fm);
-        if (r.d >= n || r.c == kJoinSelf || !join_fields_valid(E, r)) continue;
+        if (r.d >= n || join_is_self(fm, r)) continue;
         const JoinSrc sd = src[r.d];
         const u64 D = sd.key;
         int nh, h0, h1, p0, p1;
-        const u64 X = join_decode(E, D, r.c, r.hi, r.pi, px, py, &nh, &h0, &h1, &p0, &p1);
+        u64 X;
+        if (!join_connection(fm, E, D, r, px, py, &X, &nh, &h0, &h1, &p0, &p1)) continue;
         bool t_acts;
         OpDesc op;
         const int k = linking_operator(optab, npairs, nh, h0, h1, p0, p1, &t_acts, &op);
@@ -410,7 +442,7 @@ k_join_reduce(const u64* __restrict__ recs, u64 R, const u64* __restrict__ curso
 // Record layout for a state of n stored entries: kb bucket bits for about
 // 256 records per bucket (8, 16 or 24), the connection fields, the index.
 // Returns false when they do not fit 64 bits.
-bool join_format(const ExcSpace& E, u64 n, u64 R, int* kb, int* bh, int* bp) {
+bool join_format(const ExcSpace& E, u64 n, u64 R, int* kb, int* bh, int* bp, int* orb) {
   auto bits_for = [](u64 v) {
     int b = 1;
     while (b < 64 && (v >> b) != 0) ++b;
@@ -424,22 +456,24 @@ bool join_format(const ExcSpace& E, u64 n, u64 R, int* kb, int* bh, int* bp) {
   *bp = bits_for((u64)(np - 1));
   *kb = 8;
   while (*kb < 24 && (R >> *kb) > 256) *kb += 8;
-  return *kb + 3 + *bh + *bp + bits_for(n > 0 ? n - 1 : 0) <= 64;
+  const int bd = bits_for(n > 0 ? n - 1 : 0);
+  *orb = (*kb + 24 + bd <= 64) ? 1 : 0;
+  return *orb || *kb + 3 + *bh + *bp + bd <= 64;
 }
 
 hipError_t launch_join_emit(const DeviceState& st, const ExcSpace& E, u64 n, u64* recs, u64 cap_recs,
-                            u64* cursor, int kb, int bh, int bp, void* src, int grid, hipStream_t stream) {
-  const JoinFmt fm{kb, bh, bp};
+                            u64* cursor, int kb, int bh, int bp, int orb, void* src, int grid, hipStream_t stream) {
+  const JoinFmt fm{kb, bh, bp, orb};
   hipLaunchKernelGGL(k_join_emit, dim3(grid), dim3(kJoinEmitBlock), conn_tables_bytes(E), stream, st.keys, st.amps, E,
                      n, recs, cap_recs, cursor, fm, (JoinSrc*)src, &st.ctr->flags);
   return hipGetLastError();
 }
 
 hipError_t launch_join_reduce(const DeviceState& st, const u64* recs, u64 R, const u64* cursor, int kb, int bh,
-                              int bp, const void* src, u64 n, const Ints& I, const ExcSpace& E, const int* optab,
-                              int npairs, const unsigned char* selected, double* gacc, double* inserted, int grid,
-                              hipStream_t stream) {
-  const JoinFmt fm{kb, bh, bp};
+                              int bp, int orb, const void* src, u64 n, const Ints& I, const ExcSpace& E,
+                              const int* optab, int npairs, const unsigned char* selected, double* gacc,
+                              double* inserted, int grid, hipStream_t stream) {
+  const JoinFmt fm{kb, bh, bp, orb};
   hipLaunchKernelGGL(k_join_reduce, dim3(grid), dim3(kJoinBlock), 0, stream, recs, R, cursor, fm,
                      (const JoinSrc*)src, st.diag, n, I, E, optab, npairs, selected, gacc, &st.ctr->flags, inserted);
   return hipGetLastError();

@@ -1646,8 +1646,8 @@ static int join_gradients(swcs_ctx* c, const Counters& h, const unsigned char* d
   const bool forced = c->pool_method == SWCS_POOL_JOIN;
   const u64 n = h.n, C = (u64)c->exc.total;
   const u64 R = h.alive * (C + 1);
-  int kb, bh, bp;
-  if (!join_format(c->exc, n, R, &kb, &bh, &bp)) {
+  int kb, bh, bp, orb;
+  if (!join_format(c->exc, n, R, &kb, &bh, &bp, &orb)) {
     if (forced) return fail(c, SWCS_E_CAPACITY, "join records do not fit 64 bits");
     return 1;
   }
@@ -1669,7 +1669,7 @@ static int join_gradients(swcs_ctx* c, const Counters& h, const unsigned char* d
   u64* cursor = c->scalars.as<u64>() + 32;
   HIP_TRY(c, launch_fill_u32(cursor, 0u, 2, c->stream), "zero cursor");
   u64* recs = c->hp_key.as<u64>();
-  TIMED(c, SWCS_K_JOIN_EMIT, launch_join_emit(c->st, c->exc, n, recs, R, cursor, kb, bh, bp,
+  TIMED(c, SWCS_K_JOIN_EMIT, launch_join_emit(c->st, c->exc, n, recs, R, cursor, kb, bh, bp, orb,
                                                 c->join_src.p, sigma_grid(c, n), c->stream),
         "join emit");
   u64* sorted = recs;
@@ -1677,7 +1677,7 @@ static int join_gradients(swcs_ctx* c, const Counters& h, const unsigned char* d
                                              c->stream, &sorted), "join sort");
   HIP_TRY(c, launch_fill_u32(c->gacc.p, 0u, (u64)c->K_pool * 2, c->stream), "zero g");
   double* ins = c->partial2.as<double>();
-  TIMED(c, SWCS_K_JOIN_REDUCE, launch_join_reduce(c->st, sorted, R, cursor, kb, bh, bp, c->join_src.p, n,
+  TIMED(c, SWCS_K_JOIN_REDUCE, launch_join_reduce(c->st, sorted, R, cursor, kb, bh, bp, orb, c->join_src.p, n,
                                                   ints_view(c), c->exc, c->opmap.as<int>(),
                                                   c->npairs, d_sel, c->gacc.as<double>(), ins, rgrid, c->stream),
         "join reduce");

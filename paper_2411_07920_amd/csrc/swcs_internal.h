@@ -388,13 +388,13 @@ hipError_t launch_reduce_partials(const double* partial, int count, int stride, 
 // Full-pool gradients by sort and join (k_join.hip); kJoinRunHost records
 // per step of the join kernel.
 constexpr u64 kJoinRunHost = 2048;
-bool join_format(const ExcSpace& E, u64 n, u64 R, int* kb, int* bh, int* bp);
+bool join_format(const ExcSpace& E, u64 n, u64 R, int* kb, int* bh, int* bp, int* orb);
 hipError_t launch_join_emit(const DeviceState& st, const ExcSpace& E, u64 n, u64* recs, u64 cap_recs,
-                            u64* cursor, int kb, int bh, int bp, void* src, int grid, hipStream_t stream);
+                            u64* cursor, int kb, int bh, int bp, int orb, void* src, int grid, hipStream_t stream);
 hipError_t launch_join_reduce(const DeviceState& st, const u64* recs, u64 R, const u64* cursor, int kb, int bh,
-                              int bp, const void* src, u64 n, const Ints& I, const ExcSpace& E, const int* optab,
-                              int npairs, const unsigned char* selected, double* gacc, double* inserted, int grid,
-                              hipStream_t stream);
+                              int bp, int orb, const void* src, u64 n, const Ints& I, const ExcSpace& E,
+                              const int* optab, int npairs, const unsigned char* selected, double* gacc,
+                              double* inserted, int grid, hipStream_t stream);
 hipError_t launch_sigma_push(const DeviceState& st, const Ints& I, const ExcSpace& E, u64 n,
                              AccSlot* tab, u64 tmask, int nbatch, int batch, double* inserted,
                              int grid, hipStream_t stream);

@@ -5,9 +5,11 @@ The HIP path (k_join.hip) evaluates the whole-pool gradient of ADAPT step 4
 (Sec. II.C), g_k = (2/<psi|psi>) sum_D psi(D) a_k(D) sigma(X_k(D)), from one
 64-bit record per (alive D, connection X) pair plus one per alive D:
 
-  emit:   record = (d << (kb + 3 + bh + bp)) | (field << kb) | (mix64(X) & (2^kb - 1)),
-          field = (class << (bh + bp)) | (hole set << bp) | particle set, class 7
-          for D itself; D's occupied and virtual lists go to a table by d;
+  emit:   record = (d << (kb + bj)) | (field << kb) | (mix64(X) & (2^kb - 1)), with
+          either orbital fields (bj = 24: h0 | h1 << 6 | p0 << 12 | p1 << 18, all
+          ones for D itself) when they fit the word, or rank fields
+          (bj = 3 + bh + bp: (class << (bh + bp)) | (hole set << bp) | particle
+          set, class 7 for D itself);
   sort:   stable, by the kb bucket bits only;
   join:   per run of whole buckets, sigma(X) summed over the run's records
           (H_{X D} psi(D), or H_{D D} psi(D) for class 7), then
@@ -59,7 +61,8 @@ def _bits_for(v):
     return b
 
 
-def record_format(n, na, nb, n_stored, R):
+def record_format(n, na, nb, n_stored, R, orbital=None):
+    """(kb, bh, bp, orb, fits); orbital=None picks orbital fields when they fit."""
     va, vb = n - na, n - nb
     nh, np_ = class_sizes(na, nb, va, vb)
     bh = _bits_for(max(max(nh), 1) - 1)
@@ -67,8 +70,10 @@ def record_format(n, na, nb, n_stored, R):
     kb = 8
     while kb < 24 and (R >> kb) > 256:
         kb += 8
-    fits = kb + 3 + bh + bp + _bits_for(max(n_stored - 1, 0)) <= 64
-    return kb, bh, bp, fits
+    bd = _bits_for(max(n_stored - 1, 0))
+    orb = (kb + 24 + bd <= 64) if orbital is None else orbital
+    fits = kb + (24 if orb else 3 + bh + bp) + bd <= 64
+    return kb, bh, bp, orb, fits
 
 
 def hole_particle_sets(D, n, na, nb):
@@ -89,7 +94,7 @@ def hole_particle_sets(D, n, na, nb):
     return hp
 
 
-def emit(keys, amps, n, na, nb):
+def emit(keys, amps, n, na, nb, orbital=None):
     """Records (uint64), each record's X by direct enumeration, and the
     format, in storage order of the alive entries."""
     keys = np.asarray(keys, dtype=np.uint64)
@@ -98,7 +103,7 @@ def emit(keys, amps, n, na, nb):
     nh, np_ = class_sizes(na, nb, va, vb)
     C = sum(a * b for a, b in zip(nh, np_))
     R = len(alive) * (C + 1)
-    kb, bh, bp, fits = record_format(n, na, nb, len(keys), R)
+    kb, bh, bp, orb, fits = record_format(n, na, nb, len(keys), R, orbital)
     assert fits
     one = np.uint64(1)
     out, xs = [], []
@@ -112,32 +117,51 @@ def emit(keys, amps, n, na, nb):
             hm = (one << h0[hi].astype(np.uint64)) | (one << h1[hi].astype(np.uint64))
             pm = (one << p0[pi].astype(np.uint64)) | (one << p1[pi].astype(np.uint64))
             X = np.uint64(D) ^ hm ^ pm
-            field = (np.uint64(c) << np.uint64(bh + bp)) | (hi.astype(np.uint64) << np.uint64(bp)) | pi.astype(np.uint64)
-            out.append(rec(d, field, X, kb, bh, bp))
+            if orb:
+                field = (h0[hi].astype(np.uint64) | (h1[hi].astype(np.uint64) << np.uint64(6))
+                         | (p0[pi].astype(np.uint64) << np.uint64(12)) | (p1[pi].astype(np.uint64) << np.uint64(18)))
+            else:
+                field = ((np.uint64(c) << np.uint64(bh + bp)) | (hi.astype(np.uint64) << np.uint64(bp))
+                         | pi.astype(np.uint64))
+            out.append(rec(d, field, X, kb, bh, bp, orb))
             xs.append(X)
-        out.append(rec(d, np.array([7 << (bh + bp)], dtype=np.uint64), np.array([D], dtype=np.uint64), kb, bh, bp))
+        self_field = 0xFFFFFF if orb else 7 << (bh + bp)
+        out.append(rec(d, np.array([self_field], dtype=np.uint64), np.array([D], dtype=np.uint64), kb, bh, bp, orb))
         xs.append(np.array([D], dtype=np.uint64))
     recs = np.concatenate(out)
     assert len(recs) == R
-    return recs, np.concatenate(xs), (kb, bh, bp)
+    return recs, np.concatenate(xs), (kb, bh, bp, orb)
 
 
-def rec(d, field, X, kb, bh, bp):
+def rec(d, field, X, kb, bh, bp, orb):
     bucket = sm.mix64(X) & np.uint64((1 << kb) - 1)
-    return (np.uint64(d) << np.uint64(kb + 3 + bh + bp)) | (field << np.uint64(kb)) | bucket
+    bj = 24 if orb else 3 + bh + bp
+    return (np.uint64(d) << np.uint64(kb + bj)) | (field << np.uint64(kb)) | bucket
 
 
 def decode(recs, fmt, keys, n, na, nb):
     """(d, class, X, nh, h0, h1, p0, p1) of every record, from its fields and
     D's lists only."""
-    kb, bh, bp = fmt
+    kb, bh, bp, orb = fmt
     va, vb = n - na, n - nb
-    f = recs >> np.uint64(kb)
+    bj = 24 if orb else 3 + bh + bp
+    f = (recs >> np.uint64(kb)) & np.uint64((1 << bj) - 1)
+    d = (recs >> np.uint64(kb + bj)).astype(np.int64)
+    keys = np.asarray(keys, dtype=np.uint64)
+    if orb:
+        fi = f.astype(np.int64)
+        h0, h1, p0, p1 = fi & 63, (fi >> 6) & 63, (fi >> 12) & 63, (fi >> 18) & 63
+        c = np.where(fi == 0xFFFFFF, 7, 0)
+        nh = np.where(h0 == h1, 1, 2)
+        one = np.uint64(1)
+        D = keys[d]
+        hm = (one << h0.astype(np.uint64)) | (one << h1.astype(np.uint64))
+        pm = (one << p0.astype(np.uint64)) | (one << p1.astype(np.uint64))
+        X = np.where(c == 7, D, D ^ hm ^ pm)
+        return d, c, X, nh, h0, h1, p0, p1
     pi = (f & np.uint64((1 << bp) - 1)).astype(np.int64)
     hi = ((f >> np.uint64(bp)) & np.uint64((1 << bh) - 1)).astype(np.int64)
     c = ((f >> np.uint64(bp + bh)) & np.uint64(7)).astype(np.int64)
-    d = (recs >> np.uint64(kb + 3 + bh + bp)).astype(np.int64)
-    keys = np.asarray(keys, dtype=np.uint64)
     L = np.array([sum(lists_of(int(k), n), []) for k in keys.tolist()], dtype=np.int64)
     oa, ob, xa, xb = 0, na, na + nb, na + nb + va
     tri = _tri_pairs(max(na, nb, va, vb))
@@ -172,14 +196,14 @@ def decode(recs, fmt, keys, n, na, nb):
     return d, c, X, nh, h0, h1, p0, p1
 
 
-def join_gradients(keys, amps, pool, h, eri, na, nb):
+def join_gradients(keys, amps, pool, h, eri, na, nb, orbital=None):
     """Whole-pool g by emit, sort and join; also returns every record's X as
     decoded from its fields and as enumerated when it was emitted (same
     order), and the record format."""
     n = h.shape[0]
     keys = np.asarray(keys, dtype=np.uint64)
     amps = np.asarray(amps, dtype=np.float64)
-    recs, X_enum, fmt = emit(keys, amps, n, na, nb)
+    recs, X_enum, fmt = emit(keys, amps, n, na, nb, orbital)
     kb = fmt[0]
     order = np.argsort(recs & np.uint64((1 << kb) - 1), kind="stable")
     recs, X_enum = recs[order], X_enum[order]

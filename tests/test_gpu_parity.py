@@ -183,6 +183,32 @@ def test_pool_methods_join_and_table(swcs, c1, c2, spread, name):
     ctx.close()
 
 
+def test_join_rank_fields_large_state(swcs):
+    """More than 65,536 stored entries: the join's records carry rank fields
+    (24 bits of orbital fields, 24 hash bits and a 17-bit index do not fit one
+    word).  Whole-pool gradients by the join against the accumulation table,
+    which the oracle pins on the smaller cases, and the same distinct-key
+    count."""
+    c = CONFIGS["c2"]
+    h, eri = make_integrals(c.n, c.rank, c.seed_int)
+    pool = enumerate_pool(c.n)
+    na = c.n_elec // 2
+    keys, amps = draw_synthetic_state(c.n, na, na, 70_000, 4007)
+    ctx = swcs.make_context(c.n, na, na, h, eri, pool, reference_key(c.n_elec))
+    ctx.set_state(keys, amps)
+    out = {}
+    for method in ("join", "table"):
+        _say(f"[parity] 70,000-entry c2 state: whole pool by {method}")
+        ctx.set_pool_method(method)
+        out[method] = (ctx.pool_gradients(), ctx.pool_stats())
+    (g_j, st_j), (g_t, st_t) = out["join"], out["table"]
+    assert st_j["table_slots"] == 0 and st_t["table_slots"] > 0
+    assert st_j["keys"] == st_t["keys"]
+    assert np.abs(g_t).max() > 1e-6
+    assert np.abs(g_j - g_t).max() < TOL
+    ctx.close()
+
+
 def test_c2_subset_paths(swcs, c2):
     """Screened pool gradients on both restricted paths: a subset smaller than
     the connection count is walked operator-major, a larger one (still under

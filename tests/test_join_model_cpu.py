@@ -12,8 +12,8 @@ from paper_2411_07920_amd.inputs import (CONFIGS, draw_ansatz, draw_synthetic_st
                                          make_integrals, reference_key)
 
 
-@pytest.mark.parametrize("name", ["c1", "c2"])
-def test_join_model_matches_oracle(name):
+@pytest.mark.parametrize("name,orbital", [("c1", None), ("c2", None), ("c1", False), ("c2", False)])
+def test_join_model_matches_oracle(name, orbital):
     c = CONFIGS[name]
     h, eri = make_integrals(c.n, c.rank, c.seed_int)
     pool = enumerate_pool(c.n)
@@ -23,7 +23,8 @@ def test_join_model_matches_oracle(name):
     st = oracle.Oracle.apply_ansatz(pool, ops, theta, c.eps, reference_key(c.n_elec))
     orc = oracle.Oracle(c.n, na, nb, h, eri)
     keys, amps = st.export()
-    g, X_dec, X_enum, fmt = jm.join_gradients(keys, amps, pool, h, eri, na, nb)
+    g, X_dec, X_enum, fmt = jm.join_gradients(keys, amps, pool, h, eri, na, nb, orbital)
+    assert fmt[3] == (orbital is None)  # orbital fields fit these small states
     assert np.array_equal(X_dec, X_enum)
     g_ref = orc.pool_gradients(st, pool)
     assert np.abs(g_ref).max() > 1e-3
@@ -32,7 +33,7 @@ def test_join_model_matches_oracle(name):
 
 def test_join_model_open_shell_and_dead_entries():
     """Unequal spin counts (every class size differs) and pruned entries in
-    storage, which emit nothing."""
+    storage, which emit nothing; both record formats."""
     n, na, nb = 6, 3, 2
     h, eri = make_integrals(n, n, 1203)
     pool = enumerate_pool(n)
@@ -42,6 +43,8 @@ def test_join_model_open_shell_and_dead_entries():
     alive = ~np.isnan(amps)
     st = oracle.OracleState.from_arrays(keys[alive], amps[alive])
     orc = oracle.Oracle(n, na, nb, h, eri)
-    g, X_dec, X_enum, fmt = jm.join_gradients(keys, amps, pool, h, eri, na, nb)
-    assert np.array_equal(X_dec, X_enum)
-    assert np.abs(g - orc.pool_gradients(st, pool)).max() < 1e-12
+    g_ref = orc.pool_gradients(st, pool)
+    for orbital in (None, False):
+        g, X_dec, X_enum, fmt = jm.join_gradients(keys, amps, pool, h, eri, na, nb, orbital)
+        assert np.array_equal(X_dec, X_enum)
+        assert np.abs(g - g_ref).max() < 1e-12
