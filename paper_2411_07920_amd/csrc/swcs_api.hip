@@ -329,6 +329,19 @@ void release_scratch(swcs_ctx* c) {
   for (DevBuf* b : bufs) b->release();
 }
 
+// The sort-and-join pool pass keeps its records, sort buffers and source
+// table between calls (they hold nothing); a table pass that sizes itself
+// from free memory gives them back first when they are large, so that the
+// join of a smaller state earlier does not shrink (and split into batches)
+// the table of a larger one.
+void release_join_scratch(swcs_ctx* c) {
+  DevBuf* bufs[] = {&c->hp_key, &c->hp_tk, &c->join_src, &c->sort_scratch};
+  size_t held = 0;
+  for (DevBuf* b : bufs) held += b->bytes;
+  if (held < ((size_t)1 << 30)) return;
+  for (DevBuf* b : bufs) b->release();
+}
+
 u64 max_capacity(swcs_ctx* c) {
   u64 cap = c->sector;
   if (c->max_dets > 0 && (u64)c->max_dets < cap) cap = (u64)c->max_dets;
@@ -1509,8 +1522,10 @@ static int screened_gradients(swcs_ctx* c, u64 n, u64 alive, const int* d_subset
   auto batches = [&]() {
     int nb = 1;
     if (budget <= 0.0 && (double)slots_for(1) * sizeof(AccSlot) <= kQueryBoundBytes) return nb;
-    if (budget <= 0.0)
+    if (budget <= 0.0) {
+      release_join_scratch(c);
       budget = std::max<double>(64.0 * 1024 * 1024, 0.4 * (double)(avail_bytes(c) + c->acc_tab.bytes));
+    }
     while (nb < 4096 && (double)slots_for(nb) * sizeof(AccSlot) > budget) nb *= 2;
     return nb;
   };
@@ -1771,6 +1786,7 @@ int swcs_pool_gradients(swcs_ctx* c, const int32_t* subset, int64_t n_subset, do
   if (c->table_budget > 0) {
     budget = (double)c->table_budget;
   } else if (4.0 * guess * sizeof(AccSlot) > budget) {
+    release_join_scratch(c);
     budget = std::max<double>(64.0 * 1024 * 1024, 0.4 * (double)(avail_bytes(c) + c->acc_tab.bytes));
   }
   const int sgrid = sigma_grid(c, n);
