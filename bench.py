@@ -62,6 +62,12 @@ def parse():
                     help="instead of the step benchmark: ADAPT iteration time, screened vs "
                          "full pool, on this workload (prints its own JSON line)")
     ap.add_argument("--iters", type=int, default=150)
+    ap.add_argument("--adapt-segment", default=None, choices=sorted(CONFIGS),
+                    help="instead of the step benchmark: one screened ADAPT run on this workload "
+                         "that continues from --checkpoint if it exists, writes it after every "
+                         "iteration and stops after --time-limit seconds (a long run in segments)")
+    ap.add_argument("--checkpoint", default=None, help="checkpoint file of --adapt-segment")
+    ap.add_argument("--time-limit", type=float, default=None, help="seconds per --adapt-segment run")
     ap.add_argument("--large-state", type=int, default=16_000_000,
                     help="determinants of the synthetic state for the HBM-path gate and sigma "
                          "measurement added to the step line (0 = skip)")
@@ -438,6 +444,44 @@ def adapt_bench(args):
     print(json.dumps(out))
 
 
+def adapt_segment(args):
+    """One segment of a long screened ADAPT run (the learned screener with the
+    workload's eps and L-BFGS), resumed from and saved to args.checkpoint, up
+    to args.iters iterations in all; prints one JSON line for the segment."""
+    import torch
+    from paper_2411_07920_amd import adapt, swcs
+
+    torch.cuda.set_device(0)
+    wl = Workload(args.adapt_segment)
+    c = wl.c
+    ctx = swcs.make_context(c.n, wl.na, wl.na, wl.h, wl.eri, wl.pool, wl.ref,
+                            stream=torch.cuda.current_stream())
+    cfg = adapt.AdaptConfig(eps=c.eps, max_iter=args.iters, grad_tol=None, optimizer="lbfgs",
+                            screener=True, shadow_full=False, seed=3000 + int(args.adapt_segment[1:]))
+    done = []
+
+    def log(r):
+        done.append(r)
+        print(f"[adapt segment] it={r['iter']} E={r.get('E_after', r['E']):.10f} k={r['kstar']} "
+              f"exact={r['n_exact']} pool={1e3 * r['t_pool']:.1f}ms vqe={1e3 * r.get('t_vqe', 0.0):.1f}ms "
+              f"n_det={r['n_det']}", file=sys.stderr, flush=True)
+
+    t = time.perf_counter()
+    ops, theta, hist = adapt.run_adapt(ctx, wl.K, cfg, log=log, checkpoint=args.checkpoint,
+                                       time_limit=args.time_limit)
+    wall = time.perf_counter() - t
+    last = hist[-1] if hist else {}
+    print(json.dumps({
+        "metric": "ADAPT segment (screened)",
+        "workload": f"{args.adapt_segment}: {c.n_so} spin-orbitals, {c.n_elec} electrons, eps={c.eps:g}, "
+                    f"pool {wl.K}",
+        "iterations_total": len(hist), "iterations_this_segment": len(done), "target": args.iters,
+        "wall_s": wall, "E_last": last.get("E_after", last.get("E")), "n_det_last": last.get("n_det"),
+        "ms_per_iteration_this_segment": 1e3 * wall / max(1, len(done)),
+    }))
+    ctx.close()
+
+
 def large_state_bench(N, sigma=True):
     """Gate and sigma_P kernels on a structure-free synthetic state of N
     determinants in the 52-spin-orbital, 16-electron sector (uniform alpha and
@@ -725,6 +769,9 @@ def main():
         sys.exit(2)
     if args.adapt:
         adapt_bench(args)
+        return
+    if args.adapt_segment:
+        adapt_segment(args)
         return
     if args.uccsd:
         uccsd_bench(args)

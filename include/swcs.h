@@ -153,10 +153,11 @@ int swcs_set_sigma_method(swcs_ctx* ctx, int method);
  * (D, X) pair (alive * (C + 1) records, C the connections per determinant),
  * sorts them by a hash of X and forms sigma(X) and the gradients per group
  * in LDS; it needs 16 bytes per record of device memory and storage index,
- * connection ordinal and 8 to 24 hash bits within one 64-bit word.  AUTO
- * (default) takes JOIN when no table budget is set, the records fit within
- * half of the free device memory and the word, else TABLE; a JOIN pass whose
- * hash group overflows its LDS table is redone by TABLE.  Forced JOIN that
+ * connection fields and 8 to 24 hash bits within one 64-bit word.  AUTO
+ * (default) takes JOIN when no table budget is set, there are at most 2^31
+ * records (beyond that the table was faster at 52 spin-orbitals) and they fit
+ * within half of the free device memory and the word, else TABLE; a JOIN pass
+ * whose hash group overflows its LDS table is redone by TABLE.  Forced JOIN that
  * does not fit returns SWCS_E_CAPACITY.  Both agree up to summation order.
  * Returns SWCS_E_INVALID for an unknown method. */
 enum { SWCS_POOL_AUTO = 0, SWCS_POOL_TABLE = 1, SWCS_POOL_JOIN = 2 };

@@ -388,6 +388,8 @@ hipError_t launch_reduce_partials(const double* partial, int count, int stride, 
 // Full-pool gradients by sort and join (k_join.hip); kJoinRunHost records
 // per step of the join kernel.
 constexpr u64 kJoinRunHost = 2048;
+// Largest record count for which SWCS_POOL_AUTO takes the join.
+constexpr u64 kJoinAutoMaxRecords = 1ULL << 31;
 bool join_format(const ExcSpace& E, u64 n, u64 R, int* kb, int* bh, int* bp, int* orb);
 hipError_t launch_join_emit(const DeviceState& st, const ExcSpace& E, u64 n, u64* recs, u64 cap_recs,
                             u64* cursor, int kb, int bh, int bp, int orb, void* src, int grid, hipStream_t stream);
