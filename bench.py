@@ -253,7 +253,7 @@ def gpu_bench(args, wl):
     reps = 3
     for kname in ("chain_lds", "gate", "adjoint_lds", "adjoint_replay_lds", "gate_replay", "adjoint_rec", "sigma_proj",
                   "holepair", "sigma_push", "sigma_push_into", "pool_contract", "contract_ops", "select",
-                  "join_emit", "join_sort", "join_reduce"):
+                  "join_emit", "join_sort", "join_reduce", "join_terms"):
         if not args.kernel_times:
             break
         ctx.timer_start(kname)
@@ -280,7 +280,8 @@ def algorithmic_bytes(kname, wl, r):
     Whole-pool gradients by sort and join: 8 B per (source, connection)
     record written (plus 16 B per source read) by the emit; 16 B per record
     and radix pass (read and written once) by the sort; 8 B per record read
-    and 8 B per gradient update by the join."""
+    and 8 B per gradient update by the join; the binned gradient terms (8 B
+    value and 2 B operator index per pair record) read once by their sum."""
     from paper_2411_07920_amd.inputs import sector_size  # noqa: F401
     n_in = r["n_in"]
     M = len(n_in)
@@ -303,6 +304,8 @@ def algorithmic_bytes(kname, wl, r):
         return n * (C * 8.0 + 16.0)
     if kname == "contract_ops":
         return n * 16.0 + wl.n_top * 0.0
+    if kname == "join_terms":
+        return n * C * 10.0
     if kname in ("join_emit", "join_sort", "join_reduce"):
         R = n * (C + 1)
         if kname == "join_emit":

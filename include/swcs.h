@@ -153,7 +153,10 @@ int swcs_set_sigma_method(swcs_ctx* ctx, int method);
  * (D, X) pair (alive * (C + 1) records, C the connections per determinant),
  * sorts them by a hash of X and forms sigma(X) and the gradients per group
  * in LDS; it needs 16 bytes per record of device memory and storage index,
- * connection fields and 8 to 24 hash bits within one 64-bit word.  AUTO
+ * connection fields and 8 to 24 hash bits within one 64-bit word.  When
+ * another 12.5 bytes per record fit as well, the gradient terms are summed
+ * through per-operator bins (LDS sums, then one device-scope add per
+ * operator and bin chunk) instead of one device-scope add per record.  AUTO
  * (default) takes JOIN when no table budget is set, there are at most 2^31
  * records (beyond that the table was faster at 52 spin-orbitals) and they fit
  * within half of the free device memory and the word, else TABLE; a JOIN pass
@@ -342,7 +345,8 @@ enum {
   SWCS_K_SELECT = 13,        /* screener selection (top + random), swcs_select   */
   SWCS_K_JOIN_EMIT = 14,     /* full-pool gradients: one record per connection   */
   SWCS_K_JOIN_SORT = 15,     /* full-pool gradients: radix sort of the records   */
-  SWCS_K_JOIN_REDUCE = 16    /* full-pool gradients: sigma and g per bucket run  */
+  SWCS_K_JOIN_REDUCE = 16,   /* full-pool gradients: sigma and g per bucket run  */
+  SWCS_K_JOIN_TERMS = 17     /* full-pool gradients: sums of the binned g terms  */
 };
 
 /* From now on record HIP events on the context stream around every launch

@@ -169,14 +169,43 @@ __device__ inline void for_each_connection(const ConnTables& T, u64 D, F&& f) {
   }
 }
 
+// Generator table (P, Q, R, S) -> pool index for nsp spatial orbitals:
+// singles (P > Q, one spin) at pair(P, Q) = P (P - 1) / 2 + Q; doubles by the
+// spin class of their pairs -- both alpha, both beta, mixed -- each class a
+// triangle over its own pair indices (p (p - 1) / 2 + q for a same-spin pair
+// of spatial orbitals p > q; alpha * nsp + beta for a mixed pair).  A
+// spin-conserving double pairs two pairs of one class, so the table holds
+// 2 tri(nsp (nsp - 1) / 2) + tri(nsp^2) double slots (333,450 at nsp = 26,
+// 1.3 MB, against 878,475 for a triangle over all spin-orbital pairs), and
+// the lookups of the pool kernels stay in L2.
+__host__ __device__ inline int pair_index(int a, int b) { return a * (a - 1) / 2 + b; }
+
+__host__ __device__ inline long long optab_size(int nsp) {
+  const long long nso = 2LL * nsp, ss = (long long)nsp * (nsp - 1) / 2, mx = (long long)nsp * nsp;
+  return nso * (nso - 1) / 2 + ss * (ss - 1) + mx * (mx - 1) / 2;
+}
+
+// Slot of the double (P, Q, R, S): P > Q, R > S, both pairs of one spin class.
+__host__ __device__ inline int optab_double_slot(int nsp, int P, int Q, int R, int S) {
+  const int nso = 2 * nsp, ss = nsp * (nsp - 1) / 2;
+  int a, b, base = nso * (nso - 1) / 2;
+  if ((P & 1) == (Q & 1)) {
+    a = pair_index(P >> 1, Q >> 1);
+    b = pair_index(R >> 1, S >> 1);
+    if (P & 1) base += ss * (ss - 1) / 2;
+  } else {
+    a = ((P & 1) ? Q : P) / 2 * nsp + ((P & 1) ? P : Q) / 2;
+    b = ((R & 1) ? S : R) / 2 * nsp + ((R & 1) ? R : S) / 2;
+    base += ss * (ss - 1);
+  }
+  const int hi = a > b ? a : b, lo = a > b ? b : a;
+  return base + pair_index(hi, lo);
+}
+
 // Operator of the pool that links D to its connection (holes h0 < h1,
 // particles p0 < p1): returns its index (or -1), whether T (rather than
-// T^dagger) acts on D, and the operator's (P, Q, R, S).  The generator table
-// is indexed directly: singles at pair(P, Q), doubles at npairs +
-// tri(pair(P, Q)) + pair(R, S) with pair(a, b) = a (a - 1) / 2 + b.
-__device__ inline int pair_index(int a, int b) { return a * (a - 1) / 2 + b; }
-
-__device__ inline int linking_operator(const int* __restrict__ optab, int npairs, int nh, int h0,
+// T^dagger) acts on D, and the operator's (P, Q, R, S).
+__device__ inline int linking_operator(const int* __restrict__ optab, int nsp, int nh, int h0,
                                        int h1, int p0, int p1, bool* t_acts, OpDesc* op) {
   if (nh == 1) {
     *t_acts = p0 > h0;
@@ -190,8 +219,7 @@ __device__ inline int linking_operator(const int* __restrict__ optab, int npairs
   op->Q = *t_acts ? p0 : h0;
   op->R = *t_acts ? h1 : p1;
   op->S = *t_acts ? h0 : p0;
-  const int pq = pair_index(op->P, op->Q), rs = pair_index(op->R, op->S);
-  return optab[npairs + pq * (pq - 1) / 2 + rs];
+  return optab[optab_double_slot(nsp, op->P, op->Q, op->R, op->S)];
 }
 
 }  // namespace swcs

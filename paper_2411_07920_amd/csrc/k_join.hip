@@ -282,44 +282,110 @@ __device__ inline bool join_connection(const JoinFmt& fm, const ExcSpace& E, u64
   return true;
 }
 
+// 64-bit lane exchange: the value v of lane src.
+__device__ inline u64 shfl_u64(u64 v, int src) {
+  const unsigned lo = (unsigned)__shfl((int)(unsigned)v, src);
+  const unsigned hi = (unsigned)__shfl((int)(unsigned)(v >> 32), src);
+  return ((u64)hi << 32) | lo;
+}
+
+// <X|H|D> for the single excitations X = a+_A a_Ih D held by the lanes set
+// in ball (each lane its own D, Ih and A), formed by the whole wavefront:
+// sixteen lanes per excitation, each adding the two-electron terms of every
+// sixteenth occupied spin-orbital of D, then a four-step reduction.  A wave
+// whose records include a single (most waves: singles are scattered through
+// the sorted records) thus pays one round of integral loads per four
+// singles instead of one per electron.  Called by every lane of the wave.
+// Returns the element in the lanes set in ball.
+__device__ inline double single_elements_wave(const Ints& I, u64 ball, u64 D, int Ih, int A) {
+  const int lane = (int)(threadIdx.x & 63u);
+  const int g = lane >> 4, j = lane & 15;
+  const int cnt = __popcll(ball);
+  const bool mine = ((ball >> lane) & 1ULL) != 0;
+  const int rank = __popcll(ball & ((1ULL << lane) - 1ULL));
+  double two = 0.0;
+  for (int base = 0; base < cnt; base += 4) {
+    const bool act = base + g < cnt;
+    const int from = act ? select_bit(ball, (unsigned)(base + g)) : lane;
+    const u64 Dg = shfl_u64(D, from);
+    const int Ig = __shfl(Ih, from), Ag = __shfl(A, from);
+    double t = 0.0;
+    if (act) {
+      const int a = Ag >> 1, i = Ig >> 1, ne = __popcll(Dg);
+      for (int r = j; r < ne; r += 16) {
+        const int Q = select_bit(Dg, (unsigned)r);
+        const int q = Q >> 1;
+        t += eri_sp(I, a, i, q, q);
+        if (((Q ^ Ag) & 1) == 0) t -= eri_sp(I, a, q, q, i);
+      }
+    }
+    t += __shfl_xor(t, 8);
+    t += __shfl_xor(t, 4);
+    t += __shfl_xor(t, 2);
+    t += __shfl_xor(t, 1);
+    const double got = __shfl(t, ((rank - base) & 3) << 4);
+    if (mine && rank >= base && rank < base + 4) two = got;
+  }
+  if (!mine) return 0.0;
+  int s = __popcll(D & ((1ULL << Ih) - 1ULL));
+  s += __popcll((D ^ (1ULL << Ih)) & ((1ULL << A) - 1ULL));
+  const double v = I.h[(A >> 1) * I.n + (Ih >> 1)] + two;
+  return (s & 1) ? -v : v;
+}
+
 // First pass over one record: sigma(X) += H_{X D} psi(D) (or H_{D D} psi(D)
 // for the record of D itself) in the LDS table; *s_bad is set when the table
 // is full.  With term, also the record's gradient term: *k the linking
 // operator (-1 for none, for an operator not selected and for D itself), *sl
-// the LDS slot of X and *w = psi(D) a_k(D).
-__device__ inline void join_record_sigma(u64 rec, const JoinFmt& fm, const JoinSrc* __restrict__ src,
+// the LDS slot of X and *w = psi(D) a_k(D).  Called by every lane of the
+// wave (singles are formed by the wave together); lanes without a record
+// pass valid = false.
+__device__ inline void join_record_sigma(bool valid, u64 rec, const JoinFmt& fm, const JoinSrc* __restrict__ src,
                                          const double* __restrict__ diag, u64 n, const Ints& I,
-                                         const ExcSpace& E, const int* __restrict__ optab, int npairs,
+                                         const ExcSpace& E, const int* __restrict__ optab, int nsp,
                                          const unsigned char* __restrict__ selected, const unsigned char* px,
                                          const unsigned char* py, u64* tk, double* tv, double* ins,
                                          unsigned* s_bad, bool term, int* k, int* sl, double* w) {
   *k = -1;
   *sl = 0;
   *w = 0.0;
-  const JoinRec r = join_rec(rec, fm);
-  if (r.d >= n) return;
-  const bool self = join_is_self(fm, r);
-  const JoinSrc sd = src[r.d];
-  const u64 D = sd.key;
-  const double psi = sd.psi;
-  u64 X = D;
-  double v;
+  bool ok = valid;
+  JoinRec r{0, 0};
+  JoinSrc sd{0, 0.0};
+  if (ok) {
+    r = join_rec(rec, fm);
+    ok = r.d < n;
+  }
+  u64 X = 0;
+  double v = 0.0;
   int kk = -1;
   double a = 0.0;
-  if (self) {
-    v = diag[r.d] * psi;
-  } else {
-    int nh, h0, h1, p0, p1;
-    if (!join_connection(fm, E, D, r, px, py, &X, &nh, &h0, &h1, &p0, &p1)) return;
-    v = connection_element(I, D, nh, h0, h1, p0, p1) * psi;
-    if (term) {
-      bool t_acts;
-      OpDesc op;
-      kk = linking_operator(optab, npairs, nh, h0, h1, p0, p1, &t_acts, &op);
-      if (kk >= 0 && selected && !selected[kk]) kk = -1;
-      if (kk >= 0) a = t_acts ? (double)phase_of_T(op, D) : -(double)phase_of_T(op, X);
+  int nh = 0, h0 = 0, h1 = 0, p0 = 0, p1 = 0;
+  if (ok) {
+    sd = src[r.d];
+    X = sd.key;
+    if (join_is_self(fm, r)) {
+      v = diag[r.d] * sd.psi;
+    } else if (!join_connection(fm, E, sd.key, r, px, py, &X, &nh, &h0, &h1, &p0, &p1)) {
+      ok = false;
+    } else {
+      if (nh == 2) v = double_element(I, sd.key, h0, h1, p0, p1) * sd.psi;
+      if (term) {
+        bool t_acts;
+        OpDesc op;
+        kk = linking_operator(optab, nsp, nh, h0, h1, p0, p1, &t_acts, &op);
+        if (kk >= 0 && selected && !selected[kk]) kk = -1;
+        if (kk >= 0) a = t_acts ? (double)phase_of_T(op, sd.key) : -(double)phase_of_T(op, X);
+      }
     }
   }
+  const bool single = ok && nh == 1;
+  const u64 ball = __ballot(single);
+  if (ball != 0) {  // uniform over the wave
+    const double e = single_elements_wave(I, ball, sd.key, h0, p0);
+    if (single) v = e * sd.psi;
+  }
+  if (!ok) return;
   const int s = join_slot(tk, X, true, ins);
   if (s < 0) {
     *s_bad = 1;
@@ -329,7 +395,7 @@ __device__ inline void join_record_sigma(u64 rec, const JoinFmt& fm, const JoinS
   if (kk >= 0) {
     *k = kk;
     *sl = s;
-    *w = psi * a;
+    *w = sd.psi * a;
   }
 }
 
@@ -345,9 +411,16 @@ __global__ void __launch_bounds__(kJoinBlock)
 k_join_reduce(const u64* __restrict__ recs, u64 R, const u64* __restrict__ cursor, JoinFmt fm,
               const JoinSrc* __restrict__ src, const double* __restrict__ diag, u64 n, Ints I, ExcSpace E,
               const int* __restrict__ optab,
-              int npairs, const unsigned char* __restrict__ selected, double* __restrict__ gacc,
-              unsigned* __restrict__ flags, double* __restrict__ inserted) {
+              int nsp, const unsigned char* __restrict__ selected, double* __restrict__ gacc,
+              JoinTerms terms, unsigned* __restrict__ flags, double* __restrict__ inserted) {
   __shared__ u64 tk[kJoinSlots];
+  __shared__ unsigned s_bcnt[1 << kJoinMaxBinsLog], s_boff[1 << kJoinMaxBinsLog];
+  __shared__ u64 s_bbase[1 << kJoinMaxBinsLog];
+  __shared__ unsigned s_nterm;
+  // the staged terms of a step (8 B value, 2 B operator, 1 B bin each) fit
+  // the key table
+  static_assert(kJoinCache * kJoinBlock * (8 + 2 + 1) <= kJoinSlots * 8, "staging");
+  static_assert((1 << kJoinMaxBinsLog) <= 4 * 64 && (1 << kJoinMaxBinsLog) <= kJoinBlock, "bin scan");
   __shared__ double tv[kJoinSlots];
   __shared__ unsigned char px[kMaxPairs], py[kMaxPairs];
   __shared__ unsigned s_found, s_bad;
@@ -371,6 +444,8 @@ k_join_reduce(const u64* __restrict__ recs, u64 R, const u64* __restrict__ curso
     px[s] = (unsigned char)(s - y * (y - 1) / 2);
   }
   for (int s = threadIdx.x; s < kJoinSlots; s += kJoinBlock) tk[s] = kEmptyKey;
+  const int nbins = terms.lb >= 0 ? 1 << terms.lb : 0;
+  for (int b = threadIdx.x; b < nbins; b += kJoinBlock) s_bcnt[b] = 0;
   for (u64 p = (u64)blockIdx.x * kJoinRun; p < R; p += (u64)gridDim.x * kJoinRun) {
     const u64 lo = bucket_boundary(recs, R, p, bmask, &s_found, &s_pos);
     const u64 hi = bucket_boundary(recs, R, p + kJoinRun, bmask, &s_found, &s_pos);
@@ -387,26 +462,33 @@ k_join_reduce(const u64* __restrict__ recs, u64 R, const u64* __restrict__ curso
 #pragma unroll
     for (int m = 0; m < kJoinCache; ++m) {
       const u64 i = lo + threadIdx.x + (u64)m * kJoinBlock;
-      ck[m] = -1;
-      csl[m] = 0;
-      cw[m] = 0.0;
-      if (i < hi) join_record_sigma(recs[i], fm, src, diag, n, I, E, optab, npairs, selected, px, py, tk, tv, &ins,
-                                    &s_bad, true, &ck[m], &csl[m], &cw[m]);
+      const bool valid = i < hi;
+      join_record_sigma(valid, valid ? recs[i] : 0, fm, src, diag, n, I, E, optab, nsp, selected, px, py, tk,
+                        tv, &ins, &s_bad, true, &ck[m], &csl[m], &cw[m]);
     }
-    for (u64 i = lo + threadIdx.x + (u64)kJoinCache * kJoinBlock; i < hi; i += kJoinBlock) {
+    // (b is uniform over the block, so every lane of a wave takes part)
+    for (u64 b = lo + (u64)kJoinCache * kJoinBlock; b < hi; b += kJoinBlock) {
+      const u64 i = b + threadIdx.x;
+      const bool valid = i < hi;
       int k, sl;
       double w;
-      join_record_sigma(recs[i], fm, src, diag, n, I, E, optab, npairs, selected, px, py, tk, tv, &ins, &s_bad,
-                        false, &k, &sl, &w);
+      join_record_sigma(valid, valid ? recs[i] : 0, fm, src, diag, n, I, E, optab, nsp, selected, px, py, tk,
+                        tv, &ins, &s_bad, false, &k, &sl, &w);
     }
     __syncthreads();
     if (s_bad) {
       if (threadIdx.x == 0) atomicOr(flags, kFlagOverflow);
     } else {
-      // psi(D) a_k(D) sigma(X) for every pair record
+      // psi(D) a_k(D) sigma(X) for every pair record: the terms of the
+      // records beyond the cached ones go straight to g[k]; with bins, the
+      // cached terms are then appended to their operator's bin -- ranks
+      // from LDS counters, one cursor add per bin and step, the step's
+      // terms staged in LDS in bin order (over the key table, which is no
+      // longer read) and written as one contiguous run per bin.  A term
+      // past its bin's capacity goes straight to g[k].
+      double xv[kJoinCache];
 #pragma unroll
-      for (int m = 0; m < kJoinCache; ++m)
-        if (ck[m] >= 0) unsafeAtomicAdd(&gacc[ck[m]], cw[m] * tv[csl[m]]);
+      for (int m = 0; m < kJoinCache; ++m) xv[m] = ck[m] >= 0 ? cw[m] * tv[csl[m]] : 0.0;
       for (u64 i = lo + threadIdx.x + (u64)kJoinCache * kJoinBlock; i < hi; i += kJoinBlock) {
         const JoinRec r = join_rec(recs[i], fm);
         if (r.d >= n || join_is_self(fm, r)) continue;
@@ -417,12 +499,77 @@ k_join_reduce(const u64* __restrict__ recs, u64 R, const u64* __restrict__ curso
         if (!join_connection(fm, E, D, r, px, py, &X, &nh, &h0, &h1, &p0, &p1)) continue;
         bool t_acts;
         OpDesc op;
-        const int k = linking_operator(optab, npairs, nh, h0, h1, p0, p1, &t_acts, &op);
+        const int k = linking_operator(optab, nsp, nh, h0, h1, p0, p1, &t_acts, &op);
         if (k < 0 || (selected && !selected[k])) continue;
         const int sl = join_slot(tk, X, false, &ins);
         if (sl < 0) continue;  // not reached: pass 1 inserted every key of the step
         const double a = t_acts ? (double)phase_of_T(op, D) : -(double)phase_of_T(op, X);
         unsafeAtomicAdd(&gacc[k], sd.psi * a * tv[sl]);
+      }
+      if (nbins > 0) {
+        unsigned rk[kJoinCache];
+#pragma unroll
+        for (int m = 0; m < kJoinCache; ++m)
+          rk[m] = ck[m] >= 0 ? atomicAdd(&s_bcnt[ck[m] & (nbins - 1)], 1u) : 0u;
+        __syncthreads();
+        if (threadIdx.x < (unsigned)nbins) {
+          const unsigned c = s_bcnt[threadIdx.x];
+          s_bbase[threadIdx.x] =
+              c ? (u64)atomicAdd((unsigned long long*)&terms.cursor[threadIdx.x], (unsigned long long)c) : 0ULL;
+        }
+        if (threadIdx.x < 64) {  // exclusive scan of the counts, four bins per lane
+          const int l = (int)threadIdx.x;
+          unsigned c4[4], sum = 0;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int b = 4 * l + q;
+            c4[q] = b < nbins ? s_bcnt[b] : 0u;
+            sum += c4[q];
+          }
+          unsigned inc = sum;
+          for (int off = 1; off < 64; off <<= 1) {
+            const unsigned v = __shfl_up(inc, off);
+            if (l >= off) inc += v;
+          }
+          unsigned run = inc - sum;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int b = 4 * l + q;
+            if (b < nbins) s_boff[b] = run;
+            run += c4[q];
+          }
+          if (l == 63) s_nterm = inc;
+        }
+        __syncthreads();
+        double* sw = reinterpret_cast<double*>(tk);
+        unsigned short* sj = reinterpret_cast<unsigned short*>(tk + kJoinCache * kJoinBlock);
+        unsigned char* sb = reinterpret_cast<unsigned char*>(tk + kJoinCache * kJoinBlock * 5 / 4);
+#pragma unroll
+        for (int m = 0; m < kJoinCache; ++m) {
+          if (ck[m] < 0) continue;
+          const int b = ck[m] & (nbins - 1);
+          const unsigned lp = s_boff[b] + rk[m];
+          sw[lp] = xv[m];
+          sj[lp] = (unsigned short)(ck[m] >> terms.lb);
+          sb[lp] = (unsigned char)b;
+        }
+        if (threadIdx.x < (unsigned)nbins) s_bcnt[threadIdx.x] = 0;
+        __syncthreads();
+        const unsigned total = s_nterm;
+        for (unsigned i = threadIdx.x; i < total; i += kJoinBlock) {
+          const int b = sb[i];
+          const u64 pos = s_bbase[b] + (i - s_boff[b]);
+          if (pos < terms.cap) {
+            terms.w[(u64)b * terms.cap + pos] = sw[i];
+            terms.j[(u64)b * terms.cap + pos] = sj[i];
+          } else {
+            unsafeAtomicAdd(&gacc[((long long)sj[i] << terms.lb) | b], sw[i]);
+          }
+        }
+      } else {
+#pragma unroll
+        for (int m = 0; m < kJoinCache; ++m)
+          if (ck[m] >= 0) unsafeAtomicAdd(&gacc[ck[m]], xv[m]);
       }
     }
     __syncthreads();
@@ -471,11 +618,65 @@ hipError_t launch_join_emit(const DeviceState& st, const ExcSpace& E, u64 n, u64
 
 hipError_t launch_join_reduce(const DeviceState& st, const u64* recs, u64 R, const u64* cursor, int kb, int bh,
                               int bp, int orb, const void* src, u64 n, const Ints& I, const ExcSpace& E,
-                              const int* optab, int npairs, const unsigned char* selected, double* gacc,
-                              double* inserted, int grid, hipStream_t stream) {
+                              const int* optab, int nsp, const unsigned char* selected, double* gacc,
+                              JoinTerms terms, double* inserted, int grid, hipStream_t stream) {
+  if (terms.lb > kJoinMaxBinsLog) return hipErrorInvalidValue;
   const JoinFmt fm{kb, bh, bp, orb};
   hipLaunchKernelGGL(k_join_reduce, dim3(grid), dim3(kJoinBlock), 0, stream, recs, R, cursor, fm,
-                     (const JoinSrc*)src, st.diag, n, I, E, optab, npairs, selected, gacc, &st.ctr->flags, inserted);
+                     (const JoinSrc*)src, st.diag, n, I, E, optab, nsp, selected, gacc, terms, &st.ctr->flags,
+                     inserted);
+  return hipGetLastError();
+}
+
+// One block per (bin, chunk of kJoinTermChunk terms): the chunk's terms are
+// added into an LDS table of the bin's operators, then each nonzero sum goes
+// to g[k] with one device-scope add.
+constexpr u64 kJoinTermChunk = 1ULL << 20;
+__global__ void __launch_bounds__(kJoinBlock)
+k_join_terms(JoinTerms terms, int per_bin, double* __restrict__ gacc, long long K) {
+  __shared__ double acc[kJoinTermSlots];
+  const int b = (int)(blockIdx.x / (unsigned)per_bin);
+  const u64 c = blockIdx.x % (unsigned)per_bin;
+  const u64 filled = terms.cursor[b] < terms.cap ? terms.cursor[b] : terms.cap;
+  const u64 lo = c * kJoinTermChunk;
+  if (lo >= filled) return;  // uniform over the block
+  const u64 hi = lo + kJoinTermChunk < filled ? lo + kJoinTermChunk : filled;
+  for (int s = threadIdx.x; s < kJoinTermSlots; s += kJoinBlock) acc[s] = 0.0;
+  __syncthreads();
+  const double* __restrict__ w = terms.w + (u64)b * terms.cap;
+  const unsigned short* __restrict__ j = terms.j + (u64)b * terms.cap;
+  // four terms per thread and load (chunks start at multiples of four and
+  // bins at multiples of eight entries, so the vector loads are aligned)
+  const u64 n4 = (hi - lo) / 4;
+  const double2* __restrict__ w2 = reinterpret_cast<const double2*>(w + lo);
+  const ushort4* __restrict__ j4 = reinterpret_cast<const ushort4*>(j + lo);
+  for (u64 q = threadIdx.x; q < n4; q += kJoinBlock) {
+    const double2 a = w2[2 * q], bb = w2[2 * q + 1];
+    const ushort4 s = j4[q];
+    if (s.x < kJoinTermSlots) atomicAdd(&acc[s.x], a.x);
+    if (s.y < kJoinTermSlots) atomicAdd(&acc[s.y], a.y);
+    if (s.z < kJoinTermSlots) atomicAdd(&acc[s.z], bb.x);
+    if (s.w < kJoinTermSlots) atomicAdd(&acc[s.w], bb.y);
+  }
+  for (u64 i = lo + 4 * n4 + threadIdx.x; i < hi; i += kJoinBlock) {
+    const unsigned s = j[i];
+    if (s < (unsigned)kJoinTermSlots) atomicAdd(&acc[s], w[i]);
+  }
+  __syncthreads();
+  for (int s = threadIdx.x; s < kJoinTermSlots; s += kJoinBlock) {
+    const double v = acc[s];
+    const long long k = ((long long)s << terms.lb) | b;
+    if (v != 0.0 && k < K) unsafeAtomicAdd(&gacc[k], v);
+  }
+}
+
+hipError_t launch_join_terms(JoinTerms terms, double* gacc, long long K, hipStream_t stream) {
+  if (terms.lb < 0) return hipSuccess;
+  if (terms.lb > kJoinMaxBinsLog) return hipErrorInvalidValue;
+  const u64 per_bin = (terms.cap + kJoinTermChunk - 1) / kJoinTermChunk;
+  const u64 grid = per_bin << terms.lb;
+  if (per_bin == 0 || grid > 0x7fffffffULL) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_join_terms, dim3((unsigned)grid), dim3(kJoinBlock), 0, stream, terms, (int)per_bin, gacc, K);
   return hipGetLastError();
 }
 

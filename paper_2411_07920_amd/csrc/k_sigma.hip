@@ -595,7 +595,7 @@ k_sigma_push(const u64* __restrict__ keys, const double* __restrict__ amps, Ints
 // (only X of the current batch when the sigma table is split).
 __global__ void __launch_bounds__(kSigBlock)
 k_pool_contract_det(const u64* __restrict__ keys, const double* __restrict__ amps, ExcSpace E,
-                    int n_spatial, u64 n, const int* __restrict__ optab, int npairs,
+                    int n_spatial, u64 n, const int* __restrict__ optab, int nsp,
                     const unsigned char* __restrict__ selected, const AccSlot* __restrict__ tab,
                     u64 tmask, int nbatch, int batch, double* __restrict__ gacc) {
   __shared__ SigShared S;
@@ -616,7 +616,7 @@ k_pool_contract_det(const u64* __restrict__ keys, const double* __restrict__ amp
       if (nbatch > 1 && batch_of(X, nbatch) != batch) return;
       bool t_acts;
       OpDesc op;
-      const int k = linking_operator(optab, npairs, nh, h0, h1, p0, p1, &t_acts, &op);
+      const int k = linking_operator(optab, nsp, nh, h0, h1, p0, p1, &t_acts, &op);
       if (k < 0) return;
       if (selected && !selected[k]) return;
       double sx;
@@ -654,7 +654,7 @@ __device__ inline void query_insert(AccSlot* tab, u64 tmask, u64 X, unsigned* qf
 }
 __global__ void __launch_bounds__(kSigBlock)
 k_query_set(const u64* __restrict__ keys, const double* __restrict__ amps, ExcSpace E, int n_spatial,
-            u64 n, const int* __restrict__ optab, int npairs,
+            u64 n, const int* __restrict__ optab, int nsp,
             const unsigned char* __restrict__ selected, AccSlot* __restrict__ tab, u64 tmask,
             int count_only, u64* __restrict__ counter, unsigned* __restrict__ flags, int nbatch, int batch,
             unsigned* __restrict__ qf, u64 qfmask) {
@@ -676,7 +676,7 @@ k_query_set(const u64* __restrict__ keys, const double* __restrict__ amps, ExcSp
     for_each_connection(T, D, [&](u64 X, int nh, int h0, int h1, int p0, int p1) {
       bool t_acts;
       OpDesc op;
-      const int k = linking_operator(optab, npairs, nh, h0, h1, p0, p1, &t_acts, &op);
+      const int k = linking_operator(optab, nsp, nh, h0, h1, p0, p1, &t_acts, &op);
       if (k < 0 || !selected[k]) return;
       if (count_only) {
         ++mine;
@@ -1005,21 +1005,21 @@ hipError_t launch_sigma_push(const DeviceState& st, const Ints& I, const ExcSpac
 }
 
 hipError_t launch_pool_contract_det(const DeviceState& st, const ExcSpace& E, int n_spatial, u64 n,
-                                   const int* optab, int npairs, const unsigned char* selected,
+                                   const int* optab, int nsp, const unsigned char* selected,
                                    const AccSlot* tab, u64 tmask, int nbatch, int batch,
                                    double* gacc, int grid, hipStream_t stream) {
   hipLaunchKernelGGL(k_pool_contract_det, dim3(grid), dim3(kSigBlock), conn_tables_bytes(E), stream, st.keys, st.amps,
-                     E, n_spatial, n, optab, npairs, selected, tab, tmask, nbatch, batch, gacc);
+                     E, n_spatial, n, optab, nsp, selected, tab, tmask, nbatch, batch, gacc);
   return hipGetLastError();
 }
 
 hipError_t launch_query_set(const DeviceState& st, const ExcSpace& E, int n_spatial, u64 n,
-                            const int* optab, int npairs, const unsigned char* selected,
+                            const int* optab, int nsp, const unsigned char* selected,
                             AccSlot* tab, u64 tmask, int count_only, u64* counter, int grid,
                             hipStream_t stream, int nbatch, int batch, unsigned* qf, u64 qfmask) {
   if (nbatch < 1 || batch < 0 || batch >= nbatch) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_query_set, dim3(grid), dim3(kSigBlock), conn_tables_bytes(E), stream, st.keys, st.amps, E,
-                     n_spatial, n, optab, npairs, selected, tab, tmask, count_only, counter,
+                     n_spatial, n, optab, nsp, selected, tab, tmask, count_only, counter,
                      &st.ctr->flags, nbatch, batch, qf, qfmask);
   return hipGetLastError();
 }

@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "../../include/swcs.h"
+#include "conn_ops.h"
 #include "gate_ops.h"
 #include "swcs_internal.h"
 
@@ -130,7 +131,6 @@ struct swcs_ctx {
   std::vector<OpDesc> ops_host;
   std::vector<int32_t> pool_rows;
   DevBuf ops, opmap;  // pool rows; generator table (P, Q, R, S) -> pool index
-  int npairs = 0;
 
   // state
   DevBuf keys, amps, hash, ctr, filt;
@@ -171,7 +171,8 @@ struct swcs_ctx {
   // scratch
   DevBuf gacc, selected, ncut_state, qfilt;
   DevBuf partial, partial2, sigma, mu, work, seg_states, acc_tab, gbuf, subset_buf, scalars,
-      exp_keys, exp_amps, exp_tmp_k, exp_tmp_v, sort_scratch, ctr_r, occ, sel_scratch, mlp_partial, mse_partial, hp_key, hp_val, hp_tk, hp_tv, diag, join_src;
+      exp_keys, exp_amps, exp_tmp_k, exp_tmp_v, sort_scratch, ctr_r, occ, sel_scratch, mlp_partial, mse_partial, hp_key, hp_val, hp_tk, hp_tv, diag, join_src,
+      join_w, join_j, join_bins;
   int sigma_method = SWCS_SIGMA_AUTO;
   int pool_method = SWCS_POOL_AUTO;
   double ext_count = 0.0, ext_alive = 0.0;  // distinct external keys of the last full pool pass
@@ -335,7 +336,7 @@ void release_scratch(swcs_ctx* c) {
 // join of a smaller state earlier does not shrink (and split into batches)
 // the table of a larger one.
 void release_join_scratch(swcs_ctx* c) {
-  DevBuf* bufs[] = {&c->hp_key, &c->hp_tk, &c->join_src, &c->sort_scratch};
+  DevBuf* bufs[] = {&c->hp_key, &c->hp_tk, &c->join_src, &c->sort_scratch, &c->join_w, &c->join_j};
   size_t held = 0;
   for (DevBuf* b : bufs) held += b->bytes;
   if (held < ((size_t)1 << 30)) return;
@@ -918,22 +919,13 @@ int swcs_set_pool(swcs_ctx* c, const int32_t* rows, int64_t K) {
     }
     ops[(size_t)k] = o;
   }
-  // Generator table (P, Q, R, S) -> pool index, indexed directly: singles at
-  // pair(P, Q), doubles at npairs + tri(pair(P, Q)) + pair(R, S), with
-  // pair(a, b) = a (a - 1) / 2 + b; -1 where the pool has no operator.
+  // Generator table (P, Q, R, S) -> pool index in the layout of
+  // optab_double_slot (conn_ops.h); -1 where the pool has no operator.
   // Rejects duplicate rows.
-  const int64_t npairs = (int64_t)c->nso * (c->nso - 1) / 2;
-  std::vector<int> optab((size_t)(npairs + npairs * (npairs - 1) / 2), -1);
-  auto pair_index = [](int64_t a, int64_t b) { return a * (a - 1) / 2 + b; };
+  std::vector<int> optab((size_t)optab_size(c->n), -1);
   for (int64_t k = 0; k < K; ++k) {
     const OpDesc& o = ops[(size_t)k];
-    int64_t slot;
-    if (o.R < 0) {
-      slot = pair_index(o.P, o.Q);
-    } else {
-      const int64_t pq = pair_index(o.P, o.Q), rs = pair_index(o.R, o.S);
-      slot = npairs + pq * (pq - 1) / 2 + rs;
-    }
+    const int64_t slot = o.R < 0 ? pair_index(o.P, o.Q) : optab_double_slot(c->n, o.P, o.Q, o.R, o.S);
     if (optab[(size_t)slot] >= 0)
       return fail(c, SWCS_E_INVALID, "pool row " + std::to_string(k) + " duplicates an earlier row");
     optab[(size_t)slot] = (int)k;
@@ -943,7 +935,6 @@ int swcs_set_pool(swcs_ctx* c, const int32_t* rows, int64_t K) {
   HIP_TRY(c, c->opmap.ensure(optab.size() * sizeof(int)), "alloc generator table");
   HIP_TRY(c, hipMemcpyAsync(c->opmap.p, optab.data(), optab.size() * sizeof(int), hipMemcpyHostToDevice, c->stream),
           "copy generator table");
-  c->npairs = (int)npairs;
   HIP_TRY(c, c->ops.ensure(std::max<size_t>(1, (size_t)K) * sizeof(OpDesc)), "alloc pool");
   if (K > 0)
     HIP_TRY(c, hipMemcpyAsync(c->ops.p, ops.data(), (size_t)K * sizeof(OpDesc), hipMemcpyHostToDevice, c->stream),
@@ -1495,7 +1486,7 @@ static int screened_gradients(swcs_ctx* c, u64 n, u64 alive, const int* d_subset
       HIP_TRY(c, launch_query_ops(c->st, n, c->ops.as<OpDesc>(), d_subset, n_subset, nullptr, 0, stride,
                                   qcount, c->stream), "count");
     else
-      HIP_TRY(c, launch_query_set(c->st, c->exc, c->n, n, c->opmap.as<int>(), c->npairs, d_sel,
+      HIP_TRY(c, launch_query_set(c->st, c->exc, c->n, n, c->opmap.as<int>(), c->n, d_sel,
                                   nullptr, 0, stride, qcount, sigma_grid(c, n), c->stream), "count");
     HIP_TRY(c, hipMemcpyAsync(&nq, qcount, 8, hipMemcpyDeviceToHost, c->stream), "copy");
     HIP_TRY(c, hipStreamSynchronize(c->stream), "sync");
@@ -1554,7 +1545,7 @@ static int screened_gradients(swcs_ctx* c, u64 n, u64 alive, const int* d_subset
                                     c->acc_tab.as<AccSlot>(), qslots - 1, 0, nullptr, c->stream, nbatch, b,
                                     qf, qbits - 1), "query set");
       else
-        HIP_TRY(c, launch_query_set(c->st, c->exc, c->n, n, c->opmap.as<int>(), c->npairs, d_sel,
+        HIP_TRY(c, launch_query_set(c->st, c->exc, c->n, n, c->opmap.as<int>(), c->n, d_sel,
                                     c->acc_tab.as<AccSlot>(), qslots - 1, 0, nullptr, sigma_grid(c, n),
                                     c->stream, nbatch, b, qf, qbits - 1), "query set");
       TIMED(c, SWCS_K_SIGMA_PUSH_INTO, launch_sigma_push_into(c->st, ints_view(c), c->exc, n, c->acc_tab.as<AccSlot>(),
@@ -1566,7 +1557,7 @@ static int screened_gradients(swcs_ctx* c, u64 n, u64 alive, const int* d_subset
                                                           c->acc_tab.as<AccSlot>(), qslots - 1, d_out, c->stream,
                                                           nbatch, b), "contract");
       else
-        TIMED(c, SWCS_K_POOL_CONTRACT, launch_pool_contract_det(c->st, c->exc, c->n, n, c->opmap.as<int>(), c->npairs,
+        TIMED(c, SWCS_K_POOL_CONTRACT, launch_pool_contract_det(c->st, c->exc, c->n, n, c->opmap.as<int>(), c->n,
                                                                 d_sel, c->acc_tab.as<AccSlot>(), qslots - 1, nbatch, b,
                                                                 c->gacc.as<double>(), sigma_grid(c, n), c->stream),
               "contract");
@@ -1675,10 +1666,29 @@ static int join_gradients(swcs_ctx* c, const Counters& h, const unsigned char* d
   const u64 list_bytes = n * 16;  // (key, psi) of every stored entry
   const double need = 16.0 * (double)R + 8.0 * (double)scr + (double)list_bytes;
   const double have = (double)(avail_bytes(c) + c->hp_key.bytes + c->hp_tk.bytes + c->sort_scratch.bytes +
-                               c->join_src.bytes);
+                               c->join_src.bytes + c->join_w.bytes + c->join_j.bytes);
   if (need > 0.5 * have) {
     if (forced) return fail(c, SWCS_E_CAPACITY, "join records exceed half of the free device memory");
     return 1;
+  }
+  // Gradient terms by operator bin (2^lb bins of at most kJoinTermSlots
+  // operators, k mod 2^lb), each with room for 1.25 times an even share of
+  // the records: the device-scope adds into g[K] then number about 8192 per
+  // bin and chunk instead of one per record.  Terms past a full bin, and
+  // every term when the bins do not fit, take the direct adds.
+  JoinTerms terms{-1, 0, nullptr, nullptr, nullptr};
+  {
+    int lb = 0;
+    while (lb <= kJoinMaxBinsLog && (u64)c->K_pool > ((u64)kJoinTermSlots << lb)) ++lb;
+    const u64 cap = ((u64)(1.25 * (double)R / (double)(1ULL << lb)) + 4096 + 7) & ~7ULL;
+    const double bin_bytes = 10.0 * (double)cap * (double)(1ULL << lb);
+    if (lb <= kJoinMaxBinsLog && need + bin_bytes <= 0.5 * have) {
+      HIP_TRY(c, c->join_w.ensure((size_t)(cap << lb) * 8), "alloc join terms");
+      HIP_TRY(c, c->join_j.ensure((size_t)(cap << lb) * 2), "alloc join terms");
+      HIP_TRY(c, c->join_bins.ensure((size_t)8 << lb), "alloc join bins");
+      HIP_TRY(c, launch_fill_u32(c->join_bins.p, 0u, (u64)2 << lb, c->stream), "zero bins");
+      terms = JoinTerms{lb, cap, c->join_bins.as<u64>(), c->join_w.as<double>(), c->join_j.as<unsigned short>()};
+    }
   }
   HIP_TRY(c, c->hp_key.ensure(R * 8), "alloc join records");
   HIP_TRY(c, c->hp_tk.ensure(R * 8), "alloc join records");
@@ -1699,8 +1709,10 @@ static int join_gradients(swcs_ctx* c, const Counters& h, const unsigned char* d
   double* ins = c->partial2.as<double>();
   TIMED(c, SWCS_K_JOIN_REDUCE, launch_join_reduce(c->st, sorted, R, cursor, kb, bh, bp, orb, c->join_src.p, n,
                                                   ints_view(c), c->exc, c->opmap.as<int>(),
-                                                  c->npairs, d_sel, c->gacc.as<double>(), ins, rgrid, c->stream),
+                                                  c->n, d_sel, c->gacc.as<double>(), terms, ins, rgrid,
+                                                  c->stream),
         "join reduce");
+  TIMED(c, SWCS_K_JOIN_TERMS, launch_join_terms(terms, c->gacc.as<double>(), c->K_pool, c->stream), "join terms");
   HIP_TRY(c, launch_reduce_partials(ins, rgrid, rgrid, 1, c->scalars.as<double>() + 24, c->stream), "count");
   double distinct = 0.0;
   HIP_TRY(c, hipMemcpyAsync(&distinct, c->scalars.as<double>() + 24, 8, hipMemcpyDeviceToHost, c->stream), "copy");
@@ -1809,7 +1821,7 @@ int swcs_pool_gradients(swcs_ctx* c, const int32_t* subset, int64_t n_subset, do
       HIP_TRY(c, launch_fill_u32(c->acc_tab.p, 0u, slots * (sizeof(AccSlot) / 4), c->stream), "clear table");
       TIMED(c, SWCS_K_SIGMA_PUSH, launch_sigma_push(c->st, ints_view(c), c->exc, n, c->acc_tab.as<AccSlot>(), slots - 1,
                                    nbatch, b, ins + (size_t)b * sgrid, sgrid, c->stream), "sigma push");
-      TIMED(c, SWCS_K_POOL_CONTRACT, launch_pool_contract_det(c->st, c->exc, c->n, n, c->opmap.as<int>(), c->npairs,
+      TIMED(c, SWCS_K_POOL_CONTRACT, launch_pool_contract_det(c->st, c->exc, c->n, n, c->opmap.as<int>(), c->n,
                                           d_sel, c->acc_tab.as<AccSlot>(), slots - 1, nbatch, b,
                                           c->gacc.as<double>(), sgrid, c->stream), "contract");
     }
@@ -2046,7 +2058,7 @@ int swcs_occupations(swcs_ctx* c, double* n_out) {
 
 int swcs_timer_start(swcs_ctx* c, int kernel_id) {
   if (!c) return SWCS_E_INVALID;
-  if (kernel_id < SWCS_K_CHAIN_LDS || kernel_id > SWCS_K_JOIN_REDUCE)
+  if (kernel_id < SWCS_K_CHAIN_LDS || kernel_id > SWCS_K_JOIN_TERMS)
     return fail(c, SWCS_E_INVALID, "unknown kernel id");
   c->timer_kernel = kernel_id;
   c->ev_used = 0;

@@ -393,19 +393,34 @@ constexpr u64 kJoinAutoMaxRecords = 1ULL << 31;
 bool join_format(const ExcSpace& E, u64 n, u64 R, int* kb, int* bh, int* bp, int* orb);
 hipError_t launch_join_emit(const DeviceState& st, const ExcSpace& E, u64 n, u64* recs, u64 cap_recs,
                             u64* cursor, int kb, int bh, int bp, int orb, void* src, int grid, hipStream_t stream);
+// Gradient terms of the join partitioned by operator: bin b = k mod 2^lb
+// holds the terms of operators k = j 2^lb + b (j < kJoinTermSlots) as
+// (j, value) at w / j arrays [b cap, b cap + cap), filled up to cursor[b];
+// lb < 0 sends every term straight to g[k] with a device-scope add.
+constexpr int kJoinTermSlots = 8192;  // operators per bin (one FP64 LDS table of 64 KB)
+constexpr int kJoinMaxBinsLog = 8;
+struct JoinTerms {
+  int lb;
+  u64 cap;
+  u64* cursor;
+  double* w;
+  unsigned short* j;
+};
 hipError_t launch_join_reduce(const DeviceState& st, const u64* recs, u64 R, const u64* cursor, int kb, int bh,
                               int bp, int orb, const void* src, u64 n, const Ints& I, const ExcSpace& E,
-                              const int* optab, int npairs, const unsigned char* selected, double* gacc,
-                              double* inserted, int grid, hipStream_t stream);
+                              const int* optab, int nsp, const unsigned char* selected, double* gacc,
+                              JoinTerms terms, double* inserted, int grid, hipStream_t stream);
+// Sums the binned terms into g[K] (nothing when terms.lb < 0).
+hipError_t launch_join_terms(JoinTerms terms, double* gacc, long long K, hipStream_t stream);
 hipError_t launch_sigma_push(const DeviceState& st, const Ints& I, const ExcSpace& E, u64 n,
                              AccSlot* tab, u64 tmask, int nbatch, int batch, double* inserted,
                              int grid, hipStream_t stream);
 hipError_t launch_pool_contract_det(const DeviceState& st, const ExcSpace& E, int n_spatial, u64 n,
-                                   const int* optab, int npairs, const unsigned char* selected,
+                                   const int* optab, int nsp, const unsigned char* selected,
                                    const AccSlot* tab, u64 tmask, int nbatch, int batch,
                                    double* gacc, int grid, hipStream_t stream);
 hipError_t launch_query_set(const DeviceState& st, const ExcSpace& E, int n_spatial, u64 n,
-                            const int* optab, int npairs, const unsigned char* selected,
+                            const int* optab, int nsp, const unsigned char* selected,
                             AccSlot* tab, u64 tmask, int count_only, u64* counter, int grid,
                             hipStream_t stream, int nbatch = 1, int batch = 0, unsigned* qf = nullptr,
                             u64 qfmask = 0);

@@ -28,7 +28,8 @@ SWCS_E_UNSUPPORTED = -6
 KERNELS = {"chain_lds": 1, "gate": 2, "sigma_proj": 3, "sigma_push": 4, "pool_contract": 5,
            "adjoint_lds": 6, "gate_replay": 7, "adjoint_rec": 8, "sigma_push_into": 9,
            "contract_ops": 10, "holepair": 11, "adjoint_replay_lds": 12, "select": 13,
-           "join_emit": 14, "join_sort": 15, "join_reduce": 16}
+           "join_emit": 14, "join_sort": 15, "join_reduce": 16,
+           "join_terms": 17}
 SIGMA_METHODS = {"auto": 0, "enumerate": 1, "hole_pairs": 2, "pairs": 3}
 POOL_METHODS = {"auto": 0, "table": 1, "join": 2}
 _NAMES = {0: "SWCS_OK", -1: "SWCS_E_INVALID", -2: "SWCS_E_STATE", -3: "SWCS_E_OOM",

@@ -183,6 +183,47 @@ def test_pool_methods_join_and_table(swcs, c1, c2, spread, name):
     ctx.close()
 
 
+def test_join_bin_overflow_takes_direct_adds(swcs, c2):
+    """Whole-pool gradients by the join when an operator bin overflows.  At
+    22,750 operators the join bins gradient terms by k mod 4, each bin with
+    room for 1.25 R / 4 + 4096 terms (R = alive (C + 1) records); here the
+    pool is reordered so that the most active quarter of the operators shares
+    bin 0, which then receives more terms than it holds, and the terms past
+    it take the direct adds into g.  Against the oracle, reordered alike."""
+    keys, amps = c2.st.export()
+    keys = np.asarray(keys, dtype=np.uint64)
+    pool = c2.pool
+    K = len(pool)
+    one = np.uint64(1)
+    act = np.zeros(K, np.int64)
+    for k, (P, Q, R, S) in enumerate(pool.tolist()):
+        cre, ann = ([P, Q], [R, S]) if R >= 0 else ([P], [Q])
+        mc = np.uint64(sum(1 << x for x in cre))
+        ma = np.uint64(sum(1 << x for x in ann))
+        acts = (((keys & ma) == ma) & ((keys & mc) == 0)) | (((keys & mc) == mc) & ((keys & ma) == 0))
+        act[k] = int(acts.sum())
+    n, na = c2.n, c2.na
+    nv = n - na
+    C = 2 * na * nv + 2 * (na * (na - 1) // 2) * (nv * (nv - 1) // 2) + na * na * nv * nv
+    assert act.sum() == len(keys) * C  # every connection has one operator of the complete pool
+    order = np.argsort(-act, kind="stable")
+    bin0 = np.arange(0, K, 4)
+    perm = np.empty(K, np.int64)
+    perm[bin0] = order[:len(bin0)]
+    perm[np.setdiff1d(np.arange(K), bin0)] = order[len(bin0):]
+    room = (int(1.25 * len(keys) * (C + 1) / 4) + 4096 + 7) & ~7
+    assert act[perm[bin0]].sum() > room
+    ctx = swcs.make_context(c2.n, c2.na, c2.nb, c2.h, c2.eri, pool[perm], c2.ref)
+    ctx.set_state(keys, np.asarray(amps))
+    ctx.set_pool_method("join")
+    _say("[parity] c2: join with an overflowing operator bin")
+    g = ctx.pool_gradients()
+    g_ref = c2.orc.pool_gradients(c2.st, pool)[perm]
+    assert np.abs(g_ref).max() > 1e-3
+    assert np.abs(g - g_ref).max() < TOL
+    ctx.close()
+
+
 def test_join_rank_fields_large_state(swcs):
     """More than 65,536 stored entries: the join's records carry rank fields
     (24 bits of orbital fields, 24 hash bits and a 17-bit index do not fit one
