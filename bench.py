@@ -227,15 +227,20 @@ def gpu_bench(args, wl):
     ev = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
            for _ in phases] for _ in range(args.steps)]
     torch.cuda.synchronize()
+    retries0 = torch.cuda.memory_stats().get("num_alloc_retries", 0)
     t0 = time.perf_counter()
     for s in range(args.steps):
         step(ev[s])
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    # cache flushes of the caching allocator (each frees and synchronizes)
+    alloc_retries = torch.cuda.memory_stats().get("num_alloc_retries", 0) - retries0
     ms_step = (t1 - t0) * 1e3 / args.steps
     progress(f"{wl.c.name}: {args.steps} timed steps, {ms_step:.2f} ms per step")
     phase_ms = {name: float(np.mean([ev[s][i][0].elapsed_time(ev[s][i][1]) for s in range(args.steps)]))
                 for i, (name, _) in enumerate(phases)}
+    phase_max_ms = {name: float(np.max([ev[s][i][0].elapsed_time(ev[s][i][1]) for s in range(args.steps)]))
+                    for i, (name, _) in enumerate(phases)}
 
     # Work counts of one step.
     n_det = phase_apply()
@@ -265,7 +270,8 @@ def gpu_bench(args, wl):
             kern[kname] = {"launches_per_step": launches / reps, "ms_per_step": total / reps,
                            "us_per_launch": 1e3 * total / launches}
     ctx.close()
-    return dict(ms_step=ms_step, phase_ms=phase_ms, n_det=n_det, n_in=n_in, applies=applies,
+    return dict(ms_step=ms_step, phase_ms=phase_ms, phase_max_ms=phase_max_ms, alloc_retries=alloc_retries,
+                n_det=n_det, n_in=n_in, applies=applies,
                 fwd_applies=fwd_applies, adj_applies=adj_applies, kernels=kern, seg=seg,
                 stored=stored, pool_table=pool_table)
 
@@ -813,6 +819,8 @@ def main():
                    "applies_per_step": r["applies"], "input_sha256": wl.digest[:16]},
         "pool_table": r["pool_table"],
         "phases_ms": {k: round(v, 4) for k, v in r["phase_ms"].items()},
+        "phases_max_ms": {k: round(v, 4) for k, v in r["phase_max_ms"].items()},
+        "alloc_retries": r["alloc_retries"],
     }
     if kern:
         dom = max(kern, key=lambda k: kern[k]["ms_per_step"])

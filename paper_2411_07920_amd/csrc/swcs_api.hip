@@ -343,6 +343,23 @@ void release_join_scratch(swcs_ctx* c) {
   for (DevBuf* b : bufs) b->release();
 }
 
+// Budget for a table sized from free memory: 40 % of what is free (blocks
+// cached by the allocator included) plus the table's own allocation.  The
+// join's scratch is given back first only when a table of `need` bytes would
+// not fit that budget otherwise: giving it back on every call makes a caching
+// allocator split and regrow its blocks from one call to the next.
+double free_table_budget(swcs_ctx* c, double need) {
+  auto budget = [&]() {
+    return std::max<double>(64.0 * 1024 * 1024, 0.4 * (double)(avail_bytes(c) + c->acc_tab.bytes));
+  };
+  double b = budget();
+  if (need > b) {
+    release_join_scratch(c);
+    b = budget();
+  }
+  return b;
+}
+
 u64 max_capacity(swcs_ctx* c) {
   u64 cap = c->sector;
   if (c->max_dets > 0 && (u64)c->max_dets < cap) cap = (u64)c->max_dets;
@@ -1513,10 +1530,7 @@ static int screened_gradients(swcs_ctx* c, u64 n, u64 alive, const int* d_subset
   auto batches = [&]() {
     int nb = 1;
     if (budget <= 0.0 && (double)slots_for(1) * sizeof(AccSlot) <= kQueryBoundBytes) return nb;
-    if (budget <= 0.0) {
-      release_join_scratch(c);
-      budget = std::max<double>(64.0 * 1024 * 1024, 0.4 * (double)(avail_bytes(c) + c->acc_tab.bytes));
-    }
+    if (budget <= 0.0) budget = free_table_budget(c, (double)slots_for(1) * sizeof(AccSlot));
     while (nb < 4096 && (double)slots_for(nb) * sizeof(AccSlot) > budget) nb *= 2;
     return nb;
   };
@@ -1803,8 +1817,7 @@ int swcs_pool_gradients(swcs_ctx* c, const int32_t* subset, int64_t n_subset, do
   if (c->table_budget > 0) {
     budget = (double)c->table_budget;
   } else if (4.0 * guess * sizeof(AccSlot) > budget) {
-    release_join_scratch(c);
-    budget = std::max<double>(64.0 * 1024 * 1024, 0.4 * (double)(avail_bytes(c) + c->acc_tab.bytes));
+    budget = free_table_budget(c, 4.0 * guess * sizeof(AccSlot));
   }
   const int sgrid = sigma_grid(c, n);
   for (int attempt = 0;; ++attempt) {
