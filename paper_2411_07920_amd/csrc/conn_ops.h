@@ -178,7 +178,11 @@ __device__ inline void for_each_connection(const ConnTables& T, u64 D, F&& f) {
 // 2 tri(nsp (nsp - 1) / 2) + tri(nsp^2) double slots (333,450 at nsp = 26,
 // 1.3 MB, against 878,475 for a triangle over all spin-orbital pairs), and
 // the lookups of the pool kernels stay in L2.
-__host__ __device__ inline int pair_index(int a, int b) { return a * (a - 1) / 2 + b; }
+// (a below 2^12: the masked product is a full-rate 24-bit multiply)
+__host__ __device__ inline int pair_index(int a, int b) {
+  const unsigned u = (unsigned)a & 0xFFFu;
+  return (int)((u * u - u) >> 1) + b;
+}
 
 __host__ __device__ inline long long optab_size(int nsp) {
   const long long nso = 2LL * nsp, ss = (long long)nsp * (nsp - 1) / 2, mx = (long long)nsp * nsp;
@@ -187,16 +191,17 @@ __host__ __device__ inline long long optab_size(int nsp) {
 
 // Slot of the double (P, Q, R, S): P > Q, R > S, both pairs of one spin class.
 __host__ __device__ inline int optab_double_slot(int nsp, int P, int Q, int R, int S) {
-  const int nso = 2 * nsp, ss = nsp * (nsp - 1) / 2;
-  int a, b, base = nso * (nso - 1) / 2;
+  nsp &= 63;
+  const int nso = 2 * nsp, ss = pair_index(nsp, 0);
+  int a, b, base = pair_index(nso, 0);
   if ((P & 1) == (Q & 1)) {
     a = pair_index(P >> 1, Q >> 1);
     b = pair_index(R >> 1, S >> 1);
-    if (P & 1) base += ss * (ss - 1) / 2;
+    if (P & 1) base += pair_index(ss, 0);
   } else {
-    a = ((P & 1) ? Q : P) / 2 * nsp + ((P & 1) ? P : Q) / 2;
-    b = ((R & 1) ? S : R) / 2 * nsp + ((R & 1) ? R : S) / 2;
-    base += ss * (ss - 1);
+    a = (((P & 1) ? Q : P) >> 1 & 63) * nsp + (((P & 1) ? P : Q) >> 1);
+    b = (((R & 1) ? S : R) >> 1 & 63) * nsp + (((R & 1) ? R : S) >> 1);
+    base += 2 * pair_index(ss, 0);
   }
   const int hi = a > b ? a : b, lo = a > b ? b : a;
   return base + pair_index(hi, lo);

@@ -173,10 +173,18 @@ struct Ints {
 // has m (m + 1) / 2 entries, m = n (n + 1) / 2 (61,776 doubles, 494 KB, at
 // n = 26 against 3.7 MB for n^4), so the lookups of the sigma and gradient
 // kernels stay in L2.
+// Orbital indices are below 64, so every product fits 24 bits; the masks let
+// the compiler use full-rate 24-bit multiplies instead of 32-bit ones.
 __host__ __device__ inline unsigned eri_packed_index(unsigned p, unsigned q, unsigned r, unsigned s) {
-  const unsigned pq = p >= q ? p * (p + 1) / 2 + q : q * (q + 1) / 2 + p;
-  const unsigned rs = r >= s ? r * (r + 1) / 2 + s : s * (s + 1) / 2 + r;
-  return pq >= rs ? pq * (pq + 1) / 2 + rs : rs * (rs + 1) / 2 + pq;
+  p &= 63u;
+  q &= 63u;
+  r &= 63u;
+  s &= 63u;
+  const unsigned hi1 = p >= q ? p : q, lo1 = p >= q ? q : p;
+  const unsigned hi2 = r >= s ? r : s, lo2 = r >= s ? s : r;
+  const unsigned pq = ((hi1 * hi1 + hi1) >> 1) + lo1, rs = ((hi2 * hi2 + hi2) >> 1) + lo2;
+  const unsigned a = (pq >= rs ? pq : rs) & 0xFFFu, b = pq >= rs ? rs : pq;
+  return ((a * a + a) >> 1) + b;
 }
 
 __device__ inline double eri_sp(const Ints& I, int p, int q, int r, int s) {
