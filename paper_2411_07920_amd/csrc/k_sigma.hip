@@ -645,10 +645,30 @@ __device__ inline bool qfilter_maybe(const unsigned* __restrict__ qf, u64 qfmask
   return !qf || filter_maybe(qf, qfmask, key);
 }
 
+// Key-only insert into an accumulation table whose values start at zero:
+// 2 when the key was new, 1 when it was there, 0 when no slot was found
+// within the probe limit (acc_add without its value add, which for a query
+// key would be a device-scope add of zero per (operator, determinant) pair).
+__device__ inline int acc_insert(AccSlot* tab, u64 mask, u64 key) {
+  u64 h = mix64(key) & mask;
+  const u64 lim = mask < kAccMaxProbes ? mask : kAccMaxProbes;
+  for (u64 probes = 0; probes <= lim; ++probes) {
+    const u64 k = tab[h].key;
+    if (k == key) return 1;
+    if (k == kEmptyKey) {
+      const u64 prev = atomicCAS(&tab[h].key, kEmptyKey, key);
+      if (prev == kEmptyKey) return 2;
+      if (prev == key) return 1;
+    }
+    h = (h + 1) & mask;
+  }
+  return 0;
+}
+
 // Insert a query key; sets its filter bit on the first insert.
 __device__ inline void query_insert(AccSlot* tab, u64 tmask, u64 X, unsigned* qf, u64 qfmask,
                                     unsigned* flags) {
-  const int r = acc_add(tab, tmask, X, 0.0);
+  const int r = acc_insert(tab, tmask, X);
   if (!r) atomicOr(flags, kFlagOverflow);
   else if (r == 2 && qf) qfilter_set(qf, qfmask, X);
 }
