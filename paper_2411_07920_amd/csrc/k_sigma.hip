@@ -717,6 +717,10 @@ k_query_set(const u64* __restrict__ keys, const double* __restrict__ amps, ExcSp
 // Pass "query" counts or inserts X_k(D) for every active (k, D); pass
 // "contract" accumulates psi(D) a_k(D) sigma(X_k(D)) per operator slot.
 constexpr int kOpTile = 16;
+// The contraction's tile is longer: one device-scope add per (operator,
+// tile) with a nonzero sum, so 64 determinants per tile send a quarter of
+// the adds a 16-determinant tile would.
+constexpr int kOpTileContract = 64;
 
 __global__ void __launch_bounds__(256)
 k_query_ops(const u64* __restrict__ keys, const double* __restrict__ amps, u64 n,
@@ -756,10 +760,10 @@ k_contract_ops(const u64* __restrict__ keys, const double* __restrict__ amps, u6
                const OpDesc* __restrict__ ops, const int* __restrict__ subset, long long n_sub,
                const AccSlot* __restrict__ tab, u64 tmask, double* __restrict__ gslot, int nbatch,
                int batch) {
-  __shared__ u64 skey[kOpTile];
-  __shared__ double samp[kOpTile];
-  const u64 t0 = (u64)blockIdx.x * kOpTile;
-  const int tile = (int)((n - t0) < (u64)kOpTile ? (n - t0) : (u64)kOpTile);
+  __shared__ u64 skey[kOpTileContract];
+  __shared__ double samp[kOpTileContract];
+  const u64 t0 = (u64)blockIdx.x * kOpTileContract;
+  const int tile = (int)((n - t0) < (u64)kOpTileContract ? (n - t0) : (u64)kOpTileContract);
   for (int t = threadIdx.x; t < tile; t += blockDim.x) {
     const double a = amps[t0 + t];
     skey[t] = is_dead(a) ? 0ULL : keys[t0 + t];
@@ -1061,7 +1065,7 @@ hipError_t launch_contract_ops(const DeviceState& st, u64 n, const OpDesc* ops, 
                                hipStream_t stream, int nbatch, int batch) {
   if (nbatch < 1 || batch < 0 || batch >= nbatch) return hipErrorInvalidValue;
   if (n == 0 || n_sub == 0) return hipSuccess;
-  const dim3 grid((unsigned)((n + kOpTile - 1) / kOpTile), (unsigned)((n_sub + 255) / 256));
+  const dim3 grid((unsigned)((n + kOpTileContract - 1) / kOpTileContract), (unsigned)((n_sub + 255) / 256));
   hipLaunchKernelGGL(k_contract_ops, grid, dim3(256), 0, stream, st.keys, st.amps, n, ops, subset,
                      n_sub, tab, tmask, gslot, nbatch, batch);
   return hipGetLastError();
