@@ -55,3 +55,14 @@ def test_null_context_calls_are_rejected():
     assert lib.swcs_set_stream(None, None) == swcs.SWCS_E_INVALID
     assert lib.swcs_energy(None, None, None, None) == swcs.SWCS_E_INVALID
     lib.swcs_destroy(None)
+
+
+def test_kernel_timer_ids_match_header():
+    """The binding's kernel names map to the header's SWCS_K_* values."""
+    from paper_2411_07920_amd import swcs
+    text = open(os.path.join(ROOT, "include", "swcs.h")).read()
+    ids = {m.group(1).lower(): int(m.group(2)) for m in re.finditer(r"SWCS_K_([A-Z_]+)\s*=\s*(\d+)", text)}
+    assert sorted(ids.values()) == list(range(1, len(ids) + 1))
+    assert sorted(swcs.KERNELS.values()) == sorted(ids.values())
+    for name, kid in swcs.KERNELS.items():
+        assert ids.get(name) == kid, name
