@@ -471,9 +471,11 @@ def adapt_segment(args):
 
     def log(r):
         done.append(r)
+        ps = r.get("pool_stats", {})
         print(f"[adapt segment] it={r['iter']} E={r.get('E_after', r['E']):.10f} k={r['kstar']} "
               f"exact={r['n_exact']} pool={1e3 * r['t_pool']:.1f}ms vqe={1e3 * r.get('t_vqe', 0.0):.1f}ms "
-              f"n_det={r['n_det']}", file=sys.stderr, flush=True)
+              f"n_det={r['n_det']} pool_keys={ps.get('keys', 0):.3g} slots={ps.get('table_slots', 0)} "
+              f"batches={ps.get('batches', 0)} passes={ps.get('passes', 0)}", file=sys.stderr, flush=True)
 
     t = time.perf_counter()
     ops, theta, hist = adapt.run_adapt(ctx, wl.K, cfg, log=log, checkpoint=args.checkpoint,

@@ -265,6 +265,10 @@ def run_adapt(ctx, K: int, cfg: AdaptConfig, ops0=None, theta0=None, log=None, c
             gsel = g_d.cpu().numpy()
             rec_idx, rec_g = idx_d, g_d
         t2 = time.perf_counter()
+        # sizing of the pass (keys, table slots, key-hash batches, repeats)
+        # when the context reports it
+        if hasattr(ctx, "pool_stats"):
+            rec["pool_stats"] = ctx.pool_stats()
         kpos = select_operator(gsel, idx)
         kstar = int(idx[kpos])
         gnorm = float(np.linalg.norm(gsel))

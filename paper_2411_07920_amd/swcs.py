@@ -181,6 +181,12 @@ class Context:
         if getattr(self, "_h", None):
             self._lib.swcs_destroy(self._h)
             self._h = None
+            if getattr(self, "_torch_memory", False):
+                # the library sizes its tables from the device's free memory
+                # (plus what it handed back itself); blocks a closed context
+                # leaves in PyTorch's cache would be invisible to the next one
+                import torch
+                torch.cuda.empty_cache()
         self._alloc_cb = None
 
     def __del__(self):
@@ -251,6 +257,9 @@ class Context:
         dev = self.device
         st = stream if stream is not None else torch.cuda.current_stream(dev)
         self.set_stream(st)
+        # blocks already cached by PyTorch would not show as free device memory
+        torch.cuda.empty_cache()
+        self._torch_memory = True
 
         def alloc(nbytes):
             return torch.cuda.caching_allocator_alloc(nbytes, dev, st)
