@@ -343,6 +343,14 @@ void release_join_scratch(swcs_ctx* c) {
   for (DevBuf* b : bufs) b->release();
 }
 
+// Whether the whole-pool join is taken for a state of `alive` entries: a
+// forced join always, AUTO up to kJoinAutoMaxRecords records.
+bool join_fits_state(swcs_ctx* c, u64 alive) {
+  if (c->pool_method == SWCS_POOL_TABLE) return false;
+  if (c->pool_method == SWCS_POOL_JOIN) return true;
+  return alive * (u64)(c->exc.total + 1) <= kJoinAutoMaxRecords;
+}
+
 // Budget for a table sized from free memory: 40 % of what is free (blocks
 // cached by the allocator included) plus the table's own allocation.  The
 // join's scratch is given back first only when a table of `need` bytes would
@@ -1474,6 +1482,8 @@ static int mark_subset(swcs_ctx* c, const int* d_subset, int64_t n_subset);
 
 static int screened_gradients(swcs_ctx* c, u64 n, u64 alive, const int* d_subset, int64_t n_subset,
                               const double* norm2, double* d_out, bool may_sync) {
+  // a state too large for the join makes its scratch dead weight
+  if (!join_fits_state(c, alive)) release_join_scratch(c);
   const bool op_major = n_subset <= c->exc.total;
   const unsigned char* d_sel = nullptr;
   if (!op_major) {
@@ -1669,8 +1679,12 @@ static int join_gradients(swcs_ctx* c, const Counters& h, const unsigned char* d
   // Measured at 52 spin-orbitals: 1.54e9 records take 120 ms by the join
   // against 187 ms by the table, but 7.9e9 records (266,101 determinants)
   // take 1.9 s, where the table needs about 1 s: beyond 2^31 records AUTO
-  // takes the table.
-  if (!forced && R > kJoinAutoMaxRecords) return 1;
+  // takes the table (and gives back the join's scratch, which a state of
+  // this size leaves unused).
+  if (!join_fits_state(c, h.alive)) {
+    release_join_scratch(c);
+    return 1;
+  }
   int kb, bh, bp, orb;
   if (!join_format(c->exc, n, R, &kb, &bh, &bp, &orb)) {
     if (forced) return fail(c, SWCS_E_CAPACITY, "join records do not fit 64 bits");
