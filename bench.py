@@ -406,8 +406,9 @@ def adapt_bench(args):
         def log(r):
             print(f"[adapt {name}] it={r['iter']} E={r.get('E_after', r['E']):.10f} "
                   f"k={r['kstar']} exact={r['n_exact']} pool={1e3 * r['t_pool']:.1f}ms "
-                  f"vqe={1e3 * r.get('t_vqe', 0.0):.1f}ms evals={r.get('vqe_evals', 0)} n_det={r['n_det']}",
-                  file=sys.stderr, flush=True)
+                  f"vqe={1e3 * r.get('t_vqe', 0.0):.1f}ms evals={r.get('vqe_evals', 0)} n_det={r['n_det']} "
+                  f"batches={r.get('pool_stats', {}).get('batches', 0)} "
+                  f"passes={r.get('pool_stats', {}).get('passes', 0)}", file=sys.stderr, flush=True)
 
         ops, theta, hist = adapt.run_adapt(ctx, wl.K, cfg, log=log)
         wall = time.perf_counter() - t
