@@ -665,13 +665,19 @@ __device__ inline int acc_insert(AccSlot* tab, u64 mask, u64 key) {
   return 0;
 }
 
-// Insert a query key; sets its filter bit on the first insert.
-__device__ inline void query_insert(AccSlot* tab, u64 tmask, u64 X, unsigned* qf, u64 qfmask,
-                                    unsigned* flags) {
+// Insert a query key; sets its filter bit on the first insert.  Returns 1
+// when the key was new.
+__device__ inline int query_insert(AccSlot* tab, u64 tmask, u64 X, unsigned* qf, u64 qfmask,
+                                   unsigned* flags) {
   const int r = acc_insert(tab, tmask, X);
   if (!r) atomicOr(flags, kFlagOverflow);
   else if (r == 2 && qf) qfilter_set(qf, qfmask, X);
+  return r == 2 ? 1 : 0;
 }
+
+// Determinant-major query pass: as k_query_ops (counts or inserts, with
+// the same use of counter), over the connections of each determinant whose
+// linking operator is selected.
 __global__ void __launch_bounds__(kSigBlock)
 k_query_set(const u64* __restrict__ keys, const double* __restrict__ amps, ExcSpace E, int n_spatial,
             u64 n, const int* __restrict__ optab, int nsp,
@@ -703,10 +709,10 @@ k_query_set(const u64* __restrict__ keys, const double* __restrict__ amps, ExcSp
         return;
       }
       if (nbatch > 1 && batch_of(X, nbatch) != batch) return;
-      query_insert(tab, tmask, X, qf, qfmask, flags);
+      mine += query_insert(tab, tmask, X, qf, qfmask, flags);
     });
   }
-  if (count_only) {
+  if (counter) {
     for (int off = 32; off > 0; off >>= 1) mine += __shfl_xor(mine, off);
     if (__lane_id() == 0 && mine) atomicAdd(counter, (u64)mine);
   }
@@ -714,8 +720,11 @@ k_query_set(const u64* __restrict__ keys, const double* __restrict__ amps, ExcSp
 
 // Operator-major passes for a screened subset: block (x, y) stages a tile of
 // determinants in LDS (x) and gives each thread one selected operator (y).
-// Pass "query" counts or inserts X_k(D) for every active (k, D); pass
-// "contract" accumulates psi(D) a_k(D) sigma(X_k(D)) per operator slot.
+// Pass "query" counts (count_only > 0: the active pairs of every
+// count_only-th tile, into *counter) or inserts X_k(D) for every active
+// (k, D) (adding the number of keys that were new to *counter when counter is
+// given); pass "contract" accumulates psi(D) a_k(D) sigma(X_k(D)) per
+// operator slot.
 constexpr int kOpTile = 16;
 // The contraction's tile is longer: one device-scope add per (operator,
 // tile) with a nonzero sum, so 64 determinants per tile send a quarter of
@@ -746,10 +755,10 @@ k_query_ops(const u64* __restrict__ keys, const double* __restrict__ amps, u64 n
       if (!act) continue;
       if (count_only) ++mine;
       else if (nbatch > 1 && batch_of(D ^ pm, nbatch) != batch) continue;
-      else query_insert(tab, tmask, D ^ pm, qf, qfmask, flags);
+      else mine += query_insert(tab, tmask, D ^ pm, qf, qfmask, flags);
     }
   }
-  if (count_only) {
+  if (counter) {
     for (int off = 32; off > 0; off >>= 1) mine += __shfl_xor(mine, off);
     if (__lane_id() == 0 && mine) atomicAdd(counter, (u64)mine);
   }

@@ -1545,7 +1545,7 @@ static int screened_gradients(swcs_ctx* c, u64 n, u64 alive, const int* d_subset
     return nb;
   };
   int nbatch = batches();
-  bool checked = false;
+  bool checked = false, replanned = false;
   int passes = 0;
   for (int attempt = 0;;) {
     const u64 qslots = slots_for(nbatch);
@@ -1561,17 +1561,43 @@ static int screened_gradients(swcs_ctx* c, u64 n, u64 alive, const int* d_subset
       HIP_TRY(c, launch_fill_u32(d_out, 0u, (u64)n_subset * 2, c->stream), "zero g");
     else
       HIP_TRY(c, launch_fill_u32(c->gacc.p, 0u, (u64)c->K_pool * 2, c->stream), "zero g");
+    bool replan = false;
     for (int b = 0; b < nbatch; ++b) {
       HIP_TRY(c, launch_fill_u32(c->acc_tab.p, 0u, qslots * (sizeof(AccSlot) / 4), c->stream), "clear table");
       HIP_TRY(c, launch_fill_u32(qf, 0u, qbits / 32, c->stream), "clear filter");
+      // The estimate that set the batch count is an upper bound (pairs, or
+      // the distinct count of all external keys); the first batch of a
+      // batched pass counts its new keys, and since key-hash batches split
+      // the query set evenly, a set much smaller than planned restarts the
+      // pass with fewer batches (only this batch's query pass is lost).
+      u64* qnew = (b == 0 && nbatch > 1 && estimated && !replanned) ? c->scalars.as<u64>() + 40 : nullptr;
+      if (qnew) HIP_TRY(c, launch_fill_u32(qnew, 0u, 2, c->stream), "zero counter");
       if (op_major)
         HIP_TRY(c, launch_query_ops(c->st, n, c->ops.as<OpDesc>(), d_subset, n_subset,
-                                    c->acc_tab.as<AccSlot>(), qslots - 1, 0, nullptr, c->stream, nbatch, b,
+                                    c->acc_tab.as<AccSlot>(), qslots - 1, 0, qnew, c->stream, nbatch, b,
                                     qf, qbits - 1), "query set");
       else
         HIP_TRY(c, launch_query_set(c->st, c->exc, c->n, n, c->opmap.as<int>(), c->n, d_sel,
-                                    c->acc_tab.as<AccSlot>(), qslots - 1, 0, nullptr, sigma_grid(c, n),
+                                    c->acc_tab.as<AccSlot>(), qslots - 1, 0, qnew, sigma_grid(c, n),
                                     c->stream, nbatch, b, qf, qbits - 1), "query set");
+      if (qnew) {
+        replanned = true;
+        u64 got = 0;
+        HIP_TRY(c, hipMemcpyAsync(&got, qnew, 8, hipMemcpyDeviceToHost, c->stream), "copy");
+        HIP_TRY(c, hipStreamSynchronize(c->stream), "sync");
+        const double q_new = std::max(64.0, 1.25 * (double)got * nbatch);
+        if (q_new < 0.5 * q) {
+          const double q_old = q;
+          q = q_new;
+          const int nb_new = batches();
+          if (nb_new < nbatch) {
+            nbatch = nb_new;
+            replan = true;
+            break;
+          }
+          q = q_old;
+        }
+      }
       TIMED(c, SWCS_K_SIGMA_PUSH_INTO, launch_sigma_push_into(c->st, ints_view(c), c->exc, n, c->acc_tab.as<AccSlot>(),
                                                               qslots - 1, sigma_grid(c, n), c->stream, nbatch, b,
                                                               qf, qbits - 1),
@@ -1586,6 +1612,7 @@ static int screened_gradients(swcs_ctx* c, u64 n, u64 alive, const int* d_subset
                                                                 c->gacc.as<double>(), sigma_grid(c, n), c->stream),
               "contract");
     }
+    if (replan) continue;
     // A single bound-sized table (at most half full) is checked on the
     // device when the caller does not synchronize (below); otherwise a pass
     // in which a table filled is repeated with twice the estimate.
