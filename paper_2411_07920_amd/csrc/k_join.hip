@@ -628,19 +628,21 @@ hipError_t launch_join_reduce(const DeviceState& st, const u64* recs, u64 R, con
   return hipGetLastError();
 }
 
-// One block per (bin, chunk of kJoinTermChunk terms): the chunk's terms are
-// added into an LDS table of the bin's operators, then each nonzero sum goes
-// to g[k] with one device-scope add.
-constexpr u64 kJoinTermChunk = 1ULL << 20;
+// One block per (bin, chunk of `chunk` terms): the chunk's terms are added
+// into an LDS table of the bin's operators, then each nonzero sum goes to g[k]
+// with one device-scope add.  Chunks hold 2^20 terms for large joins and
+// fewer (down to 4,096) for small ones, so that a launch has about a thousand
+// blocks.
+constexpr u64 kJoinTermChunkMax = 1ULL << 20, kJoinTermChunkMin = 1ULL << 12;
 __global__ void __launch_bounds__(kJoinBlock)
-k_join_terms(JoinTerms terms, int per_bin, double* __restrict__ gacc, long long K) {
+k_join_terms(JoinTerms terms, int per_bin, u64 chunk, double* __restrict__ gacc, long long K) {
   __shared__ double acc[kJoinTermSlots];
   const int b = (int)(blockIdx.x / (unsigned)per_bin);
   const u64 c = blockIdx.x % (unsigned)per_bin;
   const u64 filled = terms.cursor[b] < terms.cap ? terms.cursor[b] : terms.cap;
-  const u64 lo = c * kJoinTermChunk;
+  const u64 lo = c * chunk;
   if (lo >= filled) return;  // uniform over the block
-  const u64 hi = lo + kJoinTermChunk < filled ? lo + kJoinTermChunk : filled;
+  const u64 hi = lo + chunk < filled ? lo + chunk : filled;
   for (int s = threadIdx.x; s < kJoinTermSlots; s += kJoinBlock) acc[s] = 0.0;
   __syncthreads();
   const double* __restrict__ w = terms.w + (u64)b * terms.cap;
@@ -673,10 +675,13 @@ k_join_terms(JoinTerms terms, int per_bin, double* __restrict__ gacc, long long 
 hipError_t launch_join_terms(JoinTerms terms, double* gacc, long long K, hipStream_t stream) {
   if (terms.lb < 0) return hipSuccess;
   if (terms.lb > kJoinMaxBinsLog) return hipErrorInvalidValue;
-  const u64 per_bin = (terms.cap + kJoinTermChunk - 1) / kJoinTermChunk;
+  u64 chunk = kJoinTermChunkMin;
+  while (chunk < kJoinTermChunkMax && (terms.cap << terms.lb) / chunk > 1024) chunk <<= 1;
+  const u64 per_bin = (terms.cap + chunk - 1) / chunk;
   const u64 grid = per_bin << terms.lb;
   if (per_bin == 0 || grid > 0x7fffffffULL) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_join_terms, dim3((unsigned)grid), dim3(kJoinBlock), 0, stream, terms, (int)per_bin, gacc, K);
+  hipLaunchKernelGGL(k_join_terms, dim3((unsigned)grid), dim3(kJoinBlock), 0, stream, terms, (int)per_bin, chunk,
+                     gacc, K);
   return hipGetLastError();
 }
 
