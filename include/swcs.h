@@ -259,10 +259,14 @@ int swcs_pool_gradients(swcs_ctx* ctx, const int32_t* subset, int64_t n_subset, 
  * query table of the selected operators is sized from the bound
  * (alive determinants x min(n_subset, C)) when that table stays below
  * 512 MB and no table budget is set (swcs_set_table_budget); otherwise from
- * an exact count of (determinant, operator) pairs, capped by the distinct
- * external count of the last full-pool call, which synchronizes once, and
- * again after each pass that was split into key-hash batches or sized by
- * that cap (a pass whose table filled is repeated with twice the estimate).
+ * a count of (determinant, operator) pairs (on every 16th determinant tile
+ * from 16,384 stored entries, scaled), capped by the distinct external count
+ * of the last full-pool call, which synchronizes once, and again after each
+ * pass that was split into key-hash batches or sized by that cap (a pass
+ * whose table filled is repeated with twice the estimate).  A pass split
+ * into batches also counts the new keys of its first batch (one more
+ * synchronization) and restarts with fewer batches when the query set is
+ * under half the estimate.
  * A bound-sized table is not checked on the host: if an insert found it full
  * (more than 4,096 probes at load <= 1/2), every entry of d_g is NaN.
  * Returns SWCS_E_OOM if even 4,096 batches do not fit the table memory. */
